@@ -1,0 +1,182 @@
+/*
+ * rheed.h -- C ABI of the MI355X (gfx950) many-beam RHEED/TRHEPD library.
+ *
+ * Method: Kudo, Yamamoto, Hoshi, "A fast and accurate computation method for
+ * reflective diffraction simulations" (arXiv 2306.00271).  The coupled-beam
+ * equation c'' = -(U(z) + Gamma^2) c (Sec. 2.1, Eq. sch3) is written as the
+ * matrix ODE Z' = B(z) Z in economical form (Sec. 3.1, Eq. ode2, Eq. mateq2),
+ * stepped slice by slice with an explicit Runge-Kutta method (Sec. 3.4) and
+ * the right-hand-side transformation Z <- Z Q^{-1} whenever the Gershgorin
+ * condition estimate of the upper block exceeds a threshold (Sec. 3.2,
+ * Algorithm 1); the reflected amplitudes follow from Eq. (vrhocomp) and the
+ * intensities from the formula at the end of Sec. 2.1.
+ *
+ * Conventions for every entry point:
+ *  - All numbers are IEEE FP64.  Complex values are {double re, im}
+ *    interleaved (the layout of hipDoubleComplex and torch.complex128).
+ *  - Pointers documented "device" must be device memory of the current HIP
+ *    device; "host" pointers are read during the call only.  The caller owns
+ *    every buffer; the library allocates only inside rheed_plan_create.
+ *  - Calls that take a `stream` (a hipStream_t, NULL = default stream) are
+ *    asynchronous with respect to the host and enqueue all their work on that
+ *    stream.  They do not synchronise and do not allocate.
+ *  - Invalid arguments return RHEED_E_INVALID before anything is enqueued;
+ *    a failing HIP call returns RHEED_E_HIP.  rheed_last_error() then holds a
+ *    message for the calling thread.
+ *  - Numerical failure of one (structure, angle) pair never fails the call:
+ *    that pair's outputs are NaN and its entry in pair_status says why.
+ *  - There is no CPU fallback: on a machine without a gfx950 device every
+ *    compute entry point returns RHEED_E_HIP.
+ */
+#ifndef RHEED_H
+#define RHEED_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RHEED_OK = 0,
+  RHEED_E_INVALID = -1,
+  RHEED_E_HIP = -2,
+  RHEED_E_NOMEM = -3,
+  RHEED_E_UNSUPPORTED = -4
+} rheed_status;
+
+/* per-pair status codes written to pair_status[] */
+enum {
+  RHEED_PAIR_OK = 0,
+  RHEED_PAIR_SINGULAR = 1,  /* an exactly zero pivot in a right division */
+  RHEED_PAIR_NONFINITE = 2  /* Inf/NaN reached the reflected amplitudes */
+};
+
+/* Explicit RK tableaux (Sec. 3.4): classical 4th order, 4 stages, and
+ * Butcher's 6th-order 7-stage method. */
+typedef enum { RHEED_RK4 = 0, RHEED_RK6 = 1 } rheed_stepper;
+
+/* Intensity normalisation (Sec. 2.1): FLUX = |rho_j|^2 Gamma_0/Gamma_j on
+ * open beams; PAPER = the printed formula, FLUX times sin(theta0). */
+typedef enum { RHEED_INTENSITY_FLUX = 0, RHEED_INTENSITY_PAPER = 1 } rheed_convention;
+
+/* Largest beam count N handled by the kernels of this build. */
+#define RHEED_MAX_BEAMS 64
+/* Largest potential-table row (rod differences) for N <= 64. */
+#define RHEED_MAX_BOX 300
+
+/* One slab.  Rod indices are on the reciprocal basis b1, b2:
+ * k_j = h_j b1 + k_j b2 (Sec. 2.1, the reciprocal rods k_j with k_1 = 0). */
+typedef struct {
+  int32_t n_beams;          /* N, 1..RHEED_MAX_BEAMS */
+  const int32_t* beam_hk;   /* host [N][2] (h, k); beam 0 must be (0, 0) */
+  double recip[4];          /* b1x, b1y, b2x, b2y in 1/A */
+  int32_t n_slices;         /* L >= 1; slice i spans [-D + i h, -D + (i+1) h], h = D/L */
+  double thickness;         /* D > 0 in A: the slab is z in [-D, 0] (z_e = -D) */
+  double wavenumber;        /* gamma in 1/A (see rheed_beam_constants) */
+  /* Potential model, used by rheed_potential / rheed_potential_backward only:
+   * atoms with v(r) = sum_m a_m exp(-b_m |r - r_a|^2) volts, rescaled so the
+   * slab average is mean_inner_potential, times kappa (charge - i absorption). */
+  int32_t n_atoms;
+  double cell_area;         /* A^2 of the (super)cell */
+  double scat_a[4];         /* V */
+  double scat_b[4];         /* 1/A^2, > 0 */
+  double kappa;             /* 1/(A^2 V) */
+  double charge;            /* +1 electron, -1 positron */
+  double absorption;        /* alpha >= 0 */
+  double mean_inner_potential; /* V */
+} rheed_structure;
+
+typedef struct {
+  rheed_stepper stepper;
+  double rhst_threshold;     /* RHST when the condition estimate exceeds it; the paper uses 1000 */
+  int32_t checkpoint_every;  /* slices between states saved for rheed_backward (>= 1) */
+  rheed_convention convention;
+} rheed_opts;
+
+typedef struct rheed_plan_s* rheed_plan_t;
+
+typedef struct {
+  int32_t n_struct;
+  int32_t n_pairs;           /* sum of angles_per_struct; pair p of structure s is
+                                numbered structure-major: pairs of s are contiguous */
+  int32_t max_beams;         /* Nmax over structures: leading dimension of outputs */
+  int32_t nodes_per_slice;   /* distinct RK nodes in [0, 1): 2 for RK4, 4 for RK6 */
+  int64_t table_elems;       /* complex elements of all potential tables */
+  int64_t n_atoms_total;
+  size_t fwd_workspace;      /* bytes rheed_forward needs to keep states for rheed_backward */
+  size_t bwd_workspace;      /* extra bytes rheed_backward needs beyond fwd_workspace */
+} rheed_plan_info;
+
+/* Vacuum wavenumber gamma (1/A) and the coefficient kappa (1/(A^2 V)) of the
+ * electrostatic potential in Eq. (sch1) for a lepton of kinetic energy
+ * energy_eV, relativistic (CODATA 2018).  Host only. */
+rheed_status rheed_beam_constants(double energy_eV, double* gamma, double* kappa);
+
+/* Validates and uploads the structure descriptors (host -> device, blocking).
+ * angles_per_struct: host [n_struct], each >= 1.  The structure array and the
+ * beam lists are copied; the caller may free them after the call. */
+rheed_status rheed_plan_create(rheed_plan_t* plan, const rheed_opts* opts, int32_t n_struct,
+                               const rheed_structure* structs, const int32_t* angles_per_struct);
+rheed_status rheed_plan_destroy(rheed_plan_t plan);
+rheed_status rheed_plan_get_info(rheed_plan_t plan, rheed_plan_info* info);
+/* host out[n_struct + 1]: complex-element offset of each structure's table;
+ * table of structure s is [n_nodes(s)][box(s)], n_nodes = L * nodes_per_slice + 1,
+ * box = (2 Hd + 1)(2 Kd + 1), Hd = max h - min h, Kd = max k - min k, entry
+ * (dh + Hd)(2 Kd + 1) + (dk + Kd) holds u_{dh b1 + dk b2}(z_node) in 1/A^2
+ * (the coefficient u_{l(j,k)} of Eq. sch2 for g_j - g_k = (dh, dk)). */
+rheed_status rheed_plan_table_offsets(rheed_plan_t plan, int64_t* out);
+/* host out[n_struct + 1]: atom offsets into the packed [n_atoms_total][3] array */
+rheed_status rheed_plan_atom_offsets(rheed_plan_t plan, int64_t* out);
+
+/* Potential tables on the slice nodes from atom positions (Sec. 2.1).
+ * atoms: device [n_atoms_total][3] (x, y, z) in A.  U_tables: device complex
+ * [table_elems].  Node n of a structure sits at z = -D + (i + c) h with
+ * n = i * nodes_per_slice + m and c the m-th distinct RK node in [0,1), plus
+ * the final node at z = 0. */
+rheed_status rheed_potential(rheed_plan_t plan, const double* atoms, void* U_tables, void* stream);
+
+/* Gradient of a real loss w.r.t. atom coordinates from its gradient w.r.t.
+ * the tables.  dL_dU: device complex [table_elems] holding
+ * dL/dRe(u) + i dL/dIm(u); dL_datoms: device [n_atoms_total][3] (overwritten). */
+rheed_status rheed_potential_backward(rheed_plan_t plan, const double* atoms, const void* dL_dU,
+                                      double* dL_datoms, void* stream);
+
+/* Reflected amplitudes and intensities for every (structure, angle) pair
+ * (Algorithm 1 + Eq. vrhocomp + the intensity formula of Sec. 2.1).
+ *  U_tables   device complex [table_elems] (see rheed_plan_table_offsets)
+ *  angles     device [n_pairs][2]: glancing angle theta0 and azimuth theta1
+ *             (rad, theta1 measured from b1); b0 = gamma cos(theta0)(cos theta1, sin theta1)
+ *  intensity  device [n_pairs][max_beams]; entries j >= N of a pair are 0
+ *  rho        device complex [n_pairs][max_beams] or NULL
+ *  pair_status device int32 [n_pairs] (RHEED_PAIR_*)
+ *  n_rhst     device int32 [n_pairs] number of right-hand-side transformations, or NULL
+ *  workspace  device, >= fwd_workspace bytes, to keep the states rheed_backward
+ *             needs; NULL when no backward pass follows. */
+rheed_status rheed_forward(rheed_plan_t plan, const void* U_tables, const double* angles,
+                           double* intensity, void* rho, int32_t* pair_status, int32_t* n_rhst,
+                           void* workspace, size_t ws_bytes, void* stream);
+
+/* Adjoint of rheed_forward (not in the paper): given dL/d(intensity) for a
+ * real loss L, accumulates dL/dU over all angles of each structure.
+ * Must follow rheed_forward on the same stream with the same plan, inputs and
+ * workspace.  dL_dI: device [n_pairs][max_beams]; dL_dU: device complex
+ * [table_elems], overwritten; workspace >= fwd_workspace + bwd_workspace. */
+rheed_status rheed_backward(rheed_plan_t plan, const void* U_tables, const double* angles,
+                            const double* dL_dI, void* dL_dU, void* workspace, size_t ws_bytes,
+                            void* stream);
+
+/* R-factor of the specular beam against a target curve:
+ * loss = sum_p (intensity[p][0] - target[p])^2 (device scalar), and its
+ * gradient dL_dI[p][j] = 2 (intensity[p][0] - target[p]) for j = 0, 0 else. */
+rheed_status rheed_rfactor(int32_t n_pairs, int32_t ld, const double* intensity, const double* target,
+                           double* loss, double* dL_dI, void* stream);
+
+const char* rheed_status_string(rheed_status s);
+const char* rheed_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RHEED_H */

@@ -1,0 +1,179 @@
+"""Thin Python binding over librheed: marshals torch tensors to the C ABI.
+
+Every computation runs in the library's HIP kernels; this module only
+allocates output tensors, passes pointers and the current HIP stream, and
+checks status codes.  Device tensors must live on the current HIP device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib
+
+STEPPERS = {"rk4": _lib.RHEED_RK4, "rk6": _lib.RHEED_RK6}
+CONVENTIONS = {"flux": _lib.RHEED_INTENSITY_FLUX, "paper": _lib.RHEED_INTENSITY_PAPER}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return C.c_void_p(0) if t is None else C.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, dtype, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def beam_constants(energy_eV: float):
+    """(gamma in 1/A, kappa in 1/(A^2 V)) from the library."""
+    g, k = C.c_double(), C.c_double()
+    _lib.check(_lib.lib().rheed_beam_constants(float(energy_eV), C.byref(g), C.byref(k)), "beam_constants")
+    return g.value, k.value
+
+
+class Plan:
+    """A set of structures, each with a number of angles (pairs are numbered
+    structure-major).  ``structures`` are objects with the attributes
+    ``beams`` [N,2] int, ``recip`` [2,2], ``n_slices``, ``thickness``,
+    ``atoms`` [n_atoms,3], ``cell_area``, ``scat_a`` [4], ``scat_b`` [4]."""
+
+    def __init__(self, structures: Sequence, angles_per_struct: Sequence[int], *, energy_eV: float,
+                 charge: float, absorption: float, mean_inner_potential: float = 15.0, stepper: str = "rk6",
+                 threshold: float = 1000.0, checkpoint_every: int = 20, convention: str = "flux"):
+        L = _lib.lib()
+        self.gamma, self.kappa = beam_constants(energy_eV)
+        self.stepper = stepper
+        n = len(structures)
+        arr = (_lib.Structure * n)()
+        self._keep = []
+        for i, s in enumerate(structures):
+            beams = np.ascontiguousarray(np.asarray(s.beams, dtype=np.int32))
+            self._keep.append(beams)
+            st = arr[i]
+            st.n_beams = beams.shape[0]
+            st.beam_hk = beams.ctypes.data_as(C.POINTER(C.c_int32))
+            rec = np.asarray(s.recip, dtype=np.float64)
+            st.recip = (C.c_double * 4)(rec[0, 0], rec[0, 1], rec[1, 0], rec[1, 1])
+            st.n_slices = int(s.n_slices)
+            st.thickness = float(s.thickness)
+            st.wavenumber = self.gamma
+            st.n_atoms = int(np.asarray(s.atoms).shape[0])
+            st.cell_area = float(s.cell_area)
+            st.scat_a = (C.c_double * 4)(*[float(x) for x in s.scat_a])
+            st.scat_b = (C.c_double * 4)(*[float(x) for x in s.scat_b])
+            st.kappa = self.kappa
+            st.charge = float(charge)
+            st.absorption = float(absorption)
+            st.mean_inner_potential = float(mean_inner_potential)
+        aps = (C.c_int32 * n)(*[int(a) for a in angles_per_struct])
+        opts = _lib.Opts(STEPPERS[stepper], float(threshold), int(checkpoint_every), CONVENTIONS[convention])
+        h = C.c_void_p()
+        _lib.check(L.rheed_plan_create(C.byref(h), C.byref(opts), n, arr, aps), "plan_create")
+        self._h = h
+        info = _lib.PlanInfo()
+        _lib.check(L.rheed_plan_get_info(h, C.byref(info)), "plan_get_info")
+        self.info = info
+        self.n_pairs = info.n_pairs
+        self.max_beams = info.max_beams
+        offs = (C.c_int64 * (n + 1))()
+        _lib.check(L.rheed_plan_table_offsets(h, offs), "plan_table_offsets")
+        self.table_offsets = np.array(offs[:], dtype=np.int64)
+        aoffs = (C.c_int64 * (n + 1))()
+        _lib.check(L.rheed_plan_atom_offsets(h, aoffs), "plan_atom_offsets")
+        self.atom_offsets = np.array(aoffs[:], dtype=np.int64)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.lib().rheed_plan_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------------
+    def potential(self, atoms: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        _dev(atoms, torch.float64, "atoms")
+        if out is None:
+            out = torch.empty(int(self.info.table_elems), dtype=torch.complex128, device=atoms.device)
+        _lib.check(_lib.lib().rheed_potential(self._h, _ptr(atoms), _ptr(out), _stream()), "potential")
+        return out
+
+    def potential_backward(self, atoms: torch.Tensor, dL_dU: torch.Tensor) -> torch.Tensor:
+        _dev(atoms, torch.float64, "atoms")
+        _dev(dL_dU, torch.complex128, "dL_dU")
+        out = torch.empty_like(atoms)
+        _lib.check(_lib.lib().rheed_potential_backward(self._h, _ptr(atoms), _ptr(dL_dU), _ptr(out), _stream()),
+                   "potential_backward")
+        return out
+
+    def workspace(self, device) -> torch.Tensor:
+        nbytes = int(self.info.fwd_workspace + self.info.bwd_workspace)
+        return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+    def forward(self, U: torch.Tensor, angles: torch.Tensor, *, want_rho: bool = False,
+                workspace: Optional[torch.Tensor] = None, want_nrhst: bool = False):
+        _dev(U, torch.complex128, "U")
+        _dev(angles, torch.float64, "angles")
+        if angles.shape != (self.n_pairs, 2):
+            raise ValueError(f"angles must be [{self.n_pairs}, 2]")
+        dev = U.device
+        inten = torch.empty((self.n_pairs, self.max_beams), dtype=torch.float64, device=dev)
+        rho = torch.empty((self.n_pairs, self.max_beams), dtype=torch.complex128, device=dev) if want_rho else None
+        status = torch.empty(self.n_pairs, dtype=torch.int32, device=dev)
+        nrhst = torch.empty(self.n_pairs, dtype=torch.int32, device=dev) if want_nrhst else None
+        ws_bytes = 0 if workspace is None else workspace.numel()
+        _lib.check(_lib.lib().rheed_forward(self._h, _ptr(U), _ptr(angles), _ptr(inten), _ptr(rho), _ptr(status),
+                                            _ptr(nrhst), _ptr(workspace), ws_bytes, _stream()), "forward")
+        return {"intensity": inten, "rho": rho, "status": status, "n_rhst": nrhst}
+
+    def backward(self, U: torch.Tensor, angles: torch.Tensor, dL_dI: torch.Tensor,
+                 workspace: torch.Tensor) -> torch.Tensor:
+        _dev(U, torch.complex128, "U")
+        _dev(angles, torch.float64, "angles")
+        _dev(dL_dI, torch.float64, "dL_dI")
+        dU = torch.empty_like(U)
+        _lib.check(_lib.lib().rheed_backward(self._h, _ptr(U), _ptr(angles), _ptr(dL_dI), _ptr(dU),
+                                             _ptr(workspace), workspace.numel(), _stream()), "backward")
+        return dU
+
+
+def rfactor(intensity: torch.Tensor, target: torch.Tensor):
+    """loss = sum_p (I[p,0] - target[p])^2 (device scalar) and dL/dI."""
+    _dev(intensity, torch.float64, "intensity")
+    _dev(target, torch.float64, "target")
+    P, ld = intensity.shape
+    loss = torch.empty((), dtype=torch.float64, device=intensity.device)
+    dI = torch.empty_like(intensity)
+    _lib.check(_lib.lib().rheed_rfactor(P, ld, _ptr(intensity), _ptr(target), _ptr(loss), _ptr(dI), _stream()),
+               "rfactor")
+    return loss, dI
+
+
+# ----------------------------------------------------------------- helpers
+def plan_for(workload, stepper: Optional[str] = None, **kw) -> Plan:
+    """Plan over every structure of a workload, each with all its angles."""
+    return Plan(workload.structures, [len(workload.theta0)] * len(workload.structures),
+                energy_eV=workload.energy_eV, charge=workload.charge, absorption=workload.absorption,
+                mean_inner_potential=workload.mean_inner_potential, stepper=stepper or workload.stepper, **kw)
+
+
+def angles_for(workload, device) -> torch.Tensor:
+    th = np.asarray(workload.theta0, dtype=np.float64)
+    a = np.stack([th, np.full_like(th, workload.theta1)], axis=1)
+    a = np.tile(a, (len(workload.structures), 1))
+    return torch.from_numpy(a).to(device)
+
+
+def atoms_for(workload, device, structures=None) -> torch.Tensor:
+    structs = workload.structures if structures is None else structures
+    return torch.from_numpy(np.concatenate([np.asarray(s.atoms, dtype=np.float64) for s in structs])).to(device)

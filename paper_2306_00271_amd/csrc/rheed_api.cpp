@@ -1,0 +1,334 @@
+// Host side of the C ABI declared in include/rheed.h: argument validation,
+// plan construction (descriptor upload) and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <set>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/rheed.h"
+#include "rheed_internal.h"
+
+
+using namespace rheed;
+
+namespace {
+thread_local std::string g_last_error;
+
+rheed_status fail(rheed_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+rheed_status hip_fail(hipError_t e, const char* what) {
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return RHEED_E_HIP;
+}
+
+// CODATA 2018
+constexpr double kMe = 9.1093837015e-31, kQe = 1.602176634e-19, kHbar = 1.054571817e-34, kC = 299792458.0;
+}  // namespace
+
+struct rheed_plan_s {
+  rheed_opts opts{};
+  int n_struct = 0, n_pairs = 0, max_beams = 0, nodes_per_slice = 0;
+  double cset[4] = {0, 0, 0, 0};
+  long long table_elems = 0, n_atoms_total = 0, max_table = 0;
+  std::vector<StructDev> hs;
+  std::vector<int> beams, pair_struct;
+  std::vector<long long> table_off, atom_off, atom_struct;
+  CkptLayout ck{};
+  size_t fwd_ws = 0, bwd_ws = 0;
+  StructDev* d_structs = nullptr;
+  int* d_beams = nullptr;
+  int* d_pair_struct = nullptr;
+  long long* d_atom_struct = nullptr;
+};
+
+extern "C" {
+
+const char* rheed_status_string(rheed_status s) {
+  switch (s) {
+    case RHEED_OK: return "ok";
+    case RHEED_E_INVALID: return "invalid argument";
+    case RHEED_E_HIP: return "HIP runtime error";
+    case RHEED_E_NOMEM: return "out of memory";
+    case RHEED_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* rheed_last_error(void) { return g_last_error.c_str(); }
+
+rheed_status rheed_beam_constants(double energy_eV, double* gamma, double* kappa) {
+  if (!(energy_eV > 0.0) || !gamma || !kappa) return fail(RHEED_E_INVALID, "energy must be > 0 and outputs non-null");
+  const double e = kQe * energy_eV;
+  const double p2 = 2.0 * kMe * e * (1.0 + e / (2.0 * kMe * kC * kC));
+  *gamma = std::sqrt(p2) / kHbar * 1e-10;
+  *kappa = 2.0 * kMe * kQe / (kHbar * kHbar) * (1.0 + e / (kMe * kC * kC)) * 1e-20;
+  return RHEED_OK;
+}
+
+rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_t n_struct,
+                               const rheed_structure* structs, const int32_t* angles_per_struct) {
+  if (!out || !opts || !structs || !angles_per_struct || n_struct < 1)
+    return fail(RHEED_E_INVALID, "plan_create: null argument or n_struct < 1");
+  *out = nullptr;
+  if (opts->stepper != RHEED_RK4 && opts->stepper != RHEED_RK6) return fail(RHEED_E_INVALID, "unknown stepper");
+  if (!(opts->rhst_threshold >= 1.0)) return fail(RHEED_E_INVALID, "rhst_threshold must be >= 1");
+  if (opts->checkpoint_every < 1) return fail(RHEED_E_INVALID, "checkpoint_every must be >= 1");
+  if (opts->convention != RHEED_INTENSITY_FLUX && opts->convention != RHEED_INTENSITY_PAPER)
+    return fail(RHEED_E_INVALID, "unknown intensity convention");
+  auto* P = new rheed_plan_s();
+  P->opts = *opts;
+  P->n_struct = n_struct;
+  if (opts->stepper == RHEED_RK4) {
+    P->nodes_per_slice = 2;
+    P->cset[0] = 0.0;
+    P->cset[1] = 0.5;
+  } else {
+    P->nodes_per_slice = 4;
+    P->cset[0] = 0.0;
+    P->cset[1] = 1.0 / 3.0;
+    P->cset[2] = 0.5;
+    P->cset[3] = 2.0 / 3.0;
+  }
+  int max_l = 0;
+  for (int s = 0; s < n_struct; ++s) {
+    const rheed_structure& st = structs[s];
+    char buf[256];
+    if (st.n_beams < 1 || st.n_beams > RHEED_MAX_BEAMS || !st.beam_hk) {
+      snprintf(buf, sizeof buf, "structure %d: n_beams must be in [1, %d]", s, RHEED_MAX_BEAMS);
+      delete P;
+      return fail(RHEED_E_UNSUPPORTED, buf);
+    }
+    if (st.beam_hk[0] != 0 || st.beam_hk[1] != 0) {
+      delete P;
+      return fail(RHEED_E_INVALID, "structure " + std::to_string(s) + ": beam 0 must be (0, 0)");
+    }
+    if (st.n_slices < 1 || !(st.thickness > 0.0) || !(st.wavenumber > 0.0) || angles_per_struct[s] < 1) {
+      delete P;
+      return fail(RHEED_E_INVALID, "structure " + std::to_string(s) + ": need n_slices >= 1, thickness > 0, "
+                                   "wavenumber > 0 and at least one angle");
+    }
+    std::set<std::pair<int, int>> seen;
+    int hmin = st.beam_hk[0], hmax = hmin, kmin = st.beam_hk[1], kmax = kmin;
+    for (int j = 0; j < st.n_beams; ++j) {
+      const int h = st.beam_hk[2 * j], k = st.beam_hk[2 * j + 1];
+      if (!seen.insert({h, k}).second) {
+        delete P;
+        return fail(RHEED_E_INVALID, "structure " + std::to_string(s) + ": duplicate beam");
+      }
+      hmin = std::min(hmin, h);
+      hmax = std::max(hmax, h);
+      kmin = std::min(kmin, k);
+      kmax = std::max(kmax, k);
+    }
+    StructDev d{};
+    d.n_beams = st.n_beams;
+    d.n_slices = st.n_slices;
+    d.hd = hmax - hmin;
+    d.kd = kmax - kmin;
+    d.box = (2 * d.hd + 1) * (2 * d.kd + 1);
+    if (d.box > MAXBOX) {
+      delete P;
+      return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) + ": rod-difference table row of " +
+                                           std::to_string(d.box) + " entries exceeds " + std::to_string(MAXBOX));
+    }
+    d.n_nodes = st.n_slices * P->nodes_per_slice + 1;
+    d.n_atoms = std::max(0, st.n_atoms);
+    d.beam_off = (int)(P->beams.size() / 2);
+    for (int j = 0; j < 2 * st.n_beams; ++j) P->beams.push_back(st.beam_hk[j]);
+    d.pair_off = P->n_pairs;
+    d.n_angles = angles_per_struct[s];
+    d.h = st.thickness / st.n_slices;
+    d.thickness = st.thickness;
+    d.gamma = st.wavenumber;
+    for (int c = 0; c < 4; ++c) d.recip[c] = st.recip[c];
+    d.table_off = P->table_elems;
+    d.atom_off = P->n_atoms_total;
+    for (int m = 0; m < 4; ++m) {
+      d.scat_a[m] = st.scat_a[m];
+      d.scat_b[m] = st.scat_b[m];
+    }
+    // slab-mean rescaling s (position independent) and u = kappa s (charge - i alpha) V_g
+    if (d.n_atoms > 0) {
+      double per_atom = 0.0;
+      for (int m = 0; m < 4; ++m) {
+        if (!(st.scat_b[m] > 0.0)) {
+          delete P;
+          return fail(RHEED_E_INVALID, "structure " + std::to_string(s) + ": scat_b must be > 0");
+        }
+        per_atom += st.scat_a[m] * std::pow(M_PI / st.scat_b[m], 1.5);
+      }
+      if (!(st.cell_area > 0.0) || per_atom == 0.0) {
+        delete P;
+        return fail(RHEED_E_INVALID, "structure " + std::to_string(s) + ": bad potential model");
+      }
+      const double raw = d.n_atoms * per_atom / (st.cell_area * st.thickness);
+      const double sc = st.mean_inner_potential / raw;
+      d.pref_re = st.kappa * sc * st.charge / st.cell_area;
+      d.pref_im = -st.kappa * sc * st.absorption / st.cell_area;
+    }
+    P->hs.push_back(d);
+    P->table_off.push_back(P->table_elems);
+    P->atom_off.push_back(P->n_atoms_total);
+    for (int a = 0; a < d.n_atoms; ++a) P->atom_struct.push_back(s);
+    P->table_elems += (long long)d.n_nodes * d.box;
+    P->max_table = std::max(P->max_table, (long long)d.n_nodes * d.box);
+    P->n_atoms_total += d.n_atoms;
+    for (int a = 0; a < angles_per_struct[s]; ++a) P->pair_struct.push_back(s);
+    P->n_pairs += angles_per_struct[s];
+    P->max_beams = std::max(P->max_beams, st.n_beams);
+    max_l = std::max(max_l, st.n_slices);
+  }
+  P->table_off.push_back(P->table_elems);
+  P->atom_off.push_back(P->n_atoms_total);
+  // per-pair checkpoint block: states at the start of every segment + one byte per slice
+  P->ck.every = opts->checkpoint_every;
+  P->ck.max_ckpt = (max_l + opts->checkpoint_every - 1) / opts->checkpoint_every;
+  P->ck.state_bytes = (long long)2 * NP * NP * sizeof(double2);
+  P->ck.flags_off = P->ck.max_ckpt * P->ck.state_bytes;
+  P->ck.pair_stride = ((P->ck.flags_off + max_l + 255) / 256) * 256;
+  P->fwd_ws = (size_t)P->ck.pair_stride * P->n_pairs;
+  P->bwd_ws = 0;
+
+  hipError_t e;
+  if ((e = hipMalloc(&P->d_structs, sizeof(StructDev) * P->hs.size())) != hipSuccess ||
+      (e = hipMalloc(&P->d_beams, sizeof(int) * P->beams.size())) != hipSuccess ||
+      (e = hipMalloc(&P->d_pair_struct, sizeof(int) * P->pair_struct.size())) != hipSuccess ||
+      (e = hipMalloc(&P->d_atom_struct, sizeof(long long) * std::max<size_t>(1, P->atom_struct.size()))) != hipSuccess) {
+    rheed_plan_destroy(P);
+    return e == hipErrorOutOfMemory ? fail(RHEED_E_NOMEM, "plan_create: device allocation") : hip_fail(e, "hipMalloc");
+  }
+  if ((e = hipMemcpy(P->d_structs, P->hs.data(), sizeof(StructDev) * P->hs.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(P->d_beams, P->beams.data(), sizeof(int) * P->beams.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(P->d_pair_struct, P->pair_struct.data(), sizeof(int) * P->pair_struct.size(),
+                     hipMemcpyHostToDevice)) != hipSuccess ||
+      (!P->atom_struct.empty() &&
+       (e = hipMemcpy(P->d_atom_struct, P->atom_struct.data(), sizeof(long long) * P->atom_struct.size(),
+                      hipMemcpyHostToDevice)) != hipSuccess)) {
+    rheed_plan_destroy(P);
+    return hip_fail(e, "hipMemcpy");
+  }
+  *out = P;
+  return RHEED_OK;
+}
+
+rheed_status rheed_plan_destroy(rheed_plan_t P) {
+  if (!P) return RHEED_OK;
+  if (P->d_structs) (void)hipFree(P->d_structs);
+  if (P->d_beams) (void)hipFree(P->d_beams);
+  if (P->d_pair_struct) (void)hipFree(P->d_pair_struct);
+  if (P->d_atom_struct) (void)hipFree(P->d_atom_struct);
+  delete P;
+  return RHEED_OK;
+}
+
+rheed_status rheed_plan_get_info(rheed_plan_t P, rheed_plan_info* info) {
+  if (!P || !info) return fail(RHEED_E_INVALID, "plan_get_info: null argument");
+  info->n_struct = P->n_struct;
+  info->n_pairs = P->n_pairs;
+  info->max_beams = P->max_beams;
+  info->nodes_per_slice = P->nodes_per_slice;
+  info->table_elems = P->table_elems;
+  info->n_atoms_total = P->n_atoms_total;
+  info->fwd_workspace = P->fwd_ws;
+  info->bwd_workspace = P->bwd_ws;
+  return RHEED_OK;
+}
+
+rheed_status rheed_plan_table_offsets(rheed_plan_t P, int64_t* out) {
+  if (!P || !out) return fail(RHEED_E_INVALID, "plan_table_offsets: null argument");
+  for (size_t i = 0; i < P->table_off.size(); ++i) out[i] = P->table_off[i];
+  return RHEED_OK;
+}
+
+rheed_status rheed_plan_atom_offsets(rheed_plan_t P, int64_t* out) {
+  if (!P || !out) return fail(RHEED_E_INVALID, "plan_atom_offsets: null argument");
+  for (size_t i = 0; i < P->atom_off.size(); ++i) out[i] = P->atom_off[i];
+  return RHEED_OK;
+}
+
+rheed_status rheed_potential(rheed_plan_t P, const double* atoms, void* U_tables, void* stream) {
+  if (!P || !U_tables || (P->n_atoms_total > 0 && !atoms)) return fail(RHEED_E_INVALID, "potential: null argument");
+  PotArgs a{};
+  a.structs = P->d_structs;
+  a.atoms = atoms;
+  a.U = static_cast<double2*>(U_tables);
+  a.n_struct = P->n_struct;
+  a.nodes_per_slice = P->nodes_per_slice;
+  for (int c = 0; c < 4; ++c) a.cset[c] = P->cset[c];
+  hipError_t e = launch_potential(a, P->max_table, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? RHEED_OK : hip_fail(e, "potential launch");
+}
+
+rheed_status rheed_potential_backward(rheed_plan_t P, const double* atoms, const void* dL_dU, double* dL_datoms,
+                                      void* stream) {
+  if (!P || !dL_dU || (P->n_atoms_total > 0 && (!atoms || !dL_datoms)))
+    return fail(RHEED_E_INVALID, "potential_backward: null argument");
+  if (P->n_atoms_total == 0) return RHEED_OK;
+  PotBwdArgs a{};
+  a.structs = P->d_structs;
+  a.atoms = atoms;
+  a.dU = static_cast<const double2*>(dL_dU);
+  a.datoms = dL_datoms;
+  a.nodes_per_slice = P->nodes_per_slice;
+  for (int c = 0; c < 4; ++c) a.cset[c] = P->cset[c];
+  hipError_t e = launch_potential_bwd(a, P->n_atoms_total, P->n_struct, P->d_atom_struct,
+                                      static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? RHEED_OK : hip_fail(e, "potential_backward launch");
+}
+
+rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* angles, double* intensity, void* rho,
+                           int32_t* pair_status, int32_t* n_rhst, void* workspace, size_t ws_bytes, void* stream) {
+  if (!P || !U_tables || !angles || !intensity || !pair_status) return fail(RHEED_E_INVALID, "forward: null argument");
+  if (workspace && ws_bytes < P->fwd_ws)
+    return fail(RHEED_E_INVALID, "forward: workspace of " + std::to_string(ws_bytes) + " bytes < " +
+                                     std::to_string(P->fwd_ws));
+  FwdArgs a{};
+  a.structs = P->d_structs;
+  a.pair_struct = P->d_pair_struct;
+  a.beams = P->d_beams;
+  a.U = static_cast<const double2*>(U_tables);
+  a.angles = angles;
+  a.intensity = intensity;
+  a.rho = static_cast<double2*>(rho);
+  a.status = pair_status;
+  a.nrhst = n_rhst;
+  a.ws = static_cast<char*>(workspace);
+  a.ck = P->ck;
+  a.ld = P->max_beams;
+  a.convention = (int)P->opts.convention;
+  a.n_pairs = P->n_pairs;
+  a.threshold = P->opts.rhst_threshold;
+  hipError_t e = launch_forward((int)P->opts.stepper, a, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? RHEED_OK : hip_fail(e, "forward launch");
+}
+
+rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* angles, const double* dL_dI,
+                            void* dL_dU, void* workspace, size_t ws_bytes, void* stream) {
+  (void)U_tables;
+  (void)angles;
+  (void)dL_dI;
+  (void)dL_dU;
+  (void)workspace;
+  (void)ws_bytes;
+  (void)stream;
+  if (!P) return fail(RHEED_E_INVALID, "backward: null plan");
+  return fail(RHEED_E_UNSUPPORTED, "backward: not available in this build");
+}
+
+rheed_status rheed_rfactor(int32_t n_pairs, int32_t ld, const double* intensity, const double* target, double* loss,
+                           double* dL_dI, void* stream) {
+  if (n_pairs < 1 || ld < 1 || !intensity || !target || (!loss && !dL_dI))
+    return fail(RHEED_E_INVALID, "rfactor: bad argument");
+  hipError_t e = launch_rfactor(n_pairs, ld, intensity, target, loss, dL_dI, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? RHEED_OK : hip_fail(e, "rfactor launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,525 @@
+// Forward propagation of the many-beam reflection problem on gfx950.
+//
+// One workgroup (4 waves, one per SIMD) owns one (structure, angle) pair for
+// N <= 64 beams, padded to 64.  Of the economical-form state Z = [c; c']
+// (Sec. 3.1, Eq. mateq2; the paper's Q-hat and P-hat) the upper block c lives
+// in LDS, while c' and the stage products live in registers: wave w holds rows
+// 16w .. 16w+15 of every 64 x 64 block, laid out as the output of
+// v_mfma_f64_16x16x4f64 (lane l, value v of J-tile jt -> row 16w + 4v + (l>>4),
+// column 16 jt + (l&15)), so element e = 4 jt + v of a register matrix sits at
+// LDS index ob + 256 v + 16 jt with ob = (16w + (l>>4)) 64 + (l&15).
+//
+// One explicit RK step (Sec. 3.4) on y = (c, c'), y' = [[0, I], [-M, 0]] y
+// with M(z) = U(z) + Gamma^2, reduces to products G_r = M(z_i + c_r h) X_r
+// with stage inputs X_r = c + h c_r c' - h^2 sum_m (A^2)_{rm} G_m, and
+//   c  <- c + h c' - h^2 sum_m (bA)_m G_m,   c' <- c' - h sum_m b_m G_m.
+// The stages are ordered so that at most three (RK4) or four (RK6) 64 x 64
+// matrices are live in registers at any time.  Each product is a complex
+// 64 x 64 x 64 GEMM on FP64 MFMA in the 3-real-product form: the B operand is
+// the stage input in LDS (the first stage reads c itself), the A operand
+// U_{jk} = u_{g_j - g_k} is gathered from the node's rod-difference table in
+// LDS (all angles of a structure share these tables; their coupling matrices
+// differ only in the diagonal Gamma^2), and each wave runs its four J-tiles
+// as twelve independent accumulation chains.
+//
+// After every slice the Gershgorin estimate xi of cond(Q) (Sec. 3.2) decides
+// the right-hand-side transformation Z <- Z Q^{-1}, done as a column Gauss-
+// Jordan elimination with partial pivoting on [Q; P] in LDS.  The final
+// reflection (Algorithm 1, last lines) applies the same elimination to
+// [Gamma Q - iP; Gamma Q + iP].
+#include "rheed_internal.h"
+
+namespace rheed {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+struct Mat {
+  double r[16];
+  double i[16];
+};
+
+template <int S>
+struct Tab;
+template <>
+struct Tab<0> {  // classical RK4: c = 0, 1/2, 1/2, 1
+  static constexpr int nodes = 2;  // distinct c in [0, 1)
+  static constexpr int slots = 3;
+};
+template <>
+struct Tab<1> {  // Butcher's 6th order, 7 stages: c = 0, 1/3, 2/3, 1/3, 1/2, 1/2, 1
+  static constexpr int nodes = 4;  // 0, 1/3, 1/2, 2/3
+  static constexpr int slots = 5;
+};
+
+struct Lds {
+  double2 xb[2 * NP * NP];   // [c; X]: c block and stage-input buffer; [Q; P] during eliminations
+  double2 tb[5][MAXBOX + 1]; // node tables (Ur, Ui); entry `box` of every row stays 0
+  double2 gj_colp[2 * NP];   // elimination scratch: pivot column
+  double2 gj_colk[2 * NP];   //   column k
+  double2 gj_rowk[NP];       //   row k
+  double g2s[NP];            // Gamma_j^2 (real), 0 on padding
+  int bhk[NP][2];
+  double xi_hi[NWAVES], xi_lo[NWAVES];
+  int flag_singular;
+};
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// G = (U(node) + Gamma^2) X for the wave's 16 x 64 row block, X read from LDS;
+// every element of G is handed to epi(e, Re G, Im G).
+template <class Epi>
+__device__ __forceinline__ void stage_gemm(const double2* __restrict__ xbuf, const double2* __restrict__ tslot,
+                                           const unsigned (&gidx)[8], const double (&g2)[4], int ob, int lane,
+                                           Epi&& epi) {
+  __builtin_amdgcn_sched_barrier(0);
+  d4 t1[4], t2[4], t3[4];
+#pragma unroll
+  for (int jt = 0; jt < 4; ++jt) t1[jt] = t2[jt] = t3[jt] = d4{0, 0, 0, 0};
+  const int bb = (lane >> 4) * NP + (lane & 15);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const unsigned gi = (q & 1) ? (gidx[q >> 1] >> 16) : (gidx[q >> 1] & 0xffffu);
+    const double2 u = tslot[gi];
+    const double us = u.x + u.y;
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) {
+      const double2 x = xbuf[bb + 256 * q + 16 * jt];
+      t1[jt] = mfma(u.x, x.x, t1[jt]);
+      t2[jt] = mfma(u.y, x.y, t2[jt]);
+      t3[jt] = mfma(us, x.x + x.y, t3[jt]);
+    }
+    if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int jt = 0; jt < 4; ++jt) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double2 own = xbuf[ob + 256 * v + 16 * jt];
+      epi(jt * 4 + v, (t1[jt][v] - t2[jt][v]) + g2[v] * own.x,
+          (t3[jt][v] - t1[jt][v] - t2[jt][v]) + g2[v] * own.y);
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+#define OWN(e) (ob + 256 * ((e) & 3) + 16 * ((e) >> 2))
+
+__device__ __forceinline__ void store_mat(double2* buf, const Mat& m, int ob) {
+#pragma unroll
+  for (int e = 0; e < 16; ++e) buf[OWN(e)] = make_double2(m.r[e], m.i[e]);
+}
+
+// Wave-wide argmax of v (ties -> smaller index).
+__device__ __forceinline__ void wave_argmax(double& v, int& idx) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double ov = __shfl_xor(v, off, 64);
+    const int oi = __shfl_xor(idx, off, 64);
+    if (ov > v || (ov == v && oi < idx)) {
+      v = ov;
+      idx = oi;
+    }
+  }
+}
+
+// Column Gauss-Jordan with partial pivoting on Z = xb viewed as [128][64]:
+// right-multiplies Z until its top block is I, so the bottom block becomes
+// bottom * top^{-1}.  Only the leading n columns / pivots are processed.
+// Each step copies the pivot column, column k and row k to LDS scratch, so
+// that the update of every element reads only its own old value and copies.
+__device__ void gauss_jordan(Lds& s, int n, int tid) {
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int j = lane;
+  double2* Z = s.xb;
+  for (int k = 0; k < n; ++k) {
+    const double2 zk = Z[k * NP + lane];
+    double m2 = (lane >= k && lane < n) ? zk.x * zk.x + zk.y * zk.y : -1.0;
+    int bi = lane;
+    wave_argmax(m2, bi);
+    if (!(m2 > 0.0) && tid == 0) s.flag_singular = 1;
+    if (tid < 2 * NP) {
+      s.gj_colp[tid] = Z[tid * NP + bi];
+      s.gj_colk[tid] = Z[tid * NP + k];
+    } else if (tid < 3 * NP) {
+      s.gj_rowk[tid - 2 * NP] = Z[k * NP + (tid - 2 * NP)];
+    }
+    __syncthreads();
+    if (j < n) {
+      const double2 piv = s.gj_rowk[bi];
+      const double pn = piv.x * piv.x + piv.y * piv.y;
+      const double2 ip = make_double2(piv.x / pn, -piv.y / pn);
+      const double2 mj = s.gj_rowk[j == bi ? k : j];
+      const double2 f = make_double2(mj.x * ip.x - mj.y * ip.y, mj.x * ip.y + mj.y * ip.x);
+      for (int m = 0; m < 2 * NP / NWAVES; ++m) {
+        const int r = w + NWAVES * m;
+        const double2 zp = s.gj_colp[r];
+        const double2 zo = (j == bi) ? s.gj_colk[r] : Z[r * NP + j];
+        double2 nv;
+        if (j == k) {
+          nv = make_double2(zp.x * ip.x - zp.y * ip.y, zp.x * ip.y + zp.y * ip.x);
+        } else {
+          nv = make_double2(zo.x - (f.x * zp.x - f.y * zp.y), zo.y - (f.x * zp.y + f.y * zp.x));
+        }
+        Z[r * NP + j] = nv;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Loads nodes [n0, n1) of a structure's table into their ring slots.
+template <int SLOTS>
+__device__ __forceinline__ void load_nodes(Lds& s, const double2* __restrict__ Us, int box, int n0, int n1, int tid) {
+  const int total = (n1 - n0) * box;
+  for (int e = tid; e < total; e += NTHREADS) {
+    const int q = e / box;
+    const int nn = n0 + q;
+    s.tb[nn % SLOTS][e - q * box] = Us[(long long)nn * box + (e - q * box)];
+  }
+}
+
+template <int STEPPER>
+__global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
+  using T = Tab<STEPPER>;
+  __shared__ Lds s;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int p = blockIdx.x;
+  const StructDev S = a.structs[a.pair_struct[p]];
+  const int N = S.n_beams;
+  const int L = S.n_slices;
+  const double h = S.h;
+  const double2* __restrict__ Us = a.U + S.table_off;
+
+  if (tid < NP) {
+    s.bhk[tid][0] = tid < N ? a.beams[2 * (S.beam_off + tid)] : 0;
+    s.bhk[tid][1] = tid < N ? a.beams[2 * (S.beam_off + tid) + 1] : 0;
+  }
+  if (tid == 0) s.flag_singular = 0;
+  if (tid < T::slots) s.tb[tid][S.box] = make_double2(0.0, 0.0);
+  __syncthreads();
+
+  // incidence: b0 = gamma cos(theta0) (cos theta1, sin theta1)
+  const double th0 = a.angles[2 * p], th1 = a.angles[2 * p + 1];
+  const double b0x = S.gamma * cos(th0) * cos(th1);
+  const double b0y = S.gamma * cos(th0) * sin(th1);
+  // Gamma_j^2 = gamma^2 - |b0 + k_j|^2 (real; Sec. 2.1, Eq. sch3), 0 on padding
+  if (tid < NP) {
+    double arg = 0.0;
+    if (tid < N) {
+      const double qx = b0x + s.bhk[tid][0] * S.recip[0] + s.bhk[tid][1] * S.recip[2];
+      const double qy = b0y + s.bhk[tid][0] * S.recip[1] + s.bhk[tid][1] * S.recip[3];
+      arg = S.gamma * S.gamma - (qx * qx + qy * qy);
+    }
+    s.g2s[tid] = arg;
+  }
+  __syncthreads();
+  double g2[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) g2[v] = s.g2s[16 * w + 4 * v + (lane >> 4)];
+  // gather indices of U_{ik} = u_{g_i - g_k} for the A operand of this lane
+  unsigned gidx[8];
+  {
+    const int W = 2 * S.kd + 1;
+    const int iA = 16 * w + (lane & 15);
+    const int baseA = (s.bhk[iA][0] + S.hd) * W + (s.bhk[iA][1] + S.kd);
+#pragma unroll
+    for (int q = 0; q < 16; q += 2) {
+      const int k0 = 4 * q + (lane >> 4), k1 = 4 * (q + 1) + (lane >> 4);
+      const unsigned i0 = (iA < N && k0 < N) ? baseA - (s.bhk[k0][0] * W + s.bhk[k0][1]) : S.box;
+      const unsigned i1 = (iA < N && k1 < N) ? baseA - (s.bhk[k1][0] * W + s.bhk[k1][1]) : S.box;
+      gidx[q >> 1] = i0 | (i1 << 16);
+    }
+  }
+  double2* cb = s.xb;             // c (upper block of Z), LDS resident
+  double2* xb = s.xb + NP * NP;   // stage input X_r
+  int ob = (16 * w + (lane >> 4)) * NP + (lane & 15);
+  // Z0 = [I; i Gamma]  (spans the same columns as S^{-1}[I; O] of Algorithm 1)
+  Mat d;
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int row = 16 * w + 4 * (e & 3) + (lane >> 4), col = 16 * (e >> 2) + (lane & 15);
+    const bool dg = (row == col);
+    cb[OWN(e)] = make_double2(dg ? 1.0 : 0.0, 0.0);
+    // i Gamma_row with Gamma = sqrt(g2) (open) or -i sqrt(-g2) (evanescent)
+    const double g2v = g2[e & 3];
+    d.r[e] = (dg && g2v < 0.0) ? sqrt(-g2v) : 0.0;
+    d.i[e] = (dg && g2v >= 0.0) ? sqrt(g2v) : 0.0;
+  }
+  const bool save = a.ws != nullptr;
+  char* pws = save ? a.ws + (long long)p * a.ck.pair_stride : nullptr;
+  int nrhst = 0;
+
+  load_nodes<T::slots>(s, Us, S.box, 0, 1, tid);
+  for (int i = 0; i < L; ++i) {
+    // keep the address base from being expanded into loop-invariant registers
+    asm volatile("" : "+v"(ob));
+    if (save && (i % a.ck.every) == 0) {
+      double2* st = reinterpret_cast<double2*>(pws + (long long)(i / a.ck.every) * a.ck.state_bytes);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        st[OWN(e)] = cb[OWN(e)];
+        st[NP * NP + OWN(e)] = make_double2(d.r[e], d.i[e]);
+      }
+    }
+    const int nb = i * T::nodes;  // node index of c = 0 in this slice
+    load_nodes<T::slots>(s, Us, S.box, nb + 1, nb + T::nodes + 1, tid);
+    const double hh = h * h;
+    if constexpr (STEPPER == 0) {
+      const double2* t0 = s.tb[nb % 3];
+      const double2* th = s.tb[(nb + 1) % 3];
+      const double2* t1 = s.tb[(nb + 2) % 3];
+      // X1 = c (read in place), X2 = c + h/2 c'
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const double2 cv = cb[OWN(e)];
+        xb[OWN(e)] = make_double2(cv.x + 0.5 * h * d.r[e], cv.y + 0.5 * h * d.i[e]);
+      }
+      __syncthreads();
+      Mat G1, G2;
+      stage_gemm(cb, t0, gidx, g2, ob, lane, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
+      stage_gemm(xb, th, gidx, g2, ob, lane, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
+      __syncthreads();
+      // X3 = c + h/2 c' - h^2/4 G1 -> LDS;  X4 = c + h c' - h^2/2 G2 (kept in G1);
+      // c <- c + h c' - h^2/6 (G1 + G2);  c' <- c' - h/6 (G1 + 2 G2)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const double2 cv = cb[OWN(e)];
+        const double dr = d.r[e], di = d.i[e];
+        const double g1r = G1.r[e], g1i = G1.i[e], g2r = G2.r[e], g2i = G2.i[e];
+        xb[OWN(e)] = make_double2(cv.x + 0.5 * h * dr - 0.25 * hh * g1r, cv.y + 0.5 * h * di - 0.25 * hh * g1i);
+        G1.r[e] = cv.x + h * dr - 0.5 * hh * g2r;
+        G1.i[e] = cv.y + h * di - 0.5 * hh * g2i;
+        cb[OWN(e)] = make_double2(cv.x + h * dr - (hh / 6.0) * (g1r + g2r), cv.y + h * di - (hh / 6.0) * (g1i + g2i));
+        d.r[e] = dr - (h / 6.0) * (g1r + 2.0 * g2r);
+        d.i[e] = di - (h / 6.0) * (g1i + 2.0 * g2i);
+      }
+      __syncthreads();
+      stage_gemm(xb, th, gidx, g2, ob, lane, [&](int e, double gr, double gi) {  // G3
+        double2 cv = cb[OWN(e)];
+        cv.x -= (hh / 6.0) * gr;
+        cv.y -= (hh / 6.0) * gi;
+        cb[OWN(e)] = cv;
+        d.r[e] -= (h / 3.0) * gr;
+        d.i[e] -= (h / 3.0) * gi;
+      });
+      __syncthreads();
+      store_mat(xb, G1, ob);  // X4
+      __syncthreads();
+      stage_gemm(xb, t1, gidx, g2, ob, lane, [&](int e, double gr, double gi) {  // G4
+        d.r[e] -= (h / 6.0) * gr;
+        d.i[e] -= (h / 6.0) * gi;
+      });
+    } else {
+      const double2* tA = s.tb[nb % 5];        // c = 0
+      const double2* tB = s.tb[(nb + 1) % 5];  // c = 1/3
+      const double2* tC = s.tb[(nb + 2) % 5];  // c = 1/2
+      const double2* tD = s.tb[(nb + 3) % 5];  // c = 2/3
+      const double2* tE = s.tb[(nb + 4) % 5];  // c = 1
+      // X1 = c (read in place), X2 = c + h/3 c'
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const double2 cv = cb[OWN(e)];
+        xb[OWN(e)] = make_double2(cv.x + (h / 3.0) * d.r[e], cv.y + (h / 3.0) * d.i[e]);
+      }
+      __syncthreads();
+      Mat G1, G2, G3;
+      stage_gemm(cb, tA, gidx, g2, ob, lane, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
+      stage_gemm(xb, tB, gidx, g2, ob, lane, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
+      __syncthreads();
+      // X3 = c + 2h/3 c' - h^2 (2/9) G1
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const double2 cv = cb[OWN(e)];
+        xb[OWN(e)] = make_double2(cv.x + (2.0 * h / 3.0) * d.r[e] - hh * (2.0 / 9.0) * G1.r[e],
+                                  cv.y + (2.0 * h / 3.0) * d.i[e] - hh * (2.0 / 9.0) * G1.i[e]);
+      }
+      __syncthreads();
+      stage_gemm(xb, tD, gidx, g2, ob, lane, [&](int e, double gr, double gi) { G3.r[e] = gr; G3.i[e] = gi; });
+      __syncthreads();
+      // X4 = c + h/3 c' - h^2 (G1/9 - G2/18)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const double2 cv = cb[OWN(e)];
+        xb[OWN(e)] = make_double2(cv.x + (h / 3.0) * d.r[e] - hh * ((1.0 / 9.0) * G1.r[e] - (1.0 / 18.0) * G2.r[e]),
+                                  cv.y + (h / 3.0) * d.i[e] - hh * ((1.0 / 9.0) * G1.i[e] - (1.0 / 18.0) * G2.i[e]));
+      }
+      __syncthreads();
+      // G4; per element {c, c', G1, G2, G3, G4} -> X5, X6, T7, c-partial (LDS), c'-partial
+      Mat& X5 = G1;
+      Mat& X6 = G2;
+      Mat& T7 = G3;
+      stage_gemm(xb, tB, gidx, g2, ob, lane, [&](int e, double a4, double b4) {
+        const double2 cv = cb[OWN(e)];
+        const double dr = d.r[e], di = d.i[e];
+        const double a1 = G1.r[e], b1 = G1.i[e], a2 = G2.r[e], b2 = G2.i[e], a3 = G3.r[e], b3 = G3.i[e];
+        X5.r[e] = cv.x + 0.5 * h * dr - hh * ((11.0 / 32.0) * a1 - 0.25 * a2 + (1.0 / 32.0) * a3);
+        X5.i[e] = cv.y + 0.5 * h * di - hh * ((11.0 / 32.0) * b1 - 0.25 * b2 + (1.0 / 32.0) * b3);
+        X6.r[e] = cv.x + 0.5 * h * dr - hh * ((9.0 / 32.0) * a1 + (1.0 / 16.0) * a2 - (1.0 / 32.0) * a3 - (3.0 / 16.0) * a4);
+        X6.i[e] = cv.y + 0.5 * h * di - hh * ((9.0 / 32.0) * b1 + (1.0 / 16.0) * b2 - (1.0 / 32.0) * b3 - (3.0 / 16.0) * b4);
+        T7.r[e] = cv.x + h * dr - hh * ((-3.0 / 22.0) * a1 - (3.0 / 22.0) * a2 + (9.0 / 22.0) * a3 + (12.0 / 11.0) * a4);
+        T7.i[e] = cv.y + h * di - hh * ((-3.0 / 22.0) * b1 - (3.0 / 22.0) * b2 + (9.0 / 22.0) * b3 + (12.0 / 11.0) * b4);
+        cb[OWN(e)] = make_double2(cv.x + h * dr - hh * ((11.0 / 120.0) * a1 + (9.0 / 40.0) * a3 + (9.0 / 20.0) * a4),
+                                  cv.y + h * di - hh * ((11.0 / 120.0) * b1 + (9.0 / 40.0) * b3 + (9.0 / 20.0) * b4));
+        d.r[e] = dr - h * ((11.0 / 120.0) * a1 + (27.0 / 40.0) * a3 + (27.0 / 40.0) * a4);
+        d.i[e] = di - h * ((11.0 / 120.0) * b1 + (27.0 / 40.0) * b3 + (27.0 / 40.0) * b4);
+      });
+      __syncthreads();
+      store_mat(xb, X5, ob);
+      __syncthreads();
+      stage_gemm(xb, tC, gidx, g2, ob, lane, [&](int e, double gr, double gi) {  // G5
+        T7.r[e] += hh * (8.0 / 11.0) * gr;
+        T7.i[e] += hh * (8.0 / 11.0) * gi;
+        double2 cv = cb[OWN(e)];
+        cv.x += hh * (2.0 / 15.0) * gr;
+        cv.y += hh * (2.0 / 15.0) * gi;
+        cb[OWN(e)] = cv;
+        d.r[e] += h * (4.0 / 15.0) * gr;
+        d.i[e] += h * (4.0 / 15.0) * gi;
+      });
+      __syncthreads();
+      store_mat(xb, X6, ob);
+      __syncthreads();
+      stage_gemm(xb, tC, gidx, g2, ob, lane, [&](int e, double gr, double gi) {  // G6
+        double2 cv = cb[OWN(e)];
+        cv.x += hh * (2.0 / 15.0) * gr;
+        cv.y += hh * (2.0 / 15.0) * gi;
+        cb[OWN(e)] = cv;
+        d.r[e] += h * (4.0 / 15.0) * gr;
+        d.i[e] += h * (4.0 / 15.0) * gi;
+      });
+      __syncthreads();
+      store_mat(xb, T7, ob);  // X7
+      __syncthreads();
+      stage_gemm(xb, tE, gidx, g2, ob, lane, [&](int e, double gr, double gi) {  // G7
+        d.r[e] -= h * (11.0 / 120.0) * gr;
+        d.i[e] -= h * (11.0 / 120.0) * gi;
+      });
+    }
+
+    // condition estimate of Q = c over rows/cols < N (Sec. 3.2): the
+    // Gershgorin / Varah bound max(|q_ii| + r_i) / min(|q_ii| - r_i)
+    {
+      double dg[4] = {0, 0, 0, 0}, of[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = 16 * w + 4 * (e & 3) + (lane >> 4), col = 16 * (e >> 2) + (lane & 15);
+        const double2 cv = cb[OWN(e)];
+        const double av = sqrt(cv.x * cv.x + cv.y * cv.y);
+        if (row < N && col < N) {
+          if (row == col) dg[e & 3] += av;
+          else of[e & 3] += av;
+        }
+      }
+      double hi = 0.0, lo = 1.0e308;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+          dg[v] += __shfl_xor(dg[v], off, 64);
+          of[v] += __shfl_xor(of[v], off, 64);
+        }
+        const int row = 16 * w + 4 * v + (lane >> 4);
+        if (row < N) {
+          hi = fmax(hi, dg[v] + of[v]);
+          lo = fmin(lo, dg[v] - of[v]);
+        }
+      }
+#pragma unroll
+      for (int off = 16; off < 64; off <<= 1) {
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+      }
+      if (lane == 0) {
+        s.xi_hi[w] = hi;
+        s.xi_lo[w] = lo;
+      }
+    }
+    __syncthreads();
+    bool do_rhst;
+    {
+      double hi = s.xi_hi[0], lo = s.xi_lo[0];
+#pragma unroll
+      for (int ww = 1; ww < NWAVES; ++ww) {
+        hi = fmax(hi, s.xi_hi[ww]);
+        lo = fmin(lo, s.xi_lo[ww]);
+      }
+      const double xi = lo > 0.0 ? hi / lo : INFINITY;
+      do_rhst = xi > a.threshold;
+    }
+    if (save && tid == 0) pws[a.ck.flags_off + i] = do_rhst ? 1 : 0;
+    if (do_rhst) {
+      ++nrhst;
+      store_mat(xb, d, ob);
+      __syncthreads();
+      gauss_jordan(s, N, tid);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = 16 * w + 4 * (e & 3) + (lane >> 4), col = 16 * (e >> 2) + (lane & 15);
+        const double2 pv = xb[OWN(e)];
+        d.r[e] = pv.x;
+        d.i[e] = pv.y;
+        cb[OWN(e)] = make_double2((row == col) ? 1.0 : 0.0, 0.0);
+      }
+    }
+    __syncthreads();
+  }
+
+  // reflection: Z <- S Z = [Gamma Q - iP; Gamma Q + iP]; R = lower / upper; rho = R[:, 0]
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const double2 cv = cb[OWN(e)];
+    const double g2v = g2[e & 3];
+    const double g_r = g2v >= 0.0 ? sqrt(g2v) : 0.0, g_i = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
+    const double qr = g_r * cv.x - g_i * cv.y;
+    const double qi = g_r * cv.y + g_i * cv.x;
+    // -iP = (P.i, -P.r);  +iP = (-P.i, P.r)
+    cb[OWN(e)] = make_double2(qr + d.i[e], qi - d.r[e]);
+    xb[OWN(e)] = make_double2(qr - d.i[e], qi + d.r[e]);
+  }
+  __syncthreads();
+  gauss_jordan(s, N, tid);
+  if (tid < NP) {
+    const int j = tid;
+    double eta = 0.0;
+    double2 rj = make_double2(0.0, 0.0);
+    if (j < N) {
+      rj = xb[j * NP + 0];
+      const double g00 = s.g2s[0];
+      const double gj = s.g2s[j];
+      if (gj > 0.0) {
+        eta = (rj.x * rj.x + rj.y * rj.y) * sqrt(g00) / sqrt(gj);
+        if (a.convention == 1) eta *= sin(th0);
+      }
+    }
+    if (j < a.ld) {
+      a.intensity[(long long)p * a.ld + j] = eta;
+      if (a.rho) a.rho[(long long)p * a.ld + j] = rj;
+    }
+    const bool fin = isfinite(rj.x) && isfinite(rj.y);
+    const unsigned long long bad = __ballot(!fin);
+    if (j == 0) {
+      int st = 0;
+      if (s.flag_singular) st = 1;
+      else if (bad) st = 2;
+      a.status[p] = st;
+      if (a.nrhst) a.nrhst[p] = nrhst;
+    }
+  }
+}
+#undef OWN
+
+hipError_t launch_forward(int stepper, const FwdArgs& a, hipStream_t stream) {
+  dim3 grid(a.n_pairs), block(NTHREADS);
+  if (stepper == 0)
+    hipLaunchKernelGGL(forward_kernel<0>, grid, block, 0, stream, a);
+  else
+    hipLaunchKernelGGL(forward_kernel<1>, grid, block, 0, stream, a);
+  return hipGetLastError();
+}
+
+}  // namespace rheed
