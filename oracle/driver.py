@@ -119,3 +119,25 @@ def rfactor_directional(wl, s_idx, direction, target00, angle_idx=None, stepper=
         loss += diff * diff
         dL += 2.0 * diff * deta[0]
     return loss, dL
+
+
+def rfactor_directional_table(wl, s_idx, dtable, target00, angle_idx=None, stepper=None, convention="flux"):
+    """Directional derivative of the R-factor along a perturbation ``dtable``
+    of the potential table itself ([n_nodes, box] complex), tangent-linear."""
+    tab = TABLEAUX[stepper or wl.stepper]
+    st = StructureSetup(wl, wl.structures[s_idx], tab)
+    idx = range(len(wl.theta0)) if angle_idx is None else angle_idx
+    loss, dL = 0.0, 0.0
+    for k, a in enumerate(idx):
+        th = float(wl.theta0[a])
+        gam, mask = st.angle(th)
+
+        def dU(i, r):
+            return dtable[tab.node_index(i, r)][st.cidx]
+        rho, drho = tangent.solve_ode_str_tangent(st.mfun(gam), dU, gam, st.h, st.s.n_slices, tab)
+        eta = rk.intensity(rho, gam, mask, th, convention)
+        deta = tangent.intensity_tangent(rho, drho, gam, mask, th, convention)
+        diff = eta[0] - target00[k]
+        loss += diff * diff
+        dL += 2.0 * diff * deta[0]
+    return loss, dL

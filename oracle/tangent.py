@@ -4,16 +4,19 @@ Differentiates ``rk.solve_ode_str`` along a direction dU of the potential
 table.  Every step of Algorithm 1 (Sec. 3.2) is linear in Z, so the
 tangent dZ is stepped by the same stages with the extra source
 -(dU_r) Y_r^{(c)} in each stage (Sec. 3.4).  At a right-hand-side
-transformation Z <- Z T the tangent becomes dZ T with T held fixed: by the
-invariance argument of Sec. 3.2 the output does not change when Z is
-multiplied from the right by any invertible matrix, so the derivative of
-T itself contributes nothing to d rho(0).  The final formula
+transformation Z' = Z Q^{-1} (T = Q^{-1}, Q the upper block) the tangent
+is the exact derivative dZ' = (dZ - Z' dQ) Q^{-1}, whose upper block is 0.
+(By the invariance of Sec. 3.2, dropping the term Z' dQ Q^{-1} would not
+change d rho(0) in exact arithmetic, but that term is what keeps the
+tangent from growing along the dominant modes: without it the tangent's
+norm grows like the unnormalised state and the final formula cancels
+catastrophically on thick slabs.)  The final formula
 rho = (Gamma Q + iP) x, (Gamma Q - iP) x = e_1 (Eq. vrhocomp, first
 column) is differentiated by the product and inverse rules.
 
 Pins: central finite differences of the oracle forward, and the
 dot-product identity between this tangent and finite differences along
-random directions (tests/test_oracle_tangent.py).
+random directions (tests/test_oracle_solvers.py).
 """
 from __future__ import annotations
 
@@ -55,7 +58,7 @@ def solve_ode_str_tangent(Mfun, dUfun, gam, h, n_slices, tab, threshold=THRESHOL
         if estcond_gershgorin(Z[:n]) > threshold:
             T = np.linalg.inv(Z[:n])
             Z = Z @ T
-            dZ = dZ @ T
+            dZ = (dZ - Z @ dZ[:n]) @ T
     Q, P, dQ, dP = Z[:n], Z[n:], dZ[:n], dZ[n:]
     top = gam[:, None] * Q - 1j * P
     bot = gam[:, None] * Q + 1j * P

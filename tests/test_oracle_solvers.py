@@ -214,3 +214,27 @@ def test_tangent_linear_matches_central_differences():
     fd = (loss_at(eps) - loss_at(-eps)) / (2 * eps)
     assert loss == pytest.approx(loss_at(0.0), rel=1e-12)
     assert dl == pytest.approx(fd, rel=2e-6)
+
+
+def test_tangent_along_a_table_direction_on_a_thick_slab():
+    """Tangent vs central differences along a random complex perturbation of
+    the potential table, over a slab thick enough for many right-hand-side
+    transformations (the tangent must differentiate Q^{-1} too, or it grows
+    along the dominant modes and cancels catastrophically)."""
+    from oracle.tableaux import TABLEAUX
+    wl = small_2d(n_beams=21, n_slices=80, thickness=4.0, n_layers=1, n_angles=3)
+    tab = TABLEAUX["rk4"]
+    st = driver.StructureSetup(wl, wl.structures[0], tab)
+    rng = np.random.default_rng(11)
+    dt = rng.normal(size=st.table.shape) + 1j * rng.normal(size=st.table.shape)
+    th = float(wl.theta0[0])
+    gam, mask = st.angle(th)
+
+    def dU(i, r):
+        return dt[tab.node_index(i, r)][st.cidx]
+    rho, drho, = tangent.solve_ode_str_tangent(st.mfun(gam), dU, gam, st.h, st.s.n_slices, tab)
+    eps = 1e-6
+    rp = rk.solve_ode_str(st.mfun(gam, table=st.table + eps * dt), gam, st.h, st.s.n_slices, tab)[0]
+    rm = rk.solve_ode_str(st.mfun(gam, table=st.table - eps * dt), gam, st.h, st.s.n_slices, tab)[0]
+    fd = (rp - rm) / (2 * eps)
+    assert np.abs(drho - fd).max() <= 1e-6 * np.abs(fd).max()
