@@ -51,7 +51,7 @@ class Plan:
 
     def __init__(self, structures: Sequence, angles_per_struct: Sequence[int], *, energy_eV: float,
                  charge: float, absorption: float, mean_inner_potential: float = 15.0, stepper: str = "rk6",
-                 threshold: float = 1000.0, checkpoint_every: int = 20, convention: str = "flux"):
+                 threshold: float = 1000.0, checkpoint_every: int = 1, convention: str = "flux"):
         L = _lib.lib()
         self.gamma, self.kappa = beam_constants(energy_eV)
         self.stepper = stepper

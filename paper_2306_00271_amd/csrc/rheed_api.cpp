@@ -41,12 +41,16 @@ struct rheed_plan_s {
   std::vector<StructDev> hs;
   std::vector<int> beams, pair_struct;
   std::vector<long long> table_off, atom_off, atom_struct;
+  std::vector<int> bin_ptr, bin_jk;
   CkptLayout ck{};
   size_t fwd_ws = 0, bwd_ws = 0;
   StructDev* d_structs = nullptr;
   int* d_beams = nullptr;
   int* d_pair_struct = nullptr;
   long long* d_atom_struct = nullptr;
+  int* d_bin_ptr = nullptr;
+  int* d_bin_jk = nullptr;
+  double2* d_ubar = nullptr;  // not owned: points into the caller's workspace
 };
 
 extern "C" {
@@ -140,6 +144,25 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
                                            std::to_string(d.box) + " entries exceeds " + std::to_string(MAXBOX));
     }
     d.n_nodes = st.n_slices * P->nodes_per_slice + 1;
+    // (j, k) pairs of every rod difference g_j - g_k, grouped by table entry
+    {
+      const int W = 2 * d.kd + 1;
+      std::vector<std::vector<int>> lists(d.box);
+      for (int j = 0; j < st.n_beams; ++j)
+        for (int k = 0; k < st.n_beams; ++k) {
+          const int dh = st.beam_hk[2 * j] - st.beam_hk[2 * k], dk = st.beam_hk[2 * j + 1] - st.beam_hk[2 * k + 1];
+          lists[(dh + d.hd) * W + (dk + d.kd)].push_back(j * NP + k);
+        }
+      d.bin_ptr_off = (int)P->bin_ptr.size();
+      d.bin_jk_off = (int)P->bin_jk.size();
+      int acc = 0;
+      for (int b = 0; b < d.box; ++b) {
+        P->bin_ptr.push_back(acc);
+        for (int v : lists[b]) P->bin_jk.push_back(v);
+        acc += (int)lists[b].size();
+      }
+      P->bin_ptr.push_back(acc);
+    }
     d.n_atoms = std::max(0, st.n_atoms);
     d.beam_off = (int)(P->beams.size() / 2);
     for (int j = 0; j < 2 * st.n_beams; ++j) P->beams.push_back(st.beam_hk[j]);
@@ -190,18 +213,21 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
   P->atom_off.push_back(P->n_atoms_total);
   // per-pair checkpoint block: states at the start of every segment + one byte per slice
   P->ck.every = opts->checkpoint_every;
-  P->ck.max_ckpt = (max_l + opts->checkpoint_every - 1) / opts->checkpoint_every;
+  P->ck.max_ckpt = (max_l + opts->checkpoint_every - 1) / opts->checkpoint_every + 1;
   P->ck.state_bytes = (long long)2 * NP * NP * sizeof(double2);
-  P->ck.flags_off = P->ck.max_ckpt * P->ck.state_bytes;
+  P->ck.q_off = P->ck.max_ckpt * P->ck.state_bytes;
+  P->ck.flags_off = P->ck.q_off + (long long)max_l * NP * NP * sizeof(double2);
   P->ck.pair_stride = ((P->ck.flags_off + max_l + 255) / 256) * 256;
   P->fwd_ws = (size_t)P->ck.pair_stride * P->n_pairs;
-  P->bwd_ws = 0;
+  P->bwd_ws = (size_t)P->max_table * sizeof(double2) * P->n_pairs;
 
   hipError_t e;
   if ((e = hipMalloc(&P->d_structs, sizeof(StructDev) * P->hs.size())) != hipSuccess ||
       (e = hipMalloc(&P->d_beams, sizeof(int) * P->beams.size())) != hipSuccess ||
       (e = hipMalloc(&P->d_pair_struct, sizeof(int) * P->pair_struct.size())) != hipSuccess ||
-      (e = hipMalloc(&P->d_atom_struct, sizeof(long long) * std::max<size_t>(1, P->atom_struct.size()))) != hipSuccess) {
+      (e = hipMalloc(&P->d_atom_struct, sizeof(long long) * std::max<size_t>(1, P->atom_struct.size()))) != hipSuccess ||
+      (e = hipMalloc(&P->d_bin_ptr, sizeof(int) * P->bin_ptr.size())) != hipSuccess ||
+      (e = hipMalloc(&P->d_bin_jk, sizeof(int) * P->bin_jk.size())) != hipSuccess) {
     rheed_plan_destroy(P);
     return e == hipErrorOutOfMemory ? fail(RHEED_E_NOMEM, "plan_create: device allocation") : hip_fail(e, "hipMalloc");
   }
@@ -209,6 +235,10 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (e = hipMemcpy(P->d_beams, P->beams.data(), sizeof(int) * P->beams.size(), hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(P->d_pair_struct, P->pair_struct.data(), sizeof(int) * P->pair_struct.size(),
                      hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(P->d_bin_ptr, P->bin_ptr.data(), sizeof(int) * P->bin_ptr.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
+      (e = hipMemcpy(P->d_bin_jk, P->bin_jk.data(), sizeof(int) * P->bin_jk.size(), hipMemcpyHostToDevice)) !=
+          hipSuccess ||
       (!P->atom_struct.empty() &&
        (e = hipMemcpy(P->d_atom_struct, P->atom_struct.data(), sizeof(long long) * P->atom_struct.size(),
                       hipMemcpyHostToDevice)) != hipSuccess)) {
@@ -225,6 +255,8 @@ rheed_status rheed_plan_destroy(rheed_plan_t P) {
   if (P->d_beams) (void)hipFree(P->d_beams);
   if (P->d_pair_struct) (void)hipFree(P->d_pair_struct);
   if (P->d_atom_struct) (void)hipFree(P->d_atom_struct);
+  if (P->d_bin_ptr) (void)hipFree(P->d_bin_ptr);
+  if (P->d_bin_jk) (void)hipFree(P->d_bin_jk);
   delete P;
   return RHEED_OK;
 }
@@ -312,15 +344,74 @@ rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* a
 
 rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* angles, const double* dL_dI,
                             void* dL_dU, void* workspace, size_t ws_bytes, void* stream) {
-  (void)U_tables;
-  (void)angles;
-  (void)dL_dI;
-  (void)dL_dU;
-  (void)workspace;
-  (void)ws_bytes;
-  (void)stream;
-  if (!P) return fail(RHEED_E_INVALID, "backward: null plan");
-  return fail(RHEED_E_UNSUPPORTED, "backward: not available in this build");
+  if (!P || !U_tables || !angles || !dL_dI || !dL_dU || !workspace)
+    return fail(RHEED_E_INVALID, "backward: null argument");
+  if (ws_bytes < P->fwd_ws + P->bwd_ws)
+    return fail(RHEED_E_INVALID, "backward: workspace of " + std::to_string(ws_bytes) + " bytes < " +
+                                     std::to_string(P->fwd_ws + P->bwd_ws));
+  if (P->ck.every != 1)
+    return fail(RHEED_E_UNSUPPORTED, "backward: this build keeps every slice state (checkpoint_every must be 1)");
+  BwdArgs a{};
+  a.structs = P->d_structs;
+  a.pair_struct = P->d_pair_struct;
+  a.beams = P->d_beams;
+  a.U = static_cast<const double2*>(U_tables);
+  a.angles = angles;
+  a.dLdI = dL_dI;
+  a.ws = static_cast<const char*>(workspace);
+  a.ck = P->ck;
+  a.ubar = reinterpret_cast<double2*>(static_cast<char*>(workspace) + P->fwd_ws);
+  a.ubar_stride = P->max_table;
+  a.bin_ptr = P->d_bin_ptr;
+  a.bin_jk = P->d_bin_jk;
+  a.ld = P->max_beams;
+  a.convention = (int)P->opts.convention;
+  a.n_pairs = P->n_pairs;
+  a.nodes_per_slice = P->nodes_per_slice;
+  for (int r = 0; r < 7; ++r) {
+    a.b[r] = 0.0;
+    for (int j = 0; j < 7; ++j) a.A[r][j] = 0.0;
+  }
+  if (P->opts.stepper == RHEED_RK4) {
+    // classical RK4 (Sec. 3.4 form): c = 0, 1/2, 1/2, 1
+    a.stages = 4;
+    a.A[1][0] = 0.5;
+    a.A[2][1] = 0.5;
+    a.A[3][2] = 1.0;
+    const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    const int nd[4] = {0, 1, 1, 2};
+    for (int r = 0; r < 4; ++r) {
+      a.b[r] = b[r];
+      a.stage_node[r] = nd[r];
+    }
+  } else {
+    // Butcher's sixth-order seven-stage method: c = 0, 1/3, 2/3, 1/3, 1/2, 1/2, 1;
+    // node offsets in the slice's distinct nodes {0, 1/3, 1/2, 2/3} (4 = next slice)
+    a.stages = 7;
+    a.A[1][0] = 1.0 / 3.0;
+    a.A[2][1] = 2.0 / 3.0;
+    a.A[3][0] = 1.0 / 12.0; a.A[3][1] = 1.0 / 3.0; a.A[3][2] = -1.0 / 12.0;
+    a.A[4][0] = -1.0 / 16.0; a.A[4][1] = 9.0 / 8.0; a.A[4][2] = -3.0 / 16.0; a.A[4][3] = -3.0 / 8.0;
+    a.A[5][1] = 9.0 / 8.0; a.A[5][2] = -3.0 / 8.0; a.A[5][3] = -3.0 / 4.0; a.A[5][4] = 1.0 / 2.0;
+    a.A[6][0] = 9.0 / 44.0; a.A[6][1] = -9.0 / 11.0; a.A[6][2] = 63.0 / 44.0; a.A[6][3] = 18.0 / 11.0;
+    a.A[6][5] = -16.0 / 11.0;
+    const double b[7] = {11.0 / 120.0, 0.0, 27.0 / 40.0, 27.0 / 40.0, -4.0 / 15.0, -4.0 / 15.0, 11.0 / 120.0};
+    const int nd[7] = {0, 1, 3, 1, 2, 2, 4};
+    for (int r = 0; r < 7; ++r) {
+      a.b[r] = b[r];
+      a.stage_node[r] = nd[r];
+    }
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = launch_backward(a, st);
+  if (e != hipSuccess) return hip_fail(e, "backward launch");
+  ReduceArgs r{};
+  r.structs = P->d_structs;
+  r.ubar = a.ubar;
+  r.ubar_stride = a.ubar_stride;
+  r.dU = static_cast<double2*>(dL_dU);
+  e = launch_reduce_ubar(r, P->n_struct, P->max_table, st);
+  return e == hipSuccess ? RHEED_OK : hip_fail(e, "backward reduction launch");
 }
 
 rheed_status rheed_rfactor(int32_t n_pairs, int32_t ld, const double* intensity, const double* target, double* loss,

@@ -28,6 +28,7 @@
 // reflection (Algorithm 1, last lines) applies the same elimination to
 // [Gamma Q - iP; Gamma Q + iP].
 #include "rheed_internal.h"
+#include "rheed_gj.h"
 
 namespace rheed {
 
@@ -109,65 +110,6 @@ __device__ __forceinline__ void stage_gemm(const double2* __restrict__ xbuf, con
 __device__ __forceinline__ void store_mat(double2* buf, const Mat& m, int ob) {
 #pragma unroll
   for (int e = 0; e < 16; ++e) buf[OWN(e)] = make_double2(m.r[e], m.i[e]);
-}
-
-// Wave-wide argmax of v (ties -> smaller index).
-__device__ __forceinline__ void wave_argmax(double& v, int& idx) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const double ov = __shfl_xor(v, off, 64);
-    const int oi = __shfl_xor(idx, off, 64);
-    if (ov > v || (ov == v && oi < idx)) {
-      v = ov;
-      idx = oi;
-    }
-  }
-}
-
-// Column Gauss-Jordan with partial pivoting on Z = xb viewed as [128][64]:
-// right-multiplies Z until its top block is I, so the bottom block becomes
-// bottom * top^{-1}.  Only the leading n columns / pivots are processed.
-// Each step copies the pivot column, column k and row k to LDS scratch, so
-// that the update of every element reads only its own old value and copies.
-__device__ void gauss_jordan(Lds& s, int n, int tid) {
-  const int lane = tid & 63;
-  const int w = tid >> 6;
-  const int j = lane;
-  double2* Z = s.xb;
-  for (int k = 0; k < n; ++k) {
-    const double2 zk = Z[k * NP + lane];
-    double m2 = (lane >= k && lane < n) ? zk.x * zk.x + zk.y * zk.y : -1.0;
-    int bi = lane;
-    wave_argmax(m2, bi);
-    if (!(m2 > 0.0) && tid == 0) s.flag_singular = 1;
-    if (tid < 2 * NP) {
-      s.gj_colp[tid] = Z[tid * NP + bi];
-      s.gj_colk[tid] = Z[tid * NP + k];
-    } else if (tid < 3 * NP) {
-      s.gj_rowk[tid - 2 * NP] = Z[k * NP + (tid - 2 * NP)];
-    }
-    __syncthreads();
-    if (j < n) {
-      const double2 piv = s.gj_rowk[bi];
-      const double pn = piv.x * piv.x + piv.y * piv.y;
-      const double2 ip = make_double2(piv.x / pn, -piv.y / pn);
-      const double2 mj = s.gj_rowk[j == bi ? k : j];
-      const double2 f = make_double2(mj.x * ip.x - mj.y * ip.y, mj.x * ip.y + mj.y * ip.x);
-      for (int m = 0; m < 2 * NP / NWAVES; ++m) {
-        const int r = w + NWAVES * m;
-        const double2 zp = s.gj_colp[r];
-        const double2 zo = (j == bi) ? s.gj_colk[r] : Z[r * NP + j];
-        double2 nv;
-        if (j == k) {
-          nv = make_double2(zp.x * ip.x - zp.y * ip.y, zp.x * ip.y + zp.y * ip.x);
-        } else {
-          nv = make_double2(zo.x - (f.x * zp.x - f.y * zp.y), zo.y - (f.x * zp.y + f.y * zp.x));
-        }
-        Z[r * NP + j] = nv;
-      }
-    }
-    __syncthreads();
-  }
 }
 
 // Loads nodes [n0, n1) of a structure's table into their ring slots.
@@ -454,9 +396,14 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
     if (save && tid == 0) pws[a.ck.flags_off + i] = do_rhst ? 1 : 0;
     if (do_rhst) {
       ++nrhst;
+      if (save) {
+        double2* qs = reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * NP * NP * sizeof(double2));
+#pragma unroll
+        for (int e = 0; e < 16; ++e) qs[OWN(e)] = cb[OWN(e)];
+      }
       store_mat(xb, d, ob);
       __syncthreads();
-      gauss_jordan(s, N, tid);
+      gauss_jordan(s.xb, s.gj_colp, s.gj_colk, s.gj_rowk, &s.flag_singular, N, tid);
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int row = 16 * w + 4 * (e & 3) + (lane >> 4), col = 16 * (e >> 2) + (lane & 15);
@@ -469,6 +416,14 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
     __syncthreads();
   }
 
+  if (save) {
+    double2* st = reinterpret_cast<double2*>(pws + (long long)(a.ck.max_ckpt - 1) * a.ck.state_bytes);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      st[OWN(e)] = cb[OWN(e)];
+      st[NP * NP + OWN(e)] = make_double2(d.r[e], d.i[e]);
+    }
+  }
   // reflection: Z <- S Z = [Gamma Q - iP; Gamma Q + iP]; R = lower / upper; rho = R[:, 0]
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
@@ -482,7 +437,7 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
     xb[OWN(e)] = make_double2(qr - d.i[e], qi + d.r[e]);
   }
   __syncthreads();
-  gauss_jordan(s, N, tid);
+  gauss_jordan(s.xb, s.gj_colp, s.gj_colk, s.gj_rowk, &s.flag_singular, N, tid);
   if (tid < NP) {
     const int j = tid;
     double eta = 0.0;

@@ -14,7 +14,7 @@ constexpr int MAXBOX = 300;     // rod-difference entries per node table row in 
 struct StructDev {
   int n_beams, n_slices, hd, kd;
   int box, n_nodes, n_atoms, beam_off;
-  int pair_off, n_angles, pad0, pad1;
+  int pair_off, n_angles, bin_ptr_off, bin_jk_off;  // bins: (j,k) pairs of each rod difference
   double h, thickness, gamma, pad2;
   double recip[4];
   long long table_off;   // complex elements
@@ -23,15 +23,17 @@ struct StructDev {
   double pref_re, pref_im;  // kappa * s * (charge - i alpha) / A  (volts -> 1/A^2 per unit cell area)
 };
 
-// Per-pair storage kept by the forward pass for the adjoint: states (c, d)
-// at the start of every checkpoint segment, and one byte per slice telling
-// whether the right-hand-side transformation was applied after it.
+// Per-pair storage kept by the forward pass for the adjoint: the state (c, c')
+// at the start of every slice and after the last one, the upper block Q of
+// every slice that was followed by a right-hand-side transformation (before
+// it), and one byte per slice telling whether that transformation was applied.
 struct CkptLayout {
   long long pair_stride;   // bytes per pair
   long long state_bytes;   // one state: 2 * NP * NP complex
-  int every;               // slices per segment
-  int max_ckpt;            // states per pair
-  long long flags_off;     // byte offset of the decision bytes inside a pair's block
+  int every;               // slices between stored states (1: every slice)
+  int max_ckpt;            // stored states per pair, including the final state
+  long long q_off;         // byte offset of the Q slots (one per slice)
+  long long flags_off;     // byte offset of the decision bytes
 };
 
 struct FwdArgs {
@@ -71,7 +73,39 @@ struct PotBwdArgs {
   double cset[4];
 };
 
+struct BwdArgs {
+  const StructDev* structs;
+  const int* pair_struct;
+  const int* beams;
+  const double2* U;
+  const double* angles;
+  const double* dLdI;        // [P][ld]
+  const char* ws;            // forward workspace
+  CkptLayout ck;
+  double2* ubar;             // per-pair dL/dU tables, stride ubar_stride elements
+  long long ubar_stride;
+  const int* bin_ptr;        // per structure: box + 1 offsets into bin_jk
+  const int* bin_jk;         // j * NP + k
+  int ld;
+  int convention;
+  int n_pairs;
+  int stages;
+  int nodes_per_slice;
+  int stage_node[7];         // node offset of each stage inside its slice (nodes_per_slice = next slice)
+  double A[7][7];
+  double b[7];
+};
+
+struct ReduceArgs {
+  const StructDev* structs;
+  const double2* ubar;
+  long long ubar_stride;
+  double2* dU;               // all tables
+};
+
 hipError_t launch_forward(int stepper, const FwdArgs& a, hipStream_t stream);
+hipError_t launch_backward(const BwdArgs& a, hipStream_t stream);
+hipError_t launch_reduce_ubar(const ReduceArgs& a, int n_struct, long long max_table, hipStream_t stream);
 hipError_t launch_potential(const PotArgs& a, long long max_elems, hipStream_t stream);
 hipError_t launch_potential_bwd(const PotBwdArgs& a, long long n_atoms_total, int n_struct,
                                 const long long* atom_struct, hipStream_t stream);
