@@ -11,7 +11,7 @@
 #include <utility>
 #include <vector>
 
-#include "../../include/rheed.h"
+#include "rheed.h"
 #include "rheed_internal.h"
 
 
@@ -50,7 +50,8 @@ struct rheed_plan_s {
   long long* d_atom_struct = nullptr;
   int* d_bin_ptr = nullptr;
   int* d_bin_jk = nullptr;
-  double2* d_ubar = nullptr;  // not owned: points into the caller's workspace
+  long long g_pair_stride = 0;  // adjoint stage buffer elements per pair
+  int max_nodes = 0;
 };
 
 extern "C" {
@@ -203,6 +204,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     for (int a = 0; a < d.n_atoms; ++a) P->atom_struct.push_back(s);
     P->table_elems += (long long)d.n_nodes * d.box;
     P->max_table = std::max(P->max_table, (long long)d.n_nodes * d.box);
+    P->max_nodes = std::max(P->max_nodes, d.n_nodes);
     P->n_atoms_total += d.n_atoms;
     for (int a = 0; a < angles_per_struct[s]; ++a) P->pair_struct.push_back(s);
     P->n_pairs += angles_per_struct[s];
@@ -219,7 +221,9 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
   P->ck.flags_off = P->ck.q_off + (long long)max_l * NP * NP * sizeof(double2);
   P->ck.pair_stride = ((P->ck.flags_off + max_l + 255) / 256) * 256;
   P->fwd_ws = (size_t)P->ck.pair_stride * P->n_pairs;
-  P->bwd_ws = (size_t)P->max_table * sizeof(double2) * P->n_pairs;
+  // adjoint stage buffer: (v_r, g_r) of every stage of every slice
+  P->g_pair_stride = (long long)max_l * (P->opts.stepper == RHEED_RK4 ? 4 : 7) * 2 * NP;
+  P->bwd_ws = (size_t)P->g_pair_stride * sizeof(double2) * P->n_pairs;
 
   hipError_t e;
   if ((e = hipMalloc(&P->d_structs, sizeof(StructDev) * P->hs.size())) != hipSuccess ||
@@ -360,58 +364,36 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
   a.dLdI = dL_dI;
   a.ws = static_cast<const char*>(workspace);
   a.ck = P->ck;
-  a.ubar = reinterpret_cast<double2*>(static_cast<char*>(workspace) + P->fwd_ws);
-  a.ubar_stride = P->max_table;
-  a.bin_ptr = P->d_bin_ptr;
-  a.bin_jk = P->d_bin_jk;
+  a.gbuf = reinterpret_cast<double2*>(static_cast<char*>(workspace) + P->fwd_ws);
+  a.g_pair_stride = P->g_pair_stride;
   a.ld = P->max_beams;
   a.convention = (int)P->opts.convention;
   a.n_pairs = P->n_pairs;
-  a.nodes_per_slice = P->nodes_per_slice;
-  for (int r = 0; r < 7; ++r) {
-    a.b[r] = 0.0;
-    for (int j = 0; j < 7; ++j) a.A[r][j] = 0.0;
-  }
-  if (P->opts.stepper == RHEED_RK4) {
-    // classical RK4 (Sec. 3.4 form): c = 0, 1/2, 1/2, 1
-    a.stages = 4;
-    a.A[1][0] = 0.5;
-    a.A[2][1] = 0.5;
-    a.A[3][2] = 1.0;
-    const double b[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
-    const int nd[4] = {0, 1, 1, 2};
-    for (int r = 0; r < 4; ++r) {
-      a.b[r] = b[r];
-      a.stage_node[r] = nd[r];
-    }
-  } else {
-    // Butcher's sixth-order seven-stage method: c = 0, 1/3, 2/3, 1/3, 1/2, 1/2, 1;
-    // node offsets in the slice's distinct nodes {0, 1/3, 1/2, 2/3} (4 = next slice)
-    a.stages = 7;
-    a.A[1][0] = 1.0 / 3.0;
-    a.A[2][1] = 2.0 / 3.0;
-    a.A[3][0] = 1.0 / 12.0; a.A[3][1] = 1.0 / 3.0; a.A[3][2] = -1.0 / 12.0;
-    a.A[4][0] = -1.0 / 16.0; a.A[4][1] = 9.0 / 8.0; a.A[4][2] = -3.0 / 16.0; a.A[4][3] = -3.0 / 8.0;
-    a.A[5][1] = 9.0 / 8.0; a.A[5][2] = -3.0 / 8.0; a.A[5][3] = -3.0 / 4.0; a.A[5][4] = 1.0 / 2.0;
-    a.A[6][0] = 9.0 / 44.0; a.A[6][1] = -9.0 / 11.0; a.A[6][2] = 63.0 / 44.0; a.A[6][3] = 18.0 / 11.0;
-    a.A[6][5] = -16.0 / 11.0;
-    const double b[7] = {11.0 / 120.0, 0.0, 27.0 / 40.0, 27.0 / 40.0, -4.0 / 15.0, -4.0 / 15.0, 11.0 / 120.0};
-    const int nd[7] = {0, 1, 3, 1, 2, 2, 4};
-    for (int r = 0; r < 7; ++r) {
-      a.b[r] = b[r];
-      a.stage_node[r] = nd[r];
-    }
-  }
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_backward(a, st);
+  hipError_t e = launch_backward((int)P->opts.stepper, a, st);
   if (e != hipSuccess) return hip_fail(e, "backward launch");
-  ReduceArgs r{};
-  r.structs = P->d_structs;
-  r.ubar = a.ubar;
-  r.ubar_stride = a.ubar_stride;
-  r.dU = static_cast<double2*>(dL_dU);
-  e = launch_reduce_ubar(r, P->n_struct, P->max_table, st);
-  return e == hipSuccess ? RHEED_OK : hip_fail(e, "backward reduction launch");
+  // stages that use each node of a slice: node offsets of the stages in
+  // {0, 1/2} (RK4) or {0, 1/3, 1/2, 2/3} (RK6); offset nps is the next slice's 0
+  GradArgs g{};
+  g.structs = P->d_structs;
+  g.gbuf = a.gbuf;
+  g.g_pair_stride = a.g_pair_stride;
+  g.bin_ptr = P->d_bin_ptr;
+  g.bin_jk = P->d_bin_jk;
+  g.dU = static_cast<double2*>(dL_dU);
+  const bool rk4 = P->opts.stepper == RHEED_RK4;
+  static const int node4[4] = {0, 1, 1, 2}, node6[7] = {0, 1, 3, 1, 2, 2, 4};
+  g.stages = rk4 ? 4 : 7;
+  g.nps = P->nodes_per_slice;
+  const int* node = rk4 ? node4 : node6;
+  for (int r = 0; r < g.stages; ++r) {
+    const int res = node[r] % g.nps, di = node[r] / g.nps;  // node i nps + node[r] = (i + di) nps + res
+    const int t = g.n_contrib[res]++;
+    g.contrib_di[res][t] = -di;
+    g.contrib_r[res][t] = r;
+  }
+  e = launch_grad_assemble(g, P->n_struct, P->max_nodes, st);
+  return e == hipSuccess ? RHEED_OK : hip_fail(e, "gradient assembly launch");
 }
 
 rheed_status rheed_rfactor(int32_t n_pairs, int32_t ld, const double* intensity, const double* target, double* loss,

@@ -6,21 +6,27 @@
 //   * through a slice map Z <- Phi Z (an RK step is linear from the left)
 //     the cotangent becomes (Phi^H y) x^H;
 //   * through a right-hand-side transformation Z' = Z Q^{-1} (Sec. 3.2) it
-//     becomes y x^H with x = Q^{-1} x' and y = y' - [Z'^H y'; 0]; the second
-//     term is the derivative of Q^{-1} itself.  The output is invariant under
-//     right multiplication of Z, so in exact arithmetic that term changes
-//     nothing, but it removes the components of y that the backward
-//     recursion would amplify;
+//     becomes y x^H with x = Q^{-1} x' and y = y' - [Z'^H y'; 0] =
+//     [-R^H y'_(c'); y'_(c')] for Z' = [I; R]; the second term is the
+//     derivative of Q^{-1} itself.  The output is invariant under right
+//     multiplication of Z, so in exact arithmetic that term changes nothing,
+//     but it removes the components of y that the backward recursion would
+//     amplify;
 //   * the gradient of the coupling matrix at stage r is g_r v_r^H with v_r the
 //     stage input of the RK step applied to the single physical column
-//     psi = Z x, and g_r the adjoint of that stage's product.
+//     psi = Z x, and g_r = -K_bar_r^(c') the adjoint of that stage's product.
 // One workgroup per (structure, angle) pair therefore walks the slices
-// backwards with vectors only: x is carried back through the stored upper
-// blocks Q (x <- Q^{-1} x where a transformation happened), psi = Z_i x comes
-// from the stored slice-start states, and each stage costs a few N x N
-// matrix-vector products.  Gradients land in a per-pair table of rod
-// differences; a second kernel sums them over the angles of each structure
-// in a fixed order.
+// backwards with vectors only.  The forward pass keeps Z at the start of every
+// slice and T = Q^{-1} of every transformation; psi_i = Z_i x_i is formed from
+// them (the loads for slice i-1 are issued at the start of slice i), and each
+// stage costs one N x N matrix-vector product against the node's rod-
+// difference table in LDS.  Every stage writes (v_r, g_r) to a stage buffer;
+// grad_assemble_kernel then sums g v^H over the angles and stages of each
+// node on the FP64 units and bins the sum by rod difference, in a fixed order.
+//
+// Thread layout of the vector work: 512 threads, thread t works on row
+// j = t >> 3 and on columns 8 (t & 7) .. +7; the eight threads of a row reduce
+// by butterflies and all hold the row's result.
 //
 // Final step (Eq. vrhocomp, first column): with B = Gamma Q - iP,
 // A = Gamma Q + iP, B x = e_1, rho = A x and
@@ -33,29 +39,46 @@
 
 namespace rheed {
 
-struct StageVecs {
-  double2 yc[7][NP], yd[7][NP];    // stage inputs of the RK step applied to psi
-  double2 kd[7][NP];               // K^(c') of each stage
-  double2 ybc[7][NP], ybd[7][NP];  // stage-input cotangents
+constexpr int BW = 8;          // waves per workgroup
+constexpr int BT = BW * 64;    // threads per workgroup
+constexpr int RING = 9;        // node-table slots: current slice (nps + 1) and the next one down (nps)
+
+// Explicit RK tableaux (Sec. 3.4).  node[r] is the table node of stage r
+// counted from the slice's c = 0 node (nps = the next slice's c = 0).
+template <int S>
+struct BTab;
+template <>
+struct BTab<0> {  // classical RK4, c = 0, 1/2, 1/2, 1
+  static constexpr int stages = 4, nps = 2;
+  static constexpr int node[4] = {0, 1, 1, 2};
+  static constexpr double a[4][4] = {{0, 0, 0, 0}, {0.5, 0, 0, 0}, {0, 0.5, 0, 0}, {0, 0, 1, 0}};
+  static constexpr double b[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+};
+template <>
+struct BTab<1> {  // Butcher's 6th order, 7 stages, c = 0, 1/3, 2/3, 1/3, 1/2, 1/2, 1
+  static constexpr int stages = 7, nps = 4;
+  static constexpr int node[7] = {0, 1, 3, 1, 2, 2, 4};
+  static constexpr double a[7][7] = {
+      {0, 0, 0, 0, 0, 0, 0},
+      {1.0 / 3, 0, 0, 0, 0, 0, 0},
+      {0, 2.0 / 3, 0, 0, 0, 0, 0},
+      {1.0 / 12, 1.0 / 3, -1.0 / 12, 0, 0, 0, 0},
+      {-1.0 / 16, 9.0 / 8, -3.0 / 16, -3.0 / 8, 0, 0, 0},
+      {0, 9.0 / 8, -3.0 / 8, -3.0 / 4, 1.0 / 2, 0, 0},
+      {9.0 / 44, -9.0 / 11, 63.0 / 44, 18.0 / 11, 0, -16.0 / 11, 0}};
+  static constexpr double b[7] = {11.0 / 120, 0, 27.0 / 40, 27.0 / 40, -4.0 / 15, -4.0 / 15, 11.0 / 120};
 };
 
 struct BLds {
-  union {
-    double2 zb[2 * NP * NP];   // elimination workspace [top; bottom]
-    StageVecs sv;              // per-slice vectors (the eliminations of a slice finish before its stages start)
-  };
-  double2 tb[1][MAXBOX + 1];   // node table of the current stage; entry box = 0
-  double2 gj_colp[2 * NP];
-  double2 gj_colk[2 * NP];
-  double2 gj_rowk[NP];
-  double2 x[NP];               // coefficients of the physical column
-  double2 pc[NP], pd[NP];      // psi = Z x: c and c' parts
-  double2 cb_[NP], db_[NP];    // running cotangent y = (c_bar, c'_bar)
-  double2 tmp[NP], tmp2[NP];
+  double2 tb[RING][MAXBOX + 1];  // node tables; entry `box` of every slot stays 0
+  double2 vin[2][NP];            // matrix-vector inputs (double buffered: one barrier per product)
+  double2 x[NP];                 // coefficients of the physical column
+  double2 red[BW][NP];           // per-wave partial sums
+  double2 gj_row[2 * NP];
+  double2 gj_col[2 * NP];
+  int gj_piv[NP];
   double g2s[NP];
   int bhk[NP][2];
-  int offk[NP];                // h_k W + k_k
-  int basej[NP];               // (h_j + Hd) W + k_j + Kd
   int flag_singular;
 };
 
@@ -65,117 +88,85 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 __device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) * b
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 caxpy(double s, double2 x, double2 y) {  // y + s x
+  return make_double2(y.x + s * x.x, y.y + s * x.y);
+}
 
-// out = M v (herm = false) or M^H v (herm = true) with M = U(node) + Gamma^2,
-// U_{jk} = table[idx(j, k)]; 4 threads per row, rows < n.
-__device__ __forceinline__ void matvec_u(BLds& s, const double2* tslot, const double2* v, double2* out, bool herm,
-                                         int n, int box, int tid) {
-  const int j = tid >> 2, part = tid & 3;
-  double2 acc = make_double2(0.0, 0.0);
-  if (j < n) {
-    for (int k = part; k < n; k += 4) {
-      const int idx = herm ? (s.basej[k] - s.offk[j]) : (s.basej[j] - s.offk[k]);
-      const double2 u = tslot[idx];
-      acc = herm ? make_double2(acc.x + u.x * v[k].x + u.y * v[k].y, acc.y + u.x * v[k].y - u.y * v[k].x)
-                 : make_double2(acc.x + u.x * v[k].x - u.y * v[k].y, acc.y + u.x * v[k].y + u.y * v[k].x);
-    }
+// Sum over the eight threads of a row (lanes differing in their low 3 bits).
+__device__ __forceinline__ double2 row_sum(double2 v) {
+#pragma unroll
+  for (int off = 1; off < 8; off <<= 1) {
+    v.x += __shfl_xor(v.x, off, 64);
+    v.y += __shfl_xor(v.y, off, 64);
   }
-  acc.x += __shfl_xor(acc.x, 1, 64);
-  acc.y += __shfl_xor(acc.y, 1, 64);
-  acc.x += __shfl_xor(acc.x, 2, 64);
-  acc.y += __shfl_xor(acc.y, 2, 64);
-  if (part == 0 && j < NP) {
-    if (j < n) out[j] = make_double2(acc.x + s.g2s[j] * v[j].x, acc.y + s.g2s[j] * v[j].y);
-    else out[j] = make_double2(0.0, 0.0);
-  }
-  (void)box;
+  return v;
 }
 
-// out = Mat v for a dense [NP][NP] complex matrix in global memory (rows < n)
-__device__ __forceinline__ void matvec_dense(const double2* __restrict__ Mg, const double2* v, double2* out, int n,
-                                             int tid) {
-  const int j = tid >> 2, part = tid & 3;
+// (M v)_j (HERM = false) or (M^H v)_j (HERM = true), M = U(node) + Gamma^2;
+// ix[q] is the table entry of U_{j,k} (or U_{k,j}) for k = 8 part + q, or
+// `box` (a zero entry) outside the n x n block.
+template <bool HERM>
+__device__ __forceinline__ double2 matvec_row(const double2* __restrict__ tslot, const double2* __restrict__ v,
+                                              const int (&ix)[8], int part, int j, double g2j) {
   double2 acc = make_double2(0.0, 0.0);
-  if (j < n)
-    for (int k = part; k < n; k += 4) {
-      const double2 m = Mg[j * NP + k];
-      acc.x += m.x * v[k].x - m.y * v[k].y;
-      acc.y += m.x * v[k].y + m.y * v[k].x;
-    }
-  acc.x += __shfl_xor(acc.x, 1, 64);
-  acc.y += __shfl_xor(acc.y, 1, 64);
-  acc.x += __shfl_xor(acc.x, 2, 64);
-  acc.y += __shfl_xor(acc.y, 2, 64);
-  if (part == 0 && j < NP) out[j] = j < n ? acc : make_double2(0.0, 0.0);
-}
-
-// out = Mat^H v for a dense [NP][NP] complex matrix in global memory (n x n)
-__device__ __forceinline__ void matvec_dense_h(const double2* __restrict__ Mg, const double2* v, double2* out, int n,
-                                               int tid) {
-  const int k = tid >> 2, part = tid & 3;
-  double2 acc = make_double2(0.0, 0.0);
-  if (k < n)
-    for (int j = part; j < n; j += 4) {
-      const double2 m = Mg[j * NP + k];
-      acc.x += m.x * v[j].x + m.y * v[j].y;
-      acc.y += m.x * v[j].y - m.y * v[j].x;
-    }
-  acc.x += __shfl_xor(acc.x, 1, 64);
-  acc.y += __shfl_xor(acc.y, 1, 64);
-  acc.x += __shfl_xor(acc.x, 2, 64);
-  acc.y += __shfl_xor(acc.y, 2, 64);
-  if (part == 0 && k < NP) out[k] = k < n ? acc : make_double2(0.0, 0.0);
-}
-
-// Loads M (global, [NP][NP]) into the top block and I into the bottom block,
-// eliminates, and leaves M^{-1} (leading n x n) in the bottom block.
-__device__ __forceinline__ void invert_into_bottom(BLds& s, const double2* __restrict__ Mg, int n, int tid) {
-  for (int e = tid; e < NP * NP; e += NTHREADS) {
-    const int r = e / NP, c = e - r * NP;
-    s.zb[e] = (r < n && c < n) ? Mg[e] : make_double2(r == c ? 1.0 : 0.0, 0.0);
-    s.zb[NP * NP + e] = make_double2(r == c ? 1.0 : 0.0, 0.0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double2 u = tslot[ix[q]];
+    const double2 vk = v[8 * part + q];
+    acc = cadd(acc, HERM ? cmulc(u, vk) : cmul(u, vk));
   }
-  __syncthreads();
-  gauss_jordan(s.zb, s.gj_colp, s.gj_colk, s.gj_rowk, &s.flag_singular, n, tid);
+  acc = row_sum(acc);
+  const double2 vj = v[j];
+  return make_double2(acc.x + g2j * vj.x, acc.y + g2j * vj.y);
 }
 
-__device__ __forceinline__ void load_table(BLds& s, const double2* __restrict__ Us, int node, int box, int tid) {
-  for (int e = tid; e < box; e += NTHREADS) s.tb[0][e] = Us[(long long)node * box + e];
+// sum_q Mg[j][8 part + q] v[8 part + q] for a dense [NP][NP] matrix in global memory
+__device__ __forceinline__ double2 dense_row(const double2* __restrict__ Mg, const double2* v, int j, int part) {
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc = cadd(acc, cmul(Mg[j * NP + 8 * part + q], v[8 * part + q]));
+  return row_sum(acc);
+}
+// sum_q conj(Mg[8 part + q][k]) v[8 part + q]  (row k of Mg^H v)
+__device__ __forceinline__ double2 dense_row_h(const double2* __restrict__ Mg, const double2* v, int k, int part) {
+  double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc = cadd(acc, cmulc(Mg[(8 * part + q) * NP + k], v[8 * part + q]));
+  return row_sum(acc);
 }
 
-__global__ __launch_bounds__(NTHREADS, 1) void backward_kernel(BwdArgs a) {
+template <int STEPPER>
+__global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
+  using T = BTab<STEPPER>;
+  constexpr int NS = T::stages;
+  constexpr int NPS = T::nps;
   __shared__ BLds s;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int j = tid >> 3, part = tid & 7;
   const int p = blockIdx.x;
   const StructDev S = a.structs[a.pair_struct[p]];
   const int N = S.n_beams;
   const int L = S.n_slices;
+  const int box = S.box;
   const double h = S.h;
-  const int nps = a.nodes_per_slice;
   const double2* __restrict__ Us = a.U + S.table_off;
   const char* pws = a.ws + (long long)p * a.ck.pair_stride;
-  double2* __restrict__ ub = a.ubar + (long long)p * a.ubar_stride;
-  const int* bptr = a.bin_ptr + S.bin_ptr_off;
-  const int* bjk = a.bin_jk + S.bin_jk_off;
+  const char* flags = pws + a.ck.flags_off;
+  double2* __restrict__ gb = a.gbuf + (long long)p * a.g_pair_stride;
 
-  const long long tot = (long long)S.n_nodes * S.box;
-  for (long long e = tid; e < tot; e += NTHREADS) ub[e] = make_double2(0.0, 0.0);
-  const int W = 2 * S.kd + 1;
   if (tid < NP) {
-    const int hh_ = tid < N ? a.beams[2 * (S.beam_off + tid)] : 0;
-    const int kk_ = tid < N ? a.beams[2 * (S.beam_off + tid) + 1] : 0;
-    s.bhk[tid][0] = hh_;
-    s.bhk[tid][1] = kk_;
-    s.offk[tid] = hh_ * W + kk_;
-    s.basej[tid] = (hh_ + S.hd) * W + kk_ + S.kd;
+    s.bhk[tid][0] = tid < N ? a.beams[2 * (S.beam_off + tid)] : 0;
+    s.bhk[tid][1] = tid < N ? a.beams[2 * (S.beam_off + tid) + 1] : 0;
   }
+  if (tid < RING) s.tb[tid][box] = make_double2(0.0, 0.0);
   if (tid == 0) s.flag_singular = 0;
-  if (tid == 0) s.tb[0][S.box] = make_double2(0.0, 0.0);
   __syncthreads();
   const double th0 = a.angles[2 * p], th1 = a.angles[2 * p + 1];
-  const double b0x = S.gamma * cos(th0) * cos(th1);
-  const double b0y = S.gamma * cos(th0) * sin(th1);
   if (tid < NP) {
+    const double b0x = S.gamma * cos(th0) * cos(th1);
+    const double b0y = S.gamma * cos(th0) * sin(th1);
     double arg = 0.0;
     if (tid < N) {
       const double qx = b0x + s.bhk[tid][0] * S.recip[0] + s.bhk[tid][1] * S.recip[2];
@@ -184,238 +175,315 @@ __global__ __launch_bounds__(NTHREADS, 1) void backward_kernel(BwdArgs a) {
     }
     s.g2s[tid] = arg;
   }
+  // table entries of U_{j,k} and U_{k,j} for k = 8 part + q
+  int ixf[8], ixh[8];
+  {
+    const int W = 2 * S.kd + 1;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = 8 * part + q;
+      const bool in = j < N && k < N;
+      const int bj = (s.bhk[j][0] + S.hd) * W + s.bhk[j][1] + S.kd, oj = s.bhk[j][0] * W + s.bhk[j][1];
+      const int bk = (s.bhk[k][0] + S.hd) * W + s.bhk[k][1] + S.kd, ok = s.bhk[k][0] * W + s.bhk[k][1];
+      ixf[q] = in ? bj - ok : box;
+      ixh[q] = in ? bk - oj : box;
+    }
+  }
+  // node tables of slice L - 1
+  for (int e = tid; e < (NPS + 1) * box; e += BT) {
+    const int nn = (L - 1) * NPS + e / box;
+    s.tb[nn % RING][e % box] = Us[(long long)nn * box + e % box];
+  }
   __syncthreads();
+  const double g2j = s.g2s[j];
 
-  // ---- final step: x = B^{-1} e_1, rho = A x, cotangent of Z_L = y x^H
+  // ---- final step: x = B^{-1} e_1 (B^{-1} by elimination), rho = A x
   const double2* zL = reinterpret_cast<const double2*>(pws + (long long)(a.ck.max_ckpt - 1) * a.ck.state_bytes);
-  for (int e = tid; e < NP * NP; e += NTHREADS) {
-    const int r = e / NP;
-    const double g2v = s.g2s[r];
-    const double gr = g2v >= 0.0 ? sqrt(g2v) : 0.0, gi = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
-    const double2 q = zL[e], pp = zL[NP * NP + e];
-    const double qr = gr * q.x - gi * q.y, qi = gr * q.y + gi * q.x;
-    s.zb[e] = make_double2(qr + pp.y, qi - pp.x);  // B = Gamma Q - iP
-    const int c = e - r * NP;
-    s.zb[NP * NP + e] = make_double2(r == c ? 1.0 : 0.0, 0.0);
-  }
-  __syncthreads();
-  gauss_jordan(s.zb, s.gj_colp, s.gj_colk, s.gj_rowk, &s.flag_singular, N, tid);
-  const double2* Binv = s.zb + NP * NP;
-  if (tid < NP) s.x[tid] = tid < N ? Binv[tid * NP + 0] : make_double2(0.0, 0.0);
-  __syncthreads();
-  // rho = A x with A = Gamma Q + iP (rows < N), into tmp
+  double2 yc, yd;  // cotangent of row j of the current state
   {
-    const int j = tid >> 2, part = tid & 3;
-    double2 acc = make_double2(0.0, 0.0);
-    if (j < N) {
-      const double g2v = s.g2s[j];
+    double2 z[16];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int r = w + BW * m;
+      const double g2v = s.g2s[r];
       const double gr = g2v >= 0.0 ? sqrt(g2v) : 0.0, gi = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
-      for (int k = part; k < N; k += 4) {
-        const double2 q = zL[j * NP + k], pp = zL[NP * NP + j * NP + k];
-        const double2 aj = make_double2(gr * q.x - gi * q.y - pp.y, gr * q.y + gi * q.x + pp.x);
-        acc.x += aj.x * s.x[k].x - aj.y * s.x[k].y;
-        acc.y += aj.x * s.x[k].y + aj.y * s.x[k].x;
+      const double2 q = zL[r * NP + lane], pp = zL[NP * NP + r * NP + lane];
+      z[m] = make_double2(gr * q.x - gi * q.y + pp.y, gr * q.y + gi * q.x - pp.x);  // Gamma Q - iP
+    }
+    if (tid < NP) s.x[tid] = make_double2(0.0, 0.0);
+    const int pos = gj_inverse<BW>(z, N, lane, w, s.gj_row, s.gj_col, s.gj_piv, &s.flag_singular);
+    // slot sl = w + BW (m - 8) < N holds row gj_piv[sl] of B^{-1}, column pos in this lane
+    if (pos == 0) {
+#pragma unroll
+      for (int m = 8; m < 16; ++m) {
+        const int sl = w + BW * (m - 8);
+        if (sl < N) s.x[s.gj_piv[sl]] = z[m];
       }
     }
-    acc.x += __shfl_xor(acc.x, 1, 64);
-    acc.y += __shfl_xor(acc.y, 1, 64);
-    acc.x += __shfl_xor(acc.x, 2, 64);
-    acc.y += __shfl_xor(acc.y, 2, 64);
-    if (part == 0) s.tmp[j] = acc;
-  }
-  __syncthreads();
-  // rho_bar (into tmp2)
-  if (tid < NP) {
+    __syncthreads();
+    // rho_j = sum_k A[j][k] x_k, A = Gamma Q + iP
+    double2 rho;
+    {
+      const double gr = g2j >= 0.0 ? sqrt(g2j) : 0.0, gi = g2j >= 0.0 ? 0.0 : -sqrt(-g2j);
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int k = 8 * part + q;
+        const double2 qv = zL[j * NP + k], pv = zL[NP * NP + j * NP + k];
+        const double2 av = make_double2(gr * qv.x - gi * qv.y - pv.y, gr * qv.y + gi * qv.x + pv.x);
+        acc = cadd(acc, cmul(av, s.x[k]));
+      }
+      rho = row_sum(acc);
+    }
+    // rho_bar
     double2 rb = make_double2(0.0, 0.0);
-    const double gj = s.g2s[tid];
-    if (tid < N && gj > 0.0) {
-      double wgt = sqrt(s.g2s[0]) / sqrt(gj);
+    if (j < N && g2j > 0.0) {
+      double wgt = sqrt(s.g2s[0]) / sqrt(g2j);
       if (a.convention == 1) wgt *= sin(th0);
-      const double sc = 2.0 * wgt * a.dLdI[(long long)p * a.ld + tid];
-      rb = make_double2(sc * s.tmp[tid].x, sc * s.tmp[tid].y);
+      const double sc = 2.0 * wgt * a.dLdI[(long long)p * a.ld + j];
+      rb = make_double2(sc * rho.x, sc * rho.y);
     }
-    s.tmp2[tid] = rb;
-  }
-  __syncthreads();
-  // x_bar = A^H rho_bar (into tmp)
-  {
-    const int k = tid >> 2, part = tid & 3;
-    double2 acc = make_double2(0.0, 0.0);
-    if (k < N)
-      for (int j = part; j < N; j += 4) {
-        const double g2v = s.g2s[j];
-        const double gr = g2v >= 0.0 ? sqrt(g2v) : 0.0, gi = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
-        const double2 q = zL[j * NP + k], pp = zL[NP * NP + j * NP + k];
-        const double2 aj = make_double2(gr * q.x - gi * q.y - pp.y, gr * q.y + gi * q.x + pp.x);
-        const double2 t = cmulc(aj, s.tmp2[j]);
-        acc.x += t.x;
-        acc.y += t.y;
-      }
-    acc.x += __shfl_xor(acc.x, 1, 64);
-    acc.y += __shfl_xor(acc.y, 1, 64);
-    acc.x += __shfl_xor(acc.x, 2, 64);
-    acc.y += __shfl_xor(acc.y, 2, 64);
+    if (part == 0) s.vin[0][j] = rb;
     __syncthreads();
-    if (part == 0) s.tmp[k] = acc;
-  }
-  __syncthreads();
-  // w = Binv^H x_bar; y = [conj(Gamma)(rho_bar - w); -i (rho_bar + w)]
-  {
-    const int k = tid >> 2, part = tid & 3;
-    double2 acc = make_double2(0.0, 0.0);
-    if (k < N)
-      for (int j = part; j < N; j += 4) {
-        const double2 t = cmulc(Binv[j * NP + k], s.tmp[j]);
-        acc.x += t.x;
-        acc.y += t.y;
-      }
-    acc.x += __shfl_xor(acc.x, 1, 64);
-    acc.y += __shfl_xor(acc.y, 1, 64);
-    acc.x += __shfl_xor(acc.x, 2, 64);
-    acc.y += __shfl_xor(acc.y, 2, 64);
-    if (part == 0 && k < NP) {
-      double2 cbv = make_double2(0.0, 0.0), dbv = make_double2(0.0, 0.0);
-      if (k < N) {
-        const double g2v = s.g2s[k];
+    // x_bar_k = sum_j conj(A[j][k]) rho_bar_j
+    double2 xbar;
+    {
+      const int k = j;
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int jj = 8 * part + q;
+        const double g2v = s.g2s[jj];
         const double gr = g2v >= 0.0 ? sqrt(g2v) : 0.0, gi = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
-        const double2 rb = s.tmp2[k];
-        const double2 dm = make_double2(rb.x - acc.x, rb.y - acc.y);
-        cbv = make_double2(gr * dm.x + gi * dm.y, gr * dm.y - gi * dm.x);  // conj(Gamma) (rho_bar - w)
-        const double2 sp = make_double2(rb.x + acc.x, rb.y + acc.y);
-        dbv = make_double2(sp.y, -sp.x);                                    // -i (rho_bar + w)
+        const double2 qv = zL[jj * NP + k], pv = zL[NP * NP + jj * NP + k];
+        const double2 av = make_double2(gr * qv.x - gi * qv.y - pv.y, gr * qv.y + gi * qv.x + pv.x);
+        acc = cadd(acc, cmulc(av, s.vin[0][jj]));
       }
-      s.cb_[k] = cbv;
-      s.db_[k] = dbv;
+      xbar = row_sum(acc);
     }
+    if (part == 0) s.vin[1][j] = xbar;
+    __syncthreads();
+    // w_k = sum_j conj(Binv[j][k]) xbar_j: lane holds column pos of the rows in its slots
+    {
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int m = 8; m < 16; ++m) {
+        const int sl = w + BW * (m - 8);
+        if (sl < N) acc = cadd(acc, cmulc(z[m], s.vin[1][s.gj_piv[sl]]));
+      }
+      s.red[w][pos] = acc;
+    }
+    __syncthreads();
+    double2 wv = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < BW; ++q) wv = cadd(wv, s.red[q][j]);
+    yc = make_double2(0.0, 0.0);
+    yd = make_double2(0.0, 0.0);
+    if (j < N) {
+      const double gr = g2j >= 0.0 ? sqrt(g2j) : 0.0, gi = g2j >= 0.0 ? 0.0 : -sqrt(-g2j);
+      const double2 dm = make_double2(rb.x - wv.x, rb.y - wv.y);
+      yc = make_double2(gr * dm.x + gi * dm.y, gr * dm.y - gi * dm.x);  // conj(Gamma) (rho_bar - w)
+      const double2 sp = make_double2(rb.x + wv.x, rb.y + wv.y);
+      yd = make_double2(sp.y, -sp.x);                                    // -i (rho_bar + w)
+    }
+    __syncthreads();
   }
-  __syncthreads();
 
-  // ---- slices, last to first
-  for (int i = L - 1; i >= 0; --i) {
-    if (pws[a.ck.flags_off + i]) {
-      // Through Z' = Z Q^{-1} (with its dependence on Z): the cotangent
-      // y' x'^H of Z' = [I; R] becomes y x^H with x = Q^{-1} x' and
-      // y = y' - [Z'^H y'; 0] = [-R^H y'_(c'); y'_(c')].  The projection keeps y
-      // free of the components that grow under the backward recursion.
-      const double2* rz = reinterpret_cast<const double2*>(pws + (long long)(i + 1) * a.ck.state_bytes) + NP * NP;
-      matvec_dense_h(rz, s.db_, s.tmp, N, tid);
+  // Crossing from the start of slice i back into slice i - 1: the
+  // transformation after slice i - 1 (if any), then psi_{i-1} = Z_{i-1} x.
+  double2 psic, psid;
+  auto cross = [&](int i, const double2 (&zc)[8], const double2 (&zd)[8]) {
+    if (flags[i - 1]) {
+      // y_c = -R^H y_d with [I; R] the stored state i
+      const double2* R =
+          (i == L ? zL : reinterpret_cast<const double2*>(pws + (long long)i * a.ck.state_bytes)) + NP * NP;
+      if (part == 0) s.vin[0][j] = yd;
       __syncthreads();
-      if (tid < NP) s.cb_[tid] = make_double2(-s.tmp[tid].x, -s.tmp[tid].y);
+      const double2 t = dense_row_h(R, s.vin[0], j, part);
+      yc = make_double2(-t.x, -t.y);
+      // x = T_{i-1} x
+      const double2* Tm = reinterpret_cast<const double2*>(pws + a.ck.q_off + (long long)(i - 1) * NP * NP * sizeof(double2));
+      const double2 xn = dense_row(Tm, s.x, j, part);
       __syncthreads();
-      const double2* qs = reinterpret_cast<const double2*>(pws + a.ck.q_off + (long long)i * NP * NP * sizeof(double2));
-      invert_into_bottom(s, qs, N, tid);
-      matvec_dense(s.zb + NP * NP, s.x, s.tmp, N, tid);  // shared-memory matrix via generic pointer
-      __syncthreads();
-      if (tid < NP) s.x[tid] = s.tmp[tid];
+      if (part == 0) s.x[j] = xn;
       __syncthreads();
     }
-    // psi = Z_i x
-    const double2* zi = reinterpret_cast<const double2*>(pws + (long long)i * a.ck.state_bytes);
-    matvec_dense(zi, s.x, s.pc, N, tid);
-    matvec_dense(zi + NP * NP, s.x, s.pd, N, tid);
-    const int nb = i * nps;
-    __syncthreads();
-    // RK stages on psi: Y_r = psi + h sum_{j<r} a_rj K_j,  K_r = (Y_r^(c'), -M_r Y_r^(c))
-    for (int r = 0; r < a.stages; ++r) {
-      if (tid < NP) {
-        double2 c = s.pc[tid], dd = s.pd[tid];
-        for (int j2 = 0; j2 < r; ++j2) {
-          const double ar = a.A[r][j2];
-          if (ar != 0.0) {
-            c.x += h * ar * s.sv.yd[j2][tid].x;
-            c.y += h * ar * s.sv.yd[j2][tid].y;
-            dd.x += h * ar * s.sv.kd[j2][tid].x;
-            dd.y += h * ar * s.sv.kd[j2][tid].y;
-          }
-        }
-        s.sv.yc[r][tid] = c;
-        s.sv.yd[r][tid] = dd;
+    double2 ac = make_double2(0.0, 0.0), ad = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double2 xk = s.x[8 * part + q];
+      ac = cadd(ac, cmul(zc[q], xk));
+      ad = cadd(ad, cmul(zd[q], xk));
+    }
+    psic = row_sum(ac);
+    psid = row_sum(ad);
+  };
+  {
+    double2 zc[8], zd[8];
+    const double2* zi = reinterpret_cast<const double2*>(pws + (long long)(L - 1) * a.ck.state_bytes);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      zc[q] = zi[j * NP + 8 * part + q];
+      zd[q] = zi[NP * NP + j * NP + 8 * part + q];
+    }
+    cross(L, zc, zd);
+  }
+
+  for (int i = L - 1; i >= 0; --i) {
+    const int nb = i * NPS;
+    // loads for slice i - 1: its new node tables and its start state
+    double2 pf[3];
+    double2 zc[8], zd[8];
+    if (i > 0) {
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int e = tid + BT * t;
+        if (e < NPS * box) pf[t] = Us[(long long)(nb - NPS) * box + e];
       }
-      load_table(s, Us, nb + a.stage_node[r], S.box, tid);
+      const double2* zi = reinterpret_cast<const double2*>(pws + (long long)(i - 1) * a.ck.state_bytes);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        zc[q] = zi[j * NP + 8 * part + q];
+        zd[q] = zi[NP * NP + j * NP + 8 * part + q];
+      }
+    }
+    // RK stages on psi: Y_r = psi + h sum_{m<r} a_rm K_m, K_r = (Y_r^(c'), -M_r Y_r^(c))
+    double2* gs = gb + (long long)i * NS * 2 * NP;
+    double2 Yd[NS], Kd[NS];
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      double2 yr = psic, ydr = psid;
+#pragma unroll
+      for (int m = 0; m < r; ++m) {
+        if (T::a[r][m] != 0.0) {
+          yr = caxpy(h * T::a[r][m], Yd[m], yr);
+          ydr = caxpy(h * T::a[r][m], Kd[m], ydr);
+        }
+      }
+      Yd[r] = ydr;
+      if (part == 0) {
+        s.vin[r & 1][j] = yr;
+        gs[r * 2 * NP + j] = yr;  // v_r
+      }
       __syncthreads();
-      matvec_u(s, s.tb[0], s.sv.yc[r], s.tmp, false, N, S.box, tid);
-      __syncthreads();
-      if (tid < NP) s.sv.kd[r][tid] = make_double2(-s.tmp[tid].x, -s.tmp[tid].y);
-      __syncthreads();
+      const double2 mv = matvec_row<false>(s.tb[(nb + T::node[r]) % RING], s.vin[r & 1], ixf, part, j, g2j);
+      Kd[r] = make_double2(-mv.x, -mv.y);
     }
     // adjoint of the step, stages last to first
-    for (int r = a.stages - 1; r >= 0; --r) {
-      if (tid < NP) {
-        double2 kc = make_double2(h * a.b[r] * s.cb_[tid].x, h * a.b[r] * s.cb_[tid].y);
-        double2 kdb = make_double2(h * a.b[r] * s.db_[tid].x, h * a.b[r] * s.db_[tid].y);
-        for (int m = r + 1; m < a.stages; ++m) {
-          const double am = a.A[m][r];
-          if (am != 0.0) {
-            kc.x += h * am * s.sv.ybc[m][tid].x;
-            kc.y += h * am * s.sv.ybc[m][tid].y;
-            kdb.x += h * am * s.sv.ybd[m][tid].x;
-            kdb.y += h * am * s.sv.ybd[m][tid].y;
-          }
+    double2 Ybc[NS], Ybd[NS];
+#pragma unroll
+    for (int r = NS - 1; r >= 0; --r) {
+      double2 kc = make_double2(h * T::b[r] * yc.x, h * T::b[r] * yc.y);
+      double2 kd = make_double2(h * T::b[r] * yd.x, h * T::b[r] * yd.y);
+#pragma unroll
+      for (int m = r + 1; m < NS; ++m) {
+        if (T::a[m][r] != 0.0) {
+          kc = caxpy(h * T::a[m][r], Ybc[m], kc);
+          kd = caxpy(h * T::a[m][r], Ybd[m], kd);
         }
-        s.sv.ybd[r][tid] = kc;   // Y_bar^(c') of stage r = K_bar^(c)
-        s.tmp2[tid] = kdb;    // K_bar^(c') of stage r
       }
-      load_table(s, Us, nb + a.stage_node[r], S.box, tid);
-      __syncthreads();
-      matvec_u(s, s.tb[0], s.tmp2, s.tmp, true, N, S.box, tid);
-      __syncthreads();
-      if (tid < NP) s.sv.ybc[r][tid] = make_double2(-s.tmp[tid].x, -s.tmp[tid].y);
-      // dL/dU at this stage's node: sum over (j,k) of a rod difference of
-      // g_j conj(v_k) with g = -K_bar^(c'), v = Y_r^(c)
-      double2* un = ub + (long long)(nb + a.stage_node[r]) * S.box;
-      for (int bin = tid; bin < S.box; bin += NTHREADS) {
-        double2 acc = make_double2(0.0, 0.0);
-        for (int t = bptr[bin]; t < bptr[bin + 1]; ++t) {
-          const int jk = bjk[t];
-          const int j = jk / NP, k = jk - j * NP;
-          const double2 g = s.tmp2[j];
-          const double2 v = s.sv.yc[r][k];
-          // -g * conj(v)
-          acc.x -= g.x * v.x + g.y * v.y;
-          acc.y -= g.y * v.x - g.x * v.y;
-        }
-        const double2 o = un[bin];
-        un[bin] = make_double2(o.x + acc.x, o.y + acc.y);
+      Ybd[r] = kc;  // Y_bar^(c') = K_bar^(c)
+      const int buf = (r + 1) & 1;  // product number 2 NS - 1 - r of the slice: buffers keep alternating
+      if (part == 0) {
+        s.vin[buf][j] = kd;
+        gs[r * 2 * NP + NP + j] = make_double2(-kd.x, -kd.y);  // g_r = -K_bar^(c')
       }
       __syncthreads();
+      const double2 mv = matvec_row<true>(s.tb[(nb + T::node[r]) % RING], s.vin[buf], ixh, part, j, g2j);
+      Ybc[r] = make_double2(-mv.x, -mv.y);  // Y_bar^(c) = -M^H K_bar^(c')
     }
-    if (tid < NP) {
-      double2 c = s.cb_[tid], dd = s.db_[tid];
-      for (int r = 0; r < a.stages; ++r) {
-        c.x += s.sv.ybc[r][tid].x;
-        c.y += s.sv.ybc[r][tid].y;
-        dd.x += s.sv.ybd[r][tid].x;
-        dd.y += s.sv.ybd[r][tid].y;
+#pragma unroll
+    for (int r = 0; r < NS; ++r) {
+      yc = cadd(yc, Ybc[r]);
+      yd = cadd(yd, Ybd[r]);
+    }
+    if (i > 0) {
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        const int e = tid + BT * t;
+        if (e < NPS * box) {
+          const int q = e / box;
+          s.tb[(nb - NPS + q) % RING][e - q * box] = pf[t];
+        }
       }
-      s.cb_[tid] = c;
-      s.db_[tid] = dd;
+      cross(i, zc, zd);
     }
     __syncthreads();
   }
 }
 
-// dL/dU of structure s = sum over its pairs of the per-pair tables (fixed order).
-__global__ __launch_bounds__(256) void reduce_ubar_kernel(ReduceArgs a) {
+// dL/dU of node n of structure s: sum over the angles of s and over the
+// stages that use node n of g v^H, binned by rod difference:
+//   dU[n][d] = sum_{(j,k): g_j - g_k = d} sum g_j conj(v_k).
+// One workgroup per (node, structure), 256 threads; thread t accumulates row
+// t >> 2, columns (t & 3) + 4 e.
+__global__ __launch_bounds__(256) void grad_assemble_kernel(GradArgs a) {
+  __shared__ double2 vs[16][NP], gsh[16][NP];
+  __shared__ double2 C[NP][NP + 1];
   const StructDev S = a.structs[blockIdx.y];
-  const long long tot = (long long)S.n_nodes * S.box;
-  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= tot) return;
-  double2 acc = make_double2(0.0, 0.0);
-  for (int q = 0; q < S.n_angles; ++q) {
-    const double2 v = a.ubar[(long long)(S.pair_off + q) * a.ubar_stride + e];
-    acc.x += v.x;
-    acc.y += v.y;
+  const int n = blockIdx.x;
+  if (n >= S.n_nodes) return;
+  const int tid = threadIdx.x;
+  const int jr = tid >> 2, kc = tid & 3;
+  const int res = n % a.nps;
+  const int i0 = n / a.nps;
+  // contributing (slice, stage) of node n
+  int ci[2], cr[2], nc = 0;
+  for (int t = 0; t < a.n_contrib[res]; ++t) {
+    const int ii = i0 + a.contrib_di[res][t];
+    if (ii >= 0 && ii < S.n_slices) {
+      ci[nc] = ii;
+      cr[nc] = a.contrib_r[res][t];
+      ++nc;
+    }
   }
-  a.dU[S.table_off + e] = acc;
+  double2 acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = make_double2(0.0, 0.0);
+  const int total = S.n_angles * nc;
+  for (int t0 = 0; t0 < total; t0 += 16) {
+    const int cnt = min(16, total - t0);
+    for (int e = tid; e < cnt * NP; e += 256) {
+      const int t = t0 + e / NP, jj = e % NP;
+      const int pr = S.pair_off + t / nc, c = t % nc;
+      const double2* src = a.gbuf + (long long)pr * a.g_pair_stride + ((long long)ci[c] * a.stages + cr[c]) * 2 * NP;
+      vs[e / NP][jj] = src[jj];
+      gsh[e / NP][jj] = src[NP + jj];
+    }
+    __syncthreads();
+    for (int t = 0; t < cnt; ++t) {
+      const double2 g = gsh[t][jr];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[e] = cadd(acc[e], cmulc(vs[t][kc + 4 * e], g));
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) C[jr][kc + 4 * e] = acc[e];
+  __syncthreads();
+  const int* bp = a.bin_ptr + S.bin_ptr_off;
+  const int* bj = a.bin_jk + S.bin_jk_off;
+  double2* out = a.dU + S.table_off + (long long)n * S.box;
+  for (int d = tid; d < S.box; d += 256) {
+    double2 v = make_double2(0.0, 0.0);
+    for (int t = bp[d]; t < bp[d + 1]; ++t) {
+      const int jk = bj[t];
+      v = cadd(v, C[jk / NP][jk % NP]);
+    }
+    out[d] = v;
+  }
 }
 
-hipError_t launch_backward(const BwdArgs& a, hipStream_t stream) {
-  hipLaunchKernelGGL(backward_kernel, dim3(a.n_pairs), dim3(NTHREADS), 0, stream, a);
+hipError_t launch_backward(int stepper, const BwdArgs& a, hipStream_t stream) {
+  if (stepper == 0)
+    hipLaunchKernelGGL(backward_kernel<0>, dim3(a.n_pairs), dim3(BT), 0, stream, a);
+  else
+    hipLaunchKernelGGL(backward_kernel<1>, dim3(a.n_pairs), dim3(BT), 0, stream, a);
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_ubar(const ReduceArgs& a, int n_struct, long long max_table, hipStream_t stream) {
-  hipLaunchKernelGGL(reduce_ubar_kernel, dim3((unsigned)((max_table + 255) / 256), n_struct), dim3(256), 0, stream, a);
+hipError_t launch_grad_assemble(const GradArgs& a, int n_struct, int max_nodes, hipStream_t stream) {
+  hipLaunchKernelGGL(grad_assemble_kernel, dim3(max_nodes, n_struct), dim3(256), 0, stream, a);
   return hipGetLastError();
 }
 

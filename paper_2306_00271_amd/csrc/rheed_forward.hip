@@ -1,13 +1,15 @@
 // Forward propagation of the many-beam reflection problem on gfx950.
 //
-// One workgroup (4 waves, one per SIMD) owns one (structure, angle) pair for
+// One workgroup (8 waves, two per SIMD) owns one (structure, angle) pair for
 // N <= 64 beams, padded to 64.  Of the economical-form state Z = [c; c']
 // (Sec. 3.1, Eq. mateq2; the paper's Q-hat and P-hat) the upper block c lives
-// in LDS, while c' and the stage products live in registers: wave w holds rows
-// 16w .. 16w+15 of every 64 x 64 block, laid out as the output of
-// v_mfma_f64_16x16x4f64 (lane l, value v of J-tile jt -> row 16w + 4v + (l>>4),
-// column 16 jt + (l&15)), so element e = 4 jt + v of a register matrix sits at
-// LDS index ob + 256 v + 16 jt with ob = (16w + (l>>4)) 64 + (l&15).
+// in LDS, while c' and the stage products live in registers: wave w holds the
+// 16 x 32 block of rows 16 (w & 3) .. +15 and columns 32 (w >> 2) .. +31 of
+// every 64 x 64 matrix, laid out as the output of v_mfma_f64_16x16x4f64
+// (lane l, value v of J-tile jt -> row 16 (w & 3) + 4v + (l>>4), column
+// 32 (w >> 2) + 16 jt + (l&15)), so element e = 4 jt + v of a register matrix
+// sits at LDS index ob + 256 v + 16 jt with
+// ob = (16 (w & 3) + (l>>4)) 64 + 32 (w >> 2) + (l&15).
 //
 // One explicit RK step (Sec. 3.4) on y = (c, c'), y' = [[0, I], [-M, 0]] y
 // with M(z) = U(z) + Gamma^2, reduces to products G_r = M(z_i + c_r h) X_r
@@ -19,14 +21,16 @@
 // the stage input in LDS (the first stage reads c itself), the A operand
 // U_{jk} = u_{g_j - g_k} is gathered from the node's rod-difference table in
 // LDS (all angles of a structure share these tables; their coupling matrices
-// differ only in the diagonal Gamma^2), and each wave runs its four J-tiles
-// as twelve independent accumulation chains.
+// differ only in the diagonal Gamma^2), and each wave runs its two J-tiles
+// as six independent accumulation chains.
 //
 // After every slice the Gershgorin estimate xi of cond(Q) (Sec. 3.2) decides
-// the right-hand-side transformation Z <- Z Q^{-1}, done as a column Gauss-
-// Jordan elimination with partial pivoting on [Q; P] in LDS.  The final
-// reflection (Algorithm 1, last lines) applies the same elimination to
-// [Gamma Q - iP; Gamma Q + iP].
+// the right-hand-side transformation Z <- Z Q^{-1}: T = Q^{-1} by a register-
+// resident column Gauss-Jordan elimination with partial pivoting (kept for the
+// adjoint), then P <- P T as one more complex GEMM on the matrix cores and
+// Q <- I.  The final reflection (Algorithm 1, last lines) inverts
+// Gamma Q - iP the same way and applies it to the first column of
+// Gamma Q + iP.
 #include "rheed_internal.h"
 #include "rheed_gj.h"
 
@@ -34,9 +38,16 @@ namespace rheed {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
+// J-tiles (16 columns each) per wave: 2 -> 8 waves of 16 rows x 32 columns,
+// two waves per SIMD, at most ~216 registers per wave for the RK6 schedule.
+constexpr int NJT = 2;
+constexpr int NE = 4 * NJT;              // register elements per lane of one 64 x 64 matrix
+constexpr int FW = 16 / NJT;             // waves per workgroup
+constexpr int FT = FW * 64;              // threads per workgroup
+
 struct Mat {
-  double r[16];
-  double i[16];
+  double r[NE];
+  double i[NE];
 };
 
 template <int S>
@@ -55,14 +66,41 @@ struct Tab<1> {  // Butcher's 6th order, 7 stages: c = 0, 1/3, 2/3, 1/3, 1/2, 1/
 struct Lds {
   double2 xb[2 * NP * NP];   // [c; X]: c block and stage-input buffer; [Q; P] during eliminations
   double2 tb[5][MAXBOX + 1]; // node tables (Ur, Ui); entry `box` of every row stays 0
-  double2 gj_colp[2 * NP];   // elimination scratch: pivot column
-  double2 gj_colk[2 * NP];   //   column k
-  double2 gj_rowk[NP];       //   row k
+  double2 gj_row[2 * NP];    // elimination scratch: pivot rows (two steps in flight)
+  double2 gj_col[2 * NP];    //   pivot column, per wave
+  int gj_piv[NP];            //   pivot column of every step
   double g2s[NP];            // Gamma_j^2 (real), 0 on padding
   int bhk[NP][2];
-  double xi_hi[NWAVES], xi_lo[NWAVES];
+  double xo_[4 / NJT][NP];            // per-row sums of |q_ij|, j != i, per column block
+  double xdg[4 / NJT][NP];            // per-row |q_ii| partials per column block
   int flag_singular;
 };
+
+__shared__ Lds fwd_lds;
+
+// top^{-1} for the leading n x n block of the 64 x 64 matrix in s.xb[0 .. NP NP)
+// (row major), written back over it (identity outside the n x n block) and,
+// with WITH_T, also to t in global memory.  Kept out of line so that its
+// registers (the matrix is held in registers during the elimination) do not
+// add to those of the RK stages.
+template <bool WITH_T>
+__device__ __noinline__ void invert_top(int n, double2* t) {
+  Lds& s = fwd_lds;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double2 z[2 * NP / FW];
+#pragma unroll
+  for (int m = 0; m < NP / FW; ++m) z[m] = s.xb[(w + FW * m) * NP + lane];
+  const int pos = gj_inverse<FW>(z, n, lane, w, s.gj_row, s.gj_col, s.gj_piv, &s.flag_singular);
+#pragma unroll
+  for (int m = NP / FW; m < 2 * NP / FW; ++m) {
+    const int sl = w + FW * (m - NP / FW);
+    const int row = sl < n ? s.gj_piv[sl] : sl;
+    const double2 val = sl < n ? z[m] : make_double2(pos == sl ? 1.0 : 0.0, 0.0);
+    s.xb[row * NP + pos] = val;
+    if (WITH_T) t[row * NP + pos] = val;
+  }
+  __syncthreads();
+}
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -73,19 +111,19 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 template <class Epi>
 __device__ __forceinline__ void stage_gemm(const double2* __restrict__ xbuf, const double2* __restrict__ tslot,
                                            const unsigned (&gidx)[8], const double (&g2)[4], int ob, int lane,
-                                           Epi&& epi) {
+                                           int CH, Epi&& epi) {
   __builtin_amdgcn_sched_barrier(0);
-  d4 t1[4], t2[4], t3[4];
+  d4 t1[NJT], t2[NJT], t3[NJT];
 #pragma unroll
-  for (int jt = 0; jt < 4; ++jt) t1[jt] = t2[jt] = t3[jt] = d4{0, 0, 0, 0};
-  const int bb = (lane >> 4) * NP + (lane & 15);
+  for (int jt = 0; jt < NJT; ++jt) t1[jt] = t2[jt] = t3[jt] = d4{0, 0, 0, 0};
+  const int bb = (lane >> 4) * NP + 16 * NJT * CH + (lane & 15);
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const unsigned gi = (q & 1) ? (gidx[q >> 1] >> 16) : (gidx[q >> 1] & 0xffffu);
     const double2 u = tslot[gi];
     const double us = u.x + u.y;
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt) {
+    for (int jt = 0; jt < NJT; ++jt) {
       const double2 x = xbuf[bb + 256 * q + 16 * jt];
       t1[jt] = mfma(u.x, x.x, t1[jt]);
       t2[jt] = mfma(u.y, x.y, t2[jt]);
@@ -94,7 +132,7 @@ __device__ __forceinline__ void stage_gemm(const double2* __restrict__ xbuf, con
     if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
-  for (int jt = 0; jt < 4; ++jt) {
+  for (int jt = 0; jt < NJT; ++jt) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const double2 own = xbuf[ob + 256 * v + 16 * jt];
@@ -105,18 +143,49 @@ __device__ __forceinline__ void stage_gemm(const double2* __restrict__ xbuf, con
   __builtin_amdgcn_sched_barrier(0);
 }
 
+// D = A B for 64 x 64 complex A and B in LDS (row major), the wave's 16 x 32
+// block of D handed to epi(e, Re D, Im D); 3-real-product form on FP64 MFMA.
+template <class Epi>
+__device__ __forceinline__ void dense_gemm(const double2* __restrict__ abuf, const double2* __restrict__ bbuf,
+                                           int lane, int RT, int CH, Epi&& epi) {
+  __builtin_amdgcn_sched_barrier(0);
+  d4 t1[NJT], t2[NJT], t3[NJT];
+#pragma unroll
+  for (int jt = 0; jt < NJT; ++jt) t1[jt] = t2[jt] = t3[jt] = d4{0, 0, 0, 0};
+  const int ab = (16 * RT + (lane & 15)) * NP + (lane >> 4);
+  const int bb = (lane >> 4) * NP + 16 * NJT * CH + (lane & 15);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const double2 u = abuf[ab + 4 * q];
+    const double us = u.x + u.y;
+#pragma unroll
+    for (int jt = 0; jt < NJT; ++jt) {
+      const double2 x = bbuf[bb + 256 * q + 16 * jt];
+      t1[jt] = mfma(u.x, x.x, t1[jt]);
+      t2[jt] = mfma(u.y, x.y, t2[jt]);
+      t3[jt] = mfma(us, x.x + x.y, t3[jt]);
+    }
+    if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int jt = 0; jt < NJT; ++jt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) epi(jt * 4 + v, t1[jt][v] - t2[jt][v], t3[jt][v] - t1[jt][v] - t2[jt][v]);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 #define OWN(e) (ob + 256 * ((e) & 3) + 16 * ((e) >> 2))
 
 __device__ __forceinline__ void store_mat(double2* buf, const Mat& m, int ob) {
 #pragma unroll
-  for (int e = 0; e < 16; ++e) buf[OWN(e)] = make_double2(m.r[e], m.i[e]);
+  for (int e = 0; e < NE; ++e) buf[OWN(e)] = make_double2(m.r[e], m.i[e]);
 }
 
 // Loads nodes [n0, n1) of a structure's table into their ring slots.
-template <int SLOTS>
+template <int SLOTS, int NT>
 __device__ __forceinline__ void load_nodes(Lds& s, const double2* __restrict__ Us, int box, int n0, int n1, int tid) {
   const int total = (n1 - n0) * box;
-  for (int e = tid; e < total; e += NTHREADS) {
+  for (int e = tid; e < total; e += NT) {
     const int q = e / box;
     const int nn = n0 + q;
     s.tb[nn % SLOTS][e - q * box] = Us[(long long)nn * box + (e - q * box)];
@@ -124,12 +193,13 @@ __device__ __forceinline__ void load_nodes(Lds& s, const double2* __restrict__ U
 }
 
 template <int STEPPER>
-__global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
+__global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
   using T = Tab<STEPPER>;
-  __shared__ Lds s;
+  Lds& s = fwd_lds;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
+  const int RT = w & 3, CH = w >> 2;   // row tile, column block of this wave
   const int p = blockIdx.x;
   const StructDev S = a.structs[a.pair_struct[p]];
   const int N = S.n_beams;
@@ -162,12 +232,12 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
   __syncthreads();
   double g2[4];
 #pragma unroll
-  for (int v = 0; v < 4; ++v) g2[v] = s.g2s[16 * w + 4 * v + (lane >> 4)];
+  for (int v = 0; v < 4; ++v) g2[v] = s.g2s[16 * RT + 4 * v + (lane >> 4)];
   // gather indices of U_{ik} = u_{g_i - g_k} for the A operand of this lane
   unsigned gidx[8];
   {
     const int W = 2 * S.kd + 1;
-    const int iA = 16 * w + (lane & 15);
+    const int iA = 16 * RT + (lane & 15);
     const int baseA = (s.bhk[iA][0] + S.hd) * W + (s.bhk[iA][1] + S.kd);
 #pragma unroll
     for (int q = 0; q < 16; q += 2) {
@@ -179,12 +249,12 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
   }
   double2* cb = s.xb;             // c (upper block of Z), LDS resident
   double2* xb = s.xb + NP * NP;   // stage input X_r
-  int ob = (16 * w + (lane >> 4)) * NP + (lane & 15);
+  int ob = (16 * RT + (lane >> 4)) * NP + 16 * NJT * CH + (lane & 15);
   // Z0 = [I; i Gamma]  (spans the same columns as S^{-1}[I; O] of Algorithm 1)
   Mat d;
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int row = 16 * w + 4 * (e & 3) + (lane >> 4), col = 16 * (e >> 2) + (lane & 15);
+  for (int e = 0; e < NE; ++e) {
+    const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), col = 16 * (NJT * CH + (e >> 2)) + (lane & 15);
     const bool dg = (row == col);
     cb[OWN(e)] = make_double2(dg ? 1.0 : 0.0, 0.0);
     // i Gamma_row with Gamma = sqrt(g2) (open) or -i sqrt(-g2) (evanescent)
@@ -196,20 +266,20 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
   char* pws = save ? a.ws + (long long)p * a.ck.pair_stride : nullptr;
   int nrhst = 0;
 
-  load_nodes<T::slots>(s, Us, S.box, 0, 1, tid);
+  load_nodes<T::slots, FT>(s, Us, S.box, 0, 1, tid);
   for (int i = 0; i < L; ++i) {
     // keep the address base from being expanded into loop-invariant registers
     asm volatile("" : "+v"(ob));
     if (save && (i % a.ck.every) == 0) {
       double2* st = reinterpret_cast<double2*>(pws + (long long)(i / a.ck.every) * a.ck.state_bytes);
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
+      for (int e = 0; e < NE; ++e) {
         st[OWN(e)] = cb[OWN(e)];
         st[NP * NP + OWN(e)] = make_double2(d.r[e], d.i[e]);
       }
     }
     const int nb = i * T::nodes;  // node index of c = 0 in this slice
-    load_nodes<T::slots>(s, Us, S.box, nb + 1, nb + T::nodes + 1, tid);
+    load_nodes<T::slots, FT>(s, Us, S.box, nb + 1, nb + T::nodes + 1, tid);
     const double hh = h * h;
     if constexpr (STEPPER == 0) {
       const double2* t0 = s.tb[nb % 3];
@@ -217,19 +287,19 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
       const double2* t1 = s.tb[(nb + 2) % 3];
       // X1 = c (read in place), X2 = c + h/2 c'
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
+      for (int e = 0; e < NE; ++e) {
         const double2 cv = cb[OWN(e)];
         xb[OWN(e)] = make_double2(cv.x + 0.5 * h * d.r[e], cv.y + 0.5 * h * d.i[e]);
       }
       __syncthreads();
       Mat G1, G2;
-      stage_gemm(cb, t0, gidx, g2, ob, lane, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
-      stage_gemm(xb, th, gidx, g2, ob, lane, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
+      stage_gemm(cb, t0, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
+      stage_gemm(xb, th, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
       __syncthreads();
       // X3 = c + h/2 c' - h^2/4 G1 -> LDS;  X4 = c + h c' - h^2/2 G2 (kept in G1);
       // c <- c + h c' - h^2/6 (G1 + G2);  c' <- c' - h/6 (G1 + 2 G2)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
+      for (int e = 0; e < NE; ++e) {
         const double2 cv = cb[OWN(e)];
         const double dr = d.r[e], di = d.i[e];
         const double g1r = G1.r[e], g1i = G1.i[e], g2r = G2.r[e], g2i = G2.i[e];
@@ -241,7 +311,7 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
         d.i[e] = di - (h / 6.0) * (g1i + 2.0 * g2i);
       }
       __syncthreads();
-      stage_gemm(xb, th, gidx, g2, ob, lane, [&](int e, double gr, double gi) {  // G3
+      stage_gemm(xb, th, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) {  // G3
         double2 cv = cb[OWN(e)];
         cv.x -= (hh / 6.0) * gr;
         cv.y -= (hh / 6.0) * gi;
@@ -252,7 +322,7 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
       __syncthreads();
       store_mat(xb, G1, ob);  // X4
       __syncthreads();
-      stage_gemm(xb, t1, gidx, g2, ob, lane, [&](int e, double gr, double gi) {  // G4
+      stage_gemm(xb, t1, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) {  // G4
         d.r[e] -= (h / 6.0) * gr;
         d.i[e] -= (h / 6.0) * gi;
       });
@@ -264,28 +334,28 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
       const double2* tE = s.tb[(nb + 4) % 5];  // c = 1
       // X1 = c (read in place), X2 = c + h/3 c'
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
+      for (int e = 0; e < NE; ++e) {
         const double2 cv = cb[OWN(e)];
         xb[OWN(e)] = make_double2(cv.x + (h / 3.0) * d.r[e], cv.y + (h / 3.0) * d.i[e]);
       }
       __syncthreads();
       Mat G1, G2, G3;
-      stage_gemm(cb, tA, gidx, g2, ob, lane, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
-      stage_gemm(xb, tB, gidx, g2, ob, lane, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
+      stage_gemm(cb, tA, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
+      stage_gemm(xb, tB, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
       __syncthreads();
       // X3 = c + 2h/3 c' - h^2 (2/9) G1
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
+      for (int e = 0; e < NE; ++e) {
         const double2 cv = cb[OWN(e)];
         xb[OWN(e)] = make_double2(cv.x + (2.0 * h / 3.0) * d.r[e] - hh * (2.0 / 9.0) * G1.r[e],
                                   cv.y + (2.0 * h / 3.0) * d.i[e] - hh * (2.0 / 9.0) * G1.i[e]);
       }
       __syncthreads();
-      stage_gemm(xb, tD, gidx, g2, ob, lane, [&](int e, double gr, double gi) { G3.r[e] = gr; G3.i[e] = gi; });
+      stage_gemm(xb, tD, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) { G3.r[e] = gr; G3.i[e] = gi; });
       __syncthreads();
       // X4 = c + h/3 c' - h^2 (G1/9 - G2/18)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
+      for (int e = 0; e < NE; ++e) {
         const double2 cv = cb[OWN(e)];
         xb[OWN(e)] = make_double2(cv.x + (h / 3.0) * d.r[e] - hh * ((1.0 / 9.0) * G1.r[e] - (1.0 / 18.0) * G2.r[e]),
                                   cv.y + (h / 3.0) * d.i[e] - hh * ((1.0 / 9.0) * G1.i[e] - (1.0 / 18.0) * G2.i[e]));
@@ -295,7 +365,7 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
       Mat& X5 = G1;
       Mat& X6 = G2;
       Mat& T7 = G3;
-      stage_gemm(xb, tB, gidx, g2, ob, lane, [&](int e, double a4, double b4) {
+      stage_gemm(xb, tB, gidx, g2, ob, lane, CH, [&](int e, double a4, double b4) {
         const double2 cv = cb[OWN(e)];
         const double dr = d.r[e], di = d.i[e];
         const double a1 = G1.r[e], b1 = G1.i[e], a2 = G2.r[e], b2 = G2.i[e], a3 = G3.r[e], b3 = G3.i[e];
@@ -313,7 +383,7 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
       __syncthreads();
       store_mat(xb, X5, ob);
       __syncthreads();
-      stage_gemm(xb, tC, gidx, g2, ob, lane, [&](int e, double gr, double gi) {  // G5
+      stage_gemm(xb, tC, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) {  // G5
         T7.r[e] += hh * (8.0 / 11.0) * gr;
         T7.i[e] += hh * (8.0 / 11.0) * gi;
         double2 cv = cb[OWN(e)];
@@ -326,7 +396,7 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
       __syncthreads();
       store_mat(xb, X6, ob);
       __syncthreads();
-      stage_gemm(xb, tC, gidx, g2, ob, lane, [&](int e, double gr, double gi) {  // G6
+      stage_gemm(xb, tC, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) {  // G6
         double2 cv = cb[OWN(e)];
         cv.x += hh * (2.0 / 15.0) * gr;
         cv.y += hh * (2.0 / 15.0) * gi;
@@ -337,7 +407,7 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
       __syncthreads();
       store_mat(xb, T7, ob);  // X7
       __syncthreads();
-      stage_gemm(xb, tE, gidx, g2, ob, lane, [&](int e, double gr, double gi) {  // G7
+      stage_gemm(xb, tE, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) {  // G7
         d.r[e] -= h * (11.0 / 120.0) * gr;
         d.i[e] -= h * (11.0 / 120.0) * gi;
       });
@@ -348,8 +418,8 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
     {
       double dg[4] = {0, 0, 0, 0}, of[4] = {0, 0, 0, 0};
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = 16 * w + 4 * (e & 3) + (lane >> 4), col = 16 * (e >> 2) + (lane & 15);
+      for (int e = 0; e < NE; ++e) {
+        const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), col = 16 * (NJT * CH + (e >> 2)) + (lane & 15);
         const double2 cv = cb[OWN(e)];
         const double av = sqrt(cv.x * cv.x + cv.y * cv.y);
         if (row < N && col < N) {
@@ -357,7 +427,6 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
           else of[e & 3] += av;
         }
       }
-      double hi = 0.0, lo = 1.0e308;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
 #pragma unroll
@@ -365,51 +434,54 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
           dg[v] += __shfl_xor(dg[v], off, 64);
           of[v] += __shfl_xor(of[v], off, 64);
         }
-        const int row = 16 * w + 4 * v + (lane >> 4);
-        if (row < N) {
-          hi = fmax(hi, dg[v] + of[v]);
-          lo = fmin(lo, dg[v] - of[v]);
-        }
       }
+      if ((lane & 15) == 0) {
 #pragma unroll
-      for (int off = 16; off < 64; off <<= 1) {
-        hi = fmax(hi, __shfl_xor(hi, off, 64));
-        lo = fmin(lo, __shfl_xor(lo, off, 64));
-      }
-      if (lane == 0) {
-        s.xi_hi[w] = hi;
-        s.xi_lo[w] = lo;
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * RT + 4 * v + (lane >> 4);
+          s.xdg[CH][row] = dg[v];
+          s.xo_[CH][row] = of[v];
+        }
       }
     }
     __syncthreads();
     bool do_rhst;
     {
-      double hi = s.xi_hi[0], lo = s.xi_lo[0];
+      double dgl = 0.0, ofl = 0.0;
 #pragma unroll
-      for (int ww = 1; ww < NWAVES; ++ww) {
-        hi = fmax(hi, s.xi_hi[ww]);
-        lo = fmin(lo, s.xi_lo[ww]);
+      for (int c2 = 0; c2 < 4 / NJT; ++c2) {
+        dgl += s.xdg[c2][lane];
+        ofl += s.xo_[c2][lane];
+      }
+      double hi = lane < N ? dgl + ofl : 0.0;
+      double lo = lane < N ? dgl - ofl : 1.0e308;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
       }
       const double xi = lo > 0.0 ? hi / lo : INFINITY;
       do_rhst = xi > a.threshold;
     }
     if (save && tid == 0) pws[a.ck.flags_off + i] = do_rhst ? 1 : 0;
     if (do_rhst) {
+      // Z <- Z Q^{-1}: T = Q^{-1} by elimination (kept for the adjoint when
+      // saving), then P <- P T on the matrix cores, c <- I
       ++nrhst;
-      if (save) {
-        double2* qs = reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * NP * NP * sizeof(double2));
-#pragma unroll
-        for (int e = 0; e < 16; ++e) qs[OWN(e)] = cb[OWN(e)];
-      }
       store_mat(xb, d, ob);
       __syncthreads();
-      gauss_jordan(s.xb, s.gj_colp, s.gj_colk, s.gj_rowk, &s.flag_singular, N, tid);
+      if (save)
+        invert_top<true>(N, reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * NP * NP * sizeof(double2)));
+      else
+        invert_top<false>(N, nullptr);
+      dense_gemm(xb, cb, lane, RT, CH, [&](int e, double gr, double gi) {
+        d.r[e] = gr;
+        d.i[e] = gi;
+      });
+      __syncthreads();
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = 16 * w + 4 * (e & 3) + (lane >> 4), col = 16 * (e >> 2) + (lane & 15);
-        const double2 pv = xb[OWN(e)];
-        d.r[e] = pv.x;
-        d.i[e] = pv.y;
+      for (int e = 0; e < NE; ++e) {
+        const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), col = 16 * (NJT * CH + (e >> 2)) + (lane & 15);
         cb[OWN(e)] = make_double2((row == col) ? 1.0 : 0.0, 0.0);
       }
     }
@@ -419,14 +491,15 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
   if (save) {
     double2* st = reinterpret_cast<double2*>(pws + (long long)(a.ck.max_ckpt - 1) * a.ck.state_bytes);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
+    for (int e = 0; e < NE; ++e) {
       st[OWN(e)] = cb[OWN(e)];
       st[NP * NP + OWN(e)] = make_double2(d.r[e], d.i[e]);
     }
   }
-  // reflection: Z <- S Z = [Gamma Q - iP; Gamma Q + iP]; R = lower / upper; rho = R[:, 0]
+  // reflection: Z <- S Z = [Gamma Q - iP; Gamma Q + iP]; R = lower upper^{-1};
+  // rho = R e_1 = lower (upper^{-1} e_1)
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
+  for (int e = 0; e < NE; ++e) {
     const double2 cv = cb[OWN(e)];
     const double g2v = g2[e & 3];
     const double g_r = g2v >= 0.0 ? sqrt(g2v) : 0.0, g_i = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
@@ -437,13 +510,17 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
     xb[OWN(e)] = make_double2(qr - d.i[e], qi + d.r[e]);
   }
   __syncthreads();
-  gauss_jordan(s.xb, s.gj_colp, s.gj_colk, s.gj_rowk, &s.flag_singular, N, tid);
+  invert_top<false>(N, nullptr);
   if (tid < NP) {
     const int j = tid;
     double eta = 0.0;
     double2 rj = make_double2(0.0, 0.0);
     if (j < N) {
-      rj = xb[j * NP + 0];
+      for (int k = 0; k < N; ++k) {
+        const double2 l = xb[j * NP + k], x = cb[k * NP];
+        rj.x += l.x * x.x - l.y * x.y;
+        rj.y += l.x * x.y + l.y * x.x;
+      }
       const double g00 = s.g2s[0];
       const double gj = s.g2s[j];
       if (gj > 0.0) {
@@ -469,7 +546,7 @@ __global__ __launch_bounds__(NTHREADS, 1) void forward_kernel(FwdArgs a) {
 #undef OWN
 
 hipError_t launch_forward(int stepper, const FwdArgs& a, hipStream_t stream) {
-  dim3 grid(a.n_pairs), block(NTHREADS);
+  dim3 grid(a.n_pairs), block(FT);
   if (stepper == 0)
     hipLaunchKernelGGL(forward_kernel<0>, grid, block, 0, stream, a);
   else

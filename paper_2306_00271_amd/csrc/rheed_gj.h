@@ -4,63 +4,126 @@
 
 namespace rheed {
 
-// Wave-wide argmax of v (ties -> smaller index).
-__device__ __forceinline__ void wave_argmax(double& v, int& idx) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const double ov = __shfl_xor(v, off, 64);
-    const int oi = __shfl_xor(idx, off, 64);
-    if (ov > v || (ov == v && oi < idx)) {
-      v = ov;
-      idx = oi;
-    }
+// Maximum of a 64-bit key over the wave, by DPP: butterflies inside rows of
+// 16 lanes, then the row broadcasts; the result is read from lane 63.
+#define RHEED_DPP_MAX_STEP(CTRL, RMASK)                                                          \
+  {                                                                                              \
+    const int lo = (int)(unsigned)v, hi = (int)(unsigned)(v >> 32);                              \
+    const unsigned olo = (unsigned)__builtin_amdgcn_update_dpp(lo, lo, CTRL, RMASK, 0xf, false); \
+    const unsigned ohi = (unsigned)__builtin_amdgcn_update_dpp(hi, hi, CTRL, RMASK, 0xf, false); \
+    const unsigned long long o = ((unsigned long long)ohi << 32) | olo;                          \
+    v = o > v ? o : v;                                                                           \
   }
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long v) {
+  RHEED_DPP_MAX_STEP(0xB1, 0xf)   // quad_perm [1,0,3,2]
+  RHEED_DPP_MAX_STEP(0x4E, 0xf)   // quad_perm [2,3,0,1]
+  RHEED_DPP_MAX_STEP(0x141, 0xf)  // row_half_mirror
+  RHEED_DPP_MAX_STEP(0x140, 0xf)  // row_mirror
+  RHEED_DPP_MAX_STEP(0x142, 0xa)  // row_bcast:15
+  RHEED_DPP_MAX_STEP(0x143, 0xc)  // row_bcast:31
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), 63);
+  return ((unsigned long long)hi << 32) | lo;
 }
+#undef RHEED_DPP_MAX_STEP
 
-// Column Gauss-Jordan with partial pivoting on Z = xb viewed as [128][64]:
-// right-multiplies Z until its top block is I, so the bottom block becomes
-// bottom * top^{-1}.  Only the leading n columns / pivots are processed.
-// Each step copies the pivot column, column k and row k to LDS scratch, so
-// that the update of every element reads only its own old value and copies.
-__device__ __forceinline__ void gauss_jordan(double2* Z, double2* colp, double2* colk, double2* rowk, int* flag_singular,
-                                             int n, int tid) {
-  const int lane = tid & 63;
-  const int w = tid >> 6;
-  const int j = lane;
-  for (int k = 0; k < n; ++k) {
-    const double2 zk = Z[k * NP + lane];
-    double m2 = (lane >= k && lane < n) ? zk.x * zk.x + zk.y * zk.y : -1.0;
-    int bi = lane;
-    wave_argmax(m2, bi);
-    if (!(m2 > 0.0) && tid == 0) *flag_singular = 1;
-    if (tid < 2 * NP) {
-      colp[tid] = Z[tid * NP + bi];
-      colk[tid] = Z[tid * NP + k];
-    } else if (tid < 3 * NP) {
-      rowk[tid - 2 * NP] = Z[k * NP + (tid - 2 * NP)];
-    }
-    __syncthreads();
-    if (j < n) {
-      const double2 piv = rowk[bi];
-      const double pn = piv.x * piv.x + piv.y * piv.y;
-      const double2 ip = make_double2(piv.x / pn, -piv.y / pn);
-      const double2 mj = rowk[j == bi ? k : j];
-      const double2 f = make_double2(mj.x * ip.x - mj.y * ip.y, mj.x * ip.y + mj.y * ip.x);
-      for (int m = 0; m < 2 * NP / NWAVES; ++m) {
-        const int r = w + NWAVES * m;
-        const double2 zp = colp[r];
-        const double2 zo = (j == bi) ? colk[r] : Z[r * NP + j];
-        double2 nv;
-        if (j == k) {
-          nv = make_double2(zp.x * ip.x - zp.y * ip.y, zp.x * ip.y + zp.y * ip.x);
-        } else {
-          nv = make_double2(zo.x - (f.x * zp.x - f.y * zp.y), zo.y - (f.x * zp.y + f.y * zp.x));
-        }
-        Z[r * NP + j] = nv;
+// Register-resident inversion by column Gauss-Jordan elimination with partial
+// pivoting and no column exchanges.  A workgroup of NWV waves holds the n x n
+// matrix A (padded to NP x NP) column-wise: lane j of wave w keeps column j of
+// rows w + NWV m of A in z[m], m < IB = NP / NWV.  Step k picks, among the
+// columns not yet used, the one with the largest |A_kj| (pc_k), scales it so
+// that A_{k,pc_k} = 1 and subtracts it from every other column so that row k
+// becomes a unit row.  The same column operations, applied to I, give A^{-1};
+// row pc_k of that product is untouched (e_{pc_k}^T) until step k, so it is
+// kept in slot k only from step k on: slot s = w + NWV (m - IB) lives in z[m],
+// m >= IB.  At the end slot s < n holds row pc_s of A^{-1}, with the entry of
+// column c of A^{-1} in the lane whose column was the pivot of step c (the
+// returned position; columns >= n keep their own, and their rows < n of A must
+// be zero, as padding is).  pivrec[s] = pc_s.  Per step every wave updates
+// about IB + 1 rows per lane: the rows k.. of A and the slots ..k.
+// Per step: one workgroup barrier.  Row k, written to LDS by the wave that
+// owns it as soon as the previous step has produced it, is read by every
+// wave, which finds the pivot itself (largest |A_kj|^2 with the low 6 bits of
+// its bit pattern replaced by 63 - j, so that ties go to the smaller index,
+// reduced by DPP); the pivot column is exchanged through LDS inside each wave,
+// all of its rows at once.
+//   rowbuf: 2 NP entries, colbuf: 2 NP entries, pivrec: NP ints.
+template <int NWV, int KB>
+struct GjInv {
+  static constexpr int IB = NP / NWV, RM = 2 * NP / NWV;
+  static __device__ __forceinline__ void run(double2 (&z)[RM], int n, int lane, int wu, bool& used, int& pos,
+                                             double2* rowbuf, double2* colbuf, int* pivrec, int* flag_singular) {
+    if (KB * NWV >= n) return;
+    double2* cw = colbuf + wu * RM;
+    for (int kk = 0; kk < NWV; ++kk) {
+      const int k = KB * NWV + kk;
+      if (k >= n) return;
+      const int slot = k & 1;
+      __syncthreads();
+      const double2 v = rowbuf[slot * NP + lane];
+      const double m2 = v.x * v.x + v.y * v.y;
+      unsigned long long key = 0;
+      if (!used && lane < n)
+        key = (((unsigned long long)__double_as_longlong(m2)) & ~63ull) | (unsigned long long)(63 - lane);
+      key = wave_max_u64(key);
+      if ((key >> 6) == 0 && lane == 0 && wu == 0) *flag_singular = 1;
+      const int pc = 63 - (int)(key & 63);
+      if (lane == 0 && wu == 0) pivrec[k] = pc;
+      if (wu == kk) z[IB + KB] = make_double2(lane == pc ? 1.0 : 0.0, 0.0);  // slot k starts as e_pc
+      if (lane == pc) {
+        used = true;
+        pos = k;
+#pragma unroll
+        for (int m = KB; m <= IB + KB; ++m) cw[m] = z[m];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      double2 zp[RM];
+#pragma unroll
+      for (int m = KB; m <= IB + KB; ++m) zp[m] = cw[m];
+      const double2 piv = rowbuf[slot * NP + pc];
+      const double inv = 1.0 / (piv.x * piv.x + piv.y * piv.y);
+      const double2 ip = make_double2(piv.x * inv, -piv.y * inv);
+      // column pc becomes z ip = z - (1 - ip) z; every other column z - (a_kj ip) z_pc
+      double2 f = make_double2(v.x * ip.x - v.y * ip.y, v.x * ip.y + v.y * ip.x);
+      if (lane == pc) f = make_double2(1.0 - ip.x, -ip.y);
+#pragma unroll
+      for (int m = KB; m <= IB + KB; ++m) {
+        // rows of A above row k are final; slots above slot k are not in use yet
+        const bool act = (m == KB) ? wu >= kk : (m == IB + KB) ? wu <= kk : true;
+        if (act) z[m] = make_double2(z[m].x - (f.x * zp[m].x - f.y * zp[m].y), z[m].y - (f.x * zp[m].y + f.y * zp[m].x));
+      }
+      // publish row k + 1 (owned by wave (k + 1) % NWV, register (k + 1) / NWV)
+      if (k + 1 < n && wu == (k + 1) % NWV) {
+        const double2 rv = ((k + 1) / NWV == KB) ? z[KB] : z[KB + 1 < IB ? KB + 1 : KB];
+        rowbuf[(slot ^ 1) * NP + lane] = rv;
       }
     }
-    __syncthreads();
+    GjInv<NWV, KB + 1>::run(z, n, lane, wu, used, pos, rowbuf, colbuf, pivrec, flag_singular);
   }
+};
+
+template <int NWV>
+struct GjInv<NWV, NP / NWV> {
+  static __device__ __forceinline__ void run(double2 (&)[2 * NP / NWV], int, int, int, bool&, int&, double2*,
+                                             double2*, int*, int*) {}
+};
+
+// z[m < NP / NWV]: rows of A as above; z[m >= NP / NWV] is overwritten.
+// Returns this lane's column position; pivrec is valid after the call.
+template <int NWV>
+__device__ __forceinline__ int gj_inverse(double2 (&z)[2 * NP / NWV], int n, int lane, int w, double2* rowbuf,
+                                          double2* colbuf, int* pivrec, int* flag_singular) {
+  bool used = false;
+  int pos = lane;
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+#pragma unroll
+  for (int m = NP / NWV; m < 2 * NP / NWV; ++m) z[m] = make_double2(0.0, 0.0);
+  if (wu == 0) rowbuf[lane] = z[0];  // row 0
+  GjInv<NWV, 0>::run(z, n, lane, wu, used, pos, rowbuf, colbuf, pivrec, flag_singular);
+  __syncthreads();
+  return pos;
 }
 
 }  // namespace rheed

@@ -6,8 +6,6 @@
 namespace rheed {
 
 constexpr int NP = 64;          // padded beam count of the N <= 64 kernels
-constexpr int NWAVES = 4;       // waves per workgroup of the propagation kernels (one per SIMD)
-constexpr int NTHREADS = NWAVES * 64;
 constexpr int MAXBOX = 300;     // rod-difference entries per node table row in LDS
 
 // Device-side copy of one structure.
@@ -24,15 +22,15 @@ struct StructDev {
 };
 
 // Per-pair storage kept by the forward pass for the adjoint: the state (c, c')
-// at the start of every slice and after the last one, the upper block Q of
-// every slice that was followed by a right-hand-side transformation (before
-// it), and one byte per slice telling whether that transformation was applied.
+// at the start of every slice and after the last one, T = Q^{-1} of every
+// slice that was followed by a right-hand-side transformation, and one byte
+// per slice telling whether that transformation was applied.
 struct CkptLayout {
   long long pair_stride;   // bytes per pair
   long long state_bytes;   // one state: 2 * NP * NP complex
   int every;               // slices between stored states (1: every slice)
   int max_ckpt;            // stored states per pair, including the final state
-  long long q_off;         // byte offset of the Q slots (one per slice)
+  long long q_off;         // byte offset of the T slots (one per slice)
   long long flags_off;     // byte offset of the decision bytes
 };
 
@@ -82,30 +80,32 @@ struct BwdArgs {
   const double* dLdI;        // [P][ld]
   const char* ws;            // forward workspace
   CkptLayout ck;
-  double2* ubar;             // per-pair dL/dU tables, stride ubar_stride elements
-  long long ubar_stride;
-  const int* bin_ptr;        // per structure: box + 1 offsets into bin_jk
-  const int* bin_jk;         // j * NP + k
+  double2* gbuf;             // stage buffer: per pair [slice][stage][v | g][NP]
+  long long g_pair_stride;   // elements per pair
   int ld;
   int convention;
   int n_pairs;
-  int stages;
-  int nodes_per_slice;
-  int stage_node[7];         // node offset of each stage inside its slice (nodes_per_slice = next slice)
-  double A[7][7];
-  double b[7];
+  int pad;
 };
 
-struct ReduceArgs {
+// Stages that use node n = i * nps + res: (slice i + contrib_di, stage contrib_r).
+struct GradArgs {
   const StructDev* structs;
-  const double2* ubar;
-  long long ubar_stride;
+  const double2* gbuf;
+  long long g_pair_stride;
+  const int* bin_ptr;        // per structure: box + 1 offsets into bin_jk
+  const int* bin_jk;         // j * NP + k
   double2* dU;               // all tables
+  int stages;
+  int nps;
+  int n_contrib[4];
+  int contrib_di[4][2];
+  int contrib_r[4][2];
 };
 
 hipError_t launch_forward(int stepper, const FwdArgs& a, hipStream_t stream);
-hipError_t launch_backward(const BwdArgs& a, hipStream_t stream);
-hipError_t launch_reduce_ubar(const ReduceArgs& a, int n_struct, long long max_table, hipStream_t stream);
+hipError_t launch_backward(int stepper, const BwdArgs& a, hipStream_t stream);
+hipError_t launch_grad_assemble(const GradArgs& a, int n_struct, int max_nodes, hipStream_t stream);
 hipError_t launch_potential(const PotArgs& a, long long max_elems, hipStream_t stream);
 hipError_t launch_potential_bwd(const PotBwdArgs& a, long long n_atoms_total, int n_struct,
                                 const long long* atom_struct, hipStream_t stream);
