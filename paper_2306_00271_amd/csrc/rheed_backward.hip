@@ -75,7 +75,6 @@ struct BLds {
   double2 x[NP];                 // coefficients of the physical column
   double2 red[BW][NP];           // per-wave partial sums
   double2 gj_row[2 * NP];
-  double2 gj_col[2 * NP];
   int gj_piv[NP];
   double g2s[NP];
   int bhk[NP][2];
@@ -211,7 +210,7 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
       z[m] = make_double2(gr * q.x - gi * q.y + pp.y, gr * q.y + gi * q.x - pp.x);  // Gamma Q - iP
     }
     if (tid < NP) s.x[tid] = make_double2(0.0, 0.0);
-    const int pos = gj_inverse<BW>(z, N, lane, w, s.gj_row, s.gj_col, s.gj_piv, &s.flag_singular);
+    const int pos = gj_inverse<BW>(z, N, lane, w, s.gj_row, s.gj_piv, &s.flag_singular);
     // slot sl = w + BW (m - 8) < N holds row gj_piv[sl] of B^{-1}, column pos in this lane
     if (pos == 0) {
 #pragma unroll

@@ -67,7 +67,6 @@ struct Lds {
   double2 xb[2 * NP * NP];   // [c; X]: c block and stage-input buffer; [Q; P] during eliminations
   double2 tb[5][MAXBOX + 1]; // node tables (Ur, Ui); entry `box` of every row stays 0
   double2 gj_row[2 * NP];    // elimination scratch: pivot rows (two steps in flight)
-  double2 gj_col[2 * NP];    //   pivot column, per wave
   int gj_piv[NP];            //   pivot column of every step
   double g2s[NP];            // Gamma_j^2 (real), 0 on padding
   int bhk[NP][2];
@@ -90,7 +89,7 @@ __device__ __noinline__ void invert_top(int n, double2* t) {
   double2 z[2 * NP / FW];
 #pragma unroll
   for (int m = 0; m < NP / FW; ++m) z[m] = s.xb[(w + FW * m) * NP + lane];
-  const int pos = gj_inverse<FW>(z, n, lane, w, s.gj_row, s.gj_col, s.gj_piv, &s.flag_singular);
+  const int pos = gj_inverse<FW>(z, n, lane, w, s.gj_row, s.gj_piv, &s.flag_singular);
 #pragma unroll
   for (int m = NP / FW; m < 2 * NP / FW; ++m) {
     const int sl = w + FW * (m - NP / FW);
