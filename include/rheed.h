@@ -139,7 +139,10 @@ rheed_status rheed_potential(rheed_plan_t plan, const double* atoms, void* U_tab
 
 /* Gradient of a real loss w.r.t. atom coordinates from its gradient w.r.t.
  * the tables.  dL_dU: device complex [table_elems] holding
- * dL/dRe(u) + i dL/dIm(u); dL_datoms: device [n_atoms_total][3] (overwritten). */
+ * dL/dRe(u) + i dL/dIm(u); dL_datoms: device [n_atoms_total][3] (overwritten).
+ * The sum over table entries runs in a fixed order (bitwise reproducible) and
+ * uses partial sums held by the plan, so calls on one plan must not overlap
+ * (issue them on one stream). */
 rheed_status rheed_potential_backward(rheed_plan_t plan, const double* atoms, const void* dL_dU,
                                       double* dL_datoms, void* stream);
 

@@ -50,6 +50,7 @@ struct rheed_plan_s {
   long long* d_atom_struct = nullptr;
   int* d_bin_ptr = nullptr;
   int* d_bin_jk = nullptr;
+  double* d_pbwd = nullptr;  // partial sums of the potential adjoint
   long long g_pair_stride = 0;  // adjoint stage buffer elements per pair
   int max_nodes = 0;
 };
@@ -231,7 +232,9 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (e = hipMalloc(&P->d_pair_struct, sizeof(int) * P->pair_struct.size())) != hipSuccess ||
       (e = hipMalloc(&P->d_atom_struct, sizeof(long long) * std::max<size_t>(1, P->atom_struct.size()))) != hipSuccess ||
       (e = hipMalloc(&P->d_bin_ptr, sizeof(int) * P->bin_ptr.size())) != hipSuccess ||
-      (e = hipMalloc(&P->d_bin_jk, sizeof(int) * P->bin_jk.size())) != hipSuccess) {
+      (e = hipMalloc(&P->d_bin_jk, sizeof(int) * P->bin_jk.size())) != hipSuccess ||
+      (e = hipMalloc(&P->d_pbwd, sizeof(double) * 3 * PBWD_CHUNKS * std::max<long long>(1, P->n_atoms_total))) !=
+          hipSuccess) {
     rheed_plan_destroy(P);
     return e == hipErrorOutOfMemory ? fail(RHEED_E_NOMEM, "plan_create: device allocation") : hip_fail(e, "hipMalloc");
   }
@@ -261,6 +264,7 @@ rheed_status rheed_plan_destroy(rheed_plan_t P) {
   if (P->d_atom_struct) (void)hipFree(P->d_atom_struct);
   if (P->d_bin_ptr) (void)hipFree(P->d_bin_ptr);
   if (P->d_bin_jk) (void)hipFree(P->d_bin_jk);
+  if (P->d_pbwd) (void)hipFree(P->d_pbwd);
   delete P;
   return RHEED_OK;
 }
@@ -313,6 +317,7 @@ rheed_status rheed_potential_backward(rheed_plan_t P, const double* atoms, const
   a.atoms = atoms;
   a.dU = static_cast<const double2*>(dL_dU);
   a.datoms = dL_datoms;
+  a.partial = P->d_pbwd;
   a.nodes_per_slice = P->nodes_per_slice;
   for (int c = 0; c < 4; ++c) a.cset[c] = P->cset[c];
   hipError_t e = launch_potential_bwd(a, P->n_atoms_total, P->n_struct, P->d_atom_struct,

@@ -92,13 +92,26 @@ __device__ __forceinline__ double2 caxpy(double s, double2 x, double2 y) {  // y
   return make_double2(y.x + s * x.x, y.y + s * x.y);
 }
 
-// Sum over the eight threads of a row (lanes differing in their low 3 bits).
+// v from another lane of the same row of 8, by DPP (CTRL: a quad_perm or
+// row_half_mirror pattern).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the eight threads of a row (lanes 8r .. 8r+7): pairs, then quads
+// (quad_perm), then the two quads (row_half_mirror); every lane of the eight
+// ends with the same sum.
 __device__ __forceinline__ double2 row_sum(double2 v) {
-#pragma unroll
-  for (int off = 1; off < 8; off <<= 1) {
-    v.x += __shfl_xor(v.x, off, 64);
-    v.y += __shfl_xor(v.y, off, 64);
-  }
+  v.x += dpp_f64<0xB1>(v.x);
+  v.y += dpp_f64<0xB1>(v.y);
+  v.x += dpp_f64<0x4E>(v.x);
+  v.y += dpp_f64<0x4E>(v.y);
+  v.x += dpp_f64<0x141>(v.x);
+  v.y += dpp_f64<0x141>(v.y);
   return v;
 }
 
@@ -108,31 +121,24 @@ __device__ __forceinline__ double2 row_sum(double2 v) {
 template <bool HERM>
 __device__ __forceinline__ double2 matvec_row(const double2* __restrict__ tslot, const double2* __restrict__ v,
                                               const int (&ix)[8], int part, int j, double g2j) {
-  double2 acc = make_double2(0.0, 0.0);
+  double2 a0 = make_double2(0.0, 0.0), a1 = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const double2 u = tslot[ix[q]];
-    const double2 vk = v[8 * part + q];
-    acc = cadd(acc, HERM ? cmulc(u, vk) : cmul(u, vk));
+  for (int h = 0; h < 8; h += 4) {  // four products' operands in flight at a time
+    double2 u[4], vk[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      u[q] = tslot[ix[h + q]];
+      vk[q] = v[8 * part + h + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q += 2) {
+      a0 = cadd(a0, HERM ? cmulc(u[q], vk[q]) : cmul(u[q], vk[q]));
+      a1 = cadd(a1, HERM ? cmulc(u[q + 1], vk[q + 1]) : cmul(u[q + 1], vk[q + 1]));
+    }
   }
-  acc = row_sum(acc);
   const double2 vj = v[j];
+  const double2 acc = row_sum(cadd(a0, a1));
   return make_double2(acc.x + g2j * vj.x, acc.y + g2j * vj.y);
-}
-
-// sum_q Mg[j][8 part + q] v[8 part + q] for a dense [NP][NP] matrix in global memory
-__device__ __forceinline__ double2 dense_row(const double2* __restrict__ Mg, const double2* v, int j, int part) {
-  double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) acc = cadd(acc, cmul(Mg[j * NP + 8 * part + q], v[8 * part + q]));
-  return row_sum(acc);
-}
-// sum_q conj(Mg[8 part + q][k]) v[8 part + q]  (row k of Mg^H v)
-__device__ __forceinline__ double2 dense_row_h(const double2* __restrict__ Mg, const double2* v, int k, int part) {
-  double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-  for (int q = 0; q < 8; ++q) acc = cadd(acc, cmulc(Mg[(8 * part + q) * NP + k], v[8 * part + q]));
-  return row_sum(acc);
 }
 
 template <int STEPPER>
@@ -291,18 +297,45 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
   // Crossing from the start of slice i back into slice i - 1: the
   // transformation after slice i - 1 (if any), then psi_{i-1} = Z_{i-1} x.
   double2 psic, psid;
-  auto cross = [&](int i, const double2 (&zc)[8], const double2 (&zd)[8]) {
-    if (flags[i - 1]) {
-      // y_c = -R^H y_d with [I; R] the stored state i
+  // Loads for crossing into slice i - 1, issued a slice ahead: the flag of
+  // the transformation after slice i - 1 and Z_{i-1}.
+  struct CrossLoads {
+    double2 zc[8], zd[8];
+    int flag;
+  };
+  auto load_cross = [&](int i, CrossLoads& c) {
+    c.flag = flags[i - 1];
+    const double2* zi = reinterpret_cast<const double2*>(pws + (long long)(i - 1) * a.ck.state_bytes);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      c.zc[q] = zi[j * NP + 8 * part + q];
+      c.zd[q] = zi[NP * NP + j * NP + 8 * part + q];
+    }
+  };
+  auto cross = [&](int i, const CrossLoads& c) {
+    if (c.flag) {
+      // y_c = -R^H y_d with [I; R] the stored state i, and x = T_{i-1} x
       const double2* R =
           (i == L ? zL : reinterpret_cast<const double2*>(pws + (long long)i * a.ck.state_bytes)) + NP * NP;
+      const double2* Tm =
+          reinterpret_cast<const double2*>(pws + a.ck.q_off + (long long)(i - 1) * NP * NP * sizeof(double2));
+      double2 rh[8], tm[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        rh[q] = R[(8 * part + q) * NP + j];
+        tm[q] = Tm[j * NP + 8 * part + q];
+      }
       if (part == 0) s.vin[0][j] = yd;
       __syncthreads();
-      const double2 t = dense_row_h(R, s.vin[0], j, part);
+      double2 t = make_double2(0.0, 0.0), xn = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        t = cadd(t, cmulc(rh[q], s.vin[0][8 * part + q]));
+        xn = cadd(xn, cmul(tm[q], s.x[8 * part + q]));
+      }
+      t = row_sum(t);
+      xn = row_sum(xn);
       yc = make_double2(-t.x, -t.y);
-      // x = T_{i-1} x
-      const double2* Tm = reinterpret_cast<const double2*>(pws + a.ck.q_off + (long long)(i - 1) * NP * NP * sizeof(double2));
-      const double2 xn = dense_row(Tm, s.x, j, part);
       __syncthreads();
       if (part == 0) s.x[j] = xn;
       __syncthreads();
@@ -311,40 +344,30 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const double2 xk = s.x[8 * part + q];
-      ac = cadd(ac, cmul(zc[q], xk));
-      ad = cadd(ad, cmul(zd[q], xk));
+      ac = cadd(ac, cmul(c.zc[q], xk));
+      ad = cadd(ad, cmul(c.zd[q], xk));
     }
     psic = row_sum(ac);
     psid = row_sum(ad);
   };
   {
-    double2 zc[8], zd[8];
-    const double2* zi = reinterpret_cast<const double2*>(pws + (long long)(L - 1) * a.ck.state_bytes);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      zc[q] = zi[j * NP + 8 * part + q];
-      zd[q] = zi[NP * NP + j * NP + 8 * part + q];
-    }
-    cross(L, zc, zd);
+    CrossLoads c0;
+    load_cross(L, c0);
+    cross(L, c0);
   }
 
   for (int i = L - 1; i >= 0; --i) {
     const int nb = i * NPS;
-    // loads for slice i - 1: its new node tables and its start state
+    // loads for slice i - 1: its new node tables and what crossing into it needs
     double2 pf[3];
-    double2 zc[8], zd[8];
+    CrossLoads cl;
     if (i > 0) {
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         const int e = tid + BT * t;
         if (e < NPS * box) pf[t] = Us[(long long)(nb - NPS) * box + e];
       }
-      const double2* zi = reinterpret_cast<const double2*>(pws + (long long)(i - 1) * a.ck.state_bytes);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        zc[q] = zi[j * NP + 8 * part + q];
-        zd[q] = zi[NP * NP + j * NP + 8 * part + q];
-      }
+      load_cross(i, cl);
     }
     // RK stages on psi: Y_r = psi + h sum_{m<r} a_rm K_m, K_r = (Y_r^(c'), -M_r Y_r^(c))
     double2* gs = gb + (long long)i * NS * 2 * NP;
@@ -405,7 +428,7 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
           s.tb[(nb - NPS + q) % RING][e - q * box] = pf[t];
         }
       }
-      cross(i, zc, zd);
+      cross(i, cl);
     }
     __syncthreads();
   }

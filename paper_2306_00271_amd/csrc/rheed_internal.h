@@ -62,11 +62,14 @@ struct PotArgs {
   double cset[4];        // distinct RK node fractions in [0, 1)
 };
 
+constexpr int PBWD_CHUNKS = 64;  // partial sums per atom in the potential adjoint
+
 struct PotBwdArgs {
   const StructDev* structs;
   const double* atoms;
   const double2* dU;     // dL/dRe(u) + i dL/dIm(u)
   double* datoms;        // [n_atoms_total][3]
+  double* partial;       // [n_atoms_total][PBWD_CHUNKS][3] (plan-owned)
   int nodes_per_slice;
   double cset[4];
 };

@@ -52,18 +52,23 @@ __global__ __launch_bounds__(256) void potential_kernel(PotArgs a) {
   a.U[S.table_off + e] = make_double2(S.pref_re * re - S.pref_im * im, S.pref_re * im + S.pref_im * re);
 }
 
-// One workgroup per atom: dL/dr_a = sum_{n,g} Re(conj(dU) du/dr_a), with
+// dL/dr_a = sum_{n,g} Re(conj(dU) du/dr_a), with
 // du/dx_a = -i g_x t, du/dy_a = -i g_y t, du/dz_a = pref e^{-i g.rho} sum_m 2 b_m (z - z_a) w_m e^{-b_m dz^2}
-// where t is the atom's term of u.  Reduction in a fixed order (deterministic).
+// where t is the atom's term of u.  Workgroup (atom, chunk) sums a contiguous
+// chunk of the (node, g) entries and writes one partial per chunk;
+// potential_bwd_sum_kernel adds the chunks in order (deterministic).
 __global__ __launch_bounds__(256) void potential_bwd_kernel(PotBwdArgs a, int n_struct, const long long* atom_struct) {
   const long long ga = blockIdx.x;              // global atom index
+  const int chunk = blockIdx.y;
   const int sidx = (int)atom_struct[ga];
   const StructDev S = a.structs[sidx];
   const double x = a.atoms[3 * ga], y = a.atoms[3 * ga + 1], za = a.atoms[3 * ga + 2];
   const long long total = (long long)S.n_nodes * S.box;
+  const long long per = (total + PBWD_CHUNKS - 1) / PBWD_CHUNKS;
+  const long long e0 = chunk * per, e1 = min(total, e0 + per);
   const int W = 2 * S.kd + 1;
   double sx = 0.0, sy = 0.0, sz = 0.0;
-  for (long long e = threadIdx.x; e < total; e += blockDim.x) {
+  for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
     const int n = (int)(e / S.box);
     const int b = (int)(e - (long long)n * S.box);
     const int dh = b / W - S.hd, dk = b % W - S.kd;
@@ -105,11 +110,16 @@ __global__ __launch_bounds__(256) void potential_bwd_kernel(PotBwdArgs a, int n_
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    a.datoms[3 * ga] = red[0][0];
-    a.datoms[3 * ga + 1] = red[1][0];
-    a.datoms[3 * ga + 2] = red[2][0];
-  }
+  if (threadIdx.x < 3) a.partial[(ga * PBWD_CHUNKS + chunk) * 3 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(256) void potential_bwd_sum_kernel(const double* partial, double* datoms, long long n) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // atom * 3 + component
+  if (c >= n) return;
+  const long long ga = c / 3, comp = c - 3 * ga;
+  double acc = 0.0;
+  for (int k = 0; k < PBWD_CHUNKS; ++k) acc += partial[(ga * PBWD_CHUNKS + k) * 3 + comp];
+  datoms[c] = acc;
 }
 
 // R-factor of the specular beam: loss = sum_p (I[p][0] - t[p])^2 and
@@ -144,7 +154,13 @@ hipError_t launch_potential(const PotArgs& a, long long max_elems, hipStream_t s
 
 hipError_t launch_potential_bwd(const PotBwdArgs& a, long long n_atoms_total, int n_struct, const long long* atom_struct,
                                 hipStream_t stream) {
-  hipLaunchKernelGGL(potential_bwd_kernel, dim3((unsigned)n_atoms_total), dim3(256), 0, stream, a, n_struct, atom_struct);
+  hipLaunchKernelGGL(potential_bwd_kernel, dim3((unsigned)n_atoms_total, PBWD_CHUNKS), dim3(256), 0, stream, a, n_struct,
+                     atom_struct);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long n = 3 * n_atoms_total;
+  hipLaunchKernelGGL(potential_bwd_sum_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, a.partial,
+                     a.datoms, n);
   return hipGetLastError();
 }
 
