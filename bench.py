@@ -9,12 +9,14 @@ respect to atom coordinates.  Inputs are seeded synthetic slabs, resident in
 HBM before the timed region.  Prints one JSON line.
 
 ``--mode fwd`` times the forward pass alone (potential + propagation).
+``--traffic-probe`` runs one forward launch and a 1 GiB device copy for the
+HBM counter runs whose summary is kept under profiles/.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -24,6 +26,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MFMA_FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 matrix, published
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "forward_kernel_rk6_n61_traffic.md")
 
 
 def _flops_forward(N, L, stages, n_rhst_total, n_pairs):
@@ -35,40 +38,98 @@ def _flops_forward(N, L, stages, n_rhst_total, n_pairs):
     return n_pairs * (L * stages * 8.0 * n3 + (8.0 / 3.0) * n3) + n_rhst_total * (8.0 / 3.0 + 8.0) * n3
 
 
+# ---------------------------------------------------------------- CPU baseline
 def _cpu_worker(args):
     os.environ["OMP_NUM_THREADS"] = "1"
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
     os.environ["MKL_NUM_THREADS"] = "1"
-    wl_name, idx, stepper = args
-    from synth import WORKLOADS
+    kind, idx, stepper = args
+    import numpy as np
+    from synth import config4
     from oracle import driver
-    wl = WORKLOADS[wl_name]()
+    wl = config4(1)
     t0 = time.perf_counter()
-    driver.rocking_curve(wl, angle_idx=idx, stepper=stepper)
-    return time.perf_counter() - t0, len(idx)
+    if kind == "fwd":
+        driver.rocking_curve(wl, angle_idx=[idx], stepper=stepper)
+    else:
+        # one tangent-linear pass: forward plus the derivative along one atom coordinate
+        direction = np.zeros((wl.structures[0].atoms.shape[0], 3))
+        direction[idx % len(wl.structures[0].grad_atoms), idx % 3] = 1.0
+        driver.rfactor_directional(wl, 0, direction, np.zeros(1), angle_idx=[idx], stepper=stepper)
+    return time.perf_counter() - t0
 
 
-def cpu_baseline(wl_name, stepper, n_angles_total, cores, budget_s=20.0):
-    """The oracle (NumPy FP64, one BLAS thread per process) over a sample of
-    pairs on `cores` host processes; returns forward pairs/s."""
+def cpu_baseline(stepper, n_angles, n_coords, cores, mode):
+    """The oracle (NumPy FP64, one BLAS thread per process) on `cores` host
+    processes, each timing one (structure, angle) pair of the workload at a
+    different angle.  fwd+adj: the oracle's gradient of a point is one
+    tangent-linear pass (forward + directional derivative) per atom
+    coordinate, so a point costs n_coords passes and the rate is
+    cores / (n_coords * mean pass time).  fwd: cores / mean forward time."""
     import multiprocessing as mp
-    # probe one pair to size the sample
-    t1, _ = _cpu_worker((wl_name, [n_angles_total // 2], stepper))
-    per_core = max(1, int(budget_s / max(t1, 1e-3) / 2))
-    per_core = min(per_core, max(1, n_angles_total // cores))
-    jobs = []
-    for c in range(cores):
-        idx = [(c * per_core + k) % n_angles_total for k in range(per_core)]
-        jobs.append((wl_name, idx, stepper))
+    kind = "fwd" if mode == "fwd" else "tl"
+    jobs = [(kind, (c * n_angles) // cores, stepper) for c in range(cores)]
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
-        res = pool.map(_cpu_worker, jobs)
+        times = pool.map(_cpu_worker, jobs)
     wall = time.perf_counter() - t0
-    pairs = sum(r[1] for r in res)
-    return pairs / wall, pairs, wall, t1
+    per_pass = float(sum(times) / len(times))
+    per_point = per_pass if kind == "fwd" else n_coords * per_pass
+    return cores / per_point, per_pass, wall
 
 
+# ------------------------------------------------------------- HBM traffic
+def kernel_source_hash():
+    """sha256 of the sources the forward kernel is built from."""
+    h = hashlib.sha256()
+    for f in ("rheed_forward.hip", "rheed_gj.h", "rheed_internal.h"):
+        with open(os.path.join(ROOT, "paper_2306_00271_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_from_profile():
+    """HBM bytes per forward launch from the committed counter summary, or
+    None if the summary is missing or was taken on other kernel sources."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    fields = {}
+    with open(TRAFFIC_SUMMARY) as fh:
+        for line in fh:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("source sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def traffic_probe():
+    """One forward launch of the timed workload (with the adjoint's state
+    saving) and one device copy of 1 GiB, for FETCH_SIZE / WRITE_SIZE counter
+    runs; prints the copy size so the counters can be calibrated."""
+    import torch
+    from paper_2306_00271_amd import api
+    from synth import config4
+    dev = torch.device("cuda:0")
+    wl = config4(1)
+    plan = api.plan_for(wl, stepper="rk6")
+    angles = api.angles_for(wl, dev)
+    U = plan.potential(api.atoms_for(wl, dev))
+    ws = plan.workspace(dev)
+    plan.forward(U, angles, workspace=ws)
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": src.numel() * 8, "source_sha256": kernel_source_hash()}))
+
+
+# -------------------------------------------------------------------- bench
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,11 +138,16 @@ def main():
     ap.add_argument("--mode", choices=["fwd", "fwd+adj"], default="fwd+adj")
     ap.add_argument("--structures", type=int, default=1, help="structures in the batch (128 angles each)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run one forward launch and a 1 GiB copy for HBM counter runs, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every box in this setup has a single MI355X; "
               "pairs are independent and would shard across GPUs (see DESIGN.md).", file=sys.stderr)
         sys.exit(2)
+    if args.traffic_probe:
+        traffic_probe()
+        return
 
     import numpy as np
     import torch
@@ -145,18 +211,28 @@ def main():
     fwd_ms = float(np.mean([a.elapsed_time(b) for a, b in fwd_events]))
     fl = _flops_forward(N, L, stages, nrhst, n_pairs)
     achieved = fl / (fwd_ms / 1e3) / 1e12
+    # counters were taken on the single-structure launch with state saving
+    traffic = traffic_from_profile() if (do_adj and args.structures == 1) else None
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": MFMA_FP64_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / MFMA_FP64_PEAK_TFLOPS, 4), "traffic": None,
-                "kernel": "forward_kernel<1>", "kernel_ms": round(fwd_ms, 4),
-                "flops_per_launch": fl}
+                "unit": "TFLOP/s", "frac": round(achieved / MFMA_FP64_PEAK_TFLOPS, 4), "traffic": traffic,
+                "kernel": "forward_kernel<1>", "kernel_ms": round(fwd_ms, 4), "flops_per_launch": fl}
 
     cpu = None
     if not args.no_cpu:
         cores = min(16, os.cpu_count() or 1)
-        rate, pairs, cwall, t1p = cpu_baseline("c4", stepper, len(wl.theta0), cores)
-        cpu = {"value": round(rate, 4), "unit": "points/s (forward only)", "cores": cores, "kind": "oracle",
-               "sample": f"{pairs} (structure, angle) pairs of the N=61 workload, RK6, 400 slices, forward only, "
-                         f"{cores} processes x 1 BLAS thread, {cwall:.1f} s wall; one pair alone {t1p:.2f} s"}
+        n_coords = 3 * len(wl.structures[0].grad_atoms)
+        rate, per_pass, cwall = cpu_baseline(stepper, len(wl.theta0), n_coords, cores, args.mode)
+        if do_adj:
+            sample = (f"{cores} (structure, angle) pairs of this workload, one per process at different angles, "
+                      f"each one tangent-linear pass of the oracle (forward plus the derivative along one atom "
+                      f"coordinate), mean {per_pass:.2f} s per pass; a point's gradient takes {n_coords} passes "
+                      f"({n_coords // 3} atoms x 3 coordinates), so value = {cores} / ({n_coords} x "
+                      f"{per_pass:.2f} s); {cores} processes x 1 BLAS thread, {cwall:.1f} s wall")
+        else:
+            sample = (f"{cores} (structure, angle) pairs of this workload, one per process at different angles, "
+                      f"oracle forward, mean {per_pass:.2f} s per pair; {cores} processes x 1 BLAS thread, "
+                      f"{cwall:.1f} s wall")
+        cpu = {"value": round(rate, 5), "unit": "points/s", "cores": cores, "kind": "oracle", "sample": sample}
 
     rec = {
         "metric": "rocking-curve points (structure x angle)/s at N=61 FP64; " +
