@@ -50,7 +50,8 @@ typedef enum {
 enum {
   RHEED_PAIR_OK = 0,
   RHEED_PAIR_SINGULAR = 1,  /* an exactly zero pivot in a right division */
-  RHEED_PAIR_NONFINITE = 2  /* Inf/NaN reached the reflected amplitudes */
+  RHEED_PAIR_NONFINITE = 2, /* Inf/NaN reached the reflected amplitudes */
+  RHEED_PAIR_SYNC = 3       /* split launch: the two workgroups of the pair lost contact */
 };
 
 /* Explicit RK tableaux (Sec. 3.4): classical 4th order, 4 stages, and
@@ -88,11 +89,21 @@ typedef struct {
   double mean_inner_potential; /* V */
 } rheed_structure;
 
+/* How rheed_forward lays pairs out on the GPU.  SPLIT runs each pair on two
+ * workgroups (two CUs) that own 32 columns of the state each and exchange
+ * through memory the data that couples the columns; it needs both workgroups
+ * of every pair resident at once, so it holds at most one pair per two CUs
+ * (rheed_plan_info.split_max_pairs).  WHOLE runs a pair on one workgroup.
+ * AUTO picks SPLIT when the batch fits, WHOLE otherwise.  The results of the
+ * two layouts agree to rounding. */
+typedef enum { RHEED_LAYOUT_AUTO = 0, RHEED_LAYOUT_WHOLE = 1, RHEED_LAYOUT_SPLIT = 2 } rheed_layout;
+
 typedef struct {
   rheed_stepper stepper;
   double rhst_threshold;     /* RHST when the condition estimate exceeds it; the paper uses 1000 */
   int32_t checkpoint_every;  /* slices between states saved for rheed_backward (>= 1) */
   rheed_convention convention;
+  rheed_layout layout;       /* SPLIT when the batch does not fit -> RHEED_E_UNSUPPORTED at plan creation */
 } rheed_opts;
 
 typedef struct rheed_plan_s* rheed_plan_t;
@@ -107,6 +118,8 @@ typedef struct {
   int64_t n_atoms_total;
   size_t fwd_workspace;      /* bytes rheed_forward needs to keep states for rheed_backward */
   size_t bwd_workspace;      /* extra bytes rheed_backward needs beyond fwd_workspace */
+  int32_t split;             /* 1 if rheed_forward runs the split layout */
+  int32_t split_max_pairs;   /* pairs a split launch can hold on the current device */
 } rheed_plan_info;
 
 /* Vacuum wavenumber gamma (1/A) and the coefficient kappa (1/(A^2 V)) of the

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "librheed.so")
 RHEED_OK, RHEED_E_INVALID, RHEED_E_HIP, RHEED_E_NOMEM, RHEED_E_UNSUPPORTED = 0, -1, -2, -3, -4
 RHEED_RK4, RHEED_RK6 = 0, 1
 RHEED_INTENSITY_FLUX, RHEED_INTENSITY_PAPER = 0, 1
+RHEED_LAYOUT_AUTO, RHEED_LAYOUT_WHOLE, RHEED_LAYOUT_SPLIT = 0, 1, 2
 RHEED_MAX_BEAMS = 64
 RHEED_MAX_BOX = 300
 
@@ -44,6 +45,7 @@ class Opts(C.Structure):
         ("rhst_threshold", C.c_double),
         ("checkpoint_every", C.c_int32),
         ("convention", C.c_int),
+        ("layout", C.c_int),
     ]
 
 
@@ -57,6 +59,8 @@ class PlanInfo(C.Structure):
         ("n_atoms_total", C.c_int64),
         ("fwd_workspace", C.c_size_t),
         ("bwd_workspace", C.c_size_t),
+        ("split", C.c_int32),
+        ("split_max_pairs", C.c_int32),
     ]
 
 

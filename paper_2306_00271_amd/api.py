@@ -16,6 +16,7 @@ from . import _lib
 
 STEPPERS = {"rk4": _lib.RHEED_RK4, "rk6": _lib.RHEED_RK6}
 CONVENTIONS = {"flux": _lib.RHEED_INTENSITY_FLUX, "paper": _lib.RHEED_INTENSITY_PAPER}
+LAYOUTS = {"auto": _lib.RHEED_LAYOUT_AUTO, "whole": _lib.RHEED_LAYOUT_WHOLE, "split": _lib.RHEED_LAYOUT_SPLIT}
 
 
 def _stream():
@@ -51,7 +52,8 @@ class Plan:
 
     def __init__(self, structures: Sequence, angles_per_struct: Sequence[int], *, energy_eV: float,
                  charge: float, absorption: float, mean_inner_potential: float = 15.0, stepper: str = "rk6",
-                 threshold: float = 1000.0, checkpoint_every: int = 1, convention: str = "flux"):
+                 threshold: float = 1000.0, checkpoint_every: int = 1, convention: str = "flux",
+                 layout: str = "auto"):
         L = _lib.lib()
         self.gamma, self.kappa = beam_constants(energy_eV)
         self.stepper = stepper
@@ -78,7 +80,8 @@ class Plan:
             st.absorption = float(absorption)
             st.mean_inner_potential = float(mean_inner_potential)
         aps = (C.c_int32 * n)(*[int(a) for a in angles_per_struct])
-        opts = _lib.Opts(STEPPERS[stepper], float(threshold), int(checkpoint_every), CONVENTIONS[convention])
+        opts = _lib.Opts(STEPPERS[stepper], float(threshold), int(checkpoint_every), CONVENTIONS[convention],
+                         LAYOUTS[layout])
         h = C.c_void_p()
         _lib.check(L.rheed_plan_create(C.byref(h), C.byref(opts), n, arr, aps), "plan_create")
         self._h = h
@@ -87,6 +90,7 @@ class Plan:
         self.info = info
         self.n_pairs = info.n_pairs
         self.max_beams = info.max_beams
+        self.split = bool(info.split)
         offs = (C.c_int64 * (n + 1))()
         _lib.check(L.rheed_plan_table_offsets(h, offs), "plan_table_offsets")
         self.table_offsets = np.array(offs[:], dtype=np.int64)

@@ -51,6 +51,10 @@ struct rheed_plan_s {
   int* d_bin_ptr = nullptr;
   int* d_bin_jk = nullptr;
   double* d_pbwd = nullptr;  // partial sums of the potential adjoint
+  char* d_xch = nullptr;     // exchange blocks of the split layout
+  bool split = false;
+  int split_max = 0;
+  unsigned long long epoch = 0;  // split launches so far (tags the exchange counters)
   long long g_pair_stride = 0;  // adjoint stage buffer elements per pair
   int max_nodes = 0;
 };
@@ -89,6 +93,8 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
   if (opts->checkpoint_every < 1) return fail(RHEED_E_INVALID, "checkpoint_every must be >= 1");
   if (opts->convention != RHEED_INTENSITY_FLUX && opts->convention != RHEED_INTENSITY_PAPER)
     return fail(RHEED_E_INVALID, "unknown intensity convention");
+  if (opts->layout != RHEED_LAYOUT_AUTO && opts->layout != RHEED_LAYOUT_WHOLE && opts->layout != RHEED_LAYOUT_SPLIT)
+    return fail(RHEED_E_INVALID, "unknown layout");
   auto* P = new rheed_plan_s();
   P->opts = *opts;
   P->n_struct = n_struct;
@@ -226,6 +232,18 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
   P->g_pair_stride = (long long)max_l * (P->opts.stepper == RHEED_RK4 ? 4 : 7) * 2 * NP;
   P->bwd_ws = (size_t)P->g_pair_stride * sizeof(double2) * P->n_pairs;
 
+  // split layout: two workgroups per pair, both resident (cooperative launch)
+  {
+    int dev = 0;
+    P->split_max = hipGetDevice(&dev) == hipSuccess ? forward_split_max_pairs(dev) : 0;
+    P->split = opts->layout != RHEED_LAYOUT_WHOLE && P->n_pairs <= P->split_max;
+    if (opts->layout == RHEED_LAYOUT_SPLIT && !P->split) {
+      const int mx = P->split_max;
+      delete P;
+      return fail(RHEED_E_UNSUPPORTED, "layout SPLIT holds at most " + std::to_string(mx) + " pairs on this device");
+    }
+  }
+
   hipError_t e;
   if ((e = hipMalloc(&P->d_structs, sizeof(StructDev) * P->hs.size())) != hipSuccess ||
       (e = hipMalloc(&P->d_beams, sizeof(int) * P->beams.size())) != hipSuccess ||
@@ -234,7 +252,8 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (e = hipMalloc(&P->d_bin_ptr, sizeof(int) * P->bin_ptr.size())) != hipSuccess ||
       (e = hipMalloc(&P->d_bin_jk, sizeof(int) * P->bin_jk.size())) != hipSuccess ||
       (e = hipMalloc(&P->d_pbwd, sizeof(double) * 3 * PBWD_CHUNKS * std::max<long long>(1, P->n_atoms_total))) !=
-          hipSuccess) {
+          hipSuccess ||
+      (P->split && (e = hipMalloc(&P->d_xch, (size_t)XCH_STRIDE * P->n_pairs)) != hipSuccess)) {
     rheed_plan_destroy(P);
     return e == hipErrorOutOfMemory ? fail(RHEED_E_NOMEM, "plan_create: device allocation") : hip_fail(e, "hipMalloc");
   }
@@ -248,7 +267,9 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
           hipSuccess ||
       (!P->atom_struct.empty() &&
        (e = hipMemcpy(P->d_atom_struct, P->atom_struct.data(), sizeof(long long) * P->atom_struct.size(),
-                      hipMemcpyHostToDevice)) != hipSuccess)) {
+                      hipMemcpyHostToDevice)) != hipSuccess) ||
+      (P->split && (e = hipMemset(P->d_xch, 0, (size_t)XCH_STRIDE * P->n_pairs)) != hipSuccess) ||
+      (e = hipDeviceSynchronize()) != hipSuccess) {
     rheed_plan_destroy(P);
     return hip_fail(e, "hipMemcpy");
   }
@@ -265,6 +286,7 @@ rheed_status rheed_plan_destroy(rheed_plan_t P) {
   if (P->d_bin_ptr) (void)hipFree(P->d_bin_ptr);
   if (P->d_bin_jk) (void)hipFree(P->d_bin_jk);
   if (P->d_pbwd) (void)hipFree(P->d_pbwd);
+  if (P->d_xch) (void)hipFree(P->d_xch);
   delete P;
   return RHEED_OK;
 }
@@ -279,6 +301,8 @@ rheed_status rheed_plan_get_info(rheed_plan_t P, rheed_plan_info* info) {
   info->n_atoms_total = P->n_atoms_total;
   info->fwd_workspace = P->fwd_ws;
   info->bwd_workspace = P->bwd_ws;
+  info->split = P->split ? 1 : 0;
+  info->split_max_pairs = P->split_max;
   return RHEED_OK;
 }
 
@@ -347,7 +371,14 @@ rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* a
   a.convention = (int)P->opts.convention;
   a.n_pairs = P->n_pairs;
   a.threshold = P->opts.rhst_threshold;
-  hipError_t e = launch_forward((int)P->opts.stepper, a, static_cast<hipStream_t>(stream));
+  hipError_t e;
+  if (P->split) {
+    a.xch = P->d_xch;
+    a.epoch = ++P->epoch;
+    e = launch_forward_split((int)P->opts.stepper, a, static_cast<hipStream_t>(stream));
+  } else {
+    e = launch_forward((int)P->opts.stepper, a, static_cast<hipStream_t>(stream));
+  }
   return e == hipSuccess ? RHEED_OK : hip_fail(e, "forward launch");
 }
 

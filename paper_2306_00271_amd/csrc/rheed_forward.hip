@@ -49,6 +49,12 @@ struct Mat {
   double r[NE];
   double i[NE];
 };
+struct Gidx {  // packed 16-bit table entries of the A operand, two per word
+  unsigned v[8];
+};
+struct G2 {    // Gamma^2 of the lane's four rows
+  double v[4];
+};
 
 template <int S>
 struct Tab;
@@ -105,17 +111,25 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// G = (U(node) + Gamma^2) X for the wave's 16 x 64 row block, X read from LDS;
-// every element of G is handed to epi(e, Re G, Im G).
-template <class Epi>
+// Element e = 4 jt + v of a wave's register matrix sits at LDS index
+// own<LD>(ob, e) of a matrix with row stride LD.
+template <int LD>
+__device__ __forceinline__ int own(int ob, int e) {
+  return ob + 4 * LD * (e & 3) + 16 * (e >> 2);
+}
+
+// G = (U(node) + Gamma^2) X for the wave's 16 x 32 block, X read from LDS
+// (row stride LD, the block's columns from cofs); every element of G is
+// handed to epi(e, Re G, Im G).
+template <int LD, class Epi>
 __device__ __forceinline__ void stage_gemm(const double2* __restrict__ xbuf, const double2* __restrict__ tslot,
                                            const unsigned (&gidx)[8], const double (&g2)[4], int ob, int lane,
-                                           int CH, Epi&& epi) {
+                                           int cofs, Epi&& epi) {
   __builtin_amdgcn_sched_barrier(0);
   d4 t1[NJT], t2[NJT], t3[NJT];
 #pragma unroll
   for (int jt = 0; jt < NJT; ++jt) t1[jt] = t2[jt] = t3[jt] = d4{0, 0, 0, 0};
-  const int bb = (lane >> 4) * NP + 16 * NJT * CH + (lane & 15);
+  const int bb = (lane >> 4) * LD + cofs + (lane & 15);
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const unsigned gi = (q & 1) ? (gidx[q >> 1] >> 16) : (gidx[q >> 1] & 0xffffu);
@@ -123,7 +137,7 @@ __device__ __forceinline__ void stage_gemm(const double2* __restrict__ xbuf, con
     const double us = u.x + u.y;
 #pragma unroll
     for (int jt = 0; jt < NJT; ++jt) {
-      const double2 x = xbuf[bb + 256 * q + 16 * jt];
+      const double2 x = xbuf[bb + 4 * LD * q + 16 * jt];
       t1[jt] = mfma(u.x, x.x, t1[jt]);
       t2[jt] = mfma(u.y, x.y, t2[jt]);
       t3[jt] = mfma(us, x.x + x.y, t3[jt]);
@@ -134,9 +148,8 @@ __device__ __forceinline__ void stage_gemm(const double2* __restrict__ xbuf, con
   for (int jt = 0; jt < NJT; ++jt) {
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const double2 own = xbuf[ob + 256 * v + 16 * jt];
-      epi(jt * 4 + v, (t1[jt][v] - t2[jt][v]) + g2[v] * own.x,
-          (t3[jt][v] - t1[jt][v] - t2[jt][v]) + g2[v] * own.y);
+      const double2 ov = xbuf[ob + 4 * LD * v + 16 * jt];
+      epi(jt * 4 + v, (t1[jt][v] - t2[jt][v]) + g2[v] * ov.x, (t3[jt][v] - t1[jt][v] - t2[jt][v]) + g2[v] * ov.y);
     }
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -173,7 +186,7 @@ __device__ __forceinline__ void dense_gemm(const double2* __restrict__ abuf, con
   __builtin_amdgcn_sched_barrier(0);
 }
 
-#define OWN(e) (ob + 256 * ((e) & 3) + 16 * ((e) >> 2))
+#define OWN(e) own<NP>(ob, e)
 
 __device__ __forceinline__ void store_mat(double2* buf, const Mat& m, int ob) {
 #pragma unroll
@@ -292,8 +305,8 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       }
       __syncthreads();
       Mat G1, G2;
-      stage_gemm(cb, t0, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
-      stage_gemm(xb, th, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
+      stage_gemm<NP>(cb, t0, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
+      stage_gemm<NP>(xb, th, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
       __syncthreads();
       // X3 = c + h/2 c' - h^2/4 G1 -> LDS;  X4 = c + h c' - h^2/2 G2 (kept in G1);
       // c <- c + h c' - h^2/6 (G1 + G2);  c' <- c' - h/6 (G1 + 2 G2)
@@ -310,7 +323,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
         d.i[e] = di - (h / 6.0) * (g1i + 2.0 * g2i);
       }
       __syncthreads();
-      stage_gemm(xb, th, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) {  // G3
+      stage_gemm<NP>(xb, th, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G3
         double2 cv = cb[OWN(e)];
         cv.x -= (hh / 6.0) * gr;
         cv.y -= (hh / 6.0) * gi;
@@ -321,7 +334,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       __syncthreads();
       store_mat(xb, G1, ob);  // X4
       __syncthreads();
-      stage_gemm(xb, t1, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) {  // G4
+      stage_gemm<NP>(xb, t1, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G4
         d.r[e] -= (h / 6.0) * gr;
         d.i[e] -= (h / 6.0) * gi;
       });
@@ -339,8 +352,8 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       }
       __syncthreads();
       Mat G1, G2, G3;
-      stage_gemm(cb, tA, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
-      stage_gemm(xb, tB, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
+      stage_gemm<NP>(cb, tA, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
+      stage_gemm<NP>(xb, tB, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
       __syncthreads();
       // X3 = c + 2h/3 c' - h^2 (2/9) G1
 #pragma unroll
@@ -350,7 +363,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
                                   cv.y + (2.0 * h / 3.0) * d.i[e] - hh * (2.0 / 9.0) * G1.i[e]);
       }
       __syncthreads();
-      stage_gemm(xb, tD, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) { G3.r[e] = gr; G3.i[e] = gi; });
+      stage_gemm<NP>(xb, tD, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G3.r[e] = gr; G3.i[e] = gi; });
       __syncthreads();
       // X4 = c + h/3 c' - h^2 (G1/9 - G2/18)
 #pragma unroll
@@ -364,7 +377,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       Mat& X5 = G1;
       Mat& X6 = G2;
       Mat& T7 = G3;
-      stage_gemm(xb, tB, gidx, g2, ob, lane, CH, [&](int e, double a4, double b4) {
+      stage_gemm<NP>(xb, tB, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double a4, double b4) {
         const double2 cv = cb[OWN(e)];
         const double dr = d.r[e], di = d.i[e];
         const double a1 = G1.r[e], b1 = G1.i[e], a2 = G2.r[e], b2 = G2.i[e], a3 = G3.r[e], b3 = G3.i[e];
@@ -382,7 +395,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       __syncthreads();
       store_mat(xb, X5, ob);
       __syncthreads();
-      stage_gemm(xb, tC, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) {  // G5
+      stage_gemm<NP>(xb, tC, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G5
         T7.r[e] += hh * (8.0 / 11.0) * gr;
         T7.i[e] += hh * (8.0 / 11.0) * gi;
         double2 cv = cb[OWN(e)];
@@ -395,7 +408,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       __syncthreads();
       store_mat(xb, X6, ob);
       __syncthreads();
-      stage_gemm(xb, tC, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) {  // G6
+      stage_gemm<NP>(xb, tC, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G6
         double2 cv = cb[OWN(e)];
         cv.x += hh * (2.0 / 15.0) * gr;
         cv.y += hh * (2.0 / 15.0) * gi;
@@ -406,7 +419,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       __syncthreads();
       store_mat(xb, T7, ob);  // X7
       __syncthreads();
-      stage_gemm(xb, tE, gidx, g2, ob, lane, CH, [&](int e, double gr, double gi) {  // G7
+      stage_gemm<NP>(xb, tE, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G7
         d.r[e] -= h * (11.0 / 120.0) * gr;
         d.i[e] -= h * (11.0 / 120.0) * gi;
       });
@@ -544,6 +557,588 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
 }
 #undef OWN
 
+
+template <int LD>
+__device__ __forceinline__ void store_mat_ld(double2* buf, const Mat& m, int ob) {
+#pragma unroll
+  for (int e = 0; e < NE; ++e) buf[own<LD>(ob, e)] = make_double2(m.r[e], m.i[e]);
+}
+
+// One explicit RK step of the slice on (c, c'): c in LDS (cb), c' in
+// registers (d), stage inputs through xb; the slice's node tables (the c
+// values of Tab<STEPPER>, then the next slice's c = 0) are ring slots
+// (nb + q) % slots of tb0, each MAXBOX + 1 entries.  LD is the LDS
+// row stride of cb and xb, cofs the column offset of this wave's block.
+template <int STEPPER, int LD>
+__device__ __forceinline__ Mat rk_slice(double2* cb, double2* xb, const double2* tb0, int nb, const Gidx gx,
+                                        const G2 gg, int ob, int lane, int cofs, double h, Mat d) {
+  constexpr int SL = Tab<STEPPER>::slots;
+  unsigned gidx[8];
+  double g2[4];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) gidx[q] = gx.v[q];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) g2[q] = gg.v[q];
+const double hh = h * h;
+  if constexpr (STEPPER == 0) {
+    const double2* t0 = tb0 + (nb % SL) * (MAXBOX + 1);
+    const double2* th = tb0 + ((nb + 1) % SL) * (MAXBOX + 1);
+    const double2* t1 = tb0 + ((nb + 2) % SL) * (MAXBOX + 1);
+    // X1 = c (read in place), X2 = c + h/2 c'
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const double2 cv = cb[own<LD>(ob, e)];
+      xb[own<LD>(ob, e)] = make_double2(cv.x + 0.5 * h * d.r[e], cv.y + 0.5 * h * d.i[e]);
+    }
+    __syncthreads();
+    Mat G1, G2;
+    stage_gemm<LD>(cb, t0, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
+    stage_gemm<LD>(xb, th, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
+    __syncthreads();
+    // X3 = c + h/2 c' - h^2/4 G1 -> LDS;  X4 = c + h c' - h^2/2 G2 (kept in G1);
+    // c <- c + h c' - h^2/6 (G1 + G2);  c' <- c' - h/6 (G1 + 2 G2)
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const double2 cv = cb[own<LD>(ob, e)];
+      const double dr = d.r[e], di = d.i[e];
+      const double g1r = G1.r[e], g1i = G1.i[e], g2r = G2.r[e], g2i = G2.i[e];
+      xb[own<LD>(ob, e)] = make_double2(cv.x + 0.5 * h * dr - 0.25 * hh * g1r, cv.y + 0.5 * h * di - 0.25 * hh * g1i);
+      G1.r[e] = cv.x + h * dr - 0.5 * hh * g2r;
+      G1.i[e] = cv.y + h * di - 0.5 * hh * g2i;
+      cb[own<LD>(ob, e)] = make_double2(cv.x + h * dr - (hh / 6.0) * (g1r + g2r), cv.y + h * di - (hh / 6.0) * (g1i + g2i));
+      d.r[e] = dr - (h / 6.0) * (g1r + 2.0 * g2r);
+      d.i[e] = di - (h / 6.0) * (g1i + 2.0 * g2i);
+    }
+    __syncthreads();
+    stage_gemm<LD>(xb, th, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G3
+      double2 cv = cb[own<LD>(ob, e)];
+      cv.x -= (hh / 6.0) * gr;
+      cv.y -= (hh / 6.0) * gi;
+      cb[own<LD>(ob, e)] = cv;
+      d.r[e] -= (h / 3.0) * gr;
+      d.i[e] -= (h / 3.0) * gi;
+    });
+    __syncthreads();
+    store_mat_ld<LD>(xb, G1, ob);  // X4
+    __syncthreads();
+    stage_gemm<LD>(xb, t1, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G4
+      d.r[e] -= (h / 6.0) * gr;
+      d.i[e] -= (h / 6.0) * gi;
+    });
+  } else {
+    const double2* tA = tb0 + (nb % SL) * (MAXBOX + 1);        // c = 0
+    const double2* tB = tb0 + ((nb + 1) % SL) * (MAXBOX + 1);  // c = 1/3
+    const double2* tC = tb0 + ((nb + 2) % SL) * (MAXBOX + 1);  // c = 1/2
+    const double2* tD = tb0 + ((nb + 3) % SL) * (MAXBOX + 1);  // c = 2/3
+    const double2* tE = tb0 + ((nb + 4) % SL) * (MAXBOX + 1);  // c = 1
+    // X1 = c (read in place), X2 = c + h/3 c'
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const double2 cv = cb[own<LD>(ob, e)];
+      xb[own<LD>(ob, e)] = make_double2(cv.x + (h / 3.0) * d.r[e], cv.y + (h / 3.0) * d.i[e]);
+    }
+    __syncthreads();
+    Mat G1, G2, G3;
+    stage_gemm<LD>(cb, tA, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
+    stage_gemm<LD>(xb, tB, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
+    __syncthreads();
+    // X3 = c + 2h/3 c' - h^2 (2/9) G1
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const double2 cv = cb[own<LD>(ob, e)];
+      xb[own<LD>(ob, e)] = make_double2(cv.x + (2.0 * h / 3.0) * d.r[e] - hh * (2.0 / 9.0) * G1.r[e],
+                                cv.y + (2.0 * h / 3.0) * d.i[e] - hh * (2.0 / 9.0) * G1.i[e]);
+    }
+    __syncthreads();
+    stage_gemm<LD>(xb, tD, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G3.r[e] = gr; G3.i[e] = gi; });
+    __syncthreads();
+    // X4 = c + h/3 c' - h^2 (G1/9 - G2/18)
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const double2 cv = cb[own<LD>(ob, e)];
+      xb[own<LD>(ob, e)] = make_double2(cv.x + (h / 3.0) * d.r[e] - hh * ((1.0 / 9.0) * G1.r[e] - (1.0 / 18.0) * G2.r[e]),
+                                cv.y + (h / 3.0) * d.i[e] - hh * ((1.0 / 9.0) * G1.i[e] - (1.0 / 18.0) * G2.i[e]));
+    }
+    __syncthreads();
+    // G4; per element {c, c', G1, G2, G3, G4} -> X5, X6, T7, c-partial (LDS), c'-partial
+    Mat& X5 = G1;
+    Mat& X6 = G2;
+    Mat& T7 = G3;
+    stage_gemm<LD>(xb, tB, gidx, g2, ob, lane, cofs, [&](int e, double a4, double b4) {
+      const double2 cv = cb[own<LD>(ob, e)];
+      const double dr = d.r[e], di = d.i[e];
+      const double a1 = G1.r[e], b1 = G1.i[e], a2 = G2.r[e], b2 = G2.i[e], a3 = G3.r[e], b3 = G3.i[e];
+      X5.r[e] = cv.x + 0.5 * h * dr - hh * ((11.0 / 32.0) * a1 - 0.25 * a2 + (1.0 / 32.0) * a3);
+      X5.i[e] = cv.y + 0.5 * h * di - hh * ((11.0 / 32.0) * b1 - 0.25 * b2 + (1.0 / 32.0) * b3);
+      X6.r[e] = cv.x + 0.5 * h * dr - hh * ((9.0 / 32.0) * a1 + (1.0 / 16.0) * a2 - (1.0 / 32.0) * a3 - (3.0 / 16.0) * a4);
+      X6.i[e] = cv.y + 0.5 * h * di - hh * ((9.0 / 32.0) * b1 + (1.0 / 16.0) * b2 - (1.0 / 32.0) * b3 - (3.0 / 16.0) * b4);
+      T7.r[e] = cv.x + h * dr - hh * ((-3.0 / 22.0) * a1 - (3.0 / 22.0) * a2 + (9.0 / 22.0) * a3 + (12.0 / 11.0) * a4);
+      T7.i[e] = cv.y + h * di - hh * ((-3.0 / 22.0) * b1 - (3.0 / 22.0) * b2 + (9.0 / 22.0) * b3 + (12.0 / 11.0) * b4);
+      cb[own<LD>(ob, e)] = make_double2(cv.x + h * dr - hh * ((11.0 / 120.0) * a1 + (9.0 / 40.0) * a3 + (9.0 / 20.0) * a4),
+                                cv.y + h * di - hh * ((11.0 / 120.0) * b1 + (9.0 / 40.0) * b3 + (9.0 / 20.0) * b4));
+      d.r[e] = dr - h * ((11.0 / 120.0) * a1 + (27.0 / 40.0) * a3 + (27.0 / 40.0) * a4);
+      d.i[e] = di - h * ((11.0 / 120.0) * b1 + (27.0 / 40.0) * b3 + (27.0 / 40.0) * b4);
+    });
+    __syncthreads();
+    store_mat_ld<LD>(xb, X5, ob);
+    __syncthreads();
+    stage_gemm<LD>(xb, tC, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G5
+      T7.r[e] += hh * (8.0 / 11.0) * gr;
+      T7.i[e] += hh * (8.0 / 11.0) * gi;
+      double2 cv = cb[own<LD>(ob, e)];
+      cv.x += hh * (2.0 / 15.0) * gr;
+      cv.y += hh * (2.0 / 15.0) * gi;
+      cb[own<LD>(ob, e)] = cv;
+      d.r[e] += h * (4.0 / 15.0) * gr;
+      d.i[e] += h * (4.0 / 15.0) * gi;
+    });
+    __syncthreads();
+    store_mat_ld<LD>(xb, X6, ob);
+    __syncthreads();
+    stage_gemm<LD>(xb, tC, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G6
+      double2 cv = cb[own<LD>(ob, e)];
+      cv.x += hh * (2.0 / 15.0) * gr;
+      cv.y += hh * (2.0 / 15.0) * gi;
+      cb[own<LD>(ob, e)] = cv;
+      d.r[e] += h * (4.0 / 15.0) * gr;
+      d.i[e] += h * (4.0 / 15.0) * gi;
+    });
+    __syncthreads();
+    store_mat_ld<LD>(xb, T7, ob);  // X7
+    __syncthreads();
+    stage_gemm<LD>(xb, tE, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G7
+      d.r[e] -= h * (11.0 / 120.0) * gr;
+      d.i[e] -= h * (11.0 / 120.0) * gi;
+    });
+  }
+  return d;
+}
+
+
+// ---------------------------------------------------------------------------
+// Split launch: two workgroups of four waves per pair (one per SIMD, so each
+// wave has the whole register file of its SIMD), each owning 32 of the 64
+// columns of Z.  The RK stages act on columns independently, so each half
+// steps its own columns; what couples the columns goes through a per-pair
+// exchange block in global memory: the badness partials (row sums over each
+// half's columns) after every slice, and the halves of [Q; P] at every
+// right-hand-side transformation and before the reflection solve.  Both
+// halves combine the partials in the same order, so they take the same
+// decisions; at a transformation both invert the whole Q (the elimination is
+// latency-bound, so the redundant work costs no time) and multiply P by the
+// columns of Q^{-1} they own.  A launch needs both halves of every pair
+// resident at once (cooperative launch), which holds up to one pair per two
+// CUs; a bounded wait marks the pair RHEED_PAIR_SYNC instead of hanging.
+// ---------------------------------------------------------------------------
+
+constexpr int SW = 4;        // waves per half-pair workgroup
+constexpr int ST = SW * 64;  // threads per half-pair workgroup
+constexpr int HC = NP / 2;   // columns per half
+
+struct SplitLds {
+  double2 cx[2 * NP * HC];   // c of this half [NP][HC], then the stage input [NP][HC]; [NP][NP] at the end
+  double2 ext[NP * NP];      // Q of both halves for the elimination, then Q^{-1}
+  double2 tb[5][MAXBOX + 1];
+  double2 gj_row[2 * NP];
+  int gj_piv[NP];
+  double g2s[NP];
+  int bhk[NP][2];
+  double xi_loc[2][NP];      // this half's |q_rr| and sum_{j != r} |q_rj| per row
+  int flag_singular;
+  int sync_fail;
+};
+
+__shared__ SplitLds split_lds;
+
+constexpr int XCH_SPIN = 1 << 20;  // polls before a wait gives up
+
+// Exchange data goes through memory with system-scope accesses, which are
+// not kept in the (per-XCD) L2: a writer's stores are complete once its
+// vector-memory counter drains, and a reader's loads see memory, so no
+// cache-wide write-back or invalidation is needed around the counters.
+__device__ __forceinline__ void xput(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ double xget(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void xput2(double2* p, double2 v) {
+  xput(&p->x, v.x);
+  xput(&p->y, v.y);
+}
+__device__ __forceinline__ double2 xget2(const double2* p) {
+  return make_double2(xget(&p->x), xget(&p->y));
+}
+
+// Makes this workgroup's exchange stores complete, then raises its counter to v.
+__device__ __forceinline__ void xch_publish(unsigned long long* cnt, unsigned long long v) {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's stores are done
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(cnt, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Waits until the partner's counter reaches v.  After one wait has given up
+// (*fail set), later waits return at once, so a lost partner costs one time-out.
+__device__ __forceinline__ void xch_wait(unsigned long long* cnt, unsigned long long v, int* fail) {
+  if (threadIdx.x == 0 && !*fail) {
+    int it = 0;
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) < v) {
+      if (++it > XCH_SPIN) {
+        *fail = 1;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+  }
+  __syncthreads();
+}
+
+// Q^{-1} of the leading n x n block of split_lds.ext (row major, identity
+// outside the block), written back over it; with t != null the columns
+// [col0, col0 + HC) also go to t (global, row major [NP][NP]).
+__device__ __noinline__ void invert_split(int n, double2* t, int col0) {
+  SplitLds& s = split_lds;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double2 z[2 * NP / SW];
+#pragma unroll
+  for (int m = 0; m < NP / SW; ++m) z[m] = s.ext[(w + SW * m) * NP + lane];
+  const int pos = gj_inverse<SW>(z, n, lane, w, s.gj_row, s.gj_piv, &s.flag_singular);
+  const bool mine = t != nullptr && pos >= col0 && pos < col0 + HC;
+#pragma unroll
+  for (int m = NP / SW; m < 2 * NP / SW; ++m) {
+    const int sl = w + SW * (m - NP / SW);
+    const int row = sl < n ? s.gj_piv[sl] : sl;
+    const double2 val = sl < n ? z[m] : make_double2(pos == sl ? 1.0 : 0.0, 0.0);
+    s.ext[row * NP + pos] = val;
+    if (mine) t[row * NP + pos] = val;
+  }
+  __syncthreads();
+}
+
+// D = [P_0 | P_1] T[:, col0 ..] for the wave's 16 x 32 block: P_h in pcx at
+// h NP HC (row stride HC), T in tbuf (row stride NP).
+template <class Epi>
+__device__ __forceinline__ void split_gemm(const double2* __restrict__ pcx, const double2* __restrict__ tbuf, int lane,
+                                           int RT, int col0, Epi&& epi) {
+  __builtin_amdgcn_sched_barrier(0);
+  d4 t1[NJT], t2[NJT], t3[NJT];
+#pragma unroll
+  for (int jt = 0; jt < NJT; ++jt) t1[jt] = t2[jt] = t3[jt] = d4{0, 0, 0, 0};
+  const int ar = (16 * RT + (lane & 15)) * HC + (lane >> 4);
+  const int bb = (lane >> 4) * NP + col0 + (lane & 15);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const double2 u = q < 8 ? pcx[ar + 4 * q] : pcx[NP * HC + ar + 4 * (q - 8)];
+    const double us = u.x + u.y;
+#pragma unroll
+    for (int jt = 0; jt < NJT; ++jt) {
+      const double2 x = tbuf[bb + 4 * NP * q + 16 * jt];
+      t1[jt] = mfma(u.x, x.x, t1[jt]);
+      t2[jt] = mfma(u.y, x.y, t2[jt]);
+      t3[jt] = mfma(us, x.x + x.y, t3[jt]);
+    }
+    if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int jt = 0; jt < NJT; ++jt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) epi(jt * 4 + v, t1[jt][v] - t2[jt][v], t3[jt][v] - t1[jt][v] - t2[jt][v]);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int SLOTS, int NT>
+__device__ __forceinline__ void load_table_nodes(double2 (*tb)[MAXBOX + 1], const double2* __restrict__ Us, int box,
+                                                 int n0, int n1, int tid) {
+  const int total = (n1 - n0) * box;
+  for (int e = tid; e < total; e += NT) {
+    const int q = e / box;
+    const int nn = n0 + q;
+    tb[nn % SLOTS][e - q * box] = Us[(long long)nn * box + (e - q * box)];
+  }
+}
+
+template <int STEPPER>
+__global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
+  using T = Tab<STEPPER>;
+  SplitLds& s = split_lds;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int RT = w;                    // row tile of this wave
+  const int p = blockIdx.x >> 1, half = blockIdx.x & 1;
+  const int col0 = HC * half;          // first column of this half
+  const StructDev S = a.structs[a.pair_struct[p]];
+  const int N = S.n_beams;
+  const int L = S.n_slices;
+  const double h = S.h;
+  const double2* __restrict__ Us = a.U + S.table_off;
+
+  if (tid < NP) {
+    s.bhk[tid][0] = tid < N ? a.beams[2 * (S.beam_off + tid)] : 0;
+    s.bhk[tid][1] = tid < N ? a.beams[2 * (S.beam_off + tid) + 1] : 0;
+  }
+  if (tid == 0) {
+    s.flag_singular = 0;
+    s.sync_fail = 0;
+  }
+  if (tid < T::slots) s.tb[tid][S.box] = make_double2(0.0, 0.0);
+  __syncthreads();
+  const double th0 = a.angles[2 * p], th1 = a.angles[2 * p + 1];
+  if (tid < NP) {
+    const double b0x = S.gamma * cos(th0) * cos(th1);
+    const double b0y = S.gamma * cos(th0) * sin(th1);
+    double arg = 0.0;
+    if (tid < N) {
+      const double qx = b0x + s.bhk[tid][0] * S.recip[0] + s.bhk[tid][1] * S.recip[2];
+      const double qy = b0y + s.bhk[tid][0] * S.recip[1] + s.bhk[tid][1] * S.recip[3];
+      arg = S.gamma * S.gamma - (qx * qx + qy * qy);
+    }
+    s.g2s[tid] = arg;
+  }
+  __syncthreads();
+  G2 gg;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) gg.v[v] = s.g2s[16 * RT + 4 * v + (lane >> 4)];
+  Gidx gx;
+  {
+    const int W = 2 * S.kd + 1;
+    const int iA = 16 * RT + (lane & 15);
+    const int baseA = (s.bhk[iA][0] + S.hd) * W + (s.bhk[iA][1] + S.kd);
+#pragma unroll
+    for (int q = 0; q < 16; q += 2) {
+      const int k0 = 4 * q + (lane >> 4), k1 = 4 * (q + 1) + (lane >> 4);
+      const unsigned i0 = (iA < N && k0 < N) ? baseA - (s.bhk[k0][0] * W + s.bhk[k0][1]) : S.box;
+      const unsigned i1 = (iA < N && k1 < N) ? baseA - (s.bhk[k1][0] * W + s.bhk[k1][1]) : S.box;
+      gx.v[q >> 1] = i0 | (i1 << 16);
+    }
+  }
+  double2* cb = s.cx;             // c of this half
+  double2* xb = s.cx + NP * HC;   // stage input of this half
+  int ob = (16 * RT + (lane >> 4)) * HC + (lane & 15);
+  Mat d;
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), col = col0 + 16 * (e >> 2) + (lane & 15);
+    const bool dg = (row == col);
+    cb[own<HC>(ob, e)] = make_double2(dg ? 1.0 : 0.0, 0.0);
+    const double g2v = gg.v[e & 3];
+    d.r[e] = (dg && g2v < 0.0) ? sqrt(-g2v) : 0.0;
+    d.i[e] = (dg && g2v >= 0.0) ? sqrt(g2v) : 0.0;
+  }
+  const bool save = a.ws != nullptr;
+  char* pws = save ? a.ws + (long long)p * a.ck.pair_stride : nullptr;
+  char* X = a.xch + (long long)p * XCH_STRIDE;
+  unsigned long long* cnt_me = reinterpret_cast<unsigned long long*>(X) + half;
+  unsigned long long* cnt_other = reinterpret_cast<unsigned long long*>(X) + (1 - half);
+  double* xi_g = reinterpret_cast<double*>(X + XCH_XI);       // [half][parity][2][NP]
+  double2* big_g = reinterpret_cast<double2*>(X + XCH_BIG);   // [half][parity][2][NP][HC]
+  unsigned long long ev = a.epoch << 32;
+  int nrhst = 0;
+  // this half's [Q; P] columns to the exchange block of event ev
+  auto publish_qp = [&]() {
+    double2* mine = big_g + (long long)(half * 2 + (int)(ev & 1)) * 2 * NP * HC;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), cl = 16 * (e >> 2) + (lane & 15);
+      xput2(&mine[row * HC + cl], cb[own<HC>(ob, e)]);
+      xput2(&mine[NP * HC + row * HC + cl], make_double2(d.r[e], d.i[e]));
+    }
+  };
+
+  load_table_nodes<T::slots, ST>(s.tb, Us, S.box, 0, 1, tid);
+  for (int i = 0; i < L; ++i) {
+    asm volatile("" : "+v"(ob));
+    if (save && (i % a.ck.every) == 0) {
+      double2* st = reinterpret_cast<double2*>(pws + (long long)(i / a.ck.every) * a.ck.state_bytes);
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), col = col0 + 16 * (e >> 2) + (lane & 15);
+        st[row * NP + col] = cb[own<HC>(ob, e)];
+        st[NP * NP + row * NP + col] = make_double2(d.r[e], d.i[e]);
+      }
+    }
+    const int nb = i * T::nodes;
+    load_table_nodes<T::slots, ST>(s.tb, Us, S.box, nb + 1, nb + T::nodes + 1, tid);
+    d = rk_slice<STEPPER, HC>(cb, xb, &s.tb[0][0], nb, gx, gg, ob, lane, 0, h, d);
+
+    // badness (Sec. 3.2): this half's row sums, then both halves' in half order
+    {
+      double dg[4] = {0, 0, 0, 0}, of[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), col = col0 + 16 * (e >> 2) + (lane & 15);
+        const double2 cv = cb[own<HC>(ob, e)];
+        const double av = sqrt(cv.x * cv.x + cv.y * cv.y);
+        if (row < N && col < N) {
+          if (row == col) dg[e & 3] += av;
+          else of[e & 3] += av;
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+          dg[v] += __shfl_xor(dg[v], off, 64);
+          of[v] += __shfl_xor(of[v], off, 64);
+        }
+      }
+      if ((lane & 15) == 0) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * RT + 4 * v + (lane >> 4);
+          s.xi_loc[0][row] = dg[v];
+          s.xi_loc[1][row] = of[v];
+        }
+      }
+    }
+    __syncthreads();
+    ++ev;
+    if (tid < 2 * NP) xput(&xi_g[(half * 2 + (int)(ev & 1)) * 2 * NP + tid], s.xi_loc[tid / NP][tid % NP]);
+    xch_publish(cnt_me, ev);
+    xch_wait(cnt_other, ev, &s.sync_fail);
+    bool do_rhst;
+    {
+      const double* xo = xi_g + ((1 - half) * 2 + (int)(ev & 1)) * 2 * NP;
+      const double dm = s.xi_loc[0][lane], om = s.xi_loc[1][lane], dt = xget(&xo[lane]), ot = xget(&xo[NP + lane]);
+      const double dgl = half == 0 ? dm + dt : dt + dm;
+      const double ofl = half == 0 ? om + ot : ot + om;
+      double hi = lane < N ? dgl + ofl : 0.0;
+      double lo = lane < N ? dgl - ofl : 1.0e308;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+      }
+      const double xi = lo > 0.0 ? hi / lo : INFINITY;
+      do_rhst = xi > a.threshold;
+    }
+    if (save && tid == 0 && half == 0) pws[a.ck.flags_off + i] = do_rhst ? 1 : 0;
+    if (do_rhst) {
+      // Z <- Z Q^{-1}: gather Q and P of both halves, invert Q, P <- P Q^{-1} for this half's columns
+      ++nrhst;
+      ++ev;
+      publish_qp();
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), cl = 16 * (e >> 2) + (lane & 15);
+        s.ext[row * NP + col0 + cl] = cb[own<HC>(ob, e)];
+      }
+      __syncthreads();
+      double2* pme = s.cx + half * NP * HC;   // P of half h goes to cx[h NP HC ..]
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), cl = 16 * (e >> 2) + (lane & 15);
+        pme[row * HC + cl] = make_double2(d.r[e], d.i[e]);
+      }
+      xch_publish(cnt_me, ev);
+      xch_wait(cnt_other, ev, &s.sync_fail);
+      {
+        const double2* theirs = big_g + (long long)((1 - half) * 2 + (int)(ev & 1)) * 2 * NP * HC;
+        double2* pot = s.cx + (1 - half) * NP * HC;
+        for (int idx = tid; idx < NP * HC; idx += ST) {
+          const int r = idx / HC, c = idx - r * HC;
+          s.ext[r * NP + HC * (1 - half) + c] = xget2(&theirs[idx]);
+          pot[idx] = xget2(&theirs[NP * HC + idx]);
+        }
+      }
+      __syncthreads();
+      invert_split(N, save ? reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * NP * NP * sizeof(double2))
+                           : nullptr,
+                   col0);
+      split_gemm(s.cx, s.ext, lane, RT, col0, [&](int e, double gr, double gi) {
+        d.r[e] = gr;
+        d.i[e] = gi;
+      });
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), col = col0 + 16 * (e >> 2) + (lane & 15);
+        cb[own<HC>(ob, e)] = make_double2((row == col) ? 1.0 : 0.0, 0.0);
+      }
+    }
+    __syncthreads();
+  }
+
+  if (save) {
+    double2* st = reinterpret_cast<double2*>(pws + (long long)(a.ck.max_ckpt - 1) * a.ck.state_bytes);
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), col = col0 + 16 * (e >> 2) + (lane & 15);
+      st[row * NP + col] = cb[own<HC>(ob, e)];
+      st[NP * NP + row * NP + col] = make_double2(d.r[e], d.i[e]);
+    }
+  }
+  // reflection (half 0): [Gamma Q - iP; Gamma Q + iP] of both halves, rho = lower (upper^{-1} e_1)
+  ++ev;
+  publish_qp();
+  xch_publish(cnt_me, ev);
+  if (half == 1) return;
+  xch_wait(cnt_other, ev, &s.sync_fail);
+  double2 low[NE];
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), cl = 16 * (e >> 2) + (lane & 15);
+    const double2 cv = cb[own<HC>(ob, e)];
+    const double g2v = gg.v[e & 3];
+    const double g_r = g2v >= 0.0 ? sqrt(g2v) : 0.0, g_i = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
+    const double qr = g_r * cv.x - g_i * cv.y, qi = g_r * cv.y + g_i * cv.x;
+    s.ext[row * NP + cl] = make_double2(qr + d.i[e], qi - d.r[e]);   // Gamma Q - iP
+    low[e] = make_double2(qr - d.i[e], qi + d.r[e]);                  // Gamma Q + iP
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), cl = 16 * (e >> 2) + (lane & 15);
+    s.cx[row * NP + cl] = low[e];
+  }
+  {
+    const double2* theirs = big_g + (long long)(2 + (int)(ev & 1)) * 2 * NP * HC;
+    for (int idx = tid; idx < NP * HC; idx += ST) {
+      const int r = idx / HC, c = idx - r * HC;
+      const double g2v = s.g2s[r];
+      const double g_r = g2v >= 0.0 ? sqrt(g2v) : 0.0, g_i = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
+      const double2 cv = xget2(&theirs[idx]), pv = xget2(&theirs[NP * HC + idx]);
+      const double qr = g_r * cv.x - g_i * cv.y, qi = g_r * cv.y + g_i * cv.x;
+      s.ext[r * NP + HC + c] = make_double2(qr + pv.y, qi - pv.x);
+      s.cx[r * NP + HC + c] = make_double2(qr - pv.y, qi + pv.x);
+    }
+  }
+  __syncthreads();
+  invert_split(N, nullptr, 0);
+  if (tid < NP) {
+    const int j = tid;
+    double eta = 0.0;
+    double2 rj = make_double2(0.0, 0.0);
+    if (j < N) {
+      for (int k = 0; k < N; ++k) {
+        const double2 l = s.cx[j * NP + k], x = s.ext[k * NP];
+        rj.x += l.x * x.x - l.y * x.y;
+        rj.y += l.x * x.y + l.y * x.x;
+      }
+      const double g00 = s.g2s[0];
+      const double gj = s.g2s[j];
+      if (gj > 0.0) {
+        eta = (rj.x * rj.x + rj.y * rj.y) * sqrt(g00) / sqrt(gj);
+        if (a.convention == 1) eta *= sin(th0);
+      }
+    }
+    if (j < a.ld) {
+      a.intensity[(long long)p * a.ld + j] = eta;
+      if (a.rho) a.rho[(long long)p * a.ld + j] = rj;
+    }
+    const bool fin = isfinite(rj.x) && isfinite(rj.y);
+    const unsigned long long bad = __ballot(!fin);
+    if (j == 0) {
+      int stv = 0;
+      if (s.sync_fail) stv = 3;
+      else if (s.flag_singular) stv = 1;
+      else if (bad) stv = 2;
+      a.status[p] = stv;
+      if (a.nrhst) a.nrhst[p] = nrhst;
+    }
+  }
+}
+
 hipError_t launch_forward(int stepper, const FwdArgs& a, hipStream_t stream) {
   dim3 grid(a.n_pairs), block(FT);
   if (stepper == 0)
@@ -551,6 +1146,24 @@ hipError_t launch_forward(int stepper, const FwdArgs& a, hipStream_t stream) {
   else
     hipLaunchKernelGGL(forward_kernel<1>, grid, block, 0, stream, a);
   return hipGetLastError();
+}
+
+hipError_t launch_forward_split(int stepper, const FwdArgs& a, hipStream_t stream) {
+  FwdArgs arg = a;
+  void* params[] = {&arg};
+  const void* f = stepper == 0 ? reinterpret_cast<const void*>(&forward_split_kernel<0>)
+                               : reinterpret_cast<const void*>(&forward_split_kernel<1>);
+  return hipLaunchCooperativeKernel(f, dim3(2 * a.n_pairs), dim3(ST), params, 0, stream);
+}
+
+int forward_split_max_pairs(int device) {
+  int coop = 0, cus = 0, per_cu0 = 0, per_cu1 = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu0, forward_split_kernel<0>, ST, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu1, forward_split_kernel<1>, ST, 0) != hipSuccess)
+    return 0;
+  return cus * (per_cu0 < per_cu1 ? per_cu0 : per_cu1) / 2;
 }
 
 }  // namespace rheed

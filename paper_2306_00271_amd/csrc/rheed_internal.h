@@ -51,7 +51,19 @@ struct FwdArgs {
   int n_pairs;
   int pad;
   double threshold;
+  // split launches (two workgroups per pair): per-pair exchange blocks and the
+  // launch number that tags their counters
+  char* xch;
+  unsigned long long epoch;
 };
+
+// Exchange block of one pair in a split launch (bytes): two 64-bit counters,
+// per half and parity the badness partials [2][NP] doubles, and per half and
+// parity the half's [Q; P] columns, [2][NP][32] complex.
+constexpr long long XCH_XI = 256;
+constexpr long long XCH_BIG = XCH_XI + 2 * 2 * 2 * NP * 8;
+constexpr long long XCH_HALF = 2LL * NP * 32 * 16;
+constexpr long long XCH_STRIDE = XCH_BIG + 2 * 2 * XCH_HALF;
 
 struct PotArgs {
   const StructDev* structs;
@@ -107,6 +119,8 @@ struct GradArgs {
 };
 
 hipError_t launch_forward(int stepper, const FwdArgs& a, hipStream_t stream);
+hipError_t launch_forward_split(int stepper, const FwdArgs& a, hipStream_t stream);
+int forward_split_max_pairs(int device);  // pairs a split launch can hold at once (0: not available)
 hipError_t launch_backward(int stepper, const BwdArgs& a, hipStream_t stream);
 hipError_t launch_grad_assemble(const GradArgs& a, int n_struct, int max_nodes, hipStream_t stream);
 hipError_t launch_potential(const PotArgs& a, long long max_elems, hipStream_t stream);

@@ -5,14 +5,15 @@ import numpy as np
 from oracle import driver
 
 
-def gpu_forward(wl, stepper=None, threshold=1000.0, convention="flux", want_rho=False, structures=None):
+def gpu_forward(wl, stepper=None, threshold=1000.0, convention="flux", want_rho=False, structures=None,
+                layout="auto"):
     import torch
     from paper_2306_00271_amd import api
     dev = torch.device("cuda:0")
     if structures is not None:
         import dataclasses
         wl = dataclasses.replace(wl, structures=structures)
-    plan = api.plan_for(wl, stepper=stepper, threshold=threshold, convention=convention)
+    plan = api.plan_for(wl, stepper=stepper, threshold=threshold, convention=convention, layout=layout)
     atoms = api.atoms_for(wl, dev)
     U = plan.potential(atoms)
     out = plan.forward(U, api.angles_for(wl, dev), want_rho=want_rho, want_nrhst=True)

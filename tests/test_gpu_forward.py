@@ -29,27 +29,30 @@ def test_potential_table_matches_oracle(stepper):
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("layout", ["whole", "split"])
 @pytest.mark.parametrize("stepper", ["rk4", "rk6"])
 @pytest.mark.parametrize("n_beams", [21, 45, 61, 64])
-def test_forward_small_2d(stepper, n_beams):
+def test_forward_small_2d(stepper, n_beams, layout):
     # step sizes in the converged regime of each tableau (RK4 at 0.1 A diverges
     # on the N = 61 slabs, RK6 does not)
     wl = small_2d(n_beams=n_beams, n_slices=80 if stepper == "rk4" else 40, thickness=4.0, n_layers=2, n_angles=4)
-    res = gpu_forward(wl, stepper=stepper)
+    res = gpu_forward(wl, stepper=stepper, layout=layout)
+    assert res["plan"].split == (layout == "split")
     ref, rho_ref, nr = oracle_forward(wl, stepper=stepper)
     N = n_beams
     got = res["intensity"][:, :N]
     assert (res["status"] == 0).all()
     e = eacc(got, ref)
-    _report(f"small2d N={N} {stepper} rhst={nr.tolist()} gpu_rhst={res['n_rhst'].tolist()}", e)
+    _report(f"small2d N={N} {stepper} {layout} rhst={nr.tolist()} gpu_rhst={res['n_rhst'].tolist()}", e)
     assert e <= TOL
     big = ref > 1e-6
     assert np.all(np.abs(got[big] - ref[big]) <= 1e-9 * ref[big])
 
 
-def test_forward_row_positron_rk4():
+@pytest.mark.parametrize("layout", ["whole", "split"])
+def test_forward_row_positron_rk4(layout):
     wl = small_row(hmax=6, n_slices=80, thickness=12.0, n_layers=4, n_angles=6)
-    res = gpu_forward(wl, stepper="rk4", want_rho=True)
+    res = gpu_forward(wl, stepper="rk4", want_rho=True, layout=layout)
     ref, rho_ref, _ = oracle_forward(wl, stepper="rk4")
     got = res["intensity"][:, :13]
     e = eacc(got, ref)
@@ -89,13 +92,27 @@ def test_config1_full_size():
     assert e <= TOL
 
 
-def test_config2_full_size_rk6():
+@pytest.mark.parametrize("layout", ["whole", "split"])
+def test_config2_full_size_rk6(layout):
     wl = config2(stepper="rk6")
-    res = gpu_forward(wl)
+    res = gpu_forward(wl, layout=layout)
     assert (res["status"] == 0).all()
     idx = [0, 64, 127]
     ref, _, nr = oracle_forward(wl, angle_idx=idx)
     got = res["intensity"][idx, :61]
     e = eacc(got, ref)
-    _report(f"config2 full size rk6 (sampled angles) rhst={nr.tolist()}", e)
+    _report(f"config2 full size rk6 {layout} (sampled angles) rhst={nr.tolist()}", e)
     assert e <= TOL
+
+
+def test_layouts_agree_on_every_angle():
+    """The split and whole layouts on all 128 angles of the N = 61 workload:
+    the same discretisation, so they agree to rounding everywhere."""
+    wl = config2(stepper="rk6")
+    a = gpu_forward(wl, layout="whole", want_rho=True)
+    b = gpu_forward(wl, layout="split", want_rho=True)
+    assert (a["status"] == 0).all() and (b["status"] == 0).all()
+    assert (a["n_rhst"] == b["n_rhst"]).all()
+    e = eacc(b["intensity"], a["intensity"])
+    _report("split vs whole, all angles", e)
+    assert e <= 1e-12
