@@ -169,7 +169,10 @@ rheed_status rheed_potential_backward(rheed_plan_t plan, const double* atoms, co
  *  pair_status device int32 [n_pairs] (RHEED_PAIR_*)
  *  n_rhst     device int32 [n_pairs] number of right-hand-side transformations, or NULL
  *  workspace  device, >= fwd_workspace bytes, to keep the states rheed_backward
- *             needs; NULL when no backward pass follows. */
+ *             needs; NULL when no backward pass follows.
+ * With the split layout the launch is cooperative and uses exchange blocks
+ * owned by the plan, so forward calls on one plan must not overlap (issue them
+ * on one stream). */
 rheed_status rheed_forward(rheed_plan_t plan, const void* U_tables, const double* angles,
                            double* intensity, void* rho, int32_t* pair_status, int32_t* n_rhst,
                            void* workspace, size_t ws_bytes, void* stream);

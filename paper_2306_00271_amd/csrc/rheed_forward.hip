@@ -750,17 +750,20 @@ struct SplitLds {
 
 __shared__ SplitLds split_lds;
 
-constexpr int XCH_SPIN = 1 << 20;  // polls before a wait gives up
+constexpr int XCH_SPIN = 1 << 22;  // polls before a wait gives up
 
-// Exchange data goes through memory with system-scope accesses, which are
-// not kept in the (per-XCD) L2: a writer's stores are complete once its
-// vector-memory counter drains, and a reader's loads see memory, so no
-// cache-wide write-back or invalidation is needed around the counters.
+// Exchange protocol.  Data goes through memory as agent-scope atomic
+// accesses (coherent across the XCDs' L2 caches).  A writer makes its
+// stores complete (each wave), synchronises its workgroup, and raises its
+// counter with an agent-scope release store, which writes the L2 back first,
+// so the data is in memory before the counter is.  A reader polls the
+// partner's counter with coherent loads and then reads the data, issued
+// after the counter was seen.
 __device__ __forceinline__ void xput(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ double xget(const double* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void xput2(double2* p, double2 v) {
   xput(&p->x, v.x);
@@ -770,20 +773,23 @@ __device__ __forceinline__ double2 xget2(const double2* p) {
   return make_double2(xget(&p->x), xget(&p->y));
 }
 
-// Makes this workgroup's exchange stores complete, then raises its counter to v.
+// Raises this workgroup's counter to v once its exchange stores are in memory.
 __device__ __forceinline__ void xch_publish(unsigned long long* cnt, unsigned long long v) {
-  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's stores are done
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores have reached the L2
   __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(cnt, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  if (threadIdx.x == 0) __hip_atomic_store(cnt, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Waits until the partner's counter reaches v.  After one wait has given up
-// (*fail set), later waits return at once, so a lost partner costs one time-out.
+// Waits until the partner's counter reaches v.  A wait gives up after about
+// XCH_TICKS of the constant-rate clock (far beyond any legitimate skew between
+// the halves) and sets *fail; after that, later waits return at once.
+constexpr long long XCH_TICKS = 2000000;
 __device__ __forceinline__ void xch_wait(unsigned long long* cnt, unsigned long long v, int* fail) {
   if (threadIdx.x == 0 && !*fail) {
+    const long long t0 = wall_clock64();
     int it = 0;
-    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) < v) {
-      if (++it > XCH_SPIN) {
+    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) {
+      if (++it > XCH_SPIN || wall_clock64() - t0 > XCH_TICKS) {
         *fail = 1;
         break;
       }

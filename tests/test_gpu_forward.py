@@ -116,3 +116,21 @@ def test_layouts_agree_on_every_angle():
     e = eacc(b["intensity"], a["intensity"])
     _report("split vs whole, all angles", e)
     assert e <= 1e-12
+
+
+def test_split_layout_repeated_launches_on_one_plan():
+    """Launches on one plan reuse its exchange blocks (their counters are tagged
+    with the launch number): every launch must give the same bits."""
+    import torch
+    from paper_2306_00271_amd import api
+    wl = small_2d(n_beams=45, n_slices=40, thickness=4.0, n_layers=2, n_angles=6)
+    dev = torch.device("cuda:0")
+    plan = api.plan_for(wl, stepper="rk6", layout="split")
+    U = plan.potential(api.atoms_for(wl, dev))
+    ang = api.angles_for(wl, dev)
+    outs = [plan.forward(U, ang, want_rho=True, want_nrhst=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    for o in outs:
+        assert (o["status"] == 0).all()
+        assert torch.equal(o["rho"], outs[0]["rho"])
+        assert torch.equal(o["n_rhst"], outs[0]["n_rhst"])
