@@ -26,7 +26,15 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MFMA_FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 matrix, published
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "forward_kernel_rk6_n61_traffic.md")
+
+
+def kernel_name(split):
+    return "forward_split_kernel<1>" if split else "forward_kernel<1>"
+
+
+def traffic_summary(split):
+    stem = "forward_split_kernel" if split else "forward_kernel"
+    return os.path.join(ROOT, "profiles", f"{stem}_rk6_n61_traffic.md")
 
 
 def _flops_forward(N, L, stages, n_rhst_total, n_pairs):
@@ -89,13 +97,14 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def traffic_from_profile():
+def traffic_from_profile(split):
     """HBM bytes per forward launch from the committed counter summary, or
     None if the summary is missing or was taken on other kernel sources."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+    path = traffic_summary(split)
+    if not os.path.exists(path):
         return None
     fields = {}
-    with open(TRAFFIC_SUMMARY) as fh:
+    with open(path) as fh:
         for line in fh:
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].split(": ", 1)
@@ -126,7 +135,8 @@ def traffic_probe():
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes": src.numel() * 8, "source_sha256": kernel_source_hash()}))
+    print(json.dumps({"copy_bytes": src.numel() * 8, "source_sha256": kernel_source_hash(),
+                      "kernel": kernel_name(plan.split)}))
 
 
 # -------------------------------------------------------------------- bench
@@ -212,10 +222,10 @@ def main():
     fl = _flops_forward(N, L, stages, nrhst, n_pairs)
     achieved = fl / (fwd_ms / 1e3) / 1e12
     # counters were taken on the single-structure launch with state saving
-    traffic = traffic_from_profile() if (do_adj and args.structures == 1) else None
+    traffic = traffic_from_profile(plan.split) if (do_adj and args.structures == 1) else None
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": MFMA_FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / MFMA_FP64_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": "forward_kernel<1>", "kernel_ms": round(fwd_ms, 4), "flops_per_launch": fl}
+                "kernel": kernel_name(plan.split), "kernel_ms": round(fwd_ms, 4), "flops_per_launch": fl}
 
     cpu = None
     if not args.no_cpu:
@@ -250,7 +260,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name + ("" if do_adj else "-forward"), "structures": len(wl.structures),
                    "angles": len(wl.theta0), "n_beams": N, "slices": L, "stepper": stepper,
-                   "pairs": n_pairs, "rhst_per_pair": round(nrhst / n_pairs, 2),
+                   "pairs": n_pairs, "layout": "split" if plan.split else "whole", "rhst_per_pair": round(nrhst / n_pairs, 2),
                    "bad_pairs": int((status != 0).sum()), "wall_s": round(wall, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
