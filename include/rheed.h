@@ -192,6 +192,14 @@ rheed_status rheed_backward(rheed_plan_t plan, const void* U_tables, const doubl
 rheed_status rheed_rfactor(int32_t n_pairs, int32_t ld, const double* intensity, const double* target,
                            double* loss, double* dL_dI, void* stream);
 
+/* Measured FP64 matrix-core throughput of the current device, for reading the
+ * propagation kernels' roofline against an achievable ceiling beside the
+ * published one: `blocks` workgroups of 4 waves each run 8 independent chains
+ * of `iters` v_mfma_f64_16x16x4f64 (2048 flop each) on the null stream,
+ * timed with HIP events after one untimed launch.  *tflops (host) receives
+ * the rate.  Allocates and frees a small device buffer; synchronises. */
+rheed_status rheed_mfma_f64_peak(int32_t blocks, int32_t iters, double* tflops);
+
 const char* rheed_status_string(rheed_status s);
 const char* rheed_last_error(void);
 

@@ -79,6 +79,7 @@ SYMBOLS = {
     "rheed_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                         C.c_void_p], C.c_int),
     "rheed_rfactor": ([C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "rheed_mfma_f64_peak": ([C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "rheed_status_string": ([C.c_int], C.c_char_p),
     "rheed_last_error": ([], C.c_char_p),
 }

@@ -163,6 +163,43 @@ def rfactor(intensity: torch.Tensor, target: torch.Tensor):
     return loss, dI
 
 
+class _Intensity(torch.autograd.Function):
+    """Intensities of every pair as a differentiable function of the atom
+    coordinates: tables (rheed_potential) -> propagation (rheed_forward) on
+    the way forward; rheed_backward -> rheed_potential_backward on the way
+    back.  The forward keeps the workspace only when a gradient is needed."""
+
+    @staticmethod
+    def forward(ctx, atoms, plan, angles):
+        U = plan.potential(atoms)
+        ws = plan.workspace(atoms.device) if ctx.needs_input_grad[0] else None
+        out = plan.forward(U, angles, workspace=ws)
+        ctx.plan = plan
+        if ws is not None:
+            ctx.save_for_backward(atoms, U, angles, ws)
+        ctx.mark_non_differentiable(out["status"])
+        return out["intensity"], out["status"]
+
+    @staticmethod
+    def backward(ctx, dI, _dstatus):
+        atoms, U, angles, ws = ctx.saved_tensors
+        dU = ctx.plan.backward(U, angles, dI.contiguous(), ws)
+        return ctx.plan.potential_backward(atoms, dU), None, None
+
+
+def intensity(plan: Plan, atoms: torch.Tensor, angles: torch.Tensor):
+    """(intensity [n_pairs][max_beams], pair status [n_pairs]) with autograd
+    support: a loss built from the intensities back-propagates to `atoms`."""
+    return _Intensity.apply(atoms, plan, angles)
+
+
+def mfma_f64_peak(blocks: int = 1024, iters: int = 4000) -> float:
+    """Measured FP64 matrix-core TFLOP/s of the current device."""
+    out = C.c_double()
+    _lib.check(_lib.lib().rheed_mfma_f64_peak(int(blocks), int(iters), C.byref(out)), "mfma_f64_peak")
+    return out.value
+
+
 # ----------------------------------------------------------------- helpers
 def plan_for(workload, stepper: Optional[str] = None, **kw) -> Plan:
     """Plan over every structure of a workload, each with all its angles."""

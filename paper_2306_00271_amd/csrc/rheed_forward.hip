@@ -863,6 +863,25 @@ __device__ __forceinline__ void load_table_nodes(double2 (*tb)[MAXBOX + 1], cons
   }
 }
 
+// Starts direct-to-LDS copies of nodes [n0, n1) of a structure's table into
+// their ring slots: the (node, 64-entry chunk) pairs are dealt out over the
+// SW waves, each chunk one 16-byte load per lane written at slot + 64 c + lane.
+// The copies complete asynchronously; a wait for the vector memory counter
+// followed by a workgroup barrier makes them visible.
+template <int SLOTS>
+__device__ __forceinline__ void prefetch_table_nodes(double2 (*tb)[MAXBOX + 1], const double2* __restrict__ Us,
+                                                     int box, int n0, int n1, int w, int lane) {
+  const int chunks = (box + 63) >> 6;
+  const int total = (n1 - n0) * chunks;
+  for (int t = __builtin_amdgcn_readfirstlane(w); t < total; t += SW) {
+    const int q = t / chunks, c = t - q * chunks;
+    const int nn = n0 + q;
+    if (64 * c + lane < box)
+      __builtin_amdgcn_global_load_lds((const void*)(Us + (long long)nn * box + 64 * c + lane),
+                                       (__attribute__((address_space(3))) void*)(tb[nn % SLOTS] + 64 * c), 16, 0, 0);
+  }
+}
+
 template <int STEPPER>
 __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
   using T = Tab<STEPPER>;
@@ -951,7 +970,8 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
     }
   };
 
-  load_table_nodes<T::slots, ST>(s.tb, Us, S.box, 0, 1, tid);
+  load_table_nodes<T::slots, ST>(s.tb, Us, S.box, 0, T::nodes + 1, tid);
+  __syncthreads();
   for (int i = 0; i < L; ++i) {
     asm volatile("" : "+v"(ob));
     if (save && (i % a.ck.every) == 0) {
@@ -964,8 +984,10 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
       }
     }
     const int nb = i * T::nodes;
-    load_table_nodes<T::slots, ST>(s.tb, Us, S.box, nb + 1, nb + T::nodes + 1, tid);
     d = rk_slice<STEPPER, HC>(cb, xb, &s.tb[0][0], nb, gx, gg, ob, lane, 0, h, d);
+    // the next slice's new nodes go to the ring slots of this slice's first
+    // nodes, which the last stage (node nb + nodes only) no longer reads
+    if (i + 1 < L) prefetch_table_nodes<T::slots>(s.tb, Us, S.box, nb + T::nodes + 1, nb + 2 * T::nodes + 1, w, lane);
 
     // badness (Sec. 3.2): this half's row sums, then both halves' in half order
     {
@@ -1062,6 +1084,7 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
         cb[own<HC>(ob, e)] = make_double2((row == col) ? 1.0 : 0.0, 0.0);
       }
     }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // table copies of the next slice
     __syncthreads();
   }
 

@@ -19,7 +19,7 @@ def test_library_exports_every_declared_symbol():
     lib = _lib()
     so = lib.load()
     header = open(os.path.join(ROOT, "include", "rheed.h")).read()
-    names = set(re.findall(r"\b(rheed_[a-z_]+)\s*\(", header))
+    names = set(re.findall(r"\b(rheed_[a-z0-9_]+)\s*\(", header))
     assert names, "no declarations found"
     for n in sorted(names):
         assert hasattr(so, n), n

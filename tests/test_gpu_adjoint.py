@@ -132,3 +132,33 @@ def test_gradient_workload_full_size():
     got = float(np.sum(res_sub["datoms"] * d))
     print(f"[adjoint] full size (3 angles) direction: gpu {got:.12e} oracle {dl:.12e}", flush=True)
     assert got == pytest.approx(dl, rel=1e-8)
+
+
+def test_autograd_wrapper_matches_explicit_adjoint():
+    """api.intensity under torch.autograd gives the same loss and atom
+    gradient as the explicit rfactor -> backward -> potential_backward path."""
+    import torch
+    from paper_2306_00271_amd import api
+    wl = small_2d(n_beams=21, n_slices=40, thickness=4.0, n_layers=1, n_angles=3)
+    tgt = _target(3)
+    res = _run(wl, "rk6", tgt)
+    dev = torch.device("cuda:0")
+    plan = res["plan"]
+    atoms = api.atoms_for(wl, dev).requires_grad_(True)
+    inten, status = api.intensity(plan, atoms, api.angles_for(wl, dev))
+    t = torch.from_numpy(tgt).to(dev)
+    loss = ((inten[:, 0] - t) ** 2).sum()
+    loss.backward()
+    assert (status.cpu().numpy() == 0).all()
+    np.testing.assert_allclose(loss.item(), res["loss"], rtol=1e-13)
+    np.testing.assert_allclose(atoms.grad.cpu().numpy(), res["datoms"], rtol=1e-12, atol=1e-15)
+    # without a gradient the wrapper keeps no workspace and returns the same intensities
+    with torch.no_grad():
+        inten2, _ = api.intensity(plan, atoms.detach(), api.angles_for(wl, dev))
+    np.testing.assert_array_equal(inten2.cpu().numpy(), res["eta"])
+
+
+def test_mfma_peak_probe():
+    from paper_2306_00271_amd import api
+    tf = api.mfma_f64_peak(blocks=256, iters=500)
+    assert 5.0 < tf < 200.0
