@@ -1061,12 +1061,22 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
       xch_publish(cnt_me, ev);
       xch_wait(cnt_other, ev, &s.sync_fail);
       {
+        // all of the partner's entries in flight at once, then into LDS
         const double2* theirs = big_g + (long long)((1 - half) * 2 + (int)(ev & 1)) * 2 * NP * HC;
         double2* pot = s.cx + (1 - half) * NP * HC;
-        for (int idx = tid; idx < NP * HC; idx += ST) {
+        constexpr int PER = NP * HC / ST;
+        double2 qv[PER], pv[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          qv[q] = xget2(&theirs[tid + q * ST]);
+          pv[q] = xget2(&theirs[NP * HC + tid + q * ST]);
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int idx = tid + q * ST;
           const int r = idx / HC, c = idx - r * HC;
-          s.ext[r * NP + HC * (1 - half) + c] = xget2(&theirs[idx]);
-          pot[idx] = xget2(&theirs[NP * HC + idx]);
+          s.ext[r * NP + HC * (1 - half) + c] = qv[q];
+          pot[idx] = pv[q];
         }
       }
       __syncthreads();
