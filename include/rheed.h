@@ -101,7 +101,9 @@ typedef enum { RHEED_LAYOUT_AUTO = 0, RHEED_LAYOUT_WHOLE = 1, RHEED_LAYOUT_SPLIT
 typedef struct {
   rheed_stepper stepper;
   double rhst_threshold;     /* RHST when the condition estimate exceeds it; the paper uses 1000 */
-  int32_t checkpoint_every;  /* slices between states saved for rheed_backward (>= 1) */
+  int32_t checkpoint_every;  /* slices between states rheed_forward keeps for rheed_backward (>= 1);
+                                with K > 1 the adjoint replays each K-slice segment from its
+                                stored state (needs cooperative launches on the device) */
   rheed_convention convention;
   rheed_layout layout;       /* SPLIT when the batch does not fit -> RHEED_E_UNSUPPORTED at plan creation */
 } rheed_opts;
@@ -181,7 +183,14 @@ rheed_status rheed_forward(rheed_plan_t plan, const void* U_tables, const double
  * real loss L, accumulates dL/dU over all angles of each structure.
  * Must follow rheed_forward on the same stream with the same plan, inputs and
  * workspace.  dL_dI: device [n_pairs][max_beams]; dL_dU: device complex
- * [table_elems], overwritten; workspace >= fwd_workspace + bwd_workspace. */
+ * [table_elems], overwritten; workspace >= fwd_workspace + bwd_workspace.
+ * With checkpoint_every = K > 1 the forward keeps the state at every K-th
+ * slice together with each transformation's Q^{-1} and decision byte; this
+ * call walks the K-slice segments from the top down, first recomputing a
+ * segment's states from its stored state (the stored Q^{-1} applied where the
+ * forward applied it, so the states are the forward's bit for bit), then
+ * running the adjoint over the segment.  The replay uses the plan's exchange
+ * blocks, so calls on one plan must not overlap (issue them on one stream). */
 rheed_status rheed_backward(rheed_plan_t plan, const void* U_tables, const double* angles,
                             const double* dL_dI, void* dL_dU, void* workspace, size_t ws_bytes,
                             void* stream);

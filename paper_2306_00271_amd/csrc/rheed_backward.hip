@@ -157,8 +157,14 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
   const int box = S.box;
   const double h = S.h;
   const double2* __restrict__ Us = a.U + S.table_off;
+  // slices of this launch: all of them, or one checkpoint segment
+  const int lo = a.seg ? a.i0 : 0;
+  const int hi = a.seg ? (a.i1 < L ? a.i1 : L) : L;
+  if (lo >= hi) return;
+  const bool top = hi == L;  // holds the last slice: starts from the reflection
   const char* pws = a.ws + (long long)p * a.ck.pair_stride;
   const char* flags = pws + a.ck.flags_off;
+  const char* segp = a.seg ? a.seg + (long long)p * a.seg_stride : nullptr;
   double2* __restrict__ gb = a.gbuf + (long long)p * a.g_pair_stride;
 
   if (tid < NP) {
@@ -194,9 +200,9 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
       ixh[q] = in ? bk - oj : box;
     }
   }
-  // node tables of slice L - 1
+  // node tables of slice hi - 1
   for (int e = tid; e < (NPS + 1) * box; e += BT) {
-    const int nn = (L - 1) * NPS + e / box;
+    const int nn = (hi - 1) * NPS + e / box;
     s.tb[nn % RING][e % box] = Us[(long long)nn * box + e % box];
   }
   __syncthreads();
@@ -204,8 +210,20 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
 
   // ---- final step: x = B^{-1} e_1 (B^{-1} by elimination), rho = A x
   const double2* zL = reinterpret_cast<const double2*>(pws + (long long)(a.ck.max_ckpt - 1) * a.ck.state_bytes);
+  // the state at the start of slice i: replayed segment, stored state or final state
+  auto state_at = [&](int i) -> const double2* {
+    if (segp && i >= lo && i < hi) return reinterpret_cast<const double2*>(segp + (long long)(i - lo) * a.ck.state_bytes);
+    if (i == L) return zL;
+    return reinterpret_cast<const double2*>(pws + (long long)(i / a.ck.every) * a.ck.state_bytes);
+  };
   double2 yc, yd;  // cotangent of row j of the current state
-  {
+  if (!top) {      // handed over by the launch of the segment above
+    const double2* cr = a.carry + (long long)p * 3 * NP;
+    yc = cr[j];
+    yd = cr[NP + j];
+    if (tid < NP) s.x[tid] = cr[2 * NP + tid];
+    __syncthreads();
+  } else {
     double2 z[16];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
@@ -305,7 +323,7 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
   };
   auto load_cross = [&](int i, CrossLoads& c) {
     c.flag = flags[i - 1];
-    const double2* zi = reinterpret_cast<const double2*>(pws + (long long)(i - 1) * a.ck.state_bytes);
+    const double2* zi = state_at(i - 1);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       c.zc[q] = zi[j * NP + 8 * part + q];
@@ -315,8 +333,7 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
   auto cross = [&](int i, const CrossLoads& c) {
     if (c.flag) {
       // y_c = -R^H y_d with [I; R] the stored state i, and x = T_{i-1} x
-      const double2* R =
-          (i == L ? zL : reinterpret_cast<const double2*>(pws + (long long)i * a.ck.state_bytes)) + NP * NP;
+      const double2* R = state_at(i) + NP * NP;
       const double2* Tm =
           reinterpret_cast<const double2*>(pws + a.ck.q_off + (long long)(i - 1) * NP * NP * sizeof(double2));
       double2 rh[8], tm[8];
@@ -352,16 +369,16 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
   };
   {
     CrossLoads c0;
-    load_cross(L, c0);
-    cross(L, c0);
+    load_cross(hi, c0);
+    cross(hi, c0);
   }
 
-  for (int i = L - 1; i >= 0; --i) {
+  for (int i = hi - 1; i >= lo; --i) {
     const int nb = i * NPS;
     // loads for slice i - 1: its new node tables and what crossing into it needs
     double2 pf[3];
     CrossLoads cl;
-    if (i > 0) {
+    if (i > lo) {
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         const int e = tid + BT * t;
@@ -419,7 +436,7 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
       yc = cadd(yc, Ybc[r]);
       yd = cadd(yd, Ybd[r]);
     }
-    if (i > 0) {
+    if (i > lo) {
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         const int e = tid + BT * t;
@@ -431,6 +448,14 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
       cross(i, cl);
     }
     __syncthreads();
+  }
+  if (lo > 0) {  // the crossing into slice lo - 1 belongs to the launch of the segment below
+    double2* cr = a.carry + (long long)p * 3 * NP;
+    if (part == 0) {
+      cr[j] = yc;
+      cr[NP + j] = yd;
+    }
+    if (tid < NP) cr[2 * NP + tid] = s.x[tid];
   }
 }
 
