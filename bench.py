@@ -3,10 +3,12 @@
 One step = one pass of the whole hot path over the gradient workload
 (15 keV electrons, N = 61 rods of a 3x3 supercell, 9 atoms x 10 layers,
 40 A in 400 slices, 128 glancing angles 0.3..6.0 deg, 6th-order RK):
-potential tables from atoms -> forward propagation with RHST and reflection
--> R-factor against a target curve -> adjoint propagation -> gradient with
-respect to atom coordinates.  Inputs are seeded synthetic slabs, resident in
-HBM before the timed region.  Prints one JSON line.
+potential tables from atoms -> forward propagation with RHST and reflection,
+keeping the state every 20 slices -> R-factor against a target curve ->
+adjoint propagation, segment by segment, each segment's states recomputed
+from its checkpoint -> gradient with respect to atom coordinates.  Inputs
+are seeded synthetic slabs, resident in HBM before the timed region.  Prints
+one JSON line; "variants" adds the same step with every slice state kept.
 
 ``--mode fwd`` times the forward pass alone (potential + propagation).
 ``--traffic-probe`` runs one forward launch and a 1 GiB device copy for the
@@ -26,6 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 MFMA_FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 matrix, published
+CHECKPOINT_EVERY = 20           # the gradient workload keeps the state every 20 slices
 
 
 def kernel_name(split):
@@ -117,7 +120,7 @@ def traffic_from_profile(split):
         return None
 
 
-def traffic_probe():
+def traffic_probe(checkpoint_every):
     """One forward launch of the timed workload (with the adjoint's state
     saving) and one device copy of 1 GiB, for FETCH_SIZE / WRITE_SIZE counter
     runs; prints the copy size so the counters can be calibrated."""
@@ -126,7 +129,7 @@ def traffic_probe():
     from synth import config4
     dev = torch.device("cuda:0")
     wl = config4(1)
-    plan = api.plan_for(wl, stepper="rk6")
+    plan = api.plan_for(wl, stepper="rk6", checkpoint_every=checkpoint_every)
     angles = api.angles_for(wl, dev)
     U = plan.potential(api.atoms_for(wl, dev))
     ws = plan.workspace(dev)
@@ -136,7 +139,7 @@ def traffic_probe():
     dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": src.numel() * 8, "source_sha256": kernel_source_hash(),
-                      "kernel": kernel_name(plan.split)}))
+                      "kernel": kernel_name(plan.split), "checkpoint_every": checkpoint_every}))
 
 
 # -------------------------------------------------------------------- bench
@@ -148,6 +151,8 @@ def main():
     ap.add_argument("--mode", choices=["fwd", "fwd+adj"], default="fwd+adj")
     ap.add_argument("--structures", type=int, default=1, help="structures in the batch (128 angles each)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--checkpoint-every", type=int, default=CHECKPOINT_EVERY,
+                    help="slices between states kept for the adjoint (the gradient workload keeps every 20th)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run one forward launch and a 1 GiB copy for HBM counter runs, then exit")
     args = ap.parse_args()
@@ -156,7 +161,7 @@ def main():
               "pairs are independent and would shard across GPUs (see DESIGN.md).", file=sys.stderr)
         sys.exit(2)
     if args.traffic_probe:
-        traffic_probe()
+        traffic_probe(args.checkpoint_every)
         return
 
     import numpy as np
@@ -167,7 +172,6 @@ def main():
     dev = torch.device("cuda:0")
     wl = config4(args.structures)
     stepper = "rk6"
-    plan = api.plan_for(wl, stepper=stepper)
     tplan = api.plan_for(dataclasses_replace(wl, wl.target), stepper=stepper)
     angles = api.angles_for(wl, dev)
     atoms = api.atoms_for(wl, dev)
@@ -175,44 +179,51 @@ def main():
     # target curve (setup, not timed): specular intensities of the perturbed slabs
     tU = tplan.potential(tatoms)
     target = tplan.forward(tU, angles)["intensity"][:, 0].contiguous()
+    del tplan, tU
     do_adj = args.mode == "fwd+adj"
-    ws = plan.workspace(dev) if do_adj else None
     stream = torch.cuda.current_stream()
-    fwd_events = []
 
-    def step(record):
-        U = plan.potential(atoms)
-        if record:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-        out = plan.forward(U, angles, workspace=ws, want_nrhst=True)
-        if record:
-            e1.record(stream)
-            fwd_events.append((e0, e1))
-        if do_adj:
-            loss, dI = api.rfactor(out["intensity"], target)
-            dU = plan.backward(U, angles, dI, ws)
-            grad = plan.potential_backward(atoms, dU)
-            return out, grad
-        return out, None
+    def measure(every):
+        """(plan, ms per step, forward event pairs, last forward output, wall s)"""
+        plan = api.plan_for(wl, stepper=stepper, checkpoint_every=every)
+        ws = plan.workspace(dev) if do_adj else None
+        fwd_events = []
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record(stream)
-    wall0 = time.perf_counter()
-    for _ in range(args.steps):
-        out, grad = step(True)
-    t1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = t0.elapsed_time(t1) / args.steps
+        def step(record):
+            U = plan.potential(atoms)
+            if record:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            out = plan.forward(U, angles, workspace=ws, want_nrhst=True)
+            if record:
+                e1.record(stream)
+                fwd_events.append((e0, e1))
+            if do_adj:
+                loss, dI = api.rfactor(out["intensity"], target)
+                dU = plan.backward(U, angles, dI, ws)
+                plan.potential_backward(atoms, dU)
+            return out
+
+        for _ in range(args.warmup):
+            step(False)
+        torch.cuda.synchronize()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        wall0 = time.perf_counter()
+        for _ in range(args.steps):
+            out = step(True)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        return plan, t0.elapsed_time(t1) / args.steps, fwd_events, out, wall
+
+    every = args.checkpoint_every if do_adj else 1
+    plan, ms, fwd_events, out, wall = measure(every)
     n_pairs = plan.n_pairs
+    split = plan.split
     value = n_pairs / (ms / 1e3)
-
     status = out["status"].cpu().numpy()
     nrhst = int(out["n_rhst"].sum().item())
     N = int(wl.structures[0].n_beams)
@@ -222,13 +233,13 @@ def main():
     fl = _flops_forward(N, L, stages, nrhst, n_pairs)
     achieved = fl / (fwd_ms / 1e3) / 1e12
     # counters were taken on the single-structure launch with state saving
-    traffic = traffic_from_profile(plan.split) if (do_adj and args.structures == 1) else None
+    traffic = traffic_from_profile(split) if (do_adj and args.structures == 1 and every == CHECKPOINT_EVERY) else None
     # the published peak is the reference; the probe gives the rate this device
     # actually reaches with register-resident operands
     measured_peak = api.mfma_f64_peak()
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": MFMA_FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / MFMA_FP64_PEAK_TFLOPS, 4), "traffic": traffic,
-                "kernel": kernel_name(plan.split), "kernel_ms": round(fwd_ms, 4), "flops_per_launch": fl,
+                "kernel": kernel_name(split), "kernel_ms": round(fwd_ms, 4), "flops_per_launch": fl,
                 "measured_peak": round(measured_peak, 2), "frac_of_measured": round(achieved / measured_peak, 4)}
 
     cpu = None
@@ -248,6 +259,12 @@ def main():
                       f"{cwall:.1f} s wall")
         cpu = {"value": round(rate, 5), "unit": "points/s", "cores": cores, "kind": "oracle", "sample": sample}
 
+    variants = None
+    if do_adj and every != 1:
+        del plan
+        _, ms1, _, _, _ = measure(1)
+        variants = {"checkpoint_every_1": {"value": round(n_pairs / (ms1 / 1e3), 3), "ms_per_step": round(ms1, 4)}}
+
     rec = {
         "metric": "rocking-curve points (structure x angle)/s at N=61 FP64; " +
                   ("fwd+adjoint" if do_adj else "forward only"),
@@ -264,10 +281,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name + ("" if do_adj else "-forward"), "structures": len(wl.structures),
                    "angles": len(wl.theta0), "n_beams": N, "slices": L, "stepper": stepper,
-                   "pairs": n_pairs, "layout": "split" if plan.split else "whole", "rhst_per_pair": round(nrhst / n_pairs, 2),
+                   "pairs": n_pairs, "layout": "split" if split else "whole",
+                   "checkpoint_every": every if do_adj else None, "rhst_per_pair": round(nrhst / n_pairs, 2),
                    "bad_pairs": int((status != 0).sum()), "wall_s": round(wall, 3)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "variants": variants,
     }
     print(json.dumps(rec))
 

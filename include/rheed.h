@@ -101,9 +101,7 @@ typedef enum { RHEED_LAYOUT_AUTO = 0, RHEED_LAYOUT_WHOLE = 1, RHEED_LAYOUT_SPLIT
 typedef struct {
   rheed_stepper stepper;
   double rhst_threshold;     /* RHST when the condition estimate exceeds it; the paper uses 1000 */
-  int32_t checkpoint_every;  /* slices between states rheed_forward keeps for rheed_backward (>= 1);
-                                with K > 1 the adjoint replays each K-slice segment from its
-                                stored state (needs cooperative launches on the device) */
+  int32_t checkpoint_every;  /* slices between states rheed_forward keeps for rheed_backward (>= 1) */
   rheed_convention convention;
   rheed_layout layout;       /* SPLIT when the batch does not fit -> RHEED_E_UNSUPPORTED at plan creation */
 } rheed_opts;
@@ -184,13 +182,14 @@ rheed_status rheed_forward(rheed_plan_t plan, const void* U_tables, const double
  * Must follow rheed_forward on the same stream with the same plan, inputs and
  * workspace.  dL_dI: device [n_pairs][max_beams]; dL_dU: device complex
  * [table_elems], overwritten; workspace >= fwd_workspace + bwd_workspace.
- * With checkpoint_every = K > 1 the forward keeps the state at every K-th
- * slice together with each transformation's Q^{-1} and decision byte; this
- * call walks the K-slice segments from the top down, first recomputing a
- * segment's states from its stored state (the stored Q^{-1} applied where the
- * forward applied it, so the states are the forward's bit for bit), then
- * running the adjoint over the segment.  The replay uses the plan's exchange
- * blocks, so calls on one plan must not overlap (issue them on one stream). */
+ * rheed_forward keeps the state at the start of every K-th slice
+ * (K = checkpoint_every) and the final state, Q^{-1} and a decision byte for
+ * every transformation, and for K > 1 also the normalised P after it.  The
+ * adjoint walks K-slice segments from the top: the physical column psi = Z x
+ * of a segment is formed from its stored state and stepped up through the
+ * segment by the RK step itself, then the adjoint walks back down.  The
+ * adjoint does the same products for every K; a larger K keeps fewer states
+ * (fwd_workspace) at the price of the R slots. */
 rheed_status rheed_backward(rheed_plan_t plan, const void* U_tables, const double* angles,
                             const double* dL_dI, void* dL_dU, void* workspace, size_t ws_bytes,
                             void* stream);

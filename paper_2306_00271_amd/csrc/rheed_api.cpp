@@ -57,13 +57,7 @@ struct rheed_plan_s {
   unsigned long long epoch = 0;  // split launches so far (tags the exchange counters)
   long long g_pair_stride = 0;  // adjoint stage buffer elements per pair
   int max_nodes = 0;
-  int max_l = 0;
-  // checkpoint segments (checkpoint_every > 1): replayed states and the
-  // hand-over between segment launches, inside the adjoint's workspace
-  long long seg_stride = 0;     // bytes of replayed states per pair
-  size_t seg_off = 0, carry_off = 0;
-  int replay_chunk = 0;         // pairs per replay launch
-  int xch_pairs = 0;            // exchange blocks allocated
+  size_t xs_off = 0;            // adjoint workspace: x of a segment's transformed states
 };
 
 extern "C" {
@@ -227,47 +221,37 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
   }
   P->table_off.push_back(P->table_elems);
   P->atom_off.push_back(P->n_atoms_total);
-  // per-pair checkpoint block: states at the start of every segment + one byte per slice
+  // per-pair checkpoint block: the state at the start of every segment and
+  // the final state, T = Q^{-1} of every transformation, with segments
+  // longer than one slice also R = P Q^{-1} (the normalised P) of every
+  // transformation, and one decision byte per slice
   P->ck.every = opts->checkpoint_every;
   P->ck.max_ckpt = (max_l + opts->checkpoint_every - 1) / opts->checkpoint_every + 1;
   P->ck.state_bytes = (long long)2 * NP * NP * sizeof(double2);
+  const long long slot_bytes = (long long)max_l * NP * NP * sizeof(double2);
   P->ck.q_off = P->ck.max_ckpt * P->ck.state_bytes;
-  P->ck.flags_off = P->ck.q_off + (long long)max_l * NP * NP * sizeof(double2);
+  P->ck.r_off = P->ck.every > 1 ? P->ck.q_off + slot_bytes : 0;
+  P->ck.flags_off = (P->ck.every > 1 ? P->ck.r_off : P->ck.q_off) + slot_bytes;
   P->ck.pair_stride = ((P->ck.flags_off + max_l + 255) / 256) * 256;
   P->fwd_ws = (size_t)P->ck.pair_stride * P->n_pairs;
   // adjoint stage buffer: (v_r, g_r) of every stage of every slice
-  P->max_l = max_l;
   P->g_pair_stride = (long long)max_l * (P->opts.stepper == RHEED_RK4 ? 4 : 7) * 2 * NP;
   P->bwd_ws = (size_t)P->g_pair_stride * sizeof(double2) * P->n_pairs;
-  if (P->ck.every > 1) {
-    // the states of one segment, replayed for the adjoint, and y_c, y_d, x per pair
-    P->seg_stride = (long long)P->ck.every * P->ck.state_bytes;
-    P->seg_off = ((P->bwd_ws + 255) / 256) * 256;
-    P->carry_off = P->seg_off + (size_t)P->seg_stride * P->n_pairs;
-    P->bwd_ws = P->carry_off + (size_t)3 * NP * sizeof(double2) * P->n_pairs;
+  if (P->ck.every > 1) {  // x at the transformed states of a segment
+    P->xs_off = P->bwd_ws;
+    P->bwd_ws += (size_t)P->ck.every * NP * sizeof(double2) * P->n_pairs;
   }
 
   // split layout: two workgroups per pair, both resident (cooperative launch)
   {
     int dev = 0;
-    const bool have_dev = hipGetDevice(&dev) == hipSuccess;
-    P->split_max = have_dev ? forward_split_max_pairs(dev) : 0;
+    P->split_max = hipGetDevice(&dev) == hipSuccess ? forward_split_max_pairs(dev) : 0;
     P->split = opts->layout != RHEED_LAYOUT_WHOLE && P->n_pairs <= P->split_max;
     if (opts->layout == RHEED_LAYOUT_SPLIT && !P->split) {
       const int mx = P->split_max;
       delete P;
       return fail(RHEED_E_UNSUPPORTED, "layout SPLIT holds at most " + std::to_string(mx) + " pairs on this device");
     }
-    if (P->ck.every > 1) {
-      const int rmax = have_dev ? replay_split_max_pairs(dev) : 0;
-      if (rmax < 1) {
-        delete P;
-        return fail(RHEED_E_UNSUPPORTED, "checkpoint_every > 1 replays segments with cooperative launches, "
-                                         "which this device does not offer");
-      }
-      P->replay_chunk = std::min(rmax, P->n_pairs);
-    }
-    P->xch_pairs = std::max(P->split ? P->n_pairs : 0, P->replay_chunk);
   }
 
   hipError_t e;
@@ -279,7 +263,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (e = hipMalloc(&P->d_bin_jk, sizeof(int) * P->bin_jk.size())) != hipSuccess ||
       (e = hipMalloc(&P->d_pbwd, sizeof(double) * 3 * PBWD_CHUNKS * std::max<long long>(1, P->n_atoms_total))) !=
           hipSuccess ||
-      (P->xch_pairs > 0 && (e = hipMalloc(&P->d_xch, (size_t)XCH_STRIDE * P->xch_pairs)) != hipSuccess)) {
+      (P->split && (e = hipMalloc(&P->d_xch, (size_t)XCH_STRIDE * P->n_pairs)) != hipSuccess)) {
     rheed_plan_destroy(P);
     return e == hipErrorOutOfMemory ? fail(RHEED_E_NOMEM, "plan_create: device allocation") : hip_fail(e, "hipMalloc");
   }
@@ -294,7 +278,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (!P->atom_struct.empty() &&
        (e = hipMemcpy(P->d_atom_struct, P->atom_struct.data(), sizeof(long long) * P->atom_struct.size(),
                       hipMemcpyHostToDevice)) != hipSuccess) ||
-      (P->xch_pairs > 0 && (e = hipMemset(P->d_xch, 0, (size_t)XCH_STRIDE * P->xch_pairs)) != hipSuccess) ||
+      (P->split && (e = hipMemset(P->d_xch, 0, (size_t)XCH_STRIDE * P->n_pairs)) != hipSuccess) ||
       (e = hipDeviceSynchronize()) != hipSuccess) {
     rheed_plan_destroy(P);
     return hip_fail(e, "hipMemcpy");
@@ -426,46 +410,16 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
   a.ck = P->ck;
   a.gbuf = reinterpret_cast<double2*>(static_cast<char*>(workspace) + P->fwd_ws);
   a.g_pair_stride = P->g_pair_stride;
+  if (P->ck.every > 1) {
+    a.xs = reinterpret_cast<double2*>(static_cast<char*>(workspace) + P->fwd_ws + P->xs_off);
+    a.xs_stride = (long long)P->ck.every * NP;
+  }
   a.ld = P->max_beams;
   a.convention = (int)P->opts.convention;
   a.n_pairs = P->n_pairs;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = hipSuccess;
-  if (P->ck.every == 1) {
-    e = launch_backward((int)P->opts.stepper, a, st);
-    if (e != hipSuccess) return hip_fail(e, "backward launch");
-  } else {
-    // segments from the top down: replay the segment's states from its stored
-    // state, then walk its slices backwards
-    char* wsb = static_cast<char*>(workspace) + P->fwd_ws;
-    ReplayArgs r{};
-    r.structs = P->d_structs;
-    r.pair_struct = P->d_pair_struct;
-    r.beams = P->d_beams;
-    r.U = a.U;
-    r.angles = angles;
-    r.ws = static_cast<const char*>(workspace);
-    r.ck = P->ck;
-    r.seg = wsb + P->seg_off;
-    r.seg_stride = P->seg_stride;
-    r.xch = P->d_xch;
-    a.seg = r.seg;
-    a.seg_stride = r.seg_stride;
-    a.carry = reinterpret_cast<double2*>(wsb + P->carry_off);
-    const int nseg = (P->max_l + P->ck.every - 1) / P->ck.every;
-    for (int sg = nseg - 1; sg >= 0; --sg) {
-      r.i0 = a.i0 = sg * P->ck.every;
-      r.i1 = a.i1 = r.i0 + P->ck.every;
-      for (int p0 = 0; p0 < P->n_pairs; p0 += P->replay_chunk) {
-        r.pair0 = p0;
-        r.epoch = ++P->epoch;
-        e = launch_replay_split((int)P->opts.stepper, r, std::min(P->replay_chunk, P->n_pairs - p0), st);
-        if (e != hipSuccess) return hip_fail(e, "segment replay launch");
-      }
-      e = launch_backward((int)P->opts.stepper, a, st);
-      if (e != hipSuccess) return hip_fail(e, "backward launch");
-    }
-  }
+  hipError_t e = launch_backward((int)P->opts.stepper, a, st);
+  if (e != hipSuccess) return hip_fail(e, "backward launch");
   // stages that use each node of a slice: node offsets of the stages in
   // {0, 1/2} (RK4) or {0, 1/3, 1/2, 2/3} (RK6); offset nps is the next slice's 0
   GradArgs g{};

@@ -17,10 +17,13 @@
 //     psi = Z x, and g_r = -K_bar_r^(c') the adjoint of that stage's product.
 // One workgroup per (structure, angle) pair therefore walks the slices
 // backwards with vectors only.  The forward pass keeps Z at the start of every
-// slice and T = Q^{-1} of every transformation; psi_i = Z_i x_i is formed from
-// them (the loads for slice i-1 are issued at the start of slice i), and each
-// stage costs one N x N matrix-vector product against the node's rod-
-// difference table in LDS.  Every stage writes (v_r, g_r) to a stage buffer;
+// K-th slice, T = Q^{-1} of every transformation and, for K > 1, R (the
+// normalised P after it).  Per K-slice segment, from the top: x is carried
+// down through the segment's transformations, psi = Z x is formed at the
+// segment's stored state and stepped up through the segment by the RK step
+// (psi = Z x is unchanged by Z <- Z T, x <- T^{-1} x), and the adjoint then
+// walks back down.  Each stage costs one N x N matrix-vector product against
+// the node's rod-difference table in LDS.  Every stage writes (v_r, g_r) to a stage buffer;
 // grad_assemble_kernel then sums g v^H over the angles and stages of each
 // node on the FP64 units and bins the sum by rod difference, in a fixed order.
 //
@@ -157,14 +160,8 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
   const int box = S.box;
   const double h = S.h;
   const double2* __restrict__ Us = a.U + S.table_off;
-  // slices of this launch: all of them, or one checkpoint segment
-  const int lo = a.seg ? a.i0 : 0;
-  const int hi = a.seg ? (a.i1 < L ? a.i1 : L) : L;
-  if (lo >= hi) return;
-  const bool top = hi == L;  // holds the last slice: starts from the reflection
   const char* pws = a.ws + (long long)p * a.ck.pair_stride;
   const char* flags = pws + a.ck.flags_off;
-  const char* segp = a.seg ? a.seg + (long long)p * a.seg_stride : nullptr;
   double2* __restrict__ gb = a.gbuf + (long long)p * a.g_pair_stride;
 
   if (tid < NP) {
@@ -200,30 +197,13 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
       ixh[q] = in ? bk - oj : box;
     }
   }
-  // node tables of slice hi - 1
-  for (int e = tid; e < (NPS + 1) * box; e += BT) {
-    const int nn = (hi - 1) * NPS + e / box;
-    s.tb[nn % RING][e % box] = Us[(long long)nn * box + e % box];
-  }
   __syncthreads();
   const double g2j = s.g2s[j];
 
   // ---- final step: x = B^{-1} e_1 (B^{-1} by elimination), rho = A x
   const double2* zL = reinterpret_cast<const double2*>(pws + (long long)(a.ck.max_ckpt - 1) * a.ck.state_bytes);
-  // the state at the start of slice i: replayed segment, stored state or final state
-  auto state_at = [&](int i) -> const double2* {
-    if (segp && i >= lo && i < hi) return reinterpret_cast<const double2*>(segp + (long long)(i - lo) * a.ck.state_bytes);
-    if (i == L) return zL;
-    return reinterpret_cast<const double2*>(pws + (long long)(i / a.ck.every) * a.ck.state_bytes);
-  };
   double2 yc, yd;  // cotangent of row j of the current state
-  if (!top) {      // handed over by the launch of the segment above
-    const double2* cr = a.carry + (long long)p * 3 * NP;
-    yc = cr[j];
-    yd = cr[NP + j];
-    if (tid < NP) s.x[tid] = cr[2 * NP + tid];
-    __syncthreads();
-  } else {
+  {
     double2 z[16];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
@@ -312,150 +292,192 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
     __syncthreads();
   }
 
-  // Crossing from the start of slice i back into slice i - 1: the
-  // transformation after slice i - 1 (if any), then psi_{i-1} = Z_{i-1} x.
-  double2 psic, psid;
-  // Loads for crossing into slice i - 1, issued a slice ahead: the flag of
-  // the transformation after slice i - 1 and Z_{i-1}.
-  struct CrossLoads {
-    double2 zc[8], zd[8];
-    int flag;
-  };
-  auto load_cross = [&](int i, CrossLoads& c) {
-    c.flag = flags[i - 1];
-    const double2* zi = state_at(i - 1);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      c.zc[q] = zi[j * NP + 8 * part + q];
-      c.zd[q] = zi[NP * NP + j * NP + 8 * part + q];
+  // Segments of K = ck.every slices, from the top down.  For a segment
+  // [lo, hi): (A) x moves down through the segment's transformations,
+  // x <- T_m x for every slice m whose decision byte is set; (B) psi_lo =
+  // Z_lo x_lo from the stored state, then psi goes up slice by slice with the
+  // RK step itself (psi_{i+1} = Phi_i psi_i: psi = Z x does not change under
+  // Z <- Z T, x <- T^{-1} x), the stage inputs v_r going to the stage buffer;
+  // (C) down again through the adjoint of every slice, preceded by the
+  // projection y_c = -R^H y_d wherever a transformation followed the slice,
+  // R the normalised P after it (stored state for K = 1, R slot otherwise).
+  const int K = a.ck.every;
+  auto load_tables = [&](int i) {  // nodes of slice i, in their ring slots
+    for (int e = tid; e < (NPS + 1) * box; e += BT) {
+      const int nn = i * NPS + e / box;
+      s.tb[nn % RING][e % box] = Us[(long long)nn * box + e % box];
     }
   };
-  auto cross = [&](int i, const CrossLoads& c) {
-    if (c.flag) {
-      // y_c = -R^H y_d with [I; R] the stored state i, and x = T_{i-1} x
-      const double2* R = state_at(i) + NP * NP;
-      const double2* Tm =
-          reinterpret_cast<const double2*>(pws + a.ck.q_off + (long long)(i - 1) * NP * NP * sizeof(double2));
-      double2 rh[8], tm[8];
+  for (int hi = L; hi > 0;) {
+    const int lo = ((hi - 1) / K) * K;
+    // (A) x down to the bottom of the segment; x at each transformed state
+    // inside the segment is kept for (B)
+    double2* xs = a.xs + (long long)p * a.xs_stride;
+    for (int m = hi - 1; m >= lo; --m) {
+      if (flags[m]) {
+        if (K > 1 && m + 1 < hi && tid < NP) xs[(m + 1 - lo) * NP + tid] = s.x[tid];
+        const double2* Tm = reinterpret_cast<const double2*>(pws + a.ck.q_off + (long long)m * NP * NP * sizeof(double2));
+        double2 tm[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) tm[q] = Tm[j * NP + 8 * part + q];
+        double2 xn = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) xn = cadd(xn, cmul(tm[q], s.x[8 * part + q]));
+        xn = row_sum(xn);
+        __syncthreads();
+        if (part == 0) s.x[j] = xn;
+        __syncthreads();
+      }
+    }
+    // (B) psi_lo = Z_lo x_lo, then up through the segment; at a state that a
+    // transformation left as [I; R], psi = [I; R] x is formed afresh, so the
+    // RK step carries psi only across well-conditioned stretches
+    double2 psic, psid;
+    {
+      const double2* z = reinterpret_cast<const double2*>(pws + (long long)(lo / K) * a.ck.state_bytes);
+      double2 ac = make_double2(0.0, 0.0), ad = make_double2(0.0, 0.0);
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        rh[q] = R[(8 * part + q) * NP + j];
-        tm[q] = Tm[j * NP + 8 * part + q];
+        const double2 xk = s.x[8 * part + q];
+        ac = cadd(ac, cmul(z[j * NP + 8 * part + q], xk));
+        ad = cadd(ad, cmul(z[NP * NP + j * NP + 8 * part + q], xk));
       }
-      if (part == 0) s.vin[0][j] = yd;
-      __syncthreads();
-      double2 t = make_double2(0.0, 0.0), xn = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        t = cadd(t, cmulc(rh[q], s.vin[0][8 * part + q]));
-        xn = cadd(xn, cmul(tm[q], s.x[8 * part + q]));
-      }
-      t = row_sum(t);
-      xn = row_sum(xn);
-      yc = make_double2(-t.x, -t.y);
-      __syncthreads();
-      if (part == 0) s.x[j] = xn;
-      __syncthreads();
+      psic = row_sum(ac);
+      psid = row_sum(ad);
     }
-    double2 ac = make_double2(0.0, 0.0), ad = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const double2 xk = s.x[8 * part + q];
-      ac = cadd(ac, cmul(c.zc[q], xk));
-      ad = cadd(ad, cmul(c.zd[q], xk));
-    }
-    psic = row_sum(ac);
-    psid = row_sum(ad);
-  };
-  {
-    CrossLoads c0;
-    load_cross(hi, c0);
-    cross(hi, c0);
-  }
-
-  for (int i = hi - 1; i >= lo; --i) {
-    const int nb = i * NPS;
-    // loads for slice i - 1: its new node tables and what crossing into it needs
-    double2 pf[3];
-    CrossLoads cl;
-    if (i > lo) {
-#pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        const int e = tid + BT * t;
-        if (e < NPS * box) pf[t] = Us[(long long)(nb - NPS) * box + e];
-      }
-      load_cross(i, cl);
-    }
-    // RK stages on psi: Y_r = psi + h sum_{m<r} a_rm K_m, K_r = (Y_r^(c'), -M_r Y_r^(c))
-    double2* gs = gb + (long long)i * NS * 2 * NP;
-    double2 Yd[NS], Kd[NS];
-#pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      double2 yr = psic, ydr = psid;
-#pragma unroll
-      for (int m = 0; m < r; ++m) {
-        if (T::a[r][m] != 0.0) {
-          yr = caxpy(h * T::a[r][m], Yd[m], yr);
-          ydr = caxpy(h * T::a[r][m], Kd[m], ydr);
-        }
-      }
-      Yd[r] = ydr;
-      if (part == 0) {
-        s.vin[r & 1][j] = yr;
-        gs[r * 2 * NP + j] = yr;  // v_r
-      }
-      __syncthreads();
-      const double2 mv = matvec_row<false>(s.tb[(nb + T::node[r]) % RING], s.vin[r & 1], ixf, part, j, g2j);
-      Kd[r] = make_double2(-mv.x, -mv.y);
-    }
-    // adjoint of the step, stages last to first
-    double2 Ybc[NS], Ybd[NS];
-#pragma unroll
-    for (int r = NS - 1; r >= 0; --r) {
-      double2 kc = make_double2(h * T::b[r] * yc.x, h * T::b[r] * yc.y);
-      double2 kd = make_double2(h * T::b[r] * yd.x, h * T::b[r] * yd.y);
-#pragma unroll
-      for (int m = r + 1; m < NS; ++m) {
-        if (T::a[m][r] != 0.0) {
-          kc = caxpy(h * T::a[m][r], Ybc[m], kc);
-          kd = caxpy(h * T::a[m][r], Ybd[m], kd);
-        }
-      }
-      Ybd[r] = kc;  // Y_bar^(c') = K_bar^(c)
-      const int buf = (r + 1) & 1;  // product number 2 NS - 1 - r of the slice: buffers keep alternating
-      if (part == 0) {
-        s.vin[buf][j] = kd;
-        gs[r * 2 * NP + NP + j] = make_double2(-kd.x, -kd.y);  // g_r = -K_bar^(c')
-      }
-      __syncthreads();
-      const double2 mv = matvec_row<true>(s.tb[(nb + T::node[r]) % RING], s.vin[buf], ixh, part, j, g2j);
-      Ybc[r] = make_double2(-mv.x, -mv.y);  // Y_bar^(c) = -M^H K_bar^(c')
-    }
-#pragma unroll
-    for (int r = 0; r < NS; ++r) {
-      yc = cadd(yc, Ybc[r]);
-      yd = cadd(yd, Ybd[r]);
-    }
-    if (i > lo) {
-#pragma unroll
-      for (int t = 0; t < 3; ++t) {
-        const int e = tid + BT * t;
-        if (e < NPS * box) {
-          const int q = e / box;
-          s.tb[(nb - NPS + q) % RING][e - q * box] = pf[t];
-        }
-      }
-      cross(i, cl);
-    }
+    load_tables(lo);
     __syncthreads();
-  }
-  if (lo > 0) {  // the crossing into slice lo - 1 belongs to the launch of the segment below
-    double2* cr = a.carry + (long long)p * 3 * NP;
-    if (part == 0) {
-      cr[j] = yc;
-      cr[NP + j] = yd;
+    for (int i = lo; i < hi; ++i) {
+      const int nb = i * NPS;
+      if (i > lo && flags[i - 1]) {
+        const double2* R = reinterpret_cast<const double2*>(pws + a.ck.r_off + (long long)(i - 1) * NP * NP * sizeof(double2));
+        const double2* xi = xs + (i - lo) * NP;
+        double2 ad = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) ad = cadd(ad, cmul(R[j * NP + 8 * part + q], xi[8 * part + q]));
+        psic = xi[j];
+        psid = row_sum(ad);
+      }
+      double2 pf[3];  // the next slice's new nodes, loaded during this one
+      if (i + 1 < hi) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const int e = tid + BT * t;
+          if (e < NPS * box) pf[t] = Us[(long long)(nb + NPS + 1) * box + e];
+        }
+      }
+      // RK stages on psi: Y_r = psi + h sum_{m<r} a_rm K_m, K_r = (Y_r^(c'), -M_r Y_r^(c))
+      double2* gs = gb + (long long)i * NS * 2 * NP;
+      double2 Yd[NS], Kd[NS];
+#pragma unroll
+      for (int r = 0; r < NS; ++r) {
+        double2 yr = psic, ydr = psid;
+#pragma unroll
+        for (int m = 0; m < r; ++m) {
+          if (T::a[r][m] != 0.0) {
+            yr = caxpy(h * T::a[r][m], Yd[m], yr);
+            ydr = caxpy(h * T::a[r][m], Kd[m], ydr);
+          }
+        }
+        Yd[r] = ydr;
+        if (part == 0) {
+          s.vin[r & 1][j] = yr;
+          gs[r * 2 * NP + j] = yr;  // v_r
+        }
+        __syncthreads();
+        const double2 mv = matvec_row<false>(s.tb[(nb + T::node[r]) % RING], s.vin[r & 1], ixf, part, j, g2j);
+        Kd[r] = make_double2(-mv.x, -mv.y);
+      }
+      if (i + 1 < hi) {
+#pragma unroll
+        for (int r = 0; r < NS; ++r) {
+          if (T::b[r] != 0.0) {
+            psic = caxpy(h * T::b[r], Yd[r], psic);
+            psid = caxpy(h * T::b[r], Kd[r], psid);
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const int e = tid + BT * t;
+          if (e < NPS * box) {
+            const int q = e / box;
+            s.tb[(nb + NPS + 1 + q) % RING][e - q * box] = pf[t];
+          }
+        }
+      }
     }
-    if (tid < NP) cr[2 * NP + tid] = s.x[tid];
+    // (C) down through the segment: projection, then the adjoint of the slice
+    for (int i = hi - 1; i >= lo; --i) {
+      const int nb = i * NPS;
+      double2 pf[3];  // the new nodes of slice i - 1
+      if (i > lo) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const int e = tid + BT * t;
+          if (e < NPS * box) pf[t] = Us[(long long)(nb - NPS) * box + e];
+        }
+      }
+      if (flags[i]) {
+        // y_c = -R^H y_d, R the normalised P after the transformation that followed slice i
+        const double2* R =
+            K == 1 ? (i + 1 == L ? zL : reinterpret_cast<const double2*>(pws + (long long)(i + 1) * a.ck.state_bytes)) +
+                         NP * NP
+                   : reinterpret_cast<const double2*>(pws + a.ck.r_off + (long long)i * NP * NP * sizeof(double2));
+        double2 rh[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) rh[q] = R[(8 * part + q) * NP + j];
+        __syncthreads();
+        if (part == 0) s.vin[0][j] = yd;
+        __syncthreads();
+        double2 t = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) t = cadd(t, cmulc(rh[q], s.vin[0][8 * part + q]));
+        t = row_sum(t);
+        yc = make_double2(-t.x, -t.y);
+        __syncthreads();
+      }
+      // adjoint of the step, stages last to first
+      double2* gs = gb + (long long)i * NS * 2 * NP;
+      double2 Ybc[NS], Ybd[NS];
+#pragma unroll
+      for (int r = NS - 1; r >= 0; --r) {
+        double2 kc = make_double2(h * T::b[r] * yc.x, h * T::b[r] * yc.y);
+        double2 kd = make_double2(h * T::b[r] * yd.x, h * T::b[r] * yd.y);
+#pragma unroll
+        for (int m = r + 1; m < NS; ++m) {
+          if (T::a[m][r] != 0.0) {
+            kc = caxpy(h * T::a[m][r], Ybc[m], kc);
+            kd = caxpy(h * T::a[m][r], Ybd[m], kd);
+          }
+        }
+        Ybd[r] = kc;  // Y_bar^(c') = K_bar^(c)
+        const int buf = (r + 1) & 1;  // the products alternate between the two input buffers
+        if (part == 0) {
+          s.vin[buf][j] = kd;
+          gs[r * 2 * NP + NP + j] = make_double2(-kd.x, -kd.y);  // g_r = -K_bar^(c')
+        }
+        __syncthreads();
+        const double2 mv = matvec_row<true>(s.tb[(nb + T::node[r]) % RING], s.vin[buf], ixh, part, j, g2j);
+        Ybc[r] = make_double2(-mv.x, -mv.y);  // Y_bar^(c) = -M^H K_bar^(c')
+      }
+#pragma unroll
+      for (int r = 0; r < NS; ++r) {
+        yc = cadd(yc, Ybc[r]);
+        yd = cadd(yd, Ybd[r]);
+      }
+      if (i > lo) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const int e = tid + BT * t;
+          if (e < NPS * box) {
+            const int q = e / box;
+            s.tb[(nb - NPS + q) % RING][e - q * box] = pf[t];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    hi = lo;
   }
 }
 

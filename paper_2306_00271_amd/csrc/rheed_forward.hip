@@ -490,6 +490,11 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
         d.r[e] = gr;
         d.i[e] = gi;
       });
+      if (save && a.ck.r_off) {  // R = P Q^{-1} for an adjoint that keeps states only every few slices
+        double2* rs = reinterpret_cast<double2*>(pws + a.ck.r_off + (long long)i * NP * NP * sizeof(double2));
+#pragma unroll
+        for (int e = 0; e < NE; ++e) rs[OWN(e)] = make_double2(d.r[e], d.i[e]);
+      }
       __syncthreads();
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
@@ -1087,6 +1092,14 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
         d.r[e] = gr;
         d.i[e] = gi;
       });
+      if (save && a.ck.r_off) {  // R = P Q^{-1} for an adjoint that keeps states only every few slices
+        double2* rs = reinterpret_cast<double2*>(pws + a.ck.r_off + (long long)i * NP * NP * sizeof(double2));
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+          const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), col = col0 + 16 * (e >> 2) + (lane & 15);
+          rs[row * NP + col] = make_double2(d.r[e], d.i[e]);
+        }
+      }
       __syncthreads();
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
@@ -1187,189 +1200,12 @@ hipError_t launch_forward(int stepper, const FwdArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// Replay of one checkpoint segment for the adjoint.  Pairs pair0 .. pair0 + n
-// recompute the states at the start of slices [i0, min(i1, L)) from the state
-// the forward stored at i0, in the split layout: the same stage schedule as
-// the forward, and after every slice whose decision byte is set the forward's
-// Q^{-1} (read back from its T slot) applied to P, with Q reset to I.  The
-// operations and their order are those of the forward, so the states come out
-// bit for bit equal to the ones it passed through.
-template <int STEPPER>
-__global__ __launch_bounds__(ST, 1) void replay_split_kernel(ReplayArgs a) {
-  using T = Tab<STEPPER>;
-  SplitLds& s = split_lds;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int w = tid >> 6;
-  const int RT = w;
-  const int pl = blockIdx.x >> 1, half = blockIdx.x & 1;
-  const int p = a.pair0 + pl;
-  const int col0 = HC * half;
-  const StructDev S = a.structs[a.pair_struct[p]];
-  const int N = S.n_beams;
-  const int L = S.n_slices;
-  const int i0 = a.i0, i1 = a.i1 < L ? a.i1 : L;
-  if (i0 >= i1) return;  // both halves of the pair leave together
-  const double h = S.h;
-  const double2* __restrict__ Us = a.U + S.table_off;
-  const char* pws = a.ws + (long long)p * a.ck.pair_stride;
-  char* seg = a.seg + (long long)p * a.seg_stride;
-
-  if (tid < NP) {
-    s.bhk[tid][0] = tid < N ? a.beams[2 * (S.beam_off + tid)] : 0;
-    s.bhk[tid][1] = tid < N ? a.beams[2 * (S.beam_off + tid) + 1] : 0;
-  }
-  if (tid == 0) s.sync_fail = 0;
-  if (tid < T::slots) s.tb[tid][S.box] = make_double2(0.0, 0.0);
-  __syncthreads();
-  const double th0 = a.angles[2 * p], th1 = a.angles[2 * p + 1];
-  if (tid < NP) {
-    const double b0x = S.gamma * cos(th0) * cos(th1);
-    const double b0y = S.gamma * cos(th0) * sin(th1);
-    double arg = 0.0;
-    if (tid < N) {
-      const double qx = b0x + s.bhk[tid][0] * S.recip[0] + s.bhk[tid][1] * S.recip[2];
-      const double qy = b0y + s.bhk[tid][0] * S.recip[1] + s.bhk[tid][1] * S.recip[3];
-      arg = S.gamma * S.gamma - (qx * qx + qy * qy);
-    }
-    s.g2s[tid] = arg;
-  }
-  __syncthreads();
-  G2 gg;
-#pragma unroll
-  for (int v = 0; v < 4; ++v) gg.v[v] = s.g2s[16 * RT + 4 * v + (lane >> 4)];
-  Gidx gx;
-  {
-    const int W = 2 * S.kd + 1;
-    const int iA = 16 * RT + (lane & 15);
-    const int baseA = (s.bhk[iA][0] + S.hd) * W + (s.bhk[iA][1] + S.kd);
-#pragma unroll
-    for (int q = 0; q < 16; q += 2) {
-      const int k0 = 4 * q + (lane >> 4), k1 = 4 * (q + 1) + (lane >> 4);
-      const unsigned u0 = (iA < N && k0 < N) ? baseA - (s.bhk[k0][0] * W + s.bhk[k0][1]) : S.box;
-      const unsigned u1 = (iA < N && k1 < N) ? baseA - (s.bhk[k1][0] * W + s.bhk[k1][1]) : S.box;
-      gx.v[q >> 1] = u0 | (u1 << 16);
-    }
-  }
-  double2* cb = s.cx;
-  double2* xb = s.cx + NP * HC;
-  int ob = (16 * RT + (lane >> 4)) * HC + (lane & 15);
-  Mat d;
-  {  // the stored state at i0 (a multiple of the checkpoint interval)
-    const double2* st = reinterpret_cast<const double2*>(pws + (long long)(i0 / a.ck.every) * a.ck.state_bytes);
-#pragma unroll
-    for (int e = 0; e < NE; ++e) {
-      const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), col = col0 + 16 * (e >> 2) + (lane & 15);
-      cb[own<HC>(ob, e)] = st[row * NP + col];
-      const double2 dv = st[NP * NP + row * NP + col];
-      d.r[e] = dv.x;
-      d.i[e] = dv.y;
-    }
-  }
-  char* X = a.xch + (long long)pl * XCH_STRIDE;
-  unsigned long long* cnt_me = reinterpret_cast<unsigned long long*>(X) + half;
-  unsigned long long* cnt_other = reinterpret_cast<unsigned long long*>(X) + (1 - half);
-  double2* big_g = reinterpret_cast<double2*>(X + XCH_BIG);
-  unsigned long long ev = a.epoch << 32;
-
-  load_table_nodes<T::slots, ST>(s.tb, Us, S.box, i0 * T::nodes, i0 * T::nodes + T::nodes + 1, tid);
-  __syncthreads();
-  for (int i = i0; i < i1; ++i) {
-    asm volatile("" : "+v"(ob));
-    {
-      double2* st = reinterpret_cast<double2*>(seg + (long long)(i - i0) * a.ck.state_bytes);
-#pragma unroll
-      for (int e = 0; e < NE; ++e) {
-        const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), col = col0 + 16 * (e >> 2) + (lane & 15);
-        st[row * NP + col] = cb[own<HC>(ob, e)];
-        st[NP * NP + row * NP + col] = make_double2(d.r[e], d.i[e]);
-      }
-    }
-    const int nb = i * T::nodes;
-    d = rk_slice<STEPPER, HC>(cb, xb, &s.tb[0][0], nb, gx, gg, ob, lane, 0, h, d);
-    if (i + 1 < i1) prefetch_table_nodes<T::slots>(s.tb, Us, S.box, nb + T::nodes + 1, nb + 2 * T::nodes + 1, w, lane);
-    if (pws[a.ck.flags_off + i]) {
-      // P <- P T_i: the partner's P columns through the exchange block, T_i from its slot
-      ++ev;
-      double2* mine = big_g + (long long)(half * 2 + (int)(ev & 1)) * 2 * NP * HC;
-#pragma unroll
-      for (int e = 0; e < NE; ++e) {
-        const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), cl = 16 * (e >> 2) + (lane & 15);
-        xput2(&mine[NP * HC + row * HC + cl], make_double2(d.r[e], d.i[e]));
-      }
-      // every wave is done with the last stage's input: P of this half goes to
-      // cx (c is reset below), T_i to ext
-      __syncthreads();
-      double2* pme = s.cx + half * NP * HC;
-#pragma unroll
-      for (int e = 0; e < NE; ++e) {
-        const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), cl = 16 * (e >> 2) + (lane & 15);
-        pme[row * HC + cl] = make_double2(d.r[e], d.i[e]);
-      }
-      {
-        const double2* tg =
-            reinterpret_cast<const double2*>(pws + a.ck.q_off + (long long)i * NP * NP * sizeof(double2));
-        constexpr int PT = NP * NP / ST;
-        double2 tv[PT];
-#pragma unroll
-        for (int q = 0; q < PT; ++q) tv[q] = tg[tid + q * ST];
-#pragma unroll
-        for (int q = 0; q < PT; ++q) s.ext[tid + q * ST] = tv[q];
-      }
-      xch_publish(cnt_me, ev);
-      xch_wait(cnt_other, ev, &s.sync_fail);
-      {
-        const double2* theirs = big_g + (long long)((1 - half) * 2 + (int)(ev & 1)) * 2 * NP * HC;
-        double2* pot = s.cx + (1 - half) * NP * HC;
-        constexpr int PER = NP * HC / ST;
-        double2 pv[PER];
-#pragma unroll
-        for (int q = 0; q < PER; ++q) pv[q] = xget2(&theirs[NP * HC + tid + q * ST]);
-#pragma unroll
-        for (int q = 0; q < PER; ++q) pot[tid + q * ST] = pv[q];
-      }
-      __syncthreads();
-      split_gemm(s.cx, s.ext, lane, RT, col0, [&](int e, double gr, double gi) {
-        d.r[e] = gr;
-        d.i[e] = gi;
-      });
-      __syncthreads();
-#pragma unroll
-      for (int e = 0; e < NE; ++e) {
-        const int row = 16 * RT + 4 * (e & 3) + (lane >> 4), col = col0 + 16 * (e >> 2) + (lane & 15);
-        cb[own<HC>(ob, e)] = make_double2((row == col) ? 1.0 : 0.0, 0.0);
-      }
-    }
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // table copies of the next slice
-    __syncthreads();
-  }
-}
-
 hipError_t launch_forward_split(int stepper, const FwdArgs& a, hipStream_t stream) {
   FwdArgs arg = a;
   void* params[] = {&arg};
   const void* f = stepper == 0 ? reinterpret_cast<const void*>(&forward_split_kernel<0>)
                                : reinterpret_cast<const void*>(&forward_split_kernel<1>);
   return hipLaunchCooperativeKernel(f, dim3(2 * a.n_pairs), dim3(ST), params, 0, stream);
-}
-
-hipError_t launch_replay_split(int stepper, const ReplayArgs& a, int n, hipStream_t stream) {
-  ReplayArgs arg = a;
-  void* params[] = {&arg};
-  const void* f = stepper == 0 ? reinterpret_cast<const void*>(&replay_split_kernel<0>)
-                               : reinterpret_cast<const void*>(&replay_split_kernel<1>);
-  return hipLaunchCooperativeKernel(f, dim3(2 * n), dim3(ST), params, 0, stream);
-}
-
-int replay_split_max_pairs(int device) {
-  int coop = 0, cus = 0, per_cu0 = 0, per_cu1 = 0;
-  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu0, replay_split_kernel<0>, ST, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu1, replay_split_kernel<1>, ST, 0) != hipSuccess)
-    return 0;
-  return cus * (per_cu0 < per_cu1 ? per_cu0 : per_cu1) / 2;
 }
 
 int forward_split_max_pairs(int device) {

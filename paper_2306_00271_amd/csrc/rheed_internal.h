@@ -31,6 +31,7 @@ struct CkptLayout {
   int every;               // slices between stored states (1: every slice)
   int max_ckpt;            // stored states per pair, including the final state
   long long q_off;         // byte offset of the T slots (one per slice)
+  long long r_off;         // byte offset of the R slots (one per slice) when every > 1, else 0
   long long flags_off;     // byte offset of the decision bytes
 };
 
@@ -54,26 +55,6 @@ struct FwdArgs {
   // split launches (two workgroups per pair): per-pair exchange blocks and the
   // launch number that tags their counters
   char* xch;
-  unsigned long long epoch;
-};
-
-// Recomputation of one checkpoint segment for the adjoint: the states at the
-// start of slices [i0, min(i1, L)) of pairs [pair0, pair0 + n), replayed from
-// the state stored at i0 with the stored transformations (split layout).
-struct ReplayArgs {
-  const StructDev* structs;
-  const int* pair_struct;
-  const int* beams;
-  const double2* U;
-  const double* angles;
-  const char* ws;            // forward workspace: stored states, T slots, decision bytes
-  CkptLayout ck;
-  char* seg;                 // replayed states: per pair [ck.every][2 NP NP] complex
-  long long seg_stride;      // bytes per pair
-  int i0, i1;
-  int pair0;
-  int pad;
-  char* xch;                 // exchange blocks, one per pair of the launch
   unsigned long long epoch;
 };
 
@@ -117,17 +98,12 @@ struct BwdArgs {
   CkptLayout ck;
   double2* gbuf;             // stage buffer: per pair [slice][stage][v | g][NP]
   long long g_pair_stride;   // elements per pair
+  double2* xs;               // ck.every > 1: per pair [ck.every][NP], x of the segment's transformed states
+  long long xs_stride;       // elements per pair
   int ld;
   int convention;
   int n_pairs;
   int pad;
-  // checkpoint segments (ck.every > 1): this launch walks slices [i0, i1)
-  // with their states in seg (replayed) and hands y_c, y_d and x to the
-  // launch of the segment below through carry
-  const char* seg;           // null: every slice state is in ws
-  long long seg_stride;      // bytes per pair
-  double2* carry;            // per pair [3][NP]
-  int i0, i1;
 };
 
 // Stages that use node n = i * nps + res: (slice i + contrib_di, stage contrib_r).
@@ -148,8 +124,6 @@ struct GradArgs {
 hipError_t launch_forward(int stepper, const FwdArgs& a, hipStream_t stream);
 hipError_t launch_forward_split(int stepper, const FwdArgs& a, hipStream_t stream);
 int forward_split_max_pairs(int device);  // pairs a split launch can hold at once (0: not available)
-hipError_t launch_replay_split(int stepper, const ReplayArgs& a, int n, hipStream_t stream);
-int replay_split_max_pairs(int device);
 hipError_t launch_backward(int stepper, const BwdArgs& a, hipStream_t stream);
 hipError_t launch_grad_assemble(const GradArgs& a, int n_struct, int max_nodes, hipStream_t stream);
 hipError_t launch_potential(const PotArgs& a, long long max_elems, hipStream_t stream);

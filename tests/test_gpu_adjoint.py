@@ -11,11 +11,11 @@ from synth import config4, small_2d, small_row
 pytestmark = pytest.mark.gpu
 
 
-def _run(wl, stepper, target, convention="flux"):
+def _run(wl, stepper, target, convention="flux", checkpoint_every=1):
     import torch
     from paper_2306_00271_amd import api
     dev = torch.device("cuda:0")
-    plan = api.plan_for(wl, stepper=stepper, convention=convention)
+    plan = api.plan_for(wl, stepper=stepper, convention=convention, checkpoint_every=checkpoint_every)
     atoms = api.atoms_for(wl, dev)
     U = plan.potential(atoms)
     ang = api.angles_for(wl, dev)
@@ -46,11 +46,15 @@ def _target(n, seed=3):
     return np.random.default_rng(seed).uniform(0.0, 0.3, size=n)
 
 
+@pytest.mark.parametrize("every", [1, 20])
 @pytest.mark.parametrize("stepper", ["rk4", "rk6"])
-def test_table_gradient_matches_oracle_tangent(stepper):
+def test_table_gradient_matches_oracle_tangent(stepper, every):
+    """Table gradient along random directions against the oracle's
+    tangent-linear derivative, with a stored state at every slice and every
+    20 slices."""
     wl = small_2d(n_beams=21, n_slices=40 if stepper == "rk6" else 80, thickness=4.0, n_layers=1, n_angles=3)
     tgt = _target(3)
-    res = _run(wl, stepper, tgt)
+    res = _run(wl, stepper, tgt, checkpoint_every=every)
     assert (res["status"] == 0).all()
     ub = res["dU"]
     rng = np.random.default_rng(11)
@@ -59,7 +63,7 @@ def test_table_gradient_matches_oracle_tangent(stepper):
         dt = rng.normal(size=st.table.shape) + 1j * rng.normal(size=st.table.shape)
         loss, dl = driver.rfactor_directional_table(wl, 0, dt, tgt, stepper=stepper)
         got = float(np.real(np.sum(np.conj(ub) * dt.ravel())))
-        print(f"[adjoint] {stepper} table direction: gpu {got:.12e} oracle {dl:.12e}", flush=True)
+        print(f"[adjoint] {stepper} every {every} table direction: gpu {got:.12e} oracle {dl:.12e}", flush=True)
         assert res["loss"] == pytest.approx(loss, rel=1e-10)
         assert got == pytest.approx(dl, rel=1e-9, abs=1e-14 * abs(dl) + 1e-300)
 
@@ -107,12 +111,13 @@ def test_rfactor_kernel():
 
 
 def test_gradient_workload_full_size():
-    """N=61, 400 slices, RK6, 128 angles: the gradient w.r.t. atom
-    coordinates against central differences of the same GPU forward, and the
-    oracle's tangent-linear derivative on three of the angles (same N, L)."""
+    """N=61, 400 slices, RK6, 128 angles, states kept every 20 slices as the
+    workload states: the gradient w.r.t. atom coordinates against central
+    differences of the same GPU forward, and the oracle's tangent-linear
+    derivative on three of the angles (same N, L)."""
     wl = config4()
     tgt = _target(len(wl.theta0), seed=9)
-    res = _run(wl, "rk6", tgt)
+    res = _run(wl, "rk6", tgt, checkpoint_every=20)
     assert (res["status"] == 0).all()
     g = res["datoms"]
     s = wl.structures[0]
@@ -124,7 +129,7 @@ def test_gradient_workload_full_size():
         assert g[ia, c] == pytest.approx(fd, rel=1e-5, abs=1e-8 * np.abs(g).max())
     idx = [5, 60, 120]
     sub = dataclasses.replace(wl, theta0=wl.theta0[idx])
-    res_sub = _run(sub, "rk6", tgt[idx])
+    res_sub = _run(sub, "rk6", tgt[idx], checkpoint_every=20)
     rng = np.random.default_rng(2)
     d = np.zeros_like(s.atoms)
     d[:27] = rng.normal(size=(27, 3))
@@ -185,12 +190,12 @@ def _table_grad(wl, stepper, target, every):
 
 
 @pytest.mark.parametrize("stepper", ["rk4", "rk6"])
-def test_checkpoint_segments_replay_bitwise(stepper):
-    """States kept every 7 or 20 slices, with each segment replayed for the
-    adjoint, give the same table gradient as keeping every slice, bit for
-    bit: the replay repeats the forward's operations.  50 slices leave a
-    partial top segment; a second structure of 33 slices ends inside a
-    lower one."""
+def test_checkpoint_segments_match_every_slice_states(stepper):
+    """States kept every 7 or 20 slices (the physical column re-stepped
+    through each segment from its stored state) give the table gradient of
+    the adjoint that reads a stored state at every slice, to rounding.  50
+    slices leave a partial top segment; a second structure of 33 slices ends
+    inside a lower one."""
     wl = small_2d(n_beams=21, n_slices=50, thickness=5.0, n_layers=1, n_angles=3)
     s2 = dataclasses.replace(wl.structures[0], n_slices=33, thickness=3.3)
     wl = dataclasses.replace(wl, structures=[wl.structures[0], s2])
@@ -199,22 +204,19 @@ def test_checkpoint_segments_replay_bitwise(stepper):
     assert (st == 0).all()
     for every in (7, 20):
         got, _, _ = _table_grad(wl, stepper, tgt, every)
-        np.testing.assert_array_equal(got, ref)
+        np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-10 * np.abs(ref).max())
 
 
 def test_checkpoint_every_20_gradient_workload():
-    """The gradient workload at its stated checkpoint interval of 20 slices:
-    one structure (split forward, replay in one launch per segment) matches
-    the every-slice adjoint bit for bit; two structures (256 pairs: the
-    forward runs one workgroup per pair, the replay goes in chunks of pairs)
-    match to rounding."""
+    """The gradient workload at its stated checkpoint interval of 20 slices
+    matches the every-slice adjoint to rounding, with one structure (split
+    forward) and with two (256 pairs, one workgroup per pair)."""
     for ns in (1, 2):
         wl = config4(ns)
         tgt = _target(len(wl.theta0) * ns, seed=9)
-        ref, st, split_ref = _table_grad(wl, "rk6", tgt, 1)
+        ref, st, _ = _table_grad(wl, "rk6", tgt, 1)
         got, _, _ = _table_grad(wl, "rk6", tgt, 20)
         assert (st == 0).all()
-        if split_ref:
-            np.testing.assert_array_equal(got, ref)
-        else:
-            np.testing.assert_allclose(got, ref, rtol=1e-11, atol=1e-13 * np.abs(ref).max())
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        print(f"[adjoint] c4 x{ns}: max |dU(K=20) - dU(K=1)| / max |dU| = {err:.3e}", flush=True)
+        np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-10 * np.abs(ref).max())
