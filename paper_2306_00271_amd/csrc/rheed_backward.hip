@@ -345,7 +345,7 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
       psic = row_sum(ac);
       psid = row_sum(ad);
     }
-    load_tables(lo);
+    if (hi == L) load_tables(lo);  // lower segments find them loaded by (C) of the segment above
     __syncthreads();
     for (int i = lo; i < hi; ++i) {
       const int nb = i * NPS;
@@ -409,12 +409,20 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
     // (C) down through the segment: projection, then the adjoint of the slice
     for (int i = hi - 1; i >= lo; --i) {
       const int nb = i * NPS;
-      double2 pf[3];  // the new nodes of slice i - 1
+      // the new nodes of slice i - 1 or, at the bottom of the segment, all
+      // nodes of the next segment's bottom slice lo - K
+      double2 pf[3];
       if (i > lo) {
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
           const int e = tid + BT * t;
           if (e < NPS * box) pf[t] = Us[(long long)(nb - NPS) * box + e];
+        }
+      } else if (lo > 0) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const int e = tid + BT * t;
+          if (e < (NPS + 1) * box) pf[t] = Us[(long long)(lo - K) * NPS * box + e];
         }
       }
       if (flags[i]) {
@@ -472,6 +480,16 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
           if (e < NPS * box) {
             const int q = e / box;
             s.tb[(nb - NPS + q) % RING][e - q * box] = pf[t];
+          }
+        }
+      } else if (lo > 0) {
+        __syncthreads();  // these slots may hold nodes the slice's last products still read
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const int e = tid + BT * t;
+          if (e < (NPS + 1) * box) {
+            const int q = e / box;
+            s.tb[((lo - K) * NPS + q) % RING][e - q * box] = pf[t];
           }
         }
       }
