@@ -153,7 +153,11 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int j = tid >> 3, part = tid & 7;
-  const int p = blockIdx.x;
+  // two workgroups per pair: role 0 carries x down and psi up and writes the
+  // stage inputs v_r, role 1 walks the adjoint stages down and writes g_r;
+  // the two need nothing from each other
+  const int role = blockIdx.x & 1;
+  const int p = blockIdx.x >> 1;
   const StructDev S = a.structs[a.pair_struct[p]];
   const int N = S.n_beams;
   const int L = S.n_slices;
@@ -292,15 +296,6 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
     __syncthreads();
   }
 
-  // Segments of K = ck.every slices, from the top down.  For a segment
-  // [lo, hi): (A) x moves down through the segment's transformations,
-  // x <- T_m x for every slice m whose decision byte is set; (B) psi_lo =
-  // Z_lo x_lo from the stored state, then psi goes up slice by slice with the
-  // RK step itself (psi_{i+1} = Phi_i psi_i: psi = Z x does not change under
-  // Z <- Z T, x <- T^{-1} x), the stage inputs v_r going to the stage buffer;
-  // (C) down again through the adjoint of every slice, preceded by the
-  // projection y_c = -R^H y_d wherever a transformation followed the slice,
-  // R the normalised P after it (stored state for K = 1, R slot otherwise).
   const int K = a.ck.every;
   auto load_tables = [&](int i) {  // nodes of slice i, in their ring slots
     for (int e = tid; e < (NPS + 1) * box; e += BT) {
@@ -308,125 +303,134 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
       s.tb[nn % RING][e % box] = Us[(long long)nn * box + e % box];
     }
   };
-  for (int hi = L; hi > 0;) {
-    const int lo = ((hi - 1) / K) * K;
-    // (A) x down to the bottom of the segment; x at each transformed state
-    // inside the segment is kept for (B)
-    double2* xs = a.xs + (long long)p * a.xs_stride;
-    for (int m = hi - 1; m >= lo; --m) {
-      if (flags[m]) {
-        if (K > 1 && m + 1 < hi && tid < NP) xs[(m + 1 - lo) * NP + tid] = s.x[tid];
-        const double2* Tm = reinterpret_cast<const double2*>(pws + a.ck.q_off + (long long)m * NP * NP * sizeof(double2));
-        double2 tm[8];
+  if (role == 0) {
+    // Segments of K = ck.every slices, from the top down.  (A) x moves down
+    // through the segment's transformations, x <- T_m x for every slice m
+    // whose decision byte is set; (B) psi_lo = Z_lo x_lo from the stored
+    // state, then psi goes up slice by slice with the RK step itself
+    // (psi_{i+1} = Phi_i psi_i: psi = Z x does not change under Z <- Z T,
+    // x <- T^{-1} x), the stage inputs v_r going to the stage buffer.
+    for (int hi = L; hi > 0;) {
+      const int lo = ((hi - 1) / K) * K;
+      // (A) x down to the bottom of the segment; x at each transformed state
+      // inside the segment is kept for (B)
+      double2* xs = a.xs + (long long)p * a.xs_stride;
+      for (int m = hi - 1; m >= lo; --m) {
+        if (flags[m]) {
+          if (K > 1 && m + 1 < hi && tid < NP) xs[(m + 1 - lo) * NP + tid] = s.x[tid];
+          const double2* Tm =
+              reinterpret_cast<const double2*>(pws + a.ck.q_off + (long long)m * NP * NP * sizeof(double2));
+          double2 tm[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) tm[q] = Tm[j * NP + 8 * part + q];
-        double2 xn = make_double2(0.0, 0.0);
+          for (int q = 0; q < 8; ++q) tm[q] = Tm[j * NP + 8 * part + q];
+          double2 xn = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) xn = cadd(xn, cmul(tm[q], s.x[8 * part + q]));
-        xn = row_sum(xn);
-        __syncthreads();
-        if (part == 0) s.x[j] = xn;
-        __syncthreads();
+          for (int q = 0; q < 8; ++q) xn = cadd(xn, cmul(tm[q], s.x[8 * part + q]));
+          xn = row_sum(xn);
+          __syncthreads();
+          if (part == 0) s.x[j] = xn;
+          __syncthreads();
+        }
       }
-    }
-    // (B) psi_lo = Z_lo x_lo, then up through the segment; at a state that a
-    // transformation left as [I; R], psi = [I; R] x is formed afresh, so the
-    // RK step carries psi only across well-conditioned stretches
-    double2 psic, psid;
-    {
-      const double2* z = reinterpret_cast<const double2*>(pws + (long long)(lo / K) * a.ck.state_bytes);
-      double2 ac = make_double2(0.0, 0.0), ad = make_double2(0.0, 0.0);
+      // (B) psi_lo = Z_lo x_lo, then up through the segment; at a state that a
+      // transformation left as [I; R], psi = [I; R] x is formed afresh, so the
+      // RK step carries psi only across well-conditioned stretches
+      double2 psic, psid;
+      {
+        const double2* z = reinterpret_cast<const double2*>(pws + (long long)(lo / K) * a.ck.state_bytes);
+        double2 ac = make_double2(0.0, 0.0), ad = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const double2 xk = s.x[8 * part + q];
-        ac = cadd(ac, cmul(z[j * NP + 8 * part + q], xk));
-        ad = cadd(ad, cmul(z[NP * NP + j * NP + 8 * part + q], xk));
-      }
-      psic = row_sum(ac);
-      psid = row_sum(ad);
-    }
-    if (hi == L) load_tables(lo);  // lower segments find them loaded by (C) of the segment above
-    __syncthreads();
-    for (int i = lo; i < hi; ++i) {
-      const int nb = i * NPS;
-      if (i > lo && flags[i - 1]) {
-        const double2* R = reinterpret_cast<const double2*>(pws + a.ck.r_off + (long long)(i - 1) * NP * NP * sizeof(double2));
-        const double2* xi = xs + (i - lo) * NP;
-        double2 ad = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) ad = cadd(ad, cmul(R[j * NP + 8 * part + q], xi[8 * part + q]));
-        psic = xi[j];
+        for (int q = 0; q < 8; ++q) {
+          const double2 xk = s.x[8 * part + q];
+          ac = cadd(ac, cmul(z[j * NP + 8 * part + q], xk));
+          ad = cadd(ad, cmul(z[NP * NP + j * NP + 8 * part + q], xk));
+        }
+        psic = row_sum(ac);
         psid = row_sum(ad);
       }
-      double2 pf[3];  // the next slice's new nodes, loaded during this one
-      if (i + 1 < hi) {
+      __syncthreads();  // the previous segment's last products are done with the ring
+      load_tables(lo);
+      __syncthreads();
+      for (int i = lo; i < hi; ++i) {
+        const int nb = i * NPS;
+        if (i > lo && flags[i - 1]) {
+          const double2* R =
+              reinterpret_cast<const double2*>(pws + a.ck.r_off + (long long)(i - 1) * NP * NP * sizeof(double2));
+          const double2* xi = xs + (i - lo) * NP;
+          double2 ad = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-          const int e = tid + BT * t;
-          if (e < NPS * box) pf[t] = Us[(long long)(nb + NPS + 1) * box + e];
+          for (int q = 0; q < 8; ++q) ad = cadd(ad, cmul(R[j * NP + 8 * part + q], xi[8 * part + q]));
+          psic = xi[j];
+          psid = row_sum(ad);
         }
-      }
-      // RK stages on psi: Y_r = psi + h sum_{m<r} a_rm K_m, K_r = (Y_r^(c'), -M_r Y_r^(c))
-      double2* gs = gb + (long long)i * NS * 2 * NP;
-      double2 Yd[NS], Kd[NS];
+        double2 pf[3];  // the next slice's new nodes, loaded during this one
+        if (i + 1 < hi) {
 #pragma unroll
-      for (int r = 0; r < NS; ++r) {
-        double2 yr = psic, ydr = psid;
-#pragma unroll
-        for (int m = 0; m < r; ++m) {
-          if (T::a[r][m] != 0.0) {
-            yr = caxpy(h * T::a[r][m], Yd[m], yr);
-            ydr = caxpy(h * T::a[r][m], Kd[m], ydr);
+          for (int t = 0; t < 3; ++t) {
+            const int e = tid + BT * t;
+            if (e < NPS * box) pf[t] = Us[(long long)(nb + NPS + 1) * box + e];
           }
         }
-        Yd[r] = ydr;
-        if (part == 0) {
-          s.vin[r & 1][j] = yr;
-          gs[r * 2 * NP + j] = yr;  // v_r
-        }
-        __syncthreads();
-        const double2 mv = matvec_row<false>(s.tb[(nb + T::node[r]) % RING], s.vin[r & 1], ixf, part, j, g2j);
-        Kd[r] = make_double2(-mv.x, -mv.y);
-      }
-      if (i + 1 < hi) {
+        // RK stages on psi: Y_r = psi + h sum_{m<r} a_rm K_m, K_r = (Y_r^(c'), -M_r Y_r^(c))
+        double2* gs = gb + (long long)i * NS * 2 * NP;
+        double2 Yd[NS], Kd[NS];
 #pragma unroll
         for (int r = 0; r < NS; ++r) {
-          if (T::b[r] != 0.0) {
-            psic = caxpy(h * T::b[r], Yd[r], psic);
-            psid = caxpy(h * T::b[r], Kd[r], psid);
-          }
-        }
+          double2 yr = psic, ydr = psid;
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-          const int e = tid + BT * t;
-          if (e < NPS * box) {
-            const int q = e / box;
-            s.tb[(nb + NPS + 1 + q) % RING][e - q * box] = pf[t];
+          for (int m = 0; m < r; ++m) {
+            if (T::a[r][m] != 0.0) {
+              yr = caxpy(h * T::a[r][m], Yd[m], yr);
+              ydr = caxpy(h * T::a[r][m], Kd[m], ydr);
+            }
+          }
+          Yd[r] = ydr;
+          if (part == 0) {
+            s.vin[r & 1][j] = yr;
+            gs[r * 2 * NP + j] = yr;  // v_r
+          }
+          __syncthreads();
+          const double2 mv = matvec_row<false>(s.tb[(nb + T::node[r]) % RING], s.vin[r & 1], ixf, part, j, g2j);
+          Kd[r] = make_double2(-mv.x, -mv.y);
+        }
+        if (i + 1 < hi) {
+#pragma unroll
+          for (int r = 0; r < NS; ++r) {
+            if (T::b[r] != 0.0) {
+              psic = caxpy(h * T::b[r], Yd[r], psic);
+              psid = caxpy(h * T::b[r], Kd[r], psid);
+            }
+          }
+#pragma unroll
+          for (int t = 0; t < 3; ++t) {
+            const int e = tid + BT * t;
+            if (e < NPS * box) {
+              const int q = e / box;
+              s.tb[(nb + NPS + 1 + q) % RING][e - q * box] = pf[t];
+            }
           }
         }
       }
+      hi = lo;
     }
-    // (C) down through the segment: projection, then the adjoint of the slice
-    for (int i = hi - 1; i >= lo; --i) {
+  } else {
+    // Down through every slice: the projection y_c = -R^H y_d wherever a
+    // transformation followed the slice (R the normalised P after it: the
+    // stored state for K = 1, the R slot otherwise), then the adjoint of the
+    // slice's RK step, stages last to first, its g_r going to the stage buffer.
+    load_tables(L - 1);
+    __syncthreads();
+    for (int i = L - 1; i >= 0; --i) {
       const int nb = i * NPS;
-      // the new nodes of slice i - 1 or, at the bottom of the segment, all
-      // nodes of the next segment's bottom slice lo - K
-      double2 pf[3];
-      if (i > lo) {
+      double2 pf[3];  // the new nodes of slice i - 1
+      if (i > 0) {
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
           const int e = tid + BT * t;
           if (e < NPS * box) pf[t] = Us[(long long)(nb - NPS) * box + e];
         }
-      } else if (lo > 0) {
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-          const int e = tid + BT * t;
-          if (e < (NPS + 1) * box) pf[t] = Us[(long long)(lo - K) * NPS * box + e];
-        }
       }
       if (flags[i]) {
-        // y_c = -R^H y_d, R the normalised P after the transformation that followed slice i
         const double2* R =
             K == 1 ? (i + 1 == L ? zL : reinterpret_cast<const double2*>(pws + (long long)(i + 1) * a.ck.state_bytes)) +
                          NP * NP
@@ -434,7 +438,6 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
         double2 rh[8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) rh[q] = R[(8 * part + q) * NP + j];
-        __syncthreads();
         if (part == 0) s.vin[0][j] = yd;
         __syncthreads();
         double2 t = make_double2(0.0, 0.0);
@@ -444,7 +447,6 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
         yc = make_double2(-t.x, -t.y);
         __syncthreads();
       }
-      // adjoint of the step, stages last to first
       double2* gs = gb + (long long)i * NS * 2 * NP;
       double2 Ybc[NS], Ybd[NS];
 #pragma unroll
@@ -473,7 +475,7 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
         yc = cadd(yc, Ybc[r]);
         yd = cadd(yd, Ybd[r]);
       }
-      if (i > lo) {
+      if (i > 0) {
 #pragma unroll
         for (int t = 0; t < 3; ++t) {
           const int e = tid + BT * t;
@@ -482,20 +484,9 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
             s.tb[(nb - NPS + q) % RING][e - q * box] = pf[t];
           }
         }
-      } else if (lo > 0) {
-        __syncthreads();  // these slots may hold nodes the slice's last products still read
-#pragma unroll
-        for (int t = 0; t < 3; ++t) {
-          const int e = tid + BT * t;
-          if (e < (NPS + 1) * box) {
-            const int q = e / box;
-            s.tb[((lo - K) * NPS + q) % RING][e - q * box] = pf[t];
-          }
-        }
       }
       __syncthreads();
     }
-    hi = lo;
   }
 }
 
@@ -563,9 +554,9 @@ __global__ __launch_bounds__(256) void grad_assemble_kernel(GradArgs a) {
 
 hipError_t launch_backward(int stepper, const BwdArgs& a, hipStream_t stream) {
   if (stepper == 0)
-    hipLaunchKernelGGL(backward_kernel<0>, dim3(a.n_pairs), dim3(BT), 0, stream, a);
+    hipLaunchKernelGGL(backward_kernel<0>, dim3(2 * a.n_pairs), dim3(BT), 0, stream, a);
   else
-    hipLaunchKernelGGL(backward_kernel<1>, dim3(a.n_pairs), dim3(BT), 0, stream, a);
+    hipLaunchKernelGGL(backward_kernel<1>, dim3(2 * a.n_pairs), dim3(BT), 0, stream, a);
   return hipGetLastError();
 }
 
