@@ -8,7 +8,8 @@ keeping the state every 20 slices -> R-factor against a target curve ->
 adjoint propagation, segment by segment, each segment's states recomputed
 from its checkpoint -> gradient with respect to atom coordinates.  Inputs
 are seeded synthetic slabs, resident in HBM before the timed region.  Prints
-one JSON line; "variants" adds the same step with every slice state kept.
+one JSON line; "variants" adds the same step with every slice state kept and
+the plain per-angle form (the same kernels on one pair at a time).
 
 ``--mode fwd`` times the forward pass alone (potential + propagation).
 ``--traffic-probe`` runs one forward launch and a 1 GiB device copy for the
@@ -151,6 +152,8 @@ def main():
     ap.add_argument("--mode", choices=["fwd", "fwd+adj"], default="fwd+adj")
     ap.add_argument("--structures", type=int, default=1, help="structures in the batch (128 angles each)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-per-angle", action="store_true",
+                    help="skip timing the plain per-angle form (the same step one (structure, angle) pair at a time)")
     ap.add_argument("--checkpoint-every", type=int, default=CHECKPOINT_EVERY,
                     help="slices between states kept for the adjoint (the gradient workload keeps every 20th)")
     ap.add_argument("--traffic-probe", action="store_true",
@@ -264,6 +267,39 @@ def main():
         del plan
         _, ms1, _, _, _ = measure(1)
         variants = {"checkpoint_every_1": {"value": round(n_pairs / (ms1 / 1e3), 3), "ms_per_step": round(ms1, 4)}}
+    if not args.no_per_angle and args.structures == 1:
+        # the plain per-angle GPU form: the same kernels on one pair at a time,
+        # the table gradient summed over the angles, one atom gradient at the end
+        import dataclasses
+        one = dataclasses.replace(wl, theta0=wl.theta0[:1])
+        p1 = api.plan_for(one, stepper=stepper, checkpoint_every=every if do_adj else 1)
+        ws1 = p1.workspace(dev) if do_adj else None
+        ang_all = angles
+
+        def per_angle_step():
+            U = p1.potential(atoms)
+            dU_sum = torch.zeros_like(U) if do_adj else None
+            for k in range(ang_all.shape[0]):
+                a1 = ang_all[k:k + 1]
+                o1 = p1.forward(U, a1, workspace=ws1)
+                if do_adj:
+                    _, dI1 = api.rfactor(o1["intensity"], target[k:k + 1])
+                    dU_sum += p1.backward(U, a1, dI1, ws1)
+            if do_adj:
+                p1.potential_backward(atoms, dU_sum)
+
+        per_angle_step()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        per_angle_step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_pa = e0.elapsed_time(e1)
+        variants = variants or {}
+        variants["per_angle"] = {"value": round(n_pairs / (ms_pa / 1e3), 3), "ms_per_step": round(ms_pa, 3),
+                                 "speedup_of_batched": round(ms_pa / ms, 2)}
 
     rec = {
         "metric": "rocking-curve points (structure x angle)/s at N=61 FP64; " +
