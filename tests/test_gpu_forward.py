@@ -134,3 +134,25 @@ def test_split_layout_repeated_launches_on_one_plan():
         assert (o["status"] == 0).all()
         assert torch.equal(o["rho"], outs[0]["rho"])
         assert torch.equal(o["n_rhst"], outs[0]["n_rhst"])
+
+
+@pytest.mark.parametrize("layout", ["whole", "split"])
+def test_uneven_batch_in_one_launch(layout):
+    """Structures of N = 21, 45 and 61 beams with 40, 30 and 35 slices in one
+    plan (one launch): each structure's pairs against the oracle."""
+    import dataclasses
+    parts = [small_2d(n_beams=n, n_slices=L, thickness=0.1 * L, n_layers=2, n_angles=3)
+             for n, L in ((21, 40), (45, 30), (61, 35))]
+    wl = dataclasses.replace(parts[0], structures=[p.structures[0] for p in parts])
+    res = gpu_forward(wl, stepper="rk6", layout=layout)
+    assert res["plan"].split == (layout == "split")
+    assert (res["status"] == 0).all()
+    A = len(wl.theta0)
+    for s, p in enumerate(parts):
+        N = p.structures[0].n_beams
+        ref, _, nr = oracle_forward(wl, s_idx=s, stepper="rk6")
+        got = res["intensity"][s * A:(s + 1) * A, :N]
+        e = eacc(got, ref)
+        _report(f"uneven batch {layout} structure {s} N={N} L={p.structures[0].n_slices}", e)
+        assert e <= TOL
+        assert np.all(res["intensity"][s * A:(s + 1) * A, N:] == 0.0)
