@@ -172,7 +172,10 @@ rheed_status rheed_potential_backward(rheed_plan_t plan, const double* atoms, co
  *             needs; NULL when no backward pass follows.
  * With the split layout the launch is cooperative and uses exchange blocks
  * owned by the plan, so forward calls on one plan must not overlap (issue them
- * on one stream). */
+ * on one stream).  Like every compute call, it only launches kernels (no
+ * allocation, no memset, no synchronisation), so a stream capture records it
+ * into a HIP graph, and each replay behaves like a new call (the exchange
+ * blocks count their own launches). */
 rheed_status rheed_forward(rheed_plan_t plan, const void* U_tables, const double* angles,
                            double* intensity, void* rho, int32_t* pair_status, int32_t* n_rhst,
                            void* workspace, size_t ws_bytes, void* stream);

@@ -54,7 +54,6 @@ struct rheed_plan_s {
   char* d_xch = nullptr;     // exchange blocks of the split layout
   bool split = false;
   int split_max = 0;
-  unsigned long long epoch = 0;  // split launches so far (tags the exchange counters)
   long long g_pair_stride = 0;  // adjoint stage buffer elements per pair
   int max_nodes = 0;
   size_t xs_off = 0;            // adjoint workspace: x of a segment's transformed states
@@ -384,7 +383,6 @@ rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* a
   hipError_t e;
   if (P->split) {
     a.xch = P->d_xch;
-    a.epoch = ++P->epoch;
     e = launch_forward_split((int)P->opts.stepper, a, static_cast<hipStream_t>(stream));
   } else {
     e = launch_forward((int)P->opts.stepper, a, static_cast<hipStream_t>(stream));

@@ -962,7 +962,12 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
   unsigned long long* cnt_other = reinterpret_cast<unsigned long long*>(X) + (1 - half);
   double* xi_g = reinterpret_cast<double*>(X + XCH_XI);       // [half][parity][2][NP]
   double2* big_g = reinterpret_cast<double2*>(X + XCH_BIG);   // [half][parity][2][NP][HC]
-  unsigned long long ev = a.epoch << 32;
+  // launch number of this pair's block, kept in the block itself so that a
+  // replayed launch (graph) moves on like a new one: both halves read it
+  // here, half 0 writes it back after its last wait
+  unsigned long long* ep_word = reinterpret_cast<unsigned long long*>(X) + 2;
+  const unsigned long long epoch = __hip_atomic_load(ep_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+  unsigned long long ev = epoch << 32;
   int nrhst = 0;
   // this half's [Q; P] columns to the exchange block of event ev
   auto publish_qp = [&]() {
@@ -1126,6 +1131,7 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
   xch_publish(cnt_me, ev);
   if (half == 1) return;
   xch_wait(cnt_other, ev, &s.sync_fail);
+  if (tid == 0) __hip_atomic_store(ep_word, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   double2 low[NE];
 #pragma unroll
   for (int e = 0; e < NE; ++e) {

@@ -52,15 +52,14 @@ struct FwdArgs {
   int n_pairs;
   int pad;
   double threshold;
-  // split launches (two workgroups per pair): per-pair exchange blocks and the
-  // launch number that tags their counters
+  // split launches (two workgroups per pair): per-pair exchange blocks
   char* xch;
-  unsigned long long epoch;
 };
 
-// Exchange block of one pair in a split launch (bytes): two 64-bit counters,
-// per half and parity the badness partials [2][NP] doubles, and per half and
-// parity the half's [Q; P] columns, [2][NP][32] complex.
+// Exchange block of one pair in a split launch (bytes): two 64-bit counters
+// and the launch number, per half and parity the badness partials [2][NP]
+// doubles, and per half and parity the half's [Q; P] columns, [2][NP][32]
+// complex.
 constexpr long long XCH_XI = 256;
 constexpr long long XCH_BIG = XCH_XI + 2 * 2 * 2 * NP * 8;
 constexpr long long XCH_HALF = 2LL * NP * 32 * 16;

@@ -220,3 +220,46 @@ def test_checkpoint_every_20_gradient_workload():
         err = np.abs(got - ref).max() / np.abs(ref).max()
         print(f"[adjoint] c4 x{ns}: max |dU(K=20) - dU(K=1)| / max |dU| = {err:.3e}", flush=True)
         np.testing.assert_allclose(got, ref, rtol=1e-9, atol=1e-10 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("layout", ["whole", "split"])
+def test_graph_capture_of_the_gradient_step(layout):
+    """The whole gradient step (tables, forward keeping a state every 20
+    slices, R-factor, adjoint, atom gradient) captured once in a HIP graph:
+    every replay, with eager steps and synchronisations between replays,
+    reproduces the eager step bit for bit."""
+    import torch
+    from paper_2306_00271_amd import api
+    dev = torch.device("cuda:0")
+    wl = small_2d(n_beams=21, n_slices=50, thickness=5.0, n_layers=1, n_angles=3)
+    plan = api.plan_for(wl, stepper="rk6", layout=layout, checkpoint_every=20)
+    atoms = api.atoms_for(wl, dev)
+    ang = api.angles_for(wl, dev)
+    ws = plan.workspace(dev)
+    tgt = torch.from_numpy(_target(3)).to(dev)
+
+    def step():
+        U = plan.potential(atoms)
+        out = plan.forward(U, ang, workspace=ws)
+        loss, dI = api.rfactor(out["intensity"], tgt)
+        dU = plan.backward(U, ang, dI, ws)
+        return out["intensity"], loss, plan.potential_backward(atoms, dU)
+
+    ref = [t.clone() for t in step()]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        outs = step()
+    for r in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        for o, rf in zip(outs, ref):
+            assert torch.equal(o, rf), f"replay {r}"
+        step()
+        torch.cuda.synchronize()
