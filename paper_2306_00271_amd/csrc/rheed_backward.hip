@@ -119,8 +119,9 @@ __device__ __forceinline__ double2 row_sum(double2 v) {
 }
 
 // (M v)_j (HERM = false) or (M^H v)_j (HERM = true), M = U(node) + Gamma^2;
-// ix[q] is the table entry of U_{j,k} (or U_{k,j}) for k = 8 part + q, or
-// `box` (a zero entry) outside the n x n block.
+// ix[q] is the table entry of U_{j,k} (or U_{k,j}) for
+// k = 8 part + ((q + part) mod 8), or `box` (a zero entry) outside the n x n
+// block.
 template <bool HERM>
 __device__ __forceinline__ double2 matvec_row(const double2* __restrict__ tslot, const double2* __restrict__ v,
                                               const int (&ix)[8], int part, int j, double g2j) {
@@ -131,7 +132,7 @@ __device__ __forceinline__ double2 matvec_row(const double2* __restrict__ tslot,
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       u[q] = tslot[ix[h + q]];
-      vk[q] = v[8 * part + h + q];
+      vk[q] = v[8 * part + ((h + q + part) & 7)];
     }
 #pragma unroll
     for (int q = 0; q < 4; q += 2) {
@@ -187,13 +188,15 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
     }
     s.g2s[tid] = arg;
   }
-  // table entries of U_{j,k} and U_{k,j} for k = 8 part + q
+  // table entries of U_{j,k} and U_{k,j} for k = 8 part + ((q + part) mod 8):
+  // the eight threads of a row visit their columns in rotated order, so that
+  // their reads of the input vector fall in eight different LDS bank groups
   int ixf[8], ixh[8];
   {
     const int W = 2 * S.kd + 1;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int k = 8 * part + q;
+      const int k = 8 * part + ((q + part) & 7);
       const bool in = j < N && k < N;
       const int bj = (s.bhk[j][0] + S.hd) * W + s.bhk[j][1] + S.kd, oj = s.bhk[j][0] * W + s.bhk[j][1];
       const int bk = (s.bhk[k][0] + S.hd) * W + s.bhk[k][1] + S.kd, ok = s.bhk[k][0] * W + s.bhk[k][1];
