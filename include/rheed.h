@@ -62,10 +62,14 @@ typedef enum { RHEED_RK4 = 0, RHEED_RK6 = 1 } rheed_stepper;
  * open beams; PAPER = the printed formula, FLUX times sin(theta0). */
 typedef enum { RHEED_INTENSITY_FLUX = 0, RHEED_INTENSITY_PAPER = 1 } rheed_convention;
 
-/* Largest beam count N handled by the kernels of this build. */
-#define RHEED_MAX_BEAMS 64
-/* Largest potential-table row (rod differences) for N <= 64. */
+/* Largest beam count N handled by the kernels of this build.  Structures with
+ * N <= 64 run on the one- or two-workgroup kernels (forward and adjoint);
+ * structures with 64 < N <= 128 run on a kernel that keeps the state of a
+ * pair in device memory owned by the plan (forward only). */
+#define RHEED_MAX_BEAMS 128
+/* Largest potential-table row (rod differences) for N <= 64, and for N > 64. */
 #define RHEED_MAX_BOX 300
+#define RHEED_MAX_BOX_LARGE 1024
 
 /* One slab.  Rod indices are on the reciprocal basis b1, b2:
  * k_j = h_j b1 + k_j b2 (Sec. 2.1, the reciprocal rods k_j with k_1 = 0). */
@@ -118,8 +122,10 @@ typedef struct {
   int64_t n_atoms_total;
   size_t fwd_workspace;      /* bytes rheed_forward needs to keep states for rheed_backward */
   size_t bwd_workspace;      /* extra bytes rheed_backward needs beyond fwd_workspace */
-  int32_t split;             /* 1 if rheed_forward runs the split layout */
+  int32_t split;             /* 1 if rheed_forward runs the split layout (for the pairs with N <= 64) */
   int32_t split_max_pairs;   /* pairs a split launch can hold on the current device */
+  int32_t large_pairs;       /* pairs of structures with N > 64 */
+  int32_t large_slots;       /* workgroups (state slots of 768 KiB each, plan-owned) that run them */
 } rheed_plan_info;
 
 /* Vacuum wavenumber gamma (1/A) and the coefficient kappa (1/(A^2 V)) of the

@@ -61,6 +61,8 @@ class PlanInfo(C.Structure):
         ("bwd_workspace", C.c_size_t),
         ("split", C.c_int32),
         ("split_max_pairs", C.c_int32),
+        ("large_pairs", C.c_int32),
+        ("large_slots", C.c_int32),
     ]
 
 

@@ -13,6 +13,7 @@
 
 #include "rheed.h"
 #include "rheed_internal.h"
+#include "rheed_large.h"
 
 
 using namespace rheed;
@@ -57,6 +58,13 @@ struct rheed_plan_s {
   long long g_pair_stride = 0;  // adjoint stage buffer elements per pair
   int max_nodes = 0;
   size_t xs_off = 0;            // adjoint workspace: x of a segment's transformed states
+  // pairs of structures with N <= 64 (propagated by the one- and two-workgroup
+  // kernels) and with 64 < N <= 128 (the large kernel), in pair order
+  std::vector<int> small_pairs, large_pairs;
+  int* d_small_pairs = nullptr;  // only when both kinds are present
+  int* d_large_pairs = nullptr;
+  char* d_lscratch = nullptr;    // per resident workgroup of the large kernel: its state slot
+  int large_slots = 0;
 };
 
 extern "C" {
@@ -146,17 +154,20 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     d.hd = hmax - hmin;
     d.kd = kmax - kmin;
     d.box = (2 * d.hd + 1) * (2 * d.kd + 1);
-    if (d.box > MAXBOX) {
+    const int box_max = st.n_beams <= NP ? MAXBOX : MAXBOXL;
+    if (d.box > box_max) {
       delete P;
       return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) + ": rod-difference table row of " +
-                                           std::to_string(d.box) + " entries exceeds " + std::to_string(MAXBOX));
+                                           std::to_string(d.box) + " entries exceeds " + std::to_string(box_max) +
+                                           " for N = " + std::to_string(st.n_beams));
     }
     d.n_nodes = st.n_slices * P->nodes_per_slice + 1;
     // (j, k) pairs of every rod difference g_j - g_k, grouped by table entry
+    // (for the adjoint's gradient assembly, which handles N <= 64)
     {
       const int W = 2 * d.kd + 1;
       std::vector<std::vector<int>> lists(d.box);
-      for (int j = 0; j < st.n_beams; ++j)
+      for (int j = 0; j < (st.n_beams <= NP ? st.n_beams : 0); ++j)
         for (int k = 0; k < st.n_beams; ++k) {
           const int dh = st.beam_hk[2 * j] - st.beam_hk[2 * k], dk = st.beam_hk[2 * j + 1] - st.beam_hk[2 * k + 1];
           lists[(dh + d.hd) * W + (dk + d.kd)].push_back(j * NP + k);
@@ -213,7 +224,10 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     P->max_table = std::max(P->max_table, (long long)d.n_nodes * d.box);
     P->max_nodes = std::max(P->max_nodes, d.n_nodes);
     P->n_atoms_total += d.n_atoms;
-    for (int a = 0; a < angles_per_struct[s]; ++a) P->pair_struct.push_back(s);
+    for (int a = 0; a < angles_per_struct[s]; ++a) {
+      (st.n_beams <= NP ? P->small_pairs : P->large_pairs).push_back(P->n_pairs + a);
+      P->pair_struct.push_back(s);
+    }
     P->n_pairs += angles_per_struct[s];
     P->max_beams = std::max(P->max_beams, st.n_beams);
     max_l = std::max(max_l, st.n_slices);
@@ -241,12 +255,28 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     P->bwd_ws += (size_t)P->ck.every * NP * sizeof(double2) * P->n_pairs;
   }
 
+  // the adjoint and its state saving handle N <= 64 only
+  if (!P->large_pairs.empty()) {
+    P->fwd_ws = 0;
+    P->bwd_ws = 0;
+  }
+
   // split layout: two workgroups per pair, both resident (cooperative launch)
+  const int n_small = (int)P->small_pairs.size(), n_large = (int)P->large_pairs.size();
   {
     int dev = 0;
-    P->split_max = hipGetDevice(&dev) == hipSuccess ? forward_split_max_pairs(dev) : 0;
-    P->split = opts->layout != RHEED_LAYOUT_WHOLE && P->n_pairs <= P->split_max;
-    if (opts->layout == RHEED_LAYOUT_SPLIT && !P->split) {
+    const bool have_dev = hipGetDevice(&dev) == hipSuccess;
+    P->split_max = have_dev ? forward_split_max_pairs(dev) : 0;
+    P->split = opts->layout != RHEED_LAYOUT_WHOLE && n_small > 0 && n_small <= P->split_max;
+    if (n_large > 0) {
+      const int slots = have_dev ? forward_large_slots(dev) : 0;
+      if (slots < 1) {
+        delete P;
+        return fail(RHEED_E_HIP, "the kernel for N > 64 cannot be resident on this device");
+      }
+      P->large_slots = std::min(n_large, slots);
+    }
+    if (opts->layout == RHEED_LAYOUT_SPLIT && !P->split && n_small > 0) {
       const int mx = P->split_max;
       delete P;
       return fail(RHEED_E_UNSUPPORTED, "layout SPLIT holds at most " + std::to_string(mx) + " pairs on this device");
@@ -262,7 +292,10 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (e = hipMalloc(&P->d_bin_jk, sizeof(int) * P->bin_jk.size())) != hipSuccess ||
       (e = hipMalloc(&P->d_pbwd, sizeof(double) * 3 * PBWD_CHUNKS * std::max<long long>(1, P->n_atoms_total))) !=
           hipSuccess ||
-      (P->split && (e = hipMalloc(&P->d_xch, (size_t)XCH_STRIDE * P->n_pairs)) != hipSuccess)) {
+      (P->split && (e = hipMalloc(&P->d_xch, (size_t)XCH_STRIDE * n_small)) != hipSuccess) ||
+      (n_large > 0 && n_small > 0 && (e = hipMalloc(&P->d_small_pairs, sizeof(int) * n_small)) != hipSuccess) ||
+      (n_large > 0 && n_small > 0 && (e = hipMalloc(&P->d_large_pairs, sizeof(int) * n_large)) != hipSuccess) ||
+      (n_large > 0 && (e = hipMalloc(&P->d_lscratch, (size_t)LSLOT_BYTES * P->large_slots)) != hipSuccess)) {
     rheed_plan_destroy(P);
     return e == hipErrorOutOfMemory ? fail(RHEED_E_NOMEM, "plan_create: device allocation") : hip_fail(e, "hipMalloc");
   }
@@ -277,7 +310,11 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (!P->atom_struct.empty() &&
        (e = hipMemcpy(P->d_atom_struct, P->atom_struct.data(), sizeof(long long) * P->atom_struct.size(),
                       hipMemcpyHostToDevice)) != hipSuccess) ||
-      (P->split && (e = hipMemset(P->d_xch, 0, (size_t)XCH_STRIDE * P->n_pairs)) != hipSuccess) ||
+      (P->split && (e = hipMemset(P->d_xch, 0, (size_t)XCH_STRIDE * n_small)) != hipSuccess) ||
+      (P->d_small_pairs && (e = hipMemcpy(P->d_small_pairs, P->small_pairs.data(), sizeof(int) * n_small,
+                                          hipMemcpyHostToDevice)) != hipSuccess) ||
+      (P->d_large_pairs && (e = hipMemcpy(P->d_large_pairs, P->large_pairs.data(), sizeof(int) * n_large,
+                                          hipMemcpyHostToDevice)) != hipSuccess) ||
       (e = hipDeviceSynchronize()) != hipSuccess) {
     rheed_plan_destroy(P);
     return hip_fail(e, "hipMemcpy");
@@ -296,6 +333,9 @@ rheed_status rheed_plan_destroy(rheed_plan_t P) {
   if (P->d_bin_jk) (void)hipFree(P->d_bin_jk);
   if (P->d_pbwd) (void)hipFree(P->d_pbwd);
   if (P->d_xch) (void)hipFree(P->d_xch);
+  if (P->d_small_pairs) (void)hipFree(P->d_small_pairs);
+  if (P->d_large_pairs) (void)hipFree(P->d_large_pairs);
+  if (P->d_lscratch) (void)hipFree(P->d_lscratch);
   delete P;
   return RHEED_OK;
 }
@@ -312,6 +352,8 @@ rheed_status rheed_plan_get_info(rheed_plan_t P, rheed_plan_info* info) {
   info->bwd_workspace = P->bwd_ws;
   info->split = P->split ? 1 : 0;
   info->split_max_pairs = P->split_max;
+  info->large_pairs = (int32_t)P->large_pairs.size();
+  info->large_slots = P->large_slots;
   return RHEED_OK;
 }
 
@@ -361,6 +403,8 @@ rheed_status rheed_potential_backward(rheed_plan_t P, const double* atoms, const
 rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* angles, double* intensity, void* rho,
                            int32_t* pair_status, int32_t* n_rhst, void* workspace, size_t ws_bytes, void* stream) {
   if (!P || !U_tables || !angles || !intensity || !pair_status) return fail(RHEED_E_INVALID, "forward: null argument");
+  if (workspace && !P->large_pairs.empty())
+    return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs every structure to have N <= 64");
   if (workspace && ws_bytes < P->fwd_ws)
     return fail(RHEED_E_INVALID, "forward: workspace of " + std::to_string(ws_bytes) + " bytes < " +
                                      std::to_string(P->fwd_ws));
@@ -378,22 +422,41 @@ rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* a
   a.ck = P->ck;
   a.ld = P->max_beams;
   a.convention = (int)P->opts.convention;
-  a.n_pairs = P->n_pairs;
   a.threshold = P->opts.rhst_threshold;
-  hipError_t e;
-  if (P->split) {
-    a.xch = P->d_xch;
-    e = launch_forward_split((int)P->opts.stepper, a, static_cast<hipStream_t>(stream));
-  } else {
-    e = launch_forward((int)P->opts.stepper, a, static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (!P->small_pairs.empty()) {
+    a.pair_list = P->d_small_pairs;  // null when every pair is small
+    a.n_pairs = (int)P->small_pairs.size();
+    if (P->split) {
+      a.xch = P->d_xch;
+      e = launch_forward_split((int)P->opts.stepper, a, st);
+    } else {
+      e = launch_forward((int)P->opts.stepper, a, st);
+    }
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
   }
-  return e == hipSuccess ? RHEED_OK : hip_fail(e, "forward launch");
+  if (!P->large_pairs.empty()) {
+    LargeArgs la{};
+    la.f = a;
+    la.f.pair_list = P->d_large_pairs;  // null when every pair is large
+    la.f.n_pairs = (int)P->large_pairs.size();
+    la.f.ws = nullptr;
+    la.f.xch = nullptr;
+    la.scratch = P->d_lscratch;
+    la.n_slots = P->large_slots;
+    e = launch_forward_large((int)P->opts.stepper, la, st);
+    if (e != hipSuccess) return hip_fail(e, "forward launch (N > 64)");
+  }
+  return RHEED_OK;
 }
 
 rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* angles, const double* dL_dI,
                             void* dL_dU, void* workspace, size_t ws_bytes, void* stream) {
   if (!P || !U_tables || !angles || !dL_dI || !dL_dU || !workspace)
     return fail(RHEED_E_INVALID, "backward: null argument");
+  if (!P->large_pairs.empty())
+    return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs every structure to have N <= 64");
   if (ws_bytes < P->fwd_ws + P->bwd_ws)
     return fail(RHEED_E_INVALID, "backward: workspace of " + std::to_string(ws_bytes) + " bytes < " +
                                      std::to_string(P->fwd_ws + P->bwd_ws));

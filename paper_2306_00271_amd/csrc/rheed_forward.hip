@@ -212,7 +212,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
   const int lane = tid & 63;
   const int w = tid >> 6;
   const int RT = w & 3, CH = w >> 2;   // row tile, column block of this wave
-  const int p = blockIdx.x;
+  const int p = a.pair_list ? a.pair_list[blockIdx.x] : blockIdx.x;
   const StructDev S = a.structs[a.pair_struct[p]];
   const int N = S.n_beams;
   const int L = S.n_slices;
@@ -548,6 +548,10 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
     if (j < a.ld) {
       a.intensity[(long long)p * a.ld + j] = eta;
       if (a.rho) a.rho[(long long)p * a.ld + j] = rj;
+    }
+    for (int jt = NP + j; jt < a.ld; jt += NP) {  // outputs of a wider plan's padding
+      a.intensity[(long long)p * a.ld + jt] = 0.0;
+      if (a.rho) a.rho[(long long)p * a.ld + jt] = make_double2(0.0, 0.0);
     }
     const bool fin = isfinite(rj.x) && isfinite(rj.y);
     const unsigned long long bad = __ballot(!fin);
@@ -895,7 +899,8 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
   const int lane = tid & 63;
   const int w = tid >> 6;
   const int RT = w;                    // row tile of this wave
-  const int p = blockIdx.x >> 1, half = blockIdx.x & 1;
+  const int pi = blockIdx.x >> 1, half = blockIdx.x & 1;  // launch slot of the pair, half
+  const int p = a.pair_list ? a.pair_list[pi] : pi;
   const int col0 = HC * half;          // first column of this half
   const StructDev S = a.structs[a.pair_struct[p]];
   const int N = S.n_beams;
@@ -957,7 +962,7 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
   }
   const bool save = a.ws != nullptr;
   char* pws = save ? a.ws + (long long)p * a.ck.pair_stride : nullptr;
-  char* X = a.xch + (long long)p * XCH_STRIDE;
+  char* X = a.xch + (long long)pi * XCH_STRIDE;
   unsigned long long* cnt_me = reinterpret_cast<unsigned long long*>(X) + half;
   unsigned long long* cnt_other = reinterpret_cast<unsigned long long*>(X) + (1 - half);
   double* xi_g = reinterpret_cast<double*>(X + XCH_XI);       // [half][parity][2][NP]
@@ -1183,6 +1188,10 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
     if (j < a.ld) {
       a.intensity[(long long)p * a.ld + j] = eta;
       if (a.rho) a.rho[(long long)p * a.ld + j] = rj;
+    }
+    for (int jt = NP + j; jt < a.ld; jt += NP) {  // outputs of a wider plan's padding
+      a.intensity[(long long)p * a.ld + jt] = 0.0;
+      if (a.rho) a.rho[(long long)p * a.ld + jt] = make_double2(0.0, 0.0);
     }
     const bool fin = isfinite(rj.x) && isfinite(rj.y);
     const unsigned long long bad = __ballot(!fin);

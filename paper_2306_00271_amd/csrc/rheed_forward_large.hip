@@ -1,0 +1,641 @@
+// Forward propagation for 64 < N <= 128 beams on gfx950.
+//
+// The state Z = [c; c'] of a pair padded to 128 beams (two 128 x 128 complex
+// blocks, 512 KB) does not fit on one CU, so it lives in a slot of device
+// memory owned by the workgroup running the pair.  The RK stages act on the
+// columns of Z independently (Sec. 3.4: the right-hand side is B(z) Z), so a
+// slice is stepped in eight blocks of 16 columns: each wave of the 8-wave
+// workgroup reads its 16 x 16 tile of the block's c and c' into registers,
+// the s stages run with the stage input X_r of the block in LDS, and the tile
+// goes back to memory.  Per slice the slot sees 1 MB of reads and writes
+// against 7 x 8 x 128^3 flop (RK6), so the stage loop stays on the matrix
+// cores.  The stages are the same Nystrom form as in the N <= 64 kernels:
+// products G_r = M(z_i + c_r h) X_r with M = U + Gamma^2,
+//   X_r = c + h c_r c' - h^2 sum_m (A^2)_{rm} G_m,
+//   c <- c + h c' - h^2 sum_m (bA)_m G_m,   c' <- c' - h sum_m b_m G_m,
+// each a complex 128 x 16 x 128 product in the 3-real-product form on
+// v_mfma_f64_16x16x4f64, with U_{jk} = u_{g_j - g_k} gathered from the node's
+// rod-difference table in LDS.
+//
+// After every slice the Gershgorin / Varah estimate of cond(Q), Q = c, over
+// rows and columns < N decides the right-hand-side transformation
+// Z <- Z Q^{-1} (Sec. 3.2, Algorithm 1).  It runs in two passes over rows held
+// in registers (wave w: rows w + 8 m, two columns per lane): a column
+// Gauss-Jordan elimination of Q with partial pivoting records the multipliers
+// and pivot column of every step, Q E = Pi (E the product of the column
+// operations, Pi a permutation); the same operations are then replayed on the
+// rows of P, and P E with its columns put back in pivot order is P Q^{-1};
+// c <- I.  The reflection (Eq. vrhocomp) eliminates Gamma Q - iP the same
+// way; its first inverse column is E e_{pc_0}, formed by applying the recorded
+// operations to a unit vector in reverse order, and rho = (Gamma Q + iP) x.
+//
+// The launch is a persistent grid of one workgroup per CU (the LDS holds one);
+// workgroup b runs pairs b, b + grid, ...; no workgroup waits for another.
+#include "rheed_large.h"
+#include "rheed_gj.h"
+
+namespace rheed {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int LW = 8;              // waves per workgroup
+constexpr int LT = LW * 64;        // threads per workgroup
+constexpr int LCB = 16;            // columns per block
+constexpr int NCB = NL / LCB;      // column blocks
+constexpr int LNE = 4;             // tile elements per lane (one 16 x 16 tile)
+constexpr int LQ = NL / 4;         // k-steps of 4 in one product
+constexpr int LRM = NL / LW;       // rows per wave in the eliminations
+
+// Explicit RK tableaux in the Nystrom form above: node fraction c_r, the
+// node's offset in the slice's table ring, A^2, bA and b (classical RK4 and
+// Butcher's seventh-stage sixth-order method).
+template <int S>
+struct LTab;
+template <>
+struct LTab<0> {
+  static constexpr int stages = 4, nodes = 2;
+  static constexpr __device__ double c(int r) { return r == 0 ? 0.0 : r == 3 ? 1.0 : 0.5; }
+  static constexpr __device__ int node(int r) { return r == 0 ? 0 : r == 3 ? 2 : 1; }
+  static constexpr __device__ double a2(int r, int m) {
+    return (r == 2 && m == 0) ? 0.25 : (r == 3 && m == 1) ? 0.5 : 0.0;
+  }
+  static constexpr __device__ double ba(int m) { return m < 3 ? 1.0 / 6.0 : 0.0; }
+  static constexpr __device__ double b(int m) { return (m == 0 || m == 3) ? 1.0 / 6.0 : 1.0 / 3.0; }
+};
+template <>
+struct LTab<1> {
+  static constexpr int stages = 7, nodes = 4;
+  static constexpr __device__ double c(int r) {
+    return r == 0 ? 0.0 : r == 1 ? 1.0 / 3.0 : r == 2 ? 2.0 / 3.0 : r == 3 ? 1.0 / 3.0 : r == 6 ? 1.0 : 0.5;
+  }
+  static constexpr __device__ int node(int r) {  // c = 0, 1/3, 1/2, 2/3 -> 0..3; c = 1 -> 4
+    return r == 0 ? 0 : r == 1 ? 1 : r == 2 ? 3 : r == 3 ? 1 : r == 6 ? 4 : 2;
+  }
+  static constexpr __device__ double a2(int r, int m) {
+    return r == 2 ? (m == 0 ? 2.0 / 9.0 : 0.0)
+         : r == 3 ? (m == 0 ? 1.0 / 9.0 : m == 1 ? -1.0 / 18.0 : 0.0)
+         : r == 4 ? (m == 0 ? 11.0 / 32.0 : m == 1 ? -0.25 : m == 2 ? 1.0 / 32.0 : 0.0)
+         : r == 5 ? (m == 0 ? 9.0 / 32.0 : m == 1 ? 1.0 / 16.0 : m == 2 ? -1.0 / 32.0 : m == 3 ? -3.0 / 16.0 : 0.0)
+         : r == 6 ? (m == 0 ? -3.0 / 22.0 : m == 1 ? -3.0 / 22.0 : m == 2 ? 9.0 / 22.0 : m == 3 ? 12.0 / 11.0
+                   : m == 4 ? -8.0 / 11.0 : 0.0)
+         : 0.0;
+  }
+  static constexpr __device__ double ba(int m) {
+    return m == 0 ? 11.0 / 120.0 : m == 2 ? 9.0 / 40.0 : m == 3 ? 9.0 / 20.0 : (m == 4 || m == 5) ? -2.0 / 15.0 : 0.0;
+  }
+  static constexpr __device__ double b(int m) {
+    return (m == 0 || m == 6) ? 11.0 / 120.0 : (m == 2 || m == 3) ? 27.0 / 40.0 : (m == 4 || m == 5) ? -4.0 / 15.0 : 0.0;
+  }
+};
+
+struct LLds {
+  double2 xb[NL * LCB];            // stage input of one column block; pivot rows during eliminations
+  double2 tb[5][MAXBOXL + 1];      // node tables of the slice (ring); entry `box` of every row stays 0
+  int bhk[NL][2];
+  double g2s[NL];                  // Gamma_j^2, 0 on padding
+  double rdg[NL], rof[NL];         // per row: |q_ii| and sum_{j != i} |q_ij| over j < N
+  int pcrec[NL];                   // pivot column of every elimination step
+  unsigned gix[LQ / 2][LT];        // per thread: packed table indices of its A operand entries
+  double2 xv[NL];                  // first column of the inverse in the reflection
+  int flag_singular;
+  int bad;
+};
+
+__shared__ LLds large_lds;
+
+struct LMat {
+  double r[LNE];
+  double i[LNE];
+};
+
+// Rows m0 .. LRM-1 of z: column j <- column j - f_j column pc, with pc =
+// 64 HF + pl (the pivot column's half is wave-uniform, so it selects code
+// instead of data).
+template <int HF>
+__device__ __forceinline__ void col_update(double2 (&z)[LRM][2], int m0, int pl, double2 f0, double2 f1) {
+#pragma unroll
+  for (int m = 0; m < LRM; ++m) {
+    if (m < m0) continue;
+    const double2 zp = make_double2(readlane_f64(z[m][HF].x, pl), readlane_f64(z[m][HF].y, pl));
+    z[m][0].x = fma(-f0.x, zp.x, z[m][0].x);
+    z[m][0].x = fma(f0.y, zp.y, z[m][0].x);
+    z[m][0].y = fma(-f0.x, zp.y, z[m][0].y);
+    z[m][0].y = fma(-f0.y, zp.x, z[m][0].y);
+    z[m][1].x = fma(-f1.x, zp.x, z[m][1].x);
+    z[m][1].x = fma(f1.y, zp.y, z[m][1].x);
+    z[m][1].y = fma(-f1.x, zp.y, z[m][1].y);
+    z[m][1].y = fma(-f1.y, zp.x, z[m][1].y);
+  }
+}
+
+__device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// (U X) for the wave's 16 x 16 tile: A = U gathered from the node table,
+// B = X of the block in LDS (row stride LCB).  Element v of the result
+// belongs to row 16 w + 4 v + (lane >> 4), block column lane & 15.
+__device__ __forceinline__ void gemm_tile(const double2* __restrict__ xb, const double2* __restrict__ tsl,
+                                          const unsigned (&gidx)[LQ / 2], int lane, LMat& out) {
+  __builtin_amdgcn_sched_barrier(0);
+  d4 t1 = d4{0, 0, 0, 0}, t2 = t1, t3 = t1;
+  int bb = (lane >> 4) * LCB + (lane & 15);
+  asm volatile("" : "+v"(bb));  // keep the addresses from being hoisted out of the caller's loops
+#pragma unroll
+  for (int q = 0; q < LQ; ++q) {
+    const unsigned gi = (q & 1) ? (gidx[q >> 1] >> 16) : (gidx[q >> 1] & 0xffffu);
+    const double2 u = tsl[gi];
+    const double2 x = xb[bb + 4 * LCB * q];
+    t1 = mfma(u.x, x.x, t1);
+    t2 = mfma(u.y, x.y, t2);
+    t3 = mfma(u.x + u.y, x.x + x.y, t3);
+    if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    out.r[v] = t1[v] - t2[v];
+    out.i[v] = t3[v] - t1[v] - t2[v];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// One RK step of one column block: c, d (= c') of the wave's tile in, the
+// stepped tile out.  xb holds X_r of the block while its product runs.
+template <int STEPPER>
+__device__ __forceinline__ void step_block(LLds& s, LMat& c, LMat& d, const unsigned (&gidx)[LQ / 2],
+                                           const double (&g2)[4], int ob, int lane, int nb, double h) {
+  using T = LTab<STEPPER>;
+  constexpr int SL = T::nodes + 1;
+  const double hh = h * h;
+  LMat G[T::stages];
+  LMat cn, dn;
+#pragma unroll
+  for (int e = 0; e < LNE; ++e) {
+    cn.r[e] = c.r[e] + h * d.r[e];
+    cn.i[e] = c.i[e] + h * d.i[e];
+    dn.r[e] = d.r[e];
+    dn.i[e] = d.i[e];
+  }
+#pragma unroll
+  for (int r = 0; r < T::stages; ++r) {
+    LMat X;
+    const double hc = h * T::c(r);
+#pragma unroll
+    for (int e = 0; e < LNE; ++e) {
+      double xr = c.r[e] + hc * d.r[e], xi = c.i[e] + hc * d.i[e];
+#pragma unroll
+      for (int m = 0; m < r; ++m) {
+        if (T::a2(r, m) != 0.0) {
+          xr -= hh * T::a2(r, m) * G[m].r[e];
+          xi -= hh * T::a2(r, m) * G[m].i[e];
+        }
+      }
+      X.r[e] = xr;
+      X.i[e] = xi;
+      s.xb[ob + 4 * LCB * e] = make_double2(xr, xi);
+    }
+    __syncthreads();
+    gemm_tile(s.xb, s.tb[(nb + T::node(r)) % SL], gidx, lane, G[r]);
+#pragma unroll
+    for (int e = 0; e < LNE; ++e) {
+      G[r].r[e] += g2[e] * X.r[e];
+      G[r].i[e] += g2[e] * X.i[e];
+      if (T::ba(r) != 0.0) {
+        cn.r[e] -= hh * T::ba(r) * G[r].r[e];
+        cn.i[e] -= hh * T::ba(r) * G[r].i[e];
+      }
+      dn.r[e] -= h * T::b(r) * G[r].r[e];
+      dn.i[e] -= h * T::b(r) * G[r].i[e];
+    }
+    __syncthreads();
+  }
+  c = cn;
+  d = dn;
+}
+
+// Column Gauss-Jordan elimination of the n x n leading block of the matrix
+// whose rows w + 8 m sit in z[m] (column lane in [0], 64 + lane in [1]),
+// recording what the other passes replay: the multipliers f of step k in
+// frec[k][.] and its pivot column in pcrec[k].  Step k takes, among unused
+// columns < n, the one with the largest |A_kj| (key: the upper 32 bits of
+// |A_kj|^2 with the low 7 bits replaced by 127 - j, so near-ties go to the
+// smaller index), pc; f_j = A_kj / A_k,pc and f_pc = 1 - 1 / A_k,pc; then
+// column j <- column j - f_j column pc for every j, which leaves row k a unit
+// row.  pos[h] receives, for the lane's column 64 h + lane, the step at which
+// it was the pivot (its own index if never).  Rows of earlier blocks of 8
+// are unit rows with a zero in every later pivot column, so they are skipped.
+template <int KB>
+struct GjRec {
+  static __device__ __forceinline__ void run(double2 (&z)[LRM][2], int n, int lane, int wu, bool (&used)[2],
+                                             int (&pos)[2], double2* rowbuf, double2* frec, int* pcrec,
+                                             int* flag_singular) {
+    if (KB * LW >= n) return;
+#pragma unroll 1
+    for (int kk = 0; kk < LW; ++kk) {
+      const int k = KB * LW + kk;
+      if (k >= n) return;
+      const int slot = k & 1;
+      __syncthreads();
+      const double2 v0 = rowbuf[slot * NL + lane], v1 = rowbuf[slot * NL + 64 + lane];
+      const double m0 = v0.x * v0.x + v0.y * v0.y, m1 = v1.x * v1.x + v1.y * v1.y;
+      unsigned k0 = 0, k1 = 0;
+      if (!used[0] && lane < n)
+        k0 = ((unsigned)(((unsigned long long)__double_as_longlong(m0)) >> 32) & ~127u) | (unsigned)(127 - lane);
+      if (!used[1] && 64 + lane < n)
+        k1 = ((unsigned)(((unsigned long long)__double_as_longlong(m1)) >> 32) & ~127u) | (unsigned)(63 - lane);
+      const unsigned key = wave_max_u32(k0 > k1 ? k0 : k1);
+      if ((key >> 7) == 0 && lane == 0 && wu == 0) *flag_singular = 1;
+      const int pc = 127 - (int)(key & 127);
+      const int hf = pc >> 6, pl = pc & 63;
+      if (lane == pl) {
+        if (hf) {
+          used[1] = true;
+          pos[1] = k;
+        } else {
+          used[0] = true;
+          pos[0] = k;
+        }
+      }
+      const double2 vs = hf ? v1 : v0;
+      const double2 piv = make_double2(readlane_f64(vs.x, pl), readlane_f64(vs.y, pl));
+      const double inv = 1.0 / (piv.x * piv.x + piv.y * piv.y);
+      const double2 ip = make_double2(piv.x * inv, -piv.y * inv);
+      double2 f0 = make_double2(v0.x * ip.x - v0.y * ip.y, v0.x * ip.y + v0.y * ip.x);
+      double2 f1 = make_double2(v1.x * ip.x - v1.y * ip.y, v1.x * ip.y + v1.y * ip.x);
+      if (lane == pl) {
+        if (hf) f1 = make_double2(1.0 - ip.x, -ip.y);
+        else f0 = make_double2(1.0 - ip.x, -ip.y);
+      }
+      if (wu == 0) {
+        frec[k * NL + lane] = f0;
+        frec[k * NL + 64 + lane] = f1;
+        if (lane == 0) pcrec[k] = pc;
+      }
+      if (hf) col_update<1>(z, KB, pl, f0, f1);
+      else col_update<0>(z, KB, pl, f0, f1);
+      if (k + 1 < n && wu == (k + 1) % LW) {  // row k + 1: register KB, or KB + 1 after the block's last step
+        constexpr int RB = KB + 1 < LRM ? KB + 1 : KB;
+        const bool same = kk + 1 < LW;  // select values, not addresses, so z stays in registers
+        const double2 a0 = z[KB][0], a1 = z[KB][1], b0 = z[RB][0], b1 = z[RB][1];
+        rowbuf[(slot ^ 1) * NL + lane] = make_double2(same ? a0.x : b0.x, same ? a0.y : b0.y);
+        rowbuf[(slot ^ 1) * NL + 64 + lane] = make_double2(same ? a1.x : b1.x, same ? a1.y : b1.y);
+      }
+    }
+    GjRec<KB + 1>::run(z, n, lane, wu, used, pos, rowbuf, frec, pcrec, flag_singular);
+  }
+};
+template <>
+struct GjRec<LRM> {
+  static __device__ __forceinline__ void run(double2 (&)[LRM][2], int, int, int, bool (&)[2], int (&)[2], double2*,
+                                             double2*, int*, int*) {}
+};
+
+__device__ __forceinline__ void eliminate(double2 (&z)[LRM][2], int n, int lane, int w, int (&pos)[2], LLds& s,
+                                          double2* frec) {
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  bool used[2] = {false, false};
+  pos[0] = lane;
+  pos[1] = 64 + lane;
+  double2* rowbuf = s.xb;
+  __syncthreads();  // rowbuf aliases the stage buffer
+  if (wu == 0) {
+    rowbuf[lane] = z[0][0];
+    rowbuf[64 + lane] = z[0][1];
+  }
+  GjRec<0>::run(z, n, lane, wu, used, pos, rowbuf, frec, s.pcrec, &s.flag_singular);
+  __threadfence();
+  __syncthreads();
+}
+
+// z <- z E: the recorded column operations of steps 0 .. n-1 on the rows in z.
+__device__ __forceinline__ void replay(double2 (&z)[LRM][2], int n, int lane, const LLds& s,
+                                       const double2* __restrict__ frec) {
+  double2 g0 = frec[lane], g1 = frec[64 + lane];
+#pragma unroll 1
+  for (int k = 0; k < n; ++k) {
+    const double2 f0 = g0, f1 = g1;
+    if (k + 1 < n) {  // next step's multipliers in flight during this step
+      g0 = frec[(k + 1) * NL + lane];
+      g1 = frec[(k + 1) * NL + 64 + lane];
+    }
+    const int pc = __builtin_amdgcn_readfirstlane(s.pcrec[k]);
+    const int hf = pc >> 6, pl = pc & 63;
+    if (hf) col_update<1>(z, 0, pl, f0, f1);
+    else col_update<0>(z, 0, pl, f0, f1);
+  }
+}
+
+// One slice for column block cb: the wave's 16 x 16 tile of c and c' from
+// the slot, one RK step, back to the slot; the row sums of |q_ij| (j < N) over
+// the block's columns go into s.rdg (diagonal) and s.rof (the rest), set by
+// block 0 and added to by the others (each row belongs to one lane of one
+// wave).  Kept out of line so that its registers are allocated apart from
+// the eliminations'.
+template <int STEPPER>
+__device__ __noinline__ void slice_block(double2* __restrict__ cg, double2* __restrict__ dg, int cb, int nb,
+                                         double h, int N) {
+  LLds& s = large_lds;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  unsigned gidx[LQ / 2];
+#pragma unroll
+  for (int q = 0; q < LQ / 2; ++q) gidx[q] = s.gix[q][tid];
+  double g2[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) g2[v] = s.g2s[16 * w + 4 * v + (lane >> 4)];
+  // the wave's tile: rows 16 w + 4 e + (lane >> 4), block column lane & 15
+  const int ob = (16 * w + (lane >> 4)) * LCB + (lane & 15);
+  const int gb = (16 * w + (lane >> 4)) * NL + LCB * cb + (lane & 15);
+  LMat c, d;
+#pragma unroll
+  for (int e = 0; e < LNE; ++e) {
+    const double2 cv = cg[gb + 4 * NL * e], dv = dg[gb + 4 * NL * e];
+    c.r[e] = cv.x;
+    c.i[e] = cv.y;
+    d.r[e] = dv.x;
+    d.i[e] = dv.y;
+  }
+  step_block<STEPPER>(s, c, d, gidx, g2, ob, lane, nb, h);
+  double pdg[4], pof[4];
+#pragma unroll
+  for (int e = 0; e < LNE; ++e) {
+    cg[gb + 4 * NL * e] = make_double2(c.r[e], c.i[e]);
+    dg[gb + 4 * NL * e] = make_double2(d.r[e], d.i[e]);
+    const int row = 16 * w + 4 * e + (lane >> 4), col = LCB * cb + (lane & 15);
+    const double av = sqrt(c.r[e] * c.r[e] + c.i[e] * c.i[e]);
+    const bool in = row < N && col < N;
+    pdg[e] = (in && row == col) ? av : 0.0;
+    pof[e] = (in && row != col) ? av : 0.0;
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      pdg[v] += __shfl_xor(pdg[v], off, 64);
+      pof[v] += __shfl_xor(pof[v], off, 64);
+    }
+  }
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * w + 4 * v + (lane >> 4);
+      s.rdg[row] = (cb == 0 ? 0.0 : s.rdg[row]) + pdg[v];
+      s.rof[row] = (cb == 0 ? 0.0 : s.rof[row]) + pof[v];
+    }
+  }
+}
+
+// Z <- Z Q^{-1}: eliminate Q (recording), replay the column operations on
+// the rows of P, put the columns back in pivot order; c <- I.
+__device__ __noinline__ void rhst_pass(double2* __restrict__ cg, double2* __restrict__ dg, double2* __restrict__ frec,
+                                       int N) {
+  LLds& s = large_lds;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double2 z[LRM][2];
+  int pos[2];
+#pragma unroll
+  for (int m = 0; m < LRM; ++m) {
+    z[m][0] = cg[(w + LW * m) * NL + lane];
+    z[m][1] = cg[(w + LW * m) * NL + 64 + lane];
+  }
+  eliminate(z, N, lane, w, pos, s, frec);
+#pragma unroll
+  for (int m = 0; m < LRM; ++m) {
+    z[m][0] = dg[(w + LW * m) * NL + lane];
+    z[m][1] = dg[(w + LW * m) * NL + 64 + lane];
+  }
+  replay(z, N, lane, s, frec);
+#pragma unroll
+  for (int m = 0; m < LRM; ++m) {
+    const int row = w + LW * m;
+    dg[row * NL + pos[0]] = z[m][0];
+    dg[row * NL + pos[1]] = z[m][1];
+    cg[row * NL + lane] = make_double2(row == lane ? 1.0 : 0.0, 0.0);
+    cg[row * NL + 64 + lane] = make_double2(row == 64 + lane ? 1.0 : 0.0, 0.0);
+  }
+  (void)tid;
+  __threadfence();
+  __syncthreads();
+}
+
+// Elimination of upper = Gamma Q - iP (recording) for the reflection.
+__device__ __noinline__ void reflect_eliminate(const double2* __restrict__ cg, const double2* __restrict__ dg,
+                                               double2* __restrict__ frec, int N) {
+  LLds& s = large_lds;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double2 z[LRM][2];
+  int pos[2];
+#pragma unroll
+  for (int m = 0; m < LRM; ++m) {
+    const int row = w + LW * m;
+    const double g2v = s.g2s[row];
+    const double g_r = g2v >= 0.0 ? sqrt(g2v) : 0.0, g_i = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
+#pragma unroll
+    for (int hf = 0; hf < 2; ++hf) {
+      const double2 cv = cg[row * NL + 64 * hf + lane], pv = dg[row * NL + 64 * hf + lane];
+      z[m][hf] = make_double2(g_r * cv.x - g_i * cv.y + pv.y, g_r * cv.y + g_i * cv.x - pv.x);
+    }
+  }
+  eliminate(z, N, lane, w, pos, s, frec);
+}
+
+template <int STEPPER>
+__device__ void run_pair(const LargeArgs& A, int p, char* slot) {
+  using T = LTab<STEPPER>;
+  constexpr int SL = T::nodes + 1;
+  const FwdArgs& a = A.f;
+  LLds& s = large_lds;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double2* __restrict__ cg = reinterpret_cast<double2*>(slot + LSLOT_C);
+  double2* __restrict__ dg = reinterpret_cast<double2*>(slot + LSLOT_D);
+  double2* __restrict__ frec = reinterpret_cast<double2*>(slot + LSLOT_F);
+  const StructDev S = a.structs[a.pair_struct[p]];
+  const int N = S.n_beams;
+  const int L = S.n_slices;
+  const double h = S.h;
+  const double2* __restrict__ Us = a.U + S.table_off;
+
+  if (tid < NL) {
+    s.bhk[tid][0] = tid < N ? a.beams[2 * (S.beam_off + tid)] : 0;
+    s.bhk[tid][1] = tid < N ? a.beams[2 * (S.beam_off + tid) + 1] : 0;
+  }
+  if (tid == 0) {
+    s.flag_singular = 0;
+    s.bad = 0;
+  }
+  if (tid < SL) s.tb[tid][S.box] = make_double2(0.0, 0.0);
+  __syncthreads();
+  const double th0 = a.angles[2 * p], th1 = a.angles[2 * p + 1];
+  if (tid < NL) {
+    // Gamma_j^2 = gamma^2 - |b0 + k_j|^2 (Sec. 2.1), b0 = gamma cos(theta0) (cos theta1, sin theta1)
+    const double b0x = S.gamma * cos(th0) * cos(th1);
+    const double b0y = S.gamma * cos(th0) * sin(th1);
+    double arg = 0.0;
+    if (tid < N) {
+      const double qx = b0x + s.bhk[tid][0] * S.recip[0] + s.bhk[tid][1] * S.recip[2];
+      const double qy = b0y + s.bhk[tid][0] * S.recip[1] + s.bhk[tid][1] * S.recip[3];
+      arg = S.gamma * S.gamma - (qx * qx + qy * qy);
+    }
+    s.g2s[tid] = arg;
+  }
+  __syncthreads();
+  // gather indices of U_{ik} = u_{g_i - g_k} for the thread's A operand entries
+  // (row 16 w + (lane & 15), k = 4 q + (lane >> 4)); padding reads entry `box` = 0
+  {
+    const int W = 2 * S.kd + 1;
+    const int iA = 16 * w + (lane & 15);
+    const int baseA = (s.bhk[iA][0] + S.hd) * W + (s.bhk[iA][1] + S.kd);
+#pragma unroll 4
+    for (int q = 0; q < LQ; q += 2) {
+      const int k0 = 4 * q + (lane >> 4), k1 = 4 * (q + 1) + (lane >> 4);
+      const unsigned i0 = (iA < N && k0 < N) ? baseA - (s.bhk[k0][0] * W + s.bhk[k0][1]) : S.box;
+      const unsigned i1 = (iA < N && k1 < N) ? baseA - (s.bhk[k1][0] * W + s.bhk[k1][1]) : S.box;
+      s.gix[q >> 1][tid] = i0 | (i1 << 16);
+    }
+  }
+  // Z0 = [I; i Gamma] (spans the columns of S^{-1}[I; O] of Algorithm 1), rows
+  // of the state row major in the slot
+  for (int e = tid; e < NL * NL; e += LT) {
+    const int row = e / NL, col = e - row * NL;
+    const double g2v = s.g2s[row];
+    const bool dgn = row == col;
+    cg[e] = make_double2(dgn ? 1.0 : 0.0, 0.0);
+    dg[e] = make_double2((dgn && g2v < 0.0) ? sqrt(-g2v) : 0.0, (dgn && g2v >= 0.0) ? sqrt(g2v) : 0.0);
+  }
+  for (int e = tid; e < S.box; e += LT) s.tb[0][e] = Us[e];
+  int nrhst = 0;
+
+#pragma unroll 1
+  for (int i = 0; i < L; ++i) {
+    const int nb = i * T::nodes;
+    {  // this slice's nodes after c = 0 (node nb came with the previous slice)
+      const int total = T::nodes * S.box;
+      for (int e = tid; e < total; e += LT) {
+        const int q = e / S.box, j = e - q * S.box;
+        s.tb[(nb + 1 + q) % SL][j] = Us[(long long)(nb + 1 + q) * S.box + j];
+      }
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int cb = 0; cb < NCB; ++cb) slice_block<STEPPER>(cg, dg, cb, nb, h, N);
+    __syncthreads();
+    // condition estimate of Q = c (Sec. 3.2): the Gershgorin / Varah bound
+    // max_i(|q_ii| + r_i) / min_i(|q_ii| - r_i), r_i = sum_{j != i} |q_ij|
+    bool do_rhst;
+    {
+      double hi = 0.0, lo = 1.0e308;
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) {
+        const int row = 64 * hf + lane;
+        if (row < N) {
+          const double dv = s.rdg[row], ov = s.rof[row];
+          hi = fmax(hi, dv + ov);
+          lo = fmin(lo, dv - ov);
+        }
+      }
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+      }
+      const double xi = lo > 0.0 ? hi / lo : INFINITY;
+      do_rhst = xi > a.threshold;
+    }
+    if (do_rhst) {
+      ++nrhst;
+      rhst_pass(cg, dg, frec, N);
+    }
+  }
+
+  // reflection (Eq. vrhocomp): upper = Gamma Q - iP, lower = Gamma Q + iP,
+  // rho = lower x with upper x = e_1
+  reflect_eliminate(cg, dg, frec, N);
+  if (w == 0) {
+    // x = E e_{pc_0}: the recorded operations in reverse order, each
+    // v <- v - e_pc (f . v)
+    const int pc0 = s.pcrec[0];
+    double2 v0 = make_double2(lane == pc0 ? 1.0 : 0.0, 0.0), v1 = make_double2(64 + lane == pc0 ? 1.0 : 0.0, 0.0);
+#pragma unroll 1
+    for (int k = N - 1; k >= 0; --k) {
+      const double2 f0 = frec[k * NL + lane], f1 = frec[k * NL + 64 + lane];
+      double sr = (f0.x * v0.x - f0.y * v0.y) + (f1.x * v1.x - f1.y * v1.y);
+      double si = (f0.x * v0.y + f0.y * v0.x) + (f1.x * v1.y + f1.y * v1.x);
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        sr += __shfl_xor(sr, off, 64);
+        si += __shfl_xor(si, off, 64);
+      }
+      const int pc = __builtin_amdgcn_readfirstlane(s.pcrec[k]);
+      if (lane == (pc & 63)) {
+        if (pc >> 6) v1 = make_double2(v1.x - sr, v1.y - si);
+        else v0 = make_double2(v0.x - sr, v0.y - si);
+      }
+    }
+    s.xv[lane] = v0;
+    s.xv[64 + lane] = v1;
+  }
+  __syncthreads();
+  if (tid < a.ld) {
+    const int j = tid;
+    double eta = 0.0;
+    double2 rj = make_double2(0.0, 0.0);
+    if (j < N) {
+      const double g2v = s.g2s[j];
+      const double g_r = g2v >= 0.0 ? sqrt(g2v) : 0.0, g_i = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
+      for (int k = 0; k < N; ++k) {
+        const double2 cv = cg[j * NL + k], pv = dg[j * NL + k], x = s.xv[k];
+        const double lr = g_r * cv.x - g_i * cv.y - pv.y, li = g_r * cv.y + g_i * cv.x + pv.x;
+        rj.x += lr * x.x - li * x.y;
+        rj.y += lr * x.y + li * x.x;
+      }
+      if (g2v > 0.0) {
+        eta = (rj.x * rj.x + rj.y * rj.y) * sqrt(s.g2s[0]) / sqrt(g2v);
+        if (a.convention == 1) eta *= sin(th0);
+      }
+      if (!(isfinite(rj.x) && isfinite(rj.y))) atomicOr(&s.bad, 1);
+    }
+    a.intensity[(long long)p * a.ld + j] = eta;
+    if (a.rho) a.rho[(long long)p * a.ld + j] = rj;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    a.status[p] = s.flag_singular ? 1 : s.bad ? 2 : 0;
+    if (a.nrhst) a.nrhst[p] = nrhst;
+  }
+}
+
+template <int STEPPER>
+__global__ __launch_bounds__(LT, 1) void forward_large_kernel(LargeArgs A) {
+  char* slot = A.scratch + (long long)blockIdx.x * LSLOT_BYTES;
+#pragma unroll 1
+  for (int pi = blockIdx.x; pi < A.f.n_pairs; pi += gridDim.x) {
+    const int p = A.f.pair_list ? A.f.pair_list[pi] : pi;
+    run_pair<STEPPER>(A, p, slot);
+    __syncthreads();  // LDS is reused by the next pair
+  }
+}
+
+}  // namespace
+
+hipError_t launch_forward_large(int stepper, const LargeArgs& a, hipStream_t stream) {
+  if (a.f.n_pairs < 1) return hipSuccess;
+  const int grid = a.f.n_pairs < a.n_slots ? a.f.n_pairs : a.n_slots;
+  if (grid < 1) return hipErrorInvalidValue;
+  if (stepper == 0)
+    hipLaunchKernelGGL(forward_large_kernel<0>, dim3(grid), dim3(LT), 0, stream, a);
+  else
+    hipLaunchKernelGGL(forward_large_kernel<1>, dim3(grid), dim3(LT), 0, stream, a);
+  return hipGetLastError();
+}
+
+int forward_large_slots(int device) {
+  int cus = 0, per0 = 0, per1 = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per0, forward_large_kernel<0>, LT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, forward_large_kernel<1>, LT, 0) != hipSuccess)
+    return 0;
+  const int per = per0 < per1 ? per0 : per1;
+  return cus * (per > 0 ? per : 0);
+}
+
+}  // namespace rheed

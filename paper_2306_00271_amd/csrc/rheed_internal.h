@@ -38,6 +38,7 @@ struct CkptLayout {
 struct FwdArgs {
   const StructDev* structs;
   const int* pair_struct;
+  const int* pair_list;      // pair of each launch slot (n_pairs entries), or null: slot = pair
   const int* beams;          // packed [.][2]
   const double2* U;          // all tables
   const double* angles;      // [P][2]
@@ -49,7 +50,7 @@ struct FwdArgs {
   CkptLayout ck;
   int ld;
   int convention;
-  int n_pairs;
+  int n_pairs;               // pairs of this launch
   int pad;
   double threshold;
   // split launches (two workgroups per pair): per-pair exchange blocks

@@ -1,0 +1,29 @@
+// Internal descriptors of the 64 < N <= 128 forward path.
+#pragma once
+#include "rheed_internal.h"
+
+namespace rheed {
+
+constexpr int NL = 128;         // padded beam count of the large kernel
+constexpr int MAXBOXL = 1024;   // rod-difference entries per node table row in its LDS
+
+// Device memory of one resident workgroup of the large kernel: c and c' of
+// the pair it is running ([NL][NL] complex each, row major) and the column
+// operations of its last elimination ([NL][NL] complex: multipliers of step k
+// in row k).
+constexpr long long LSLOT_C = 0;
+constexpr long long LSLOT_D = (long long)NL * NL * 16;
+constexpr long long LSLOT_F = 2LL * NL * NL * 16;
+constexpr long long LSLOT_BYTES = 3LL * NL * NL * 16;
+
+struct LargeArgs {
+  FwdArgs f;       // f.pair_list / f.n_pairs: the pairs with N > 64
+  char* scratch;   // n_slots * LSLOT_BYTES, plan-owned
+  int n_slots;     // workgroups of the launch (each loops over pairs)
+  int pad;
+};
+
+hipError_t launch_forward_large(int stepper, const LargeArgs& a, hipStream_t stream);
+int forward_large_slots(int device);  // resident workgroups of the large kernel on the device
+
+}  // namespace rheed
