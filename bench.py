@@ -143,19 +143,92 @@ def traffic_probe(checkpoint_every):
                       "kernel": kernel_name(plan.split), "checkpoint_every": checkpoint_every}))
 
 
+# ------------------------------------------------------ uneven-N workload
+def uneven_forward(n_structures, steps=2):
+    """Forward throughput on the first n_structures of the uneven-N batched
+    workload (N drawn from {31, 61, 91, 121}, 64 angles each, 400 slices,
+    RK6): the whole batch through one rheed_forward call (N <= 64 pairs on the
+    one-workgroup kernel, the rest on the N > 64 kernel), then the N > 64
+    pairs alone for the large kernel's algorithmic rate, and one pair of each
+    N alone for the per-angle form."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from paper_2306_00271_amd import api
+    from synth import config3
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    wl = config3(n_structures)
+
+    def timed(w, reps):
+        plan = api.plan_for(w, stepper="rk6")
+        U = plan.potential(api.atoms_for(w, dev))
+        ang = api.angles_for(w, dev)
+        plan.forward(U, ang)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            out = plan.forward(U, ang, want_nrhst=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return plan, e0.elapsed_time(e1) / reps, out
+
+    plan, ms, out = timed(wl, steps)
+    n_pairs = plan.n_pairs
+    bad = int((out["status"] != 0).sum().item())
+    big = [st for st in wl.structures if st.n_beams > 64]
+    res = {"structures": n_structures, "pairs": n_pairs, "ms_per_forward": round(ms, 3),
+           "value": round(n_pairs / (ms / 1e3), 2), "unit": "points/s", "bad_pairs": bad,
+           "beams": {str(n): sum(1 for st in wl.structures if st.n_beams == n) for n in (31, 61, 91, 121)}}
+    if big:
+        wb = dataclasses.replace(wl, structures=big)
+        pb, msb, outb = timed(wb, steps)
+        nr = outb["n_rhst"].cpu().numpy()
+        A = len(wl.theta0)
+        fl = 0.0
+        for k, st in enumerate(big):
+            fl += _flops_forward(st.n_beams, st.n_slices, 7, int(nr[k * A:(k + 1) * A].sum()), A)
+        res["large_kernel"] = {"pairs": pb.n_pairs, "ms": round(msb, 3), "slots": int(pb.info.large_slots),
+                               "achieved_tflops": round(fl / (msb / 1e3) / 1e12, 3),
+                               "frac_of_published": round(fl / (msb / 1e3) / 1e12 / MFMA_FP64_PEAK_TFLOPS, 4),
+                               "rhst_per_pair": round(float(nr.mean()), 1)}
+        del pb
+    # per-angle form: one pair of each N at a time, projected over the batch
+    per = {}
+    proj = 0.0
+    for n in (31, 61, 91, 121):
+        sts = [st for st in wl.structures if st.n_beams == n]
+        if not sts:
+            continue
+        one = dataclasses.replace(wl, structures=sts[:1], theta0=wl.theta0[:1])
+        _, ms1, _ = timed(one, 1)
+        per[str(n)] = round(ms1, 3)
+        proj += ms1 * len(sts) * len(wl.theta0)
+    res["per_angle"] = {"ms_per_pair": per, "projected_ms_per_forward": round(proj, 1),
+                        "speedup_of_batched": round(proj / ms, 1),
+                        "note": "one pair of each N timed alone, times the pairs of that N in the batch"}
+    return res
+
+
 # -------------------------------------------------------------------- bench
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["fwd", "fwd+adj"], default="fwd+adj")
+    ap.add_argument("--mode", choices=["fwd", "fwd+adj", "uneven"], default="fwd+adj",
+                    help="uneven: only the uneven-N batched forward variant, as its own JSON line")
     ap.add_argument("--structures", type=int, default=1, help="structures in the batch (128 angles each)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-per-angle", action="store_true",
                     help="skip timing the plain per-angle form (the same step one (structure, angle) pair at a time)")
     ap.add_argument("--checkpoint-every", type=int, default=CHECKPOINT_EVERY,
                     help="slices between states kept for the adjoint (the gradient workload keeps every 20th)")
+    ap.add_argument("--uneven-structures", type=int, default=16,
+                    help="structures of the uneven-N batched forward variant (64 angles each; 0 skips it)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run one forward launch and a 1 GiB copy for HBM counter runs, then exit")
     args = ap.parse_args()
@@ -165,6 +238,9 @@ def main():
         sys.exit(2)
     if args.traffic_probe:
         traffic_probe(args.checkpoint_every)
+        return
+    if args.mode == "uneven":
+        print(json.dumps({"uneven_n_forward": uneven_forward(max(1, args.uneven_structures), steps=args.steps)}))
         return
 
     import numpy as np
@@ -300,6 +376,10 @@ def main():
         variants = variants or {}
         variants["per_angle"] = {"value": round(n_pairs / (ms_pa / 1e3), 3), "ms_per_step": round(ms_pa, 3),
                                  "speedup_of_batched": round(ms_pa / ms, 2)}
+
+    if args.uneven_structures > 0:
+        variants = variants or {}
+        variants["uneven_n_forward"] = uneven_forward(args.uneven_structures)
 
     rec = {
         "metric": "rocking-curve points (structure x angle)/s at N=61 FP64; " +
