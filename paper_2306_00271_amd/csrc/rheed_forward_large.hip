@@ -113,19 +113,20 @@ struct LMat {
 // 64 HF + pl (the pivot column's half is wave-uniform, so it selects code
 // instead of data).
 template <int HF>
-__device__ __forceinline__ void col_update(double2 (&z)[LRM][2], int m0, int pl, double2 f0, double2 f1) {
+__device__ __forceinline__ void col_update(double2 (&z)[LRM][2], int m0, int m1, int pl, double2 f0, double2 f1) {
 #pragma unroll
   for (int m = 0; m < LRM; ++m) {
-    if (m < m0) continue;
-    const double2 zp = make_double2(readlane_f64(z[m][HF].x, pl), readlane_f64(z[m][HF].y, pl));
-    z[m][0].x = fma(-f0.x, zp.x, z[m][0].x);
-    z[m][0].x = fma(f0.y, zp.y, z[m][0].x);
-    z[m][0].y = fma(-f0.x, zp.y, z[m][0].y);
-    z[m][0].y = fma(-f0.y, zp.x, z[m][0].y);
-    z[m][1].x = fma(-f1.x, zp.x, z[m][1].x);
-    z[m][1].x = fma(f1.y, zp.y, z[m][1].x);
-    z[m][1].y = fma(-f1.x, zp.y, z[m][1].y);
-    z[m][1].y = fma(-f1.y, zp.x, z[m][1].y);
+    if (m >= m0 && m < m1) {  // m1 is wave-uniform: this wave's rows < n
+      const double2 zp = make_double2(readlane_f64(z[m][HF].x, pl), readlane_f64(z[m][HF].y, pl));
+      z[m][0].x = fma(-f0.x, zp.x, z[m][0].x);
+      z[m][0].x = fma(f0.y, zp.y, z[m][0].x);
+      z[m][0].y = fma(-f0.x, zp.y, z[m][0].y);
+      z[m][0].y = fma(-f0.y, zp.x, z[m][0].y);
+      z[m][1].x = fma(-f1.x, zp.x, z[m][1].x);
+      z[m][1].x = fma(f1.y, zp.y, z[m][1].x);
+      z[m][1].y = fma(-f1.x, zp.y, z[m][1].y);
+      z[m][1].y = fma(-f1.y, zp.x, z[m][1].y);
+    }
   }
 }
 
@@ -136,6 +137,7 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 // (U X) for the wave's 16 x 16 tile: A = U gathered from the node table,
 // B = X of the block in LDS (row stride LCB).  Element v of the result
 // belongs to row 16 w + 4 v + (lane >> 4), block column lane & 15.
+template <int KQ>
 __device__ __forceinline__ void gemm_tile(const double2* __restrict__ xb, const double2* __restrict__ tsl,
                                           const unsigned (&gidx)[LQ / 2], int lane, LMat& out) {
   __builtin_amdgcn_sched_barrier(0);
@@ -143,7 +145,7 @@ __device__ __forceinline__ void gemm_tile(const double2* __restrict__ xb, const 
   int bb = (lane >> 4) * LCB + (lane & 15);
   asm volatile("" : "+v"(bb));  // keep the addresses from being hoisted out of the caller's loops
 #pragma unroll
-  for (int q = 0; q < LQ; ++q) {
+  for (int q = 0; q < KQ; ++q) {
     const unsigned gi = (q & 1) ? (gidx[q >> 1] >> 16) : (gidx[q >> 1] & 0xffffu);
     const double2 u = tsl[gi];
     const double2 x = xb[bb + 4 * LCB * q];
@@ -162,7 +164,7 @@ __device__ __forceinline__ void gemm_tile(const double2* __restrict__ xb, const 
 
 // One RK step of one column block: c, d (= c') of the wave's tile in, the
 // stepped tile out.  xb holds X_r of the block while its product runs.
-template <int STEPPER>
+template <int STEPPER, int KQ>
 __device__ __forceinline__ void step_block(LLds& s, LMat& c, LMat& d, const unsigned (&gidx)[LQ / 2],
                                            const double (&g2)[4], int ob, int lane, int nb, double h) {
   using T = LTab<STEPPER>;
@@ -196,7 +198,7 @@ __device__ __forceinline__ void step_block(LLds& s, LMat& c, LMat& d, const unsi
       s.xb[ob + 4 * LCB * e] = make_double2(xr, xi);
     }
     __syncthreads();
-    gemm_tile(s.xb, s.tb[(nb + T::node(r)) % SL], gidx, lane, G[r]);
+    gemm_tile<KQ>(s.xb, s.tb[(nb + T::node(r)) % SL], gidx, lane, G[r]);
 #pragma unroll
     for (int e = 0; e < LNE; ++e) {
       G[r].r[e] += g2[e] * X.r[e];
@@ -231,6 +233,7 @@ struct GjRec {
                                              int (&pos)[2], double2* rowbuf, double2* frec, int* pcrec,
                                              int* flag_singular) {
     if (KB * LW >= n) return;
+    const int mlim = (n - wu + LW - 1) / LW;  // this wave's rows < n
 #pragma unroll 1
     for (int kk = 0; kk < LW; ++kk) {
       const int k = KB * LW + kk;
@@ -272,8 +275,8 @@ struct GjRec {
         frec[k * NL + 64 + lane] = f1;
         if (lane == 0) pcrec[k] = pc;
       }
-      if (hf) col_update<1>(z, KB, pl, f0, f1);
-      else col_update<0>(z, KB, pl, f0, f1);
+      if (hf) col_update<1>(z, KB, mlim, pl, f0, f1);
+      else col_update<0>(z, KB, mlim, pl, f0, f1);
       if (k + 1 < n && wu == (k + 1) % LW) {  // row k + 1: register KB, or KB + 1 after the block's last step
         constexpr int RB = KB + 1 < LRM ? KB + 1 : KB;
         const bool same = kk + 1 < LW;  // select values, not addresses, so z stays in registers
@@ -309,8 +312,9 @@ __device__ __forceinline__ void eliminate(double2 (&z)[LRM][2], int n, int lane,
 }
 
 // z <- z E: the recorded column operations of steps 0 .. n-1 on the rows in z.
-__device__ __forceinline__ void replay(double2 (&z)[LRM][2], int n, int lane, const LLds& s,
+__device__ __forceinline__ void replay(double2 (&z)[LRM][2], int n, int lane, int w, const LLds& s,
                                        const double2* __restrict__ frec) {
+  const int mlim = (n - __builtin_amdgcn_readfirstlane(w) + LW - 1) / LW;  // rows >= n are zero rows of P
   double2 g0 = frec[lane], g1 = frec[64 + lane];
 #pragma unroll 1
   for (int k = 0; k < n; ++k) {
@@ -321,8 +325,8 @@ __device__ __forceinline__ void replay(double2 (&z)[LRM][2], int n, int lane, co
     }
     const int pc = __builtin_amdgcn_readfirstlane(s.pcrec[k]);
     const int hf = pc >> 6, pl = pc & 63;
-    if (hf) col_update<1>(z, 0, pl, f0, f1);
-    else col_update<0>(z, 0, pl, f0, f1);
+    if (hf) col_update<1>(z, 0, mlim, pl, f0, f1);
+    else col_update<0>(z, 0, mlim, pl, f0, f1);
   }
 }
 
@@ -332,14 +336,14 @@ __device__ __forceinline__ void replay(double2 (&z)[LRM][2], int n, int lane, co
 // block 0 and added to by the others (each row belongs to one lane of one
 // wave).  Kept out of line so that its registers are allocated apart from
 // the eliminations'.
-template <int STEPPER>
+template <int STEPPER, int KQ>
 __device__ __noinline__ void slice_block(double2* __restrict__ cg, double2* __restrict__ dg, int cb, int nb,
                                          double h, int N) {
   LLds& s = large_lds;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   unsigned gidx[LQ / 2];
 #pragma unroll
-  for (int q = 0; q < LQ / 2; ++q) gidx[q] = s.gix[q][tid];
+  for (int q = 0; q < LQ / 2; ++q) gidx[q] = q < KQ / 2 ? s.gix[q][tid] : 0u;
   double g2[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) g2[v] = s.g2s[16 * w + 4 * v + (lane >> 4)];
@@ -355,7 +359,7 @@ __device__ __noinline__ void slice_block(double2* __restrict__ cg, double2* __re
     d.r[e] = dv.x;
     d.i[e] = dv.y;
   }
-  step_block<STEPPER>(s, c, d, gidx, g2, ob, lane, nb, h);
+  step_block<STEPPER, KQ>(s, c, d, gidx, g2, ob, lane, nb, h);
   double pdg[4], pof[4];
 #pragma unroll
   for (int e = 0; e < LNE; ++e) {
@@ -404,7 +408,7 @@ __device__ __noinline__ void rhst_pass(double2* __restrict__ cg, double2* __rest
     z[m][0] = dg[(w + LW * m) * NL + lane];
     z[m][1] = dg[(w + LW * m) * NL + 64 + lane];
   }
-  replay(z, N, lane, s, frec);
+  replay(z, N, lane, w, s, frec);
 #pragma unroll
   for (int m = 0; m < LRM; ++m) {
     const int row = w + LW * m;
@@ -454,6 +458,7 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
   const int L = S.n_slices;
   const double h = S.h;
   const double2* __restrict__ Us = a.U + S.table_off;
+  const int ncb = (N + LCB - 1) / LCB;  // column blocks holding columns < N (5 .. 8)
 
   if (tid < NL) {
     s.bhk[tid][0] = tid < N ? a.beams[2 * (S.beam_off + tid)] : 0;
@@ -516,8 +521,22 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
       }
     }
     __syncthreads();
-#pragma unroll 1
-    for (int cb = 0; cb < NCB; ++cb) slice_block<STEPPER>(cg, dg, cb, nb, h, N);
+    // column blocks and k-steps past N hold zeros only (padding columns of
+    // c and c' stay as they are, U_jk = 0 for k >= N), so both stop at N
+    switch (ncb) {
+      case 5:
+        for (int cb = 0; cb < 5; ++cb) slice_block<STEPPER, 20>(cg, dg, cb, nb, h, N);
+        break;
+      case 6:
+        for (int cb = 0; cb < 6; ++cb) slice_block<STEPPER, 24>(cg, dg, cb, nb, h, N);
+        break;
+      case 7:
+        for (int cb = 0; cb < 7; ++cb) slice_block<STEPPER, 28>(cg, dg, cb, nb, h, N);
+        break;
+      default:
+        for (int cb = 0; cb < NCB; ++cb) slice_block<STEPPER, 32>(cg, dg, cb, nb, h, N);
+        break;
+    }
     __syncthreads();
     // condition estimate of Q = c (Sec. 3.2): the Gershgorin / Varah bound
     // max_i(|q_ii| + r_i) / min_i(|q_ii| - r_i), r_i = sum_{j != i} |q_ij|
