@@ -255,6 +255,15 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     P->bwd_ws += (size_t)P->ck.every * NP * sizeof(double2) * P->n_pairs;
   }
 
+  // the N > 64 kernel takes its pairs dearest first: cost ~ (column blocks)^2 x slices
+  if (!P->large_pairs.empty()) {
+    auto cost = [&](int p) {
+      const StructDev& d = P->hs[P->pair_struct[p]];
+      const long long nb = (d.n_beams + 15) / 16;
+      return nb * nb * d.n_slices;
+    };
+    std::stable_sort(P->large_pairs.begin(), P->large_pairs.end(), [&](int x, int y) { return cost(x) > cost(y); });
+  }
   // the adjoint and its state saving handle N <= 64 only
   if (!P->large_pairs.empty()) {
     P->fwd_ws = 0;
@@ -294,7 +303,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
           hipSuccess ||
       (P->split && (e = hipMalloc(&P->d_xch, (size_t)XCH_STRIDE * n_small)) != hipSuccess) ||
       (n_large > 0 && n_small > 0 && (e = hipMalloc(&P->d_small_pairs, sizeof(int) * n_small)) != hipSuccess) ||
-      (n_large > 0 && n_small > 0 && (e = hipMalloc(&P->d_large_pairs, sizeof(int) * n_large)) != hipSuccess) ||
+      (n_large > 0 && (e = hipMalloc(&P->d_large_pairs, sizeof(int) * n_large)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_lscratch, (size_t)LSLOT_BYTES * P->large_slots)) != hipSuccess)) {
     rheed_plan_destroy(P);
     return e == hipErrorOutOfMemory ? fail(RHEED_E_NOMEM, "plan_create: device allocation") : hip_fail(e, "hipMalloc");
@@ -439,7 +448,7 @@ rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* a
   if (!P->large_pairs.empty()) {
     LargeArgs la{};
     la.f = a;
-    la.f.pair_list = P->d_large_pairs;  // null when every pair is large
+    la.f.pair_list = P->d_large_pairs;  // in cost order
     la.f.n_pairs = (int)P->large_pairs.size();
     la.f.ws = nullptr;
     la.f.xch = nullptr;

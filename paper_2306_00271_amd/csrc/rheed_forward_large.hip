@@ -29,8 +29,8 @@
 // way; its first inverse column is E e_{pc_0}, formed by applying the recorded
 // operations to a unit vector in reverse order, and rho = (Gamma Q + iP) x.
 //
-// The launch is a persistent grid of one workgroup per CU (the LDS holds one);
-// workgroup b runs pairs b, b + grid, ...; no workgroup waits for another.
+// The launch is a persistent grid of one workgroup per CU (the LDS holds one)
+// over a cost-ordered pair list; no workgroup waits for another.
 #include "rheed_large.h"
 #include "rheed_gj.h"
 
@@ -623,11 +623,18 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
   }
 }
 
+// The pair list comes ordered by estimated cost, most expensive first;
+// rounds of the grid take it in alternating directions (workgroup b gets
+// entries b, 2G - 1 - b, 2G + b, ...), which pairs the dearest pairs of one
+// round with the cheapest of the next.
 template <int STEPPER>
 __global__ __launch_bounds__(LT, 1) void forward_large_kernel(LargeArgs A) {
   char* slot = A.scratch + (long long)blockIdx.x * LSLOT_BYTES;
+  const int G = gridDim.x;
 #pragma unroll 1
-  for (int pi = blockIdx.x; pi < A.f.n_pairs; pi += gridDim.x) {
+  for (int base = 0, r = 0; base < A.f.n_pairs; base += G, ++r) {
+    const int pi = base + ((r & 1) ? G - 1 - (int)blockIdx.x : (int)blockIdx.x);
+    if (pi >= A.f.n_pairs) continue;
     const int p = A.f.pair_list ? A.f.pair_list[pi] : pi;
     run_pair<STEPPER>(A, p, slot);
     __syncthreads();  // LDS is reused by the next pair
