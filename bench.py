@@ -55,10 +55,16 @@ def _cpu_worker(args):
     os.environ["OMP_NUM_THREADS"] = "1"
     os.environ["OPENBLAS_NUM_THREADS"] = "1"
     os.environ["MKL_NUM_THREADS"] = "1"
-    kind, idx, stepper = args
+    kind, idx, stepper = args[:3]
     import numpy as np
-    from synth import config4
+    from synth import config3, config4
     from oracle import driver
+    if kind == "uneven":
+        # one pair of the uneven-N workload: structure idx of the first args[3], one angle
+        wl3 = config3(args[3])
+        t0 = time.perf_counter()
+        driver.rocking_curve(wl3, s_idx=idx, angle_idx=[(idx * 37) % len(wl3.theta0)], stepper=stepper)
+        return time.perf_counter() - t0
     wl = config4(1)
     t0 = time.perf_counter()
     if kind == "fwd":
@@ -144,7 +150,7 @@ def traffic_probe(checkpoint_every):
 
 
 # ------------------------------------------------------ uneven-N workload
-def uneven_forward(n_structures, steps=2):
+def uneven_forward(n_structures, steps=2, cpu=True):
     """Forward throughput on the first n_structures of the uneven-N batched
     workload (N drawn from {31, 61, 91, 121}, 64 angles each, 400 slices,
     RK6): the whole batch through one rheed_forward call (N <= 64 pairs on the
@@ -210,6 +216,21 @@ def uneven_forward(n_structures, steps=2):
     res["per_angle"] = {"ms_per_pair": per, "projected_ms_per_forward": round(proj, 1),
                         "speedup_of_batched": round(proj / ms, 1),
                         "note": "one pair of each N timed alone, times the pairs of that N in the batch"}
+    if cpu:
+        # the oracle on one pair of every structure (each structure has the same
+        # number of angles, so the mean over structures is the batch's mean per pair)
+        import multiprocessing as mp
+        cores = min(16, os.cpu_count() or 1)
+        jobs = [("uneven", s, "rk6", n_structures) for s in range(n_structures)]
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(cores) as pool:
+            times = pool.map(_cpu_worker, jobs)
+        cwall = time.perf_counter() - t0
+        mean = float(sum(times) / len(times))
+        res["cpu_baseline"] = {"value": round(cores / mean, 4), "unit": "points/s", "cores": cores, "kind": "oracle",
+                               "sample": f"one pair of each of the {n_structures} structures (one angle each), "
+                                         f"oracle forward, mean {mean:.2f} s per pair; {cores} processes x 1 BLAS "
+                                         f"thread, {cwall:.1f} s wall"}
     return res
 
 
@@ -240,7 +261,8 @@ def main():
         traffic_probe(args.checkpoint_every)
         return
     if args.mode == "uneven":
-        print(json.dumps({"uneven_n_forward": uneven_forward(max(1, args.uneven_structures), steps=args.steps)}))
+        print(json.dumps({"uneven_n_forward": uneven_forward(max(1, args.uneven_structures), steps=args.steps,
+                                                             cpu=not args.no_cpu)}))
         return
 
     import numpy as np
@@ -379,7 +401,7 @@ def main():
 
     if args.uneven_structures > 0:
         variants = variants or {}
-        variants["uneven_n_forward"] = uneven_forward(args.uneven_structures)
+        variants["uneven_n_forward"] = uneven_forward(args.uneven_structures, cpu=not args.no_cpu)
 
     rec = {
         "metric": "rocking-curve points (structure x angle)/s at N=61 FP64; " +
