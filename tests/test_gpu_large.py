@@ -122,3 +122,45 @@ def test_adjoint_refuses_large_plans():
     dI = torch.zeros((plan.n_pairs, plan.max_beams), dtype=torch.float64, device=dev)
     with pytest.raises(RheedError, match="N <= 64"):
         plan.backward(U, api.angles_for(wl, dev), dI, ws)
+
+
+def test_graph_capture_of_a_mixed_forward():
+    """A forward call over structures with N = 45 and N = 91 (two launches:
+    the N <= 64 kernel and the N > 64 kernel) captured once in a HIP graph:
+    every replay, with eager calls and synchronisations between replays,
+    reproduces the eager outputs bit for bit."""
+    import torch
+    from paper_2306_00271_amd import api
+    dev = torch.device("cuda:0")
+    parts = [small_2d(n_beams=n, n_slices=12, thickness=1.2, n_layers=2, n_angles=3, seed=40 + i)
+             for i, n in enumerate((45, 91))]
+    wl = dataclasses.replace(parts[0], structures=[p.structures[0] for p in parts])
+    plan = api.plan_for(wl, stepper="rk6")
+    assert plan.info.large_pairs == 3
+    atoms = api.atoms_for(wl, dev)
+    ang = api.angles_for(wl, dev)
+
+    def step():
+        U = plan.potential(atoms)
+        out = plan.forward(U, ang, want_rho=True, want_nrhst=True)
+        return out["intensity"], out["rho"], out["status"], out["n_rhst"]
+
+    ref = [t.clone() for t in step()]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        outs = step()
+    for r in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        for o, rf in zip(outs, ref):
+            assert torch.equal(o, rf), f"replay {r}"
+        step()
+        torch.cuda.synchronize()
+    assert (ref[2] == 0).all()
