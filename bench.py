@@ -167,10 +167,14 @@ def uneven_forward(n_structures, steps=2, cpu=True):
     stream = torch.cuda.current_stream()
     wl = config3(n_structures)
 
-    def timed(w, reps):
+    tune = {}
+
+    def timed(w, reps, autotune=False):
         plan = api.plan_for(w, stepper="rk6")
         U = plan.potential(api.atoms_for(w, dev))
         ang = api.angles_for(w, dev)
+        if autotune:  # launch configuration picked by timing the candidates on this batch
+            tune.update(plan.autotune(U, ang, reps=1))
         plan.forward(U, ang)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -182,13 +186,18 @@ def uneven_forward(n_structures, steps=2, cpu=True):
         torch.cuda.synchronize()
         return plan, e0.elapsed_time(e1) / reps, out
 
-    plan, ms, out = timed(wl, steps)
+    plan, ms, out = timed(wl, steps, autotune=True)
     n_pairs = plan.n_pairs
     bad = int((out["status"] != 0).sum().item())
     big = [st for st in wl.structures if st.n_beams > 64]
     res = {"structures": n_structures, "pairs": n_pairs, "ms_per_forward": round(ms, 3),
            "value": round(n_pairs / (ms / 1e3), 2), "unit": "points/s", "bad_pairs": bad,
-           "beams": {str(n): sum(1 for st in wl.structures if st.n_beams == n) for n in (31, 61, 91, 121)}}
+           "beams": {str(n): sum(1 for st in wl.structures if st.n_beams == n) for n in (31, 61, 91, 121)},
+           "autotune": {"chosen": tune.get("chosen"),
+                        "candidates_ms": [round(c["ms"], 2) for c in tune.get("candidates", [])],
+                        "candidates": [("split" if c["split"] else "whole") + "/" +
+                                       ("cost-order" if c["large_cost_order"] else "pair-order")
+                                       for c in tune.get("candidates", [])]}}
     if big:
         wb = dataclasses.replace(wl, structures=big)
         pb, msb, outb = timed(wb, steps)

@@ -186,6 +186,33 @@ rheed_status rheed_forward(rheed_plan_t plan, const void* U_tables, const double
                            double* intensity, void* rho, int32_t* pair_status, int32_t* n_rhst,
                            void* workspace, size_t ws_bytes, void* stream);
 
+/* Launch configurations rheed_autotune compares (at most RHEED_TUNE_MAX). */
+#define RHEED_TUNE_MAX 4
+typedef struct {
+  int32_t n_candidates;
+  int32_t chosen;                           /* index of the configuration the plan now uses */
+  int32_t split[RHEED_TUNE_MAX];            /* 1: pairs with N <= 64 on the two-workgroup layout */
+  int32_t large_cost_order[RHEED_TUNE_MAX]; /* 1: pairs with N > 64 dearest first, 0: in pair order */
+  float ms[RHEED_TUNE_MAX];                 /* mean duration of one rheed_forward call */
+} rheed_tune_report;
+
+/* Picks the launch configuration of rheed_forward for this plan by timing
+ * the candidates on the caller's inputs (the batching of Sec. 3.5 over
+ * (structure, angle) pairs is this library's; the paper fixes no schedule):
+ * the layout of the N <= 64 pairs (split or whole, where the plan's layout
+ * option is AUTO and the batch fits the split layout) and the order in which
+ * the N > 64 kernel takes its pairs (by estimated cost or in pair order).
+ * Each candidate runs one untimed and `reps` (1..1000) timed forward calls
+ * without state saving on `stream`, timed with HIP events; the fastest is
+ * kept by the plan for every later rheed_forward.  U_tables, angles,
+ * intensity and pair_status are as for rheed_forward (intensity and status
+ * hold the last candidate's results on return; the candidates agree to
+ * rounding).  Synchronises the stream; creates and destroys two HIP events,
+ * allocates no device memory.  report (host) may be NULL.  Calls on one plan
+ * must not overlap. */
+rheed_status rheed_autotune(rheed_plan_t plan, const void* U_tables, const double* angles, double* intensity,
+                            int32_t* pair_status, int32_t reps, void* stream, rheed_tune_report* report);
+
 /* Adjoint of rheed_forward (not in the paper): given dL/d(intensity) for a
  * real loss L, accumulates dL/dU over all angles of each structure.
  * Must follow rheed_forward on the same stream with the same plan, inputs and

@@ -66,6 +66,19 @@ class PlanInfo(C.Structure):
     ]
 
 
+RHEED_TUNE_MAX = 4
+
+
+class TuneReport(C.Structure):
+    _fields_ = [
+        ("n_candidates", C.c_int32),
+        ("chosen", C.c_int32),
+        ("split", C.c_int32 * RHEED_TUNE_MAX),
+        ("large_cost_order", C.c_int32 * RHEED_TUNE_MAX),
+        ("ms", C.c_float * RHEED_TUNE_MAX),
+    ]
+
+
 SYMBOLS = {
     "rheed_beam_constants": ([C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "rheed_plan_create": ([C.POINTER(C.c_void_p), C.POINTER(Opts), C.c_int32, C.POINTER(Structure),
@@ -80,6 +93,8 @@ SYMBOLS = {
                        C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "rheed_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                         C.c_void_p], C.c_int),
+    "rheed_autotune": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                        C.POINTER(TuneReport)], C.c_int),
     "rheed_rfactor": ([C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "rheed_mfma_f64_peak": ([C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
     "rheed_status_string": ([C.c_int], C.c_char_p),

@@ -140,6 +140,26 @@ class Plan:
                                             _ptr(nrhst), _ptr(workspace), ws_bytes, _stream()), "forward")
         return {"intensity": inten, "rho": rho, "status": status, "n_rhst": nrhst}
 
+    def autotune(self, U: torch.Tensor, angles: torch.Tensor, reps: int = 3) -> dict:
+        """Times the launch configurations of forward on these inputs and keeps
+        the fastest for later calls (rheed_autotune); returns the timings."""
+        _dev(U, torch.complex128, "U")
+        _dev(angles, torch.float64, "angles")
+        dev = U.device
+        inten = torch.empty((self.n_pairs, self.max_beams), dtype=torch.float64, device=dev)
+        status = torch.empty(self.n_pairs, dtype=torch.int32, device=dev)
+        rep = _lib.TuneReport()
+        _lib.check(_lib.lib().rheed_autotune(self._h, _ptr(U), _ptr(angles), _ptr(inten), _ptr(status), int(reps),
+                                             _stream(), C.byref(rep)), "autotune")
+        info = _lib.PlanInfo()
+        _lib.check(_lib.lib().rheed_plan_get_info(self._h, C.byref(info)), "plan_get_info")
+        self.info = info
+        self.split = bool(info.split)
+        n = rep.n_candidates
+        return {"chosen": rep.chosen,
+                "candidates": [{"split": bool(rep.split[c]), "large_cost_order": bool(rep.large_cost_order[c]),
+                                "ms": float(rep.ms[c])} for c in range(n)]}
+
     def backward(self, U: torch.Tensor, angles: torch.Tensor, dL_dI: torch.Tensor,
                  workspace: torch.Tensor) -> torch.Tensor:
         _dev(U, torch.complex128, "U")

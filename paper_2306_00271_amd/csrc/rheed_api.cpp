@@ -62,9 +62,12 @@ struct rheed_plan_s {
   // kernels) and with 64 < N <= 128 (the large kernel), in pair order
   std::vector<int> small_pairs, large_pairs;
   int* d_small_pairs = nullptr;  // only when both kinds are present
-  int* d_large_pairs = nullptr;
+  int* d_large_pairs = nullptr;  // in cost order (dearest first)
+  int* d_large_plain = nullptr;  // in pair order
+  bool large_cost_order = true;  // which of the two lists rheed_forward uses
   char* d_lscratch = nullptr;    // per resident workgroup of the large kernel: its state slot
   int large_slots = 0;
+  std::vector<int> large_plain;
 };
 
 extern "C" {
@@ -256,6 +259,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
   }
 
   // the N > 64 kernel takes its pairs dearest first: cost ~ (column blocks)^2 x slices
+  P->large_plain = P->large_pairs;
   if (!P->large_pairs.empty()) {
     auto cost = [&](int p) {
       const StructDev& d = P->hs[P->pair_struct[p]];
@@ -304,6 +308,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (P->split && (e = hipMalloc(&P->d_xch, (size_t)XCH_STRIDE * n_small)) != hipSuccess) ||
       (n_large > 0 && n_small > 0 && (e = hipMalloc(&P->d_small_pairs, sizeof(int) * n_small)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_large_pairs, sizeof(int) * n_large)) != hipSuccess) ||
+      (n_large > 0 && (e = hipMalloc(&P->d_large_plain, sizeof(int) * n_large)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_lscratch, (size_t)LSLOT_BYTES * P->large_slots)) != hipSuccess)) {
     rheed_plan_destroy(P);
     return e == hipErrorOutOfMemory ? fail(RHEED_E_NOMEM, "plan_create: device allocation") : hip_fail(e, "hipMalloc");
@@ -323,6 +328,8 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (P->d_small_pairs && (e = hipMemcpy(P->d_small_pairs, P->small_pairs.data(), sizeof(int) * n_small,
                                           hipMemcpyHostToDevice)) != hipSuccess) ||
       (P->d_large_pairs && (e = hipMemcpy(P->d_large_pairs, P->large_pairs.data(), sizeof(int) * n_large,
+                                          hipMemcpyHostToDevice)) != hipSuccess) ||
+      (P->d_large_plain && (e = hipMemcpy(P->d_large_plain, P->large_plain.data(), sizeof(int) * n_large,
                                           hipMemcpyHostToDevice)) != hipSuccess) ||
       (e = hipDeviceSynchronize()) != hipSuccess) {
     rheed_plan_destroy(P);
@@ -344,6 +351,7 @@ rheed_status rheed_plan_destroy(rheed_plan_t P) {
   if (P->d_xch) (void)hipFree(P->d_xch);
   if (P->d_small_pairs) (void)hipFree(P->d_small_pairs);
   if (P->d_large_pairs) (void)hipFree(P->d_large_pairs);
+  if (P->d_large_plain) (void)hipFree(P->d_large_plain);
   if (P->d_lscratch) (void)hipFree(P->d_lscratch);
   delete P;
   return RHEED_OK;
@@ -448,7 +456,7 @@ rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* a
   if (!P->large_pairs.empty()) {
     LargeArgs la{};
     la.f = a;
-    la.f.pair_list = P->d_large_pairs;  // in cost order
+    la.f.pair_list = P->large_cost_order ? P->d_large_pairs : P->d_large_plain;
     la.f.n_pairs = (int)P->large_pairs.size();
     la.f.ws = nullptr;
     la.f.xch = nullptr;
@@ -456,6 +464,73 @@ rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* a
     la.n_slots = P->large_slots;
     e = launch_forward_large((int)P->opts.stepper, la, st);
     if (e != hipSuccess) return hip_fail(e, "forward launch (N > 64)");
+  }
+  return RHEED_OK;
+}
+
+rheed_status rheed_autotune(rheed_plan_t P, const void* U_tables, const double* angles, double* intensity,
+                            int32_t* pair_status, int32_t reps, void* stream, rheed_tune_report* report) {
+  if (!P || !U_tables || !angles || !intensity || !pair_status || reps < 1 || reps > 1000)
+    return fail(RHEED_E_INVALID, "autotune: null argument or reps outside [1, 1000]");
+  // candidates: the N <= 64 layouts the plan allows (split needs its exchange
+  // blocks, allocated when the batch fits) x the N > 64 pair orders
+  std::vector<std::pair<bool, bool>> cand;
+  const bool has_small = !P->small_pairs.empty(), has_large = !P->large_pairs.empty();
+  std::vector<bool> layouts;
+  if (!has_small) layouts = {P->split};
+  else if (P->d_xch && P->opts.layout == RHEED_LAYOUT_AUTO) layouts = {true, false};
+  else layouts = {P->split};
+  std::vector<bool> orders = has_large ? std::vector<bool>{true, false} : std::vector<bool>{P->large_cost_order};
+  for (bool l : layouts)
+    for (bool o : orders) cand.push_back({l, o});
+  if ((int)cand.size() > RHEED_TUNE_MAX) cand.resize(RHEED_TUNE_MAX);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_fail(e, "autotune: hipEventCreate");
+  }
+  const bool keep_split = P->split, keep_order = P->large_cost_order;
+  std::vector<float> ms(cand.size(), 0.0f);
+  rheed_status rs = RHEED_OK;
+  for (size_t c = 0; c < cand.size() && rs == RHEED_OK; ++c) {
+    P->split = cand[c].first;
+    P->large_cost_order = cand[c].second;
+    rs = rheed_forward(P, U_tables, angles, intensity, nullptr, pair_status, nullptr, nullptr, 0, stream);  // untimed
+    if (rs != RHEED_OK) break;
+    if ((e = hipEventRecord(e0, st)) != hipSuccess) { rs = hip_fail(e, "autotune: hipEventRecord"); break; }
+    for (int r = 0; r < reps && rs == RHEED_OK; ++r)
+      rs = rheed_forward(P, U_tables, angles, intensity, nullptr, pair_status, nullptr, nullptr, 0, stream);
+    if (rs != RHEED_OK) break;
+    if ((e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess ||
+        (e = hipEventElapsedTime(&ms[c], e0, e1)) != hipSuccess) {
+      rs = hip_fail(e, "autotune: timing");
+      break;
+    }
+    ms[c] /= (float)reps;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rs != RHEED_OK) {
+    P->split = keep_split;
+    P->large_cost_order = keep_order;
+    return rs;
+  }
+  size_t best = 0;
+  for (size_t c = 1; c < cand.size(); ++c)
+    if (ms[c] < ms[best]) best = c;
+  P->split = cand[best].first;
+  P->large_cost_order = cand[best].second;
+  if (report) {
+    *report = rheed_tune_report{};
+    report->n_candidates = (int32_t)cand.size();
+    report->chosen = (int32_t)best;
+    for (size_t c = 0; c < cand.size(); ++c) {
+      report->split[c] = cand[c].first ? 1 : 0;
+      report->large_cost_order[c] = cand[c].second ? 1 : 0;
+      report->ms[c] = ms[c];
+    }
   }
   return RHEED_OK;
 }

@@ -164,3 +164,40 @@ def test_graph_capture_of_a_mixed_forward():
         step()
         torch.cuda.synchronize()
     assert (ref[2] == 0).all()
+
+
+def test_autotune_picks_the_fastest_candidate_and_keeps_the_results():
+    """rheed_autotune on a batch with N = 45 and N = 91 structures times the
+    four candidates (split or whole layout for N <= 64 x cost or pair order
+    for N > 64), keeps the fastest, and later forward calls still match the
+    oracle."""
+    import torch
+    from paper_2306_00271_amd import api
+    dev = torch.device("cuda:0")
+    parts = [small_2d(n_beams=n, n_slices=16, thickness=1.6, n_layers=2, n_angles=3, seed=50 + i)
+             for i, n in enumerate((45, 91))]
+    wl = dataclasses.replace(parts[0], structures=[p.structures[0] for p in parts])
+    plan = api.plan_for(wl, stepper="rk6")
+    U = plan.potential(api.atoms_for(wl, dev))
+    ang = api.angles_for(wl, dev)
+    before = plan.forward(U, ang)["intensity"].cpu().numpy()
+    rep = plan.autotune(U, ang, reps=2)
+    cands = rep["candidates"]
+    assert len(cands) == 4
+    assert {(c["split"], c["large_cost_order"]) for c in cands} == {(a, b) for a in (True, False) for b in (True, False)}
+    assert all(c["ms"] > 0.0 for c in cands)
+    best = min(range(4), key=lambda c: cands[c]["ms"])
+    assert rep["chosen"] == best
+    assert plan.split == cands[best]["split"]
+    out = plan.forward(U, ang)
+    torch.cuda.synchronize()
+    after = out["intensity"].cpu().numpy()
+    assert (out["status"].cpu().numpy() == 0).all()
+    assert np.abs(after - before).max() <= 1e-12 * np.abs(before).max()
+    A = len(wl.theta0)
+    for s, p in enumerate(parts):
+        N = p.structures[0].n_beams
+        ref, _, _ = oracle_forward(wl, s_idx=s, stepper="rk6")
+        e = eacc(after[s * A:(s + 1) * A, :N], ref)
+        _report(f"after autotune structure {s} N={N}", e)
+        assert e <= TOL
