@@ -96,6 +96,7 @@ struct LLds {
   double g2s[NL];                  // Gamma_j^2, 0 on padding
   double rdg[NL], rof[NL];         // per row: |q_ii| and sum_{j != i} |q_ij| over j < N
   int pcrec[NL];                   // pivot column of every elimination step
+  int pos[NL];                     // pivot step of every column in the last elimination
   unsigned gix[LQ / 2][LT];        // per thread: packed table indices of its A operand entries
   double2 xv[NL];                  // first column of the inverse in the reflection
   int flag_singular;
@@ -112,11 +113,15 @@ struct LMat {
 // Rows m0 .. LRM-1 of z: column j <- column j - f_j column pc, with pc =
 // 64 HF + pl (the pivot column's half is wave-uniform, so it selects code
 // instead of data).
-template <int HF>
-__device__ __forceinline__ void col_update(double2 (&z)[LRM][2], int m0, int m1, int pl, double2 f0, double2 f1) {
+// Rows >= n (padding: unit rows of Q, zero rows of P and of the reflection
+// matrix) have zeros in every pivot column and come out unchanged; the
+// elimination skips them (m < m1, wave-uniform), the replay does not (there
+// the per-row branch costs more registers than it saves).
+template <int HF, int R>
+__device__ __forceinline__ void col_update(double2 (&z)[R][2], int m0, int m1, int pl, double2 f0, double2 f1) {
 #pragma unroll
-  for (int m = 0; m < LRM; ++m) {
-    if (m >= m0 && m < m1) {  // m1 is wave-uniform: this wave's rows < n
+  for (int m = 0; m < R; ++m) {
+    if (m >= m0 && m < m1) {
       const double2 zp = make_double2(readlane_f64(z[m][HF].x, pl), readlane_f64(z[m][HF].y, pl));
       z[m][0].x = fma(-f0.x, zp.x, z[m][0].x);
       z[m][0].x = fma(f0.y, zp.y, z[m][0].x);
@@ -127,6 +132,9 @@ __device__ __forceinline__ void col_update(double2 (&z)[LRM][2], int m0, int m1,
       z[m][1].y = fma(-f1.x, zp.y, z[m][1].y);
       z[m][1].y = fma(-f1.y, zp.x, z[m][1].y);
     }
+    // rows in groups of 4: the pivot-column reads of later rows are not
+    // hoisted over earlier updates (their scalar copies would need registers)
+    if ((m & 3) == 3) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -224,13 +232,14 @@ __device__ __forceinline__ void step_block(LLds& s, LMat& c, LMat& d, const unsi
 // |A_kj|^2 with the low 7 bits replaced by 127 - j, so near-ties go to the
 // smaller index), pc; f_j = A_kj / A_k,pc and f_pc = 1 - 1 / A_k,pc; then
 // column j <- column j - f_j column pc for every j, which leaves row k a unit
-// row.  pos[h] receives, for the lane's column 64 h + lane, the step at which
-// it was the pivot (its own index if never).  Rows of earlier blocks of 8
-// are unit rows with a zero in every later pivot column, so they are skipped.
+// row.  The columns already used are two wave-uniform bit masks (um0 for
+// columns 0..63, um1 for 64..127), kept in scalar registers.  Rows of
+// earlier blocks of 8 are unit rows with a zero in every later pivot column,
+// so they are skipped.
 template <int KB>
 struct GjRec {
-  static __device__ __forceinline__ void run(double2 (&z)[LRM][2], int n, int lane, int wu, bool (&used)[2],
-                                             int (&pos)[2], double2* rowbuf, double2* frec, int* pcrec,
+  static __device__ __forceinline__ void run(double2 (&z)[LRM][2], int n, int lane, int wu, unsigned long long& um0,
+                                             unsigned long long& um1, double2* rowbuf, double2* frec, int* pcrec,
                                              int* flag_singular) {
     if (KB * LW >= n) return;
     const int mlim = (n - wu + LW - 1) / LW;  // this wave's rows < n
@@ -243,23 +252,16 @@ struct GjRec {
       const double2 v0 = rowbuf[slot * NL + lane], v1 = rowbuf[slot * NL + 64 + lane];
       const double m0 = v0.x * v0.x + v0.y * v0.y, m1 = v1.x * v1.x + v1.y * v1.y;
       unsigned k0 = 0, k1 = 0;
-      if (!used[0] && lane < n)
+      if (!((um0 >> lane) & 1ull) && lane < n)
         k0 = ((unsigned)(((unsigned long long)__double_as_longlong(m0)) >> 32) & ~127u) | (unsigned)(127 - lane);
-      if (!used[1] && 64 + lane < n)
+      if (!((um1 >> lane) & 1ull) && 64 + lane < n)
         k1 = ((unsigned)(((unsigned long long)__double_as_longlong(m1)) >> 32) & ~127u) | (unsigned)(63 - lane);
       const unsigned key = wave_max_u32(k0 > k1 ? k0 : k1);
       if ((key >> 7) == 0 && lane == 0 && wu == 0) *flag_singular = 1;
       const int pc = 127 - (int)(key & 127);
       const int hf = pc >> 6, pl = pc & 63;
-      if (lane == pl) {
-        if (hf) {
-          used[1] = true;
-          pos[1] = k;
-        } else {
-          used[0] = true;
-          pos[0] = k;
-        }
-      }
+      if (hf) um1 |= 1ull << pl;
+      else um0 |= 1ull << pl;
       const double2 vs = hf ? v1 : v0;
       const double2 piv = make_double2(readlane_f64(vs.x, pl), readlane_f64(vs.y, pl));
       const double inv = 1.0 / (piv.x * piv.x + piv.y * piv.y);
@@ -275,8 +277,8 @@ struct GjRec {
         frec[k * NL + 64 + lane] = f1;
         if (lane == 0) pcrec[k] = pc;
       }
-      if (hf) col_update<1>(z, KB, mlim, pl, f0, f1);
-      else col_update<0>(z, KB, mlim, pl, f0, f1);
+      if (hf) col_update<1, LRM>(z, KB, mlim, pl, f0, f1);
+      else col_update<0, LRM>(z, KB, mlim, pl, f0, f1);
       if (k + 1 < n && wu == (k + 1) % LW) {  // row k + 1: register KB, or KB + 1 after the block's last step
         constexpr int RB = KB + 1 < LRM ? KB + 1 : KB;
         const bool same = kk + 1 < LW;  // select values, not addresses, so z stays in registers
@@ -285,36 +287,41 @@ struct GjRec {
         rowbuf[(slot ^ 1) * NL + 64 + lane] = make_double2(same ? a1.x : b1.x, same ? a1.y : b1.y);
       }
     }
-    GjRec<KB + 1>::run(z, n, lane, wu, used, pos, rowbuf, frec, pcrec, flag_singular);
+    GjRec<KB + 1>::run(z, n, lane, wu, um0, um1, rowbuf, frec, pcrec, flag_singular);
   }
 };
 template <>
 struct GjRec<LRM> {
-  static __device__ __forceinline__ void run(double2 (&)[LRM][2], int, int, int, bool (&)[2], int (&)[2], double2*,
-                                             double2*, int*, int*) {}
+  static __device__ __forceinline__ void run(double2 (&)[LRM][2], int, int, int, unsigned long long&,
+                                             unsigned long long&, double2*, double2*, int*, int*) {}
 };
 
-__device__ __forceinline__ void eliminate(double2 (&z)[LRM][2], int n, int lane, int w, int (&pos)[2], LLds& s,
-                                          double2* frec) {
+// Runs GjRec on the rows in z and leaves in s.pos the step at which each
+// column was the pivot (its own index if never: columns >= n).
+__device__ __forceinline__ void eliminate(double2 (&z)[LRM][2], int n, int lane, int w, LLds& s, double2* frec) {
   const int wu = __builtin_amdgcn_readfirstlane(w);
-  bool used[2] = {false, false};
-  pos[0] = lane;
-  pos[1] = 64 + lane;
+  unsigned long long um0 = 0, um1 = 0;
   double2* rowbuf = s.xb;
   __syncthreads();  // rowbuf aliases the stage buffer
   if (wu == 0) {
     rowbuf[lane] = z[0][0];
     rowbuf[64 + lane] = z[0][1];
   }
-  GjRec<0>::run(z, n, lane, wu, used, pos, rowbuf, frec, s.pcrec, &s.flag_singular);
+  GjRec<0>::run(z, n, lane, wu, um0, um1, rowbuf, frec, s.pcrec, &s.flag_singular);
   __threadfence();
+  __syncthreads();
+  const int tid = threadIdx.x;
+  if (tid < NL) s.pos[tid] = tid;
+  __syncthreads();
+  if (tid < n) s.pos[s.pcrec[tid]] = tid;
   __syncthreads();
 }
 
-// z <- z E: the recorded column operations of steps 0 .. n-1 on the rows in z.
-__device__ __forceinline__ void replay(double2 (&z)[LRM][2], int n, int lane, int w, const LLds& s,
+// z <- z E: the recorded column operations of steps 0 .. n-1 on R rows of
+// this wave, rows w + 8 (m0 + m) for m < R (rows >= n are zero rows of P).
+template <int R>
+__device__ __forceinline__ void replay(double2 (&z)[R][2], int n, int lane, int w, int m0, const LLds& s,
                                        const double2* __restrict__ frec) {
-  const int mlim = (n - __builtin_amdgcn_readfirstlane(w) + LW - 1) / LW;  // rows >= n are zero rows of P
   double2 g0 = frec[lane], g1 = frec[64 + lane];
 #pragma unroll 1
   for (int k = 0; k < n; ++k) {
@@ -325,17 +332,11 @@ __device__ __forceinline__ void replay(double2 (&z)[LRM][2], int n, int lane, in
     }
     const int pc = __builtin_amdgcn_readfirstlane(s.pcrec[k]);
     const int hf = pc >> 6, pl = pc & 63;
-    if (hf) col_update<1>(z, 0, mlim, pl, f0, f1);
-    else col_update<0>(z, 0, mlim, pl, f0, f1);
+    if (hf) col_update<1, R>(z, 0, R, pl, f0, f1);
+    else col_update<0, R>(z, 0, R, pl, f0, f1);
   }
 }
 
-// One slice for column block cb: the wave's 16 x 16 tile of c and c' from
-// the slot, one RK step, back to the slot; the row sums of |q_ij| (j < N) over
-// the block's columns go into s.rdg (diagonal) and s.rof (the rest), set by
-// block 0 and added to by the others (each row belongs to one lane of one
-// wave).  Kept out of line so that its registers are allocated apart from
-// the eliminations'.
 template <int STEPPER, int KQ>
 __device__ __noinline__ void slice_block(double2* __restrict__ cg, double2* __restrict__ dg, int cb, int nb,
                                          double h, int N) {
@@ -389,58 +390,71 @@ __device__ __noinline__ void slice_block(double2* __restrict__ cg, double2* __re
   }
 }
 
-// Z <- Z Q^{-1}: eliminate Q (recording), replay the column operations on
-// the rows of P, put the columns back in pivot order; c <- I.
-__device__ __noinline__ void rhst_pass(double2* __restrict__ cg, double2* __restrict__ dg, double2* __restrict__ frec,
-                                       int N) {
-  LLds& s = large_lds;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  double2 z[LRM][2];
-  int pos[2];
-#pragma unroll
-  for (int m = 0; m < LRM; ++m) {
-    z[m][0] = cg[(w + LW * m) * NL + lane];
-    z[m][1] = cg[(w + LW * m) * NL + 64 + lane];
-  }
-  eliminate(z, N, lane, w, pos, s, frec);
-#pragma unroll
-  for (int m = 0; m < LRM; ++m) {
-    z[m][0] = dg[(w + LW * m) * NL + lane];
-    z[m][1] = dg[(w + LW * m) * NL + 64 + lane];
-  }
-  replay(z, N, lane, w, s, frec);
-#pragma unroll
-  for (int m = 0; m < LRM; ++m) {
-    const int row = w + LW * m;
-    dg[row * NL + pos[0]] = z[m][0];
-    dg[row * NL + pos[1]] = z[m][1];
-    cg[row * NL + lane] = make_double2(row == lane ? 1.0 : 0.0, 0.0);
-    cg[row * NL + 64 + lane] = make_double2(row == 64 + lane ? 1.0 : 0.0, 0.0);
-  }
-  (void)tid;
-  __threadfence();
-  __syncthreads();
-}
-
-// Elimination of upper = Gamma Q - iP (recording) for the reflection.
-__device__ __noinline__ void reflect_eliminate(const double2* __restrict__ cg, const double2* __restrict__ dg,
-                                               double2* __restrict__ frec, int N) {
+// Recording elimination (see GjRec) of Q = c (which = 0) or of the
+// reflection's Gamma Q - iP (which = 1), rows from the slot; the pivot step of
+// every column goes to s.pos.  Out of line, with n and which made
+// wave-uniform, so that its row predicates are scalar branches and its
+// registers are allocated for this loop alone.
+__device__ __noinline__ void elim_record(const double2* __restrict__ cg, const double2* __restrict__ dg,
+                                         double2* __restrict__ frec, int N, int which) {
   LLds& s = large_lds;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n = __builtin_amdgcn_readfirstlane(N);
   double2 z[LRM][2];
-  int pos[2];
+  if (__builtin_amdgcn_readfirstlane(which) == 0) {
 #pragma unroll
-  for (int m = 0; m < LRM; ++m) {
-    const int row = w + LW * m;
-    const double g2v = s.g2s[row];
-    const double g_r = g2v >= 0.0 ? sqrt(g2v) : 0.0, g_i = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
+    for (int m = 0; m < LRM; ++m) {
+      z[m][0] = cg[(w + LW * m) * NL + lane];
+      z[m][1] = cg[(w + LW * m) * NL + 64 + lane];
+    }
+  } else {
 #pragma unroll
-    for (int hf = 0; hf < 2; ++hf) {
-      const double2 cv = cg[row * NL + 64 * hf + lane], pv = dg[row * NL + 64 * hf + lane];
-      z[m][hf] = make_double2(g_r * cv.x - g_i * cv.y + pv.y, g_r * cv.y + g_i * cv.x - pv.x);
+    for (int m = 0; m < LRM; ++m) {
+      const int row = w + LW * m;
+      const double g2v = s.g2s[row];
+      const double g_r = g2v >= 0.0 ? sqrt(g2v) : 0.0, g_i = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
+#pragma unroll
+      for (int hf = 0; hf < 2; ++hf) {
+        const double2 cv = cg[row * NL + 64 * hf + lane], pv = dg[row * NL + 64 * hf + lane];
+        z[m][hf] = make_double2(g_r * cv.x - g_i * cv.y + pv.y, g_r * cv.y + g_i * cv.x - pv.x);
+      }
     }
   }
-  eliminate(z, N, lane, w, pos, s, frec);
+  eliminate(z, n, lane, w, s, frec);
+}
+
+// P <- P Q^{-1} after elim_record(which = 0): the recorded column operations
+// replayed on the rows of P, each column put at its pivot step; c <- I.
+__device__ __noinline__ void replay_p(double2* __restrict__ cg, double2* __restrict__ dg,
+                                      const double2* __restrict__ frec, int N) {
+  LLds& s = large_lds;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n = __builtin_amdgcn_readfirstlane(N);
+  const int p0 = s.pos[lane], p1 = s.pos[64 + lane];
+  // the rows of P are independent here: two passes of LRM / 2 rows per wave
+  // keep the replay within the register budget
+#pragma unroll 1
+  for (int part = 0; part < 2; ++part) {
+    constexpr int R = LRM / 2;
+    const int m0 = part * R;
+    double2 z[R][2];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      z[m][0] = dg[(w + LW * (m0 + m)) * NL + lane];
+      z[m][1] = dg[(w + LW * (m0 + m)) * NL + 64 + lane];
+    }
+    replay<R>(z, n, lane, w, m0, s, frec);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int row = w + LW * (m0 + m);
+      dg[row * NL + p0] = z[m][0];
+      dg[row * NL + p1] = z[m][1];
+      cg[row * NL + lane] = make_double2(row == lane ? 1.0 : 0.0, 0.0);
+      cg[row * NL + 64 + lane] = make_double2(row == 64 + lane ? 1.0 : 0.0, 0.0);
+    }
+  }
+  __threadfence();
+  __syncthreads();
 }
 
 template <int STEPPER>
@@ -561,14 +575,16 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
       do_rhst = xi > a.threshold;
     }
     if (do_rhst) {
+      // Z <- Z Q^{-1}: eliminate Q (recording), replay on the rows of P
       ++nrhst;
-      rhst_pass(cg, dg, frec, N);
+      elim_record(cg, dg, frec, N, 0);
+      replay_p(cg, dg, frec, N);
     }
   }
 
   // reflection (Eq. vrhocomp): upper = Gamma Q - iP, lower = Gamma Q + iP,
   // rho = lower x with upper x = e_1
-  reflect_eliminate(cg, dg, frec, N);
+  elim_record(cg, dg, frec, N, 1);
   if (w == 0) {
     // x = E e_{pc_0}: the recorded operations in reverse order, each
     // v <- v - e_pc (f . v)
