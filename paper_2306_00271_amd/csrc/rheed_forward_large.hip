@@ -110,6 +110,21 @@ struct LMat {
   double i[LNE];
 };
 
+// Slot accesses name the global address space explicitly: through the
+// pointers the out-of-line phases receive they would be flat instructions,
+// which also count against the LDS counter, so every wait for an LDS read or
+// a barrier would wait for the slot traffic as well.
+typedef __attribute__((address_space(1))) double gdbl;
+__device__ __forceinline__ double2 gld(const double2* p) {
+  const gdbl* q = (const gdbl*)p;
+  return make_double2(q[0], q[1]);
+}
+__device__ __forceinline__ void gst(double2* p, double2 v) {
+  gdbl* q = (gdbl*)p;
+  q[0] = v.x;
+  q[1] = v.y;
+}
+
 // Rows m0 .. LRM-1 of z: column j <- column j - f_j column pc, with pc =
 // 64 HF + pl (the pivot column's half is wave-uniform, so it selects code
 // instead of data).
@@ -273,8 +288,8 @@ struct GjRec {
         else f0 = make_double2(1.0 - ip.x, -ip.y);
       }
       if (wu == 0) {
-        frec[k * NL + lane] = f0;
-        frec[k * NL + 64 + lane] = f1;
+        gst(&frec[k * NL + lane], f0);
+        gst(&frec[k * NL + 64 + lane], f1);
         if (lane == 0) pcrec[k] = pc;
       }
       if (hf) col_update<1, LRM>(z, KB, mlim, pl, f0, f1);
@@ -308,7 +323,9 @@ __device__ __forceinline__ void eliminate(double2 (&z)[LRM][2], int n, int lane,
     rowbuf[64 + lane] = z[0][1];
   }
   GjRec<0>::run(z, n, lane, wu, um0, um1, rowbuf, frec, s.pcrec, &s.flag_singular);
-  __threadfence();
+  // the slot is read back by this workgroup only (one CU): workgroup-scope
+  // ordering, which the barrier gives, is all it needs (a device-scope fence
+  // would write back and invalidate the L2 that holds the multipliers)
   __syncthreads();
   const int tid = threadIdx.x;
   if (tid < NL) s.pos[tid] = tid;
@@ -322,19 +339,39 @@ __device__ __forceinline__ void eliminate(double2 (&z)[LRM][2], int n, int lane,
 template <int R>
 __device__ __forceinline__ void replay(double2 (&z)[R][2], int n, int lane, int w, int m0, const LLds& s,
                                        const double2* __restrict__ frec) {
-  double2 g0 = frec[lane], g1 = frec[64 + lane];
-#pragma unroll 1
-  for (int k = 0; k < n; ++k) {
-    const double2 f0 = g0, f1 = g1;
-    if (k + 1 < n) {  // next step's multipliers in flight during this step
-      g0 = frec[(k + 1) * NL + lane];
-      g1 = frec[(k + 1) * NL + 64 + lane];
-    }
-    const int pc = __builtin_amdgcn_readfirstlane(s.pcrec[k]);
-    const int hf = pc >> 6, pl = pc & 63;
-    if (hf) col_update<1, R>(z, 0, R, pl, f0, f1);
-    else col_update<0, R>(z, 0, R, pl, f0, f1);
+  // two multiplier buffers, each loaded two steps before its use and used on
+  // alternate steps: no register copies, so a step waits only for its own loads
+  double2 a0 = gld(&frec[lane]), a1 = gld(&frec[64 + lane]);
+  double2 b0 = a0, b1 = a1;
+  if (n > 1) {
+    b0 = gld(&frec[NL + lane]);
+    b1 = gld(&frec[NL + 64 + lane]);
   }
+#pragma unroll 1
+  for (int k = 0; k < n; k += 2) {
+    {
+      const int pc = __builtin_amdgcn_readfirstlane(s.pcrec[k]);
+      const int hf = pc >> 6, pl = pc & 63;
+      if (hf) col_update<1, R>(z, 0, R, pl, a0, a1);
+      else col_update<0, R>(z, 0, R, pl, a0, a1);
+      if (k + 2 < n) {
+        a0 = gld(&frec[(k + 2) * NL + lane]);
+        a1 = gld(&frec[(k + 2) * NL + 64 + lane]);
+      }
+    }
+    if (k + 1 < n) {
+      const int pc = __builtin_amdgcn_readfirstlane(s.pcrec[k + 1]);
+      const int hf = pc >> 6, pl = pc & 63;
+      if (hf) col_update<1, R>(z, 0, R, pl, b0, b1);
+      else col_update<0, R>(z, 0, R, pl, b0, b1);
+      if (k + 3 < n) {
+        b0 = gld(&frec[(k + 3) * NL + lane]);
+        b1 = gld(&frec[(k + 3) * NL + 64 + lane]);
+      }
+    }
+  }
+  (void)w;
+  (void)m0;
 }
 
 template <int STEPPER, int KQ>
@@ -354,7 +391,7 @@ __device__ __noinline__ void slice_block(double2* __restrict__ cg, double2* __re
   LMat c, d;
 #pragma unroll
   for (int e = 0; e < LNE; ++e) {
-    const double2 cv = cg[gb + 4 * NL * e], dv = dg[gb + 4 * NL * e];
+    const double2 cv = gld(&cg[gb + 4 * NL * e]), dv = gld(&dg[gb + 4 * NL * e]);
     c.r[e] = cv.x;
     c.i[e] = cv.y;
     d.r[e] = dv.x;
@@ -364,8 +401,8 @@ __device__ __noinline__ void slice_block(double2* __restrict__ cg, double2* __re
   double pdg[4], pof[4];
 #pragma unroll
   for (int e = 0; e < LNE; ++e) {
-    cg[gb + 4 * NL * e] = make_double2(c.r[e], c.i[e]);
-    dg[gb + 4 * NL * e] = make_double2(d.r[e], d.i[e]);
+    gst(&cg[gb + 4 * NL * e], make_double2(c.r[e], c.i[e]));
+    gst(&dg[gb + 4 * NL * e], make_double2(d.r[e], d.i[e]));
     const int row = 16 * w + 4 * e + (lane >> 4), col = LCB * cb + (lane & 15);
     const double av = sqrt(c.r[e] * c.r[e] + c.i[e] * c.i[e]);
     const bool in = row < N && col < N;
@@ -404,8 +441,8 @@ __device__ __noinline__ void elim_record(const double2* __restrict__ cg, const d
   if (__builtin_amdgcn_readfirstlane(which) == 0) {
 #pragma unroll
     for (int m = 0; m < LRM; ++m) {
-      z[m][0] = cg[(w + LW * m) * NL + lane];
-      z[m][1] = cg[(w + LW * m) * NL + 64 + lane];
+      z[m][0] = gld(&cg[(w + LW * m) * NL + lane]);
+      z[m][1] = gld(&cg[(w + LW * m) * NL + 64 + lane]);
     }
   } else {
 #pragma unroll
@@ -415,7 +452,7 @@ __device__ __noinline__ void elim_record(const double2* __restrict__ cg, const d
       const double g_r = g2v >= 0.0 ? sqrt(g2v) : 0.0, g_i = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
 #pragma unroll
       for (int hf = 0; hf < 2; ++hf) {
-        const double2 cv = cg[row * NL + 64 * hf + lane], pv = dg[row * NL + 64 * hf + lane];
+        const double2 cv = gld(&cg[row * NL + 64 * hf + lane]), pv = gld(&dg[row * NL + 64 * hf + lane]);
         z[m][hf] = make_double2(g_r * cv.x - g_i * cv.y + pv.y, g_r * cv.y + g_i * cv.x - pv.x);
       }
     }
@@ -440,20 +477,19 @@ __device__ __noinline__ void replay_p(double2* __restrict__ cg, double2* __restr
     double2 z[R][2];
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-      z[m][0] = dg[(w + LW * (m0 + m)) * NL + lane];
-      z[m][1] = dg[(w + LW * (m0 + m)) * NL + 64 + lane];
+      z[m][0] = gld(&dg[(w + LW * (m0 + m)) * NL + lane]);
+      z[m][1] = gld(&dg[(w + LW * (m0 + m)) * NL + 64 + lane]);
     }
     replay<R>(z, n, lane, w, m0, s, frec);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       const int row = w + LW * (m0 + m);
-      dg[row * NL + p0] = z[m][0];
-      dg[row * NL + p1] = z[m][1];
-      cg[row * NL + lane] = make_double2(row == lane ? 1.0 : 0.0, 0.0);
-      cg[row * NL + 64 + lane] = make_double2(row == 64 + lane ? 1.0 : 0.0, 0.0);
+      gst(&dg[row * NL + p0], z[m][0]);
+      gst(&dg[row * NL + p1], z[m][1]);
+      gst(&cg[row * NL + lane], make_double2(row == lane ? 1.0 : 0.0, 0.0));
+      gst(&cg[row * NL + 64 + lane], make_double2(row == 64 + lane ? 1.0 : 0.0, 0.0));
     }
   }
-  __threadfence();
   __syncthreads();
 }
 
@@ -518,8 +554,8 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
     const int row = e / NL, col = e - row * NL;
     const double g2v = s.g2s[row];
     const bool dgn = row == col;
-    cg[e] = make_double2(dgn ? 1.0 : 0.0, 0.0);
-    dg[e] = make_double2((dgn && g2v < 0.0) ? sqrt(-g2v) : 0.0, (dgn && g2v >= 0.0) ? sqrt(g2v) : 0.0);
+    gst(&cg[e], make_double2(dgn ? 1.0 : 0.0, 0.0));
+    gst(&dg[e], make_double2((dgn && g2v < 0.0) ? sqrt(-g2v) : 0.0, (dgn && g2v >= 0.0) ? sqrt(g2v) : 0.0));
   }
   for (int e = tid; e < S.box; e += LT) s.tb[0][e] = Us[e];
   int nrhst = 0;
@@ -592,7 +628,7 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
     double2 v0 = make_double2(lane == pc0 ? 1.0 : 0.0, 0.0), v1 = make_double2(64 + lane == pc0 ? 1.0 : 0.0, 0.0);
 #pragma unroll 1
     for (int k = N - 1; k >= 0; --k) {
-      const double2 f0 = frec[k * NL + lane], f1 = frec[k * NL + 64 + lane];
+      const double2 f0 = gld(&frec[k * NL + lane]), f1 = gld(&frec[k * NL + 64 + lane]);
       double sr = (f0.x * v0.x - f0.y * v0.y) + (f1.x * v1.x - f1.y * v1.y);
       double si = (f0.x * v0.y + f0.y * v0.x) + (f1.x * v1.y + f1.y * v1.x);
 #pragma unroll
@@ -618,7 +654,7 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
       const double g2v = s.g2s[j];
       const double g_r = g2v >= 0.0 ? sqrt(g2v) : 0.0, g_i = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
       for (int k = 0; k < N; ++k) {
-        const double2 cv = cg[j * NL + k], pv = dg[j * NL + k], x = s.xv[k];
+        const double2 cv = gld(&cg[j * NL + k]), pv = gld(&dg[j * NL + k]), x = s.xv[k];
         const double lr = g_r * cv.x - g_i * cv.y - pv.y, li = g_r * cv.y + g_i * cv.x + pv.x;
         rj.x += lr * x.x - li * x.y;
         rj.y += lr * x.y + li * x.x;
