@@ -105,7 +105,8 @@ def solve_ode_str(Mfun, gam, h, n_slices, tab, threshold=THRESHOLD, literal_z0=F
     T_acc = np.eye(n, dtype=np.complex128) if track_transform else None
     for i in range(n_slices):
         Ms = [Mfun(i, r) for r in range(tab.stages)]
-        Z = rk_slice(Z, Ms, h, tab)
+        # an RK tableau, or a splitting composition (oracle/splitting.py) with its own step
+        Z = tab.step(Z, Ms, h) if hasattr(tab, "step") else rk_slice(Z, Ms, h, tab)
         xi = estcond_gershgorin(Z[:n])
         do = xi > threshold
         decisions.append(bool(do))

@@ -70,3 +70,8 @@ def _butcher6():
 RK4 = _rk4()
 RK6 = _butcher6()
 TABLEAUX = {"rk4": RK4, "rk6": RK6}
+
+# the splitting steppers of Sec. 3.4 share the node-table interface
+from .splitting import SP4, VERLET  # noqa: E402
+
+TABLEAUX.update({"sp4": SP4, "verlet": VERLET})

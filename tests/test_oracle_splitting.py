@@ -1,0 +1,70 @@
+"""Pins of the oracle's splitting steppers (Sec. 3.4, BAB form) against what
+the mathematics fixes: the triple-jump conditions, the observed order under
+step halving on a z-dependent potential, and exact flux conservation
+without absorption at a step where the RK steppers visibly violate it."""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+from oracle import driver, rk
+from oracle.splitting import SP4, VERLET
+from oracle.tableaux import RK4
+from synth import small_2d, small_row
+
+
+def test_triple_jump_weights():
+    g1, g2 = SP4.a[0], SP4.a[1]
+    assert SP4.a[2] == g1
+    assert 2 * g1 + g2 == pytest.approx(1.0, abs=1e-15)
+    assert 2 * g1 ** 3 + g2 ** 3 == pytest.approx(0.0, abs=1e-14)    # cancels the third-order error of Verlet
+    assert SP4.b.sum() == pytest.approx(1.0, abs=1e-15)
+    assert np.allclose(SP4.b, [g1 / 2, (g1 + g2) / 2, (g1 + g2) / 2, g1 / 2], atol=0)
+    # kick positions: 0, g1, g1 + g2 inside the slice and 1 (the next slice's 0)
+    assert np.allclose(SP4.tau, [0.0, g1, g1 + g2, 1.0], atol=1e-15)
+    assert SP4.cset == pytest.approx([0.0, g1, g1 + g2])
+    assert SP4.node_index(5, 0) == 15 and SP4.node_index(5, 2) == 17 and SP4.node_index(5, 3) == 18
+
+
+@pytest.mark.parametrize("comp", [VERLET, SP4], ids=lambda c: c.name)
+def test_splitting_order_on_z_dependent_potential(comp):
+    """Error ratio under step halving -> 2^order; a kick evaluated at the
+    wrong position (e.g. after its drift) or a wrong weight drops it."""
+    base = small_row(hmax=2, n_slices=400, thickness=6.0, n_layers=2)
+    base.structures[0].scat_b = np.array([0.5, 0.8, 1.1, 1.5])
+    th = float(base.theta0[2])
+
+    def run(L):
+        s = dataclasses.replace(base.structures[0], n_slices=L)
+        w = dataclasses.replace(base, structures=[s])
+        return driver.StructureSetup(w, s, comp).solve(th)[0]
+    ref = run(2560 if comp is SP4 else 5120)
+    Ls = (40, 80, 160) if comp is SP4 else (80, 160, 320)
+    e = [np.abs(run(L) - ref).max() for L in Ls]
+    r = e[1] / e[2]
+    assert 2 ** comp.order * 0.8 < r < 2 ** comp.order * 1.25, e
+
+
+def _flux(st, th):
+    gam, mask = st.angle(th)
+    rho, _, _, info = st.solve(th, track_transform=True)
+    tau = rk.transmission(info["Z"], info["T"], gam)
+    R = rk.intensity(rho, gam, mask, th)
+    T = np.zeros_like(R)
+    T[mask] = np.abs(tau[mask]) ** 2 * gam[0].real / gam[mask].real
+    return R.sum() + T.sum()
+
+
+def test_splitting_conserves_flux_exactly_without_absorption():
+    """Each kick and drift keeps Im(c^H c') for Hermitian M, so R + T = 1 to
+    rounding even at a coarse step, where RK4 is off by far more."""
+    wl = small_2d(n_beams=9, n_slices=20, thickness=4.0, n_layers=1, absorption=0.0, n_angles=3)
+    s = wl.structures[0]
+    st = driver.StructureSetup(wl, s, SP4)
+    st4 = driver.StructureSetup(wl, s, RK4)
+    worst_rk = 0.0
+    for th in wl.theta0:
+        assert _flux(st, float(th)) == pytest.approx(1.0, abs=1e-12)
+        worst_rk = max(worst_rk, abs(_flux(st4, float(th)) - 1.0))
+    assert worst_rk > 1e-6
