@@ -54,9 +54,17 @@ enum {
   RHEED_PAIR_SYNC = 3       /* split launch: the two workgroups of the pair lost contact */
 };
 
-/* Explicit RK tableaux (Sec. 3.4): classical 4th order, 4 stages, and
- * Butcher's 6th-order 7-stage method. */
-typedef enum { RHEED_RK4 = 0, RHEED_RK6 = 1 } rheed_stepper;
+/* Steppers (Sec. 3.4): the explicit RK tableaux (classical 4th order, 4
+ * stages; Butcher's 6th-order 7-stage method) and a splitting ("BAB")
+ * method of 4th order: the triple jump of the Stormer-Verlet step (drift
+ * weights g1, 1 - 2 g1, g1 with g1 = 1 / (2 - 2^(1/3)); kicks at the slice
+ * positions 0, g1, 1 - g1 and 1 with weights g1/2, 1/2 - g1/2, 1/2 - g1/2,
+ * g1/2, each kick using the potential at the position reached before its
+ * drift).  Node tables of SP4 sit at (i + c) h for c = 0, g1, 1 - g1 (three
+ * per slice, two of them outside the slice).  SP4 runs forward only (no
+ * state saving, no rheed_backward), every structure on the kernel that keeps
+ * a pair's state in plan-owned memory (the WHOLE layout). */
+typedef enum { RHEED_RK4 = 0, RHEED_RK6 = 1, RHEED_SP4 = 2 } rheed_stepper;
 
 /* Intensity normalisation (Sec. 2.1): FLUX = |rho_j|^2 Gamma_0/Gamma_j on
  * open beams; PAPER = the printed formula, FLUX times sin(theta0). */

@@ -14,7 +14,7 @@ import torch
 
 from . import _lib
 
-STEPPERS = {"rk4": _lib.RHEED_RK4, "rk6": _lib.RHEED_RK6}
+STEPPERS = {"rk4": _lib.RHEED_RK4, "rk6": _lib.RHEED_RK6, "sp4": _lib.RHEED_SP4}
 CONVENTIONS = {"flux": _lib.RHEED_INTENSITY_FLUX, "paper": _lib.RHEED_INTENSITY_PAPER}
 LAYOUTS = {"auto": _lib.RHEED_LAYOUT_AUTO, "whole": _lib.RHEED_LAYOUT_WHOLE, "split": _lib.RHEED_LAYOUT_SPLIT}
 

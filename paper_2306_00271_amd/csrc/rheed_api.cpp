@@ -38,6 +38,7 @@ struct rheed_plan_s {
   rheed_opts opts{};
   int n_struct = 0, n_pairs = 0, max_beams = 0, nodes_per_slice = 0;
   double cset[4] = {0, 0, 0, 0};
+  double sp_a[3] = {0, 0, 0}, sp_b[4] = {0, 0, 0, 0};  // splitting stepper weights
   long long table_elems = 0, n_atoms_total = 0, max_table = 0;
   std::vector<StructDev> hs;
   std::vector<int> beams, pair_struct;
@@ -99,7 +100,10 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
   if (!out || !opts || !structs || !angles_per_struct || n_struct < 1)
     return fail(RHEED_E_INVALID, "plan_create: null argument or n_struct < 1");
   *out = nullptr;
-  if (opts->stepper != RHEED_RK4 && opts->stepper != RHEED_RK6) return fail(RHEED_E_INVALID, "unknown stepper");
+  if (opts->stepper != RHEED_RK4 && opts->stepper != RHEED_RK6 && opts->stepper != RHEED_SP4)
+    return fail(RHEED_E_INVALID, "unknown stepper");
+  if (opts->stepper == RHEED_SP4 && opts->layout == RHEED_LAYOUT_SPLIT)
+    return fail(RHEED_E_UNSUPPORTED, "the splitting stepper runs on the one-workgroup-per-pair kernel only");
   if (!(opts->rhst_threshold >= 1.0)) return fail(RHEED_E_INVALID, "rhst_threshold must be >= 1");
   if (opts->checkpoint_every < 1) return fail(RHEED_E_INVALID, "checkpoint_every must be >= 1");
   if (opts->convention != RHEED_INTENSITY_FLUX && opts->convention != RHEED_INTENSITY_PAPER)
@@ -113,13 +117,30 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     P->nodes_per_slice = 2;
     P->cset[0] = 0.0;
     P->cset[1] = 0.5;
-  } else {
+  } else if (opts->stepper == RHEED_RK6) {
     P->nodes_per_slice = 4;
     P->cset[0] = 0.0;
     P->cset[1] = 1.0 / 3.0;
     P->cset[2] = 0.5;
     P->cset[3] = 2.0 / 3.0;
+  } else {
+    // triple jump of the Stormer-Verlet step: drifts g1, g2, g1 with
+    // 2 g1 + g2 = 1 and 2 g1^3 + g2^3 = 0; kicks at 0, g1, g1 + g2 and 1
+    const double g1 = 1.0 / (2.0 - std::cbrt(2.0)), g2 = 1.0 - 2.0 * g1;
+    P->sp_a[0] = g1;
+    P->sp_a[1] = g2;
+    P->sp_a[2] = g1;
+    P->sp_b[0] = 0.5 * g1;
+    P->sp_b[1] = 0.5 * (g1 + g2);
+    P->sp_b[2] = 0.5 * (g1 + g2);
+    P->sp_b[3] = 0.5 * g1;
+    P->nodes_per_slice = 3;
+    P->cset[0] = 0.0;
+    P->cset[1] = g1;
+    P->cset[2] = g1 + g2;
   }
+  // the splitting stepper runs every structure on the kernel for N > 64
+  const bool all_large = opts->stepper == RHEED_SP4;
   int max_l = 0;
   for (int s = 0; s < n_struct; ++s) {
     const rheed_structure& st = structs[s];
@@ -157,7 +178,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     d.hd = hmax - hmin;
     d.kd = kmax - kmin;
     d.box = (2 * d.hd + 1) * (2 * d.kd + 1);
-    const int box_max = st.n_beams <= NP ? MAXBOX : MAXBOXL;
+    const int box_max = (st.n_beams <= NP && !all_large) ? MAXBOX : MAXBOXL;
     if (d.box > box_max) {
       delete P;
       return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) + ": rod-difference table row of " +
@@ -170,7 +191,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     {
       const int W = 2 * d.kd + 1;
       std::vector<std::vector<int>> lists(d.box);
-      for (int j = 0; j < (st.n_beams <= NP ? st.n_beams : 0); ++j)
+      for (int j = 0; j < ((st.n_beams <= NP && !all_large) ? st.n_beams : 0); ++j)
         for (int k = 0; k < st.n_beams; ++k) {
           const int dh = st.beam_hk[2 * j] - st.beam_hk[2 * k], dk = st.beam_hk[2 * j + 1] - st.beam_hk[2 * k + 1];
           lists[(dh + d.hd) * W + (dk + d.kd)].push_back(j * NP + k);
@@ -228,7 +249,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     P->max_nodes = std::max(P->max_nodes, d.n_nodes);
     P->n_atoms_total += d.n_atoms;
     for (int a = 0; a < angles_per_struct[s]; ++a) {
-      (st.n_beams <= NP ? P->small_pairs : P->large_pairs).push_back(P->n_pairs + a);
+      ((st.n_beams <= NP && !all_large) ? P->small_pairs : P->large_pairs).push_back(P->n_pairs + a);
       P->pair_struct.push_back(s);
     }
     P->n_pairs += angles_per_struct[s];
@@ -421,7 +442,7 @@ rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* a
                            int32_t* pair_status, int32_t* n_rhst, void* workspace, size_t ws_bytes, void* stream) {
   if (!P || !U_tables || !angles || !intensity || !pair_status) return fail(RHEED_E_INVALID, "forward: null argument");
   if (workspace && !P->large_pairs.empty())
-    return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs every structure to have N <= 64");
+    return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs an RK stepper and every structure to have N <= 64");
   if (workspace && ws_bytes < P->fwd_ws)
     return fail(RHEED_E_INVALID, "forward: workspace of " + std::to_string(ws_bytes) + " bytes < " +
                                      std::to_string(P->fwd_ws));
@@ -462,6 +483,8 @@ rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* a
     la.f.xch = nullptr;
     la.scratch = P->d_lscratch;
     la.n_slots = P->large_slots;
+    for (int q = 0; q < 3; ++q) la.sp_a[q] = P->sp_a[q];
+    for (int q = 0; q < 4; ++q) la.sp_b[q] = P->sp_b[q];
     e = launch_forward_large((int)P->opts.stepper, la, st);
     if (e != hipSuccess) return hip_fail(e, "forward launch (N > 64)");
   }
@@ -540,7 +563,7 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
   if (!P || !U_tables || !angles || !dL_dI || !dL_dU || !workspace)
     return fail(RHEED_E_INVALID, "backward: null argument");
   if (!P->large_pairs.empty())
-    return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs every structure to have N <= 64");
+    return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs an RK stepper and every structure to have N <= 64");
   if (ws_bytes < P->fwd_ws + P->bwd_ws)
     return fail(RHEED_E_INVALID, "backward: workspace of " + std::to_string(ws_bytes) + " bytes < " +
                                      std::to_string(P->fwd_ws + P->bwd_ws));

@@ -89,6 +89,14 @@ struct LTab<1> {
   }
 };
 
+// The splitting stepper (BAB, Sec. 3.4): three kick positions per slice
+// (0, g1, g1 + g2 of the slice) and the next slice's 0; weights come with the
+// launch.
+template <>
+struct LTab<2> {
+  static constexpr int stages = 3, nodes = 3;
+};
+
 struct LLds {
   double2 xb[NL * LCB];            // stage input of one column block; pivot rows during eliminations
   double2 tb[5][MAXBOXL + 1];      // node tables of the slice (ring); entry `box` of every row stays 0
@@ -374,6 +382,108 @@ __device__ __forceinline__ void replay(double2 (&z)[R][2], int n, int lane, int 
   (void)m0;
 }
 
+// Splitting step of one column block, tiles of c and c' from the slot and
+// back: for r < nk, the kick c' <- c' - h w_r M(node n0 + r) c (the product
+// on the matrix cores, c of the block as the B operand in LDS) and, with
+// drift set, the drift c <- c + h a_r c'.  Kept out of line like
+// slice_block.
+template <int KQ>
+__device__ __noinline__ void bab_block(double2* __restrict__ cg, double2* __restrict__ dg, int cb, int nk, int n0,
+                                       double w0, double w1, double w2, double a0, double a1, double a2, bool drift,
+                                       double h, int N) {
+  LLds& s = large_lds;
+  constexpr int SL = LTab<2>::nodes + 1;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  unsigned gidx[LQ / 2];
+#pragma unroll
+  for (int q = 0; q < LQ / 2; ++q) gidx[q] = q < KQ / 2 ? s.gix[q][tid] : 0u;
+  double g2[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) g2[v] = s.g2s[16 * w + 4 * v + (lane >> 4)];
+  const int ob = (16 * w + (lane >> 4)) * LCB + (lane & 15);
+  const int gb = (16 * w + (lane >> 4)) * NL + LCB * cb + (lane & 15);
+  LMat c, d;
+#pragma unroll
+  for (int e = 0; e < LNE; ++e) {
+    const double2 cv = gld(&cg[gb + 4 * NL * e]), dv = gld(&dg[gb + 4 * NL * e]);
+    c.r[e] = cv.x;
+    c.i[e] = cv.y;
+    d.r[e] = dv.x;
+    d.i[e] = dv.y;
+  }
+#pragma unroll 1
+  for (int r = 0; r < nk; ++r) {
+#pragma unroll
+    for (int e = 0; e < LNE; ++e) s.xb[ob + 4 * LCB * e] = make_double2(c.r[e], c.i[e]);
+    __syncthreads();
+    LMat G;
+    gemm_tile<KQ>(s.xb, s.tb[(n0 + r) % SL], gidx, lane, G);
+    const double hw = h * (r == 0 ? w0 : r == 1 ? w1 : w2);
+#pragma unroll
+    for (int e = 0; e < LNE; ++e) {
+      d.r[e] -= hw * (G.r[e] + g2[e] * c.r[e]);
+      d.i[e] -= hw * (G.i[e] + g2[e] * c.i[e]);
+    }
+    if (drift) {
+      const double ha = h * (r == 0 ? a0 : r == 1 ? a1 : a2);
+#pragma unroll
+      for (int e = 0; e < LNE; ++e) {
+        c.r[e] += ha * d.r[e];
+        c.i[e] += ha * d.i[e];
+      }
+    }
+    __syncthreads();
+  }
+  double pdg[4], pof[4];
+#pragma unroll
+  for (int e = 0; e < LNE; ++e) {
+    gst(&cg[gb + 4 * NL * e], make_double2(c.r[e], c.i[e]));
+    gst(&dg[gb + 4 * NL * e], make_double2(d.r[e], d.i[e]));
+    const int row = 16 * w + 4 * e + (lane >> 4), col = LCB * cb + (lane & 15);
+    const double av = sqrt(c.r[e] * c.r[e] + c.i[e] * c.i[e]);
+    const bool in = row < N && col < N;
+    pdg[e] = (in && row == col) ? av : 0.0;
+    pof[e] = (in && row != col) ? av : 0.0;
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) {
+      pdg[v] += __shfl_xor(pdg[v], off, 64);
+      pof[v] += __shfl_xor(pof[v], off, 64);
+    }
+  }
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = 16 * w + 4 * v + (lane >> 4);
+      s.rdg[row] = (cb == 0 ? 0.0 : s.rdg[row]) + pdg[v];
+      s.rof[row] = (cb == 0 ? 0.0 : s.rof[row]) + pof[v];
+    }
+  }
+}
+
+// The column blocks of a splitting step (blocks and k-steps stop at N as
+// for the RK stages; the stepper runs every N <= 128, so down to one block).
+__device__ __forceinline__ void bab_blocks(double2* cg, double2* dg, int ncb, int nk, int n0, double w0, double w1,
+                                           double w2, const double (&a)[3], bool drift, double h, int N) {
+#define RHEED_BAB(KQ)                                                                            \
+  for (int cb = 0; cb < ncb; ++cb)                                                               \
+    bab_block<KQ>(cg, dg, cb, nk, n0, w0, w1, w2, a[0], a[1], a[2], drift, h, N);                 \
+  break;
+  switch (ncb) {
+    case 1: RHEED_BAB(4)
+    case 2: RHEED_BAB(8)
+    case 3: RHEED_BAB(12)
+    case 4: RHEED_BAB(16)
+    case 5: RHEED_BAB(20)
+    case 6: RHEED_BAB(24)
+    case 7: RHEED_BAB(28)
+    default: RHEED_BAB(32)
+  }
+#undef RHEED_BAB
+}
+
 template <int STEPPER, int KQ>
 __device__ __noinline__ void slice_block(double2* __restrict__ cg, double2* __restrict__ dg, int cb, int nb,
                                          double h, int N) {
@@ -508,7 +618,7 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
   const int L = S.n_slices;
   const double h = S.h;
   const double2* __restrict__ Us = a.U + S.table_off;
-  const int ncb = (N + LCB - 1) / LCB;  // column blocks holding columns < N (5 .. 8)
+  const int ncb = (N + LCB - 1) / LCB;  // column blocks holding columns < N (5 .. 8; 1 .. 8 for splitting)
 
   if (tid < NL) {
     s.bhk[tid][0] = tid < N ? a.beams[2 * (S.beam_off + tid)] : 0;
@@ -571,6 +681,16 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
       }
     }
     __syncthreads();
+    if constexpr (STEPPER == 2) {
+      // kicks at the slice's nodes 0, g1, g1 + g2 with drifts between; the
+      // slice's last kick (at its end, the next slice's 0) is merged into the
+      // next slice's first: kicks act on c' from the left, so they commute
+      // with the transformation (a right multiplication) and leave Q = c,
+      // and with it the badness, as they are
+      const double w0 = i == 0 ? A.sp_b[0] : A.sp_b[0] + A.sp_b[3];
+      const double adr[3] = {A.sp_a[0], A.sp_a[1], A.sp_a[2]};
+      bab_blocks(cg, dg, ncb, 3, nb, w0, A.sp_b[1], A.sp_b[2], adr, true, h, N);
+    } else {
     // column blocks and k-steps past N hold zeros only (padding columns of
     // c and c' stay as they are, U_jk = 0 for k >= N), so both stop at N
     switch (ncb) {
@@ -586,6 +706,7 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
       default:
         for (int cb = 0; cb < NCB; ++cb) slice_block<STEPPER, 32>(cg, dg, cb, nb, h, N);
         break;
+    }
     }
     __syncthreads();
     // condition estimate of Q = c (Sec. 3.2): the Gershgorin / Varah bound
@@ -618,6 +739,11 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
     }
   }
 
+  if constexpr (STEPPER == 2) {  // the last slice's final kick, at z = 0
+    const double adr[3] = {0.0, 0.0, 0.0};
+    bab_blocks(cg, dg, ncb, 1, L * T::nodes, A.sp_b[3], 0.0, 0.0, adr, false, h, N);
+    __syncthreads();
+  }
   // reflection (Eq. vrhocomp): upper = Gamma Q - iP, lower = Gamma Q + iP,
   // rho = lower x with upper x = e_1
   elim_record(cg, dg, frec, N, 1);
@@ -701,18 +827,23 @@ hipError_t launch_forward_large(int stepper, const LargeArgs& a, hipStream_t str
   if (grid < 1) return hipErrorInvalidValue;
   if (stepper == 0)
     hipLaunchKernelGGL(forward_large_kernel<0>, dim3(grid), dim3(LT), 0, stream, a);
-  else
+  else if (stepper == 1)
     hipLaunchKernelGGL(forward_large_kernel<1>, dim3(grid), dim3(LT), 0, stream, a);
+  else
+    hipLaunchKernelGGL(forward_large_kernel<2>, dim3(grid), dim3(LT), 0, stream, a);
   return hipGetLastError();
 }
 
 int forward_large_slots(int device) {
   int cus = 0, per0 = 0, per1 = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  int per2 = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per0, forward_large_kernel<0>, LT, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, forward_large_kernel<1>, LT, 0) != hipSuccess)
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, forward_large_kernel<1>, LT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per2, forward_large_kernel<2>, LT, 0) != hipSuccess)
     return 0;
-  const int per = per0 < per1 ? per0 : per1;
+  int per = per0 < per1 ? per0 : per1;
+  per = per < per2 ? per : per2;
   return cus * (per > 0 ? per : 0);
 }
 

@@ -17,10 +17,13 @@ constexpr long long LSLOT_F = 2LL * NL * NL * 16;
 constexpr long long LSLOT_BYTES = 3LL * NL * NL * 16;
 
 struct LargeArgs {
-  FwdArgs f;       // f.pair_list / f.n_pairs: the pairs with N > 64
+  FwdArgs f;       // f.pair_list / f.n_pairs: the pairs this kernel runs
   char* scratch;   // n_slots * LSLOT_BYTES, plan-owned
   int n_slots;     // workgroups of the launch (each loops over pairs)
   int pad;
+  // splitting stepper: drift weights a_1..a_3 and kick weights b_1..b_4
+  double sp_a[3];
+  double sp_b[4];
 };
 
 hipError_t launch_forward_large(int stepper, const LargeArgs& a, hipStream_t stream);

@@ -1,0 +1,94 @@
+"""Parity of the splitting stepper (Sec. 3.4, BAB form; the fourth-order
+triple jump of the Stormer-Verlet step) on the GPU with the oracle's own
+splitting step, through the C ABI."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import driver
+from oracle.tableaux import TABLEAUX
+from synth import small_2d, small_row
+from tests.gpu_util import eacc, gpu_forward, oracle_forward
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _report(name, e):
+    print(f"[parity] {name}: eacc={e:.3e}", flush=True)
+
+
+def test_potential_tables_at_the_splitting_nodes():
+    """Kick positions 0, g1 and g1 + g2 of every slice (two of them outside
+    the slice) and the final node, against the oracle's table."""
+    wl = small_2d(n_beams=37, n_slices=10, n_layers=2)
+    res = gpu_forward(wl, stepper="sp4")
+    st = driver.StructureSetup(wl, wl.structures[0], TABLEAUX["sp4"])
+    ref = st.table.ravel()
+    assert res["U"].shape == ref.shape
+    assert np.abs(res["U"] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n_beams", [21, 64, 65, 121])
+def test_forward_sp4(n_beams):
+    wl = small_2d(n_beams=n_beams, n_slices=40, thickness=4.0, n_layers=2, n_angles=4)
+    res = gpu_forward(wl, stepper="sp4", want_rho=True)
+    ref, rho_ref, nr = oracle_forward(wl, stepper="sp4")
+    got = res["intensity"][:, :n_beams]
+    assert (res["status"] == 0).all()
+    e = eacc(got, ref)
+    _report(f"sp4 N={n_beams} rhst={nr.tolist()} gpu_rhst={res['n_rhst'].tolist()}", e)
+    assert e <= TOL
+    assert res["n_rhst"].tolist() == nr.tolist()
+    rho = res["rho"][:, :n_beams]
+    assert np.abs(rho - rho_ref).max() <= 1e-9 * np.abs(rho_ref).max()
+
+
+def test_forward_sp4_single_beam_and_row():
+    """N = 1 (one column block of one k-step) and the 13-beam positron row."""
+    wl = small_row(hmax=0, n_slices=60, thickness=6.0, n_layers=2, n_angles=5)
+    res = gpu_forward(wl, stepper="sp4")
+    ref, _, _ = oracle_forward(wl, stepper="sp4")
+    e = eacc(res["intensity"][:, :1], ref)
+    _report("sp4 N=1", e)
+    assert e <= TOL
+    wl = small_row(hmax=6, n_slices=80, thickness=12.0, n_layers=4, n_angles=6)
+    res = gpu_forward(wl, stepper="sp4")
+    ref, _, _ = oracle_forward(wl, stepper="sp4")
+    e = eacc(res["intensity"][:, :13], ref)
+    _report("sp4 row N=13", e)
+    assert e <= TOL
+
+
+def test_sp4_uneven_batch_in_one_launch():
+    parts = [small_2d(n_beams=n, n_slices=L, thickness=0.1 * L, n_layers=2, n_angles=3, seed=70 + i)
+             for i, (n, L) in enumerate(((13, 30), (61, 24), (91, 20)))]
+    wl = dataclasses.replace(parts[0], structures=[p.structures[0] for p in parts])
+    res = gpu_forward(wl, stepper="sp4")
+    assert res["plan"].info.large_pairs == 9
+    assert (res["status"] == 0).all()
+    A = len(wl.theta0)
+    for s, p in enumerate(parts):
+        N = p.structures[0].n_beams
+        ref, _, _ = oracle_forward(wl, s_idx=s, stepper="sp4")
+        e = eacc(res["intensity"][s * A:(s + 1) * A, :N], ref)
+        _report(f"sp4 batch structure {s} N={N}", e)
+        assert e <= TOL
+        assert np.all(res["intensity"][s * A:(s + 1) * A, N:] == 0.0)
+
+
+def test_sp4_refuses_split_layout_and_the_adjoint():
+    import torch
+    from paper_2306_00271_amd import api
+    from paper_2306_00271_amd._lib import RheedError
+    wl = small_2d(n_beams=21, n_slices=4, thickness=0.4, n_layers=2, n_angles=2)
+    with pytest.raises(RheedError, match="one-workgroup"):
+        api.plan_for(wl, stepper="sp4", layout="split")
+    plan = api.plan_for(wl, stepper="sp4")
+    dev = torch.device("cuda:0")
+    U = plan.potential(api.atoms_for(wl, dev))
+    ws = torch.empty(1024, dtype=torch.uint8, device=dev)
+    with pytest.raises(RheedError, match="RK stepper"):
+        plan.forward(U, api.angles_for(wl, dev), workspace=ws)
