@@ -243,14 +243,63 @@ def uneven_forward(n_structures, steps=2, cpu=True):
     return res
 
 
+# ------------------------------------------------- steppers: accuracy vs time
+def stepper_comparison(steps=2):
+    """The paper's comparison of steppers (Sec. 5: accuracy against time) on
+    the N = 61 slab, 128 angles: each stepper at several slice counts, eacc
+    (max over angles of the 2-norm error of the intensities over the largest
+    2-norm of the reference) against RK6 at 1600 slices (h = 0.025 A), and
+    the mean time of one forward call.  RK steppers run on the N <= 64
+    kernels (split layout at 128 pairs), the splitting stepper on the kernel
+    that keeps a pair's state in plan-owned memory."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from paper_2306_00271_amd import api
+    from synth import config2
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    base = config2()
+
+    def run(stepper, L, reps):
+        s = dataclasses.replace(base.structures[0], n_slices=L)
+        w = dataclasses.replace(base, structures=[s])
+        plan = api.plan_for(w, stepper=stepper)
+        U = plan.potential(api.atoms_for(w, dev))
+        ang = api.angles_for(w, dev)
+        out = plan.forward(U, ang)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            out = plan.forward(U, ang)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return out["intensity"].cpu().numpy()[:, :61], e0.elapsed_time(e1) / reps, int((out["status"] != 0).sum())
+
+    ref, _, _ = run("rk6", 1600, 1)
+    den = float(np.max(np.linalg.norm(ref, axis=1)))
+    rows = []
+    for stepper, Ls in (("rk4", (800, 1600, 3200)), ("rk6", (200, 400, 800)), ("sp4", (400, 800, 1600, 3200))):
+        for L in Ls:
+            eta, ms, bad = run(stepper, L, steps)
+            e = float(np.max(np.linalg.norm(eta - ref, axis=1))) / den
+            rows.append({"stepper": stepper, "slices": L, "h": round(40.0 / L, 5), "eacc": float(f"{e:.3e}"),
+                         "ms": round(ms, 3), "bad_pairs": bad})
+    return {"workload": "N=61 slab, 128 angles, forward", "reference": "rk6 at 1600 slices", "points": rows}
+
+
 # -------------------------------------------------------------------- bench
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["fwd", "fwd+adj", "uneven"], default="fwd+adj",
-                    help="uneven: only the uneven-N batched forward variant, as its own JSON line")
+    ap.add_argument("--mode", choices=["fwd", "fwd+adj", "uneven", "steppers"], default="fwd+adj",
+                    help="uneven: only the uneven-N batched forward variant; steppers: only the accuracy-vs-time "
+                         "comparison of the steppers; each as its own JSON line")
     ap.add_argument("--structures", type=int, default=1, help="structures in the batch (128 angles each)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-per-angle", action="store_true",
@@ -268,6 +317,9 @@ def main():
         sys.exit(2)
     if args.traffic_probe:
         traffic_probe(args.checkpoint_every)
+        return
+    if args.mode == "steppers":
+        print(json.dumps({"stepper_comparison": stepper_comparison(steps=args.steps)}))
         return
     if args.mode == "uneven":
         print(json.dumps({"uneven_n_forward": uneven_forward(max(1, args.uneven_structures), steps=args.steps,
