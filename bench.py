@@ -291,6 +291,36 @@ def stepper_comparison(steps=2):
     return {"workload": "N=61 slab, 128 angles, forward", "reference": "rk6 at 1600 slices", "points": rows}
 
 
+def large_source_hash():
+    """sha256 of the sources the kernel for N > 64 is built from."""
+    h = hashlib.sha256()
+    for f in ("rheed_forward_large.hip", "rheed_large.h", "rheed_gj.h", "rheed_internal.h"):
+        with open(os.path.join(ROOT, "paper_2306_00271_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_probe_uneven(n_structures):
+    """One forward launch of the N > 64 pairs of the uneven-N variant and one
+    device copy of 1 GiB, for FETCH_SIZE / WRITE_SIZE counter runs."""
+    import dataclasses
+    import torch
+    from paper_2306_00271_amd import api
+    from synth import config3
+    dev = torch.device("cuda:0")
+    wl = config3(n_structures)
+    w = dataclasses.replace(wl, structures=[st for st in wl.structures if st.n_beams > 64])
+    plan = api.plan_for(w, stepper="rk6")
+    U = plan.potential(api.atoms_for(w, dev))
+    plan.forward(U, api.angles_for(w, dev))
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": src.numel() * 8, "source_sha256": large_source_hash(),
+                      "kernel": "forward_large_kernel<1>", "pairs": plan.n_pairs}))
+
+
 # -------------------------------------------------------------------- bench
 def main():
     ap = argparse.ArgumentParser()
@@ -316,7 +346,10 @@ def main():
               "pairs are independent and would shard across GPUs (see DESIGN.md).", file=sys.stderr)
         sys.exit(2)
     if args.traffic_probe:
-        traffic_probe(args.checkpoint_every)
+        if args.mode == "uneven":
+            traffic_probe_uneven(max(1, args.uneven_structures))
+        else:
+            traffic_probe(args.checkpoint_every)
         return
     if args.mode == "steppers":
         print(json.dumps({"stepper_comparison": stepper_comparison(steps=args.steps)}))

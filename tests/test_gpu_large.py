@@ -240,3 +240,26 @@ def test_nonfinite_table_marks_only_its_pairs(layout, bad):
             e = eacc(out["intensity"][rows, :N].cpu().numpy(), ref)
             _report(f"NaN in structure {bad} ({layout}): structure {s} N={N}", e)
             assert e <= TOL
+
+
+@pytest.mark.parametrize("n_slices,threshold", [(1, 1.0), (3, 1e300), (6, 1.0)])
+def test_large_edge_cases(n_slices, threshold):
+    """One slice (and a transformation right after it), no transformation at
+    all on a thin slab, and one after every slice; N = 97."""
+    wl = small_2d(n_beams=97, n_slices=n_slices, thickness=0.1 * n_slices, n_layers=1, n_angles=3)
+    res = gpu_forward(wl, stepper="rk6", threshold=threshold)
+    ref, _, nr = oracle_forward(wl, stepper="rk6", threshold=threshold)
+    assert (res["status"] == 0).all()
+    assert res["n_rhst"].tolist() == nr.tolist()
+    e = eacc(res["intensity"][:, :97], ref)
+    _report(f"N=97 L={n_slices} threshold={threshold:g} rhst={nr.tolist()}", e)
+    assert e <= TOL
+
+
+def test_large_paper_convention():
+    wl = small_2d(n_beams=81, n_slices=12, thickness=1.2, n_layers=2, n_angles=3)
+    res = gpu_forward(wl, stepper="rk6", convention="paper")
+    ref, _, _ = oracle_forward(wl, stepper="rk6", convention="paper")
+    e = eacc(res["intensity"][:, :81], ref)
+    _report("N=81 printed convention", e)
+    assert e <= TOL
