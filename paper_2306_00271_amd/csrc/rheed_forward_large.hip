@@ -170,14 +170,16 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 // belongs to row 16 w + 4 v + (lane >> 4), block column lane & 15.
 template <int KQ>
 __device__ __forceinline__ void gemm_tile(const double2* __restrict__ xb, const double2* __restrict__ tsl,
-                                          const unsigned (&gidx)[LQ / 2], int lane, LMat& out) {
+                                          const unsigned* __restrict__ gix, int lane, LMat& out) {
   __builtin_amdgcn_sched_barrier(0);
   d4 t1 = d4{0, 0, 0, 0}, t2 = t1, t3 = t1;
   int bb = (lane >> 4) * LCB + (lane & 15);
   asm volatile("" : "+v"(bb));  // keep the addresses from being hoisted out of the caller's loops
 #pragma unroll
   for (int q = 0; q < KQ; ++q) {
-    const unsigned gi = (q & 1) ? (gidx[q >> 1] >> 16) : (gidx[q >> 1] & 0xffffu);
+    // packed gather indices from LDS (word q/2 of this thread), not held in registers
+    const unsigned gw = gix[(q >> 1) * LT];
+    const unsigned gi = (q & 1) ? (gw >> 16) : (gw & 0xffffu);
     const double2 u = tsl[gi];
     const double2 x = xb[bb + 4 * LCB * q];
     t1 = mfma(u.x, x.x, t1);
@@ -196,8 +198,8 @@ __device__ __forceinline__ void gemm_tile(const double2* __restrict__ xb, const 
 // One RK step of one column block: c, d (= c') of the wave's tile in, the
 // stepped tile out.  xb holds X_r of the block while its product runs.
 template <int STEPPER, int KQ>
-__device__ __forceinline__ void step_block(LLds& s, LMat& c, LMat& d, const unsigned (&gidx)[LQ / 2],
-                                           const double (&g2)[4], int ob, int lane, int nb, double h) {
+__device__ __forceinline__ void step_block(LLds& s, LMat& c, LMat& d, const double (&g2)[4], int ob, int lane,
+                                           int nb, double h) {
   using T = LTab<STEPPER>;
   constexpr int SL = T::nodes + 1;
   const double hh = h * h;
@@ -212,7 +214,6 @@ __device__ __forceinline__ void step_block(LLds& s, LMat& c, LMat& d, const unsi
   }
 #pragma unroll
   for (int r = 0; r < T::stages; ++r) {
-    LMat X;
     const double hc = h * T::c(r);
 #pragma unroll
     for (int e = 0; e < LNE; ++e) {
@@ -224,16 +225,15 @@ __device__ __forceinline__ void step_block(LLds& s, LMat& c, LMat& d, const unsi
           xi -= hh * T::a2(r, m) * G[m].i[e];
         }
       }
-      X.r[e] = xr;
-      X.i[e] = xi;
       s.xb[ob + 4 * LCB * e] = make_double2(xr, xi);
     }
     __syncthreads();
-    gemm_tile<KQ>(s.xb, s.tb[(nb + T::node(r)) % SL], gidx, lane, G[r]);
+    gemm_tile<KQ>(s.xb, s.tb[(nb + T::node(r)) % SL], &s.gix[0][threadIdx.x], lane, G[r]);
 #pragma unroll
     for (int e = 0; e < LNE; ++e) {
-      G[r].r[e] += g2[e] * X.r[e];
-      G[r].i[e] += g2[e] * X.i[e];
+      const double2 x = s.xb[ob + 4 * LCB * e];  // X_r back from LDS rather than kept in registers
+      G[r].r[e] += g2[e] * x.x;
+      G[r].i[e] += g2[e] * x.y;
       if (T::ba(r) != 0.0) {
         cn.r[e] -= hh * T::ba(r) * G[r].r[e];
         cn.i[e] -= hh * T::ba(r) * G[r].i[e];
@@ -385,18 +385,14 @@ __device__ __forceinline__ void replay(double2 (&z)[R][2], int n, int lane, int 
 // Splitting step of one column block, tiles of c and c' from the slot and
 // back: for r < nk, the kick c' <- c' - h w_r M(node n0 + r) c (the product
 // on the matrix cores, c of the block as the B operand in LDS) and, with
-// drift set, the drift c <- c + h a_r c'.  Kept out of line like
-// slice_block.
+// drift set, the drift c <- c + h a_r c'.
 template <int KQ>
-__device__ __noinline__ void bab_block(double2* __restrict__ cg, double2* __restrict__ dg, int cb, int nk, int n0,
+__device__ __forceinline__ void bab_block(double2* __restrict__ cg, double2* __restrict__ dg, int cb, int nk, int n0,
                                        double w0, double w1, double w2, double a0, double a1, double a2, bool drift,
                                        double h, int N) {
   LLds& s = large_lds;
   constexpr int SL = LTab<2>::nodes + 1;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  unsigned gidx[LQ / 2];
-#pragma unroll
-  for (int q = 0; q < LQ / 2; ++q) gidx[q] = q < KQ / 2 ? s.gix[q][tid] : 0u;
   double g2[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) g2[v] = s.g2s[16 * w + 4 * v + (lane >> 4)];
@@ -417,7 +413,7 @@ __device__ __noinline__ void bab_block(double2* __restrict__ cg, double2* __rest
     for (int e = 0; e < LNE; ++e) s.xb[ob + 4 * LCB * e] = make_double2(c.r[e], c.i[e]);
     __syncthreads();
     LMat G;
-    gemm_tile<KQ>(s.xb, s.tb[(n0 + r) % SL], gidx, lane, G);
+    gemm_tile<KQ>(s.xb, s.tb[(n0 + r) % SL], &s.gix[0][tid], lane, G);
     const double hw = h * (r == 0 ? w0 : r == 1 ? w1 : w2);
 #pragma unroll
     for (int e = 0; e < LNE; ++e) {
@@ -463,13 +459,23 @@ __device__ __noinline__ void bab_block(double2* __restrict__ cg, double2* __rest
   }
 }
 
+// All column blocks of one splitting step, out of line: one call per slice,
+// so the registers it saves and restores on entry and exit (to scratch, which
+// reaches memory) are paid once per slice, not once per block.
+template <int KQ>
+__device__ __noinline__ void bab_all(double2* __restrict__ cg, double2* __restrict__ dg, int ncb, int nk, int n0,
+                                     double w0, double w1, double w2, double a0, double a1, double a2, bool drift,
+                                     double h, int N) {
+#pragma unroll 1
+  for (int cb = 0; cb < ncb; ++cb) bab_block<KQ>(cg, dg, cb, nk, n0, w0, w1, w2, a0, a1, a2, drift, h, N);
+}
+
 // The column blocks of a splitting step (blocks and k-steps stop at N as
 // for the RK stages; the stepper runs every N <= 128, so down to one block).
 __device__ __forceinline__ void bab_blocks(double2* cg, double2* dg, int ncb, int nk, int n0, double w0, double w1,
                                            double w2, const double (&a)[3], bool drift, double h, int N) {
 #define RHEED_BAB(KQ)                                                                            \
-  for (int cb = 0; cb < ncb; ++cb)                                                               \
-    bab_block<KQ>(cg, dg, cb, nk, n0, w0, w1, w2, a[0], a[1], a[2], drift, h, N);                 \
+  bab_all<KQ>(cg, dg, ncb, nk, n0, w0, w1, w2, a[0], a[1], a[2], drift, h, N);                    \
   break;
   switch (ncb) {
     case 1: RHEED_BAB(4)
@@ -485,13 +491,10 @@ __device__ __forceinline__ void bab_blocks(double2* cg, double2* dg, int ncb, in
 }
 
 template <int STEPPER, int KQ>
-__device__ __noinline__ void slice_block(double2* __restrict__ cg, double2* __restrict__ dg, int cb, int nb,
+__device__ __forceinline__ void slice_block(double2* __restrict__ cg, double2* __restrict__ dg, int cb, int nb,
                                          double h, int N) {
   LLds& s = large_lds;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  unsigned gidx[LQ / 2];
-#pragma unroll
-  for (int q = 0; q < LQ / 2; ++q) gidx[q] = q < KQ / 2 ? s.gix[q][tid] : 0u;
   double g2[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) g2[v] = s.g2s[16 * w + 4 * v + (lane >> 4)];
@@ -507,7 +510,7 @@ __device__ __noinline__ void slice_block(double2* __restrict__ cg, double2* __re
     d.r[e] = dv.x;
     d.i[e] = dv.y;
   }
-  step_block<STEPPER, KQ>(s, c, d, gidx, g2, ob, lane, nb, h);
+  step_block<STEPPER, KQ>(s, c, d, g2, ob, lane, nb, h);
   double pdg[4], pof[4];
 #pragma unroll
   for (int e = 0; e < LNE; ++e) {
@@ -535,6 +538,16 @@ __device__ __noinline__ void slice_block(double2* __restrict__ cg, double2* __re
       s.rof[row] = (cb == 0 ? 0.0 : s.rof[row]) + pof[v];
     }
   }
+}
+
+// All column blocks of one slice, out of line: one call per slice, so the
+// registers it saves and restores on entry and exit (to scratch, which
+// reaches memory) are paid once per slice, not once per block.
+template <int STEPPER, int KQ>
+__device__ __noinline__ void slice_all(double2* __restrict__ cg, double2* __restrict__ dg, int ncb, int nb, double h,
+                                       int N) {
+#pragma unroll 1
+  for (int cb = 0; cb < ncb; ++cb) slice_block<STEPPER, KQ>(cg, dg, cb, nb, h, N);
 }
 
 // Recording elimination (see GjRec) of Q = c (which = 0) or of the
@@ -695,16 +708,16 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
     // c and c' stay as they are, U_jk = 0 for k >= N), so both stop at N
     switch (ncb) {
       case 5:
-        for (int cb = 0; cb < 5; ++cb) slice_block<STEPPER, 20>(cg, dg, cb, nb, h, N);
+        slice_all<STEPPER, 20>(cg, dg, 5, nb, h, N);
         break;
       case 6:
-        for (int cb = 0; cb < 6; ++cb) slice_block<STEPPER, 24>(cg, dg, cb, nb, h, N);
+        slice_all<STEPPER, 24>(cg, dg, 6, nb, h, N);
         break;
       case 7:
-        for (int cb = 0; cb < 7; ++cb) slice_block<STEPPER, 28>(cg, dg, cb, nb, h, N);
+        slice_all<STEPPER, 28>(cg, dg, 7, nb, h, N);
         break;
       default:
-        for (int cb = 0; cb < NCB; ++cb) slice_block<STEPPER, 32>(cg, dg, cb, nb, h, N);
+        slice_all<STEPPER, 32>(cg, dg, NCB, nb, h, N);
         break;
     }
     }
