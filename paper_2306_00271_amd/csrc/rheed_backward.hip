@@ -25,7 +25,8 @@
 // walks back down.  Each stage costs one N x N matrix-vector product against
 // the node's rod-difference table in LDS.  Every stage writes (v_r, g_r) to a stage buffer;
 // grad_assemble_kernel then sums g v^H over the angles and stages of each
-// node on the FP64 units and bins the sum by rod difference, in a fixed order.
+// node on the FP64 matrix cores and bins the sum by rod difference, in a
+// fixed order.
 //
 // Thread layout of the vector work: 512 threads, thread t works on row
 // j = t >> 3 and on columns 8 (t & 7) .. +7; the eight threads of a row reduce
@@ -505,7 +506,6 @@ __global__ __launch_bounds__(256) void grad_assemble_kernel(GradArgs a) {
   const int n = blockIdx.x;
   if (n >= S.n_nodes) return;
   const int tid = threadIdx.x;
-  const int jr = tid >> 2, kc = tid & 3;
   const int res = n % a.nps;
   const int i0 = n / a.nps;
   // contributing (slice, stage) of node n
@@ -518,29 +518,53 @@ __global__ __launch_bounds__(256) void grad_assemble_kernel(GradArgs a) {
       ++nc;
     }
   }
-  double2 acc[16];
+  // C = G^T conj(V) over t = (angle, contribution), a complex 64 x 64 x T
+  // product on FP64 MFMA in the 3-real-product form: wave w owns rows
+  // 16 w .. +15 and all 4 column tiles; chunks of 16 t through LDS (rows of
+  // a short last chunk are zero).
+  const int lane = tid & 63, w = tid >> 6;
+  typedef double g4 __attribute__((ext_vector_type(4)));
+  g4 p1[4], p2[4], p3[4];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) acc[e] = make_double2(0.0, 0.0);
+  for (int jt = 0; jt < 4; ++jt) p1[jt] = p2[jt] = p3[jt] = g4{0, 0, 0, 0};
   const int total = S.n_angles * nc;
   for (int t0 = 0; t0 < total; t0 += 16) {
     const int cnt = min(16, total - t0);
-    for (int e = tid; e < cnt * NP; e += 256) {
-      const int t = t0 + e / NP, jj = e % NP;
-      const int pr = S.pair_off + t / nc, c = t % nc;
-      const double2* src = a.gbuf + (long long)pr * a.g_pair_stride + ((long long)ci[c] * a.stages + cr[c]) * 2 * NP;
-      vs[e / NP][jj] = src[jj];
-      gsh[e / NP][jj] = src[NP + jj];
+    for (int e = tid; e < 16 * NP; e += 256) {
+      const int tt = e / NP, jj = e % NP;
+      double2 vv = make_double2(0.0, 0.0), gg = vv;
+      if (tt < cnt) {
+        const int t = t0 + tt;
+        const int pr = S.pair_off + t / nc, c = t % nc;
+        const double2* src = a.gbuf + (long long)pr * a.g_pair_stride + ((long long)ci[c] * a.stages + cr[c]) * 2 * NP;
+        vv = src[jj];
+        gg = src[NP + jj];
+      }
+      vs[tt][jj] = vv;
+      gsh[tt][jj] = gg;
     }
     __syncthreads();
-    for (int t = 0; t < cnt; ++t) {
-      const double2 g = gsh[t][jr];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) acc[e] = cadd(acc[e], cmulc(vs[t][kc + 4 * e], g));
+    for (int q = 0; q < 4; ++q) {
+      const int tk = 4 * q + (lane >> 4);
+      const double2 g = gsh[tk][16 * w + (lane & 15)];   // A[j][t] = g_t[j]
+      const double gs = g.x + g.y;
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt) {
+        const double2 v = vs[tk][16 * jt + (lane & 15)];  // B[t][k] = conj(v_t[k])
+        p1[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.x, v.x, p1[jt], 0, 0, 0);
+        p2[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.y, -v.y, p2[jt], 0, 0, 0);
+        p3[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(gs, v.x - v.y, p3[jt], 0, 0, 0);
+      }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int e = 0; e < 16; ++e) C[jr][kc + 4 * e] = acc[e];
+  for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      C[16 * w + 4 * v + (lane >> 4)][16 * jt + (lane & 15)] =
+          make_double2(p1[jt][v] - p2[jt][v], p3[jt][v] - p1[jt][v] - p2[jt][v]);
   __syncthreads();
   const int* bp = a.bin_ptr + S.bin_ptr_off;
   const int* bj = a.bin_jk + S.bin_jk_off;
