@@ -16,8 +16,9 @@ RHEED_OK, RHEED_E_INVALID, RHEED_E_HIP, RHEED_E_NOMEM, RHEED_E_UNSUPPORTED = 0, 
 RHEED_RK4, RHEED_RK6, RHEED_SP4 = 0, 1, 2
 RHEED_INTENSITY_FLUX, RHEED_INTENSITY_PAPER = 0, 1
 RHEED_LAYOUT_AUTO, RHEED_LAYOUT_WHOLE, RHEED_LAYOUT_SPLIT = 0, 1, 2
-RHEED_MAX_BEAMS = 64
+RHEED_MAX_BEAMS = 128
 RHEED_MAX_BOX = 300
+RHEED_MAX_BOX_LARGE = 1024
 
 
 class Structure(C.Structure):

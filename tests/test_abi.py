@@ -26,6 +26,21 @@ def test_library_exports_every_declared_symbol():
     assert names == set(lib.SYMBOLS), "binding and header disagree"
 
 
+def test_binding_constants_match_header():
+    """Every RHEED_* constant the binding defines has the header's value."""
+    lib = _lib()
+    header = open(os.path.join(ROOT, "include", "rheed.h")).read()
+    values = {m.group(1): int(m.group(2))
+              for m in re.finditer(r"\b(RHEED_[A-Z0-9_]+)\s*=\s*(-?\d+)", header)}
+    values.update({m.group(1): int(m.group(2))
+                   for m in re.finditer(r"#define\s+(RHEED_[A-Z0-9_]+)\s+(-?\d+)", header)})
+    ours = {k: v for k, v in vars(lib).items() if k.startswith("RHEED_") and isinstance(v, int)}
+    assert len(ours) >= 15
+    for k, v in sorted(ours.items()):
+        assert k in values, f"{k} is not in the header"
+        assert values[k] == v, f"{k}: binding {v}, header {values[k]}"
+
+
 def test_beam_constants_and_errors():
     lib = _lib()
     so = lib.load()
