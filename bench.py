@@ -343,7 +343,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: every box in this setup has a single MI355X; "
-              "pairs are independent and would shard across GPUs (see DESIGN.md).", file=sys.stderr)
+              "pairs are independent and would shard across GPUs, each GPU running its share of the (structure, angle) pairs.", file=sys.stderr)
         sys.exit(2)
     if args.traffic_probe:
         if args.mode == "uneven":

@@ -70,7 +70,7 @@ typedef enum { RHEED_RK4 = 0, RHEED_RK6 = 1, RHEED_SP4 = 2 } rheed_stepper;
  * open beams; PAPER = the printed formula, FLUX times sin(theta0). */
 typedef enum { RHEED_INTENSITY_FLUX = 0, RHEED_INTENSITY_PAPER = 1 } rheed_convention;
 
-/* Largest beam count N handled by the kernels of this build.  Structures with
+/* Largest beam count N the kernels of this library handle.  Structures with
  * N <= 64 run on the one- or two-workgroup kernels (forward and adjoint);
  * structures with 64 < N <= 128 run on a kernel that keeps the state of a
  * pair in device memory owned by the plan (forward only). */

@@ -13,7 +13,7 @@ What is computed for one (structure, angle) pair:
     finally Z <- S Z with S = [[Gamma, -iI], [Gamma, iI]],
     R = Z_lower Z_upper^{-1}, rho(0) = R[:, 0].
 
-Readings where the paper is silent or ambiguous (all listed in the design doc):
+Readings where the paper is silent or ambiguous:
 * Sec. 3.4 names the stage matrices p, q the other way round from Sec. 3.1;
   the stages here are the textbook explicit RK on y = (c, c'), and the RHST
   normalises the c-block (upper half), as Algorithm 1 does.

@@ -8,7 +8,7 @@ M = U + Gamma^2, an s-step BAB method alternates kicks of c' and drifts of c:
                       tau_r = tau_{r-1} + h a_r
     finally           c' <- c' - h b_{s+1} M(tau_s) c
 
-with tau_0 = z_i.  Readings (listed in the design doc): the paper's P-hat / Q-hat
+with tau_0 = z_i.  Readings: the paper's P-hat / Q-hat
 names are read as c / c' (as for the RK stages); kick r evaluates U at
 tau_{r-1}, the position reached before that step's drift, and the final kick
 uses its own weight b_{s+1} at tau_s (the printed formulas use tau_r before

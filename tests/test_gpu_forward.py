@@ -11,7 +11,7 @@ from tests.gpu_util import eacc, gpu_forward, oracle_forward
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-10   # relative intensity (eacc form); see the design doc for the derivation
+TOL = 1e-10   # target accuracy, in the paper's eacc form: max over angles of ||I - I_ref|| / ||I_ref||
 
 
 def _report(name, e):
