@@ -79,14 +79,14 @@ def _cpu_worker(args):
 
 def cpu_baseline(stepper, n_angles, n_coords, cores, mode):
     """The oracle (NumPy FP64, one BLAS thread per process) on `cores` host
-    processes, each timing one (structure, angle) pair of the workload at a
-    different angle.  fwd+adj: the oracle's gradient of a point is one
+    processes, each timing two (structure, angle) pairs of the workload, all
+    at different angles.  fwd+adj: the oracle's gradient of a point is one
     tangent-linear pass (forward + directional derivative) per atom
     coordinate, so a point costs n_coords passes and the rate is
     cores / (n_coords * mean pass time).  fwd: cores / mean forward time."""
     import multiprocessing as mp
     kind = "fwd" if mode == "fwd" else "tl"
-    jobs = [(kind, (c * n_angles) // cores, stepper) for c in range(cores)]
+    jobs = [(kind, (c * n_angles) // (2 * cores), stepper) for c in range(2 * cores)]
     ctx = mp.get_context("spawn")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
@@ -443,13 +443,13 @@ def main():
         n_coords = 3 * len(wl.structures[0].grad_atoms)
         rate, per_pass, cwall = cpu_baseline(stepper, len(wl.theta0), n_coords, cores, args.mode)
         if do_adj:
-            sample = (f"{cores} (structure, angle) pairs of this workload, one per process at different angles, "
+            sample = (f"{2 * cores} (structure, angle) pairs of this workload, two per process at different angles, "
                       f"each one tangent-linear pass of the oracle (forward plus the derivative along one atom "
                       f"coordinate), mean {per_pass:.2f} s per pass; a point's gradient takes {n_coords} passes "
                       f"({n_coords // 3} atoms x 3 coordinates), so value = {cores} / ({n_coords} x "
                       f"{per_pass:.2f} s); {cores} processes x 1 BLAS thread, {cwall:.1f} s wall")
         else:
-            sample = (f"{cores} (structure, angle) pairs of this workload, one per process at different angles, "
+            sample = (f"{2 * cores} (structure, angle) pairs of this workload, two per process at different angles, "
                       f"oracle forward, mean {per_pass:.2f} s per pair; {cores} processes x 1 BLAS thread, "
                       f"{cwall:.1f} s wall")
         cpu = {"value": round(rate, 5), "unit": "points/s", "cores": cores, "kind": "oracle", "sample": sample}
