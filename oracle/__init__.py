@@ -25,6 +25,10 @@ Contents (section numbers are the paper's, arXiv 2306.00271):
                       as a pin).
 * ``tangent``      -- tangent-linear (forward-mode) derivative of the RK
                       method, for checking gradients.
+* ``splitting``    -- BAB splitting steppers (Sec. 3.4).
+* ``bulk``         -- the bulk layer: reflection matrix of the ideal bulk
+                      by iterating one unit layer until it converges, used
+                      as the bottom condition of the surface (Sec. 2.2).
 
 Parity status of every function is listed in the module docstrings; no
 function here is "parity unpinned": each is checked by ``tests/test_oracle_*``

@@ -20,6 +20,11 @@ Readings where the paper is silent or ambiguous:
 * Z0: the paper's S^{-1}[I; O] = (1/2)[Gamma^{-1}; iI] contains Gamma^{-1};
   [I; i Gamma] spans the same column space (it is S^{-1}[I;O] (2 Gamma)) and
   has no division, so it is the default.  Both are available.
+* Bulk layer (Sec. 2.2, treatment of the bulk layer): below z_e the
+  crystal may continue as the bulk, whose reflection matrix R gives the
+  bottom condition rho(z_e) = R tau(z_e) in place of rho(z_e) = 0; the
+  initial state is then S^{-1}[I; R] (2 Gamma), which is [I; i Gamma] at
+  R = 0.
 * xi ("estcondGC"): the Gershgorin/Varah bound
   max_i(|q_ii| + r_i) / min_i(|q_ii| - r_i), r_i = sum_{j != i} |q_ij|,
   and +inf when some row is not strictly diagonally dominant.  It never
@@ -39,11 +44,24 @@ import numpy as np
 THRESHOLD = 1000.0
 
 
-def initial_state(gam: np.ndarray, literal: bool = False) -> np.ndarray:
+def boundary_matrix(gam: np.ndarray) -> np.ndarray:
+    """S of Sec. 3.1: (tau, rho) = S (c, c')."""
     n = gam.size
+    return np.block([[np.diag(gam), -1j * np.eye(n)], [np.diag(gam), 1j * np.eye(n)]])
+
+
+def initial_state(gam: np.ndarray, literal: bool = False, r_bottom=None) -> np.ndarray:
+    """Columns spanning the states at z_e allowed by the bottom condition.
+
+    Default: rho(z_e) = 0.  With ``r_bottom`` = R: rho(z_e) = R tau(z_e),
+    spanned by S^{-1}[I; R], returned times the right factor 2 Gamma."""
+    n = gam.size
+    if r_bottom is not None:
+        S = boundary_matrix(gam)
+        Z = np.linalg.solve(S, np.vstack([np.eye(n), np.asarray(r_bottom, dtype=np.complex128)]))
+        return Z * (2.0 * gam)[None, :]
     if literal:
-        S = np.block([[np.diag(gam), -1j * np.eye(n)], [np.diag(gam), 1j * np.eye(n)]])
-        return np.linalg.solve(S, np.vstack([np.eye(n), np.zeros((n, n))]))
+        return np.linalg.solve(boundary_matrix(gam), np.vstack([np.eye(n), np.zeros((n, n))]))
     return np.vstack([np.eye(n, dtype=np.complex128), 1j * np.diag(gam)])
 
 
@@ -81,25 +99,30 @@ def rk_slice(Z: np.ndarray, Ms, h: float, tab) -> np.ndarray:
     return out
 
 
-def reflection(Z: np.ndarray, gam: np.ndarray) -> np.ndarray:
-    """Final lines of Algorithm 1: rho(0) = first column of R = Z_l / Z_u after S Z."""
+def reflection_matrix(Z: np.ndarray, gam: np.ndarray) -> np.ndarray:
+    """R with rho = R tau at the top of Z: R = Z_l Z_u^{-1} after S Z."""
     n = gam.size
     Q, P = Z[:n], Z[n:]
     top = gam[:, None] * Q - 1j * P
     bot = gam[:, None] * Q + 1j * P
     # R top = bot  ->  top^T R^T = bot^T
-    R = np.linalg.solve(top.T, bot.T).T
-    return R[:, 0]
+    return np.linalg.solve(top.T, bot.T).T
+
+
+def reflection(Z: np.ndarray, gam: np.ndarray) -> np.ndarray:
+    """Final lines of Algorithm 1: rho(0) = first column of R (tau(0) = e_1)."""
+    return reflection_matrix(Z, gam)[:, 0]
 
 
 def solve_ode_str(Mfun, gam, h, n_slices, tab, threshold=THRESHOLD, literal_z0=False,
-                  track_transform=False):
+                  track_transform=False, r_bottom=None):
     """Algorithm 1 for one pair.
 
-    ``Mfun(i, r)`` returns U(z_i + c_r h) + Gamma^2 (n x n).
+    ``Mfun(i, r)`` returns U(z_i + c_r h) + Gamma^2 (n x n); ``r_bottom``
+    the bulk reflection matrix below the slab (None: vacuum).
     Returns (rho0, info) with info = {"n_rhst", "decisions", "Z", "T"}.
     """
-    Z = initial_state(gam, literal_z0)
+    Z = initial_state(gam, literal_z0, r_bottom)
     n = gam.size
     decisions = []
     T_acc = np.eye(n, dtype=np.complex128) if track_transform else None

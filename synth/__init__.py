@@ -12,6 +12,7 @@ from .workloads import (  # noqa: F401
     Workload,
     beams_nearest,
     beams_row,
+    bulk_layer,
     config1,
     config2,
     config3,

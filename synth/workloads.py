@@ -206,6 +206,33 @@ def config5(n_structures: int = 64) -> Workload:
                     _deg(np.linspace(0.3, 6.0, 256)), 0.0)
 
 
+def bulk_layer(surface: Workload, n_slices: int, images: int = 2) -> Workload:
+    """The ideal bulk under a surface workload, one unit layer per structure.
+
+    The unit layer is z in [-d, 0], d = 3.1 A (one layer spacing), with one
+    atomic layer of the surface's supercell at z = -d/2 on the ideal lattice
+    (no in-plane noise) and ``images`` periodic copies above and below, so
+    that its table is the potential of the infinite stack up to Gaussian
+    tails beyond ``images`` spacings.  The mean inner potential is counted
+    over the 2 images + 1 layers placed in one spacing, so the potential
+    scale equals that of a stack averaging the surface's value.  Beams,
+    scattering factors, energy and angles are the surface's."""
+    structs = []
+    for s in surface.structures:
+        m = int(round(math.sqrt(s.cell_area) / CELL))
+        atoms = []
+        for layer in range(-images, images + 1):
+            z = -0.5 * LAYER_D + LAYER_D * layer
+            for i in range(m):
+                for j in range(m):
+                    atoms.append((CELL * i, CELL * j, z))
+        structs.append(Structure(beams=s.beams, recip=s.recip, cell_area=s.cell_area,
+                                 atoms=np.array(atoms, dtype=np.float64), scat_a=s.scat_a, scat_b=s.scat_b,
+                                 thickness=LAYER_D, n_slices=n_slices))
+    return dataclasses.replace(surface, name=surface.name + "-bulk", structures=structs, target=None,
+                               mean_inner_potential=surface.mean_inner_potential * (2 * images + 1))
+
+
 def small_row(hmax=3, n_slices=50, n_angles=5, thickness=10.0, seed=7, n_layers=3,
               charge=-1, absorption=0.1) -> Workload:
     """A small positron row case for fast oracle checks."""
