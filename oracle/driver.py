@@ -47,11 +47,11 @@ class StructureSetup:
             return self.U_node(tab.node_index(i, r), table) + np.diag(g2)
         return M
 
-    def solve(self, theta0, threshold=rk.THRESHOLD, literal_z0=False, track_transform=False, r_bottom=None):
+    def solve(self, theta0, threshold=rk.THRESHOLD, literal_z0=False, track_transform=False, y_bottom=None):
         gam, mask = self.angle(theta0)
         rho, info = rk.solve_ode_str(self.mfun(gam), gam, self.h, self.s.n_slices, self.tab,
                                      threshold=threshold, literal_z0=literal_z0,
-                                     track_transform=track_transform, r_bottom=r_bottom)
+                                     track_transform=track_transform, y_bottom=y_bottom)
         return rho, gam, mask, info
 
     def midpoint_node(self, i):
@@ -77,9 +77,9 @@ class StructureSetup:
 
 
 def rocking_curve(wl, s_idx=0, angle_idx=None, stepper=None, convention="flux", threshold=rk.THRESHOLD,
-                  r_bottom=None):
+                  y_bottom=None):
     """eta [A, N] (float64), rho [A, N] (complex128), n_rhst [A].
-    ``r_bottom``: bulk reflection matrices [A, N, N] below the slab, one per
+    ``y_bottom``: bulk states [I; Y] below the slab as Y [A, N, N], one per
     angle of ``angle_idx`` (None: vacuum below)."""
     tab = TABLEAUX[stepper or wl.stepper]
     st = StructureSetup(wl, wl.structures[s_idx], tab)
@@ -88,27 +88,27 @@ def rocking_curve(wl, s_idx=0, angle_idx=None, stepper=None, convention="flux", 
     for k, a in enumerate(idx):
         th = float(wl.theta0[a])
         rho, gam, mask, info = st.solve(th, threshold=threshold,
-                                        r_bottom=None if r_bottom is None else r_bottom[k])
+                                        y_bottom=None if y_bottom is None else y_bottom[k])
         etas.append(rk.intensity(rho, gam, mask, th, convention))
         rhos.append(rho)
         nr.append(info["n_rhst"])
     return np.array(etas), np.array(rhos), np.array(nr)
 
 
-def bulk_matrices(wl_bulk, s_idx=0, angle_idx=None, stepper=None, tol=1e-12, max_layers=200, R0=None):
-    """R_bulk [A, N, N] and layers [A] for the unit layer of structure
-    ``s_idx`` of a bulk workload, per angle (oracle.bulk)."""
+def bulk_matrices(wl_bulk, s_idx=0, angle_idx=None, stepper=None, tol=1e-12, max_layers=200):
+    """Y_bulk [A, N, N], R_bulk [A, N, N] and layers [A] for the unit layer
+    of structure ``s_idx`` of a bulk workload, per angle (oracle.bulk)."""
     tab = TABLEAUX[stepper or wl_bulk.stepper]
     st = StructureSetup(wl_bulk, wl_bulk.structures[s_idx], tab)
     idx = range(len(wl_bulk.theta0)) if angle_idx is None else angle_idx
-    Rs, layers = [], []
-    for k, a in enumerate(idx):
+    Ys, Rs, layers = [], [], []
+    for a in idx:
         gam, _ = st.angle(float(wl_bulk.theta0[a]))
-        R, n = bulk.bulk_reflection(st.mfun(gam), gam, st.h, st.s.n_slices, tab, tol, max_layers,
-                                    None if R0 is None else R0[k])
+        Y, R, n = bulk.bulk_reflection(st.mfun(gam), gam, st.h, st.s.n_slices, tab, tol, max_layers)
+        Ys.append(Y)
         Rs.append(R)
         layers.append(n)
-    return np.array(Rs), np.array(layers)
+    return np.array(Ys), np.array(Rs), np.array(layers)
 
 
 def rfactor(eta00, target00):
@@ -142,10 +142,10 @@ def rfactor_directional(wl, s_idx, direction, target00, angle_idx=None, stepper=
 
 
 def rfactor_directional_table(wl, s_idx, dtable, target00, angle_idx=None, stepper=None, convention="flux",
-                              r_bottom=None):
+                              y_bottom=None):
     """Directional derivative of the R-factor along a perturbation ``dtable``
     of the potential table itself ([n_nodes, box] complex), tangent-linear;
-    ``r_bottom`` as for ``rocking_curve`` (held fixed)."""
+    ``y_bottom`` as for ``rocking_curve`` (held fixed)."""
     tab = TABLEAUX[stepper or wl.stepper]
     st = StructureSetup(wl, wl.structures[s_idx], tab)
     idx = range(len(wl.theta0)) if angle_idx is None else angle_idx
@@ -157,7 +157,7 @@ def rfactor_directional_table(wl, s_idx, dtable, target00, angle_idx=None, stepp
         def dU(i, r):
             return dtable[tab.node_index(i, r)][st.cidx]
         rho, drho = tangent.solve_ode_str_tangent(st.mfun(gam), dU, gam, st.h, st.s.n_slices, tab,
-                                                  r_bottom=None if r_bottom is None else r_bottom[k])
+                                                  y_bottom=None if y_bottom is None else y_bottom[k])
         eta = rk.intensity(rho, gam, mask, th, convention)
         deta = tangent.intensity_tangent(rho, drho, gam, mask, th, convention)
         diff = eta[0] - target00[k]

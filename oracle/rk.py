@@ -21,10 +21,10 @@ Readings where the paper is silent or ambiguous:
   [I; i Gamma] spans the same column space (it is S^{-1}[I;O] (2 Gamma)) and
   has no division, so it is the default.  Both are available.
 * Bulk layer (Sec. 2.2, treatment of the bulk layer): below z_e the
-  crystal may continue as the bulk, whose reflection matrix R gives the
-  bottom condition rho(z_e) = R tau(z_e) in place of rho(z_e) = 0; the
-  initial state is then S^{-1}[I; R] (2 Gamma), which is [I; i Gamma] at
-  R = 0.
+  crystal may continue as the bulk.  Its bottom condition is given as the
+  normalised state [I; Y] the bulk leaves at z_e (c' = Y c there, the form
+  a right-hand-side transformation leaves); the vacuum is Y = i Gamma, and
+  the reflection matrix at z_e is R = (Gamma + iY)(Gamma - iY)^{-1}.
 * xi ("estcondGC"): the Gershgorin/Varah bound
   max_i(|q_ii| + r_i) / min_i(|q_ii| - r_i), r_i = sum_{j != i} |q_ij|,
   and +inf when some row is not strictly diagonally dominant.  It never
@@ -50,16 +50,14 @@ def boundary_matrix(gam: np.ndarray) -> np.ndarray:
     return np.block([[np.diag(gam), -1j * np.eye(n)], [np.diag(gam), 1j * np.eye(n)]])
 
 
-def initial_state(gam: np.ndarray, literal: bool = False, r_bottom=None) -> np.ndarray:
+def initial_state(gam: np.ndarray, literal: bool = False, y_bottom=None) -> np.ndarray:
     """Columns spanning the states at z_e allowed by the bottom condition.
 
-    Default: rho(z_e) = 0.  With ``r_bottom`` = R: rho(z_e) = R tau(z_e),
-    spanned by S^{-1}[I; R], returned times the right factor 2 Gamma."""
+    Default: rho(z_e) = 0.  With ``y_bottom`` = Y: c' = Y c at z_e, the
+    state [I; Y] of a bulk below."""
     n = gam.size
-    if r_bottom is not None:
-        S = boundary_matrix(gam)
-        Z = np.linalg.solve(S, np.vstack([np.eye(n), np.asarray(r_bottom, dtype=np.complex128)]))
-        return Z * (2.0 * gam)[None, :]
+    if y_bottom is not None:
+        return np.vstack([np.eye(n, dtype=np.complex128), np.asarray(y_bottom, dtype=np.complex128)])
     if literal:
         return np.linalg.solve(boundary_matrix(gam), np.vstack([np.eye(n), np.zeros((n, n))]))
     return np.vstack([np.eye(n, dtype=np.complex128), 1j * np.diag(gam)])
@@ -109,20 +107,26 @@ def reflection_matrix(Z: np.ndarray, gam: np.ndarray) -> np.ndarray:
     return np.linalg.solve(top.T, bot.T).T
 
 
+def normalised_lower(Z: np.ndarray) -> np.ndarray:
+    """Y = P Q^{-1}: the lower block after Z <- Z Q^{-1} (Sec. 3.2)."""
+    n = Z.shape[1]
+    return Z[n:] @ np.linalg.inv(Z[:n])
+
+
 def reflection(Z: np.ndarray, gam: np.ndarray) -> np.ndarray:
     """Final lines of Algorithm 1: rho(0) = first column of R (tau(0) = e_1)."""
     return reflection_matrix(Z, gam)[:, 0]
 
 
 def solve_ode_str(Mfun, gam, h, n_slices, tab, threshold=THRESHOLD, literal_z0=False,
-                  track_transform=False, r_bottom=None):
+                  track_transform=False, y_bottom=None):
     """Algorithm 1 for one pair.
 
-    ``Mfun(i, r)`` returns U(z_i + c_r h) + Gamma^2 (n x n); ``r_bottom``
-    the bulk reflection matrix below the slab (None: vacuum).
+    ``Mfun(i, r)`` returns U(z_i + c_r h) + Gamma^2 (n x n); ``y_bottom``
+    the state [I; Y] of a bulk below the slab (None: vacuum).
     Returns (rho0, info) with info = {"n_rhst", "decisions", "Z", "T"}.
     """
-    Z = initial_state(gam, literal_z0, r_bottom)
+    Z = initial_state(gam, literal_z0, y_bottom)
     n = gam.size
     decisions = []
     T_acc = np.eye(n, dtype=np.complex128) if track_transform else None

@@ -27,12 +27,12 @@ import numpy as np
 from .rk import THRESHOLD, estcond_gershgorin, initial_state
 
 
-def solve_ode_str_tangent(Mfun, dUfun, gam, h, n_slices, tab, threshold=THRESHOLD, r_bottom=None):
+def solve_ode_str_tangent(Mfun, dUfun, gam, h, n_slices, tab, threshold=THRESHOLD, y_bottom=None):
     """Returns (rho, drho).  ``dUfun(i, r)`` is the n x n tangent of U at the
-    node of stage r of slice i (Gamma does not depend on U).  ``r_bottom``:
-    a bulk reflection matrix below the slab, held fixed (its tangent is 0)."""
+    node of stage r of slice i (Gamma does not depend on U).  ``y_bottom``:
+    the state [I; Y] of a bulk below the slab, held fixed (its tangent is 0)."""
     n = gam.size
-    Z = initial_state(gam, r_bottom=r_bottom)
+    Z = initial_state(gam, y_bottom=y_bottom)
     dZ = np.zeros_like(Z)
     for i in range(n_slices):
         K, dK = [], []

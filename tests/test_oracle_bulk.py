@@ -1,6 +1,9 @@
-"""Pins for the oracle's bulk layer (oracle/bulk.py): composition of a slab
-from its parts, the single-beam closed form after k unit layers and its
-Fresnel limit, decoupled beams, and the fixed point (CPU only)."""
+"""Pins for the oracle's bulk layer (oracle/bulk.py): the bottom state and
+its reflection matrix, composition of a slab from its parts, the
+single-beam closed form after k unit layers and its Fresnel limit,
+decoupled beams, the fixed point and its stability (CPU only)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -13,22 +16,29 @@ def _const(M):
     return lambda i, r: M
 
 
-def test_initial_state_of_a_zero_bulk_is_the_vacuum_state():
+def test_bottom_state_and_its_reflection_matrix():
     gam = np.array([0.7, 2.0, -3.0j])
+    # the vacuum is Y = i Gamma, whose reflection matrix is 0
     z0 = rk.initial_state(gam)
-    assert np.abs(rk.initial_state(gam, r_bottom=np.zeros((3, 3))) - z0).max() < 1e-15
-    # the bottom condition holds: S Z0 = [tau; rho] with rho = R tau
+    assert np.abs(rk.initial_state(gam, y_bottom=1j * np.diag(gam)) - z0).max() == 0.0
+    assert np.abs(bulk.reflection_of_state(1j * np.diag(gam), gam)).max() < 1e-15
+    # S [I; Y] = [tau; rho] with rho = R tau, R = (Gamma + iY)(Gamma - iY)^{-1}
     rng = np.random.default_rng(3)
-    R = 0.3 * (rng.normal(size=(3, 3)) + 1j * rng.normal(size=(3, 3)))
-    tr = rk.boundary_matrix(gam) @ rk.initial_state(gam, r_bottom=R)
-    assert np.abs(tr[3:] - R @ tr[:3]).max() < 1e-14
-    assert np.abs(tr[:3] - np.diag(2 * gam)).max() < 1e-14
+    Y = rng.normal(size=(3, 3)) + 1j * rng.normal(size=(3, 3))
+    tr = rk.boundary_matrix(gam) @ rk.initial_state(gam, y_bottom=Y)
+    R = bulk.reflection_of_state(Y, gam)
+    assert np.abs(tr[3:] - R @ tr[:3]).max() < 1e-13 * np.abs(tr).max()
+    # and the reflection of the final state of a solve is the same formula
+    Z = np.vstack([rng.normal(size=(3, 3)) + 1j * rng.normal(size=(3, 3)), Y])
+    Y2 = rk.normalised_lower(Z)
+    assert np.abs(rk.reflection_matrix(Z, gam) - bulk.reflection_of_state(Y2, gam)).max() < 1e-13
 
 
 @pytest.mark.parametrize("tab", [RK4, RK6])
-def test_slab_equals_its_upper_part_on_the_lower_parts_reflection(tab):
-    """Sec. 2.2: rho(0) of a slab from rho(z_e) = 0 equals that of its upper
-    part started from the top reflection matrix of its lower part."""
+def test_slab_equals_its_upper_part_on_the_lower_parts_state(tab):
+    """Sec. 2.2 and 3.2: rho(0) of a slab from the vacuum equals that of its
+    upper part started from the normalised state at the top of its lower
+    part."""
     wl = small_2d(n_beams=13, n_slices=40, thickness=6.0, n_layers=2, n_angles=2)
     st = driver.StructureSetup(wl, wl.structures[0], tab)
     L1 = 23
@@ -36,14 +46,13 @@ def test_slab_equals_its_upper_part_on_the_lower_parts_reflection(tab):
         gam, _ = st.angle(float(th))
         M = st.mfun(gam)
         whole, _ = rk.solve_ode_str(M, gam, st.h, 40, tab)
-        _, info = rk.solve_ode_str(M, gam, st.h, L1, tab)
-        Rmid = rk.reflection_matrix(info["Z"], gam)
-        upper, _ = rk.solve_ode_str(lambda i, r: M(i + L1, r), gam, st.h, 40 - L1, tab, r_bottom=Rmid)
+        Ymid = bulk.layer_map(M, gam, st.h, L1, tab, 1j * np.diag(gam))
+        upper, _ = rk.solve_ode_str(lambda i, r: M(i + L1, r), gam, st.h, 40 - L1, tab, y_bottom=Ymid)
         scale = np.abs(whole).max()
         assert np.abs(upper - whole).max() <= 1e-11 * scale
-        # a transposed or unscaled bottom matrix breaks it
-        for wrong in (Rmid.T, Rmid * (gam[None, :] / gam[:, None])):
-            bad, _ = rk.solve_ode_str(lambda i, r: M(i + L1, r), gam, st.h, 40 - L1, tab, r_bottom=wrong)
+        # a transposed state or the vacuum below breaks it
+        for wrong in (Ymid.T, 1j * np.diag(gam)):
+            bad, _ = rk.solve_ode_str(lambda i, r: M(i + L1, r), gam, st.h, 40 - L1, tab, y_bottom=wrong)
             assert np.abs(bad - whole).max() > 1e-6 * scale
 
 
@@ -55,11 +64,12 @@ def test_layers_of_a_constant_potential_follow_the_closed_form(U0):
     gam = np.array([1.1 + 0j])
     M = np.array([[U0 + gam[0] ** 2]])
     d, L = 3.1, 124
-    R = np.zeros((1, 1), complex)
+    Y = 1j * np.diag(gam)
     for k in range(1, 7):
-        R, _ = bulk.layer_map(_const(M), gam, d / L, L, RK6, R)
+        Y = bulk.layer_map(_const(M), gam, d / L, L, RK6, Y)
+        R = bulk.reflection_of_state(Y, gam)
         assert R[0, 0] == pytest.approx(closed_form.slab_rt(gam[0], U0, k * d)[0], abs=1e-10)
-    Rb, n = bulk.bulk_reflection(_const(M), gam, d / L, L, RK6, tol=1e-12, max_layers=400)
+    _, Rb, n = bulk.bulk_reflection(_const(M), gam, d / L, L, RK6, tol=1e-12, max_layers=400)
     assert n > 0
     assert Rb[0, 0] == pytest.approx(closed_form.fresnel_r(gam[0], U0), abs=1e-9)
 
@@ -69,32 +79,41 @@ def test_decoupled_beams_have_a_diagonal_bulk_matrix():
     U0 = 3.0 - 0.4j
     M = np.diag(U0 + gam ** 2)
     d, L = 3.1, 124
-    Rb, n = bulk.bulk_reflection(_const(M), gam, d / L, L, RK6, tol=1e-12, max_layers=400)
+    Yb, Rb, n = bulk.bulk_reflection(_const(M), gam, d / L, L, RK6, tol=1e-12, max_layers=400)
     assert n > 0
     assert np.abs(Rb - np.diag(np.diag(Rb))).max() < 1e-14
+    assert np.abs(Yb - np.diag(np.diag(Yb))).max() < 1e-13
     for j in range(3):
         assert Rb[j, j] == pytest.approx(closed_form.fresnel_r(gam[j], U0), abs=1e-9)
+        # the half space's state: c' = -iK c for the wave decaying downward (Im K < 0)
+        K = np.sqrt(gam[j] ** 2 + U0 + 0j)
+        K = -K if K.imag > 0 else K
+        assert Yb[j, j] == pytest.approx(1j * K, abs=1e-8)
 
 
-def test_bulk_matrix_is_a_fixed_point_and_stops_at_the_tolerance():
-    wl = small_2d(n_beams=9, n_slices=30, thickness=4.0, n_layers=1, n_angles=1)
-    b = bulk_layer(wl, 31)
-    st = driver.StructureSetup(b, b.structures[0], RK4)
+def test_bulk_iteration_stops_at_the_tolerance_and_stays_converged():
+    wl = small_2d(n_beams=21, n_slices=40, thickness=6.0, n_layers=2, n_angles=4)
+    b = bulk_layer(dataclasses.replace(wl, theta0=wl.theta0[:1]), 31)
+    st = driver.StructureSetup(b, b.structures[0], RK6)
     gam, _ = st.angle(float(b.theta0[0]))
     M = st.mfun(gam)
     tol = 1e-6
-    Rb, n = bulk.bulk_reflection(M, gam, st.h, 31, RK4, tol=tol, max_layers=300)
+    Yb, Rb, n = bulk.bulk_reflection(M, gam, st.h, 31, RK6, tol=tol, max_layers=400)
     assert n > 1
-    # the previous layer's matrix was farther than tol, the last step within it
-    prev, m = bulk.bulk_reflection(M, gam, st.h, 31, RK4, tol=tol, max_layers=n - 1)
+    # one layer fewer is not converged; the last step is within tol
+    Yp, Rp, m = bulk.bulk_reflection(M, gam, st.h, 31, RK6, tol=tol, max_layers=n - 1)
     assert m == -1
-    Fb, _ = bulk.layer_map(M, gam, st.h, 31, RK4, prev)
-    assert np.abs(Fb - Rb).max() == 0.0
-    assert np.abs(Rb - prev).max() <= tol < np.abs(prev - bulk.bulk_reflection(M, gam, st.h, 31, RK4, tol=tol,
-                                                                                  max_layers=n - 2)[0]).max()
-    # the limit is a fixed point of the layer map (contraction: the next step is smaller)
-    F2, _ = bulk.layer_map(M, gam, st.h, 31, RK4, Rb)
-    assert np.abs(F2 - Rb).max() < tol
+    assert np.abs(bulk.layer_map(M, gam, st.h, 31, RK6, Yp) - Yb).max() == 0.0
+    assert np.abs(Rb - Rp).max() <= tol
+    # 150 more layers keep contracting: the change per layer keeps falling
+    # and R stays a bounded reflection matrix
+    Y, R = Yb, Rb
+    for _ in range(150):
+        Y = bulk.layer_map(M, gam, st.h, 31, RK6, Y)
+        Rn = bulk.reflection_of_state(Y, gam)
+        last, R = np.abs(Rn - R).max(), Rn
+    assert last < 0.1 * tol
+    assert np.abs(R).max() < 1.0 + 1e-9
 
 
 def test_tangent_with_a_fixed_bulk_matches_central_differences():
@@ -103,16 +122,16 @@ def test_tangent_with_a_fixed_bulk_matches_central_differences():
     th = float(wl.theta0[0])
     gam, _ = st.angle(th)
     rng = np.random.default_rng(8)
-    R = 0.4 * (rng.normal(size=(9, 9)) + 1j * rng.normal(size=(9, 9))) / 3
+    Y = 1j * np.diag(gam) + 0.5 * (rng.normal(size=(9, 9)) + 1j * rng.normal(size=(9, 9)))
     dt = rng.normal(size=st.table.shape) + 1j * rng.normal(size=st.table.shape)
 
     def dU(i, r):
         return dt[RK4.node_index(i, r)][st.cidx]
-    rho, drho = tangent.solve_ode_str_tangent(st.mfun(gam), dU, gam, st.h, 30, RK4, r_bottom=R)
-    base, _ = rk.solve_ode_str(st.mfun(gam), gam, st.h, 30, RK4, r_bottom=R)
+    rho, drho = tangent.solve_ode_str_tangent(st.mfun(gam), dU, gam, st.h, 30, RK4, y_bottom=Y)
+    base, _ = rk.solve_ode_str(st.mfun(gam), gam, st.h, 30, RK4, y_bottom=Y)
     assert np.abs(rho - base).max() < 1e-13
     eps = 1e-6
-    rp = rk.solve_ode_str(st.mfun(gam, table=st.table + eps * dt), gam, st.h, 30, RK4, r_bottom=R)[0]
-    rm = rk.solve_ode_str(st.mfun(gam, table=st.table - eps * dt), gam, st.h, 30, RK4, r_bottom=R)[0]
+    rp = rk.solve_ode_str(st.mfun(gam, table=st.table + eps * dt), gam, st.h, 30, RK4, y_bottom=Y)[0]
+    rm = rk.solve_ode_str(st.mfun(gam, table=st.table - eps * dt), gam, st.h, 30, RK4, y_bottom=Y)[0]
     fd = (rp - rm) / (2 * eps)
     assert np.abs(drho - fd).max() <= 1e-6 * np.abs(fd).max()
