@@ -134,6 +134,7 @@ typedef struct {
   int32_t split_max_pairs;   /* pairs a split launch can hold on the current device */
   int32_t large_pairs;       /* pairs of structures with N > 64 */
   int32_t large_slots;       /* workgroups (state slots of 768 KiB each, plan-owned) that run them */
+  size_t bulk_workspace;     /* bytes rheed_bulk_reflection needs beyond fwd_workspace (0: not available) */
 } rheed_plan_info;
 
 /* Vacuum wavenumber gamma (1/A) and the coefficient kappa (1/(A^2 V)) of the
@@ -193,6 +194,51 @@ rheed_status rheed_potential_backward(rheed_plan_t plan, const double* atoms, co
 rheed_status rheed_forward(rheed_plan_t plan, const void* U_tables, const double* angles,
                            double* intensity, void* rho, int32_t* pair_status, int32_t* n_rhst,
                            void* workspace, size_t ws_bytes, void* stream);
+
+/* rheed_forward over a slab that rests on the bulk (Sec. 2.2, treatment of
+ * the bulk layer): the propagation starts from the state [I; Y] that the
+ * bulk below leaves at z_e (c' = Y c there, the normalised form of
+ * Sec. 3.2) instead of the vacuum's [I; i Gamma]; the bottom condition is
+ * then rho(z_e) = R tau(z_e) with R = (Gamma + iY)(Gamma - iY)^{-1}.
+ *  y_bottom  device complex [n_pairs][max_beams][max_beams], row major: Y of
+ *            pair p at p max_beams^2, entry (j, k) at j max_beams + k for
+ *            j, k < N of the pair (other entries are not read); typically
+ *            rheed_bulk_reflection's y_bulk for the same beams and angles.
+ * Every other argument, the workspace included, is as for rheed_forward,
+ * and rheed_backward may follow: the gradient then holds the bulk fixed (it
+ * is not fitted).  Needs an RK stepper and every structure to have N <= 64
+ * (RHEED_E_UNSUPPORTED otherwise). */
+rheed_status rheed_forward_bulk(rheed_plan_t plan, const void* U_tables, const double* angles, const void* y_bottom,
+                                double* intensity, void* rho, int32_t* pair_status, int32_t* n_rhst,
+                                void* workspace, size_t ws_bytes, void* stream);
+
+/* The ideal bulk below a surface (Sec. 2.2, treatment of the bulk layer),
+ * computed once before a structure search.  The plan's structures are unit
+ * layers of the bulk (one period each, with its potential table).  Every
+ * pair propagates the stack upward from the vacuum (Y = i Gamma, R = 0), one
+ * unit layer at a time: a forward pass from [I; Y] over the layer, then the
+ * state at its top normalised to [I; Y'] (Y' = P Q^{-1}, the transformation
+ * of Sec. 3.2) and the stack's reflection matrix
+ * R' = (Gamma + iY')(Gamma - iY')^{-1}.  A pair stops at the first layer
+ * whose change max_jk |R' - R| is <= tol; the others go on, up to
+ * max_layers layers.
+ *  y_bulk, r_bulk  device complex [n_pairs][max_beams][max_beams] as
+ *             y_bottom of rheed_forward_bulk (out; entries beyond N are 0):
+ *             the state and reflection matrix at the top of the stack
+ *  layers     device int32 [n_pairs]: layers applied when the change first
+ *             passed, -1 if it did not within max_layers or the pair failed
+ *  pair_status device int32 [n_pairs]: RHEED_PAIR_* (a failed pair keeps the
+ *             last layer's Y and R and stops)
+ *  workspace  device, >= fwd_workspace + bulk_workspace bytes (overwritten)
+ * The stepper's damping of fast beams over many layers can turn the stack
+ * to the wrong modes: use a step at which it is small (RK6 at h = 0.1 A, or
+ * RK4 at 0.05 A, on the synthetic bulks of this library's tests).
+ * Synchronises the stream after each layer to read the convergence flags
+ * (so it cannot be captured into a graph); allocates nothing.  Needs an RK
+ * stepper and every structure to have N <= 64. */
+rheed_status rheed_bulk_reflection(rheed_plan_t plan, const void* U_tables, const double* angles, double tol,
+                                   int32_t max_layers, void* y_bulk, void* r_bulk, int32_t* layers,
+                                   int32_t* pair_status, void* workspace, size_t ws_bytes, void* stream);
 
 /* Launch configurations rheed_autotune compares (at most RHEED_TUNE_MAX). */
 #define RHEED_TUNE_MAX 4

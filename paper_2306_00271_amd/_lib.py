@@ -64,6 +64,7 @@ class PlanInfo(C.Structure):
         ("split_max_pairs", C.c_int32),
         ("large_pairs", C.c_int32),
         ("large_slots", C.c_int32),
+        ("bulk_workspace", C.c_size_t),
     ]
 
 
@@ -94,6 +95,10 @@ SYMBOLS = {
                        C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "rheed_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                         C.c_void_p], C.c_int),
+    "rheed_forward_bulk": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                            C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "rheed_bulk_reflection": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
+                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "rheed_autotune": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                         C.POINTER(TuneReport)], C.c_int),
     "rheed_rfactor": ([C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),

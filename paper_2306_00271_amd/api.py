@@ -125,7 +125,10 @@ class Plan:
         return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
 
     def forward(self, U: torch.Tensor, angles: torch.Tensor, *, want_rho: bool = False,
-                workspace: Optional[torch.Tensor] = None, want_nrhst: bool = False):
+                workspace: Optional[torch.Tensor] = None, want_nrhst: bool = False,
+                y_bottom: Optional[torch.Tensor] = None):
+        """rheed_forward, or rheed_forward_bulk when ``y_bottom`` (complex
+        [n_pairs, max_beams, max_beams]: the state [I; Y] of a bulk below) is given."""
         _dev(U, torch.complex128, "U")
         _dev(angles, torch.float64, "angles")
         if angles.shape != (self.n_pairs, 2):
@@ -136,9 +139,39 @@ class Plan:
         status = torch.empty(self.n_pairs, dtype=torch.int32, device=dev)
         nrhst = torch.empty(self.n_pairs, dtype=torch.int32, device=dev) if want_nrhst else None
         ws_bytes = 0 if workspace is None else workspace.numel()
-        _lib.check(_lib.lib().rheed_forward(self._h, _ptr(U), _ptr(angles), _ptr(inten), _ptr(rho), _ptr(status),
-                                            _ptr(nrhst), _ptr(workspace), ws_bytes, _stream()), "forward")
+        if y_bottom is None:
+            _lib.check(_lib.lib().rheed_forward(self._h, _ptr(U), _ptr(angles), _ptr(inten), _ptr(rho),
+                                                _ptr(status), _ptr(nrhst), _ptr(workspace), ws_bytes, _stream()),
+                       "forward")
+        else:
+            _dev(y_bottom, torch.complex128, "y_bottom")
+            if y_bottom.shape != (self.n_pairs, self.max_beams, self.max_beams):
+                raise ValueError(f"y_bottom must be [{self.n_pairs}, {self.max_beams}, {self.max_beams}]")
+            _lib.check(_lib.lib().rheed_forward_bulk(self._h, _ptr(U), _ptr(angles), _ptr(y_bottom), _ptr(inten),
+                                                     _ptr(rho), _ptr(status), _ptr(nrhst), _ptr(workspace),
+                                                     ws_bytes, _stream()), "forward_bulk")
         return {"intensity": inten, "rho": rho, "status": status, "n_rhst": nrhst}
+
+    def bulk_reflection(self, U: torch.Tensor, angles: torch.Tensor, *, tol: float = 1e-8,
+                        max_layers: int = 1000):
+        """The bulk whose unit layers this plan's structures are, stacked from
+        the vacuum until R converges (rheed_bulk_reflection): {"y": state
+        [n_pairs, M, M] for ``forward(y_bottom=...)``, "r": reflection
+        matrices, "layers": [n_pairs] int32, "status": [n_pairs] int32}."""
+        _dev(U, torch.complex128, "U")
+        _dev(angles, torch.float64, "angles")
+        dev = U.device
+        M = self.max_beams
+        y = torch.empty((self.n_pairs, M, M), dtype=torch.complex128, device=dev)
+        r = torch.empty_like(y)
+        layers = torch.empty(self.n_pairs, dtype=torch.int32, device=dev)
+        status = torch.empty(self.n_pairs, dtype=torch.int32, device=dev)
+        nbytes = int(self.info.fwd_workspace + self.info.bulk_workspace)
+        ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+        _lib.check(_lib.lib().rheed_bulk_reflection(self._h, _ptr(U), _ptr(angles), float(tol), int(max_layers),
+                                                    _ptr(y), _ptr(r), _ptr(layers), _ptr(status), _ptr(ws),
+                                                    ws.numel(), _stream()), "bulk_reflection")
+        return {"y": y, "r": r, "layers": layers, "status": status}
 
     def autotune(self, U: torch.Tensor, angles: torch.Tensor, reps: int = 3) -> dict:
         """Times the launch configurations of forward on these inputs and keeps

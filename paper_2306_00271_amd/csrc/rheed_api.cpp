@@ -71,6 +71,19 @@ struct rheed_plan_s {
   std::vector<int> large_plain;
 };
 
+namespace {
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// extra workspace of rheed_bulk_reflection beyond fwd_ws: intensities and
+// status of each layer's forward pass, the done flags
+size_t bulk_extra(const rheed_plan_s* P) {
+  const size_t np = (size_t)P->n_pairs, m = (size_t)P->max_beams;
+  return align256(np * m * 8) + 2 * align256(np * 4);
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* rheed_status_string(rheed_status s) {
@@ -392,6 +405,7 @@ rheed_status rheed_plan_get_info(rheed_plan_t P, rheed_plan_info* info) {
   info->split_max_pairs = P->split_max;
   info->large_pairs = (int32_t)P->large_pairs.size();
   info->large_slots = P->large_slots;
+  info->bulk_workspace = P->large_pairs.empty() ? bulk_extra(P) : 0;
   return RHEED_OK;
 }
 
@@ -438,8 +452,15 @@ rheed_status rheed_potential_backward(rheed_plan_t P, const double* atoms, const
   return e == hipSuccess ? RHEED_OK : hip_fail(e, "potential_backward launch");
 }
 
-rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* angles, double* intensity, void* rho,
-                           int32_t* pair_status, int32_t* n_rhst, void* workspace, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// rheed_forward with an optional bottom state [I; Y] per pair and an
+// optional skip flag per pair (the bulk iteration's converged pairs).
+rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* angles, double* intensity, void* rho,
+                          int32_t* pair_status, int32_t* n_rhst, void* workspace, size_t ws_bytes, void* stream,
+                          const void* y_bottom, const int* skip) {
   if (!P || !U_tables || !angles || !intensity || !pair_status) return fail(RHEED_E_INVALID, "forward: null argument");
   if (workspace && !P->large_pairs.empty())
     return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs an RK stepper and every structure to have N <= 64");
@@ -447,6 +468,8 @@ rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* a
     return fail(RHEED_E_INVALID, "forward: workspace of " + std::to_string(ws_bytes) + " bytes < " +
                                      std::to_string(P->fwd_ws));
   FwdArgs a{};
+  a.y_bottom = static_cast<const double2*>(y_bottom);
+  a.skip = skip;
   a.structs = P->d_structs;
   a.pair_struct = P->d_pair_struct;
   a.beams = P->d_beams;
@@ -487,6 +510,84 @@ rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* a
     for (int q = 0; q < 4; ++q) la.sp_b[q] = P->sp_b[q];
     e = launch_forward_large((int)P->opts.stepper, la, st);
     if (e != hipSuccess) return hip_fail(e, "forward launch (N > 64)");
+  }
+  return RHEED_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rheed_status rheed_forward(rheed_plan_t P, const void* U_tables, const double* angles, double* intensity, void* rho,
+                           int32_t* pair_status, int32_t* n_rhst, void* workspace, size_t ws_bytes, void* stream) {
+  return forward_impl(P, U_tables, angles, intensity, rho, pair_status, n_rhst, workspace, ws_bytes, stream,
+                      nullptr, nullptr);
+}
+
+rheed_status rheed_forward_bulk(rheed_plan_t P, const void* U_tables, const double* angles, const void* y_bottom,
+                                double* intensity, void* rho, int32_t* pair_status, int32_t* n_rhst, void* workspace,
+                                size_t ws_bytes, void* stream) {
+  if (!P || !y_bottom) return fail(RHEED_E_INVALID, "forward_bulk: null argument");
+  if (!P->large_pairs.empty())
+    return fail(RHEED_E_UNSUPPORTED, "forward_bulk: needs an RK stepper and every structure to have N <= 64");
+  return forward_impl(P, U_tables, angles, intensity, rho, pair_status, n_rhst, workspace, ws_bytes, stream,
+                      y_bottom, nullptr);
+}
+
+rheed_status rheed_bulk_reflection(rheed_plan_t P, const void* U_tables, const double* angles, double tol,
+                                   int32_t max_layers, void* y_bulk, void* r_bulk, int32_t* layers,
+                                   int32_t* pair_status, void* workspace, size_t ws_bytes, void* stream) {
+  if (!P || !U_tables || !angles || !y_bulk || !r_bulk || !layers || !pair_status || !workspace)
+    return fail(RHEED_E_INVALID, "bulk_reflection: null argument");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(RHEED_E_INVALID, "bulk_reflection: tol must be finite and >= 0");
+  if (max_layers < 1) return fail(RHEED_E_INVALID, "bulk_reflection: max_layers must be >= 1");
+  if (!P->large_pairs.empty())
+    return fail(RHEED_E_UNSUPPORTED, "bulk_reflection: needs an RK stepper and every structure to have N <= 64");
+  const size_t need = P->fwd_ws + bulk_extra(P);
+  if (ws_bytes < need)
+    return fail(RHEED_E_INVALID, "bulk_reflection: workspace of " + std::to_string(ws_bytes) + " bytes < " +
+                                     std::to_string(need));
+  const size_t np = (size_t)P->n_pairs, m = (size_t)P->max_beams;
+  char* base = static_cast<char*>(workspace) + P->fwd_ws;
+  double* inten = reinterpret_cast<double*>(base);
+  base += align256(np * m * 8);
+  int* done = reinterpret_cast<int*>(base);
+  base += align256(np * 4);
+  int* fstat = reinterpret_cast<int*>(base);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  BulkArgs b{};
+  b.structs = P->d_structs;
+  b.pair_struct = P->d_pair_struct;
+  b.beams = P->d_beams;
+  b.angles = angles;
+  b.ws = static_cast<const char*>(workspace);
+  b.ck = P->ck;
+  b.y = static_cast<double2*>(y_bulk);
+  b.r = static_cast<double2*>(r_bulk);
+  b.done = done;
+  b.layers = layers;
+  b.status = pair_status;
+  b.fstatus = fstat;
+  b.ld = P->max_beams;
+  b.n_pairs = P->n_pairs;
+  b.tol = tol;
+  hipError_t e = launch_bulk_init(b, st);
+  if (e != hipSuccess) return hip_fail(e, "bulk_reflection: init launch");
+  std::vector<int> host_done(np);
+  for (int it = 1; it <= max_layers; ++it) {
+    // one unit layer from [I; Y] for every pair still iterating, then Y and R at its top
+    rheed_status s = forward_impl(P, U_tables, angles, inten, nullptr, fstat, nullptr, workspace, P->fwd_ws, stream,
+                                  y_bulk, done);
+    if (s != RHEED_OK) return s;
+    b.iter = it;
+    e = launch_bulk_update(b, st);
+    if (e != hipSuccess) return hip_fail(e, "bulk_reflection: update launch");
+    e = hipMemcpyAsync(host_done.data(), done, np * sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "bulk_reflection: reading the convergence flags");
+    bool all = true;
+    for (size_t q = 0; q < np && all; ++q) all = host_done[q] != 0;
+    if (all) break;
   }
   return RHEED_OK;
 }

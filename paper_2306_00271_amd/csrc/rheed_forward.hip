@@ -204,7 +204,9 @@ __device__ __forceinline__ void load_nodes(Lds& s, const double2* __restrict__ U
   }
 }
 
-template <int STEPPER>
+// BULK: the state starts from a bulk's [I; Y] (a.y_bottom) and pairs with
+// a.skip[p] set are not run; the vacuum instantiations carry neither.
+template <int STEPPER, bool BULK>
 __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
   using T = Tab<STEPPER>;
   Lds& s = fwd_lds;
@@ -213,6 +215,9 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
   const int w = tid >> 6;
   const int RT = w & 3, CH = w >> 2;   // row tile, column block of this wave
   const int p = a.pair_list ? a.pair_list[blockIdx.x] : blockIdx.x;
+  if constexpr (BULK) {
+    if (a.skip && a.skip[p]) return;
+  }
   const StructDev S = a.structs[a.pair_struct[p]];
   const int N = S.n_beams;
   const int L = S.n_slices;
@@ -262,7 +267,8 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
   double2* cb = s.xb;             // c (upper block of Z), LDS resident
   double2* xb = s.xb + NP * NP;   // stage input X_r
   int ob = (16 * RT + (lane >> 4)) * NP + 16 * NJT * CH + (lane & 15);
-  // Z0 = [I; i Gamma]  (spans the same columns as S^{-1}[I; O] of Algorithm 1)
+  // Z0 = [I; i Gamma]  (spans the same columns as S^{-1}[I; O] of Algorithm 1),
+  // or [I; Y] over a bulk whose top state is [I; Y]
   Mat d;
 #pragma unroll
   for (int e = 0; e < NE; ++e) {
@@ -273,6 +279,13 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
     const double g2v = g2[e & 3];
     d.r[e] = (dg && g2v < 0.0) ? sqrt(-g2v) : 0.0;
     d.i[e] = (dg && g2v >= 0.0) ? sqrt(g2v) : 0.0;
+    if constexpr (BULK) {
+      if (row < N && col < N) {
+        const double2 y = a.y_bottom[(long long)p * a.ld * a.ld + row * a.ld + col];
+        d.r[e] = y.x;
+        d.i[e] = y.y;
+      }
+    }
   }
   const bool save = a.ws != nullptr;
   char* pws = save ? a.ws + (long long)p * a.ck.pair_stride : nullptr;
@@ -891,7 +904,7 @@ __device__ __forceinline__ void prefetch_table_nodes(double2 (*tb)[MAXBOX + 1], 
   }
 }
 
-template <int STEPPER>
+template <int STEPPER, bool BULK>
 __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
   using T = Tab<STEPPER>;
   SplitLds& s = split_lds;
@@ -901,6 +914,9 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
   const int RT = w;                    // row tile of this wave
   const int pi = blockIdx.x >> 1, half = blockIdx.x & 1;  // launch slot of the pair, half
   const int p = a.pair_list ? a.pair_list[pi] : pi;
+  if constexpr (BULK) {
+    if (a.skip && a.skip[p]) return;   // both halves of the pair return here
+  }
   const int col0 = HC * half;          // first column of this half
   const StructDev S = a.structs[a.pair_struct[p]];
   const int N = S.n_beams;
@@ -959,6 +975,13 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
     const double g2v = gg.v[e & 3];
     d.r[e] = (dg && g2v < 0.0) ? sqrt(-g2v) : 0.0;
     d.i[e] = (dg && g2v >= 0.0) ? sqrt(g2v) : 0.0;
+    if constexpr (BULK) {
+      if (row < N && col < N) {  // [I; Y] of a bulk below
+        const double2 y = a.y_bottom[(long long)p * a.ld * a.ld + row * a.ld + col];
+        d.r[e] = y.x;
+        d.i[e] = y.y;
+      }
+    }
   }
   const bool save = a.ws != nullptr;
   char* pws = save ? a.ws + (long long)p * a.ck.pair_stride : nullptr;
@@ -1208,29 +1231,48 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
 
 hipError_t launch_forward(int stepper, const FwdArgs& a, hipStream_t stream) {
   dim3 grid(a.n_pairs), block(FT);
-  if (stepper == 0)
-    hipLaunchKernelGGL(forward_kernel<0>, grid, block, 0, stream, a);
-  else
-    hipLaunchKernelGGL(forward_kernel<1>, grid, block, 0, stream, a);
+  const bool bulk = a.y_bottom != nullptr;
+  if (stepper == 0) {
+    if (bulk)
+      hipLaunchKernelGGL((forward_kernel<0, true>), grid, block, 0, stream, a);
+    else
+      hipLaunchKernelGGL((forward_kernel<0, false>), grid, block, 0, stream, a);
+  } else {
+    if (bulk)
+      hipLaunchKernelGGL((forward_kernel<1, true>), grid, block, 0, stream, a);
+    else
+      hipLaunchKernelGGL((forward_kernel<1, false>), grid, block, 0, stream, a);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_forward_split(int stepper, const FwdArgs& a, hipStream_t stream) {
   FwdArgs arg = a;
   void* params[] = {&arg};
-  const void* f = stepper == 0 ? reinterpret_cast<const void*>(&forward_split_kernel<0>)
-                               : reinterpret_cast<const void*>(&forward_split_kernel<1>);
+  const bool bulk = a.y_bottom != nullptr;
+  const void* f = stepper == 0 ? (bulk ? reinterpret_cast<const void*>(&forward_split_kernel<0, true>)
+                                       : reinterpret_cast<const void*>(&forward_split_kernel<0, false>))
+                               : (bulk ? reinterpret_cast<const void*>(&forward_split_kernel<1, true>)
+                                       : reinterpret_cast<const void*>(&forward_split_kernel<1, false>));
   return hipLaunchCooperativeKernel(f, dim3(2 * a.n_pairs), dim3(ST), params, 0, stream);
 }
 
 int forward_split_max_pairs(int device) {
-  int coop = 0, cus = 0, per_cu0 = 0, per_cu1 = 0;
+  int coop = 0, cus = 0;
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu0, forward_split_kernel<0>, ST, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu1, forward_split_kernel<1>, ST, 0) != hipSuccess)
-    return 0;
-  return cus * (per_cu0 < per_cu1 ? per_cu0 : per_cu1) / 2;
+  // the fewest resident workgroups per CU over every instantiation a split launch may use
+  const void* fs[4] = {reinterpret_cast<const void*>(&forward_split_kernel<0, false>),
+                       reinterpret_cast<const void*>(&forward_split_kernel<1, false>),
+                       reinterpret_cast<const void*>(&forward_split_kernel<0, true>),
+                       reinterpret_cast<const void*>(&forward_split_kernel<1, true>)};
+  int per_cu = 1 << 30;
+  for (const void* f : fs) {
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, ST, 0) != hipSuccess) return 0;
+    per_cu = n < per_cu ? n : per_cu;
+  }
+  return cus * per_cu / 2;
 }
 
 }  // namespace rheed

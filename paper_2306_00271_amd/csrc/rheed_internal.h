@@ -55,7 +55,17 @@ struct FwdArgs {
   double threshold;
   // split launches (two workgroups per pair): per-pair exchange blocks
   char* xch;
+  // bottom condition of a bulk below the slab: the state starts as [I; Y],
+  // Y of pair p at y_bottom + p ld ld, row major (null: the vacuum, [I; i Gamma])
+  const double2* y_bottom;
+  const int* skip;           // [P] pairs with skip[p] != 0 are not run (or null)
 };
+
+// Gamma_j from g2 = Gamma_j^2 (Sec. 2.1): sqrt(g2) for open beams, -i sqrt(-g2)
+// for evanescent ones.
+__device__ inline double2 gamma_of(double g2) {
+  return g2 >= 0.0 ? make_double2(sqrt(g2), 0.0) : make_double2(0.0, -sqrt(-g2));
+}
 
 // Exchange block of one pair in a split launch (bytes): two 64-bit counters
 // and the launch number, per half and parity the badness partials [2][NP]
@@ -121,7 +131,32 @@ struct GradArgs {
   int contrib_r[4][2];
 };
 
+// The bulk layer: from the final states a forward pass over one unit layer
+// kept, the normalised state [I; Y] and the reflection matrix at the layer's
+// top, and the convergence test of the stack.
+struct BulkArgs {
+  const StructDev* structs;
+  const int* pair_struct;
+  const int* beams;
+  const double* angles;
+  const char* ws;            // forward workspace holding each pair's final state
+  CkptLayout ck;
+  double2* y;                // [P][ld][ld]: bottom state of this layer in, top state out
+  double2* r;                // [P][ld][ld]: reflection matrix below this layer in, at its top out
+  int* done;                 // [P]: 1 once converged or failed
+  int* layers;               // [P]: unit layers at convergence, -1 until then
+  int* status;               // [P]: RHEED_PAIR_* of the iteration
+  const int* fstatus;        // [P]: the forward pass's status for this layer
+  int ld;
+  int n_pairs;
+  int iter;                  // layers applied including this one
+  int pad;
+  double tol;
+};
+
 hipError_t launch_forward(int stepper, const FwdArgs& a, hipStream_t stream);
+hipError_t launch_bulk_update(const BulkArgs& a, hipStream_t stream);
+hipError_t launch_bulk_init(const BulkArgs& a, hipStream_t stream);  // vacuum start, flags cleared
 hipError_t launch_forward_split(int stepper, const FwdArgs& a, hipStream_t stream);
 int forward_split_max_pairs(int device);  // pairs a split launch can hold at once (0: not available)
 hipError_t launch_backward(int stepper, const BwdArgs& a, hipStream_t stream);

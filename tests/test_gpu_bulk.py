@@ -1,0 +1,255 @@
+"""Parity of the bulk layer's HIP path (rheed_forward_bulk and
+rheed_bulk_reflection, through the C ABI) with the oracle (oracle/bulk.py,
+oracle/rk.py started from a bulk's state [I; Y])."""
+import ctypes as C
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import bulk, driver
+from synth import bulk_layer, config4, small_2d
+from tests.gpu_util import eacc
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10   # relative intensity, the paper's eacc form
+
+
+def _mixed_surface():
+    """Two structures of different N (21 and 13) with 4 angles each, so that
+    the bottom matrices sit at a leading dimension above some pairs' N."""
+    a = small_2d(n_beams=21, n_slices=40, thickness=6.0, n_layers=2, n_angles=4)
+    b = small_2d(n_beams=13, n_slices=30, thickness=5.0, n_layers=2, n_angles=4, seed=12)
+    return dataclasses.replace(a, structures=[a.structures[0], b.structures[0]])
+
+
+def _random_bottom(wl, seed=4, scale=2.0):
+    """Seeded bottom states Y [P, M, M] (zero beyond each pair's N)."""
+    rng = np.random.default_rng(seed)
+    M = max(s.n_beams for s in wl.structures)
+    A = len(wl.theta0)
+    Y = np.zeros((len(wl.structures) * A, M, M), dtype=np.complex128)
+    for si, s in enumerate(wl.structures):
+        n = s.n_beams
+        for a in range(A):
+            Y[si * A + a, :n, :n] = scale * (rng.normal(size=(n, n)) + 1j * rng.normal(size=(n, n))) / np.sqrt(n)
+    return Y
+
+
+def _plan(wl, **kw):
+    import torch
+    from paper_2306_00271_amd import api
+    dev = torch.device("cuda:0")
+    plan = api.plan_for(wl, **kw)
+    U = plan.potential(api.atoms_for(wl, dev))
+    return plan, U, api.angles_for(wl, dev), dev
+
+
+@pytest.mark.parametrize("layout", ["whole", "split"])
+def test_vacuum_state_as_bottom_is_the_vacuum_forward(layout):
+    """Y = i Gamma (the vacuum's state, from the oracle's Gamma) reproduces
+    rheed_forward to rounding."""
+    import torch
+    wl = _mixed_surface()
+    plan, U, ang, dev = _plan(wl, stepper="rk6", layout=layout)
+    A = len(wl.theta0)
+    Y = np.zeros((plan.n_pairs, plan.max_beams, plan.max_beams), dtype=np.complex128)
+    for si, s in enumerate(wl.structures):
+        st = driver.StructureSetup(wl, s, driver.TABLEAUX["rk6"])
+        for a in range(A):
+            gam, _ = st.angle(float(wl.theta0[a]))
+            Y[si * A + a, :s.n_beams, :s.n_beams] = 1j * np.diag(gam)
+    a = plan.forward(U, ang, want_nrhst=True)
+    b = plan.forward(U, ang, want_nrhst=True, y_bottom=torch.from_numpy(Y).to(dev))
+    torch.cuda.synchronize()
+    ea = a["intensity"].cpu().numpy()
+    e = eacc(b["intensity"].cpu().numpy(), ea)
+    print(f"[bulk] {layout}: vacuum state as bottom vs rheed_forward: eacc={e:.3e}", flush=True)
+    assert e <= 1e-13
+    assert (b["status"].cpu().numpy() == 0).all()
+
+
+@pytest.mark.parametrize("stepper", ["rk4", "rk6"])
+@pytest.mark.parametrize("layout", ["whole", "split"])
+def test_forward_on_a_bottom_state_matches_oracle(layout, stepper):
+    import torch
+    wl = _mixed_surface()
+    Y = _random_bottom(wl)
+    plan, U, ang, dev = _plan(wl, stepper=stepper, layout=layout)
+    out = plan.forward(U, ang, want_nrhst=True, y_bottom=torch.from_numpy(Y).to(dev))
+    torch.cuda.synchronize()
+    eta = out["intensity"].cpu().numpy()
+    assert (out["status"].cpu().numpy() == 0).all()
+    A = len(wl.theta0)
+    for si, s in enumerate(wl.structures):
+        n = s.n_beams
+        ref, _, _ = driver.rocking_curve(wl, s_idx=si, stepper=stepper,
+                                         y_bottom=Y[si * A:(si + 1) * A, :n, :n])
+        e = eacc(eta[si * A:(si + 1) * A, :n], ref)
+        print(f"[bulk] {layout} {stepper} N={n}: eacc={e:.3e}", flush=True)
+        assert e <= TOL
+        assert np.abs(eta[si * A:(si + 1) * A, n:]).max(initial=0.0) == 0.0
+
+
+@pytest.mark.parametrize("layout", ["whole", "split"])
+def test_bulk_iteration_matches_oracle(layout):
+    """Unit layers of the ideal bulk under two structures (N = 21 and 13),
+    stacked until R changes by at most 1e-6 per layer: the same number of
+    layers per pair and the same Y and R as the oracle's iteration."""
+    import torch
+    surf = _mixed_surface()
+    surf = dataclasses.replace(surf, theta0=surf.theta0[:3])
+    wb = bulk_layer(surf, 31)
+    plan, U, ang, dev = _plan(wb, stepper="rk6", layout=layout)
+    tol = 1e-6
+    res = plan.bulk_reflection(U, ang, tol=tol, max_layers=400)
+    torch.cuda.synchronize()
+    Yg, Rg = res["y"].cpu().numpy(), res["r"].cpu().numpy()
+    lg = res["layers"].cpu().numpy()
+    assert (res["status"].cpu().numpy() == 0).all()
+    A = len(wb.theta0)
+    for si, s in enumerate(wb.structures):
+        n = s.n_beams
+        Yo, Ro, lo = driver.bulk_matrices(wb, s_idx=si, stepper="rk6", tol=tol, max_layers=400)
+        for a in range(A):
+            p = si * A + a
+            dr = np.abs(Rg[p, :n, :n] - Ro[a]).max()
+            dy = np.abs(Yg[p, :n, :n] - Yo[a]).max() / np.abs(Yo[a]).max()
+            print(f"[bulk] {layout} N={n} angle {a}: layers gpu {lg[p]} oracle {lo[a]}, max|dR| {dr:.3e}, "
+                  f"max|dY|/max|Y| {dy:.3e}", flush=True)
+            assert lo[a] > 1 and lg[p] == lo[a]
+            assert dr <= 1e-10 and dy <= 1e-10
+            for M in (Rg, Yg):
+                assert np.abs(M[p, n:, :]).max(initial=0.0) == 0.0 and np.abs(M[p, :, n:]).max(initial=0.0) == 0.0
+
+
+def test_one_layer_and_the_layer_count():
+    """max_layers = 1: the state and reflection matrix on top of one unit
+    layer over the vacuum (the oracle's layer map); layers = -1 with a
+    tolerance out of reach and 1 with one every change passes."""
+    import torch
+    surf = small_2d(n_beams=21, n_slices=40, thickness=6.0, n_layers=2, n_angles=3)
+    wb = bulk_layer(surf, 31)
+    plan, U, ang, dev = _plan(wb, stepper="rk6")
+    st = driver.StructureSetup(wb, wb.structures[0], driver.TABLEAUX["rk6"])
+    for tol, expect in ((1e-300, -1), (1e300, 1)):
+        res = plan.bulk_reflection(U, ang, tol=tol, max_layers=1)
+        torch.cuda.synchronize()
+        Yg, Rg = res["y"].cpu().numpy(), res["r"].cpu().numpy()
+        assert (res["layers"].cpu().numpy() == expect).all()
+        for a in range(3):
+            gam, _ = st.angle(float(wb.theta0[a]))
+            Yo = bulk.layer_map(st.mfun(gam), gam, st.h, 31, driver.TABLEAUX["rk6"], 1j * np.diag(gam))
+            Ro = bulk.reflection_of_state(Yo, gam)
+            dy = np.abs(Yg[a] - Yo).max() / np.abs(Yo).max()
+            dr = np.abs(Rg[a] - Ro).max()
+            print(f"[bulk] one layer, angle {a}: max|dY|/max|Y| {dy:.3e}, max|dR| {dr:.3e}", flush=True)
+            assert dy <= 1e-11 and dr <= 1e-11
+
+
+def test_surface_on_the_computed_bulk():
+    """End to end: the bulk under a surface computed on the GPU, then the
+    surface's rocking curve on it, against the oracle doing both."""
+    import torch
+    surf = small_2d(n_beams=21, n_slices=40, thickness=6.0, n_layers=2, n_angles=3)
+    wb = bulk_layer(surf, 31)
+    pb, Ub, angb, dev = _plan(wb, stepper="rk6")
+    res = pb.bulk_reflection(Ub, angb, tol=1e-6, max_layers=400)
+    ps, Us, angs, _ = _plan(surf, stepper="rk6")
+    out = ps.forward(Us, angs, y_bottom=res["y"])
+    torch.cuda.synchronize()
+    Yo, _, lo = driver.bulk_matrices(wb, stepper="rk6", tol=1e-6, max_layers=400)
+    ref, _, _ = driver.rocking_curve(surf, stepper="rk6", y_bottom=Yo)
+    e = eacc(out["intensity"].cpu().numpy(), ref)
+    vac, _, _ = driver.rocking_curve(surf, stepper="rk6")
+    print(f"[bulk] surface on the computed bulk: eacc={e:.3e} (the bulk changes the curve by "
+          f"{eacc(ref, vac):.3e})", flush=True)
+    assert e <= TOL
+    assert eacc(ref, vac) > 1e-6
+
+
+@pytest.mark.parametrize("stepper", ["rk4", "rk6"])
+def test_adjoint_after_a_forward_on_a_bottom_state(stepper):
+    """rheed_backward after rheed_forward_bulk: the table gradient with the
+    bulk held fixed, against the oracle's tangent-linear derivative."""
+    import torch
+    from paper_2306_00271_amd import api
+    wl = small_2d(n_beams=21, n_slices=40, thickness=4.0, n_layers=1, n_angles=3)
+    Y = _random_bottom(wl, seed=6)
+    plan, U, ang, dev = _plan(wl, stepper=stepper, checkpoint_every=7)
+    ws = plan.workspace(dev)
+    out = plan.forward(U, ang, workspace=ws, y_bottom=torch.from_numpy(Y).to(dev))
+    tgt_np = np.random.default_rng(3).uniform(0.0, 0.3, size=3)
+    loss, dI = api.rfactor(out["intensity"], torch.from_numpy(tgt_np).to(dev))
+    dU = plan.backward(U, ang, dI, ws).cpu().numpy()
+    rng = np.random.default_rng(12)
+    st = driver.StructureSetup(wl, wl.structures[0], driver.TABLEAUX[stepper])
+    for _ in range(2):
+        dt = rng.normal(size=st.table.shape) + 1j * rng.normal(size=st.table.shape)
+        lo, dl = driver.rfactor_directional_table(wl, 0, dt, tgt_np, stepper=stepper, y_bottom=Y)
+        got = float(np.real(np.sum(np.conj(dU) * dt.ravel())))
+        print(f"[bulk] adjoint {stepper}: gpu {got:.12e} oracle {dl:.12e}", flush=True)
+        assert float(loss.item()) == pytest.approx(lo, rel=1e-10)
+        assert got == pytest.approx(dl, rel=1e-9)
+
+
+def test_full_size_forward_on_a_bottom_state():
+    """The gradient workload's slab (N = 61, 400 slices, 128 angles) on
+    seeded bottom states near the vacuum's (i Gamma plus noise of 0.3 /
+    sqrt(N) per entry; arbitrary states mixing fast evanescent beams make
+    the problem worse conditioned than any bulk), in the split layout the
+    benchmark times; the oracle checks two sampled angles."""
+    import torch
+    wl = config4(1)
+    Y = _random_bottom(wl, seed=21, scale=0.3)
+    st = driver.StructureSetup(wl, wl.structures[0], driver.TABLEAUX["rk6"])
+    for a in range(len(wl.theta0)):
+        gam, _ = st.angle(float(wl.theta0[a]))
+        Y[a] += 1j * np.diag(gam)
+    plan, U, ang, dev = _plan(wl, stepper="rk6")
+    assert plan.split
+    out = plan.forward(U, ang, y_bottom=torch.from_numpy(Y).to(dev))
+    torch.cuda.synchronize()
+    eta = out["intensity"].cpu().numpy()
+    assert (out["status"].cpu().numpy() == 0).all()
+    idx = [5, 97]
+    ref, _, _ = driver.rocking_curve(wl, angle_idx=idx, stepper="rk6", y_bottom=Y[idx])
+    e = eacc(eta[idx], ref)
+    print(f"[bulk] full size N=61 sampled angles {idx}: eacc={e:.3e}", flush=True)
+    assert e <= TOL
+
+
+def test_bulk_calls_refuse_what_they_cannot_run():
+    import torch
+    from paper_2306_00271_amd import _lib, api
+    lib = _lib.lib()
+    # N > 64 (the kernel without state saving) and the splitting stepper
+    big = small_2d(n_beams=69, n_slices=10, thickness=2.0, n_layers=1, n_angles=2)
+    for wl, stepper in ((big, "rk4"), (small_2d(n_beams=9, n_slices=10, thickness=2.0, n_layers=1, n_angles=2), "sp4")):
+        plan, U, ang, dev = _plan(wl, stepper=stepper)
+        Y = torch.zeros((plan.n_pairs, plan.max_beams, plan.max_beams), dtype=torch.complex128, device=dev)
+        with pytest.raises(_lib.RheedError) as ei:
+            plan.forward(U, ang, y_bottom=Y)
+        assert ei.value.code == _lib.RHEED_E_UNSUPPORTED
+        with pytest.raises(_lib.RheedError) as ei:
+            plan.bulk_reflection(U, ang)
+        assert ei.value.code == _lib.RHEED_E_UNSUPPORTED
+    # invalid tolerance, layer count and workspace size
+    wl = small_2d(n_beams=9, n_slices=10, thickness=2.0, n_layers=1, n_angles=2)
+    plan, U, ang, dev = _plan(wl, stepper="rk4")
+    P, M = plan.n_pairs, plan.max_beams
+    y = torch.zeros((P, M, M), dtype=torch.complex128, device=dev)
+    r = torch.zeros((P, M, M), dtype=torch.complex128, device=dev)
+    lay = torch.empty(P, dtype=torch.int32, device=dev)
+    stt = torch.empty(P, dtype=torch.int32, device=dev)
+    need = int(plan.info.fwd_workspace + plan.info.bulk_workspace)
+    ws = torch.empty(need, dtype=torch.uint8, device=dev)
+    p = api._ptr
+    for tol, layers, nbytes in ((-1.0, 5, need), (float("nan"), 5, need), (1e-8, 0, need), (1e-8, 5, need - 1)):
+        code = lib.rheed_bulk_reflection(plan._h, p(U), p(ang), tol, layers, p(y), p(r), p(lay), p(stt), p(ws),
+                                         nbytes, api._stream())
+        assert code == _lib.RHEED_E_INVALID, (tol, layers, nbytes)
+    inten = torch.empty((P, M), dtype=torch.float64, device=dev)
+    assert lib.rheed_forward_bulk(plan._h, p(U), p(ang), None, p(inten), None, p(stt), None, None, 0,
+                                  api._stream()) == _lib.RHEED_E_INVALID
