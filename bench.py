@@ -33,7 +33,7 @@ CHECKPOINT_EVERY = 20           # the gradient workload keeps the state every 20
 
 
 def kernel_name(split):
-    return "forward_split_kernel<1>" if split else "forward_kernel<1>"
+    return "forward_split_kernel<1, false>" if split else "forward_kernel<1, false>"
 
 
 def traffic_summary(split):
@@ -59,6 +59,19 @@ def _cpu_worker(args):
     import numpy as np
     from synth import config3, config4
     from oracle import driver
+    if kind == "bulk_layer":
+        # one unit layer of the bulk under the gradient workload's slab, from the vacuum
+        from oracle import bulk
+        from oracle.tableaux import TABLEAUX
+        from synth import bulk_layer
+        wb = bulk_layer(config4(1), BULK_SLICES)
+        st = driver.StructureSetup(wb, wb.structures[0], TABLEAUX[stepper])
+        gam, _ = st.angle(float(wb.theta0[idx]))
+        Y = 1j * np.diag(gam)
+        t0 = time.perf_counter()
+        for _ in range(args[3]):
+            Y = bulk.layer_map(st.mfun(gam), gam, st.h, BULK_SLICES, TABLEAUX[stepper], Y)
+        return (time.perf_counter() - t0) / args[3]
     if kind == "uneven":
         # one pair of the uneven-N workload: structure idx of the first args[3], one angle
         wl3 = config3(args[3])
@@ -243,6 +256,92 @@ def uneven_forward(n_structures, steps=2, cpu=True):
     return res
 
 
+# ------------------------------------------------------------- bulk layer
+BULK_SLICES = 62   # per 3.1 A unit layer (h = 0.05 A): at 0.1 A the 61-beam stack drifts to the wrong modes
+
+
+def bulk_bench(cpu=True, tol=1e-6):
+    """The bulk layer under the benchmark's slab (N = 61, 128 angles, RK6):
+    rheed_bulk_reflection stacks the ideal bulk's 3.1 A unit layer
+    (BULK_SLICES slices) from the vacuum until R changes by at most ``tol``
+    per layer, then one forward pass over the surface slab on that bulk
+    (rheed_forward_bulk) beside the same pass over the vacuum."""
+    import numpy as np
+    import torch
+    from paper_2306_00271_amd import api
+    from synth import bulk_layer, config4
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    wl = config4(1)
+    wb = bulk_layer(wl, BULK_SLICES)
+    pb = api.plan_for(wb, stepper="rk6")
+    Ub = pb.potential(api.atoms_for(wb, dev))
+    angb = api.angles_for(wb, dev)
+    pb.bulk_reflection(Ub, angb, tol=1e300, max_layers=1)  # untimed: one layer
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    res = pb.bulk_reflection(Ub, angb, tol=tol, max_layers=2000)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_bulk = e0.elapsed_time(e1)
+    layers = res["layers"].cpu().numpy()
+    bad = int((res["status"] != 0).sum().item()) + int((layers < 0).sum())
+    n_layers = int(layers.max())
+
+    ps = api.plan_for(wl, stepper="rk6")
+    Us = ps.potential(api.atoms_for(wl, dev))
+    angs = api.angles_for(wl, dev)
+
+    def fwd_ms(**kw):
+        ps.forward(Us, angs, **kw)
+        torch.cuda.synchronize()
+        f0 = torch.cuda.Event(enable_timing=True)
+        f1 = torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        for _ in range(3):
+            out = ps.forward(Us, angs, **kw)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        return f0.elapsed_time(f1) / 3, out
+    ms_on_bulk, out = fwd_ms(y_bottom=res["y"])
+    ms_vac, vac = fwd_ms()
+    d = (out["intensity"] - vac["intensity"]).abs().max().item()
+    # stage products of every layer each pair ran (a lower bound on the work:
+    # the transformations are left out), over the whole iteration
+    N = wb.structures[0].n_beams
+    fl = float(layers.clip(min=0).sum()) * BULK_SLICES * 7 * 8.0 * float(N) ** 3
+    rec = {"pairs": pb.n_pairs, "unit_layer_slices": BULK_SLICES, "tol": tol, "layers_max": n_layers,
+           "layers_mean": round(float(layers.mean()), 1), "ms_bulk": round(ms_bulk, 2),
+           "ms_per_layer": round(ms_bulk / max(n_layers, 1), 3), "bad_pairs": bad,
+           "stage_tflops": round(fl / (ms_bulk / 1e3) / 1e12, 2),
+           "note": "pairs stop at their own convergence, so the last layers run few pairs on few CUs",
+           "forward_on_bulk_ms": round(ms_on_bulk, 3), "forward_vacuum_ms": round(ms_vac, 3),
+           "max_intensity_change_from_the_bulk": round(d, 6)}
+    if cpu:
+        # the oracle's unit layer at 16 angles, one per process; a pair's bulk
+        # costs layers_mean of them
+        import multiprocessing as mp
+        cores = min(16, os.cpu_count() or 1)
+        jobs = [("bulk_layer", (c * len(wl.theta0)) // cores, "rk6", 20) for c in range(cores)]
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(cores) as pool:
+            times = pool.map(_cpu_worker, jobs)
+        cwall = time.perf_counter() - t0
+        per_layer = float(sum(times) / len(times))
+        rec["cpu_baseline"] = {"value": round(cores / (per_layer * float(layers.mean())), 5), "unit": "pairs/s",
+                               "cores": cores, "kind": "oracle",
+                               "sample": f"20 unit layers of the bulk at each of {cores} angles, one angle per "
+                                         f"process, mean {per_layer:.3f} s per layer; a pair's bulk takes "
+                                         f"layers_mean layers; "
+                                         f"{cores} processes x 1 BLAS thread, {cwall:.1f} s wall"}
+        rec["value"] = round(pb.n_pairs / (ms_bulk / 1e3), 3)
+        rec["unit"] = "pairs/s"
+    return rec
+
+
 # ------------------------------------------------- steppers: accuracy vs time
 def stepper_comparison(steps=2):
     """The paper's comparison of steppers (Sec. 5: accuracy against time) on
@@ -327,9 +426,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["fwd", "fwd+adj", "uneven", "steppers"], default="fwd+adj",
+    ap.add_argument("--mode", choices=["fwd", "fwd+adj", "uneven", "steppers", "bulk"], default="fwd+adj",
                     help="uneven: only the uneven-N batched forward variant; steppers: only the accuracy-vs-time "
-                         "comparison of the steppers; each as its own JSON line")
+                         "comparison of the steppers; bulk: only the bulk-layer variant; each as its own JSON line")
     ap.add_argument("--structures", type=int, default=1, help="structures in the batch (128 angles each)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-per-angle", action="store_true",
@@ -338,6 +437,7 @@ def main():
                     help="slices between states kept for the adjoint (the gradient workload keeps every 20th)")
     ap.add_argument("--uneven-structures", type=int, default=16,
                     help="structures of the uneven-N batched forward variant (64 angles each; 0 skips it)")
+    ap.add_argument("--no-bulk", action="store_true", help="skip the bulk-layer variant")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run one forward launch and a 1 GiB copy for HBM counter runs, then exit")
     args = ap.parse_args()
@@ -353,6 +453,9 @@ def main():
         return
     if args.mode == "steppers":
         print(json.dumps({"stepper_comparison": stepper_comparison(steps=args.steps)}))
+        return
+    if args.mode == "bulk":
+        print(json.dumps({"bulk_layer": bulk_bench(cpu=not args.no_cpu)}))
         return
     if args.mode == "uneven":
         print(json.dumps({"uneven_n_forward": uneven_forward(max(1, args.uneven_structures), steps=args.steps,
@@ -496,6 +599,9 @@ def main():
     if args.uneven_structures > 0:
         variants = variants or {}
         variants["uneven_n_forward"] = uneven_forward(args.uneven_structures, cpu=not args.no_cpu)
+    if not args.no_bulk and args.structures == 1:
+        variants = variants or {}
+        variants["bulk_layer"] = bulk_bench(cpu=not args.no_cpu)
 
     rec = {
         "metric": "rocking-curve points (structure x angle)/s at N=61 FP64; " +

@@ -230,9 +230,11 @@ rheed_status rheed_forward_bulk(rheed_plan_t plan, const void* U_tables, const d
  *  pair_status device int32 [n_pairs]: RHEED_PAIR_* (a failed pair keeps the
  *             last layer's Y and R and stops)
  *  workspace  device, >= fwd_workspace + bulk_workspace bytes (overwritten)
- * The stepper's damping of fast beams over many layers can turn the stack
- * to the wrong modes: use a step at which it is small (RK6 at h = 0.1 A, or
- * RK4 at 0.05 A, on the synthetic bulks of this library's tests).
+ * Over many layers the stepper's error on the fastest beams can turn the
+ * stack to the wrong modes (R then grows without bound and no layer
+ * passes): use a step at which it is small.  On the synthetic bulks of this
+ * library's tests, 21 beams need RK6 at h = 0.1 A or RK4 at 0.05 A, and the
+ * 61-beam bulk of the benchmark RK6 at 0.05 A.
  * Synchronises the stream after each layer to read the convergence flags
  * (so it cannot be captured into a graph); allocates nothing.  Needs an RK
  * stepper and every structure to have N <= 64. */
