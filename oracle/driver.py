@@ -117,9 +117,10 @@ def rfactor(eta00, target00):
 
 
 def rfactor_directional(wl, s_idx, direction, target00, angle_idx=None, stepper=None,
-                        convention="flux"):
+                        convention="flux", y_bottom=None):
     """Directional derivative of the R-factor along atom displacements
-    ``direction`` [n_atoms, 3], by the tangent-linear method."""
+    ``direction`` [n_atoms, 3], by the tangent-linear method; ``y_bottom``
+    as for ``rocking_curve`` (held fixed)."""
     tab = TABLEAUX[stepper or wl.stepper]
     st = StructureSetup(wl, wl.structures[s_idx], tab)
     dtable = potential.potential_table_direction(st.s, st.z_nodes, st.kappa, wl.charge,
@@ -132,7 +133,8 @@ def rfactor_directional(wl, s_idx, direction, target00, angle_idx=None, stepper=
 
         def dU(i, r):
             return dtable[tab.node_index(i, r)][st.cidx]
-        rho, drho = tangent.solve_ode_str_tangent(st.mfun(gam), dU, gam, st.h, st.s.n_slices, tab)
+        rho, drho = tangent.solve_ode_str_tangent(st.mfun(gam), dU, gam, st.h, st.s.n_slices, tab,
+                                                  y_bottom=None if y_bottom is None else y_bottom[k])
         eta = rk.intensity(rho, gam, mask, th, convention)
         deta = tangent.intensity_tangent(rho, drho, gam, mask, th, convention)
         diff = eta[0] - target00[k]

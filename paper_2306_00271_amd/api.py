@@ -220,13 +220,14 @@ class _Intensity(torch.autograd.Function):
     """Intensities of every pair as a differentiable function of the atom
     coordinates: tables (rheed_potential) -> propagation (rheed_forward) on
     the way forward; rheed_backward -> rheed_potential_backward on the way
-    back.  The forward keeps the workspace only when a gradient is needed."""
+    back.  The forward keeps the workspace only when a gradient is needed.
+    With ``y_bottom`` (a bulk's state below the slab) the bulk is held fixed."""
 
     @staticmethod
-    def forward(ctx, atoms, plan, angles):
+    def forward(ctx, atoms, plan, angles, y_bottom):
         U = plan.potential(atoms)
         ws = plan.workspace(atoms.device) if ctx.needs_input_grad[0] else None
-        out = plan.forward(U, angles, workspace=ws)
+        out = plan.forward(U, angles, workspace=ws, y_bottom=y_bottom)
         ctx.plan = plan
         if ws is not None:
             ctx.save_for_backward(atoms, U, angles, ws)
@@ -237,13 +238,15 @@ class _Intensity(torch.autograd.Function):
     def backward(ctx, dI, _dstatus):
         atoms, U, angles, ws = ctx.saved_tensors
         dU = ctx.plan.backward(U, angles, dI.contiguous(), ws)
-        return ctx.plan.potential_backward(atoms, dU), None, None
+        return ctx.plan.potential_backward(atoms, dU), None, None, None
 
 
-def intensity(plan: Plan, atoms: torch.Tensor, angles: torch.Tensor):
+def intensity(plan: Plan, atoms: torch.Tensor, angles: torch.Tensor, y_bottom: Optional[torch.Tensor] = None):
     """(intensity [n_pairs][max_beams], pair status [n_pairs]) with autograd
-    support: a loss built from the intensities back-propagates to `atoms`."""
-    return _Intensity.apply(atoms, plan, angles)
+    support: a loss built from the intensities back-propagates to `atoms`.
+    ``y_bottom``: the state of a bulk below the slab (``Plan.bulk_reflection``),
+    held fixed; None for the vacuum."""
+    return _Intensity.apply(atoms, plan, angles, y_bottom)
 
 
 def mfma_f64_peak(blocks: int = 1024, iters: int = 4000) -> float:

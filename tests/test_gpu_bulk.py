@@ -194,6 +194,34 @@ def test_adjoint_after_a_forward_on_a_bottom_state(stepper):
         assert got == pytest.approx(dl, rel=1e-9)
 
 
+def test_autograd_on_a_bulk_matches_oracle():
+    """api.intensity with a bulk's state: the atom gradient of an R-factor
+    through torch.autograd against the oracle's tangent-linear derivative
+    along a random atom direction, with the bulk held fixed."""
+    import torch
+    from paper_2306_00271_amd import api
+    wl = small_2d(n_beams=21, n_slices=40, thickness=4.0, n_layers=2, n_angles=3)
+    Y = _random_bottom(wl, seed=13)
+    plan = api.plan_for(wl, stepper="rk6", checkpoint_every=20)
+    dev = torch.device("cuda:0")
+    atoms = api.atoms_for(wl, dev).requires_grad_(True)
+    tgt = np.random.default_rng(2).uniform(0.0, 0.3, size=3)
+    inten, status = api.intensity(plan, atoms, api.angles_for(wl, dev), y_bottom=torch.from_numpy(Y).to(dev))
+    loss = ((inten[:, 0] - torch.from_numpy(tgt).to(dev)) ** 2).sum()
+    loss.backward()
+    g = atoms.grad.cpu().numpy()
+    assert (status.cpu().numpy() == 0).all()
+    s = wl.structures[0]
+    d = np.zeros_like(s.atoms)
+    d[s.grad_atoms] = np.random.default_rng(7).normal(size=(len(s.grad_atoms), 3))
+    lo, dl = driver.rfactor_directional(wl, 0, d, tgt, stepper="rk6", y_bottom=Y)
+    got = float(np.sum(g * d))
+    print(f"[bulk] autograd on a bulk: loss gpu {loss.item():.12e} oracle {lo:.12e}; "
+          f"direction gpu {got:.12e} oracle {dl:.12e}", flush=True)
+    assert loss.item() == pytest.approx(lo, rel=1e-10)
+    assert got == pytest.approx(dl, rel=1e-8)
+
+
 def test_full_size_forward_on_a_bottom_state():
     """The gradient workload's slab (N = 61, 400 slices, 128 angles) on
     seeded bottom states near the vacuum's (i Gamma plus noise of 0.3 /
