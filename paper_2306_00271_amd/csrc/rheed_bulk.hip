@@ -141,25 +141,23 @@ __global__ __launch_bounds__(BT, 1) void bulk_update_kernel(BulkArgs a) {
   }
   __syncthreads();
   bool ok = eliminate(s, N, tid, lane, w);
+  // this thread's entries i = tid + q BT of Y' and R', kept in registers until
+  // the layer has passed (a pair that fails keeps its last Y and R)
+  constexpr int PER = NP * NP / BT;
+  double2 yv[PER], rv[PER];
+  double dmax = 0.0;
   if (ok) {
-    // Y' = P Q^{-1}: written out, then [Gamma - iY'; Gamma + iY'] for R'
-    for (int i = tid; i < NP * NP; i += BT) {
-      const int j = i / NP, k = i - j * NP;
-      const double2 y = s.m[NP + j][k];
-      if (j < N && k < N) {
-        if (!isfinite(y.x) || !isfinite(y.y)) s.nonfinite = 1;  // every writer stores 1
-        a.y[mbase + (long long)j * a.ld + k] = y;
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < NP * NP; i += BT) {
-      const int j = i / NP, k = i - j * NP;
+    // Y' = P Q^{-1}, then [Gamma - iY'; Gamma + iY'] in place for R'
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = tid + q * BT, j = i / NP, k = i - j * NP;
+      yv[q] = s.m[NP + j][k];
       double2 b = make_double2(j == k ? 1.0 : 0.0, 0.0), av = make_double2(0.0, 0.0);
       if (j < N && k < N) {
-        const double2 y = s.m[NP + j][k];
+        if (!isfinite(yv[q].x) || !isfinite(yv[q].y)) s.nonfinite = 1;  // every writer stores 1
         const double2 g = j == k ? gamma_of(s.g2s[j]) : make_double2(0.0, 0.0);
-        b = make_double2(g.x + y.y, g.y - y.x);    // Gamma - iY
-        av = make_double2(g.x - y.y, g.y + y.x);   // Gamma + iY
+        b = make_double2(g.x + yv[q].y, g.y - yv[q].x);    // Gamma - iY
+        av = make_double2(g.x - yv[q].y, g.y + yv[q].x);   // Gamma + iY
       }
       s.m[j][k] = b;  // entry (j, k) is read and written by this thread only
       s.m[NP + j][k] = av;
@@ -167,40 +165,43 @@ __global__ __launch_bounds__(BT, 1) void bulk_update_kernel(BulkArgs a) {
     __syncthreads();
     ok = eliminate(s, N, tid, lane, w);
   }
-  if (!ok) {
-    if (tid == 0) {
-      a.status[p] = 1;  // RHEED_PAIR_SINGULAR
-      a.done[p] = 1;
-    }
-    return;
-  }
-  // R' = (Gamma + iY')(Gamma - iY')^{-1}; the largest change against R
-  double dmax = 0.0;
-  for (int i = tid; i < NP * NP; i += BT) {
-    const int j = i / NP, k = i - j * NP;
-    if (j < N && k < N) {
-      const double2 r = s.m[NP + j][k];
-      if (!isfinite(r.x) || !isfinite(r.y)) s.nonfinite = 1;
-      const long long at = mbase + (long long)j * a.ld + k;
-      const double2 o = a.r[at];
-      const double dx = r.x - o.x, dy = r.y - o.y;
-      dmax = fmax(dmax, sqrt(dx * dx + dy * dy));
-      a.r[at] = r;
+  if (ok) {
+    // R' = (Gamma + iY')(Gamma - iY')^{-1}; the largest change against R
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int i = tid + q * BT, j = i / NP, k = i - j * NP;
+      rv[q] = s.m[NP + j][k];
+      if (j < N && k < N) {
+        if (!isfinite(rv[q].x) || !isfinite(rv[q].y)) s.nonfinite = 1;
+        const double2 o = a.r[mbase + (long long)j * a.ld + k];
+        const double dx = rv[q].x - o.x, dy = rv[q].y - o.y;
+        dmax = fmax(dmax, sqrt(dx * dx + dy * dy));
+      }
     }
   }
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
   if (lane == 0) s.red[w] = dmax;
   __syncthreads();
+  const bool fail = !ok || s.nonfinite;  // uniform: read after the barrier
   if (tid == 0) {
     double dm = s.red[0];
     for (int q = 1; q < BT / 64; ++q) dm = fmax(dm, s.red[q]);
-    if (s.nonfinite) {
-      a.status[p] = 2;  // RHEED_PAIR_NONFINITE
+    if (fail) {
+      a.status[p] = ok ? 2 : 1;  // RHEED_PAIR_NONFINITE : RHEED_PAIR_SINGULAR
       a.done[p] = 1;
     } else if (dm <= a.tol) {
       a.done[p] = 1;
       a.layers[p] = a.iter;
+    }
+  }
+  if (fail) return;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = tid + q * BT, j = i / NP, k = i - j * NP;
+    if (j < N && k < N) {
+      a.y[mbase + (long long)j * a.ld + k] = yv[q];
+      a.r[mbase + (long long)j * a.ld + k] = rv[q];
     }
   }
 }
