@@ -248,6 +248,33 @@ def test_full_size_forward_on_a_bottom_state():
     assert e <= TOL
 
 
+def test_full_size_bulk_layers_on_sampled_angles():
+    """The benchmark's bulk (N = 61, 128 angles, 62 slices per 3.1 A layer,
+    the split layout): three unit layers from the vacuum for every pair
+    (tolerance out of reach), Y and R against the oracle's three layers at
+    two sampled angles."""
+    import torch
+    wl = config4(1)
+    wb = bulk_layer(wl, 62)
+    plan, U, ang, dev = _plan(wb, stepper="rk6")
+    assert plan.split and plan.max_beams == 61
+    res = plan.bulk_reflection(U, ang, tol=1e-300, max_layers=3)
+    torch.cuda.synchronize()
+    assert (res["layers"].cpu().numpy() == -1).all() and (res["status"].cpu().numpy() == 0).all()
+    Yg, Rg = res["y"].cpu().numpy(), res["r"].cpu().numpy()
+    st = driver.StructureSetup(wb, wb.structures[0], driver.TABLEAUX["rk6"])
+    for a in (9, 70):
+        gam, _ = st.angle(float(wb.theta0[a]))
+        Yo = 1j * np.diag(gam)
+        for _ in range(3):
+            Yo = bulk.layer_map(st.mfun(gam), gam, st.h, 62, driver.TABLEAUX["rk6"], Yo)
+        Ro = bulk.reflection_of_state(Yo, gam)
+        dy = np.abs(Yg[a] - Yo).max() / np.abs(Yo).max()
+        dr = np.abs(Rg[a] - Ro).max()
+        print(f"[bulk] full size, 3 layers, angle {a}: max|dY|/max|Y| {dy:.3e}, max|dR| {dr:.3e}", flush=True)
+        assert dy <= 1e-10 and dr <= 1e-10
+
+
 def test_bulk_calls_refuse_what_they_cannot_run():
     import torch
     from paper_2306_00271_amd import _lib, api
