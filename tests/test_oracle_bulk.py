@@ -135,3 +135,27 @@ def test_tangent_with_a_fixed_bulk_matches_central_differences():
     rm = rk.solve_ode_str(st.mfun(gam, table=st.table - eps * dt), gam, st.h, 30, RK4, y_bottom=Y)[0]
     fd = (rp - rm) / (2 * eps)
     assert np.abs(drho - fd).max() <= 1e-6 * np.abs(fd).max()
+
+
+def test_unit_layer_table_is_periodic():
+    """The bulk's unit layer (one atomic layer at its centre with two periodic
+    images on each side) has the same coupling at its bottom and top faces,
+    up to the Gaussian tails of the images left out."""
+    from oracle import physics, potential
+    wl = small_2d(n_beams=21, n_slices=40, thickness=6.0, n_layers=2, n_angles=1)
+    b = bulk_layer(wl, 31)
+    s = b.structures[0]
+    kappa = physics.interaction_constant(b.energy_eV)
+    z = np.array([-s.thickness, -0.5 * s.thickness, 0.0])
+    t = potential.potential_table(s, z, kappa, b.charge, b.absorption, b.mean_inner_potential)
+    assert np.abs(t[0] - t[2]).max() < 1e-12 * np.abs(t).max()
+    # the layer at the centre dominates: the faces hold less than the middle
+    assert np.abs(t[0]).max() < np.abs(t[1]).max()
+    # and the mean inner potential (the g = 0 coefficient's mean over the layer)
+    # equals the surface's value: the images' atoms are counted per spacing
+    zz = np.linspace(-s.thickness, 0.0, 2001)
+    hd, kd = potential.difference_box(s.beams)
+    g0 = hd * (2 * kd + 1) + kd
+    u0 = potential.potential_table(s, zz, kappa, b.charge, 0.0, b.mean_inner_potential)[:, g0].real
+    mean = np.trapezoid(u0, zz) / s.thickness
+    assert mean == pytest.approx(kappa * wl.mean_inner_potential, rel=1e-3)
