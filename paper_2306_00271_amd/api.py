@@ -152,8 +152,8 @@ class Plan:
                                                      ws_bytes, _stream()), "forward_bulk")
         return {"intensity": inten, "rho": rho, "status": status, "n_rhst": nrhst}
 
-    def bulk_reflection(self, U: torch.Tensor, angles: torch.Tensor, *, tol: float = 1e-8,
-                        max_layers: int = 1000):
+    def bulk_reflection(self, U: torch.Tensor, angles: torch.Tensor, *, tol: float = 1e-6,
+                        max_layers: int = 2000):
         """The bulk whose unit layers this plan's structures are, stacked from
         the vacuum until R converges (rheed_bulk_reflection): {"y": state
         [n_pairs, M, M] for ``forward(y_bottom=...)``, "r": reflection
