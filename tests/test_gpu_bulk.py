@@ -222,6 +222,50 @@ def test_autograd_on_a_bulk_matches_oracle():
     assert got == pytest.approx(dl, rel=1e-8)
 
 
+@pytest.mark.parametrize("layout", ["whole", "split"])
+def test_graph_capture_of_the_gradient_step_on_a_bulk(layout):
+    """potential -> rheed_forward_bulk (keeping states) -> R-factor ->
+    rheed_backward -> potential backward captured once in a HIP graph: every
+    replay, with eager calls and synchronisations between replays,
+    reproduces the eager outputs bit for bit."""
+    import torch
+    from paper_2306_00271_amd import api
+    wl = small_2d(n_beams=21, n_slices=24, thickness=3.0, n_layers=1, n_angles=3)
+    plan, _, ang, dev = _plan(wl, stepper="rk6", layout=layout, checkpoint_every=5)
+    atoms = api.atoms_for(wl, dev)
+    Y = torch.from_numpy(_random_bottom(wl, seed=17)).to(dev)
+    ws = plan.workspace(dev)
+    tgt = torch.from_numpy(np.random.default_rng(1).uniform(0.0, 0.3, size=3)).to(dev)
+
+    def step():
+        U = plan.potential(atoms)
+        out = plan.forward(U, ang, workspace=ws, y_bottom=Y)
+        loss, dI = api.rfactor(out["intensity"], tgt)
+        dU = plan.backward(U, ang, dI, ws)
+        return out["intensity"], out["status"], loss, plan.potential_backward(atoms, dU)
+
+    ref = [t.clone() for t in step()]
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        outs = step()
+    for r in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        for o, rf in zip(outs, ref):
+            assert torch.equal(o, rf), f"replay {r}"
+        step()
+        torch.cuda.synchronize()
+    assert (ref[1] == 0).all()
+    print(f"[bulk] {layout}: the gradient step on a bulk replays bit for bit", flush=True)
+
+
 def test_full_size_forward_on_a_bottom_state():
     """The gradient workload's slab (N = 61, 400 slices, 128 angles) on
     seeded bottom states near the vacuum's (i Gamma plus noise of 0.3 /
