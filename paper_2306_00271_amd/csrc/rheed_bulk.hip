@@ -19,6 +19,7 @@ namespace rheed {
 namespace {
 
 constexpr int BT = 256;  // threads of the one workgroup per pair
+static_assert(BT % NP == 0, "each thread keeps one column in the elimination");
 
 struct BulkLds {
   double2 m[2 * NP][NP + 1];  // [Q; P], then [Gamma - iY; Gamma + iY]; columns eliminated in place
@@ -83,13 +84,21 @@ __device__ bool eliminate(BulkLds& s, int N, int tid, int lane, int w) {
     __syncthreads();
     if (tid < NP) s.f[tid] = (tid != k && tid < N) ? s.m[k][tid] : make_double2(0.0, 0.0);
     __syncthreads();
-    for (int i = tid; i < 2 * NP * NP; i += BT) {
-      const int r = i / NP, c = i - r * NP;
+    // column c -= f_c column k; each thread keeps one column (BT is a multiple
+    // of 64) and its multiplier.  Rows N.. of each block are skipped: there
+    // the eliminated columns hold 0 (identity rows of B, zero rows of A).
+    {
+      const int c = tid & (NP - 1);
       const double2 fc = s.f[c];
       if (fc.x != 0.0 || fc.y != 0.0) {
-        const double2 t = cmul(fc, s.m[r][k]);
-        s.m[r][c].x -= t.x;
-        s.m[r][c].y -= t.y;
+        for (int r = tid / NP; r < N; r += BT / NP) {
+#pragma unroll
+          for (int blk = 0; blk < 2; ++blk) {
+            const double2 t = cmul(fc, s.m[blk * NP + r][k]);
+            s.m[blk * NP + r][c].x -= t.x;
+            s.m[blk * NP + r][c].y -= t.y;
+          }
+        }
       }
     }
     __syncthreads();
