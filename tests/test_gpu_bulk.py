@@ -1,7 +1,6 @@
 """Parity of the bulk layer's HIP path (rheed_forward_bulk and
 rheed_bulk_reflection, through the C ABI) with the oracle (oracle/bulk.py,
 oracle/rk.py started from a bulk's state [I; Y])."""
-import ctypes as C
 import dataclasses
 
 import numpy as np
