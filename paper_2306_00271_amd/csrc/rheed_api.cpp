@@ -456,11 +456,12 @@ rheed_status rheed_potential_backward(rheed_plan_t P, const double* atoms, const
 
 namespace {
 
-// rheed_forward with an optional bottom state [I; Y] per pair and an
-// optional skip flag per pair (the bulk iteration's converged pairs).
+// rheed_forward with an optional bottom state [I; Y] per pair, an optional
+// skip flag per pair (the bulk iteration's converged pairs) and, with a bottom
+// state and a workspace, the option to keep only the final state.
 rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* angles, double* intensity, void* rho,
                           int32_t* pair_status, int32_t* n_rhst, void* workspace, size_t ws_bytes, void* stream,
-                          const void* y_bottom, const int* skip) {
+                          const void* y_bottom, const int* skip, bool final_only = false) {
   if (!P || !U_tables || !angles || !intensity || !pair_status) return fail(RHEED_E_INVALID, "forward: null argument");
   if (workspace && !P->large_pairs.empty())
     return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs an RK stepper and every structure to have N <= 64");
@@ -470,6 +471,7 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
   FwdArgs a{};
   a.y_bottom = static_cast<const double2*>(y_bottom);
   a.skip = skip;
+  a.final_only = final_only ? 1 : 0;
   a.structs = P->d_structs;
   a.pair_struct = P->d_pair_struct;
   a.beams = P->d_beams;
@@ -577,7 +579,7 @@ rheed_status rheed_bulk_reflection(rheed_plan_t P, const void* U_tables, const d
   for (int it = 1; it <= max_layers; ++it) {
     // one unit layer from [I; Y] for every pair still iterating, then Y and R at its top
     rheed_status s = forward_impl(P, U_tables, angles, inten, nullptr, fstat, nullptr, workspace, P->fwd_ws, stream,
-                                  y_bulk, done);
+                                  y_bulk, done, true);
     if (s != RHEED_OK) return s;
     b.iter = it;
     e = launch_bulk_update(b, st);

@@ -289,13 +289,17 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
   }
   const bool save = a.ws != nullptr;
   char* pws = save ? a.ws + (long long)p * a.ck.pair_stride : nullptr;
+  // keep: what the adjoint needs besides the final state (a bulk's layer
+  // keeps only the final state)
+  bool keep = save;
+  if constexpr (BULK) keep = save && !a.final_only;
   int nrhst = 0;
 
   load_nodes<T::slots, FT>(s, Us, S.box, 0, 1, tid);
   for (int i = 0; i < L; ++i) {
     // keep the address base from being expanded into loop-invariant registers
     asm volatile("" : "+v"(ob));
-    if (save && (i % a.ck.every) == 0) {
+    if (keep && (i % a.ck.every) == 0) {
       double2* st = reinterpret_cast<double2*>(pws + (long long)(i / a.ck.every) * a.ck.state_bytes);
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
@@ -488,14 +492,14 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       const double xi = lo > 0.0 ? hi / lo : INFINITY;
       do_rhst = xi > a.threshold;
     }
-    if (save && tid == 0) pws[a.ck.flags_off + i] = do_rhst ? 1 : 0;
+    if (keep && tid == 0) pws[a.ck.flags_off + i] = do_rhst ? 1 : 0;
     if (do_rhst) {
       // Z <- Z Q^{-1}: T = Q^{-1} by elimination (kept for the adjoint when
       // saving), then P <- P T on the matrix cores, c <- I
       ++nrhst;
       store_mat(xb, d, ob);
       __syncthreads();
-      if (save)
+      if (keep)
         invert_top<true>(N, reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * NP * NP * sizeof(double2)));
       else
         invert_top<false>(N, nullptr);
@@ -503,7 +507,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
         d.r[e] = gr;
         d.i[e] = gi;
       });
-      if (save && a.ck.r_off) {  // R = P Q^{-1} for an adjoint that keeps states only every few slices
+      if (keep && a.ck.r_off) {  // R = P Q^{-1} for an adjoint that keeps states only every few slices
         double2* rs = reinterpret_cast<double2*>(pws + a.ck.r_off + (long long)i * NP * NP * sizeof(double2));
 #pragma unroll
         for (int e = 0; e < NE; ++e) rs[OWN(e)] = make_double2(d.r[e], d.i[e]);
@@ -985,6 +989,8 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
   }
   const bool save = a.ws != nullptr;
   char* pws = save ? a.ws + (long long)p * a.ck.pair_stride : nullptr;
+  bool keep = save;  // as in forward_kernel
+  if constexpr (BULK) keep = save && !a.final_only;
   char* X = a.xch + (long long)pi * XCH_STRIDE;
   unsigned long long* cnt_me = reinterpret_cast<unsigned long long*>(X) + half;
   unsigned long long* cnt_other = reinterpret_cast<unsigned long long*>(X) + (1 - half);
@@ -1012,7 +1018,7 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
   __syncthreads();
   for (int i = 0; i < L; ++i) {
     asm volatile("" : "+v"(ob));
-    if (save && (i % a.ck.every) == 0) {
+    if (keep && (i % a.ck.every) == 0) {
       double2* st = reinterpret_cast<double2*>(pws + (long long)(i / a.ck.every) * a.ck.state_bytes);
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
@@ -1078,7 +1084,7 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
       const double xi = lo > 0.0 ? hi / lo : INFINITY;
       do_rhst = xi > a.threshold;
     }
-    if (save && tid == 0 && half == 0) pws[a.ck.flags_off + i] = do_rhst ? 1 : 0;
+    if (keep && tid == 0 && half == 0) pws[a.ck.flags_off + i] = do_rhst ? 1 : 0;
     if (do_rhst) {
       // Z <- Z Q^{-1}: gather Q and P of both halves, invert Q, P <- P Q^{-1} for this half's columns
       ++nrhst;
@@ -1118,14 +1124,14 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
         }
       }
       __syncthreads();
-      invert_split(N, save ? reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * NP * NP * sizeof(double2))
+      invert_split(N, keep ? reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * NP * NP * sizeof(double2))
                            : nullptr,
                    col0);
       split_gemm(s.cx, s.ext, lane, RT, col0, [&](int e, double gr, double gi) {
         d.r[e] = gr;
         d.i[e] = gi;
       });
-      if (save && a.ck.r_off) {  // R = P Q^{-1} for an adjoint that keeps states only every few slices
+      if (keep && a.ck.r_off) {  // R = P Q^{-1} for an adjoint that keeps states only every few slices
         double2* rs = reinterpret_cast<double2*>(pws + a.ck.r_off + (long long)i * NP * NP * sizeof(double2));
 #pragma unroll
         for (int e = 0; e < NE; ++e) {

@@ -59,6 +59,8 @@ struct FwdArgs {
   // Y of pair p at y_bottom + p ld ld, row major (null: the vacuum, [I; i Gamma])
   const double2* y_bottom;
   const int* skip;           // [P] pairs with skip[p] != 0 are not run (or null)
+  int final_only;            // with ws and a bulk start: keep only the final state (no adjoint follows)
+  int pad2;
 };
 
 // Gamma_j from g2 = Gamma_j^2 (Sec. 2.1): sqrt(g2) for open beams, -i sqrt(-g2)
