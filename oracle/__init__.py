@@ -30,7 +30,13 @@ Contents (section numbers are the paper's, arXiv 2306.00271):
                       by iterating one unit layer until it converges, used
                       as the bottom condition of the surface (Sec. 2.2).
 
-Parity status of every function is listed in the module docstrings; no
-function here is "parity unpinned": each is checked by ``tests/test_oracle_*``
-against closed forms, invariants, independent formulations or brute force.
+Every function here is pinned by ``tests/test_oracle_*.py`` against what
+the paper and the mathematics fix rather than against itself: handbook
+constants, rooted-tree order conditions, a real-space quadrature of the
+potential and of the coupling matrix element (which fixes the orientation
+of l(j,k)), closed-form single-beam slabs, the Fresnel limit, agreement of
+independent formulations (eigen, Ichimiya recursion, global product, RK),
+order under step halving, flux conservation, RHST invariance, symmetries
+and central differences.  The pins of each module are listed in its
+docstring.
 """

@@ -21,7 +21,7 @@ Three independent formulations live here:
 
 Pins: agreement of the three with each other and with the single-beam
 closed form, L-independence for piecewise-constant potentials, flux
-conservation (tests/test_oracle_conventional.py).
+conservation (tests/test_oracle_solvers.py).
 """
 from __future__ import annotations
 

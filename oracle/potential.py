@@ -27,9 +27,12 @@ Kd = max k - min k over the beam set.  Node n of a tableau with distinct
 fractional nodes ``cset`` sits at z = -D + (i + cset[m]) h with
 n = i * len(cset) + m, plus a final node at z = 0.
 
-Pins: the table is checked against a direct real-space evaluation of the
-Fourier integral (quadrature over the cell) and its derivatives against
-central differences (tests/test_oracle_potential.py).
+Pins (tests/test_oracle_basics.py): the table against a direct real-space
+evaluation of the Fourier integral (quadrature over the cell); the coupling
+matrix U_jk = u_{l(j,k)} as a whole, orientation included, against a
+quadrature of the matrix element (1/A) int exp(-i k_j.r) v(r) exp(i k_k.r)
+d^2r on a cell without in-plane symmetry (where the transpose differs); the
+derivatives against central differences.
 """
 from __future__ import annotations
 

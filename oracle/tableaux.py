@@ -8,8 +8,8 @@ order", J. Austral. Math. Soc. 4 (1964)); the paper's own high-order runs
 use splitting methods whose coefficients are not reproduced here.
 
 Pins: every order condition up to the claimed order is checked by
-rooted-tree elementary weights in tests/test_oracle_tableaux.py, and the
-observed convergence ratio under step halving in tests/test_oracle_rk.py.
+rooted-tree elementary weights in tests/test_oracle_basics.py, and the
+observed convergence ratio under step halving in tests/test_oracle_solvers.py.
 """
 from __future__ import annotations
 

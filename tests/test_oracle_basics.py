@@ -1,5 +1,6 @@
 """Pins for the oracle's building blocks: constants, tableaux, condition
 estimate, potential table (CPU only)."""
+import dataclasses
 import itertools
 import math
 import os
@@ -210,3 +211,97 @@ def test_potential_direction_matches_finite_differences():
     sm.atoms = s.atoms - eps * d
     fd = (potential.potential_table(sp, z, *args) - potential.potential_table(sm, z, *args)) / (2 * eps)
     assert np.abs(an - fd).max() <= 1e-7 * np.abs(an).max()
+
+
+# ------------------------------------------------ coupling matrix orientation
+def _asymmetric_cell():
+    """One 1x1 cell with two atoms at general in-plane positions (no mirror,
+    no inversion), so that u_g is complex and u_{-g} != u_g."""
+    wl = small_2d(n_beams=9, n_slices=4, thickness=4.0, n_layers=1, m=1, sigma_xy=0.0,
+                  absorption=0.1, n_angles=3)
+    s = wl.structures[0]
+    s.atoms = np.array([[0.7, 1.1, -1.3], [2.0, 3.1, -2.6]])
+    s.scat_b = np.array([0.6, 0.9, 1.3, 2.0])            # wide enough for a coarse grid
+    return wl, s
+
+
+def test_coupling_matrix_is_the_matrix_element_of_the_potential():
+    """Sec. 2.1, Eq. (sch2): inserting psi = sum_k c_k(z) exp(i (b0 + k_k).r)
+    into the Schroedinger equation and projecting on exp(i (b0 + k_j).r)
+    couples beam j to beam k through (1/A) int_cell exp(-i k_j.r) v(r)
+    exp(+i k_k.r) d^2r.  That matrix element is evaluated here by direct
+    quadrature of the real-space potential (periodic Gaussian atoms) and
+    compared entry by entry with the U_jk the solver uses; the transposed
+    orientation (u_{g_k - g_j}) fails on this cell."""
+    from oracle import driver
+    from oracle.tableaux import RK6
+    wl, s = _asymmetric_cell()
+    st = driver.StructureSetup(wl, s, RK6)
+    sc = potential.mip_scale(s, wl.mean_inner_potential)
+    pref = st.kappa * sc * (wl.charge - 1j * wl.absorption)
+    a = math.sqrt(s.cell_area)
+    ng = 96
+    xs = (np.arange(ng) + 0.5) * a / ng
+    X, Y = np.meshgrid(xs, xs, indexing="ij")
+    kv = physics.beam_vectors(s.beams, s.recip)
+    phase = np.exp(1j * (kv[:, 0, None, None] * X[None] + kv[:, 1, None, None] * Y[None]))  # exp(i k_k.r)
+    N = s.n_beams
+    for node in (0, 3, 7):
+        zz = st.z_nodes[node]
+        V = np.zeros_like(X)
+        for (x0, y0, z0) in s.atoms:
+            for ix in range(-3, 4):
+                for iy in range(-3, 4):
+                    r2 = (X - x0 - ix * a) ** 2 + (Y - y0 - iy * a) ** 2 + (zz - z0) ** 2
+                    for am, bm in zip(s.scat_a, s.scat_b):
+                        V += am * np.exp(-bm * r2)
+        ref = np.empty((N, N), dtype=np.complex128)
+        for j in range(N):
+            for k in range(N):
+                ref[j, k] = pref * np.mean(np.conj(phase[j]) * V * phase[k])
+        U = st.U_node(node)
+        scale = np.abs(ref).max()
+        assert np.abs(U - ref).max() <= 1e-8 * scale
+        # the orientation is observable on this cell: the transpose is far off
+        assert np.abs(U.T - ref).max() > 1e-3 * scale
+
+
+def test_transposed_coupling_changes_the_intensities():
+    """The orientation of U_jk matters for the output: U^T (u_{g_k - g_j}) is
+    the coupling of the in-plane point image v(-r) of the cell, which at the
+    same incidence equals the original cell seen from the opposite azimuth;
+    on a cell without in-plane symmetry the intensities, specular included,
+    change off the specular beam, so a parity test over all beams on such a
+    cell (the synthetic slabs carry random in-plane displacements) tells the
+    two apart."""
+    from oracle import driver
+    from oracle.tableaux import RK6
+    wl, s = _asymmetric_cell()
+    s.n_slices, s.thickness = 40, 4.0
+    st = driver.StructureSetup(wl, s, RK6)
+    th = float(wl.theta0[1])
+    gam, mask = st.angle(th)
+    g2 = np.diag(gam * gam)
+
+    def m_t(i, r):
+        return st.U_node(RK6.node_index(i, r)).T + g2
+    rho, _, _, _ = st.solve(th)
+    rho_t, _ = rk.solve_ode_str(m_t, gam, st.h, s.n_slices, RK6)
+    eta = rk.intensity(rho, gam, mask, th)
+    eta_t = rk.intensity(rho_t, gam, mask, th)
+    assert np.abs(eta_t[1:] - eta[1:]).max() > 1e-4 * eta.max()
+    # the transpose at the opposite azimuth: the image cell seen from theta1 + pi
+    # is the original cell seen from theta1, so U^T there gives eta back
+    wl_b = dataclasses.replace(wl, theta1=wl.theta1 + math.pi)
+    st_b = driver.StructureSetup(wl_b, s, RK6)
+    gam_b, mask_b = st_b.angle(th)
+    kv = physics.beam_vectors(s.beams, s.recip)
+    # beam k_j at azimuth theta1 + pi corresponds to beam -k_j at theta1
+    perm = [next(i for i in range(s.n_beams) if np.allclose(kv[i], -kv[j])) for j in range(s.n_beams)]
+    g2b = np.diag(gam_b * gam_b)
+
+    def m_bt(i, r):
+        return st_b.U_node(RK6.node_index(i, r)).T + g2b
+    rho_bt, _ = rk.solve_ode_str(m_bt, gam_b, st_b.h, s.n_slices, RK6)
+    eta_bt = rk.intensity(rho_bt, gam_b, mask_b, th)
+    assert np.allclose(eta_bt[perm], eta, rtol=1e-9, atol=1e-14)
