@@ -149,6 +149,15 @@ rheed_status rheed_plan_create(rheed_plan_t* plan, const rheed_opts* opts, int32
                                const rheed_structure* structs, const int32_t* angles_per_struct);
 rheed_status rheed_plan_destroy(rheed_plan_t plan);
 rheed_status rheed_plan_get_info(rheed_plan_t plan, rheed_plan_info* info);
+/* Failure path of the split layout, for tests: with half = 0 or 1, the
+ * first wait of that workgroup of every pair in later split launches gives
+ * up at once, as a wait does when the partner workgroup stops answering for
+ * about 20 ms.  Such a pair must come back with RHEED_PAIR_SYNC (whichever
+ * half gave up) while the call itself succeeds and every workgroup ends
+ * normally.  half = -1 (the default) turns it off.  Host only; no effect on
+ * the other layouts. */
+rheed_status rheed_plan_force_sync_failure(rheed_plan_t plan, int32_t half);
+
 /* host out[n_struct + 1]: complex-element offset of each structure's table;
  * table of structure s is [n_nodes(s)][box(s)], n_nodes = L * nodes_per_slice + 1,
  * box = (2 Hd + 1)(2 Kd + 1), Hd = max h - min h, Kd = max k - min k, entry

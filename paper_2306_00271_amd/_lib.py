@@ -87,6 +87,7 @@ SYMBOLS = {
                            C.POINTER(C.c_int32)], C.c_int),
     "rheed_plan_destroy": ([C.c_void_p], C.c_int),
     "rheed_plan_get_info": ([C.c_void_p, C.POINTER(PlanInfo)], C.c_int),
+    "rheed_plan_force_sync_failure": ([C.c_void_p, C.c_int32], C.c_int),
     "rheed_plan_table_offsets": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
     "rheed_plan_atom_offsets": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
     "rheed_potential": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),

@@ -6,7 +6,10 @@ checks status codes.  Device tensors must live on the current HIP device.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import sys
+import weakref
 from typing import Optional, Sequence
 
 import numpy as np
@@ -44,11 +47,26 @@ def beam_constants(energy_eV: float):
     return g.value, k.value
 
 
+# Plans still open; closed by an exit hook while the HIP runtime is alive, so
+# that no plan's device memory is freed from a finalizer during interpreter
+# teardown.
+_LIVE_PLANS: "weakref.WeakSet[Plan]" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_plans():
+    for plan in list(_LIVE_PLANS):
+        plan.close()
+
+
 class Plan:
     """A set of structures, each with a number of angles (pairs are numbered
     structure-major).  ``structures`` are objects with the attributes
     ``beams`` [N,2] int, ``recip`` [2,2], ``n_slices``, ``thickness``,
-    ``atoms`` [n_atoms,3], ``cell_area``, ``scat_a`` [4], ``scat_b`` [4]."""
+    ``atoms`` [n_atoms,3], ``cell_area``, ``scat_a`` [4], ``scat_b`` [4].
+
+    ``close()`` (or leaving a ``with`` block) releases the plan's device
+    memory; a plan still open at interpreter exit is closed by an exit hook."""
 
     def __init__(self, structures: Sequence, angles_per_struct: Sequence[int], *, energy_eV: float,
                  charge: float, absorption: float, mean_inner_potential: float = 15.0, stepper: str = "rk6",
@@ -85,6 +103,7 @@ class Plan:
         h = C.c_void_p()
         _lib.check(L.rheed_plan_create(C.byref(h), C.byref(opts), n, arr, aps), "plan_create")
         self._h = h
+        _LIVE_PLANS.add(self)
         info = _lib.PlanInfo()
         _lib.check(L.rheed_plan_get_info(h, C.byref(info)), "plan_get_info")
         self.info = info
@@ -98,25 +117,48 @@ class Plan:
         _lib.check(L.rheed_plan_atom_offsets(h, aoffs), "plan_atom_offsets")
         self.atom_offsets = np.array(aoffs[:], dtype=np.int64)
 
-    def __del__(self):
+    def close(self) -> None:
+        """Destroys the plan (rheed_plan_destroy); later calls on it raise."""
         h = getattr(self, "_h", None)
+        self._h = None
+        _LIVE_PLANS.discard(self)
         if h is not None and h.value:
             _lib.lib().rheed_plan_destroy(h)
-            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        # no HIP call once the interpreter is shutting down: the exit hook
+        # has closed every plan by then
+        if not sys.is_finalizing():
+            self.close()
+
+    def force_sync_failure(self, half: int) -> None:
+        """rheed_plan_force_sync_failure: the split layout's failure path, for tests."""
+        _lib.check(_lib.lib().rheed_plan_force_sync_failure(self._handle(), int(half)), "plan_force_sync_failure")
+
+    def _handle(self):
+        if self._h is None:
+            raise ValueError("the plan is closed")
+        return self._h
 
     # ------------------------------------------------------------------
     def potential(self, atoms: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         _dev(atoms, torch.float64, "atoms")
         if out is None:
             out = torch.empty(int(self.info.table_elems), dtype=torch.complex128, device=atoms.device)
-        _lib.check(_lib.lib().rheed_potential(self._h, _ptr(atoms), _ptr(out), _stream()), "potential")
+        _lib.check(_lib.lib().rheed_potential(self._handle(), _ptr(atoms), _ptr(out), _stream()), "potential")
         return out
 
     def potential_backward(self, atoms: torch.Tensor, dL_dU: torch.Tensor) -> torch.Tensor:
         _dev(atoms, torch.float64, "atoms")
         _dev(dL_dU, torch.complex128, "dL_dU")
         out = torch.empty_like(atoms)
-        _lib.check(_lib.lib().rheed_potential_backward(self._h, _ptr(atoms), _ptr(dL_dU), _ptr(out), _stream()),
+        _lib.check(_lib.lib().rheed_potential_backward(self._handle(), _ptr(atoms), _ptr(dL_dU), _ptr(out), _stream()),
                    "potential_backward")
         return out
 
@@ -140,14 +182,14 @@ class Plan:
         nrhst = torch.empty(self.n_pairs, dtype=torch.int32, device=dev) if want_nrhst else None
         ws_bytes = 0 if workspace is None else workspace.numel()
         if y_bottom is None:
-            _lib.check(_lib.lib().rheed_forward(self._h, _ptr(U), _ptr(angles), _ptr(inten), _ptr(rho),
+            _lib.check(_lib.lib().rheed_forward(self._handle(), _ptr(U), _ptr(angles), _ptr(inten), _ptr(rho),
                                                 _ptr(status), _ptr(nrhst), _ptr(workspace), ws_bytes, _stream()),
                        "forward")
         else:
             _dev(y_bottom, torch.complex128, "y_bottom")
             if y_bottom.shape != (self.n_pairs, self.max_beams, self.max_beams):
                 raise ValueError(f"y_bottom must be [{self.n_pairs}, {self.max_beams}, {self.max_beams}]")
-            _lib.check(_lib.lib().rheed_forward_bulk(self._h, _ptr(U), _ptr(angles), _ptr(y_bottom), _ptr(inten),
+            _lib.check(_lib.lib().rheed_forward_bulk(self._handle(), _ptr(U), _ptr(angles), _ptr(y_bottom), _ptr(inten),
                                                      _ptr(rho), _ptr(status), _ptr(nrhst), _ptr(workspace),
                                                      ws_bytes, _stream()), "forward_bulk")
         return {"intensity": inten, "rho": rho, "status": status, "n_rhst": nrhst}
@@ -168,7 +210,7 @@ class Plan:
         status = torch.empty(self.n_pairs, dtype=torch.int32, device=dev)
         nbytes = int(self.info.fwd_workspace + self.info.bulk_workspace)
         ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
-        _lib.check(_lib.lib().rheed_bulk_reflection(self._h, _ptr(U), _ptr(angles), float(tol), int(max_layers),
+        _lib.check(_lib.lib().rheed_bulk_reflection(self._handle(), _ptr(U), _ptr(angles), float(tol), int(max_layers),
                                                     _ptr(y), _ptr(r), _ptr(layers), _ptr(status), _ptr(ws),
                                                     ws.numel(), _stream()), "bulk_reflection")
         return {"y": y, "r": r, "layers": layers, "status": status}
@@ -182,10 +224,10 @@ class Plan:
         inten = torch.empty((self.n_pairs, self.max_beams), dtype=torch.float64, device=dev)
         status = torch.empty(self.n_pairs, dtype=torch.int32, device=dev)
         rep = _lib.TuneReport()
-        _lib.check(_lib.lib().rheed_autotune(self._h, _ptr(U), _ptr(angles), _ptr(inten), _ptr(status), int(reps),
+        _lib.check(_lib.lib().rheed_autotune(self._handle(), _ptr(U), _ptr(angles), _ptr(inten), _ptr(status), int(reps),
                                              _stream(), C.byref(rep)), "autotune")
         info = _lib.PlanInfo()
-        _lib.check(_lib.lib().rheed_plan_get_info(self._h, C.byref(info)), "plan_get_info")
+        _lib.check(_lib.lib().rheed_plan_get_info(self._handle(), C.byref(info)), "plan_get_info")
         self.info = info
         self.split = bool(info.split)
         n = rep.n_candidates
@@ -199,7 +241,7 @@ class Plan:
         _dev(angles, torch.float64, "angles")
         _dev(dL_dI, torch.float64, "dL_dI")
         dU = torch.empty_like(U)
-        _lib.check(_lib.lib().rheed_backward(self._h, _ptr(U), _ptr(angles), _ptr(dL_dI), _ptr(dU),
+        _lib.check(_lib.lib().rheed_backward(self._handle(), _ptr(U), _ptr(angles), _ptr(dL_dI), _ptr(dU),
                                              _ptr(workspace), workspace.numel(), _stream()), "backward")
         return dU
 

@@ -54,6 +54,7 @@ struct rheed_plan_s {
   int* d_bin_jk = nullptr;
   double* d_pbwd = nullptr;  // partial sums of the potential adjoint
   char* d_xch = nullptr;     // exchange blocks of the split layout
+  int xch_give_up = -1;      // rheed_plan_force_sync_failure: the half whose first wait fails at once
   bool split = false;
   int split_max = 0;
   long long g_pair_stride = 0;  // adjoint stage buffer elements per pair
@@ -409,6 +410,12 @@ rheed_status rheed_plan_get_info(rheed_plan_t P, rheed_plan_info* info) {
   return RHEED_OK;
 }
 
+rheed_status rheed_plan_force_sync_failure(rheed_plan_t P, int32_t half) {
+  if (!P || half < -1 || half > 1) return fail(RHEED_E_INVALID, "plan_force_sync_failure: half must be -1, 0 or 1");
+  P->xch_give_up = half;
+  return RHEED_OK;
+}
+
 rheed_status rheed_plan_table_offsets(rheed_plan_t P, int64_t* out) {
   if (!P || !out) return fail(RHEED_E_INVALID, "plan_table_offsets: null argument");
   for (size_t i = 0; i < P->table_off.size(); ++i) out[i] = P->table_off[i];
@@ -486,6 +493,7 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
   a.ld = P->max_beams;
   a.convention = (int)P->opts.convention;
   a.threshold = P->opts.rhst_threshold;
+  a.xch_give_up = P->xch_give_up;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
   if (!P->small_pairs.empty()) {

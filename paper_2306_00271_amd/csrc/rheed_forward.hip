@@ -808,15 +808,22 @@ __device__ __forceinline__ void xch_publish(unsigned long long* cnt, unsigned lo
 
 // Waits until the partner's counter reaches v.  A wait gives up after about
 // XCH_TICKS of the constant-rate clock (far beyond any legitimate skew between
-// the halves) and sets *fail; after that, later waits return at once.
+// the halves) and sets *fail; after that, later waits return at once.  A
+// half that gives up also writes the launch number to its failure word in the
+// exchange block (before any later counter raise, which releases it), so that
+// half 0, which writes the pair's status, reports the pair whichever half
+// lost contact.  give_up (set from the host to test this path) makes the
+// first wait fail without polling.
 constexpr long long XCH_TICKS = 2000000;
-__device__ __forceinline__ void xch_wait(unsigned long long* cnt, unsigned long long v, int* fail) {
+__device__ __forceinline__ void xch_wait(unsigned long long* cnt, unsigned long long v, int* fail,
+                                         unsigned long long* fail_word, unsigned long long epoch, bool give_up) {
   if (threadIdx.x == 0 && !*fail) {
     const long long t0 = wall_clock64();
     int it = 0;
-    while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) {
-      if (++it > XCH_SPIN || wall_clock64() - t0 > XCH_TICKS) {
+    while (give_up || __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) {
+      if (give_up || ++it > XCH_SPIN || wall_clock64() - t0 > XCH_TICKS) {
         *fail = 1;
+        __hip_atomic_store(fail_word, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         break;
       }
       __builtin_amdgcn_s_sleep(2);
@@ -1001,6 +1008,10 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
   // here, half 0 writes it back after its last wait
   unsigned long long* ep_word = reinterpret_cast<unsigned long long*>(X) + 2;
   const unsigned long long epoch = __hip_atomic_load(ep_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1;
+  // failure words of the two halves: the launch number in which the half gave up a wait
+  unsigned long long* fail_me = reinterpret_cast<unsigned long long*>(X) + 3 + half;
+  const unsigned long long* fail_other = reinterpret_cast<unsigned long long*>(X) + 3 + (1 - half);
+  const bool give_up = a.xch_give_up == half;
   unsigned long long ev = epoch << 32;
   int nrhst = 0;
   // this half's [Q; P] columns to the exchange block of event ev
@@ -1067,7 +1078,7 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
     ++ev;
     if (tid < 2 * NP) xput(&xi_g[(half * 2 + (int)(ev & 1)) * 2 * NP + tid], s.xi_loc[tid / NP][tid % NP]);
     xch_publish(cnt_me, ev);
-    xch_wait(cnt_other, ev, &s.sync_fail);
+    xch_wait(cnt_other, ev, &s.sync_fail, fail_me, epoch, give_up);
     bool do_rhst;
     {
       const double* xo = xi_g + ((1 - half) * 2 + (int)(ev & 1)) * 2 * NP;
@@ -1103,7 +1114,7 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
         pme[row * HC + cl] = make_double2(d.r[e], d.i[e]);
       }
       xch_publish(cnt_me, ev);
-      xch_wait(cnt_other, ev, &s.sync_fail);
+      xch_wait(cnt_other, ev, &s.sync_fail, fail_me, epoch, give_up);
       {
         // all of the partner's entries in flight at once, then into LDS
         const double2* theirs = big_g + (long long)((1 - half) * 2 + (int)(ev & 1)) * 2 * NP * HC;
@@ -1164,8 +1175,12 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
   publish_qp();
   xch_publish(cnt_me, ev);
   if (half == 1) return;
-  xch_wait(cnt_other, ev, &s.sync_fail);
-  if (tid == 0) __hip_atomic_store(ep_word, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  xch_wait(cnt_other, ev, &s.sync_fail, fail_me, epoch, give_up);
+  if (tid == 0) {
+    // the partner's failure word of this launch: released by its last counter raise, seen after the wait
+    if (__hip_atomic_load(fail_other, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == epoch) s.sync_fail = 1;
+    __hip_atomic_store(ep_word, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   double2 low[NE];
 #pragma unroll
   for (int e = 0; e < NE; ++e) {

@@ -51,7 +51,7 @@ struct FwdArgs {
   int ld;
   int convention;
   int n_pairs;               // pairs of this launch
-  int pad;
+  int xch_give_up;           // split launches: the half (0, 1) whose first wait fails at once; -1 normally
   double threshold;
   // split launches (two workgroups per pair): per-pair exchange blocks
   char* xch;
@@ -69,8 +69,9 @@ __device__ inline double2 gamma_of(double g2) {
   return g2 >= 0.0 ? make_double2(sqrt(g2), 0.0) : make_double2(0.0, -sqrt(-g2));
 }
 
-// Exchange block of one pair in a split launch (bytes): two 64-bit counters
-// and the launch number, per half and parity the badness partials [2][NP]
+// Exchange block of one pair in a split launch (bytes): two 64-bit counters,
+// the launch number and the two halves' failure words (the launch number in
+// which the half gave up a wait), per half and parity the badness partials [2][NP]
 // doubles, and per half and parity the half's [Q; P] columns, [2][NP][32]
 // complex.
 constexpr long long XCH_XI = 256;

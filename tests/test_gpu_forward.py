@@ -156,3 +156,35 @@ def test_uneven_batch_in_one_launch(layout):
         _report(f"uneven batch {layout} structure {s} N={N} L={p.structures[0].n_slices}", e)
         assert e <= TOL
         assert np.all(res["intensity"][s * A:(s + 1) * A, N:] == 0.0)
+
+
+@pytest.mark.parametrize("half", [0, 1])
+def test_split_layout_reports_a_lost_partner(half):
+    """The split layout's failure path, forced from the host: the first wait
+    of one workgroup of every pair gives up at once (as a wait does when the
+    partner stops answering).  Whichever half gave up, every pair must come
+    back RHEED_PAIR_SYNC from a call that succeeds; with the hook off the
+    same plan is back to oracle parity."""
+    import torch
+    from paper_2306_00271_amd import api
+    wl = small_2d(n_beams=21, n_slices=24, thickness=3.0, n_layers=1, n_angles=4)
+    dev = torch.device("cuda:0")
+    plan = api.plan_for(wl, stepper="rk6", layout="split")
+    assert plan.split
+    U = plan.potential(api.atoms_for(wl, dev))
+    ang = api.angles_for(wl, dev)
+    plan.force_sync_failure(half)
+    out = plan.forward(U, ang)
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    print(f"[sync] forced give-up in half {half}: status {st.tolist()}", flush=True)
+    assert (st == 3).all()
+    plan.force_sync_failure(-1)
+    out = plan.forward(U, ang)
+    torch.cuda.synchronize()
+    assert (out["status"].cpu().numpy() == 0).all()
+    ref, _, _ = oracle_forward(wl, stepper="rk6")
+    e = eacc(out["intensity"].cpu().numpy()[:, :21], ref)
+    _report("split after the forced failure", e)
+    assert e <= TOL
+    plan.close()
