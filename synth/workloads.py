@@ -163,13 +163,27 @@ def _perturbed(base: Structure, seed: int, n_beams: Optional[int] = None, sigma_
     return dataclasses.replace(base, atoms=atoms, beams=beams)
 
 
-def config3(n_structures: int = 1024) -> Workload:
+# Slices of the 40 A slab per beam count in the uneven-N workload.  More beams
+# reach more evanescent rods: the largest |Gamma_j| over the workload's angles
+# is 15.7, 17.7, 19.5 and 21.1 1/A for N = 31, 61, 91, 121, and with h = 0.1 A
+# (400 slices) the sixth-order step is off the physical solution for N >= 91
+# (summed reflected intensities far above 1 under absorption).  Each N takes
+# the smallest multiple of 20 slices, at least 400, with h max|Gamma_j| <= 1.45
+# (a CPU test recomputes these from the oracle's Gamma).
+UNEVEN_SLICES = {31: 440, 61: 500, 91: 540, 121: 600}
+UNEVEN_H_GAMMA = 1.45
+
+
+def config3(n_structures: int = 1024, slices=None) -> Workload:
     """1024 perturbed copies of the N=61 slab with N drawn from
-    {31, 61, 91, 121}; 64 angles each."""
+    {31, 61, 91, 121}; 64 angles each; slices per N from ``slices``
+    (default UNEVEN_SLICES; pass {n: 400} for the uniform 0.1 A grid)."""
     base = _c2_structure()
     rng = np.random.default_rng(1003)
     ns = rng.choice(np.array([31, 61, 91, 121]), size=n_structures)
-    structs = [_perturbed(base, 100000 * 1003 + s, int(ns[s])) for s in range(n_structures)]
+    table = UNEVEN_SLICES if slices is None else slices
+    structs = [dataclasses.replace(_perturbed(base, 100000 * 1003 + s, int(ns[s])), n_slices=table[int(ns[s])])
+               for s in range(n_structures)]
     return Workload("c3-batched-uneven-N", structs, 15_000.0, +1, 0.1,
                     _deg(np.linspace(0.3, 6.0, 64)), 0.0)
 

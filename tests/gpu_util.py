@@ -35,3 +35,16 @@ def eacc(eta, ref):
     num = np.max(np.linalg.norm(eta - ref, axis=1))
     den = np.max(np.linalg.norm(ref, axis=1))
     return num / den
+
+
+def physical(eta, absorption):
+    """Per-angle validity of a rocking curve (Sec. 2.1): finite, every
+    eta_j >= 0, and with absorption (alpha > 0) sum_j eta_j <= 1 + 1e-9, since
+    the reflected flux cannot exceed the incident flux.  A discretisation off
+    the physical solution (a step outside the stepper's accurate range on the
+    most evanescent rods) fails it.  Returns a boolean per angle."""
+    eta = np.atleast_2d(np.asarray(eta, dtype=np.float64))
+    ok = np.all(np.isfinite(eta), axis=1) & np.all(eta >= 0.0, axis=1)
+    if absorption > 0.0:
+        ok &= eta.sum(axis=1) <= 1.0 + 1e-9
+    return ok

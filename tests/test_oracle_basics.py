@@ -305,3 +305,23 @@ def test_transposed_coupling_changes_the_intensities():
     rho_bt, _ = rk.solve_ode_str(m_bt, gam_b, st_b.h, s.n_slices, RK6)
     eta_bt = rk.intensity(rho_bt, gam_b, mask_b, th)
     assert np.allclose(eta_bt[perm], eta, rtol=1e-9, atol=1e-14)
+
+
+def test_uneven_workload_slices_follow_the_step_rule():
+    """The uneven-N workload's slices per N are the smallest multiple of 20
+    (at least 400) with h max_j |Gamma_j| <= 1.45 over its angles, Gamma from
+    the oracle (Sec. 2.1); 400 slices break that bound for N >= 61."""
+    import math
+
+    from synth import workloads as W
+    wl = W.config3(8)
+    gamma = physics.wavenumber(wl.energy_eV)
+    seen = {}
+    for st in wl.structures:
+        kv = physics.beam_vectors(st.beams, st.recip)
+        gmax = max(np.max(np.abs(physics.gamma_diag(gamma, physics.incident_b0(gamma, float(th), wl.theta1), kv)))
+                   for th in wl.theta0)
+        want = max(400, 20 * math.ceil(st.thickness * gmax / (W.UNEVEN_H_GAMMA * 20)))
+        assert st.n_slices == want == W.UNEVEN_SLICES[st.n_beams]
+        seen[st.n_beams] = st.thickness / 400 * gmax
+    assert seen[31] < 1.6 and all(seen[n] > W.UNEVEN_H_GAMMA for n in (61, 91, 121) if n in seen)
