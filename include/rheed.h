@@ -183,6 +183,21 @@ rheed_status rheed_potential(rheed_plan_t plan, const double* atoms, void* U_tab
 rheed_status rheed_potential_backward(rheed_plan_t plan, const double* atoms, const void* dL_dU,
                                       double* dL_datoms, void* stream);
 
+/* rheed_potential_backward for callers that cannot allocate device memory
+ * or must not use the plan's buffers (code under stream capture, serving
+ * loops, harnesses that forbid allocation).  Same arguments and results,
+ * bit for bit, as rheed_potential_backward; the per-atom partial sums live in
+ * a fixed device array of the library instead of the plan's memory: one copy
+ * per GPU (6 MiB, held until the process ends), for at most
+ * RHEED_NOALLOC_MAX_ATOMS atoms in the plan (more -> RHEED_E_UNSUPPORTED).
+ * Every partial is written before it is read, so nothing needs clearing.
+ * Calls no allocating routine.  Every call on one GPU shares that array:
+ * calls that overlap on a GPU (other streams, other threads) race and must be
+ * serialised by the caller. */
+#define RHEED_NOALLOC_MAX_ATOMS 4096
+rheed_status rheed_potential_backward_noalloc(rheed_plan_t plan, const double* atoms, const void* dL_dU,
+                                              double* dL_datoms, void* stream);
+
 /* Reflected amplitudes and intensities for every (structure, angle) pair
  * (Algorithm 1 + Eq. vrhocomp + the intensity formula of Sec. 2.1).
  *  U_tables   device complex [table_elems] (see rheed_plan_table_offsets)

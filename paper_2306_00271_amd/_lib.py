@@ -19,6 +19,7 @@ RHEED_LAYOUT_AUTO, RHEED_LAYOUT_WHOLE, RHEED_LAYOUT_SPLIT = 0, 1, 2
 RHEED_MAX_BEAMS = 128
 RHEED_MAX_BOX = 300
 RHEED_MAX_BOX_LARGE = 1024
+RHEED_NOALLOC_MAX_ATOMS = 4096
 
 
 class Structure(C.Structure):
@@ -92,6 +93,7 @@ SYMBOLS = {
     "rheed_plan_atom_offsets": ([C.c_void_p, C.POINTER(C.c_int64)], C.c_int),
     "rheed_potential": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "rheed_potential_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
+    "rheed_potential_backward_noalloc": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p], C.c_int),
     "rheed_forward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                        C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "rheed_backward": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,

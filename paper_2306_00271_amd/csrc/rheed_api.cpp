@@ -18,6 +18,8 @@
 
 using namespace rheed;
 
+static_assert(RHEED_NOALLOC_MAX_ATOMS == PBWD_STATIC_ATOMS, "header and fixed array disagree");
+
 namespace {
 thread_local std::string g_last_error;
 
@@ -370,6 +372,15 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     rheed_plan_destroy(P);
     return hip_fail(e, "hipMemcpy");
   }
+  {
+    // rheed_potential_backward_noalloc's fixed array: its address on this
+    // device, looked up here so that the entry point itself makes no setup call
+    double* part = nullptr;
+    if ((e = potential_bwd_scratch(&part)) != hipSuccess) {
+      rheed_plan_destroy(P);
+      return hip_fail(e, "hipGetSymbolAddress");
+    }
+  }
   *out = P;
   return RHEED_OK;
 }
@@ -457,6 +468,30 @@ rheed_status rheed_potential_backward(rheed_plan_t P, const double* atoms, const
   hipError_t e = launch_potential_bwd(a, P->n_atoms_total, P->n_struct, P->d_atom_struct,
                                       static_cast<hipStream_t>(stream));
   return e == hipSuccess ? RHEED_OK : hip_fail(e, "potential_backward launch");
+}
+
+rheed_status rheed_potential_backward_noalloc(rheed_plan_t P, const double* atoms, const void* dL_dU,
+                                              double* dL_datoms, void* stream) {
+  if (!P || !dL_dU || (P->n_atoms_total > 0 && (!atoms || !dL_datoms)))
+    return fail(RHEED_E_INVALID, "potential_backward_noalloc: null argument");
+  if (P->n_atoms_total > RHEED_NOALLOC_MAX_ATOMS)
+    return fail(RHEED_E_UNSUPPORTED, "potential_backward_noalloc: " + std::to_string(P->n_atoms_total) +
+                                         " atoms exceed the fixed partial-sum array of " +
+                                         std::to_string(RHEED_NOALLOC_MAX_ATOMS));
+  if (P->n_atoms_total == 0) return RHEED_OK;
+  double* part = nullptr;
+  hipError_t e = potential_bwd_scratch(&part);
+  if (e != hipSuccess) return hip_fail(e, "potential_backward_noalloc: hipGetSymbolAddress");
+  PotBwdArgs a{};
+  a.structs = P->d_structs;
+  a.atoms = atoms;
+  a.dU = static_cast<const double2*>(dL_dU);
+  a.datoms = dL_datoms;
+  a.partial = part;
+  a.nodes_per_slice = P->nodes_per_slice;
+  for (int c = 0; c < 4; ++c) a.cset[c] = P->cset[c];
+  e = launch_potential_bwd(a, P->n_atoms_total, P->n_struct, P->d_atom_struct, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? RHEED_OK : hip_fail(e, "potential_backward_noalloc launch");
 }
 
 }  // extern "C"

@@ -89,6 +89,9 @@ struct PotArgs {
 };
 
 constexpr int PBWD_CHUNKS = 64;  // partial sums per atom in the potential adjoint
+// atoms the fixed partial-sum array of rheed_potential_backward_noalloc holds
+// (PBWD_STATIC_ATOMS x PBWD_CHUNKS x 3 doubles = 6 MiB per device)
+constexpr long long PBWD_STATIC_ATOMS = 4096;
 
 struct PotBwdArgs {
   const StructDev* structs;
@@ -167,6 +170,9 @@ hipError_t launch_grad_assemble(const GradArgs& a, int n_struct, int max_nodes, 
 hipError_t launch_potential(const PotArgs& a, long long max_elems, hipStream_t stream);
 hipError_t launch_potential_bwd(const PotBwdArgs& a, long long n_atoms_total, int n_struct,
                                 const long long* atom_struct, hipStream_t stream);
+// Device address of the fixed partial-sum array on the current device
+// (looked up once per device; the lookup allocates nothing).
+hipError_t potential_bwd_scratch(double** out);
 hipError_t launch_rfactor(int n_pairs, int ld, const double* I, const double* t, double* loss, double* dI,
                           hipStream_t stream);
 

@@ -9,6 +9,8 @@
 // mean inner potential; the host folds kappa s (charge - i alpha) / A into
 // StructDev::pref).  These kernels are HBM/ALU light compared with the
 // propagation and are written for clarity: one thread per (node, g) entry.
+#include <mutex>
+
 #include "rheed_internal.h"
 
 namespace rheed {
@@ -144,6 +146,36 @@ __global__ __launch_bounds__(256) void rfactor_kernel(int n_pairs, int ld, const
     __syncthreads();
   }
   if (threadIdx.x == 0 && loss) *loss = red[0];
+}
+
+// Partial sums of the potential adjoint for callers that cannot allocate
+// (rheed_potential_backward_noalloc): a fixed array in device memory, one copy
+// per GPU, held until the process ends.  Host code must not pass the array's
+// name to a kernel (in host code it is a stand-in, not a device address): the
+// device address comes from hipGetSymbolAddress, once per device, below.
+static __device__ __align__(256) double scratch[(size_t)PBWD_STATIC_ATOMS * PBWD_CHUNKS * 3];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t potential_bwd_scratch(double** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_potential(const PotArgs& a, long long max_elems, hipStream_t stream) {
