@@ -48,3 +48,36 @@ def physical(eta, absorption):
     if absorption > 0.0:
         ok &= eta.sum(axis=1) <= 1.0 + 1e-9
     return ok
+
+
+def _tangent_unit(args):
+    """Worker: the oracle's tangent-linear derivative of the R-factor along
+    one atom coordinate (structure 0)."""
+    from threadpoolctl import threadpool_limits
+    wl, ia, c, target, angle_idx, stepper = args
+    d = np.zeros_like(np.asarray(wl.structures[0].atoms, dtype=np.float64))
+    d[ia, c] = 1.0
+    with threadpool_limits(1):   # one BLAS thread per process
+        return driver.rfactor_directional(wl, 0, d, target, angle_idx=angle_idx, stepper=stepper)[1]
+
+
+def oracle_atom_gradient(wl, target, coords, angle_idx=None, stepper=None, processes=8):
+    """dR/d(atom coordinate) for every (atom, axis) in ``coords``, one
+    tangent-linear pass of the oracle per coordinate, in host processes."""
+    import multiprocessing as mp
+    jobs = [(wl, ia, c, np.asarray(target), angle_idx, stepper) for ia, c in coords]
+    with mp.get_context("spawn").Pool(min(processes, len(jobs))) as pool:
+        return np.array(pool.map(_tangent_unit, jobs))
+
+
+def assert_entrywise(got, ref, rel=1e-8, floor=1e-6, what=""):
+    """Every entry within rel of the reference, relative to the entry itself
+    where it is above floor * max|ref| and to floor * max|ref| below."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    scale = np.maximum(np.abs(ref), floor * np.abs(ref).max())
+    err = np.abs(got - ref) / scale
+    k = int(np.argmax(err))
+    print(f"[adjoint] {what}: {ref.size} entries, worst rel err {err.flat[k]:.3e} at {k} "
+          f"(got {got.flat[k]:.6e}, ref {ref.flat[k]:.6e})", flush=True)
+    assert err.max() <= rel
