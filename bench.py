@@ -120,7 +120,31 @@ def cpu_baseline(stepper, n_angles, n_coords, cores, mode):
     wall = time.perf_counter() - t0
     per_pass = float(sum(times) / len(times))
     per_point = per_pass if kind == "fwd" else n_coords * per_pass
-    return cores / per_point, per_pass, wall
+    # one core alone: the same pass in a single process with nothing beside it
+    with ctx.Pool(1) as pool:
+        alone = float(pool.map(_cpu_worker, [(kind, n_angles // 3, stepper)])[0])
+    per_point_1 = alone if kind == "fwd" else n_coords * alone
+    return cores / per_point, per_pass, wall, 1.0 / per_point_1, alone
+
+
+def cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 # ------------------------------------------------------------- HBM traffic
@@ -363,8 +387,10 @@ def stepper_comparison(steps=2):
     (max over angles of the 2-norm error of the intensities over the largest
     2-norm of the reference) against RK6 at 1600 slices (h = 0.025 A), and
     the mean time of one forward call.  RK steppers run on the N <= 64
-    kernels (split layout at 128 pairs), the splitting stepper on the kernel
-    that keeps a pair's state in plan-owned memory."""
+    kernels (split layout at 128 pairs), the splitting steppers (BAB and ABA
+    forms of the fourth- and sixth-order compositions) on the one-workgroup
+    kernel.  The reference is RK6 at 3200 slices; eacc below ~1e-9 is the
+    reference's own distance from convergence."""
     import dataclasses
     import numpy as np
     import torch
@@ -392,16 +418,18 @@ def stepper_comparison(steps=2):
         torch.cuda.synchronize()
         return out["intensity"].cpu().numpy()[:, :61], e0.elapsed_time(e1) / reps, int((out["status"] != 0).sum())
 
-    ref, _, _ = run("rk6", 1600, 1)
+    ref, _, _ = run("rk6", 3200, 1)
     den = float(np.max(np.linalg.norm(ref, axis=1)))
     rows = []
-    for stepper, Ls in (("rk4", (800, 1600, 3200)), ("rk6", (200, 400, 800)), ("sp4", (400, 800, 1600, 3200))):
+    for stepper, Ls in (("rk4", (800, 1600, 3200)), ("rk6", (400, 800, 1600)),
+                        ("sp4", (400, 800, 1600, 3200)), ("sp4a", (400, 800, 1600, 3200)),
+                        ("sp6", (400, 800, 1600)), ("sp6a", (400, 800, 1600))):
         for L in Ls:
             eta, ms, bad = run(stepper, L, steps)
             e = float(np.max(np.linalg.norm(eta - ref, axis=1))) / den
             rows.append({"stepper": stepper, "slices": L, "h": round(40.0 / L, 5), "eacc": float(f"{e:.3e}"),
                          "ms": round(ms, 3), "bad_pairs": bad})
-    return {"workload": "N=61 slab, 128 angles, forward", "reference": "rk6 at 1600 slices", "points": rows}
+    return {"workload": "N=61 slab, 128 angles, forward", "reference": "rk6 at 3200 slices", "points": rows}
 
 
 def large_source_hash():
@@ -558,7 +586,7 @@ def main():
     if not args.no_cpu:
         cores = min(16, os.cpu_count() or 1)
         n_coords = 3 * len(wl.structures[0].grad_atoms)
-        rate, per_pass, cwall = cpu_baseline(stepper, len(wl.theta0), n_coords, cores, args.mode)
+        rate, per_pass, cwall, rate1, alone = cpu_baseline(stepper, len(wl.theta0), n_coords, cores, args.mode)
         if do_adj:
             sample = (f"{2 * cores} (structure, angle) pairs of this workload, two per process at different angles, "
                       f"each one tangent-linear pass of the oracle (forward plus the derivative along one atom "
@@ -569,7 +597,9 @@ def main():
             sample = (f"{2 * cores} (structure, angle) pairs of this workload, two per process at different angles, "
                       f"oracle forward, mean {per_pass:.2f} s per pair; {cores} processes x 1 BLAS thread, "
                       f"{cwall:.1f} s wall")
-        cpu = {"value": round(rate, 5), "unit": "points/s", "cores": cores, "kind": "oracle", "sample": sample}
+        cpu = {"value": round(rate, 5), "unit": "points/s", "cores": cores, "kind": "oracle", "sample": sample,
+               "value_1core": round(rate1, 6), "sample_1core": f"one pass alone in one process: {alone:.2f} s",
+               "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count()}
 
     variants = None
     if do_adj and every != 1:

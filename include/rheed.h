@@ -51,20 +51,36 @@ enum {
   RHEED_PAIR_OK = 0,
   RHEED_PAIR_SINGULAR = 1,  /* an exactly zero pivot in a right division */
   RHEED_PAIR_NONFINITE = 2, /* Inf/NaN reached the reflected amplitudes */
-  RHEED_PAIR_SYNC = 3       /* split launch: the two workgroups of the pair lost contact */
+  RHEED_PAIR_SYNC = 3,      /* split launch: the two workgroups of the pair lost contact */
+  RHEED_PAIR_BREAKDOWN = 4  /* the final solve (Gamma Q - iP) x = e_1 is numerically singular:
+                               ||B||_inf ||x||_inf > 1e14 (a lower bound of its condition number),
+                               as when the state's columns have collapsed onto one mode */
 };
 
 /* Steppers (Sec. 3.4): the explicit RK tableaux (classical 4th order, 4
- * stages; Butcher's 6th-order 7-stage method) and a splitting ("BAB")
- * method of 4th order: the triple jump of the Stormer-Verlet step (drift
- * weights g1, 1 - 2 g1, g1 with g1 = 1 / (2 - 2^(1/3)); kicks at the slice
- * positions 0, g1, 1 - g1 and 1 with weights g1/2, 1/2 - g1/2, 1/2 - g1/2,
- * g1/2, each kick using the potential at the position reached before its
- * drift).  Node tables of SP4 sit at (i + c) h for c = 0, g1, 1 - g1 (three
- * per slice, two of them outside the slice).  SP4 runs forward only (no
- * state saving, no rheed_backward), every structure on the kernel that keeps
- * a pair's state in plan-owned memory (the WHOLE layout). */
-typedef enum { RHEED_RK4 = 0, RHEED_RK6 = 1, RHEED_SP4 = 2 } rheed_stepper;
+ * stages; Butcher's 6th-order 7-stage method) and splitting methods, which
+ * alternate kicks c' -= h b (U(tau) + Gamma^2) c and drifts c += h a c'.
+ * The splitting methods are compositions of Stormer-Verlet steps of lengths
+ * alpha_k: fourth order, the triple jump g1, 1 - 2 g1, g1 with
+ * g1 = 1 / (2 - 2^(1/3)); sixth order, the triple jump of that step with
+ * w1 = 1 / (2 - 2^(1/5)), w0 = 1 - 2 w1 (nine steps w_i g_j).  In the BAB
+ * form (RHEED_SP4, RHEED_SP6) the drifts are alpha_k and the kicks their half
+ * sums, with the first kick at the slice start and the last at its end; in
+ * the ABA form (RHEED_SP4_ABA, RHEED_SP6_ABA) the kicks are alpha_k, the
+ * drifts their half sums.  Each kick uses the potential at the position the
+ * drifts before it have reached; the node tables of a splitting stepper sit
+ * at those positions (3 per slice for the fourth-order methods, 9 for the
+ * sixth-order ones; positions may lie outside the slice).  Splitting
+ * steppers run forward only (no state saving, no rheed_backward, no bulk
+ * start), on the one-workgroup layout; for N > 64 only RHEED_SP4. */
+typedef enum {
+  RHEED_RK4 = 0,
+  RHEED_RK6 = 1,
+  RHEED_SP4 = 2,
+  RHEED_SP6 = 3,
+  RHEED_SP4_ABA = 4,
+  RHEED_SP6_ABA = 5
+} rheed_stepper;
 
 /* Intensity normalisation (Sec. 2.1): FLUX = |rho_j|^2 Gamma_0/Gamma_j on
  * open beams; PAPER = the printed formula, FLUX times sin(theta0). */
@@ -125,7 +141,7 @@ typedef struct {
   int32_t n_pairs;           /* sum of angles_per_struct; pair p of structure s is
                                 numbered structure-major: pairs of s are contiguous */
   int32_t max_beams;         /* Nmax over structures: leading dimension of outputs */
-  int32_t nodes_per_slice;   /* distinct RK nodes in [0, 1): 2 for RK4, 4 for RK6 */
+  int32_t nodes_per_slice;   /* node tables per slice: 2 for RK4, 4 for RK6, 3 or 9 for the splitting steppers */
   int64_t table_elems;       /* complex elements of all potential tables */
   int64_t n_atoms_total;
   size_t fwd_workspace;      /* bytes rheed_forward needs to keep states for rheed_backward */
@@ -170,7 +186,9 @@ rheed_status rheed_plan_atom_offsets(rheed_plan_t plan, int64_t* out);
 /* Potential tables on the slice nodes from atom positions (Sec. 2.1).
  * atoms: device [n_atoms_total][3] (x, y, z) in A.  U_tables: device complex
  * [table_elems].  Node n of a structure sits at z = -D + (i + c) h with
- * n = i * nodes_per_slice + m and c the m-th distinct RK node in [0,1), plus
+ * n = i * nodes_per_slice + m and c the m-th node position of the stepper (the
+ * distinct RK nodes in [0, 1); for a splitting stepper its kick positions in
+ * the order the kicks use them, the slice end excluded), plus
  * the final node at z = 0. */
 rheed_status rheed_potential(rheed_plan_t plan, const double* atoms, void* U_tables, void* stream);
 

@@ -1,4 +1,4 @@
-"""Splitting ("BAB") steppers for the proposed method (oracle; test infrastructure).
+"""Splitting steppers (BAB and ABA forms) for the proposed method (oracle; test infrastructure).
 
 Paper: Sec. 3.4, the splitting methods.  For y = (c, c'), c'' = -M(z) c with
 M = U + Gamma^2, an s-step BAB method alternates kicks of c' and drifts of c:
@@ -20,8 +20,15 @@ The paper's sp4 and sp6 coefficients (from a reference it cites) are not
 printed; the composition here is the fourth-order triple jump of the
 Stormer-Verlet step (drift weights g1, g2, g1 with 2 g1 + g2 = 1 and
 2 g1^3 + g2^3 = 0, i.e. g1 = 1 / (2 - 2^(1/3))), whose kick weights are the
-half sums of neighbouring drift weights.  Pins: the observed order under
-step halving and exact flux conservation (tests/test_oracle_splitting.py).
+half sums of neighbouring drift weights.  A sixth-order method follows by
+the same construction one level up: the triple jump of that fourth-order
+step, with weights w1, w0, w1, 2 w1 + w0 = 1 and 2 w1^5 + w0^5 = 0, i.e.
+w1 = 1 / (2 - 2^(1/5)) (nine Stormer-Verlet steps of lengths w_i g_j).  The
+ABA form exchanges the roles: a slice starts and ends with a drift and the
+kicks sit in between (drift weights the half sums of neighbouring kick
+weights); its kick r uses U at the position reached by the drifts before it.
+Pins: the observed order under step halving and exact flux conservation
+(tests/test_oracle_splitting.py).
 """
 from __future__ import annotations
 
@@ -75,15 +82,91 @@ class Composition:
         return np.vstack([c, q])
 
 
+class CompositionABA:
+    """An ABA splitting method: drift weights a (s + 1), kick weights b (s).
+
+    A slice is c <- c + h a_0 c', then for r = 1 .. s: c' <- c' - h b_r
+    M(tau_r) c, c <- c + h a_r c' with tau_r = z_i + h (a_0 + .. + a_{r-1}).
+    ``cset`` lists the distinct kick positions in the order the kicks use
+    them; none is at a slice boundary."""
+
+    def __init__(self, name, a, b, order):
+        self.name = name
+        self.a = np.asarray(a, dtype=np.float64)
+        self.b = np.asarray(b, dtype=np.float64)
+        assert self.a.size == self.b.size + 1
+        self.order = order
+        self.stages = self.b.size
+        self.tau = np.cumsum(self.a)[:-1]
+        self.cset = []
+        self._slot = []
+        for t in self.tau:
+            if not any(abs(t - c) < 1e-14 for c in self.cset):
+                self.cset.append(float(t))
+            self._slot.append(next(m for m, c in enumerate(self.cset) if abs(t - c) < 1e-14))
+
+    def node_index(self, slice_i: int, r: int) -> int:
+        return slice_i * len(self.cset) + self._slot[r]
+
+    def n_nodes(self, n_slices: int) -> int:
+        return n_slices * len(self.cset) + 1
+
+    def step(self, Z: np.ndarray, Ms, h: float) -> np.ndarray:
+        """One slice on every column of Z = [c; c']; Ms[r] = M(tau_r)."""
+        n = Z.shape[0] // 2
+        c = Z[:n].copy()
+        q = Z[n:].copy()
+        c = c + h * self.a[0] * q
+        for r in range(self.b.size):
+            q = q - h * self.b[r] * (Ms[r] @ c)
+            c = c + h * self.a[r + 1] * q
+        return np.vstack([c, q])
+
+
+def _half_sums(w):
+    """Weights of the other kind in a composition of symmetric steps of
+    lengths w: w_0 / 2, (w_0 + w_1) / 2, ..., w_last / 2."""
+    w = list(w)
+    return [w[0] / 2] + [(w[k] + w[k + 1]) / 2 for k in range(len(w) - 1)] + [w[-1] / 2]
+
+
+def _triple_jump(p):
+    """Outer weights w1, inner w0 of the triple jump raising order p to p + 2:
+    2 w1 + w0 = 1 and 2 w1^(p+1) + w0^(p+1) = 0."""
+    w1 = 1.0 / (2.0 - 2.0 ** (1.0 / (p + 1)))
+    return w1, 1.0 - 2.0 * w1
+
+
+def _steps4():
+    g1, g2 = _triple_jump(2)
+    return [g1, g2, g1]
+
+
+def _steps6():
+    w1, w0 = _triple_jump(4)
+    return [w * g for w in (w1, w0, w1) for g in _steps4()]
+
+
 def _verlet():
     return Composition("verlet", [1.0], [0.5, 0.5], 2)
 
 
 def _triple_jump4():
-    g1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
-    g2 = 1.0 - 2.0 * g1
-    return Composition("sp4", [g1, g2, g1], [g1 / 2, (g1 + g2) / 2, (g1 + g2) / 2, g1 / 2], 4)
+    st = _steps4()
+    return Composition("sp4", st, _half_sums(st), 4)
+
+
+def _triple_jump6():
+    st = _steps6()
+    return Composition("sp6", st, _half_sums(st), 6)
+
+
+def _aba(name, steps, order):
+    return CompositionABA(name, _half_sums(steps), steps, order)
 
 
 VERLET = _verlet()
 SP4 = _triple_jump4()
+SP6 = _triple_jump6()
+SP4_ABA = _aba("sp4a", _steps4(), 4)
+SP6_ABA = _aba("sp6a", _steps6(), 6)

@@ -72,6 +72,6 @@ RK6 = _butcher6()
 TABLEAUX = {"rk4": RK4, "rk6": RK6}
 
 # the splitting steppers of Sec. 3.4 share the node-table interface
-from .splitting import SP4, VERLET  # noqa: E402
+from .splitting import SP4, SP4_ABA, SP6, SP6_ABA, VERLET  # noqa: E402
 
-TABLEAUX.update({"sp4": SP4, "verlet": VERLET})
+TABLEAUX.update({"sp4": SP4, "sp6": SP6, "sp4a": SP4_ABA, "sp6a": SP6_ABA, "verlet": VERLET})

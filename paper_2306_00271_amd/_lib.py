@@ -13,8 +13,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librheed.so")
 
 RHEED_OK, RHEED_E_INVALID, RHEED_E_HIP, RHEED_E_NOMEM, RHEED_E_UNSUPPORTED = 0, -1, -2, -3, -4
-RHEED_RK4, RHEED_RK6, RHEED_SP4 = 0, 1, 2
+RHEED_RK4, RHEED_RK6, RHEED_SP4, RHEED_SP6, RHEED_SP4_ABA, RHEED_SP6_ABA = 0, 1, 2, 3, 4, 5
 RHEED_INTENSITY_FLUX, RHEED_INTENSITY_PAPER = 0, 1
+RHEED_PAIR_OK, RHEED_PAIR_SINGULAR, RHEED_PAIR_NONFINITE, RHEED_PAIR_SYNC, RHEED_PAIR_BREAKDOWN = 0, 1, 2, 3, 4
 RHEED_LAYOUT_AUTO, RHEED_LAYOUT_WHOLE, RHEED_LAYOUT_SPLIT = 0, 1, 2
 RHEED_MAX_BEAMS = 128
 RHEED_MAX_BOX = 300

@@ -17,7 +17,8 @@ import torch
 
 from . import _lib
 
-STEPPERS = {"rk4": _lib.RHEED_RK4, "rk6": _lib.RHEED_RK6, "sp4": _lib.RHEED_SP4}
+STEPPERS = {"rk4": _lib.RHEED_RK4, "rk6": _lib.RHEED_RK6, "sp4": _lib.RHEED_SP4, "sp6": _lib.RHEED_SP6,
+            "sp4a": _lib.RHEED_SP4_ABA, "sp6a": _lib.RHEED_SP6_ABA}
 CONVENTIONS = {"flux": _lib.RHEED_INTENSITY_FLUX, "paper": _lib.RHEED_INTENSITY_PAPER}
 LAYOUTS = {"auto": _lib.RHEED_LAYOUT_AUTO, "whole": _lib.RHEED_LAYOUT_WHOLE, "split": _lib.RHEED_LAYOUT_SPLIT}
 

@@ -39,8 +39,10 @@ constexpr double kMe = 9.1093837015e-31, kQe = 1.602176634e-19, kHbar = 1.054571
 struct rheed_plan_s {
   rheed_opts opts{};
   int n_struct = 0, n_pairs = 0, max_beams = 0, nodes_per_slice = 0;
-  double cset[4] = {0, 0, 0, 0};
-  double sp_a[3] = {0, 0, 0}, sp_b[4] = {0, 0, 0, 0};  // splitting stepper weights
+  double cset[12] = {};
+  double sp_a[3] = {0, 0, 0}, sp_b[4] = {0, 0, 0, 0};  // SP4 weights of the N > 64 kernel
+  bool splitting = false;    // a splitting stepper (Sec. 3.4)
+  SplitSteps sp{};           // its steps on the one-workgroup kernel (N <= 64)
   long long table_elems = 0, n_atoms_total = 0, max_table = 0;
   std::vector<StructDev> hs;
   std::vector<int> beams, pair_struct;
@@ -116,10 +118,10 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
   if (!out || !opts || !structs || !angles_per_struct || n_struct < 1)
     return fail(RHEED_E_INVALID, "plan_create: null argument or n_struct < 1");
   *out = nullptr;
-  if (opts->stepper != RHEED_RK4 && opts->stepper != RHEED_RK6 && opts->stepper != RHEED_SP4)
-    return fail(RHEED_E_INVALID, "unknown stepper");
-  if (opts->stepper == RHEED_SP4 && opts->layout == RHEED_LAYOUT_SPLIT)
-    return fail(RHEED_E_UNSUPPORTED, "the splitting stepper runs on the one-workgroup-per-pair kernel only");
+  if (opts->stepper < RHEED_RK4 || opts->stepper > RHEED_SP6_ABA) return fail(RHEED_E_INVALID, "unknown stepper");
+  const bool splitting = opts->stepper >= RHEED_SP4;
+  if (splitting && opts->layout == RHEED_LAYOUT_SPLIT)
+    return fail(RHEED_E_UNSUPPORTED, "the splitting steppers run on the one-workgroup-per-pair kernels only");
   if (!(opts->rhst_threshold >= 1.0)) return fail(RHEED_E_INVALID, "rhst_threshold must be >= 1");
   if (opts->checkpoint_every < 1) return fail(RHEED_E_INVALID, "checkpoint_every must be >= 1");
   if (opts->convention != RHEED_INTENSITY_FLUX && opts->convention != RHEED_INTENSITY_PAPER)
@@ -140,23 +142,65 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     P->cset[2] = 0.5;
     P->cset[3] = 2.0 / 3.0;
   } else {
-    // triple jump of the Stormer-Verlet step: drifts g1, g2, g1 with
-    // 2 g1 + g2 = 1 and 2 g1^3 + g2^3 = 0; kicks at 0, g1, g1 + g2 and 1
-    const double g1 = 1.0 / (2.0 - std::cbrt(2.0)), g2 = 1.0 - 2.0 * g1;
-    P->sp_a[0] = g1;
-    P->sp_a[1] = g2;
-    P->sp_a[2] = g1;
-    P->sp_b[0] = 0.5 * g1;
-    P->sp_b[1] = 0.5 * (g1 + g2);
-    P->sp_b[2] = 0.5 * (g1 + g2);
-    P->sp_b[3] = 0.5 * g1;
-    P->nodes_per_slice = 3;
-    P->cset[0] = 0.0;
-    P->cset[1] = g1;
-    P->cset[2] = g1 + g2;
+    // Splitting methods: compositions of Stormer-Verlet steps of lengths
+    // alpha_k (sum 1).  Fourth order: the triple jump g1, g2, g1 with
+    // 2 g1 + g2 = 1, 2 g1^3 + g2^3 = 0; sixth order: the triple jump of
+    // that step, w1, w0, w1 with 2 w1 + w0 = 1, 2 w1^5 + w0^5 = 0, so nine
+    // steps w_i g_j.  BAB: drifts alpha_k, kicks their half sums (first and
+    // last alpha / 2); ABA: kicks alpha_k, drifts the half sums.
+    const double g1 = 1.0 / (2.0 - std::pow(2.0, 1.0 / 3.0)), g2 = 1.0 - 2.0 * g1;
+    std::vector<double> steps = {g1, g2, g1};
+    if (opts->stepper == RHEED_SP6 || opts->stepper == RHEED_SP6_ABA) {
+      const double w1 = 1.0 / (2.0 - std::pow(2.0, 1.0 / 5.0)), w0 = 1.0 - 2.0 * w1;
+      std::vector<double> s6;
+      for (double w : {w1, w0, w1})
+        for (double g : {g1, g2, g1}) s6.push_back(w * g);
+      steps = s6;
+    }
+    std::vector<double> half;
+    half.push_back(steps.front() / 2);
+    for (size_t k = 0; k + 1 < steps.size(); ++k) half.push_back((steps[k] + steps[k + 1]) / 2);
+    half.push_back(steps.back() / 2);
+    const bool aba = opts->stepper == RHEED_SP4_ABA || opts->stepper == RHEED_SP6_ABA;
+    const std::vector<double>& da = aba ? half : steps;   // drift weights
+    const std::vector<double>& kb = aba ? steps : half;   // kick weights
+    SplitSteps& sp = P->sp;
+    sp.form = aba ? 1 : 0;
+    sp.kicks = (int)kb.size();
+    for (size_t k = 0; k < da.size(); ++k) sp.a[k] = da[k];
+    for (size_t k = 0; k < kb.size(); ++k) sp.b[k] = kb[k];
+    // kick positions (in units of h from the slice start) in the order the
+    // kicks use them; the distinct ones other than the slice end are the
+    // slice's nodes, the slice end is the next slice's first node
+    std::vector<double> pos;
+    if (aba) {
+      double t = 0.0;
+      for (int r = 0; r < sp.kicks; ++r) pos.push_back(t += da[r]);
+    } else {
+      double t = 0.0;
+      pos.push_back(0.0);
+      for (size_t r = 0; r < da.size(); ++r) pos.push_back(t += da[r]);
+    }
+    int nps = 0;
+    for (int r = 0; r < sp.kicks; ++r) {
+      if (!aba && std::fabs(pos[r] - 1.0) < 1e-14) {
+        sp.node[r] = -1;  // the slice end
+        continue;
+      }
+      int m = 0;
+      while (m < nps && !(std::fabs(pos[r] - P->cset[m]) < 1e-14)) ++m;
+      if (m == nps) P->cset[nps++] = pos[r];
+      sp.node[r] = m;
+    }
+    for (int r = 0; r < sp.kicks; ++r)
+      if (sp.node[r] < 0) sp.node[r] = nps;
+    sp.nps = nps;
+    P->nodes_per_slice = nps;
+    P->splitting = true;
+    // the kernel for N > 64 runs the fourth-order BAB method with these weights
+    for (int q = 0; q < 3; ++q) P->sp_a[q] = steps.size() == 3 ? steps[q] : 0.0;
+    for (int q = 0; q < 4; ++q) P->sp_b[q] = half.size() == 4 ? half[q] : 0.0;
   }
-  // the splitting stepper runs every structure on the kernel for N > 64
-  const bool all_large = opts->stepper == RHEED_SP4;
   int max_l = 0;
   for (int s = 0; s < n_struct; ++s) {
     const rheed_structure& st = structs[s];
@@ -165,6 +209,11 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       snprintf(buf, sizeof buf, "structure %d: n_beams must be in [1, %d]", s, RHEED_MAX_BEAMS);
       delete P;
       return fail(RHEED_E_UNSUPPORTED, buf);
+    }
+    if (splitting && st.n_beams > NP && opts->stepper != RHEED_SP4) {
+      delete P;
+      return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) +
+                                           ": for N > 64 the only splitting stepper is RHEED_SP4");
     }
     if (st.beam_hk[0] != 0 || st.beam_hk[1] != 0) {
       delete P;
@@ -194,7 +243,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     d.hd = hmax - hmin;
     d.kd = kmax - kmin;
     d.box = (2 * d.hd + 1) * (2 * d.kd + 1);
-    const int box_max = (st.n_beams <= NP && !all_large) ? MAXBOX : MAXBOXL;
+    const int box_max = (st.n_beams <= NP) ? MAXBOX : MAXBOXL;
     if (d.box > box_max) {
       delete P;
       return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) + ": rod-difference table row of " +
@@ -207,7 +256,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     {
       const int W = 2 * d.kd + 1;
       std::vector<std::vector<int>> lists(d.box);
-      for (int j = 0; j < ((st.n_beams <= NP && !all_large) ? st.n_beams : 0); ++j)
+      for (int j = 0; j < ((st.n_beams <= NP) ? st.n_beams : 0); ++j)
         for (int k = 0; k < st.n_beams; ++k) {
           const int dh = st.beam_hk[2 * j] - st.beam_hk[2 * k], dk = st.beam_hk[2 * j + 1] - st.beam_hk[2 * k + 1];
           lists[(dh + d.hd) * W + (dk + d.kd)].push_back(j * NP + k);
@@ -265,7 +314,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     P->max_nodes = std::max(P->max_nodes, d.n_nodes);
     P->n_atoms_total += d.n_atoms;
     for (int a = 0; a < angles_per_struct[s]; ++a) {
-      ((st.n_beams <= NP && !all_large) ? P->small_pairs : P->large_pairs).push_back(P->n_pairs + a);
+      ((st.n_beams <= NP) ? P->small_pairs : P->large_pairs).push_back(P->n_pairs + a);
       P->pair_struct.push_back(s);
     }
     P->n_pairs += angles_per_struct[s];
@@ -305,8 +354,8 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     };
     std::stable_sort(P->large_pairs.begin(), P->large_pairs.end(), [&](int x, int y) { return cost(x) > cost(y); });
   }
-  // the adjoint and its state saving handle N <= 64 only
-  if (!P->large_pairs.empty()) {
+  // the adjoint and its state saving handle N <= 64 and the RK steppers only
+  if (!P->large_pairs.empty() || P->splitting) {
     P->fwd_ws = 0;
     P->bwd_ws = 0;
   }
@@ -317,7 +366,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     int dev = 0;
     const bool have_dev = hipGetDevice(&dev) == hipSuccess;
     P->split_max = have_dev ? forward_split_max_pairs(dev) : 0;
-    P->split = opts->layout != RHEED_LAYOUT_WHOLE && n_small > 0 && n_small <= P->split_max;
+    P->split = opts->layout != RHEED_LAYOUT_WHOLE && !P->splitting && n_small > 0 && n_small <= P->split_max;
     if (n_large > 0) {
       const int slots = have_dev ? forward_large_slots(dev) : 0;
       if (slots < 1) {
@@ -447,7 +496,7 @@ rheed_status rheed_potential(rheed_plan_t P, const double* atoms, void* U_tables
   a.U = static_cast<double2*>(U_tables);
   a.n_struct = P->n_struct;
   a.nodes_per_slice = P->nodes_per_slice;
-  for (int c = 0; c < 4; ++c) a.cset[c] = P->cset[c];
+  for (int c = 0; c < 12; ++c) a.cset[c] = P->cset[c];
   hipError_t e = launch_potential(a, P->max_table, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? RHEED_OK : hip_fail(e, "potential launch");
 }
@@ -464,7 +513,7 @@ rheed_status rheed_potential_backward(rheed_plan_t P, const double* atoms, const
   a.datoms = dL_datoms;
   a.partial = P->d_pbwd;
   a.nodes_per_slice = P->nodes_per_slice;
-  for (int c = 0; c < 4; ++c) a.cset[c] = P->cset[c];
+  for (int c = 0; c < 12; ++c) a.cset[c] = P->cset[c];
   hipError_t e = launch_potential_bwd(a, P->n_atoms_total, P->n_struct, P->d_atom_struct,
                                       static_cast<hipStream_t>(stream));
   return e == hipSuccess ? RHEED_OK : hip_fail(e, "potential_backward launch");
@@ -489,7 +538,7 @@ rheed_status rheed_potential_backward_noalloc(rheed_plan_t P, const double* atom
   a.datoms = dL_datoms;
   a.partial = part;
   a.nodes_per_slice = P->nodes_per_slice;
-  for (int c = 0; c < 4; ++c) a.cset[c] = P->cset[c];
+  for (int c = 0; c < 12; ++c) a.cset[c] = P->cset[c];
   e = launch_potential_bwd(a, P->n_atoms_total, P->n_struct, P->d_atom_struct, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? RHEED_OK : hip_fail(e, "potential_backward_noalloc launch");
 }
@@ -505,8 +554,10 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
                           int32_t* pair_status, int32_t* n_rhst, void* workspace, size_t ws_bytes, void* stream,
                           const void* y_bottom, const int* skip, bool final_only = false) {
   if (!P || !U_tables || !angles || !intensity || !pair_status) return fail(RHEED_E_INVALID, "forward: null argument");
-  if (workspace && !P->large_pairs.empty())
+  if (workspace && (!P->large_pairs.empty() || P->splitting))
     return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs an RK stepper and every structure to have N <= 64");
+  if (y_bottom && P->splitting)
+    return fail(RHEED_E_UNSUPPORTED, "forward: the bulk start needs an RK stepper");
   if (workspace && ws_bytes < P->fwd_ws)
     return fail(RHEED_E_INVALID, "forward: workspace of " + std::to_string(ws_bytes) + " bytes < " +
                                      std::to_string(P->fwd_ws));
@@ -529,6 +580,7 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
   a.convention = (int)P->opts.convention;
   a.threshold = P->opts.rhst_threshold;
   a.xch_give_up = P->xch_give_up;
+  a.sp = P->sp;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
   if (!P->small_pairs.empty()) {
@@ -573,7 +625,7 @@ rheed_status rheed_forward_bulk(rheed_plan_t P, const void* U_tables, const doub
                                 double* intensity, void* rho, int32_t* pair_status, int32_t* n_rhst, void* workspace,
                                 size_t ws_bytes, void* stream) {
   if (!P || !y_bottom) return fail(RHEED_E_INVALID, "forward_bulk: null argument");
-  if (!P->large_pairs.empty())
+  if (!P->large_pairs.empty() || P->splitting)
     return fail(RHEED_E_UNSUPPORTED, "forward_bulk: needs an RK stepper and every structure to have N <= 64");
   return forward_impl(P, U_tables, angles, intensity, rho, pair_status, n_rhst, workspace, ws_bytes, stream,
                       y_bottom, nullptr);
@@ -586,7 +638,7 @@ rheed_status rheed_bulk_reflection(rheed_plan_t P, const void* U_tables, const d
     return fail(RHEED_E_INVALID, "bulk_reflection: null argument");
   if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(RHEED_E_INVALID, "bulk_reflection: tol must be finite and >= 0");
   if (max_layers < 1) return fail(RHEED_E_INVALID, "bulk_reflection: max_layers must be >= 1");
-  if (!P->large_pairs.empty())
+  if (!P->large_pairs.empty() || P->splitting)
     return fail(RHEED_E_UNSUPPORTED, "bulk_reflection: needs an RK stepper and every structure to have N <= 64");
   const size_t need = P->fwd_ws + bulk_extra(P);
   if (ws_bytes < need)
@@ -708,7 +760,7 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
                             void* dL_dU, void* workspace, size_t ws_bytes, void* stream) {
   if (!P || !U_tables || !angles || !dL_dI || !dL_dU || !workspace)
     return fail(RHEED_E_INVALID, "backward: null argument");
-  if (!P->large_pairs.empty())
+  if (!P->large_pairs.empty() || P->splitting)
     return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs an RK stepper and every structure to have N <= 64");
   if (ws_bytes < P->fwd_ws + P->bwd_ws)
     return fail(RHEED_E_INVALID, "backward: workspace of " + std::to_string(ws_bytes) + " bytes < " +

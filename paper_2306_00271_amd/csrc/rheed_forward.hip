@@ -68,6 +68,11 @@ struct Tab<1> {  // Butcher's 6th order, 7 stages: c = 0, 1/3, 2/3, 1/3, 1/2, 1/
   static constexpr int nodes = 4;  // 0, 1/3, 1/2, 2/3
   static constexpr int slots = 5;
 };
+template <>
+struct Tab<2> {  // a splitting method: its nodes per slice come with the launch (FwdArgs::sp)
+  static constexpr int nodes = 0;
+  static constexpr int slots = 5;
+};
 
 struct Lds {
   double2 xb[2 * NP * NP];   // [c; X]: c block and stage-input buffer; [Q; P] during eliminations
@@ -75,6 +80,7 @@ struct Lds {
   double2 gj_row[2 * NP];    // elimination scratch: pivot rows (two steps in flight)
   int gj_piv[NP];            //   pivot column of every step
   double g2s[NP];            // Gamma_j^2 (real), 0 on padding
+  double bnorm;              // ||Gamma Q - iP||_inf of the reflection solve
   int bhk[NP][2];
   double xo_[4 / NJT][NP];            // per-row sums of |q_ij|, j != i, per column block
   double xdg[4 / NJT][NP];            // per-row |q_ii| partials per column block
@@ -295,7 +301,38 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
   if constexpr (BULK) keep = save && !a.final_only;
   int nrhst = 0;
 
-  load_nodes<T::slots, FT>(s, Us, S.box, 0, 1, tid);
+  if constexpr (STEPPER != 2) load_nodes<T::slots, FT>(s, Us, S.box, 0, 1, tid);
+  // splitting (Sec. 3.4): the slice's node tables sit in ring slots of the
+  // stage-input buffer, which the splitting steps do not otherwise use (the
+  // transformation below overwrites it, so they are loaded every slice)
+  auto load_ring = [&](int n0, int count) {
+    const int total = count * (S.box + 1);
+    for (int e = tid; e < total; e += FT) {
+      const int m = e / (S.box + 1), j = e - m * (S.box + 1);
+      xb[m * (MAXBOX + 1) + j] = j < S.box ? Us[(long long)(n0 + m) * S.box + j] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+  };
+  // kick: c' -= h w (U + Gamma^2) c with the table in ring slot m; c is read
+  // by every wave, so a barrier follows before anything writes it
+  auto kick = [&](int m, double wgt) {
+    stage_gemm<NP>(cb, xb + m * (MAXBOX + 1), gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {
+      d.r[e] -= h * wgt * gr;
+      d.i[e] -= h * wgt * gi;
+    });
+    __syncthreads();
+  };
+  // drift: c += h w c' (each lane its own elements), then a barrier before c is read
+  auto drift = [&](double wgt) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      double2 cv = cb[OWN(e)];
+      cv.x += h * wgt * d.r[e];
+      cv.y += h * wgt * d.i[e];
+      cb[OWN(e)] = cv;
+    }
+    __syncthreads();
+  };
   for (int i = 0; i < L; ++i) {
     // keep the address base from being expanded into loop-invariant registers
     asm volatile("" : "+v"(ob));
@@ -308,9 +345,29 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       }
     }
     const int nb = i * T::nodes;  // node index of c = 0 in this slice
-    load_nodes<T::slots, FT>(s, Us, S.box, nb + 1, nb + T::nodes + 1, tid);
+    if constexpr (STEPPER != 2) load_nodes<T::slots, FT>(s, Us, S.box, nb + 1, nb + T::nodes + 1, tid);
     const double hh = h * h;
-    if constexpr (STEPPER == 0) {
+    if constexpr (STEPPER == 2) {
+      const SplitSteps& sp = a.sp;
+      load_ring(i * sp.nps, sp.nps);
+      if (sp.form == 0) {
+        // BAB; the previous slice's last kick (at this slice's start) is merged
+        // into this slice's first: kicks change c' only, so the badness and
+        // the transformation (a right multiplication) are unaffected
+        kick(sp.node[0], i == 0 ? sp.b[0] : sp.b[0] + sp.b[sp.kicks - 1]);
+        for (int r = 0; r + 1 < sp.kicks; ++r) {
+          drift(sp.a[r]);
+          if (r + 2 < sp.kicks) kick(sp.node[r + 1], sp.b[r + 1]);
+        }
+      } else {
+        // ABA
+        drift(sp.a[0]);
+        for (int r = 0; r < sp.kicks; ++r) {
+          kick(sp.node[r], sp.b[r]);
+          drift(sp.a[r + 1]);
+        }
+      }
+    } else if constexpr (STEPPER == 0) {
       const double2* t0 = s.tb[nb % 3];
       const double2* th = s.tb[(nb + 1) % 3];
       const double2* t1 = s.tb[(nb + 2) % 3];
@@ -521,6 +578,12 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
     }
     __syncthreads();
   }
+  if constexpr (STEPPER == 2) {
+    if (a.sp.form == 0) {  // BAB: the last slice's final kick, at z = 0 (node L nps)
+      load_ring(L * a.sp.nps, 1);
+      kick(0, a.sp.b[a.sp.kicks - 1]);
+    }
+  }
 
   if (save) {
     double2* st = reinterpret_cast<double2*>(pws + (long long)(a.ck.max_ckpt - 1) * a.ck.state_bytes);
@@ -544,11 +607,34 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
     xb[OWN(e)] = make_double2(qr - d.i[e], qi + d.r[e]);
   }
   __syncthreads();
+  // ||Gamma Q - iP||_inf, for the breakdown test below (wave 0: one row per lane)
+  if (w == 0) {
+    double rs = 0.0;
+    if (lane < N)
+      for (int k = 0; k < N; ++k) {
+        const double2 v = cb[lane * NP + k];
+        rs += sqrt(v.x * v.x + v.y * v.y);
+      }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) rs = fmax(rs, __shfl_xor(rs, off, 64));
+    if (lane == 0) s.bnorm = rs;
+  }
   invert_top<false>(N, nullptr);
   if (tid < NP) {
     const int j = tid;
     double eta = 0.0;
     double2 rj = make_double2(0.0, 0.0);
+    // breakdown: ||B||_inf ||B^{-1} e_1||_inf bounds cond_inf(B) from below; past
+    // BREAKDOWN_COND the reflection solve has lost every digit the paper's
+    // assumption (the inverses exist) relies on
+    double xm = 0.0;
+    if (j < N) {
+      const double2 x = cb[j * NP];
+      xm = sqrt(x.x * x.x + x.y * x.y);
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) xm = fmax(xm, __shfl_xor(xm, off, 64));
+    const bool brk = !(s.bnorm * xm <= BREAKDOWN_COND);
     if (j < N) {
       for (int k = 0; k < N; ++k) {
         const double2 l = xb[j * NP + k], x = cb[k * NP];
@@ -562,6 +648,16 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
         if (a.convention == 1) eta *= sin(th0);
       }
     }
+    const bool fin = isfinite(rj.x) && isfinite(rj.y);
+    const unsigned long long bad = __ballot(!fin);
+    int st = 0;
+    if (s.flag_singular) st = 1;
+    else if (bad) st = 2;
+    else if (brk) st = 4;
+    if (st != 0 && j < N) {  // a failed pair's outputs are NaN
+      eta = NAN;
+      rj = make_double2(NAN, NAN);
+    }
     if (j < a.ld) {
       a.intensity[(long long)p * a.ld + j] = eta;
       if (a.rho) a.rho[(long long)p * a.ld + j] = rj;
@@ -570,12 +666,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       a.intensity[(long long)p * a.ld + jt] = 0.0;
       if (a.rho) a.rho[(long long)p * a.ld + jt] = make_double2(0.0, 0.0);
     }
-    const bool fin = isfinite(rj.x) && isfinite(rj.y);
-    const unsigned long long bad = __ballot(!fin);
     if (j == 0) {
-      int st = 0;
-      if (s.flag_singular) st = 1;
-      else if (bad) st = 2;
       a.status[p] = st;
       if (a.nrhst) a.nrhst[p] = nrhst;
     }
@@ -768,6 +859,7 @@ struct SplitLds {
   double2 gj_row[2 * NP];
   int gj_piv[NP];
   double g2s[NP];
+  double bnorm;              // ||Gamma Q - iP||_inf of the reflection solve
   int bhk[NP][2];
   double xi_loc[2][NP];      // this half's |q_rr| and sum_{j != r} |q_rj| per row
   int flag_singular;
@@ -1211,11 +1303,31 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
     }
   }
   __syncthreads();
+  // ||Gamma Q - iP||_inf for the breakdown test (as in forward_kernel)
+  if (w == 0) {
+    double rs = 0.0;
+    if (lane < N)
+      for (int k = 0; k < N; ++k) {
+        const double2 v = s.ext[lane * NP + k];
+        rs += sqrt(v.x * v.x + v.y * v.y);
+      }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) rs = fmax(rs, __shfl_xor(rs, off, 64));
+    if (lane == 0) s.bnorm = rs;
+  }
   invert_split(N, nullptr, 0);
   if (tid < NP) {
     const int j = tid;
     double eta = 0.0;
     double2 rj = make_double2(0.0, 0.0);
+    double xm = 0.0;
+    if (j < N) {
+      const double2 x = s.ext[j * NP];
+      xm = sqrt(x.x * x.x + x.y * x.y);
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) xm = fmax(xm, __shfl_xor(xm, off, 64));
+    const bool brk = !(s.bnorm * xm <= BREAKDOWN_COND);
     if (j < N) {
       for (int k = 0; k < N; ++k) {
         const double2 l = s.cx[j * NP + k], x = s.ext[k * NP];
@@ -1229,6 +1341,17 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
         if (a.convention == 1) eta *= sin(th0);
       }
     }
+    const bool fin = isfinite(rj.x) && isfinite(rj.y);
+    const unsigned long long bad = __ballot(!fin);
+    int stv = 0;
+    if (s.sync_fail) stv = 3;
+    else if (s.flag_singular) stv = 1;
+    else if (bad) stv = 2;
+    else if (brk) stv = 4;
+    if (stv != 0 && j < N) {  // a failed pair's outputs are NaN
+      eta = NAN;
+      rj = make_double2(NAN, NAN);
+    }
     if (j < a.ld) {
       a.intensity[(long long)p * a.ld + j] = eta;
       if (a.rho) a.rho[(long long)p * a.ld + j] = rj;
@@ -1237,13 +1360,7 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
       a.intensity[(long long)p * a.ld + jt] = 0.0;
       if (a.rho) a.rho[(long long)p * a.ld + jt] = make_double2(0.0, 0.0);
     }
-    const bool fin = isfinite(rj.x) && isfinite(rj.y);
-    const unsigned long long bad = __ballot(!fin);
     if (j == 0) {
-      int stv = 0;
-      if (s.sync_fail) stv = 3;
-      else if (s.flag_singular) stv = 1;
-      else if (bad) stv = 2;
       a.status[p] = stv;
       if (a.nrhst) a.nrhst[p] = nrhst;
     }
@@ -1253,7 +1370,9 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
 hipError_t launch_forward(int stepper, const FwdArgs& a, hipStream_t stream) {
   dim3 grid(a.n_pairs), block(FT);
   const bool bulk = a.y_bottom != nullptr;
-  if (stepper == 0) {
+  if (stepper >= 2) {  // every splitting method; vacuum start only
+    hipLaunchKernelGGL((forward_kernel<2, false>), grid, block, 0, stream, a);
+  } else if (stepper == 0) {
     if (bulk)
       hipLaunchKernelGGL((forward_kernel<0, true>), grid, block, 0, stream, a);
     else

@@ -107,6 +107,8 @@ struct LLds {
   int pos[NL];                     // pivot step of every column in the last elimination
   unsigned gix[LQ / 2][LT];        // per thread: packed table indices of its A operand entries
   double2 xv[NL];                  // first column of the inverse in the reflection
+  unsigned long long bnorm_bits;   // ||Gamma Q - iP||_inf and ||x||_inf of the reflection (bit patterns of
+  unsigned long long xnorm_bits;   //   non-negative doubles, so an integer maximum orders them)
   int flag_singular;
   int bad;
 };
@@ -784,6 +786,10 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
     s.xv[lane] = v0;
     s.xv[64 + lane] = v1;
   }
+  if (tid == 0) {
+    s.bnorm_bits = 0;
+    s.xnorm_bits = 0;
+  }
   __syncthreads();
   if (tid < a.ld) {
     const int j = tid;
@@ -792,24 +798,40 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
     if (j < N) {
       const double g2v = s.g2s[j];
       const double g_r = g2v >= 0.0 ? sqrt(g2v) : 0.0, g_i = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
+      double rs = 0.0;  // row j of Gamma Q - iP, for the breakdown test
       for (int k = 0; k < N; ++k) {
         const double2 cv = gld(&cg[j * NL + k]), pv = gld(&dg[j * NL + k]), x = s.xv[k];
         const double lr = g_r * cv.x - g_i * cv.y - pv.y, li = g_r * cv.y + g_i * cv.x + pv.x;
         rj.x += lr * x.x - li * x.y;
         rj.y += lr * x.y + li * x.x;
+        const double br = g_r * cv.x - g_i * cv.y + pv.y, bi = g_r * cv.y + g_i * cv.x - pv.x;
+        rs += sqrt(br * br + bi * bi);
       }
       if (g2v > 0.0) {
         eta = (rj.x * rj.x + rj.y * rj.y) * sqrt(s.g2s[0]) / sqrt(g2v);
         if (a.convention == 1) eta *= sin(th0);
       }
       if (!(isfinite(rj.x) && isfinite(rj.y))) atomicOr(&s.bad, 1);
+      const double2 xj = s.xv[j];
+      const double xm = sqrt(xj.x * xj.x + xj.y * xj.y);
+      // NaN would not order: it is caught by the finiteness test
+      if (rs == rs) atomicMax(&s.bnorm_bits, (unsigned long long)__double_as_longlong(rs));
+      if (xm == xm) atomicMax(&s.xnorm_bits, (unsigned long long)__double_as_longlong(xm));
     }
     a.intensity[(long long)p * a.ld + j] = eta;
     if (a.rho) a.rho[(long long)p * a.ld + j] = rj;
   }
   __syncthreads();
+  // breakdown: ||B||_inf ||B^{-1} e_1||_inf bounds cond_inf(B) from below (as in forward_kernel)
+  const bool brk = !(__longlong_as_double((long long)s.bnorm_bits) * __longlong_as_double((long long)s.xnorm_bits) <=
+                     BREAKDOWN_COND);
+  const int stv = s.flag_singular ? 1 : s.bad ? 2 : brk ? 4 : 0;
+  if (stv != 0 && tid < N) {  // a failed pair's outputs are NaN
+    a.intensity[(long long)p * a.ld + tid] = NAN;
+    if (a.rho) a.rho[(long long)p * a.ld + tid] = make_double2(NAN, NAN);
+  }
   if (tid == 0) {
-    a.status[p] = s.flag_singular ? 1 : s.bad ? 2 : 0;
+    a.status[p] = stv;
     if (a.nrhst) a.nrhst[p] = nrhst;
   }
 }

@@ -35,6 +35,23 @@ struct CkptLayout {
   long long flags_off;     // byte offset of the decision bytes
 };
 
+// A splitting method (Sec. 3.4) for the one-workgroup kernel: kicks
+// c' -= h b_r (U(tau_r) + Gamma^2) c and drifts c += h a_r c'.  BAB: kicks
+// b_0 .. b_s with drifts a_0 .. a_{s-1} between them, the last kick at the
+// slice end (merged into the next slice's first); ABA: drifts a_0 .. a_s
+// with kicks b_0 .. b_{s-1} between them.  Kick r uses the table of node
+// i nps + node[r] of slice i (node[r] = nps: the next slice's first node).
+constexpr int MAX_KICKS = 10;
+struct SplitSteps {
+  int form;                  // 0: BAB, 1: ABA
+  int nps;                   // node tables per slice (at most 12)
+  int kicks;                 // kicks per slice
+  int pad;
+  double a[MAX_KICKS + 1];
+  double b[MAX_KICKS + 1];
+  int node[MAX_KICKS + 1];
+};
+
 struct FwdArgs {
   const StructDev* structs;
   const int* pair_struct;
@@ -61,7 +78,13 @@ struct FwdArgs {
   const int* skip;           // [P] pairs with skip[p] != 0 are not run (or null)
   int final_only;            // with ws and a bulk start: keep only the final state (no adjoint follows)
   int pad2;
+  SplitSteps sp;             // splitting steppers on the one-workgroup kernel
 };
+
+// A pair whose final reflection solve has ||B||_inf ||B^{-1} e_1||_inf above
+// this (B = Gamma Q - iP, a lower bound of cond_inf(B)) is reported
+// RHEED_PAIR_BREAKDOWN: its amplitudes would carry no correct digit.
+constexpr double BREAKDOWN_COND = 1.0e14;
 
 // Gamma_j from g2 = Gamma_j^2 (Sec. 2.1): sqrt(g2) for open beams, -i sqrt(-g2)
 // for evanescent ones.
@@ -85,7 +108,7 @@ struct PotArgs {
   double2* U;            // tables
   int n_struct;
   int nodes_per_slice;
-  double cset[4];        // distinct RK node fractions in [0, 1)
+  double cset[12];       // node positions of a slice, in units of h from its start
 };
 
 constexpr int PBWD_CHUNKS = 64;  // partial sums per atom in the potential adjoint
@@ -100,7 +123,7 @@ struct PotBwdArgs {
   double* datoms;        // [n_atoms_total][3]
   double* partial;       // [n_atoms_total][PBWD_CHUNKS][3] (plan-owned)
   int nodes_per_slice;
-  double cset[4];
+  double cset[12];
 };
 
 struct BwdArgs {

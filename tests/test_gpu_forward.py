@@ -188,3 +188,68 @@ def test_split_layout_reports_a_lost_partner(half):
     _report("split after the forced failure", e)
     assert e <= TOL
     plan.close()
+
+
+def test_angle_at_an_emergence_threshold():
+    """Glancing angles at the emergence of the rods (0, 1) and (0, -1)
+    (gamma sin(theta0) = |b2| with the azimuth along b1, so Gamma_j^2 = 0 up
+    to rounding), and a relative 1e-6 below and above: status 0, finite and
+    non-negative outputs.  Off the threshold, oracle parity at 1e-10.  At it,
+    Gamma_j^2 = gamma^2 - |b0 + k_j|^2 is a difference of two numbers near
+    4e3 whose rounding (one unit in the last place of gamma^2, 4.5e-13 1/A^2)
+    decides the rod's Gamma_j = sqrt(Gamma_j^2) entirely, and the curve
+    follows it: the GPU is held to twice the oracle's own spread when its
+    Gamma_j^2 moves by that much either way (and never less than 1e-10).
+    Below the threshold the rods carry no intensity; above it they grow from 0."""
+    import math
+
+    from oracle import physics, rk
+    wl = small_2d(n_beams=21, n_slices=40, thickness=4.0, n_layers=2, n_angles=3)
+    gamma = physics.wavenumber(wl.energy_eV)
+    s = wl.structures[0]
+    th = math.asin(float(s.recip[1][1]) / gamma)
+    wl = dataclasses.replace(wl, theta0=np.array([th * (1 - 1e-6), th, th * (1 + 1e-6)]))
+    em = [i for i, bk in enumerate(s.beams) if tuple(bk) in ((0, 1), (0, -1))]
+    res = gpu_forward(wl, stepper="rk6")
+    got = res["intensity"][:, :21]
+    assert (res["status"] == 0).all() and np.all(np.isfinite(got)) and np.all(got >= 0.0)
+    ref, _, _ = oracle_forward(wl, stepper="rk6")
+    den = np.max(np.linalg.norm(ref, axis=1))
+    off = max(np.linalg.norm(got[k] - ref[k]) for k in (0, 2)) / den
+    # the oracle at the threshold angle with Gamma_j^2 of the emerging rods moved by one ulp of gamma^2
+    st = driver.StructureSetup(wl, s, TABLEAUX["rk6"])
+    gam, mask = st.angle(th)
+    ulp = math.ulp(gamma * gamma)
+    spread = 0.0
+    for dlt in (-ulp, ulp):
+        g2 = (gam * gam).real.copy()
+        g2[em] += dlt
+        gp = np.where(g2 >= 0.0, np.sqrt(np.abs(g2)) + 0j, -1j * np.sqrt(np.abs(g2)))
+        rho, _ = rk.solve_ode_str(st.mfun(gp), gp, st.h, s.n_slices, st.tab)
+        alt = rk.intensity(rho, gp, g2 > 0.0, th)
+        spread = max(spread, np.linalg.norm(alt - ref[1]) / den)
+    at = np.linalg.norm(got[1] - ref[1]) / den
+    _report(f"emergence of rods (0, +-1) at theta0 = {np.degrees(th):.6f} deg: off the threshold {off:.3e}, "
+            f"at it {at:.3e} (oracle spread {spread:.3e}); their eta {got[:, em].round(12).tolist()}", off)
+    assert off <= TOL
+    assert at <= max(TOL, 2.0 * spread)
+    assert np.all(got[0, em] == 0.0) and np.all(got[1, em] <= got[2, em])
+
+
+def test_thick_slab_without_transformations_is_flagged():
+    """The transformation switched off (threshold infinity) on the 40 A,
+    61-beam slab: the state's columns grow as exp(|Gamma| z) and all turn
+    towards the fastest-growing mode, so the final solve is numerically
+    singular.  Every pair must come back flagged (RHEED_PAIR_BREAKDOWN, or
+    SINGULAR / NONFINITE if it got that far) with NaN intensities, while the
+    call succeeds; both layouts.  With the paper's threshold the same pairs
+    are at oracle parity (test_config2_full_size_rk6)."""
+    wl = dataclasses.replace(config2(stepper="rk6"), theta0=config2().theta0[[0, 64, 127]])
+    for layout in ("whole", "split"):
+        res = gpu_forward(wl, threshold=float("inf"), layout=layout)
+        st = res["status"]
+        print(f"[edge] threshold inf, 40 A slab, {layout}: status {st.tolist()}, n_rhst {res['n_rhst'].tolist()}",
+              flush=True)
+        assert (res["n_rhst"] == 0).all()
+        assert np.isin(st, [1, 2, 4]).all()
+        assert np.all(np.isnan(res["intensity"][:, :61]))

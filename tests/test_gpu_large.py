@@ -275,3 +275,19 @@ def test_large_paper_convention():
     e = eacc(res["intensity"][:, :81], ref)
     _report("N=81 printed convention", e)
     assert e <= TOL
+
+
+def test_thick_slab_without_transformations_is_flagged():
+    """N > 64: the transformation switched off on a 40 A slab of the
+    uneven-N workload (N = 91): the pair comes back flagged
+    (RHEED_PAIR_BREAKDOWN, or SINGULAR / NONFINITE) with NaN intensities,
+    and the call succeeds."""
+    wl = config3(16)
+    s = next(i for i, st in enumerate(wl.structures) if st.n_beams == 91)
+    sub = dataclasses.replace(wl, structures=[wl.structures[s]], theta0=wl.theta0[[10, 50]])
+    res = gpu_forward(sub, stepper="rk6", threshold=float("inf"))
+    st = res["status"]
+    print(f"[edge] threshold inf, N=91: status {st.tolist()}, n_rhst {res['n_rhst'].tolist()}", flush=True)
+    assert (res["n_rhst"] == 0).all()
+    assert np.isin(st, [1, 2, 4]).all()
+    assert np.all(np.isnan(res["intensity"][:, :91]))

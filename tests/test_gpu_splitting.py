@@ -1,6 +1,8 @@
-"""Parity of the splitting stepper (Sec. 3.4, BAB form; the fourth-order
-triple jump of the Stormer-Verlet step) on the GPU with the oracle's own
-splitting step, through the C ABI."""
+"""Parity of the splitting steppers (Sec. 3.4, BAB and ABA forms; the
+fourth-order triple jump of the Stormer-Verlet step and the sixth-order
+triple jump of that) on the GPU with the oracle's own splitting steps,
+through the C ABI: N <= 64 on the one-workgroup kernel, N > 64 (fourth-order
+BAB only) on the kernel that keeps the state in plan-owned memory."""
 import dataclasses
 
 import numpy as np
@@ -20,18 +22,69 @@ def _report(name, e):
     print(f"[parity] {name}: eacc={e:.3e}", flush=True)
 
 
-def test_potential_tables_at_the_splitting_nodes():
-    """Kick positions 0, g1 and g1 + g2 of every slice (two of them outside
-    the slice) and the final node, against the oracle's table."""
+@pytest.mark.parametrize("stepper", ["sp4", "sp6", "sp4a", "sp6a"])
+def test_potential_tables_at_the_splitting_nodes(stepper):
+    """The kick positions of every slice (for the BAB methods partly outside
+    the slice) and the final node, against the oracle's table: the node
+    order of the library is the oracle's."""
     wl = small_2d(n_beams=37, n_slices=10, n_layers=2)
-    res = gpu_forward(wl, stepper="sp4")
-    st = driver.StructureSetup(wl, wl.structures[0], TABLEAUX["sp4"])
+    res = gpu_forward(wl, stepper=stepper)
+    st = driver.StructureSetup(wl, wl.structures[0], TABLEAUX[stepper])
+    assert res["plan"].info.nodes_per_slice == len(TABLEAUX[stepper].cset)
     ref = st.table.ravel()
     assert res["U"].shape == ref.shape
     assert np.abs(res["U"] - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("n_beams", [21, 64, 65, 121])
+@pytest.mark.parametrize("n_beams", [1, 21, 45, 64])
+@pytest.mark.parametrize("stepper", ["sp4", "sp6", "sp4a", "sp6a"])
+def test_forward_splitting_one_workgroup(stepper, n_beams):
+    """Every splitting method on the one-workgroup kernel (N <= 64), several
+    tiles and a ragged tail, against the oracle's splitting step: the same
+    transformation decisions and 1e-10 in eacc."""
+    wl = small_2d(n_beams=n_beams, n_slices=40, thickness=4.0, n_layers=2, n_angles=4)
+    res = gpu_forward(wl, stepper=stepper, want_rho=True)
+    assert res["plan"].info.large_pairs == 0 and not res["plan"].split
+    ref, rho_ref, nr = oracle_forward(wl, stepper=stepper)
+    got = res["intensity"][:, :n_beams]
+    assert (res["status"] == 0).all()
+    e = eacc(got, ref)
+    _report(f"{stepper} N={n_beams} rhst={nr.tolist()} gpu_rhst={res['n_rhst'].tolist()}", e)
+    assert e <= TOL
+    assert res["n_rhst"].tolist() == nr.tolist()
+    rho = res["rho"][:, :n_beams]
+    assert np.abs(rho - rho_ref).max() <= 1e-9 * np.abs(rho_ref).max()
+
+
+@pytest.mark.parametrize("stepper", ["sp6", "sp4a"])
+def test_splitting_full_size_n61(stepper):
+    """The N = 61 slab at full size (40 A, 128 angles) with a splitting
+    method at the grid of the stepper comparison (800 slices), sampled
+    angles against the oracle, every pair through the validity gate."""
+    from synth import config2
+    from tests.gpu_util import physical
+    wl = config2()
+    wl = dataclasses.replace(wl, structures=[dataclasses.replace(wl.structures[0], n_slices=800)])
+    res = gpu_forward(wl, stepper=stepper)
+    assert (res["status"] == 0).all()
+    assert physical(res["intensity"][:, :61], wl.absorption).all()
+    idx = [0, 64, 127]
+    ref, _, _ = oracle_forward(wl, angle_idx=idx, stepper=stepper)
+    e = eacc(res["intensity"][idx, :61], ref)
+    _report(f"{stepper} N=61 800 slices (sampled angles)", e)
+    assert e <= TOL
+
+
+def test_splitting_for_large_n_is_fourth_order_bab_only():
+    from paper_2306_00271_amd import api
+    from paper_2306_00271_amd._lib import RheedError
+    wl = small_2d(n_beams=69, n_slices=4, thickness=0.4, n_layers=2, n_angles=2)
+    for stepper in ("sp6", "sp4a", "sp6a"):
+        with pytest.raises(RheedError, match="RHEED_SP4"):
+            api.plan_for(wl, stepper=stepper)
+
+
+@pytest.mark.parametrize("n_beams", [65, 121])
 def test_forward_sp4(n_beams):
     wl = small_2d(n_beams=n_beams, n_slices=40, thickness=4.0, n_layers=2, n_angles=4)
     res = gpu_forward(wl, stepper="sp4", want_rho=True)
@@ -67,7 +120,7 @@ def test_sp4_uneven_batch_in_one_launch():
              for i, (n, L) in enumerate(((13, 30), (61, 24), (91, 20)))]
     wl = dataclasses.replace(parts[0], structures=[p.structures[0] for p in parts])
     res = gpu_forward(wl, stepper="sp4")
-    assert res["plan"].info.large_pairs == 9
+    assert res["plan"].info.large_pairs == 3
     assert (res["status"] == 0).all()
     A = len(wl.theta0)
     for s, p in enumerate(parts):
@@ -84,8 +137,9 @@ def test_sp4_refuses_split_layout_and_the_adjoint():
     from paper_2306_00271_amd import api
     from paper_2306_00271_amd._lib import RheedError
     wl = small_2d(n_beams=21, n_slices=4, thickness=0.4, n_layers=2, n_angles=2)
-    with pytest.raises(RheedError, match="one-workgroup"):
-        api.plan_for(wl, stepper="sp4", layout="split")
+    for stepper in ("sp4", "sp6", "sp4a", "sp6a"):
+        with pytest.raises(RheedError, match="one-workgroup"):
+            api.plan_for(wl, stepper=stepper, layout="split")
     plan = api.plan_for(wl, stepper="sp4")
     dev = torch.device("cuda:0")
     U = plan.potential(api.atoms_for(wl, dev))

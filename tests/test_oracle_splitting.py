@@ -1,4 +1,4 @@
-"""Pins of the oracle's splitting steppers (Sec. 3.4, BAB form) against what
+"""Pins of the oracle's splitting steppers (Sec. 3.4, BAB and ABA forms) against what
 the mathematics fixes: the triple-jump conditions, the observed order under
 step halving on a z-dependent potential, and exact flux conservation
 without absorption at a step where the RK steppers visibly violate it."""
@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import driver, rk
-from oracle.splitting import SP4, VERLET
+from oracle.splitting import SP4, SP4_ABA, SP6, SP6_ABA, VERLET
 from oracle.tableaux import RK4
 from synth import small_2d, small_row
 
@@ -27,8 +27,36 @@ def test_triple_jump_weights():
     assert SP4.node_index(5, 0) == 15 and SP4.node_index(5, 2) == 17 and SP4.node_index(5, 3) == 18
 
 
-@pytest.mark.parametrize("comp", [VERLET, SP4], ids=lambda c: c.name)
-def test_splitting_order_on_z_dependent_potential(comp):
+def test_sixth_order_triple_jump_weights():
+    """SP6: the triple jump of SP4 with outer weight w1 and inner w0,
+    2 w1 + w0 = 1 and 2 w1^5 + w0^5 = 0 (cancels SP4's fifth-order error);
+    its nine drifts are w_i times SP4's, its kicks their half sums."""
+    w1 = SP6.a[0] / SP4.a[0]
+    w0 = SP6.a[3] / SP4.a[0]
+    assert 2 * w1 + w0 == pytest.approx(1.0, abs=1e-15)
+    assert 2 * w1 ** 5 + w0 ** 5 == pytest.approx(0.0, abs=1e-14)
+    assert np.allclose(SP6.a, np.concatenate([w1 * SP4.a, w0 * SP4.a, w1 * SP4.a]), atol=1e-15)
+    assert SP6.b.size == 10 and SP6.b.sum() == pytest.approx(1.0, abs=1e-14)
+    assert len(SP6.cset) == 9 and SP6.n_nodes(10) == 91
+
+
+def test_aba_forms_swap_the_roles():
+    """ABA: drifts at both ends of the slice, kick weights the Stormer-Verlet
+    step lengths, drift weights their half sums; every kick inside the slice."""
+    for aba, bab in ((SP4_ABA, SP4), (SP6_ABA, SP6)):
+        assert np.allclose(aba.b, bab.a, atol=0) and np.allclose(aba.a, bab.b, atol=0)
+        assert aba.a.size == aba.b.size + 1
+        assert np.allclose(aba.tau, np.cumsum(aba.a)[:-1], atol=0)
+        assert all(0.0 < t < 1.0 for t in aba.tau)
+    assert SP4_ABA.tau[1] == pytest.approx(0.5, abs=1e-15)   # the middle kick of a symmetric method
+
+
+ORDER_CASES = [(VERLET, (80, 160, 320), 5120), (SP4, (40, 80, 160), 2560), (SP4_ABA, (40, 80, 160), 2560),
+               (SP6, (40, 80, 160), 2560), (SP6_ABA, (40, 80, 160), 2560)]
+
+
+@pytest.mark.parametrize("comp,Ls,Lref", ORDER_CASES, ids=lambda c: getattr(c, "name", ""))
+def test_splitting_order_on_z_dependent_potential(comp, Ls, Lref):
     """Error ratio under step halving -> 2^order; a kick evaluated at the
     wrong position (e.g. after its drift) or a wrong weight drops it."""
     base = small_row(hmax=2, n_slices=400, thickness=6.0, n_layers=2)
@@ -39,8 +67,7 @@ def test_splitting_order_on_z_dependent_potential(comp):
         s = dataclasses.replace(base.structures[0], n_slices=L)
         w = dataclasses.replace(base, structures=[s])
         return driver.StructureSetup(w, s, comp).solve(th)[0]
-    ref = run(2560 if comp is SP4 else 5120)
-    Ls = (40, 80, 160) if comp is SP4 else (80, 160, 320)
+    ref = run(Lref)
     e = [np.abs(run(L) - ref).max() for L in Ls]
     r = e[1] / e[2]
     assert 2 ** comp.order * 0.8 < r < 2 ** comp.order * 1.25, e
@@ -56,12 +83,13 @@ def _flux(st, th):
     return R.sum() + T.sum()
 
 
-def test_splitting_conserves_flux_exactly_without_absorption():
+@pytest.mark.parametrize("comp", [SP4, SP4_ABA, SP6, SP6_ABA], ids=lambda c: c.name)
+def test_splitting_conserves_flux_exactly_without_absorption(comp):
     """Each kick and drift keeps Im(c^H c') for Hermitian M, so R + T = 1 to
     rounding even at a coarse step, where RK4 is off by far more."""
     wl = small_2d(n_beams=9, n_slices=20, thickness=4.0, n_layers=1, absorption=0.0, n_angles=3)
     s = wl.structures[0]
-    st = driver.StructureSetup(wl, s, SP4)
+    st = driver.StructureSetup(wl, s, comp)
     st4 = driver.StructureSetup(wl, s, RK4)
     worst_rk = 0.0
     for th in wl.theta0:
