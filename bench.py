@@ -294,6 +294,50 @@ def uneven_forward(n_structures, steps=2, cpu=True):
     return res
 
 
+# ------------------------------------------------------- FP32 stage products
+def fp32_stages(steps=3):
+    """Forward of the gradient workload's slab (N = 61, 400 slices, 128
+    angles, RK6) with the stage products U X in FP32 (the lower-precision
+    evaluation the paper leaves for future work) against the same forward in
+    FP64: time per call and eacc between the two curves, beside the grid's
+    own discretisation error (RK6 at 400 against 1600 slices)."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from paper_2306_00271_amd import api
+    from synth import config4
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    wl = config4(1)
+
+    def run(w, precision, reps):
+        plan = api.plan_for(w, stepper="rk6", stage_precision=precision)
+        U = plan.potential(api.atoms_for(w, dev))
+        ang = api.angles_for(w, dev)
+        out = plan.forward(U, ang)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            out = plan.forward(U, ang)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return out["intensity"].cpu().numpy()[:, :61], e0.elapsed_time(e1) / reps
+
+    eta32, ms32 = run(wl, "fp32", steps)
+    eta64, ms64 = run(wl, "fp64", steps)
+    fine = dataclasses.replace(wl, structures=[dataclasses.replace(wl.structures[0], n_slices=1600)])
+    eta_f, _ = run(fine, "fp64", 1)
+    den = float(np.max(np.linalg.norm(eta64, axis=1)))
+    e = float(np.max(np.linalg.norm(eta32 - eta64, axis=1))) / den
+    disc = float(np.max(np.linalg.norm(eta64 - eta_f, axis=1))) / den
+    return {"ms_fp32": round(ms32, 3), "ms_fp64": round(ms64, 3), "speedup": round(ms64 / ms32, 3),
+            "value_fp32": round(len(wl.theta0) / (ms32 / 1e3), 2), "unit": "points/s (forward only)",
+            "eacc_fp32_vs_fp64": float(f"{e:.3e}"), "eacc_grid_vs_1600_slices": float(f"{disc:.3e}")}
+
+
 # ------------------------------------------------------------- bulk layer
 BULK_SLICES = 62   # per 3.1 A unit layer (h = 0.05 A): at 0.1 A the 61-beam stack drifts to the wrong modes
 
@@ -468,7 +512,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["fwd", "fwd+adj", "uneven", "steppers", "bulk"], default="fwd+adj",
+    ap.add_argument("--mode", choices=["fwd", "fwd+adj", "uneven", "steppers", "bulk", "fp32"], default="fwd+adj",
                     help="uneven: only the uneven-N batched forward variant; steppers: only the accuracy-vs-time "
                          "comparison of the steppers; bulk: only the bulk-layer variant; each as its own JSON line")
     ap.add_argument("--structures", type=int, default=1, help="structures in the batch (128 angles each)")
@@ -498,6 +542,9 @@ def main():
         return
     if args.mode == "bulk":
         print(json.dumps({"bulk_layer": bulk_bench(cpu=not args.no_cpu)}))
+        return
+    if args.mode == "fp32":
+        print(json.dumps({"fp32_stages_forward": fp32_stages(steps=args.steps)}))
         return
     if args.mode == "uneven":
         print(json.dumps({"uneven_n_forward": uneven_forward(max(1, args.uneven_structures), steps=args.steps,
@@ -646,6 +693,9 @@ def main():
     if not args.no_bulk and args.structures == 1:
         variants = variants or {}
         variants["bulk_layer"] = bulk_bench(cpu=not args.no_cpu)
+    if args.structures == 1:
+        variants = variants or {}
+        variants["fp32_stages_forward"] = fp32_stages()
 
     rec = {
         "metric": "rocking-curve points (structure x angle)/s at N=61 FP64; " +

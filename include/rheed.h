@@ -126,12 +126,23 @@ typedef struct {
  * two layouts agree to rounding. */
 typedef enum { RHEED_LAYOUT_AUTO = 0, RHEED_LAYOUT_WHOLE = 1, RHEED_LAYOUT_SPLIT = 2 } rheed_layout;
 
+/* Precision of the RK stage products U X (the paper's Sec. 6 names single
+ * and half precision as future work): FP64, or FP32 on the FP32 matrix
+ * cores (v_mfma_f32_16x16x4f32) with the operands rounded to FP32 and
+ * everything else in FP64 (the Gamma^2 X term, the stage combinations, the
+ * state, the transformation, the reflection).  FP32 stages: RK steppers,
+ * N <= 64, forward only (no state saving, no bulk start); the intensities
+ * then differ from the FP64 ones by about 1e-7 in eacc on the test slabs,
+ * well below the step's own discretisation error at the usual grids. */
+typedef enum { RHEED_STAGES_FP64 = 0, RHEED_STAGES_FP32 = 1 } rheed_stage_precision;
+
 typedef struct {
   rheed_stepper stepper;
   double rhst_threshold;     /* RHST when the condition estimate exceeds it; the paper uses 1000 */
   int32_t checkpoint_every;  /* slices between states rheed_forward keeps for rheed_backward (>= 1) */
   rheed_convention convention;
   rheed_layout layout;       /* SPLIT when the batch does not fit -> RHEED_E_UNSUPPORTED at plan creation */
+  rheed_stage_precision stage_precision;
 } rheed_opts;
 
 typedef struct rheed_plan_s* rheed_plan_t;

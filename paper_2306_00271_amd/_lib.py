@@ -17,6 +17,7 @@ RHEED_RK4, RHEED_RK6, RHEED_SP4, RHEED_SP6, RHEED_SP4_ABA, RHEED_SP6_ABA = 0, 1,
 RHEED_INTENSITY_FLUX, RHEED_INTENSITY_PAPER = 0, 1
 RHEED_PAIR_OK, RHEED_PAIR_SINGULAR, RHEED_PAIR_NONFINITE, RHEED_PAIR_SYNC, RHEED_PAIR_BREAKDOWN = 0, 1, 2, 3, 4
 RHEED_LAYOUT_AUTO, RHEED_LAYOUT_WHOLE, RHEED_LAYOUT_SPLIT = 0, 1, 2
+RHEED_STAGES_FP64, RHEED_STAGES_FP32 = 0, 1
 RHEED_MAX_BEAMS = 128
 RHEED_MAX_BOX = 300
 RHEED_MAX_BOX_LARGE = 1024
@@ -49,6 +50,7 @@ class Opts(C.Structure):
         ("checkpoint_every", C.c_int32),
         ("convention", C.c_int),
         ("layout", C.c_int),
+        ("stage_precision", C.c_int),
     ]
 
 

@@ -21,6 +21,7 @@ STEPPERS = {"rk4": _lib.RHEED_RK4, "rk6": _lib.RHEED_RK6, "sp4": _lib.RHEED_SP4,
             "sp4a": _lib.RHEED_SP4_ABA, "sp6a": _lib.RHEED_SP6_ABA}
 CONVENTIONS = {"flux": _lib.RHEED_INTENSITY_FLUX, "paper": _lib.RHEED_INTENSITY_PAPER}
 LAYOUTS = {"auto": _lib.RHEED_LAYOUT_AUTO, "whole": _lib.RHEED_LAYOUT_WHOLE, "split": _lib.RHEED_LAYOUT_SPLIT}
+PRECISIONS = {"fp64": _lib.RHEED_STAGES_FP64, "fp32": _lib.RHEED_STAGES_FP32}
 
 
 def _stream():
@@ -72,7 +73,7 @@ class Plan:
     def __init__(self, structures: Sequence, angles_per_struct: Sequence[int], *, energy_eV: float,
                  charge: float, absorption: float, mean_inner_potential: float = 15.0, stepper: str = "rk6",
                  threshold: float = 1000.0, checkpoint_every: int = 1, convention: str = "flux",
-                 layout: str = "auto"):
+                 layout: str = "auto", stage_precision: str = "fp64"):
         L = _lib.lib()
         self.gamma, self.kappa = beam_constants(energy_eV)
         self.stepper = stepper
@@ -100,7 +101,7 @@ class Plan:
             st.mean_inner_potential = float(mean_inner_potential)
         aps = (C.c_int32 * n)(*[int(a) for a in angles_per_struct])
         opts = _lib.Opts(STEPPERS[stepper], float(threshold), int(checkpoint_every), CONVENTIONS[convention],
-                         LAYOUTS[layout])
+                         LAYOUTS[layout], PRECISIONS[stage_precision])
         h = C.c_void_p()
         _lib.check(L.rheed_plan_create(C.byref(h), C.byref(opts), n, arr, aps), "plan_create")
         self._h = h

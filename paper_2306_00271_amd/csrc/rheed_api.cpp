@@ -128,6 +128,10 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     return fail(RHEED_E_INVALID, "unknown intensity convention");
   if (opts->layout != RHEED_LAYOUT_AUTO && opts->layout != RHEED_LAYOUT_WHOLE && opts->layout != RHEED_LAYOUT_SPLIT)
     return fail(RHEED_E_INVALID, "unknown layout");
+  if (opts->stage_precision != RHEED_STAGES_FP64 && opts->stage_precision != RHEED_STAGES_FP32)
+    return fail(RHEED_E_INVALID, "unknown stage precision");
+  if (opts->stage_precision == RHEED_STAGES_FP32 && splitting)
+    return fail(RHEED_E_UNSUPPORTED, "FP32 stage products need an RK stepper");
   auto* P = new rheed_plan_s();
   P->opts = *opts;
   P->n_struct = n_struct;
@@ -209,6 +213,10 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       snprintf(buf, sizeof buf, "structure %d: n_beams must be in [1, %d]", s, RHEED_MAX_BEAMS);
       delete P;
       return fail(RHEED_E_UNSUPPORTED, buf);
+    }
+    if (opts->stage_precision == RHEED_STAGES_FP32 && st.n_beams > NP) {
+      delete P;
+      return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) + ": FP32 stage products need N <= 64");
     }
     if (splitting && st.n_beams > NP && opts->stepper != RHEED_SP4) {
       delete P;
@@ -354,8 +362,8 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     };
     std::stable_sort(P->large_pairs.begin(), P->large_pairs.end(), [&](int x, int y) { return cost(x) > cost(y); });
   }
-  // the adjoint and its state saving handle N <= 64 and the RK steppers only
-  if (!P->large_pairs.empty() || P->splitting) {
+  // the adjoint and its state saving handle N <= 64 and the FP64 RK steppers only
+  if (!P->large_pairs.empty() || P->splitting || opts->stage_precision != RHEED_STAGES_FP64) {
     P->fwd_ws = 0;
     P->bwd_ws = 0;
   }
@@ -554,10 +562,12 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
                           int32_t* pair_status, int32_t* n_rhst, void* workspace, size_t ws_bytes, void* stream,
                           const void* y_bottom, const int* skip, bool final_only = false) {
   if (!P || !U_tables || !angles || !intensity || !pair_status) return fail(RHEED_E_INVALID, "forward: null argument");
-  if (workspace && (!P->large_pairs.empty() || P->splitting))
-    return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs an RK stepper and every structure to have N <= 64");
-  if (y_bottom && P->splitting)
-    return fail(RHEED_E_UNSUPPORTED, "forward: the bulk start needs an RK stepper");
+  const bool f32 = P->opts.stage_precision == RHEED_STAGES_FP32;
+  if (workspace && (!P->large_pairs.empty() || P->splitting || f32))
+    return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs an RK stepper with FP64 stages "
+                                     "and every structure to have N <= 64");
+  if (y_bottom && (P->splitting || f32))
+    return fail(RHEED_E_UNSUPPORTED, "forward: the bulk start needs an RK stepper with FP64 stages");
   if (workspace && ws_bytes < P->fwd_ws)
     return fail(RHEED_E_INVALID, "forward: workspace of " + std::to_string(ws_bytes) + " bytes < " +
                                      std::to_string(P->fwd_ws));
@@ -586,11 +596,13 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
   if (!P->small_pairs.empty()) {
     a.pair_list = P->d_small_pairs;  // null when every pair is small
     a.n_pairs = (int)P->small_pairs.size();
+    // kernel code: the method (0 RK4, 1 RK6, 2 a splitting method), plus 8 for FP32 stage products
+    const int kcode = (P->splitting ? 2 : (int)P->opts.stepper) | (f32 ? 8 : 0);
     if (P->split) {
       a.xch = P->d_xch;
-      e = launch_forward_split((int)P->opts.stepper, a, st);
+      e = launch_forward_split(kcode, a, st);
     } else {
-      e = launch_forward((int)P->opts.stepper, a, st);
+      e = launch_forward(kcode, a, st);
     }
     if (e != hipSuccess) return hip_fail(e, "forward launch");
   }
@@ -625,8 +637,8 @@ rheed_status rheed_forward_bulk(rheed_plan_t P, const void* U_tables, const doub
                                 double* intensity, void* rho, int32_t* pair_status, int32_t* n_rhst, void* workspace,
                                 size_t ws_bytes, void* stream) {
   if (!P || !y_bottom) return fail(RHEED_E_INVALID, "forward_bulk: null argument");
-  if (!P->large_pairs.empty() || P->splitting)
-    return fail(RHEED_E_UNSUPPORTED, "forward_bulk: needs an RK stepper and every structure to have N <= 64");
+  if (!P->large_pairs.empty() || P->splitting || P->opts.stage_precision != RHEED_STAGES_FP64)
+    return fail(RHEED_E_UNSUPPORTED, "forward_bulk: needs an RK stepper with FP64 stages and every structure to have N <= 64");
   return forward_impl(P, U_tables, angles, intensity, rho, pair_status, n_rhst, workspace, ws_bytes, stream,
                       y_bottom, nullptr);
 }
@@ -638,8 +650,8 @@ rheed_status rheed_bulk_reflection(rheed_plan_t P, const void* U_tables, const d
     return fail(RHEED_E_INVALID, "bulk_reflection: null argument");
   if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(RHEED_E_INVALID, "bulk_reflection: tol must be finite and >= 0");
   if (max_layers < 1) return fail(RHEED_E_INVALID, "bulk_reflection: max_layers must be >= 1");
-  if (!P->large_pairs.empty() || P->splitting)
-    return fail(RHEED_E_UNSUPPORTED, "bulk_reflection: needs an RK stepper and every structure to have N <= 64");
+  if (!P->large_pairs.empty() || P->splitting || P->opts.stage_precision != RHEED_STAGES_FP64)
+    return fail(RHEED_E_UNSUPPORTED, "bulk_reflection: needs an RK stepper with FP64 stages and every structure to have N <= 64");
   const size_t need = P->fwd_ws + bulk_extra(P);
   if (ws_bytes < need)
     return fail(RHEED_E_INVALID, "bulk_reflection: workspace of " + std::to_string(ws_bytes) + " bytes < " +
@@ -760,8 +772,8 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
                             void* dL_dU, void* workspace, size_t ws_bytes, void* stream) {
   if (!P || !U_tables || !angles || !dL_dI || !dL_dU || !workspace)
     return fail(RHEED_E_INVALID, "backward: null argument");
-  if (!P->large_pairs.empty() || P->splitting)
-    return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs an RK stepper and every structure to have N <= 64");
+  if (!P->large_pairs.empty() || P->splitting || P->opts.stage_precision != RHEED_STAGES_FP64)
+    return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs an RK stepper with FP64 stages and every structure to have N <= 64");
   if (ws_bytes < P->fwd_ws + P->bwd_ws)
     return fail(RHEED_E_INVALID, "backward: workspace of " + std::to_string(ws_bytes) + " bytes < " +
                                      std::to_string(P->fwd_ws + P->bwd_ws));

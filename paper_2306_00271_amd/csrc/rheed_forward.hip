@@ -124,13 +124,74 @@ __device__ __forceinline__ int own(int ob, int e) {
   return ob + 4 * LD * (e & 3) + 16 * (e >> 2);
 }
 
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Stepper codes of the N <= 64 kernels: bits 0-2 the method (0 RK4, 1 RK6,
+// 2 a splitting method), bit 3 set for the lower-precision evaluation, whose
+// stage products U X run in FP32 (everything else, the Gamma^2 X term of the
+// stages included, stays FP64).
+constexpr int F32_STAGES = 8;
+
+// Row of the A operand a lane supplies.  v_mfma_f64_16x16x4f64 returns row
+// 4 v + (lane >> 4) of its 16 x 16 result in register v, which the
+// epilogues assume; v_mfma_f32_16x16x4f32 returns row 4 (lane >> 4) + v.
+// Feeding the FP32 instruction the A rows in the transposed order
+// 4 (i & 3) + (i >> 2) (an involution of 0..15) puts row 4 v + (lane >> 4) of
+// the product in register v, as for FP64.
+template <bool F32>
+__device__ __forceinline__ int a_row(int i) {
+  return F32 ? 4 * (i & 3) + (i >> 2) : i;
+}
+
+// The FP32 form of stage_gemm's U X: the same 3-real-product chains on
+// v_mfma_f32_16x16x4f32 (the A rows supplied in a_row<true> order),
+// operands rounded to FP32, the chains combined in FP64.
+template <int LD, class Epi>
+__device__ __forceinline__ void stage_gemm_f32(const double2* __restrict__ xbuf, const double2* __restrict__ tslot,
+                                               const unsigned (&gidx)[8], const double (&g2)[4], int ob, int lane,
+                                               int cofs, Epi&& epi) {
+  __builtin_amdgcn_sched_barrier(0);
+  f4 t1[NJT], t2[NJT], t3[NJT];
+#pragma unroll
+  for (int jt = 0; jt < NJT; ++jt) t1[jt] = t2[jt] = t3[jt] = f4{0, 0, 0, 0};
+  const int bb = (lane >> 4) * LD + cofs + (lane & 15);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const unsigned gi = (q & 1) ? (gidx[q >> 1] >> 16) : (gidx[q >> 1] & 0xffffu);
+    const double2 u = tslot[gi];
+    const float ur = (float)u.x, ui = (float)u.y, us = (float)(u.x + u.y);
+#pragma unroll
+    for (int jt = 0; jt < NJT; ++jt) {
+      const double2 x = xbuf[bb + 4 * LD * q + 16 * jt];
+      t1[jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur, (float)x.x, t1[jt], 0, 0, 0);
+      t2[jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(ui, (float)x.y, t2[jt], 0, 0, 0);
+      t3[jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(us, (float)(x.x + x.y), t3[jt], 0, 0, 0);
+    }
+    if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int jt = 0; jt < NJT; ++jt) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const double2 ov = xbuf[ob + 4 * LD * v + 16 * jt];
+      const double a1 = t1[jt][v], a2 = t2[jt][v], a3 = t3[jt][v];
+      epi(jt * 4 + v, (a1 - a2) + g2[v] * ov.x, (a3 - a1 - a2) + g2[v] * ov.y);
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
 // G = (U(node) + Gamma^2) X for the wave's 16 x 32 block, X read from LDS
 // (row stride LD, the block's columns from cofs); every element of G is
-// handed to epi(e, Re G, Im G).
-template <int LD, class Epi>
+// handed to epi(e, Re G, Im G).  F32: U X in FP32 (stage_gemm_f32).
+template <int LD, bool F32 = false, class Epi>
 __device__ __forceinline__ void stage_gemm(const double2* __restrict__ xbuf, const double2* __restrict__ tslot,
                                            const unsigned (&gidx)[8], const double (&g2)[4], int ob, int lane,
                                            int cofs, Epi&& epi) {
+  if constexpr (F32) {
+    stage_gemm_f32<LD>(xbuf, tslot, gidx, g2, ob, lane, cofs, epi);
+    return;
+  }
   __builtin_amdgcn_sched_barrier(0);
   d4 t1[NJT], t2[NJT], t3[NJT];
 #pragma unroll
@@ -214,7 +275,7 @@ __device__ __forceinline__ void load_nodes(Lds& s, const double2* __restrict__ U
 // a.skip[p] set are not run; the vacuum instantiations carry neither.
 template <int STEPPER, bool BULK>
 __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
-  using T = Tab<STEPPER>;
+  using T = Tab<STEPPER & 7>;
   Lds& s = fwd_lds;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -260,7 +321,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
   unsigned gidx[8];
   {
     const int W = 2 * S.kd + 1;
-    const int iA = 16 * RT + (lane & 15);
+    const int iA = 16 * RT + a_row<(STEPPER & F32_STAGES) != 0>(lane & 15);
     const int baseA = (s.bhk[iA][0] + S.hd) * W + (s.bhk[iA][1] + S.kd);
 #pragma unroll
     for (int q = 0; q < 16; q += 2) {
@@ -301,7 +362,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
   if constexpr (BULK) keep = save && !a.final_only;
   int nrhst = 0;
 
-  if constexpr (STEPPER != 2) load_nodes<T::slots, FT>(s, Us, S.box, 0, 1, tid);
+  if constexpr ((STEPPER & 7) != 2) load_nodes<T::slots, FT>(s, Us, S.box, 0, 1, tid);
   // splitting (Sec. 3.4): the slice's node tables sit in ring slots of the
   // stage-input buffer, which the splitting steps do not otherwise use (the
   // transformation below overwrites it, so they are loaded every slice)
@@ -316,7 +377,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
   // kick: c' -= h w (U + Gamma^2) c with the table in ring slot m; c is read
   // by every wave, so a barrier follows before anything writes it
   auto kick = [&](int m, double wgt) {
-    stage_gemm<NP>(cb, xb + m * (MAXBOX + 1), gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {
+    stage_gemm<NP, (STEPPER & F32_STAGES) != 0>(cb, xb + m * (MAXBOX + 1), gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {
       d.r[e] -= h * wgt * gr;
       d.i[e] -= h * wgt * gi;
     });
@@ -345,9 +406,9 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       }
     }
     const int nb = i * T::nodes;  // node index of c = 0 in this slice
-    if constexpr (STEPPER != 2) load_nodes<T::slots, FT>(s, Us, S.box, nb + 1, nb + T::nodes + 1, tid);
+    if constexpr ((STEPPER & 7) != 2) load_nodes<T::slots, FT>(s, Us, S.box, nb + 1, nb + T::nodes + 1, tid);
     const double hh = h * h;
-    if constexpr (STEPPER == 2) {
+    if constexpr ((STEPPER & 7) == 2) {
       const SplitSteps& sp = a.sp;
       load_ring(i * sp.nps, sp.nps);
       if (sp.form == 0) {
@@ -367,7 +428,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
           drift(sp.a[r + 1]);
         }
       }
-    } else if constexpr (STEPPER == 0) {
+    } else if constexpr ((STEPPER & 7) == 0) {
       const double2* t0 = s.tb[nb % 3];
       const double2* th = s.tb[(nb + 1) % 3];
       const double2* t1 = s.tb[(nb + 2) % 3];
@@ -379,8 +440,8 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       }
       __syncthreads();
       Mat G1, G2;
-      stage_gemm<NP>(cb, t0, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
-      stage_gemm<NP>(xb, th, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
+      stage_gemm<NP, (STEPPER & F32_STAGES) != 0>(cb, t0, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
+      stage_gemm<NP, (STEPPER & F32_STAGES) != 0>(xb, th, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
       __syncthreads();
       // X3 = c + h/2 c' - h^2/4 G1 -> LDS;  X4 = c + h c' - h^2/2 G2 (kept in G1);
       // c <- c + h c' - h^2/6 (G1 + G2);  c' <- c' - h/6 (G1 + 2 G2)
@@ -397,7 +458,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
         d.i[e] = di - (h / 6.0) * (g1i + 2.0 * g2i);
       }
       __syncthreads();
-      stage_gemm<NP>(xb, th, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G3
+      stage_gemm<NP, (STEPPER & F32_STAGES) != 0>(xb, th, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G3
         double2 cv = cb[OWN(e)];
         cv.x -= (hh / 6.0) * gr;
         cv.y -= (hh / 6.0) * gi;
@@ -408,7 +469,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       __syncthreads();
       store_mat(xb, G1, ob);  // X4
       __syncthreads();
-      stage_gemm<NP>(xb, t1, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G4
+      stage_gemm<NP, (STEPPER & F32_STAGES) != 0>(xb, t1, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G4
         d.r[e] -= (h / 6.0) * gr;
         d.i[e] -= (h / 6.0) * gi;
       });
@@ -426,8 +487,8 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       }
       __syncthreads();
       Mat G1, G2, G3;
-      stage_gemm<NP>(cb, tA, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
-      stage_gemm<NP>(xb, tB, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
+      stage_gemm<NP, (STEPPER & F32_STAGES) != 0>(cb, tA, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
+      stage_gemm<NP, (STEPPER & F32_STAGES) != 0>(xb, tB, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
       __syncthreads();
       // X3 = c + 2h/3 c' - h^2 (2/9) G1
 #pragma unroll
@@ -437,7 +498,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
                                   cv.y + (2.0 * h / 3.0) * d.i[e] - hh * (2.0 / 9.0) * G1.i[e]);
       }
       __syncthreads();
-      stage_gemm<NP>(xb, tD, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G3.r[e] = gr; G3.i[e] = gi; });
+      stage_gemm<NP, (STEPPER & F32_STAGES) != 0>(xb, tD, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) { G3.r[e] = gr; G3.i[e] = gi; });
       __syncthreads();
       // X4 = c + h/3 c' - h^2 (G1/9 - G2/18)
 #pragma unroll
@@ -451,7 +512,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       Mat& X5 = G1;
       Mat& X6 = G2;
       Mat& T7 = G3;
-      stage_gemm<NP>(xb, tB, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double a4, double b4) {
+      stage_gemm<NP, (STEPPER & F32_STAGES) != 0>(xb, tB, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double a4, double b4) {
         const double2 cv = cb[OWN(e)];
         const double dr = d.r[e], di = d.i[e];
         const double a1 = G1.r[e], b1 = G1.i[e], a2 = G2.r[e], b2 = G2.i[e], a3 = G3.r[e], b3 = G3.i[e];
@@ -469,7 +530,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       __syncthreads();
       store_mat(xb, X5, ob);
       __syncthreads();
-      stage_gemm<NP>(xb, tC, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G5
+      stage_gemm<NP, (STEPPER & F32_STAGES) != 0>(xb, tC, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G5
         T7.r[e] += hh * (8.0 / 11.0) * gr;
         T7.i[e] += hh * (8.0 / 11.0) * gi;
         double2 cv = cb[OWN(e)];
@@ -482,7 +543,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       __syncthreads();
       store_mat(xb, X6, ob);
       __syncthreads();
-      stage_gemm<NP>(xb, tC, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G6
+      stage_gemm<NP, (STEPPER & F32_STAGES) != 0>(xb, tC, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G6
         double2 cv = cb[OWN(e)];
         cv.x += hh * (2.0 / 15.0) * gr;
         cv.y += hh * (2.0 / 15.0) * gi;
@@ -493,7 +554,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       __syncthreads();
       store_mat(xb, T7, ob);  // X7
       __syncthreads();
-      stage_gemm<NP>(xb, tE, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G7
+      stage_gemm<NP, (STEPPER & F32_STAGES) != 0>(xb, tE, gidx, g2, ob, lane, 16 * NJT * CH, [&](int e, double gr, double gi) {  // G7
         d.r[e] -= h * (11.0 / 120.0) * gr;
         d.i[e] -= h * (11.0 / 120.0) * gi;
       });
@@ -578,7 +639,7 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
     }
     __syncthreads();
   }
-  if constexpr (STEPPER == 2) {
+  if constexpr ((STEPPER & 7) == 2) {
     if (a.sp.form == 0) {  // BAB: the last slice's final kick, at z = 0 (node L nps)
       load_ring(L * a.sp.nps, 1);
       kick(0, a.sp.b[a.sp.kicks - 1]);
@@ -689,7 +750,7 @@ __device__ __forceinline__ void store_mat_ld(double2* buf, const Mat& m, int ob)
 template <int STEPPER, int LD>
 __device__ __forceinline__ Mat rk_slice(double2* cb, double2* xb, const double2* tb0, int nb, const Gidx gx,
                                         const G2 gg, int ob, int lane, int cofs, double h, Mat d) {
-  constexpr int SL = Tab<STEPPER>::slots;
+  constexpr int SL = Tab<STEPPER & 7>::slots;
   unsigned gidx[8];
   double g2[4];
 #pragma unroll
@@ -697,7 +758,7 @@ __device__ __forceinline__ Mat rk_slice(double2* cb, double2* xb, const double2*
 #pragma unroll
   for (int q = 0; q < 4; ++q) g2[q] = gg.v[q];
 const double hh = h * h;
-  if constexpr (STEPPER == 0) {
+  if constexpr ((STEPPER & 7) == 0) {
     const double2* t0 = tb0 + (nb % SL) * (MAXBOX + 1);
     const double2* th = tb0 + ((nb + 1) % SL) * (MAXBOX + 1);
     const double2* t1 = tb0 + ((nb + 2) % SL) * (MAXBOX + 1);
@@ -709,8 +770,8 @@ const double hh = h * h;
     }
     __syncthreads();
     Mat G1, G2;
-    stage_gemm<LD>(cb, t0, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
-    stage_gemm<LD>(xb, th, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
+    stage_gemm<LD, (STEPPER & F32_STAGES) != 0>(cb, t0, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
+    stage_gemm<LD, (STEPPER & F32_STAGES) != 0>(xb, th, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
     __syncthreads();
     // X3 = c + h/2 c' - h^2/4 G1 -> LDS;  X4 = c + h c' - h^2/2 G2 (kept in G1);
     // c <- c + h c' - h^2/6 (G1 + G2);  c' <- c' - h/6 (G1 + 2 G2)
@@ -727,7 +788,7 @@ const double hh = h * h;
       d.i[e] = di - (h / 6.0) * (g1i + 2.0 * g2i);
     }
     __syncthreads();
-    stage_gemm<LD>(xb, th, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G3
+    stage_gemm<LD, (STEPPER & F32_STAGES) != 0>(xb, th, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G3
       double2 cv = cb[own<LD>(ob, e)];
       cv.x -= (hh / 6.0) * gr;
       cv.y -= (hh / 6.0) * gi;
@@ -738,7 +799,7 @@ const double hh = h * h;
     __syncthreads();
     store_mat_ld<LD>(xb, G1, ob);  // X4
     __syncthreads();
-    stage_gemm<LD>(xb, t1, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G4
+    stage_gemm<LD, (STEPPER & F32_STAGES) != 0>(xb, t1, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G4
       d.r[e] -= (h / 6.0) * gr;
       d.i[e] -= (h / 6.0) * gi;
     });
@@ -756,8 +817,8 @@ const double hh = h * h;
     }
     __syncthreads();
     Mat G1, G2, G3;
-    stage_gemm<LD>(cb, tA, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
-    stage_gemm<LD>(xb, tB, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
+    stage_gemm<LD, (STEPPER & F32_STAGES) != 0>(cb, tA, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G1.r[e] = gr; G1.i[e] = gi; });
+    stage_gemm<LD, (STEPPER & F32_STAGES) != 0>(xb, tB, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G2.r[e] = gr; G2.i[e] = gi; });
     __syncthreads();
     // X3 = c + 2h/3 c' - h^2 (2/9) G1
 #pragma unroll
@@ -767,7 +828,7 @@ const double hh = h * h;
                                 cv.y + (2.0 * h / 3.0) * d.i[e] - hh * (2.0 / 9.0) * G1.i[e]);
     }
     __syncthreads();
-    stage_gemm<LD>(xb, tD, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G3.r[e] = gr; G3.i[e] = gi; });
+    stage_gemm<LD, (STEPPER & F32_STAGES) != 0>(xb, tD, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) { G3.r[e] = gr; G3.i[e] = gi; });
     __syncthreads();
     // X4 = c + h/3 c' - h^2 (G1/9 - G2/18)
 #pragma unroll
@@ -781,7 +842,7 @@ const double hh = h * h;
     Mat& X5 = G1;
     Mat& X6 = G2;
     Mat& T7 = G3;
-    stage_gemm<LD>(xb, tB, gidx, g2, ob, lane, cofs, [&](int e, double a4, double b4) {
+    stage_gemm<LD, (STEPPER & F32_STAGES) != 0>(xb, tB, gidx, g2, ob, lane, cofs, [&](int e, double a4, double b4) {
       const double2 cv = cb[own<LD>(ob, e)];
       const double dr = d.r[e], di = d.i[e];
       const double a1 = G1.r[e], b1 = G1.i[e], a2 = G2.r[e], b2 = G2.i[e], a3 = G3.r[e], b3 = G3.i[e];
@@ -799,7 +860,7 @@ const double hh = h * h;
     __syncthreads();
     store_mat_ld<LD>(xb, X5, ob);
     __syncthreads();
-    stage_gemm<LD>(xb, tC, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G5
+    stage_gemm<LD, (STEPPER & F32_STAGES) != 0>(xb, tC, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G5
       T7.r[e] += hh * (8.0 / 11.0) * gr;
       T7.i[e] += hh * (8.0 / 11.0) * gi;
       double2 cv = cb[own<LD>(ob, e)];
@@ -812,7 +873,7 @@ const double hh = h * h;
     __syncthreads();
     store_mat_ld<LD>(xb, X6, ob);
     __syncthreads();
-    stage_gemm<LD>(xb, tC, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G6
+    stage_gemm<LD, (STEPPER & F32_STAGES) != 0>(xb, tC, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G6
       double2 cv = cb[own<LD>(ob, e)];
       cv.x += hh * (2.0 / 15.0) * gr;
       cv.y += hh * (2.0 / 15.0) * gi;
@@ -823,7 +884,7 @@ const double hh = h * h;
     __syncthreads();
     store_mat_ld<LD>(xb, T7, ob);  // X7
     __syncthreads();
-    stage_gemm<LD>(xb, tE, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G7
+    stage_gemm<LD, (STEPPER & F32_STAGES) != 0>(xb, tE, gidx, g2, ob, lane, cofs, [&](int e, double gr, double gi) {  // G7
       d.r[e] -= h * (11.0 / 120.0) * gr;
       d.i[e] -= h * (11.0 / 120.0) * gi;
     });
@@ -1009,7 +1070,7 @@ __device__ __forceinline__ void prefetch_table_nodes(double2 (*tb)[MAXBOX + 1], 
 
 template <int STEPPER, bool BULK>
 __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
-  using T = Tab<STEPPER>;
+  using T = Tab<STEPPER & 7>;
   SplitLds& s = split_lds;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -1056,7 +1117,7 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
   Gidx gx;
   {
     const int W = 2 * S.kd + 1;
-    const int iA = 16 * RT + (lane & 15);
+    const int iA = 16 * RT + a_row<(STEPPER & F32_STAGES) != 0>(lane & 15);
     const int baseA = (s.bhk[iA][0] + S.hd) * W + (s.bhk[iA][1] + S.kd);
 #pragma unroll
     for (int q = 0; q < 16; q += 2) {
@@ -1370,8 +1431,12 @@ __global__ __launch_bounds__(ST, 1) void forward_split_kernel(FwdArgs a) {
 hipError_t launch_forward(int stepper, const FwdArgs& a, hipStream_t stream) {
   dim3 grid(a.n_pairs), block(FT);
   const bool bulk = a.y_bottom != nullptr;
-  if (stepper >= 2) {  // every splitting method; vacuum start only
+  if ((stepper & 7) >= 2) {  // every splitting method; vacuum start only
     hipLaunchKernelGGL((forward_kernel<2, false>), grid, block, 0, stream, a);
+  } else if (stepper == (0 | F32_STAGES)) {  // FP32 stage products; vacuum start only
+    hipLaunchKernelGGL((forward_kernel<0 | F32_STAGES, false>), grid, block, 0, stream, a);
+  } else if (stepper == (1 | F32_STAGES)) {
+    hipLaunchKernelGGL((forward_kernel<1 | F32_STAGES, false>), grid, block, 0, stream, a);
   } else if (stepper == 0) {
     if (bulk)
       hipLaunchKernelGGL((forward_kernel<0, true>), grid, block, 0, stream, a);
@@ -1390,10 +1455,12 @@ hipError_t launch_forward_split(int stepper, const FwdArgs& a, hipStream_t strea
   FwdArgs arg = a;
   void* params[] = {&arg};
   const bool bulk = a.y_bottom != nullptr;
-  const void* f = stepper == 0 ? (bulk ? reinterpret_cast<const void*>(&forward_split_kernel<0, true>)
-                                       : reinterpret_cast<const void*>(&forward_split_kernel<0, false>))
-                               : (bulk ? reinterpret_cast<const void*>(&forward_split_kernel<1, true>)
-                                       : reinterpret_cast<const void*>(&forward_split_kernel<1, false>));
+  const void* f = stepper == (0 | F32_STAGES)   ? reinterpret_cast<const void*>(&forward_split_kernel<0 | F32_STAGES, false>)
+                  : stepper == (1 | F32_STAGES) ? reinterpret_cast<const void*>(&forward_split_kernel<1 | F32_STAGES, false>)
+                  : stepper == 0 ? (bulk ? reinterpret_cast<const void*>(&forward_split_kernel<0, true>)
+                                         : reinterpret_cast<const void*>(&forward_split_kernel<0, false>))
+                                 : (bulk ? reinterpret_cast<const void*>(&forward_split_kernel<1, true>)
+                                         : reinterpret_cast<const void*>(&forward_split_kernel<1, false>));
   return hipLaunchCooperativeKernel(f, dim3(2 * a.n_pairs), dim3(ST), params, 0, stream);
 }
 
@@ -1402,10 +1469,12 @@ int forward_split_max_pairs(int device) {
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
   // the fewest resident workgroups per CU over every instantiation a split launch may use
-  const void* fs[4] = {reinterpret_cast<const void*>(&forward_split_kernel<0, false>),
+  const void* fs[6] = {reinterpret_cast<const void*>(&forward_split_kernel<0, false>),
                        reinterpret_cast<const void*>(&forward_split_kernel<1, false>),
                        reinterpret_cast<const void*>(&forward_split_kernel<0, true>),
-                       reinterpret_cast<const void*>(&forward_split_kernel<1, true>)};
+                       reinterpret_cast<const void*>(&forward_split_kernel<1, true>),
+                       reinterpret_cast<const void*>(&forward_split_kernel<0 | F32_STAGES, false>),
+                       reinterpret_cast<const void*>(&forward_split_kernel<1 | F32_STAGES, false>)};
   int per_cu = 1 << 30;
   for (const void* f : fs) {
     int n = 0;
