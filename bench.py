@@ -151,7 +151,7 @@ def cpu_model():
 def kernel_source_hash():
     """sha256 of the sources the forward kernel is built from."""
     h = hashlib.sha256()
-    for f in ("rheed_forward.hip", "rheed_gj.h", "rheed_internal.h"):
+    for f in ("rheed_forward.hip", "rheed_forward_all.hip", "rheed_gj.h", "rheed_internal.h"):
         with open(os.path.join(ROOT, "paper_2306_00271_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -220,13 +220,18 @@ def uneven_forward(n_structures, steps=2, cpu=True):
     tune = {}
 
     def timed(w, reps, autotune=False):
+        def note(msg):
+            print(f"[uneven] {len(w.structures)} structures: {msg}", file=sys.stderr, flush=True)
         plan = api.plan_for(w, stepper="rk6")
         U = plan.potential(api.atoms_for(w, dev))
         ang = api.angles_for(w, dev)
+        torch.cuda.synchronize()
+        note(f"plan and tables ready ({plan.n_pairs} pairs, {U.numel() * 16 / 2**30:.2f} GiB of tables)")
         if autotune:  # launch configuration picked by timing the candidates on this batch
             tune.update(plan.autotune(U, ang, reps=1))
         plan.forward(U, ang)
         torch.cuda.synchronize()
+        note("warm-up forward done")
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -236,7 +241,10 @@ def uneven_forward(n_structures, steps=2, cpu=True):
         torch.cuda.synchronize()
         return plan, e0.elapsed_time(e1) / reps, out
 
-    plan, ms, out = timed(wl, steps, autotune=True)
+    # the launch configuration is tuned on batches of up to 64 structures;
+    # larger ones (the full 1024-structure workload) run the default, the
+    # one persistent launch over every pair
+    plan, ms, out = timed(wl, steps, autotune=n_structures <= 64)
     n_pairs = plan.n_pairs
     bad = invalid_pairs(out["intensity"], out["status"], wl.absorption)
     big = [st for st in wl.structures if st.n_beams > 64]
@@ -246,10 +254,12 @@ def uneven_forward(n_structures, steps=2, cpu=True):
            "slices": {str(st.n_beams): st.n_slices for st in wl.structures},
            "autotune": {"chosen": tune.get("chosen"),
                         "candidates_ms": [round(c["ms"], 2) for c in tune.get("candidates", [])],
-                        "candidates": [("split" if c["split"] else "whole") + "/" +
+                        "candidates": ["one-launch-queue" if c.get("queue") else
+                                       ("split" if c["split"] else "whole") + "/" +
                                        ("cost-order" if c["large_cost_order"] else "pair-order")
-                                       for c in tune.get("candidates", [])]}}
-    if big:
+                                       for c in tune.get("candidates", [])]},
+           "one_launch": bool(plan.info.queue)}
+    if big and n_structures <= 64:
         wb = dataclasses.replace(wl, structures=big)
         pb, msb, outb = timed(wb, steps)
         nr = outb["n_rhst"].cpu().numpy()
@@ -281,14 +291,14 @@ def uneven_forward(n_structures, steps=2, cpu=True):
         # number of angles, so the mean over structures is the batch's mean per pair)
         import multiprocessing as mp
         cores = min(16, os.cpu_count() or 1)
-        jobs = [("uneven", s, "rk6", n_structures) for s in range(n_structures)]
+        jobs = [("uneven", s, "rk6", n_structures) for s in range(min(n_structures, 16))]
         t0 = time.perf_counter()
         with mp.get_context("spawn").Pool(cores) as pool:
             times = pool.map(_cpu_worker, jobs)
         cwall = time.perf_counter() - t0
         mean = float(sum(times) / len(times))
         res["cpu_baseline"] = {"value": round(cores / mean, 4), "unit": "points/s", "cores": cores, "kind": "oracle",
-                               "sample": f"one pair of each of the {n_structures} structures (one angle each), "
+                               "sample": f"one pair of each of the first {len(jobs)} structures (one angle each), "
                                          f"oracle forward, mean {mean:.2f} s per pair; {cores} processes x 1 BLAS "
                                          f"thread, {cwall:.1f} s wall"}
     return res
@@ -477,17 +487,20 @@ def stepper_comparison(steps=2):
 
 
 def large_source_hash():
-    """sha256 of the sources the kernel for N > 64 is built from."""
+    """sha256 of the sources the kernel for N > 64 and the one-launch queue
+    kernel are built from."""
     h = hashlib.sha256()
-    for f in ("rheed_forward_large.hip", "rheed_large.h", "rheed_gj.h", "rheed_internal.h"):
+    for f in ("rheed_forward_large.hip", "rheed_forward.hip", "rheed_forward_all.hip", "rheed_large.h", "rheed_gj.h",
+              "rheed_internal.h"):
         with open(os.path.join(ROOT, "paper_2306_00271_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
 def traffic_probe_uneven(n_structures):
-    """One forward launch of the N > 64 pairs of the uneven-N variant and one
-    device copy of 1 GiB, for FETCH_SIZE / WRITE_SIZE counter runs."""
+    """One forward launch of the N > 64 pairs of the uneven-N variant, one
+    one-launch forward of the whole batch and one device copy of 1 GiB, for
+    FETCH_SIZE / WRITE_SIZE counter runs."""
     import dataclasses
     import torch
     from paper_2306_00271_amd import api
@@ -498,12 +511,19 @@ def traffic_probe_uneven(n_structures):
     plan = api.plan_for(w, stepper="rk6")
     U = plan.potential(api.atoms_for(w, dev))
     plan.forward(U, api.angles_for(w, dev))
+    torch.cuda.synchronize()
+    del plan, U
+    whole = api.plan_for(wl, stepper="rk6")
+    assert whole.info.queue
+    Uw = whole.potential(api.atoms_for(wl, dev))
+    whole.forward(Uw, api.angles_for(wl, dev))
     src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": src.numel() * 8, "source_sha256": large_source_hash(),
-                      "kernel": "forward_large_kernel<1>", "pairs": plan.n_pairs}))
+                      "kernels": ["forward_large_kernel<1>", "forward_queue_kernel<1>"],
+                      "pairs": [len(w.structures) * len(w.theta0), whole.n_pairs]}))
 
 
 # -------------------------------------------------------------------- bench

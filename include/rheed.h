@@ -162,6 +162,8 @@ typedef struct {
   int32_t large_pairs;       /* pairs of structures with N > 64 */
   int32_t large_slots;       /* workgroups (state slots of 768 KiB each, plan-owned) that run them */
   size_t bulk_workspace;     /* bytes rheed_bulk_reflection needs beyond fwd_workspace (0: not available) */
+  int32_t queue;             /* 1 if rheed_forward (without a workspace) runs the batch as one persistent
+                                launch over a queue of pairs of both kinds (N <= 64 and N > 64) */
 } rheed_plan_info;
 
 /* Vacuum wavenumber gamma (1/A) and the coefficient kappa (1/(A^2 V)) of the
@@ -238,6 +240,12 @@ rheed_status rheed_potential_backward_noalloc(rheed_plan_t plan, const double* a
  *  n_rhst     device int32 [n_pairs] number of right-hand-side transformations, or NULL
  *  workspace  device, >= fwd_workspace bytes, to keep the states rheed_backward
  *             needs; NULL when no backward pass follows.
+ * A batch that mixes N <= 64 and N > 64 (RK stepper, FP64 stages, layout
+ * AUTO or WHOLE) runs, when no workspace is given, as one persistent launch:
+ * a workgroup per CU takes pairs dearest first from a counter in plan-owned
+ * memory (set to zero by a small kernel launched before it) and runs each
+ * on the path of its N (rheed_plan_info.queue; rheed_autotune compares it
+ * with two launches).
  * With the split layout the launch is cooperative and uses exchange blocks
  * owned by the plan, so forward calls on one plan must not overlap (issue them
  * on one stream).  Like every compute call, it only launches kernels (no
@@ -296,21 +304,24 @@ rheed_status rheed_bulk_reflection(rheed_plan_t plan, const void* U_tables, cons
                                    int32_t* pair_status, void* workspace, size_t ws_bytes, void* stream);
 
 /* Launch configurations rheed_autotune compares (at most RHEED_TUNE_MAX). */
-#define RHEED_TUNE_MAX 4
+#define RHEED_TUNE_MAX 8
 typedef struct {
   int32_t n_candidates;
   int32_t chosen;                           /* index of the configuration the plan now uses */
   int32_t split[RHEED_TUNE_MAX];            /* 1: pairs with N <= 64 on the two-workgroup layout */
   int32_t large_cost_order[RHEED_TUNE_MAX]; /* 1: pairs with N > 64 dearest first, 0: in pair order */
+  int32_t queue[RHEED_TUNE_MAX];            /* 1: one persistent launch over a batch mixing N <= 64 and N > 64 */
   float ms[RHEED_TUNE_MAX];                 /* mean duration of one rheed_forward call */
 } rheed_tune_report;
 
 /* Picks the launch configuration of rheed_forward for this plan by timing
  * the candidates on the caller's inputs (the batching of Sec. 3.5 over
  * (structure, angle) pairs is this library's; the paper fixes no schedule):
- * the layout of the N <= 64 pairs (split or whole, where the plan's layout
- * option is AUTO and the batch fits the split layout) and the order in which
- * the N > 64 kernel takes its pairs (by estimated cost or in pair order).
+ * for a batch mixing N <= 64 and N > 64, one persistent launch over both;
+ * and two launches with the layout of the N <= 64 pairs (split or whole,
+ * where the plan's layout option is AUTO and the batch fits the split
+ * layout) and the order in which the N > 64 kernel takes its pairs (by
+ * estimated cost or in pair order).
  * Each candidate runs one untimed and `reps` (1..1000) timed forward calls
  * without state saving on `stream`, timed with HIP events; the fastest is
  * kept by the plan for every later rheed_forward.  U_tables, angles,

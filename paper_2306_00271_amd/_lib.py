@@ -69,10 +69,11 @@ class PlanInfo(C.Structure):
         ("large_pairs", C.c_int32),
         ("large_slots", C.c_int32),
         ("bulk_workspace", C.c_size_t),
+        ("queue", C.c_int32),
     ]
 
 
-RHEED_TUNE_MAX = 4
+RHEED_TUNE_MAX = 8
 
 
 class TuneReport(C.Structure):
@@ -81,6 +82,7 @@ class TuneReport(C.Structure):
         ("chosen", C.c_int32),
         ("split", C.c_int32 * RHEED_TUNE_MAX),
         ("large_cost_order", C.c_int32 * RHEED_TUNE_MAX),
+        ("queue", C.c_int32 * RHEED_TUNE_MAX),
         ("ms", C.c_float * RHEED_TUNE_MAX),
     ]
 

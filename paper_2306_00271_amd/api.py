@@ -235,7 +235,7 @@ class Plan:
         n = rep.n_candidates
         return {"chosen": rep.chosen,
                 "candidates": [{"split": bool(rep.split[c]), "large_cost_order": bool(rep.large_cost_order[c]),
-                                "ms": float(rep.ms[c])} for c in range(n)]}
+                                "queue": bool(rep.queue[c]), "ms": float(rep.ms[c])} for c in range(n)]}
 
     def backward(self, U: torch.Tensor, angles: torch.Tensor, dL_dI: torch.Tensor,
                  workspace: torch.Tensor) -> torch.Tensor:

@@ -15,8 +15,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librheed.so")
-SOURCES = ["rheed_api.cpp", "rheed_forward.hip", "rheed_potential.hip", "rheed_backward.hip", "rheed_probe.hip",
-           "rheed_forward_large.hip", "rheed_bulk.hip"]
+# rheed_forward_all.hip is the one unit of rheed_forward.hip and rheed_forward_large.hip
+SOURCES = ["rheed_api.cpp", "rheed_forward_all.hip", "rheed_potential.hip", "rheed_backward.hip", "rheed_probe.hip",
+           "rheed_bulk.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

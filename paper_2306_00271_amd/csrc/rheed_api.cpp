@@ -73,7 +73,15 @@ struct rheed_plan_s {
   bool large_cost_order = true;  // which of the two lists rheed_forward uses
   char* d_lscratch = nullptr;    // per resident workgroup of the large kernel: its state slot
   int large_slots = 0;
+  int scratch_slots = 0;         // slots allocated: max of large_slots and queue_grid
+  // one persistent launch over a batch mixing N <= 64 and N > 64 (RK, FP64)
+  bool queue_ok = false;         // the batch can run on forward_queue_kernel
+  bool use_queue = false;        // rheed_forward runs it (autotune may switch it off)
+  int queue_grid = 0;            // its workgroups
+  int* d_queue_order = nullptr;  // every pair, dearest first
+  int* d_queue_counter = nullptr;
   std::vector<int> large_plain;
+  std::vector<int> queue_order;
 };
 
 namespace {
@@ -362,6 +370,19 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     };
     std::stable_sort(P->large_pairs.begin(), P->large_pairs.end(), [&](int x, int y) { return cost(x) > cost(y); });
   }
+  // the queue of the one-launch path: every pair by estimated cost, dearest
+  // first (per slice about 9.5 us x (column blocks)^2 on the large path and
+  // 60 us on the one-workgroup path, as measured on MI355X)
+  {
+    auto qcost = [&](int p) {
+      const StructDev& d = P->hs[P->pair_struct[p]];
+      const double nb = (d.n_beams + 15) / 16;
+      return d.n_slices * (d.n_beams > NP ? 9.5 * nb * nb : 60.0);
+    };
+    P->queue_order.resize(P->n_pairs);
+    for (int p = 0; p < P->n_pairs; ++p) P->queue_order[p] = p;
+    std::stable_sort(P->queue_order.begin(), P->queue_order.end(), [&](int x, int y) { return qcost(x) > qcost(y); });
+  }
   // the adjoint and its state saving handle N <= 64 and the FP64 RK steppers only
   if (!P->large_pairs.empty() || P->splitting || opts->stage_precision != RHEED_STAGES_FP64) {
     P->fwd_ws = 0;
@@ -382,6 +403,16 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
         return fail(RHEED_E_HIP, "the kernel for N > 64 cannot be resident on this device");
       }
       P->large_slots = std::min(n_large, slots);
+      P->scratch_slots = P->large_slots;
+      P->queue_ok = n_small > 0 && !P->splitting && opts->stage_precision == RHEED_STAGES_FP64 &&
+                    opts->layout != RHEED_LAYOUT_SPLIT;
+      if (P->queue_ok) {
+        const int qs = forward_queue_slots(dev);
+        P->queue_ok = qs > 0;
+        P->queue_grid = std::min(P->n_pairs, qs);
+        P->scratch_slots = std::max(P->scratch_slots, P->queue_grid);
+        P->use_queue = P->queue_ok;
+      }
     }
     if (opts->layout == RHEED_LAYOUT_SPLIT && !P->split && n_small > 0) {
       const int mx = P->split_max;
@@ -403,7 +434,9 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (n_large > 0 && n_small > 0 && (e = hipMalloc(&P->d_small_pairs, sizeof(int) * n_small)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_large_pairs, sizeof(int) * n_large)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_large_plain, sizeof(int) * n_large)) != hipSuccess) ||
-      (n_large > 0 && (e = hipMalloc(&P->d_lscratch, (size_t)LSLOT_BYTES * P->large_slots)) != hipSuccess)) {
+      (n_large > 0 && (e = hipMalloc(&P->d_lscratch, (size_t)LSLOT_BYTES * P->scratch_slots)) != hipSuccess) ||
+      (P->queue_ok && (e = hipMalloc(&P->d_queue_order, sizeof(int) * P->n_pairs)) != hipSuccess) ||
+      (P->queue_ok && (e = hipMalloc(&P->d_queue_counter, sizeof(int))) != hipSuccess)) {
     rheed_plan_destroy(P);
     return e == hipErrorOutOfMemory ? fail(RHEED_E_NOMEM, "plan_create: device allocation") : hip_fail(e, "hipMalloc");
   }
@@ -424,6 +457,8 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (P->d_large_pairs && (e = hipMemcpy(P->d_large_pairs, P->large_pairs.data(), sizeof(int) * n_large,
                                           hipMemcpyHostToDevice)) != hipSuccess) ||
       (P->d_large_plain && (e = hipMemcpy(P->d_large_plain, P->large_plain.data(), sizeof(int) * n_large,
+                                          hipMemcpyHostToDevice)) != hipSuccess) ||
+      (P->d_queue_order && (e = hipMemcpy(P->d_queue_order, P->queue_order.data(), sizeof(int) * P->n_pairs,
                                           hipMemcpyHostToDevice)) != hipSuccess) ||
       (e = hipDeviceSynchronize()) != hipSuccess) {
     rheed_plan_destroy(P);
@@ -456,6 +491,8 @@ rheed_status rheed_plan_destroy(rheed_plan_t P) {
   if (P->d_large_pairs) (void)hipFree(P->d_large_pairs);
   if (P->d_large_plain) (void)hipFree(P->d_large_plain);
   if (P->d_lscratch) (void)hipFree(P->d_lscratch);
+  if (P->d_queue_order) (void)hipFree(P->d_queue_order);
+  if (P->d_queue_counter) (void)hipFree(P->d_queue_counter);
   delete P;
   return RHEED_OK;
 }
@@ -475,6 +512,7 @@ rheed_status rheed_plan_get_info(rheed_plan_t P, rheed_plan_info* info) {
   info->large_pairs = (int32_t)P->large_pairs.size();
   info->large_slots = P->large_slots;
   info->bulk_workspace = P->large_pairs.empty() ? bulk_extra(P) : 0;
+  info->queue = (P->use_queue && P->queue_ok) ? 1 : 0;
   return RHEED_OK;
 }
 
@@ -593,6 +631,20 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
   a.sp = P->sp;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
+  if (P->use_queue && P->queue_ok && !workspace && !y_bottom && !skip) {
+    // one persistent launch over the whole batch
+    QueueArgs q{};
+    q.large.f = a;
+    q.large.f.pair_list = nullptr;
+    q.large.f.n_pairs = P->n_pairs;
+    q.large.scratch = P->d_lscratch;
+    q.large.n_slots = P->scratch_slots;
+    q.order = P->d_queue_order;
+    q.counter = P->d_queue_counter;
+    q.n = P->n_pairs;
+    e = launch_forward_queue((int)P->opts.stepper, q, P->queue_grid, st);
+    return e == hipSuccess ? RHEED_OK : hip_fail(e, "forward launch (one queue over the batch)");
+  }
   if (!P->small_pairs.empty()) {
     a.pair_list = P->d_small_pairs;  // null when every pair is small
     a.n_pairs = (int)P->small_pairs.size();
@@ -705,17 +757,23 @@ rheed_status rheed_autotune(rheed_plan_t P, const void* U_tables, const double* 
                             int32_t* pair_status, int32_t reps, void* stream, rheed_tune_report* report) {
   if (!P || !U_tables || !angles || !intensity || !pair_status || reps < 1 || reps > 1000)
     return fail(RHEED_E_INVALID, "autotune: null argument or reps outside [1, 1000]");
-  // candidates: the N <= 64 layouts the plan allows (split needs its exchange
-  // blocks, allocated when the batch fits) x the N > 64 pair orders
-  std::vector<std::pair<bool, bool>> cand;
+  // candidates: one persistent launch over the batch (when it mixes N <= 64
+  // and N > 64), and two launches with the N <= 64 layouts the plan allows
+  // (split needs its exchange blocks, allocated when the batch fits) x the
+  // N > 64 pair orders
+  struct Cand {
+    bool split, cost_order, queue;
+  };
+  std::vector<Cand> cand;
   const bool has_small = !P->small_pairs.empty(), has_large = !P->large_pairs.empty();
+  if (P->queue_ok) cand.push_back({false, true, true});
   std::vector<bool> layouts;
   if (!has_small) layouts = {P->split};
   else if (P->d_xch && P->opts.layout == RHEED_LAYOUT_AUTO) layouts = {true, false};
   else layouts = {P->split};
   std::vector<bool> orders = has_large ? std::vector<bool>{true, false} : std::vector<bool>{P->large_cost_order};
   for (bool l : layouts)
-    for (bool o : orders) cand.push_back({l, o});
+    for (bool o : orders) cand.push_back({l, o, false});
   if ((int)cand.size() > RHEED_TUNE_MAX) cand.resize(RHEED_TUNE_MAX);
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -724,12 +782,13 @@ rheed_status rheed_autotune(rheed_plan_t P, const void* U_tables, const double* 
     if (e0) (void)hipEventDestroy(e0);
     return hip_fail(e, "autotune: hipEventCreate");
   }
-  const bool keep_split = P->split, keep_order = P->large_cost_order;
+  const bool keep_split = P->split, keep_order = P->large_cost_order, keep_queue = P->use_queue;
   std::vector<float> ms(cand.size(), 0.0f);
   rheed_status rs = RHEED_OK;
   for (size_t c = 0; c < cand.size() && rs == RHEED_OK; ++c) {
-    P->split = cand[c].first;
-    P->large_cost_order = cand[c].second;
+    P->split = cand[c].split;
+    P->large_cost_order = cand[c].cost_order;
+    P->use_queue = cand[c].queue;
     rs = rheed_forward(P, U_tables, angles, intensity, nullptr, pair_status, nullptr, nullptr, 0, stream);  // untimed
     if (rs != RHEED_OK) break;
     if ((e = hipEventRecord(e0, st)) != hipSuccess) { rs = hip_fail(e, "autotune: hipEventRecord"); break; }
@@ -748,20 +807,23 @@ rheed_status rheed_autotune(rheed_plan_t P, const void* U_tables, const double* 
   if (rs != RHEED_OK) {
     P->split = keep_split;
     P->large_cost_order = keep_order;
+    P->use_queue = keep_queue;
     return rs;
   }
   size_t best = 0;
   for (size_t c = 1; c < cand.size(); ++c)
     if (ms[c] < ms[best]) best = c;
-  P->split = cand[best].first;
-  P->large_cost_order = cand[best].second;
+  P->split = cand[best].split;
+  P->large_cost_order = cand[best].cost_order;
+  P->use_queue = cand[best].queue;
   if (report) {
     *report = rheed_tune_report{};
     report->n_candidates = (int32_t)cand.size();
     report->chosen = (int32_t)best;
     for (size_t c = 0; c < cand.size(); ++c) {
-      report->split[c] = cand[c].first ? 1 : 0;
-      report->large_cost_order[c] = cand[c].second ? 1 : 0;
+      report->split[c] = cand[c].split ? 1 : 0;
+      report->large_cost_order[c] = cand[c].cost_order ? 1 : 0;
+      report->queue[c] = cand[c].queue ? 1 : 0;
       report->ms[c] = ms[c];
     }
   }

@@ -87,7 +87,10 @@ struct Lds {
   int flag_singular;
 };
 
-__shared__ Lds fwd_lds;
+// The LDS of the one-workgroup kernel.  Every forward kernel of the library
+// shares one static LDS allocation (rheed_forward_all.hip), so that a
+// launch whose workgroups run pairs of both kinds holds one, not both.
+__device__ Lds& fwd_lds_ref();
 
 // top^{-1} for the leading n x n block of the 64 x 64 matrix in s.xb[0 .. NP NP)
 // (row major), written back over it (identity outside the n x n block) and,
@@ -96,7 +99,7 @@ __shared__ Lds fwd_lds;
 // add to those of the RK stages.
 template <bool WITH_T>
 __device__ __noinline__ void invert_top(int n, double2* t) {
-  Lds& s = fwd_lds;
+  Lds& s = fwd_lds_ref();
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double2 z[2 * NP / FW];
 #pragma unroll
@@ -271,17 +274,18 @@ __device__ __forceinline__ void load_nodes(Lds& s, const double2* __restrict__ U
   }
 }
 
-// BULK: the state starts from a bulk's [I; Y] (a.y_bottom) and pairs with
-// a.skip[p] set are not run; the vacuum instantiations carry neither.
+// Pair p on one workgroup of FT threads (forward_kernel; also the N <= 64
+// pairs of forward_queue_kernel).  BULK: the state starts from a bulk's
+// [I; Y] (a.y_bottom) and pairs with a.skip[p] set are not run; the vacuum
+// instantiations carry neither.
 template <int STEPPER, bool BULK>
-__global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
+__device__ __forceinline__ void small_pair(const FwdArgs& a, int p) {
   using T = Tab<STEPPER & 7>;
-  Lds& s = fwd_lds;
+  Lds& s = fwd_lds_ref();
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = tid >> 6;
   const int RT = w & 3, CH = w >> 2;   // row tile, column block of this wave
-  const int p = a.pair_list ? a.pair_list[blockIdx.x] : blockIdx.x;
   if constexpr (BULK) {
     if (a.skip && a.skip[p]) return;
   }
@@ -732,6 +736,11 @@ __global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
       if (a.nrhst) a.nrhst[p] = nrhst;
     }
   }
+}
+
+template <int STEPPER, bool BULK>
+__global__ __launch_bounds__(FT, 1) void forward_kernel(FwdArgs a) {
+  small_pair<STEPPER, BULK>(a, a.pair_list ? a.pair_list[blockIdx.x] : blockIdx.x);
 }
 #undef OWN
 

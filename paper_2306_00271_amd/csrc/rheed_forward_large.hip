@@ -113,7 +113,9 @@ struct LLds {
   int bad;
 };
 
-__shared__ LLds large_lds;
+// The LDS of the large kernel, in the forward kernels' shared allocation
+// (rheed_forward_all.hip).
+__device__ LLds& large_lds_ref();
 
 struct LMat {
   double r[LNE];
@@ -392,7 +394,7 @@ template <int KQ>
 __device__ __forceinline__ void bab_block(double2* __restrict__ cg, double2* __restrict__ dg, int cb, int nk, int n0,
                                        double w0, double w1, double w2, double a0, double a1, double a2, bool drift,
                                        double h, int N) {
-  LLds& s = large_lds;
+  LLds& s = large_lds_ref();
   constexpr int SL = LTab<2>::nodes + 1;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double g2[4];
@@ -495,7 +497,7 @@ __device__ __forceinline__ void bab_blocks(double2* cg, double2* dg, int ncb, in
 template <int STEPPER, int KQ>
 __device__ __forceinline__ void slice_block(double2* __restrict__ cg, double2* __restrict__ dg, int cb, int nb,
                                          double h, int N) {
-  LLds& s = large_lds;
+  LLds& s = large_lds_ref();
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double g2[4];
 #pragma unroll
@@ -559,7 +561,7 @@ __device__ __noinline__ void slice_all(double2* __restrict__ cg, double2* __rest
 // registers are allocated for this loop alone.
 __device__ __noinline__ void elim_record(const double2* __restrict__ cg, const double2* __restrict__ dg,
                                          double2* __restrict__ frec, int N, int which) {
-  LLds& s = large_lds;
+  LLds& s = large_lds_ref();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int n = __builtin_amdgcn_readfirstlane(N);
   double2 z[LRM][2];
@@ -589,7 +591,7 @@ __device__ __noinline__ void elim_record(const double2* __restrict__ cg, const d
 // replayed on the rows of P, each column put at its pivot step; c <- I.
 __device__ __noinline__ void replay_p(double2* __restrict__ cg, double2* __restrict__ dg,
                                       const double2* __restrict__ frec, int N) {
-  LLds& s = large_lds;
+  LLds& s = large_lds_ref();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int n = __builtin_amdgcn_readfirstlane(N);
   const int p0 = s.pos[lane], p1 = s.pos[64 + lane];
@@ -623,7 +625,7 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
   using T = LTab<STEPPER>;
   constexpr int SL = T::nodes + 1;
   const FwdArgs& a = A.f;
-  LLds& s = large_lds;
+  LLds& s = large_lds_ref();
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double2* __restrict__ cg = reinterpret_cast<double2*>(slot + LSLOT_C);
   double2* __restrict__ dg = reinterpret_cast<double2*>(slot + LSLOT_D);

@@ -29,4 +29,19 @@ struct LargeArgs {
 hipError_t launch_forward_large(int stepper, const LargeArgs& a, hipStream_t stream);
 int forward_large_slots(int device);  // resident workgroups of the large kernel on the device
 
+// One persistent launch over a batch of pairs with N <= 64 and N > 64
+// (forward_queue_kernel): workgroups take pairs in the order of `order`
+// from a counter in device memory; the N <= 64 pairs run the one-workgroup
+// path, the others the large path in the workgroup's state slot.
+struct QueueArgs {
+  LargeArgs large;   // large.f: the forward arguments of the batch (RK, vacuum start, no state saving);
+                     // large.scratch / n_slots: one state slot per workgroup
+  const int* order;  // [n] pairs, dearest first
+  int* counter;      // device int, set to 0 by the launch before the workgroups start
+  int n;
+  int pad;
+};
+hipError_t launch_forward_queue(int stepper, const QueueArgs& q, int grid, hipStream_t stream);
+int forward_queue_slots(int device);  // resident workgroups of forward_queue_kernel on the device
+
 }  // namespace rheed

@@ -180,7 +180,8 @@ def test_graph_capture_of_a_mixed_forward():
 
 def test_autotune_picks_the_fastest_candidate_and_keeps_the_results():
     """rheed_autotune on a batch with N = 45 and N = 91 structures times the
-    four candidates (split or whole layout for N <= 64 x cost or pair order
+    five candidates (one persistent launch over both kinds of pair; two
+    launches with the split or whole layout for N <= 64 x cost or pair order
     for N > 64), keeps the fastest, and later forward calls still match the
     oracle."""
     import torch
@@ -193,14 +194,19 @@ def test_autotune_picks_the_fastest_candidate_and_keeps_the_results():
     U = plan.potential(api.atoms_for(wl, dev))
     ang = api.angles_for(wl, dev)
     before = plan.forward(U, ang)["intensity"].cpu().numpy()
+    assert plan.info.queue == 1
     rep = plan.autotune(U, ang, reps=2)
     cands = rep["candidates"]
-    assert len(cands) == 4
-    assert {(c["split"], c["large_cost_order"]) for c in cands} == {(a, b) for a in (True, False) for b in (True, False)}
+    assert len(cands) == 5
+    assert cands[0]["queue"] and not any(c["queue"] for c in cands[1:])
+    assert {(c["split"], c["large_cost_order"]) for c in cands[1:]} == {(a, b) for a in (True, False)
+                                                                        for b in (True, False)}
     assert all(c["ms"] > 0.0 for c in cands)
-    best = min(range(4), key=lambda c: cands[c]["ms"])
+    best = min(range(5), key=lambda c: cands[c]["ms"])
     assert rep["chosen"] == best
-    assert plan.split == cands[best]["split"]
+    assert plan.info.queue == int(cands[best]["queue"])
+    if not cands[best]["queue"]:
+        assert plan.split == cands[best]["split"]
     out = plan.forward(U, ang)
     torch.cuda.synchronize()
     after = out["intensity"].cpu().numpy()
@@ -291,3 +297,39 @@ def test_thick_slab_without_transformations_is_flagged():
     assert (res["n_rhst"] == 0).all()
     assert np.isin(st, [1, 2, 4]).all()
     assert np.all(np.isnan(res["intensity"][:, :91]))
+
+
+def test_one_launch_queue_matches_two_launches():
+    """A batch mixing N = 21, 61, 91 and 121 structures with different slice
+    counts: the one persistent launch (workgroups taking pairs of either kind
+    from one queue, dearest first) against the same batch in two launches
+    (layout SPLIT keeps the N <= 64 pairs on their own launch), and against
+    the oracle; then 300 pairs, more than the launch has workgroups."""
+    parts = [small_2d(n_beams=n, n_slices=L, thickness=0.1 * L, n_layers=2, n_angles=10, seed=80 + i)
+             for i, (n, L) in enumerate(((21, 30), (61, 24), (91, 20), (121, 12)))]
+    wl = dataclasses.replace(parts[0], structures=[p.structures[0] for p in parts])
+    res_q = gpu_forward(wl, stepper="rk6")
+    res_2 = gpu_forward(wl, stepper="rk6", layout="split")
+    assert res_q["plan"].info.queue == 1 and res_2["plan"].info.queue == 0
+    assert (res_q["status"] == 0).all()
+    assert np.abs(res_q["intensity"] - res_2["intensity"]).max() <= 1e-12 * np.abs(res_2["intensity"]).max()
+    A = len(wl.theta0)
+    for s, p in enumerate(parts):
+        N = p.structures[0].n_beams
+        ref, _, nr = oracle_forward(wl, s_idx=s, stepper="rk6")
+        e = eacc(res_q["intensity"][s * A:(s + 1) * A, :N], ref)
+        _report(f"queue structure {s} N={N} rhst={nr.tolist()} gpu={res_q['n_rhst'][s * A:(s + 1) * A].tolist()}", e)
+        assert e <= TOL
+        assert res_q["n_rhst"][s * A:(s + 1) * A].tolist() == nr.tolist()
+    parts = [small_2d(n_beams=n, n_slices=6, thickness=0.6, n_layers=1, n_angles=150, seed=90 + i,
+                      theta_range=(0.3, 6.0)) for i, n in enumerate((31, 69))]
+    wl = dataclasses.replace(parts[0], structures=[p.structures[0] for p in parts])
+    res_q = gpu_forward(wl, stepper="rk4")
+    assert res_q["plan"].info.queue == 1 and (res_q["status"] == 0).all()
+    idx = np.array([0, 77, 149])
+    for s, p in enumerate(parts):
+        N = p.structures[0].n_beams
+        ref, _, _ = oracle_forward(wl, s_idx=s, angle_idx=idx, stepper="rk4")
+        e = eacc(res_q["intensity"][s * 150 + idx, :N], ref)
+        _report(f"queue, 300 pairs, structure {s} N={N} (sampled)", e)
+        assert e <= TOL
