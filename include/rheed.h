@@ -87,9 +87,9 @@ typedef enum {
 typedef enum { RHEED_INTENSITY_FLUX = 0, RHEED_INTENSITY_PAPER = 1 } rheed_convention;
 
 /* Largest beam count N the kernels of this library handle.  Structures with
- * N <= 64 run on the one- or two-workgroup kernels (forward and adjoint);
- * structures with 64 < N <= 128 run on a kernel that keeps the state of a
- * pair in device memory owned by the plan (forward only). */
+ * N <= 64 run on the one- or two-workgroup kernels; structures with
+ * 64 < N <= 128 run on a kernel that keeps the state of a pair in device
+ * memory owned by the plan.  Both have the adjoint (RK steppers, FP64). */
 #define RHEED_MAX_BEAMS 128
 /* Largest potential-table row (rod differences) for N <= 64, and for N > 64. */
 #define RHEED_MAX_BOX 300
@@ -345,7 +345,12 @@ rheed_status rheed_autotune(rheed_plan_t plan, const void* U_tables, const doubl
  * of a segment is formed from its stored state and stepped up through the
  * segment by the RK step itself, then the adjoint walks back down.  The
  * adjoint does the same products for every K; a larger K keeps fewer states
- * (fwd_workspace) at the price of the R slots. */
+ * (fwd_workspace) at the price of the R slots.
+ * Pairs with N <= 64 keep their matrices padded to 64 beams; pairs with
+ * 64 < N <= 128 padded to 128 (four times the bytes per matrix), and with
+ * them also B^{-1} of the final reflection solve.  A plan holding both kinds
+ * sizes every pair's block for the larger.  Needs an RK stepper with FP64
+ * stages (RHEED_E_UNSUPPORTED otherwise). */
 rheed_status rheed_backward(rheed_plan_t plan, const void* U_tables, const double* angles,
                             const double* dL_dI, void* dL_dU, void* workspace, size_t ws_bytes,
                             void* stream);

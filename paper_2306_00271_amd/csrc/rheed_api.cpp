@@ -48,7 +48,8 @@ struct rheed_plan_s {
   std::vector<int> beams, pair_struct;
   std::vector<long long> table_off, atom_off, atom_struct;
   std::vector<int> bin_ptr, bin_jk;
-  CkptLayout ck{};
+  CkptLayout ck{};   // states kept for the adjoint, pairs with N <= 64 (matrices padded to 64)
+  CkptLayout ckl{};  // the same for pairs with 64 < N <= 128 (padded to 128); same pair stride
   size_t fwd_ws = 0, bwd_ws = 0;
   StructDev* d_structs = nullptr;
   int* d_beams = nullptr;
@@ -267,15 +268,17 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
                                            " for N = " + std::to_string(st.n_beams));
     }
     d.n_nodes = st.n_slices * P->nodes_per_slice + 1;
-    // (j, k) pairs of every rod difference g_j - g_k, grouped by table entry
-    // (for the adjoint's gradient assembly, which handles N <= 64)
+    // (j, k) pairs of every rod difference g_j - g_k, grouped by table entry,
+    // for the adjoint's gradient assembly: j * Wp + k, Wp the padded beam
+    // count of the structure's kernels (64 or 128)
     {
       const int W = 2 * d.kd + 1;
+      const int Wp = st.n_beams <= NP ? NP : NL;
       std::vector<std::vector<int>> lists(d.box);
-      for (int j = 0; j < ((st.n_beams <= NP) ? st.n_beams : 0); ++j)
+      for (int j = 0; j < st.n_beams; ++j)
         for (int k = 0; k < st.n_beams; ++k) {
           const int dh = st.beam_hk[2 * j] - st.beam_hk[2 * k], dk = st.beam_hk[2 * j + 1] - st.beam_hk[2 * k + 1];
-          lists[(dh + d.hd) * W + (dk + d.kd)].push_back(j * NP + k);
+          lists[(dh + d.hd) * W + (dk + d.kd)].push_back(j * Wp + k);
         }
       d.bin_ptr_off = (int)P->bin_ptr.size();
       d.bin_jk_off = (int)P->bin_jk.size();
@@ -343,21 +346,37 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
   // the final state, T = Q^{-1} of every transformation, with segments
   // longer than one slice also R = P Q^{-1} (the normalised P) of every
   // transformation, and one decision byte per slice
-  P->ck.every = opts->checkpoint_every;
-  P->ck.max_ckpt = (max_l + opts->checkpoint_every - 1) / opts->checkpoint_every + 1;
-  P->ck.state_bytes = (long long)2 * NP * NP * sizeof(double2);
-  const long long slot_bytes = (long long)max_l * NP * NP * sizeof(double2);
-  P->ck.q_off = P->ck.max_ckpt * P->ck.state_bytes;
-  P->ck.r_off = P->ck.every > 1 ? P->ck.q_off + slot_bytes : 0;
-  P->ck.flags_off = (P->ck.every > 1 ? P->ck.r_off : P->ck.q_off) + slot_bytes;
-  P->ck.pair_stride = ((P->ck.flags_off + max_l + 255) / 256) * 256;
+  // (with N > 64 also B^{-1} of the reflection solve); the layout of the
+  // pairs with N > 64 pads every matrix to 128, and both kinds share the
+  // larger pair stride
+  auto layout = [&](int w, bool binv) {
+    CkptLayout c{};
+    c.every = opts->checkpoint_every;
+    c.max_ckpt = (max_l + opts->checkpoint_every - 1) / opts->checkpoint_every + 1;
+    c.state_bytes = (long long)2 * w * w * sizeof(double2);
+    const long long mat = (long long)w * w * sizeof(double2), slot_bytes = (long long)max_l * mat;
+    c.q_off = c.max_ckpt * c.state_bytes;
+    c.r_off = c.every > 1 ? c.q_off + slot_bytes : 0;
+    const long long end = (c.every > 1 ? c.r_off : c.q_off) + slot_bytes;
+    c.binv_off = binv ? end : 0;
+    c.flags_off = end + (binv ? mat : 0);
+    c.pair_stride = ((c.flags_off + max_l + 255) / 256) * 256;
+    return c;
+  };
+  const bool wide = !P->large_pairs.empty();
+  P->ck = layout(NP, false);
+  if (wide) {
+    P->ckl = layout(NL, true);
+    P->ck.pair_stride = P->ckl.pair_stride = std::max(P->ck.pair_stride, P->ckl.pair_stride);
+  }
+  const int wmax = wide ? NL : NP;
   P->fwd_ws = (size_t)P->ck.pair_stride * P->n_pairs;
   // adjoint stage buffer: (v_r, g_r) of every stage of every slice
-  P->g_pair_stride = (long long)max_l * (P->opts.stepper == RHEED_RK4 ? 4 : 7) * 2 * NP;
+  P->g_pair_stride = (long long)max_l * (P->opts.stepper == RHEED_RK4 ? 4 : 7) * 2 * wmax;
   P->bwd_ws = (size_t)P->g_pair_stride * sizeof(double2) * P->n_pairs;
   if (P->ck.every > 1) {  // x at the transformed states of a segment
     P->xs_off = P->bwd_ws;
-    P->bwd_ws += (size_t)P->ck.every * NP * sizeof(double2) * P->n_pairs;
+    P->bwd_ws += (size_t)P->ck.every * wmax * sizeof(double2) * P->n_pairs;
   }
 
   // the N > 64 kernel takes its pairs dearest first: cost ~ (column blocks)^2 x slices
@@ -383,8 +402,8 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     for (int p = 0; p < P->n_pairs; ++p) P->queue_order[p] = p;
     std::stable_sort(P->queue_order.begin(), P->queue_order.end(), [&](int x, int y) { return qcost(x) > qcost(y); });
   }
-  // the adjoint and its state saving handle N <= 64 and the FP64 RK steppers only
-  if (!P->large_pairs.empty() || P->splitting || opts->stage_precision != RHEED_STAGES_FP64) {
+  // the adjoint and its state saving handle the FP64 RK steppers only
+  if (P->splitting || opts->stage_precision != RHEED_STAGES_FP64) {
     P->fwd_ws = 0;
     P->bwd_ws = 0;
   }
@@ -601,9 +620,10 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
                           const void* y_bottom, const int* skip, bool final_only = false) {
   if (!P || !U_tables || !angles || !intensity || !pair_status) return fail(RHEED_E_INVALID, "forward: null argument");
   const bool f32 = P->opts.stage_precision == RHEED_STAGES_FP32;
-  if (workspace && (!P->large_pairs.empty() || P->splitting || f32))
-    return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs an RK stepper with FP64 stages "
-                                     "and every structure to have N <= 64");
+  if (workspace && (P->splitting || f32))
+    return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs an RK stepper with FP64 stages");
+  if (y_bottom && !P->large_pairs.empty())
+    return fail(RHEED_E_UNSUPPORTED, "forward: the bulk start needs every structure to have N <= 64");
   if (y_bottom && (P->splitting || f32))
     return fail(RHEED_E_UNSUPPORTED, "forward: the bulk start needs an RK stepper with FP64 stages");
   if (workspace && ws_bytes < P->fwd_ws)
@@ -663,7 +683,7 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
     la.f = a;
     la.f.pair_list = P->large_cost_order ? P->d_large_pairs : P->d_large_plain;
     la.f.n_pairs = (int)P->large_pairs.size();
-    la.f.ws = nullptr;
+    la.f.ck = P->ckl;
     la.f.xch = nullptr;
     la.scratch = P->d_lscratch;
     la.n_slots = P->large_slots;
@@ -834,8 +854,8 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
                             void* dL_dU, void* workspace, size_t ws_bytes, void* stream) {
   if (!P || !U_tables || !angles || !dL_dI || !dL_dU || !workspace)
     return fail(RHEED_E_INVALID, "backward: null argument");
-  if (!P->large_pairs.empty() || P->splitting || P->opts.stage_precision != RHEED_STAGES_FP64)
-    return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs an RK stepper with FP64 stages and every structure to have N <= 64");
+  if (P->splitting || P->opts.stage_precision != RHEED_STAGES_FP64)
+    return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs an RK stepper with FP64 stages");
   if (ws_bytes < P->fwd_ws + P->bwd_ws)
     return fail(RHEED_E_INVALID, "backward: workspace of " + std::to_string(ws_bytes) + " bytes < " +
                                      std::to_string(P->fwd_ws + P->bwd_ws));
@@ -852,14 +872,26 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
   a.g_pair_stride = P->g_pair_stride;
   if (P->ck.every > 1) {
     a.xs = reinterpret_cast<double2*>(static_cast<char*>(workspace) + P->fwd_ws + P->xs_off);
-    a.xs_stride = (long long)P->ck.every * NP;
+    a.xs_stride = (long long)P->ck.every * (P->large_pairs.empty() ? NP : NL);
   }
   a.ld = P->max_beams;
   a.convention = (int)P->opts.convention;
-  a.n_pairs = P->n_pairs;
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = launch_backward((int)P->opts.stepper, a, st);
-  if (e != hipSuccess) return hip_fail(e, "backward launch");
+  hipError_t e = hipSuccess;
+  if (!P->small_pairs.empty()) {  // N <= 64: the 64-wide state layout
+    a.pair_list = P->d_small_pairs;  // null when every pair is small
+    a.n_pairs = (int)P->small_pairs.size();
+    e = launch_backward((int)P->opts.stepper, false, a, st);
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+  }
+  if (!P->large_pairs.empty()) {  // 64 < N <= 128: the 128-wide layout
+    BwdArgs b = a;
+    b.ck = P->ckl;
+    b.pair_list = P->d_large_plain;
+    b.n_pairs = (int)P->large_pairs.size();
+    e = launch_backward((int)P->opts.stepper, true, b, st);
+    if (e != hipSuccess) return hip_fail(e, "backward launch (N > 64)");
+  }
   // stages that use each node of a slice: node offsets of the stages in
   // {0, 1/2} (RK4) or {0, 1/3, 1/2, 2/3} (RK6); offset nps is the next slice's 0
   GradArgs g{};
@@ -880,7 +912,7 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
     g.contrib_di[res][t] = -di;
     g.contrib_r[res][t] = r;
   }
-  e = launch_grad_assemble(g, P->n_struct, P->max_nodes, st);
+  e = launch_grad_assemble(g, P->n_struct, P->max_nodes, !P->small_pairs.empty(), !P->large_pairs.empty(), st);
   return e == hipSuccess ? RHEED_OK : hip_fail(e, "gradient assembly launch");
 }
 

@@ -28,9 +28,12 @@
 // node on the FP64 matrix cores and bins the sum by rod difference, in a
 // fixed order.
 //
-// Thread layout of the vector work: 512 threads, thread t works on row
-// j = t >> 3 and on columns 8 (t & 7) .. +7; the eight threads of a row reduce
-// by butterflies and all hold the row's result.
+// Thread layout of the vector work, for states padded to W = 64 (N <= 64) or
+// W = 128 (64 < N <= 128): W / 8 waves, thread t works on row j = t >> 3 and
+// on columns (W / 8) (t & 7) .. +W/8-1; the eight threads of a row reduce by
+// butterflies and all hold the row's result.  With W = 64 the final step
+// inverts B itself (register Gauss-Jordan); with W = 128 the forward pass
+// keeps B^{-1} beside the final state.
 //
 // Final step (Eq. vrhocomp, first column): with B = Gamma Q - iP,
 // A = Gamma Q + iP, B x = e_1, rho = A x and
@@ -40,12 +43,26 @@
 //   cotangent of Z_L = [conj(Gamma)(rho_bar - w); -i (rho_bar + w)] x^H.
 #include "rheed_internal.h"
 #include "rheed_gj.h"
+#include "rheed_large.h"
 
 namespace rheed {
 
-constexpr int BW = 8;          // waves per workgroup
-constexpr int BT = BW * 64;    // threads per workgroup
-constexpr int RING = 9;        // node-table slots: current slice (nps + 1) and the next one down (nps)
+// Launch geometry of the adjoint for the state width W of its pairs (64 for
+// N <= 64, 128 for 64 < N <= 128): W / 8 waves, and thread t works on row
+// j = t >> 3 and on W / 8 of its columns (the eight threads of a row reduce
+// by butterflies and all hold the row's result).
+template <int W>
+struct BGeo {
+  static constexpr int waves = W / 8;
+  static constexpr int threads = waves * 64;
+  static constexpr int cols = W / 8;
+  static constexpr int box = W == NP ? MAXBOX : MAXBOXL;  // table row entries in LDS
+  // node-table slots: with W = 64 the current slice's (nps + 1) and the next
+  // one's (nps); with W = 128 only the current slice's (LDS), so the next
+  // slice's tables go in after the current one's last product
+  static constexpr int ring = W == NP ? 9 : 5;
+  static constexpr int pf = (4 * box + threads - 1) / threads;  // prefetch registers for nps <= 4 nodes
+};
 
 // Explicit RK tableaux (Sec. 3.4).  node[r] is the table node of stage r
 // counted from the slice's c = 0 node (nps = the next slice's c = 0).
@@ -73,17 +90,19 @@ struct BTab<1> {  // Butcher's 6th order, 7 stages, c = 0, 1/3, 2/3, 1/3, 1/2, 1
   static constexpr double b[7] = {11.0 / 120, 0, 27.0 / 40, 27.0 / 40, -4.0 / 15, -4.0 / 15, 11.0 / 120};
 };
 
+template <int W>
 struct BLds {
-  double2 tb[RING][MAXBOX + 1];  // node tables; entry `box` of every slot stays 0
-  double2 vin[2][NP];            // matrix-vector inputs (double buffered: one barrier per product)
-  double2 x[NP];                 // coefficients of the physical column
-  double2 red[BW][NP];           // per-wave partial sums
-  double2 gj_row[2 * NP];
+  double2 tb[BGeo<W>::ring][BGeo<W>::box + 1];  // node tables; entry `box` of every slot stays 0
+  double2 vin[2][W];             // matrix-vector inputs (double buffered: one barrier per product)
+  double2 x[W];                  // coefficients of the physical column
+  double2 red[W == NP ? BGeo<W>::waves : 1][W];  // W = 64: per-wave partial sums
+  double2 gj_row[2 * NP];        // W = 64: the elimination of the final step
   int gj_piv[NP];
-  double g2s[NP];
-  int bhk[NP][2];
+  double g2s[W];
+  int bhk[W][2];
   int flag_singular;
 };
+
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -121,19 +140,20 @@ __device__ __forceinline__ double2 row_sum(double2 v) {
 
 // (M v)_j (HERM = false) or (M^H v)_j (HERM = true), M = U(node) + Gamma^2;
 // ix[q] is the table entry of U_{j,k} (or U_{k,j}) for
-// k = 8 part + ((q + part) mod 8), or `box` (a zero entry) outside the n x n
-// block.
-template <bool HERM>
+// k = C part + ((q + part) mod C), C = W / 8 columns per thread, or `box`
+// (a zero entry) outside the n x n block.
+template <bool HERM, int W>
 __device__ __forceinline__ double2 matvec_row(const double2* __restrict__ tslot, const double2* __restrict__ v,
-                                              const int (&ix)[8], int part, int j, double g2j) {
+                                              const int (&ix)[W / 8], int part, int j, double g2j) {
+  constexpr int C = W / 8;
   double2 a0 = make_double2(0.0, 0.0), a1 = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int h = 0; h < 8; h += 4) {  // four products' operands in flight at a time
+  for (int h = 0; h < C; h += 4) {  // four products' operands in flight at a time
     double2 u[4], vk[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       u[q] = tslot[ix[h + q]];
-      vk[q] = v[8 * part + ((h + q + part) & 7)];
+      vk[q] = v[C * part + ((h + q + part) & (C - 1))];
     }
 #pragma unroll
     for (int q = 0; q < 4; q += 2) {
@@ -146,12 +166,18 @@ __device__ __forceinline__ double2 matvec_row(const double2* __restrict__ tslot,
   return make_double2(acc.x + g2j * vj.x, acc.y + g2j * vj.y);
 }
 
-template <int STEPPER>
-__global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
+// The adjoint of one pair's forward pass in two workgroups (roles), W the
+// padded width of its stored states (64 or 128).
+template <int STEPPER, int W>
+__global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a) {
   using T = BTab<STEPPER>;
+  using G = BGeo<W>;
   constexpr int NS = T::stages;
   constexpr int NPS = T::nps;
-  __shared__ BLds s;
+  constexpr int BW = G::waves, BT = G::threads, CP = G::cols, RING = G::ring, PF = G::pf;
+  // the next slice's tables overwrite slots the current slice still reads
+  constexpr bool tight = RING < 2 * NPS + 1;
+  __shared__ BLds<W> s;
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
   const int j = tid >> 3, part = tid & 7;
@@ -159,7 +185,7 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
   // stage inputs v_r, role 1 walks the adjoint stages down and writes g_r;
   // the two need nothing from each other
   const int role = blockIdx.x & 1;
-  const int p = blockIdx.x >> 1;
+  const int p = a.pair_list ? a.pair_list[blockIdx.x >> 1] : (int)(blockIdx.x >> 1);
   const StructDev S = a.structs[a.pair_struct[p]];
   const int N = S.n_beams;
   const int L = S.n_slices;
@@ -169,8 +195,9 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
   const char* pws = a.ws + (long long)p * a.ck.pair_stride;
   const char* flags = pws + a.ck.flags_off;
   double2* __restrict__ gb = a.gbuf + (long long)p * a.g_pair_stride;
+  constexpr long long MATB = (long long)W * W * sizeof(double2);
 
-  if (tid < NP) {
+  if (tid < W) {
     s.bhk[tid][0] = tid < N ? a.beams[2 * (S.beam_off + tid)] : 0;
     s.bhk[tid][1] = tid < N ? a.beams[2 * (S.beam_off + tid) + 1] : 0;
   }
@@ -178,7 +205,7 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
   if (tid == 0) s.flag_singular = 0;
   __syncthreads();
   const double th0 = a.angles[2 * p], th1 = a.angles[2 * p + 1];
-  if (tid < NP) {
+  if (tid < W) {
     const double b0x = S.gamma * cos(th0) * cos(th1);
     const double b0y = S.gamma * cos(th0) * sin(th1);
     double arg = 0.0;
@@ -189,47 +216,55 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
     }
     s.g2s[tid] = arg;
   }
-  // table entries of U_{j,k} and U_{k,j} for k = 8 part + ((q + part) mod 8):
-  // the eight threads of a row visit their columns in rotated order, so that
-  // their reads of the input vector fall in eight different LDS bank groups
-  int ixf[8], ixh[8];
+  // table entries of U_{j,k} (role 0) or U_{k,j} (role 1) for
+  // k = CP part + ((q + part) mod CP): the eight threads of a row visit their
+  // columns in rotated order, so that their reads of the input vector fall in
+  // different LDS bank groups
+  int ix[CP];
   {
-    const int W = 2 * S.kd + 1;
+    const int Wd = 2 * S.kd + 1;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int k = 8 * part + ((q + part) & 7);
+    for (int q = 0; q < CP; ++q) {
+      const int k = CP * part + ((q + part) & (CP - 1));
       const bool in = j < N && k < N;
-      const int bj = (s.bhk[j][0] + S.hd) * W + s.bhk[j][1] + S.kd, oj = s.bhk[j][0] * W + s.bhk[j][1];
-      const int bk = (s.bhk[k][0] + S.hd) * W + s.bhk[k][1] + S.kd, ok = s.bhk[k][0] * W + s.bhk[k][1];
-      ixf[q] = in ? bj - ok : box;
-      ixh[q] = in ? bk - oj : box;
+      const int bj = (s.bhk[j][0] + S.hd) * Wd + s.bhk[j][1] + S.kd, oj = s.bhk[j][0] * Wd + s.bhk[j][1];
+      const int bk = (s.bhk[k][0] + S.hd) * Wd + s.bhk[k][1] + S.kd, ok = s.bhk[k][0] * Wd + s.bhk[k][1];
+      ix[q] = in ? (role == 0 ? bj - ok : bk - oj) : box;
     }
   }
   __syncthreads();
   const double g2j = s.g2s[j];
 
-  // ---- final step: x = B^{-1} e_1 (B^{-1} by elimination), rho = A x
+  // ---- final step: x = B^{-1} e_1, rho = A x
   const double2* zL = reinterpret_cast<const double2*>(pws + (long long)(a.ck.max_ckpt - 1) * a.ck.state_bytes);
   double2 yc, yd;  // cotangent of row j of the current state
   {
+    // W = 64: B^{-1} by elimination here; slot sl = w + BW (m - 8) < N of
+    // z holds row gj_piv[sl] of B^{-1}, column pos in this lane.  W = 128:
+    // B^{-1} as the forward pass kept it.
     double2 z[16];
+    int pos = 0;
+    const double2* Binv = reinterpret_cast<const double2*>(pws + a.ck.binv_off);
+    if constexpr (W == NP) {
+      if (tid < W) s.x[tid] = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int r = w + BW * m;
-      const double g2v = s.g2s[r];
-      const double gr = g2v >= 0.0 ? sqrt(g2v) : 0.0, gi = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
-      const double2 q = zL[r * NP + lane], pp = zL[NP * NP + r * NP + lane];
-      z[m] = make_double2(gr * q.x - gi * q.y + pp.y, gr * q.y + gi * q.x - pp.x);  // Gamma Q - iP
-    }
-    if (tid < NP) s.x[tid] = make_double2(0.0, 0.0);
-    const int pos = gj_inverse<BW>(z, N, lane, w, s.gj_row, s.gj_piv, &s.flag_singular);
-    // slot sl = w + BW (m - 8) < N holds row gj_piv[sl] of B^{-1}, column pos in this lane
-    if (pos == 0) {
-#pragma unroll
-      for (int m = 8; m < 16; ++m) {
-        const int sl = w + BW * (m - 8);
-        if (sl < N) s.x[s.gj_piv[sl]] = z[m];
+      for (int m = 0; m < 8; ++m) {
+        const int r = w + BW * m;
+        const double g2v = s.g2s[r];
+        const double gr = g2v >= 0.0 ? sqrt(g2v) : 0.0, gi = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
+        const double2 q = zL[r * W + lane], pp = zL[W * W + r * W + lane];
+        z[m] = make_double2(gr * q.x - gi * q.y + pp.y, gr * q.y + gi * q.x - pp.x);  // Gamma Q - iP
       }
+      pos = gj_inverse<BW>(z, N, lane, w, s.gj_row, s.gj_piv, &s.flag_singular);
+      if (pos == 0) {
+#pragma unroll
+        for (int m = 8; m < 16; ++m) {
+          const int sl = w + BW * (m - 8);
+          if (sl < N) s.x[s.gj_piv[sl]] = z[m];
+        }
+      }
+    } else {
+      if (part == 0) s.x[j] = j < N ? Binv[(long long)j * W] : make_double2(0.0, 0.0);
     }
     __syncthreads();
     // rho_j = sum_k A[j][k] x_k, A = Gamma Q + iP
@@ -238,9 +273,9 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
       const double gr = g2j >= 0.0 ? sqrt(g2j) : 0.0, gi = g2j >= 0.0 ? 0.0 : -sqrt(-g2j);
       double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int k = 8 * part + q;
-        const double2 qv = zL[j * NP + k], pv = zL[NP * NP + j * NP + k];
+      for (int q = 0; q < CP; ++q) {
+        const int k = CP * part + q;
+        const double2 qv = zL[j * W + k], pv = zL[W * W + j * W + k];
         const double2 av = make_double2(gr * qv.x - gi * qv.y - pv.y, gr * qv.y + gi * qv.x + pv.x);
         acc = cadd(acc, cmul(av, s.x[k]));
       }
@@ -262,11 +297,11 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
       const int k = j;
       double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int jj = 8 * part + q;
+      for (int q = 0; q < CP; ++q) {
+        const int jj = CP * part + q;
         const double g2v = s.g2s[jj];
         const double gr = g2v >= 0.0 ? sqrt(g2v) : 0.0, gi = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
-        const double2 qv = zL[jj * NP + k], pv = zL[NP * NP + jj * NP + k];
+        const double2 qv = zL[jj * W + k], pv = zL[W * W + jj * W + k];
         const double2 av = make_double2(gr * qv.x - gi * qv.y - pv.y, gr * qv.y + gi * qv.x + pv.x);
         acc = cadd(acc, cmulc(av, s.vin[0][jj]));
       }
@@ -274,8 +309,10 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
     }
     if (part == 0) s.vin[1][j] = xbar;
     __syncthreads();
-    // w_k = sum_j conj(Binv[j][k]) xbar_j: lane holds column pos of the rows in its slots
-    {
+    // w_k = sum_j conj(Binv[j][k]) xbar_j
+    double2 wv = make_double2(0.0, 0.0);
+    if constexpr (W == NP) {
+      // this lane holds column pos of the rows in its slots
       double2 acc = make_double2(0.0, 0.0);
 #pragma unroll
       for (int m = 8; m < 16; ++m) {
@@ -283,11 +320,18 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
         if (sl < N) acc = cadd(acc, cmulc(z[m], s.vin[1][s.gj_piv[sl]]));
       }
       s.red[w][pos] = acc;
-    }
-    __syncthreads();
-    double2 wv = make_double2(0.0, 0.0);
+      __syncthreads();
 #pragma unroll
-    for (int q = 0; q < BW; ++q) wv = cadd(wv, s.red[q][j]);
+      for (int q = 0; q < BW; ++q) wv = cadd(wv, s.red[q][j]);
+    } else {
+      double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int q = 0; q < CP; ++q) {
+        const int jj = CP * part + q;
+        acc = cadd(acc, cmulc(Binv[(long long)jj * W + j], s.vin[1][jj]));
+      }
+      wv = row_sum(acc);
+    }
     yc = make_double2(0.0, 0.0);
     yd = make_double2(0.0, 0.0);
     if (j < N) {
@@ -321,15 +365,11 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
       double2* xs = a.xs + (long long)p * a.xs_stride;
       for (int m = hi - 1; m >= lo; --m) {
         if (flags[m]) {
-          if (K > 1 && m + 1 < hi && tid < NP) xs[(m + 1 - lo) * NP + tid] = s.x[tid];
-          const double2* Tm =
-              reinterpret_cast<const double2*>(pws + a.ck.q_off + (long long)m * NP * NP * sizeof(double2));
-          double2 tm[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) tm[q] = Tm[j * NP + 8 * part + q];
+          if (K > 1 && m + 1 < hi && tid < W) xs[(m + 1 - lo) * W + tid] = s.x[tid];
+          const double2* Tm = reinterpret_cast<const double2*>(pws + a.ck.q_off + (long long)m * MATB);
           double2 xn = make_double2(0.0, 0.0);
 #pragma unroll
-          for (int q = 0; q < 8; ++q) xn = cadd(xn, cmul(tm[q], s.x[8 * part + q]));
+          for (int q = 0; q < CP; ++q) xn = cadd(xn, cmul(Tm[j * W + CP * part + q], s.x[CP * part + q]));
           xn = row_sum(xn);
           __syncthreads();
           if (part == 0) s.x[j] = xn;
@@ -344,10 +384,10 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
         const double2* z = reinterpret_cast<const double2*>(pws + (long long)(lo / K) * a.ck.state_bytes);
         double2 ac = make_double2(0.0, 0.0), ad = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const double2 xk = s.x[8 * part + q];
-          ac = cadd(ac, cmul(z[j * NP + 8 * part + q], xk));
-          ad = cadd(ad, cmul(z[NP * NP + j * NP + 8 * part + q], xk));
+        for (int q = 0; q < CP; ++q) {
+          const double2 xk = s.x[CP * part + q];
+          ac = cadd(ac, cmul(z[j * W + CP * part + q], xk));
+          ad = cadd(ad, cmul(z[W * W + j * W + CP * part + q], xk));
         }
         psic = row_sum(ac);
         psid = row_sum(ad);
@@ -358,25 +398,24 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
       for (int i = lo; i < hi; ++i) {
         const int nb = i * NPS;
         if (i > lo && flags[i - 1]) {
-          const double2* R =
-              reinterpret_cast<const double2*>(pws + a.ck.r_off + (long long)(i - 1) * NP * NP * sizeof(double2));
-          const double2* xi = xs + (i - lo) * NP;
+          const double2* R = reinterpret_cast<const double2*>(pws + a.ck.r_off + (long long)(i - 1) * MATB);
+          const double2* xi = xs + (i - lo) * W;
           double2 ad = make_double2(0.0, 0.0);
 #pragma unroll
-          for (int q = 0; q < 8; ++q) ad = cadd(ad, cmul(R[j * NP + 8 * part + q], xi[8 * part + q]));
+          for (int q = 0; q < CP; ++q) ad = cadd(ad, cmul(R[j * W + CP * part + q], xi[CP * part + q]));
           psic = xi[j];
           psid = row_sum(ad);
         }
-        double2 pf[3];  // the next slice's new nodes, loaded during this one
+        double2 pf[PF];  // the next slice's new nodes, loaded during this one
         if (i + 1 < hi) {
 #pragma unroll
-          for (int t = 0; t < 3; ++t) {
+          for (int t = 0; t < PF; ++t) {
             const int e = tid + BT * t;
             if (e < NPS * box) pf[t] = Us[(long long)(nb + NPS + 1) * box + e];
           }
         }
         // RK stages on psi: Y_r = psi + h sum_{m<r} a_rm K_m, K_r = (Y_r^(c'), -M_r Y_r^(c))
-        double2* gs = gb + (long long)i * NS * 2 * NP;
+        double2* gs = gb + (long long)i * NS * 2 * W;
         double2 Yd[NS], Kd[NS];
 #pragma unroll
         for (int r = 0; r < NS; ++r) {
@@ -391,10 +430,10 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
           Yd[r] = ydr;
           if (part == 0) {
             s.vin[r & 1][j] = yr;
-            gs[r * 2 * NP + j] = yr;  // v_r
+            gs[r * 2 * W + j] = yr;  // v_r
           }
           __syncthreads();
-          const double2 mv = matvec_row<false>(s.tb[(nb + T::node[r]) % RING], s.vin[r & 1], ixf, part, j, g2j);
+          const double2 mv = matvec_row<false, W>(s.tb[(nb + T::node[r]) % RING], s.vin[r & 1], ix, part, j, g2j);
           Kd[r] = make_double2(-mv.x, -mv.y);
         }
         if (i + 1 < hi) {
@@ -405,8 +444,9 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
               psid = caxpy(h * T::b[r], Kd[r], psid);
             }
           }
+          if constexpr (tight) __syncthreads();
 #pragma unroll
-          for (int t = 0; t < 3; ++t) {
+          for (int t = 0; t < PF; ++t) {
             const int e = tid + BT * t;
             if (e < NPS * box) {
               const int q = e / box;
@@ -426,10 +466,10 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
     __syncthreads();
     for (int i = L - 1; i >= 0; --i) {
       const int nb = i * NPS;
-      double2 pf[3];  // the new nodes of slice i - 1
+      double2 pf[PF];  // the new nodes of slice i - 1
       if (i > 0) {
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
+        for (int t = 0; t < PF; ++t) {
           const int e = tid + BT * t;
           if (e < NPS * box) pf[t] = Us[(long long)(nb - NPS) * box + e];
         }
@@ -437,21 +477,18 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
       if (flags[i]) {
         const double2* R =
             K == 1 ? (i + 1 == L ? zL : reinterpret_cast<const double2*>(pws + (long long)(i + 1) * a.ck.state_bytes)) +
-                         NP * NP
-                   : reinterpret_cast<const double2*>(pws + a.ck.r_off + (long long)i * NP * NP * sizeof(double2));
-        double2 rh[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) rh[q] = R[(8 * part + q) * NP + j];
+                         W * W
+                   : reinterpret_cast<const double2*>(pws + a.ck.r_off + (long long)i * MATB);
         if (part == 0) s.vin[0][j] = yd;
         __syncthreads();
         double2 t = make_double2(0.0, 0.0);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) t = cadd(t, cmulc(rh[q], s.vin[0][8 * part + q]));
+        for (int q = 0; q < CP; ++q) t = cadd(t, cmulc(R[(CP * part + q) * W + j], s.vin[0][CP * part + q]));
         t = row_sum(t);
         yc = make_double2(-t.x, -t.y);
         __syncthreads();
       }
-      double2* gs = gb + (long long)i * NS * 2 * NP;
+      double2* gs = gb + (long long)i * NS * 2 * W;
       double2 Ybc[NS], Ybd[NS];
 #pragma unroll
       for (int r = NS - 1; r >= 0; --r) {
@@ -468,10 +505,10 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
         const int buf = (r + 1) & 1;  // the products alternate between the two input buffers
         if (part == 0) {
           s.vin[buf][j] = kd;
-          gs[r * 2 * NP + NP + j] = make_double2(-kd.x, -kd.y);  // g_r = -K_bar^(c')
+          gs[r * 2 * W + W + j] = make_double2(-kd.x, -kd.y);  // g_r = -K_bar^(c')
         }
         __syncthreads();
-        const double2 mv = matvec_row<true>(s.tb[(nb + T::node[r]) % RING], s.vin[buf], ixh, part, j, g2j);
+        const double2 mv = matvec_row<true, W>(s.tb[(nb + T::node[r]) % RING], s.vin[buf], ix, part, j, g2j);
         Ybc[r] = make_double2(-mv.x, -mv.y);  // Y_bar^(c) = -M^H K_bar^(c')
       }
 #pragma unroll
@@ -480,8 +517,9 @@ __global__ __launch_bounds__(BT, 1) void backward_kernel(BwdArgs a) {
         yd = cadd(yd, Ybd[r]);
       }
       if (i > 0) {
+        if constexpr (tight) __syncthreads();
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
+        for (int t = 0; t < PF; ++t) {
           const int e = tid + BT * t;
           if (e < NPS * box) {
             const int q = e / box;
@@ -504,7 +542,7 @@ __global__ __launch_bounds__(256) void grad_assemble_kernel(GradArgs a) {
   __shared__ double2 C[NP][NP + 1];
   const StructDev S = a.structs[blockIdx.y];
   const int n = blockIdx.x;
-  if (n >= S.n_nodes) return;
+  if (S.n_beams > NP || n >= S.n_nodes) return;
   const int tid = threadIdx.x;
   const int res = n % a.nps;
   const int i0 = n / a.nps;
@@ -579,16 +617,132 @@ __global__ __launch_bounds__(256) void grad_assemble_kernel(GradArgs a) {
   }
 }
 
-hipError_t launch_backward(int stepper, const BwdArgs& a, hipStream_t stream) {
-  if (stepper == 0)
-    hipLaunchKernelGGL(backward_kernel<0>, dim3(2 * a.n_pairs), dim3(BT), 0, stream, a);
-  else
-    hipLaunchKernelGGL(backward_kernel<1>, dim3(2 * a.n_pairs), dim3(BT), 0, stream, a);
+// The same for structures with 64 < N <= 128 (stage buffer and bins of
+// width NL): one workgroup of 8 waves per (node, structure); wave w owns rows
+// 16 w .. +15 of C and all 8 column tiles.  C is binned one half of its rows
+// at a time through LDS (the half shares the LDS with the chunk buffers),
+// each table entry summing the first half's (j, k) in bin order, then the
+// second's.
+__global__ __launch_bounds__(512) void grad_assemble_wide_kernel(GradArgs a) {
+  union GLds {
+    struct {
+      double2 vs[16][NL], gsh[16][NL];
+    } in;
+    double2 C[64][NL + 1];
+  };
+  __shared__ GLds sm;
+  const StructDev S = a.structs[blockIdx.y];
+  const int n = blockIdx.x;
+  if (S.n_beams <= NP || n >= S.n_nodes) return;
+  const int tid = threadIdx.x;
+  const int res = n % a.nps;
+  const int i0 = n / a.nps;
+  int ci[2], cr[2], nc = 0;
+  for (int t = 0; t < a.n_contrib[res]; ++t) {
+    const int ii = i0 + a.contrib_di[res][t];
+    if (ii >= 0 && ii < S.n_slices) {
+      ci[nc] = ii;
+      cr[nc] = a.contrib_r[res][t];
+      ++nc;
+    }
+  }
+  const int lane = tid & 63, w = tid >> 6;
+  typedef double g4 __attribute__((ext_vector_type(4)));
+  g4 p1[8], p2[8], p3[8];
+#pragma unroll
+  for (int jt = 0; jt < 8; ++jt) p1[jt] = p2[jt] = p3[jt] = g4{0, 0, 0, 0};
+  const int total = S.n_angles * nc;
+  for (int t0 = 0; t0 < total; t0 += 16) {
+    const int cnt = min(16, total - t0);
+    for (int e = tid; e < 16 * NL; e += 512) {
+      const int tt = e / NL, jj = e % NL;
+      double2 vv = make_double2(0.0, 0.0), gg = vv;
+      if (tt < cnt) {
+        const int t = t0 + tt;
+        const int pr = S.pair_off + t / nc, c = t % nc;
+        const double2* src = a.gbuf + (long long)pr * a.g_pair_stride + ((long long)ci[c] * a.stages + cr[c]) * 2 * NL;
+        vv = src[jj];
+        gg = src[NL + jj];
+      }
+      sm.in.vs[tt][jj] = vv;
+      sm.in.gsh[tt][jj] = gg;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int tk = 4 * q + (lane >> 4);
+      const double2 g = sm.in.gsh[tk][16 * w + (lane & 15)];   // A[j][t] = g_t[j]
+      const double gs = g.x + g.y;
+#pragma unroll
+      for (int jt = 0; jt < 8; ++jt) {
+        const double2 v = sm.in.vs[tk][16 * jt + (lane & 15)];  // B[t][k] = conj(v_t[k])
+        p1[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.x, v.x, p1[jt], 0, 0, 0);
+        p2[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.y, -v.y, p2[jt], 0, 0, 0);
+        p3[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(gs, v.x - v.y, p3[jt], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  const int* bp = a.bin_ptr + S.bin_ptr_off;
+  const int* bj = a.bin_jk + S.bin_jk_off;
+  constexpr int DPT = (MAXBOXL + 511) / 512;  // table entries per thread
+  double2 acc[DPT];
+#pragma unroll
+  for (int u = 0; u < DPT; ++u) acc[u] = make_double2(0.0, 0.0);
+#pragma unroll 1
+  for (int hv = 0; hv < 2; ++hv) {
+    if ((w >> 2) == hv) {
+#pragma unroll
+      for (int jt = 0; jt < 8; ++jt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          sm.C[16 * (w & 3) + 4 * v + (lane >> 4)][16 * jt + (lane & 15)] =
+              make_double2(p1[jt][v] - p2[jt][v], p3[jt][v] - p1[jt][v] - p2[jt][v]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < DPT; ++u) {
+      const int d = tid + 512 * u;
+      if (d < S.box) {
+        for (int t = bp[d]; t < bp[d + 1]; ++t) {
+          const int jk = bj[t], jr = jk / NL;
+          if ((jr >> 6) == hv) acc[u] = cadd(acc[u], sm.C[jr - 64 * hv][jk % NL]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double2* out = a.dU + S.table_off + (long long)n * S.box;
+#pragma unroll
+  for (int u = 0; u < DPT; ++u) {
+    const int d = tid + 512 * u;
+    if (d < S.box) out[d] = acc[u];
+  }
+}
+
+hipError_t launch_backward(int stepper, bool wide, const BwdArgs& a, hipStream_t stream) {
+  if (a.n_pairs < 1) return hipSuccess;
+  const dim3 grid(2 * a.n_pairs);
+  if (wide) {
+    const dim3 block(BGeo<NL>::threads);
+    if (stepper == 0)
+      hipLaunchKernelGGL((backward_kernel<0, NL>), grid, block, 0, stream, a);
+    else
+      hipLaunchKernelGGL((backward_kernel<1, NL>), grid, block, 0, stream, a);
+  } else {
+    const dim3 block(BGeo<NP>::threads);
+    if (stepper == 0)
+      hipLaunchKernelGGL((backward_kernel<0, NP>), grid, block, 0, stream, a);
+    else
+      hipLaunchKernelGGL((backward_kernel<1, NP>), grid, block, 0, stream, a);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_grad_assemble(const GradArgs& a, int n_struct, int max_nodes, hipStream_t stream) {
-  hipLaunchKernelGGL(grad_assemble_kernel, dim3(max_nodes, n_struct), dim3(256), 0, stream, a);
+hipError_t launch_grad_assemble(const GradArgs& a, int n_struct, int max_nodes, bool narrow, bool wide,
+                                hipStream_t stream) {
+  if (narrow) hipLaunchKernelGGL(grad_assemble_kernel, dim3(max_nodes, n_struct), dim3(256), 0, stream, a);
+  if (wide) hipLaunchKernelGGL(grad_assemble_wide_kernel, dim3(max_nodes, n_struct), dim3(512), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(LT, 1) void forward_queue_kernel(QueueArgs q) {
     if (q.large.f.structs[q.large.f.pair_struct[p]].n_beams <= NP)
       small_pair<STEPPER, false>(q.large.f, p);
     else
-      run_pair<STEPPER>(q.large, p, slot);
+      run_pair<STEPPER, false>(q.large, p, slot);
     __syncthreads();  // LDS is reused by the next pair
   }
 }

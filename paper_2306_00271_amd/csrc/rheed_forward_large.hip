@@ -620,7 +620,43 @@ __device__ __noinline__ void replay_p(double2* __restrict__ cg, double2* __restr
   __syncthreads();
 }
 
-template <int STEPPER>
+// Q^{-1} (or B^{-1} of the reflection) after elim_record: the recorded
+// column operations replayed on the rows of I, each column put at its pivot
+// step as in replay_p; written, all NL rows, to out (row major, stride NL).
+__device__ __noinline__ void replay_identity(double2* __restrict__ out, const double2* __restrict__ frec, int N) {
+  LLds& s = large_lds_ref();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n = __builtin_amdgcn_readfirstlane(N);
+  const int p0 = s.pos[lane], p1 = s.pos[64 + lane];
+#pragma unroll 1
+  for (int part = 0; part < 2; ++part) {
+    constexpr int R = LRM / 2;
+    const int m0 = part * R;
+    double2 z[R][2];
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int row = w + LW * (m0 + m);
+      z[m][0] = make_double2(row == lane ? 1.0 : 0.0, 0.0);
+      z[m][1] = make_double2(row == 64 + lane ? 1.0 : 0.0, 0.0);
+    }
+    replay<R>(z, n, lane, w, m0, s, frec);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      const int row = w + LW * (m0 + m);
+      gst(&out[row * NL + p0], z[m][0]);
+      gst(&out[row * NL + p1], z[m][1]);
+    }
+  }
+}
+
+// Copy of an NL x NL block of the slot (for the states the adjoint reads).
+__device__ __forceinline__ void copy_block(double2* __restrict__ dst, const double2* __restrict__ src) {
+  for (int e = threadIdx.x; e < NL * NL; e += LT) gst(&dst[e], gld(&src[e]));
+}
+
+// SAVE: keep the states the adjoint reads (a separate instance, so that the
+// forward-only code keeps its own register allocation).
+template <int STEPPER, bool SAVE>
 __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
   using T = LTab<STEPPER>;
   constexpr int SL = T::nodes + 1;
@@ -636,6 +672,13 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
   const double h = S.h;
   const double2* __restrict__ Us = a.U + S.table_off;
   const int ncb = (N + LCB - 1) / LCB;  // column blocks holding columns < N (5 .. 8; 1 .. 8 for splitting)
+  // states kept for the adjoint (RK steppers): the state at the start of
+  // every ck.every-th slice and after the last, T = Q^{-1} and (ck.every > 1)
+  // R of every transformation, one decision byte per slice, and B^{-1} of
+  // the reflection solve, all padded to NL
+  constexpr bool save = SAVE && STEPPER != 2;
+  char* pws = save ? a.ws + (long long)p * a.ck.pair_stride : nullptr;
+  constexpr long long MATB = (long long)NL * NL * sizeof(double2);
 
   if (tid < NL) {
     s.bhk[tid][0] = tid < N ? a.beams[2 * (S.beam_off + tid)] : 0;
@@ -698,6 +741,11 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
       }
     }
     __syncthreads();
+    if (save && (i % a.ck.every) == 0) {
+      double2* st = reinterpret_cast<double2*>(pws + (long long)(i / a.ck.every) * a.ck.state_bytes);
+      copy_block(st, cg);
+      copy_block(st + NL * NL, dg);
+    }
     if constexpr (STEPPER == 2) {
       // kicks at the slice's nodes 0, g1, g1 + g2 with drifts between; the
       // slice's last kick (at its end, the next slice's 0) is merged into the
@@ -748,11 +796,17 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
       const double xi = lo > 0.0 ? hi / lo : INFINITY;
       do_rhst = xi > a.threshold;
     }
+    if (save && tid == 0) pws[a.ck.flags_off + i] = do_rhst ? 1 : 0;
     if (do_rhst) {
       // Z <- Z Q^{-1}: eliminate Q (recording), replay on the rows of P
       ++nrhst;
       elim_record(cg, dg, frec, N, 0);
+      if (save) replay_identity(reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * MATB), frec, N);
       replay_p(cg, dg, frec, N);
+      if (save && a.ck.r_off) {  // R = P Q^{-1} for an adjoint that keeps states only every few slices
+        copy_block(reinterpret_cast<double2*>(pws + a.ck.r_off + (long long)i * MATB), dg);
+        __syncthreads();
+      }
     }
   }
 
@@ -761,9 +815,15 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
     bab_blocks(cg, dg, ncb, 1, L * T::nodes, A.sp_b[3], 0.0, 0.0, adr, false, h, N);
     __syncthreads();
   }
+  if (save) {  // the final state
+    double2* st = reinterpret_cast<double2*>(pws + (long long)(a.ck.max_ckpt - 1) * a.ck.state_bytes);
+    copy_block(st, cg);
+    copy_block(st + NL * NL, dg);
+  }
   // reflection (Eq. vrhocomp): upper = Gamma Q - iP, lower = Gamma Q + iP,
   // rho = lower x with upper x = e_1
   elim_record(cg, dg, frec, N, 1);
+  if (save) replay_identity(reinterpret_cast<double2*>(pws + a.ck.binv_off), frec, N);
   if (w == 0) {
     // x = E e_{pc_0}: the recorded operations in reverse order, each
     // v <- v - e_pc (f . v)
@@ -842,7 +902,7 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
 // rounds of the grid take it in alternating directions (workgroup b gets
 // entries b, 2G - 1 - b, 2G + b, ...), which pairs the dearest pairs of one
 // round with the cheapest of the next.
-template <int STEPPER>
+template <int STEPPER, bool SAVE>
 __global__ __launch_bounds__(LT, 1) void forward_large_kernel(LargeArgs A) {
   char* slot = A.scratch + (long long)blockIdx.x * LSLOT_BYTES;
   const int G = gridDim.x;
@@ -851,7 +911,7 @@ __global__ __launch_bounds__(LT, 1) void forward_large_kernel(LargeArgs A) {
     const int pi = base + ((r & 1) ? G - 1 - (int)blockIdx.x : (int)blockIdx.x);
     if (pi >= A.f.n_pairs) continue;
     const int p = A.f.pair_list ? A.f.pair_list[pi] : pi;
-    run_pair<STEPPER>(A, p, slot);
+    run_pair<STEPPER, SAVE>(A, p, slot);
     __syncthreads();  // LDS is reused by the next pair
   }
 }
@@ -862,12 +922,18 @@ hipError_t launch_forward_large(int stepper, const LargeArgs& a, hipStream_t str
   if (a.f.n_pairs < 1) return hipSuccess;
   const int grid = a.f.n_pairs < a.n_slots ? a.f.n_pairs : a.n_slots;
   if (grid < 1) return hipErrorInvalidValue;
-  if (stepper == 0)
-    hipLaunchKernelGGL(forward_large_kernel<0>, dim3(grid), dim3(LT), 0, stream, a);
+  const bool save = a.f.ws != nullptr;
+  if (save && stepper == 2) return hipErrorInvalidValue;  // the splitting stepper keeps no states
+  if (stepper == 0 && save)
+    hipLaunchKernelGGL((forward_large_kernel<0, true>), dim3(grid), dim3(LT), 0, stream, a);
+  else if (stepper == 0)
+    hipLaunchKernelGGL((forward_large_kernel<0, false>), dim3(grid), dim3(LT), 0, stream, a);
+  else if (stepper == 1 && save)
+    hipLaunchKernelGGL((forward_large_kernel<1, true>), dim3(grid), dim3(LT), 0, stream, a);
   else if (stepper == 1)
-    hipLaunchKernelGGL(forward_large_kernel<1>, dim3(grid), dim3(LT), 0, stream, a);
+    hipLaunchKernelGGL((forward_large_kernel<1, false>), dim3(grid), dim3(LT), 0, stream, a);
   else
-    hipLaunchKernelGGL(forward_large_kernel<2>, dim3(grid), dim3(LT), 0, stream, a);
+    hipLaunchKernelGGL((forward_large_kernel<2, false>), dim3(grid), dim3(LT), 0, stream, a);
   return hipGetLastError();
 }
 
@@ -875,12 +941,17 @@ int forward_large_slots(int device) {
   int cus = 0, per0 = 0, per1 = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
   int per2 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per0, forward_large_kernel<0>, LT, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, forward_large_kernel<1>, LT, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per2, forward_large_kernel<2>, LT, 0) != hipSuccess)
+  int per3 = 0, per4 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per0, forward_large_kernel<0, false>, LT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, forward_large_kernel<1, false>, LT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per2, forward_large_kernel<2, false>, LT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per3, forward_large_kernel<0, true>, LT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per4, forward_large_kernel<1, true>, LT, 0) != hipSuccess)
     return 0;
   int per = per0 < per1 ? per0 : per1;
   per = per < per2 ? per : per2;
+  per = per < per3 ? per : per3;
+  per = per < per4 ? per : per4;
   return cus * (per > 0 ? per : 0);
 }
 

@@ -24,15 +24,19 @@ struct StructDev {
 // Per-pair storage kept by the forward pass for the adjoint: the state (c, c')
 // at the start of every slice and after the last one, T = Q^{-1} of every
 // slice that was followed by a right-hand-side transformation, and one byte
-// per slice telling whether that transformation was applied.
+// per slice telling whether that transformation was applied.  Matrices are
+// padded to the kernel's beam count W (NP = 64 for N <= 64, 128 above),
+// row major with row stride W; a plan with both kinds keeps two layouts with
+// one pair stride.
 struct CkptLayout {
   long long pair_stride;   // bytes per pair
-  long long state_bytes;   // one state: 2 * NP * NP complex
+  long long state_bytes;   // one state: 2 * W * W complex
   int every;               // slices between stored states (1: every slice)
   int max_ckpt;            // stored states per pair, including the final state
   long long q_off;         // byte offset of the T slots (one per slice)
   long long r_off;         // byte offset of the R slots (one per slice) when every > 1, else 0
   long long flags_off;     // byte offset of the decision bytes
+  long long binv_off;      // W = 128 only: byte offset of B^{-1} of the reflection solve, else 0
 };
 
 // A splitting method (Sec. 3.4) for the one-workgroup kernel: kicks
@@ -129,15 +133,16 @@ struct PotBwdArgs {
 struct BwdArgs {
   const StructDev* structs;
   const int* pair_struct;
+  const int* pair_list;      // pair of each launch slot (n_pairs entries), or null: slot = pair
   const int* beams;
   const double2* U;
   const double* angles;
   const double* dLdI;        // [P][ld]
   const char* ws;            // forward workspace
   CkptLayout ck;
-  double2* gbuf;             // stage buffer: per pair [slice][stage][v | g][NP]
+  double2* gbuf;             // stage buffer: per pair [slice][stage][v | g][W]
   long long g_pair_stride;   // elements per pair
-  double2* xs;               // ck.every > 1: per pair [ck.every][NP], x of the segment's transformed states
+  double2* xs;               // ck.every > 1: per pair [ck.every][W], x of the segment's transformed states
   long long xs_stride;       // elements per pair
   int ld;
   int convention;
@@ -151,7 +156,7 @@ struct GradArgs {
   const double2* gbuf;
   long long g_pair_stride;
   const int* bin_ptr;        // per structure: box + 1 offsets into bin_jk
-  const int* bin_jk;         // j * NP + k
+  const int* bin_jk;         // j * W + k (W = 64 for N <= 64, else 128)
   double2* dU;               // all tables
   int stages;
   int nps;
@@ -188,8 +193,11 @@ hipError_t launch_bulk_update(const BulkArgs& a, hipStream_t stream);
 hipError_t launch_bulk_init(const BulkArgs& a, hipStream_t stream);  // vacuum start, flags cleared
 hipError_t launch_forward_split(int stepper, const FwdArgs& a, hipStream_t stream);
 int forward_split_max_pairs(int device);  // pairs a split launch can hold at once (0: not available)
-hipError_t launch_backward(int stepper, const BwdArgs& a, hipStream_t stream);
-hipError_t launch_grad_assemble(const GradArgs& a, int n_struct, int max_nodes, hipStream_t stream);
+// wide: the pairs of the launch have 64 < N <= 128 (state layout W = 128)
+hipError_t launch_backward(int stepper, bool wide, const BwdArgs& a, hipStream_t stream);
+// narrow / wide: launch the assembly for the structures with N <= 64 / with N > 64
+hipError_t launch_grad_assemble(const GradArgs& a, int n_struct, int max_nodes, bool narrow, bool wide,
+                                hipStream_t stream);
 hipError_t launch_potential(const PotArgs& a, long long max_elems, hipStream_t stream);
 hipError_t launch_potential_bwd(const PotBwdArgs& a, long long n_atoms_total, int n_struct,
                                 const long long* atom_struct, hipStream_t stream);
