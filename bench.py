@@ -348,6 +348,63 @@ def fp32_stages(steps=3):
             "eacc_fp32_vs_fp64": float(f"{e:.3e}"), "eacc_grid_vs_1600_slices": float(f"{disc:.3e}")}
 
 
+def wide_gradient(steps=2):
+    """The gradient step at N = 121: one N = 121 structure of the uneven-N
+    workload (40 A in 600 slices, RK6, 64 angles, states every 20 slices),
+    potential -> forward keeping states -> R-factor -> adjoint -> atom
+    gradient, against the forward alone; time per step and the validity
+    gate."""
+    import dataclasses
+    import numpy as np
+    import torch
+    from paper_2306_00271_amd import api
+    from synth import config3
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    base = config3(16)
+    s = next(i for i, st in enumerate(base.structures) if st.n_beams == 121)
+    wl = dataclasses.replace(base, structures=[base.structures[s]])
+    plan = api.plan_for(wl, stepper="rk6", checkpoint_every=20)
+    atoms = api.atoms_for(wl, dev)
+    ang = api.angles_for(wl, dev)
+    ws = plan.workspace(dev)
+    tgt = torch.from_numpy(np.random.default_rng(31).uniform(0.0, 0.3, size=plan.n_pairs)).to(dev)
+
+    def step():
+        U = plan.potential(atoms)
+        out = plan.forward(U, ang, workspace=ws)
+        _, dI = api.rfactor(out["intensity"], tgt)
+        dU = plan.backward(U, ang, dI, ws)
+        return out, plan.potential_backward(atoms, dU)
+
+    def fwd():
+        return plan.forward(plan.potential(atoms), ang)
+
+    res = {}
+    for name, fn in (("gradient_step", step), ("forward_only", fwd)):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            r = fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = e0.elapsed_time(e1) / steps
+        if name == "gradient_step":
+            out, g = r
+            bad = invalid_pairs(out["intensity"], out["status"], wl.absorption)
+            finite = bool(torch.isfinite(g).all().item())
+    ms = res["gradient_step"]
+    return {"structure": s, "n_beams": 121, "slices": wl.structures[0].n_slices, "angles": plan.n_pairs,
+            "checkpoint_every": 20, "ms_per_step": round(ms, 3), "value": round(plan.n_pairs / (ms / 1e3), 2),
+            "unit": "points/s (gradient step)", "ms_forward_only": round(res["forward_only"], 3),
+            "workspace_gb": round((plan.info.fwd_workspace + plan.info.bwd_workspace) / 1e9, 2),
+            "invalid_pairs": bad, "gradient_finite": finite}
+
+
 # ------------------------------------------------------------- bulk layer
 BULK_SLICES = 62   # per 3.1 A unit layer (h = 0.05 A): at 0.1 A the 61-beam stack drifts to the wrong modes
 
@@ -532,7 +589,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["fwd", "fwd+adj", "uneven", "steppers", "bulk", "fp32"], default="fwd+adj",
+    ap.add_argument("--mode", choices=["fwd", "fwd+adj", "uneven", "steppers", "bulk", "fp32", "wide-grad"],
+                    default="fwd+adj",
                     help="uneven: only the uneven-N batched forward variant; steppers: only the accuracy-vs-time "
                          "comparison of the steppers; bulk: only the bulk-layer variant; each as its own JSON line")
     ap.add_argument("--structures", type=int, default=1, help="structures in the batch (128 angles each)")
@@ -565,6 +623,9 @@ def main():
         return
     if args.mode == "fp32":
         print(json.dumps({"fp32_stages_forward": fp32_stages(steps=args.steps)}))
+        return
+    if args.mode == "wide-grad":
+        print(json.dumps({"gradient_n121": wide_gradient(steps=args.steps)}))
         return
     if args.mode == "uneven":
         print(json.dumps({"uneven_n_forward": uneven_forward(max(1, args.uneven_structures), steps=args.steps,
@@ -716,6 +777,7 @@ def main():
     if args.structures == 1:
         variants = variants or {}
         variants["fp32_stages_forward"] = fp32_stages()
+        variants["gradient_n121"] = wide_gradient()
 
     rec = {
         "metric": "rocking-curve points (structure x angle)/s at N=61 FP64; " +

@@ -147,3 +147,29 @@ def test_mixed_plan_gradient_equals_separate_plans(layout):
         np.testing.assert_allclose(du, alone["dU"], rtol=0.0, atol=1e-14 * np.abs(alone["dU"]).max())
         np.testing.assert_allclose(both["datoms"][a0:a1], alone["datoms"], rtol=1e-12,
                                    atol=1e-14 * np.abs(alone["datoms"]).max())
+
+
+def test_wide_gradient_full_size_n121():
+    """An N = 121 structure of the uneven-N workload at full size (40 A in
+    600 slices, RK6, states every 20 slices) at three angles: every pair
+    through the validity gate, and the atom gradient along a random
+    direction of all 90 atoms against the oracle's tangent-linear
+    derivative."""
+    from synth import config3
+    from tests.gpu_util import physical
+    wl = config3(16)
+    s = next(i for i, st in enumerate(wl.structures) if st.n_beams == 121)
+    idx = [5, 30, 60]
+    sub = dataclasses.replace(wl, structures=[wl.structures[s]], theta0=wl.theta0[idx])
+    assert sub.structures[0].n_slices == 600
+    tgt = _target(3, seed=19)
+    res = _run(sub, "rk6", tgt, checkpoint_every=20)
+    assert (res["status"] == 0).all()
+    assert physical(res["eta"][:, :121], sub.absorption).all()
+    atoms = sub.structures[0].atoms
+    d = np.random.default_rng(23).normal(size=atoms.shape)
+    loss, dl = driver.rfactor_directional(sub, 0, d, tgt, stepper="rk6")
+    got = float(np.sum(res["datoms"] * d))
+    print(f"[adjoint-wide] N=121 full size (3 angles) direction: gpu {got:.12e} oracle {dl:.12e}", flush=True)
+    assert res["loss"] == pytest.approx(loss, rel=1e-10)
+    assert got == pytest.approx(dl, rel=1e-8)
