@@ -89,11 +89,16 @@ typedef enum { RHEED_INTENSITY_FLUX = 0, RHEED_INTENSITY_PAPER = 1 } rheed_conve
 /* Largest beam count N the kernels of this library handle.  Structures with
  * N <= 64 run on the one- or two-workgroup kernels; structures with
  * 64 < N <= 128 run on a kernel that keeps the state of a pair in device
- * memory owned by the plan.  Both have the adjoint (RK steppers, FP64). */
-#define RHEED_MAX_BEAMS 128
-/* Largest potential-table row (rod differences) for N <= 64, and for N > 64. */
+ * memory owned by the plan.  Both have the adjoint (RK steppers, FP64).
+ * Structures with 128 < N <= 256 run on a third kernel, also with the state
+ * in plan-owned memory, which streams the rows of its eliminations through
+ * that memory: RK steppers, FP64, forward only. */
+#define RHEED_MAX_BEAMS 256
+/* Largest potential-table row (rod differences) for N <= 64, for
+ * 64 < N <= 128 and for 128 < N <= 256. */
 #define RHEED_MAX_BOX 300
 #define RHEED_MAX_BOX_LARGE 1024
+#define RHEED_MAX_BOX_XL 1536
 
 /* One slab.  Rod indices are on the reciprocal basis b1, b2:
  * k_j = h_j b1 + k_j b2 (Sec. 2.1, the reciprocal rods k_j with k_1 = 0). */
@@ -164,6 +169,8 @@ typedef struct {
   size_t bulk_workspace;     /* bytes rheed_bulk_reflection needs beyond fwd_workspace (0: not available) */
   int32_t queue;             /* 1 if rheed_forward (without a workspace) runs the batch as one persistent
                                 launch over a queue of pairs of both kinds (N <= 64 and N > 64) */
+  int32_t xl_pairs;          /* pairs of structures with N > 128 */
+  int32_t xl_slots;          /* resident workgroups (state slots) of the kernel for N > 128 */
 } rheed_plan_info;
 
 /* Vacuum wavenumber gamma (1/A) and the coefficient kappa (1/(A^2 V)) of the

@@ -68,6 +68,11 @@ struct rheed_plan_s {
   // pairs of structures with N <= 64 (propagated by the one- and two-workgroup
   // kernels) and with 64 < N <= 128 (the large kernel), in pair order
   std::vector<int> small_pairs, large_pairs;
+  // pairs of structures with 128 < N <= 256 (forward only, their own kernel)
+  std::vector<int> xl_pairs;
+  int* d_xl_pairs = nullptr;
+  char* d_xscratch = nullptr;    // per resident workgroup of that kernel: its state slot
+  int xl_slots = 0;
   int* d_small_pairs = nullptr;  // only when both kinds are present
   int* d_large_pairs = nullptr;  // in cost order (dearest first)
   int* d_large_plain = nullptr;  // in pair order
@@ -227,6 +232,10 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       delete P;
       return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) + ": FP32 stage products need N <= 64");
     }
+    if (st.n_beams > NL && (splitting || opts->stage_precision != RHEED_STAGES_FP64)) {
+      delete P;
+      return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) + ": N > 128 needs an RK stepper with FP64 stages");
+    }
     if (splitting && st.n_beams > NP && opts->stepper != RHEED_SP4) {
       delete P;
       return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) +
@@ -260,7 +269,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     d.hd = hmax - hmin;
     d.kd = kmax - kmin;
     d.box = (2 * d.hd + 1) * (2 * d.kd + 1);
-    const int box_max = (st.n_beams <= NP) ? MAXBOX : MAXBOXL;
+    const int box_max = (st.n_beams <= NP) ? MAXBOX : (st.n_beams <= NL) ? MAXBOXL : MAXBOXX;
     if (d.box > box_max) {
       delete P;
       return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) + ": rod-difference table row of " +
@@ -275,8 +284,10 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       const int W = 2 * d.kd + 1;
       const int Wp = st.n_beams <= NP ? NP : NL;
       std::vector<std::vector<int>> lists(d.box);
-      for (int j = 0; j < st.n_beams; ++j)
-        for (int k = 0; k < st.n_beams; ++k) {
+      // (no adjoint above 128 beams, so no bins there)
+      const int nb = st.n_beams <= NL ? st.n_beams : 0;
+      for (int j = 0; j < nb; ++j)
+        for (int k = 0; k < nb; ++k) {
           const int dh = st.beam_hk[2 * j] - st.beam_hk[2 * k], dk = st.beam_hk[2 * j + 1] - st.beam_hk[2 * k + 1];
           lists[(dh + d.hd) * W + (dk + d.kd)].push_back(j * Wp + k);
         }
@@ -333,7 +344,8 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     P->max_nodes = std::max(P->max_nodes, d.n_nodes);
     P->n_atoms_total += d.n_atoms;
     for (int a = 0; a < angles_per_struct[s]; ++a) {
-      ((st.n_beams <= NP) ? P->small_pairs : P->large_pairs).push_back(P->n_pairs + a);
+      ((st.n_beams <= NP) ? P->small_pairs : (st.n_beams <= NL) ? P->large_pairs : P->xl_pairs)
+          .push_back(P->n_pairs + a);
       P->pair_struct.push_back(s);
     }
     P->n_pairs += angles_per_struct[s];
@@ -402,8 +414,8 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     for (int p = 0; p < P->n_pairs; ++p) P->queue_order[p] = p;
     std::stable_sort(P->queue_order.begin(), P->queue_order.end(), [&](int x, int y) { return qcost(x) > qcost(y); });
   }
-  // the adjoint and its state saving handle the FP64 RK steppers only
-  if (P->splitting || opts->stage_precision != RHEED_STAGES_FP64) {
+  // the adjoint and its state saving handle the FP64 RK steppers and N <= 128 only
+  if (P->splitting || opts->stage_precision != RHEED_STAGES_FP64 || !P->xl_pairs.empty()) {
     P->fwd_ws = 0;
     P->bwd_ws = 0;
   }
@@ -424,7 +436,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       P->large_slots = std::min(n_large, slots);
       P->scratch_slots = P->large_slots;
       P->queue_ok = n_small > 0 && !P->splitting && opts->stage_precision == RHEED_STAGES_FP64 &&
-                    opts->layout != RHEED_LAYOUT_SPLIT;
+                    opts->layout != RHEED_LAYOUT_SPLIT && P->xl_pairs.empty();
       if (P->queue_ok) {
         const int qs = forward_queue_slots(dev);
         P->queue_ok = qs > 0;
@@ -432,6 +444,14 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
         P->scratch_slots = std::max(P->scratch_slots, P->queue_grid);
         P->use_queue = P->queue_ok;
       }
+    }
+    if (!P->xl_pairs.empty()) {
+      const int slots = have_dev ? forward_xl_slots(dev) : 0;
+      if (slots < 1) {
+        delete P;
+        return fail(RHEED_E_HIP, "the kernel for N > 128 cannot be resident on this device");
+      }
+      P->xl_slots = std::min((int)P->xl_pairs.size(), slots);
     }
     if (opts->layout == RHEED_LAYOUT_SPLIT && !P->split && n_small > 0) {
       const int mx = P->split_max;
@@ -450,7 +470,11 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (e = hipMalloc(&P->d_pbwd, sizeof(double) * 3 * PBWD_CHUNKS * std::max<long long>(1, P->n_atoms_total))) !=
           hipSuccess ||
       (P->split && (e = hipMalloc(&P->d_xch, (size_t)XCH_STRIDE * n_small)) != hipSuccess) ||
-      (n_large > 0 && n_small > 0 && (e = hipMalloc(&P->d_small_pairs, sizeof(int) * n_small)) != hipSuccess) ||
+      ((n_large > 0 || !P->xl_pairs.empty()) && n_small > 0 &&
+       (e = hipMalloc(&P->d_small_pairs, sizeof(int) * n_small)) != hipSuccess) ||
+      (!P->xl_pairs.empty() && (e = hipMalloc(&P->d_xl_pairs, sizeof(int) * P->xl_pairs.size())) != hipSuccess) ||
+      (!P->xl_pairs.empty() &&
+       (e = hipMalloc(&P->d_xscratch, (size_t)XSLOT_BYTES * P->xl_slots)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_large_pairs, sizeof(int) * n_large)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_large_plain, sizeof(int) * n_large)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_lscratch, (size_t)LSLOT_BYTES * P->scratch_slots)) != hipSuccess) ||
@@ -473,6 +497,8 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (P->split && (e = hipMemset(P->d_xch, 0, (size_t)XCH_STRIDE * n_small)) != hipSuccess) ||
       (P->d_small_pairs && (e = hipMemcpy(P->d_small_pairs, P->small_pairs.data(), sizeof(int) * n_small,
                                           hipMemcpyHostToDevice)) != hipSuccess) ||
+      (P->d_xl_pairs && (e = hipMemcpy(P->d_xl_pairs, P->xl_pairs.data(), sizeof(int) * P->xl_pairs.size(),
+                                        hipMemcpyHostToDevice)) != hipSuccess) ||
       (P->d_large_pairs && (e = hipMemcpy(P->d_large_pairs, P->large_pairs.data(), sizeof(int) * n_large,
                                           hipMemcpyHostToDevice)) != hipSuccess) ||
       (P->d_large_plain && (e = hipMemcpy(P->d_large_plain, P->large_plain.data(), sizeof(int) * n_large,
@@ -510,6 +536,8 @@ rheed_status rheed_plan_destroy(rheed_plan_t P) {
   if (P->d_large_pairs) (void)hipFree(P->d_large_pairs);
   if (P->d_large_plain) (void)hipFree(P->d_large_plain);
   if (P->d_lscratch) (void)hipFree(P->d_lscratch);
+  if (P->d_xl_pairs) (void)hipFree(P->d_xl_pairs);
+  if (P->d_xscratch) (void)hipFree(P->d_xscratch);
   if (P->d_queue_order) (void)hipFree(P->d_queue_order);
   if (P->d_queue_counter) (void)hipFree(P->d_queue_counter);
   delete P;
@@ -530,7 +558,9 @@ rheed_status rheed_plan_get_info(rheed_plan_t P, rheed_plan_info* info) {
   info->split_max_pairs = P->split_max;
   info->large_pairs = (int32_t)P->large_pairs.size();
   info->large_slots = P->large_slots;
-  info->bulk_workspace = P->large_pairs.empty() ? bulk_extra(P) : 0;
+  info->bulk_workspace = (P->large_pairs.empty() && P->xl_pairs.empty()) ? bulk_extra(P) : 0;
+  info->xl_pairs = (int32_t)P->xl_pairs.size();
+  info->xl_slots = P->xl_slots;
   info->queue = (P->use_queue && P->queue_ok) ? 1 : 0;
   return RHEED_OK;
 }
@@ -622,7 +652,9 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
   const bool f32 = P->opts.stage_precision == RHEED_STAGES_FP32;
   if (workspace && (P->splitting || f32))
     return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs an RK stepper with FP64 stages");
-  if (y_bottom && !P->large_pairs.empty())
+  if (workspace && !P->xl_pairs.empty())
+    return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs every structure to have N <= 128");
+  if (y_bottom && (!P->large_pairs.empty() || !P->xl_pairs.empty()))
     return fail(RHEED_E_UNSUPPORTED, "forward: the bulk start needs every structure to have N <= 64");
   if (y_bottom && (P->splitting || f32))
     return fail(RHEED_E_UNSUPPORTED, "forward: the bulk start needs an RK stepper with FP64 stages");
@@ -692,6 +724,18 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
     e = launch_forward_large((int)P->opts.stepper, la, st);
     if (e != hipSuccess) return hip_fail(e, "forward launch (N > 64)");
   }
+  if (!P->xl_pairs.empty()) {
+    LargeArgs xa{};
+    xa.f = a;
+    xa.f.pair_list = P->d_xl_pairs;
+    xa.f.n_pairs = (int)P->xl_pairs.size();
+    xa.f.ws = nullptr;
+    xa.f.xch = nullptr;
+    xa.scratch = P->d_xscratch;
+    xa.n_slots = P->xl_slots;
+    e = launch_forward_xl((int)P->opts.stepper, xa, st);
+    if (e != hipSuccess) return hip_fail(e, "forward launch (N > 128)");
+  }
   return RHEED_OK;
 }
 
@@ -709,7 +753,7 @@ rheed_status rheed_forward_bulk(rheed_plan_t P, const void* U_tables, const doub
                                 double* intensity, void* rho, int32_t* pair_status, int32_t* n_rhst, void* workspace,
                                 size_t ws_bytes, void* stream) {
   if (!P || !y_bottom) return fail(RHEED_E_INVALID, "forward_bulk: null argument");
-  if (!P->large_pairs.empty() || P->splitting || P->opts.stage_precision != RHEED_STAGES_FP64)
+  if (!P->large_pairs.empty() || !P->xl_pairs.empty() || P->splitting || P->opts.stage_precision != RHEED_STAGES_FP64)
     return fail(RHEED_E_UNSUPPORTED, "forward_bulk: needs an RK stepper with FP64 stages and every structure to have N <= 64");
   return forward_impl(P, U_tables, angles, intensity, rho, pair_status, n_rhst, workspace, ws_bytes, stream,
                       y_bottom, nullptr);
@@ -722,7 +766,7 @@ rheed_status rheed_bulk_reflection(rheed_plan_t P, const void* U_tables, const d
     return fail(RHEED_E_INVALID, "bulk_reflection: null argument");
   if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(RHEED_E_INVALID, "bulk_reflection: tol must be finite and >= 0");
   if (max_layers < 1) return fail(RHEED_E_INVALID, "bulk_reflection: max_layers must be >= 1");
-  if (!P->large_pairs.empty() || P->splitting || P->opts.stage_precision != RHEED_STAGES_FP64)
+  if (!P->large_pairs.empty() || !P->xl_pairs.empty() || P->splitting || P->opts.stage_precision != RHEED_STAGES_FP64)
     return fail(RHEED_E_UNSUPPORTED, "bulk_reflection: needs an RK stepper with FP64 stages and every structure to have N <= 64");
   const size_t need = P->fwd_ws + bulk_extra(P);
   if (ws_bytes < need)
@@ -856,6 +900,8 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
     return fail(RHEED_E_INVALID, "backward: null argument");
   if (P->splitting || P->opts.stage_precision != RHEED_STAGES_FP64)
     return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs an RK stepper with FP64 stages");
+  if (!P->xl_pairs.empty())
+    return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs every structure to have N <= 128");
   if (ws_bytes < P->fwd_ws + P->bwd_ws)
     return fail(RHEED_E_INVALID, "backward: workspace of " + std::to_string(ws_bytes) + " bytes < " +
                                      std::to_string(P->fwd_ws + P->bwd_ws));

@@ -7,6 +7,7 @@
 // either kind one after another in the same LDS.
 #include "rheed_forward.hip"
 #include "rheed_forward_large.hip"
+#include "rheed_forward_xl.hip"
 
 namespace rheed {
 

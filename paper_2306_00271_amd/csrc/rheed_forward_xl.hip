@@ -1,0 +1,610 @@
+// Forward propagation for 128 < N <= 256 beams on gfx950 (part of the
+// translation unit rheed_forward_all.hip, after rheed_forward_large.hip,
+// whose tableaux and slot helpers it uses).
+//
+// The state Z = [c; c'] padded to NX = 256 beams (2 MB) lives in a slot of
+// device memory owned by the workgroup running the pair, as for N <= 128.
+// At this size the stage products, not the memory traffic, bound a slice
+// (7 x 8 N^3 flop against a few MB of slot reads), so the design keeps as
+// little as possible on chip:
+//   * a slice is stepped in blocks of 16 columns (the RK right-hand side
+//     acts on columns independently); wave w of the 8 owns rows
+//     32 w .. 32 w + 31 of the block (two 16 x 16 tiles of
+//     v_mfma_f64_16x16x4f64, which share each B operand);
+//   * the stage input X_r of the block is in LDS, formed from c and c' read
+//     back from the slot and the earlier stage products G_m, which go to the
+//     slot as they are made (the Nystrom combination needs up to five of
+//     them, more than the registers of two tiles hold);
+//   * U_jk = u_{g_j - g_k} is gathered from the node table of the stage in
+//     LDS, loaded per stage into one of two table slots (a row of up to
+//     MAXBOXX entries), with gather offsets from per-beam indices in LDS;
+//   * c <- c + h c' - h^2 sum (bA)_m G_m and c' <- c' - h sum b_m G_m build
+//     up in registers and go back to the slot after the block's last stage.
+// The Gershgorin / Varah estimate of cond(Q) decides the transformation
+// Z <- Z Q^{-1} (Sec. 3.2) as for N <= 128.  The elimination of Q (column
+// Gauss-Jordan with partial pivoting, recording its multipliers) does not
+// hold Q on chip: rows are taken 64 at a time (8 per wave, 4 columns per
+// lane), the column operations of all earlier steps are replayed on them
+// from the recorded multipliers, and the block's own steps are then
+// eliminated and recorded (a left-looking order of the same operations).
+// The rows of P are replayed the same way, 64 at a time, and written back
+// in pivot order: P Q^{-1}.  The reflection eliminates Gamma Q - iP likewise
+// and applies the recorded operations in reverse to a unit vector.
+//
+// The launch is a persistent grid of one workgroup per CU over the pairs;
+// no workgroup waits for another.  Forward only, RK steppers.
+
+namespace rheed {
+namespace {
+
+constexpr int XW = 8;             // waves per workgroup
+constexpr int XT = XW * 64;       // threads per workgroup
+constexpr int XCB = 16;           // columns per block
+constexpr int XEB = 64;           // rows per elimination block
+constexpr int XEM = XEB / XW;     // rows per wave of an elimination block
+constexpr int XS = NX / 64;       // columns per lane in the eliminations
+
+static_assert(XT >= NX, "the reflection's per-row epilogue has a thread per beam");
+
+struct XLds {
+  double2 xb[NX * XCB];           // stage input of a column block; the pivot rows of the eliminations
+  double2 tb[2][MAXBOXX + 1];     // node tables of two stages; entry `box` of each stays 0
+  int off[NX];                    // h_k (2 kd + 1) + k_k of beam k (the gather offset of column k)
+  int bhk[NX][2];
+  double g2s[NX];                 // Gamma_j^2, 0 on padding
+  double rdg[NX], rof[NX];        // per row: |q_ii| and sum_{j != i} |q_ij| over j < N
+  int pcrec[NX];                  // pivot column of every elimination step
+  int pos[NX];                    // pivot step of every column in the last elimination
+  double2 xv[NX];                 // first column of the inverse in the reflection
+  unsigned long long bnorm_bits;  // ||Gamma Q - iP||_inf and ||x||_inf of the reflection
+  unsigned long long xnorm_bits;
+  int flag_singular;
+  int bad;
+};
+
+__shared__ XLds xl_lds;
+
+// Loads node nn of the structure's tables into table slot sl.
+__device__ __forceinline__ void xl_load_table(int sl, const double2* __restrict__ Us, long long nn, int box) {
+  for (int e = threadIdx.x; e < box; e += XT) xl_lds.tb[sl][e] = Us[nn * box + e];
+}
+
+// One slice of the RK step for every column block holding columns < N.
+template <int STEPPER>
+__device__ __noinline__ void xl_slice(double2* __restrict__ cg, double2* __restrict__ dg, double2* __restrict__ gm,
+                                      const double2* __restrict__ Us, int nb, int box, double h, int N,
+                                      const int (&base)[2]) {
+  using T = LTab<STEPPER>;
+  XLds& s = xl_lds;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const double hh = h * h;
+  const int ncb = (N + XCB - 1) / XCB;
+  const int nq = (N + 3) / 4;  // k-steps of 4 up to N: rows of X beyond meet zero entries of U
+  double g2[2][4];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) g2[t][v] = s.g2s[32 * w + 16 * t + 4 * v + (lane >> 4)];
+  int tag0 = -1, tag1 = -1;  // node held by each table slot (the same in every thread)
+#pragma unroll 1
+  for (int cb = 0; cb < ncb; ++cb) {
+    const int col = XCB * cb + (lane & 15);
+    double cnr[2][4], cni[2][4], dnr[2][4], dni[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 32 * w + 16 * t + 4 * v + (lane >> 4);
+        const double2 c = gld(&cg[row * NX + col]), d = gld(&dg[row * NX + col]);
+        cnr[t][v] = c.x + h * d.x;
+        cni[t][v] = c.y + h * d.y;
+        dnr[t][v] = d.x;
+        dni[t][v] = d.y;
+      }
+#pragma unroll 1
+    for (int r = 0; r < T::stages; ++r) {
+      const int nn = nb + T::node(r);
+      int sl;
+      if (tag0 == nn) {
+        sl = 0;
+      } else if (tag1 == nn) {
+        sl = 1;
+      } else {  // load into the slot the previous stage did not use
+        sl = (r > 0 && tag0 == nb + T::node(r - 1)) ? 1 : 0;
+        xl_load_table(sl, Us, nn, box);
+        if (sl == 0) tag0 = nn;
+        else tag1 = nn;
+      }
+      // X_r = c + h c_r c' - h^2 sum_{m < r} (A^2)_{rm} G_m, this thread's elements
+      const double hc = h * T::c(r);
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 32 * w + 16 * t + 4 * v + (lane >> 4);
+          const double2 c = gld(&cg[row * NX + col]), d = gld(&dg[row * NX + col]);
+          double xr = c.x + hc * d.x, xi = c.y + hc * d.y;
+#pragma unroll
+          for (int m = 0; m < 6; ++m) {
+            if (m < r && T::a2(r, m) != 0.0) {
+              const double2 g = gld(&gm[(m * NX + row) * XCB + (lane & 15)]);
+              xr -= hh * T::a2(r, m) * g.x;
+              xi -= hh * T::a2(r, m) * g.y;
+            }
+          }
+          s.xb[row * XCB + (lane & 15)] = make_double2(xr, xi);
+        }
+      __syncthreads();
+      // G_r = U X_r + Gamma^2 X_r on the two tiles (3-real-product form)
+      const double2* __restrict__ tsl = s.tb[sl];
+      d4 p1[2], p2[2], p3[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) p1[t] = p2[t] = p3[t] = d4{0, 0, 0, 0};
+      const int ra0 = 32 * w + (lane & 15), ra1 = ra0 + 16;  // A-operand rows of the two tiles
+#pragma unroll 2
+      for (int q = 0; q < nq; ++q) {
+        const int k = 4 * q + (lane >> 4);
+        const double2 x = s.xb[k * XCB + (lane & 15)];
+        const int ok = s.off[k];
+        const bool kin = k < N;
+        const double2 u0 = tsl[(kin && ra0 < N) ? base[0] - ok : box];
+        const double2 u1 = tsl[(kin && ra1 < N) ? base[1] - ok : box];
+        const double xs = x.x + x.y;
+        p1[0] = mfma(u0.x, x.x, p1[0]);
+        p2[0] = mfma(u0.y, x.y, p2[0]);
+        p3[0] = mfma(u0.x + u0.y, xs, p3[0]);
+        p1[1] = mfma(u1.x, x.x, p1[1]);
+        p2[1] = mfma(u1.y, x.y, p2[1]);
+        p3[1] = mfma(u1.x + u1.y, xs, p3[1]);
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 32 * w + 16 * t + 4 * v + (lane >> 4);
+          const double2 x = s.xb[row * XCB + (lane & 15)];
+          const double gr = p1[t][v] - p2[t][v] + g2[t][v] * x.x;
+          const double gi = p3[t][v] - p1[t][v] - p2[t][v] + g2[t][v] * x.y;
+          if (r + 1 < T::stages) gst(&gm[(r * NX + row) * XCB + (lane & 15)], make_double2(gr, gi));
+          if (T::ba(r) != 0.0) {
+            cnr[t][v] -= hh * T::ba(r) * gr;
+            cni[t][v] -= hh * T::ba(r) * gi;
+          }
+          dnr[t][v] -= h * T::b(r) * gr;
+          dni[t][v] -= h * T::b(r) * gi;
+        }
+      __syncthreads();  // xb and the table slots are reused by the next stage
+    }
+    // the stepped block back to the slot, and its share of the row sums of |c|
+    double pdg[2][4], pof[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = 32 * w + 16 * t + 4 * v + (lane >> 4);
+        gst(&cg[row * NX + col], make_double2(cnr[t][v], cni[t][v]));
+        gst(&dg[row * NX + col], make_double2(dnr[t][v], dni[t][v]));
+        const double av = sqrt(cnr[t][v] * cnr[t][v] + cni[t][v] * cni[t][v]);
+        const bool in = row < N && col < N;
+        pdg[t][v] = (in && row == col) ? av : 0.0;
+        pof[t][v] = (in && row != col) ? av : 0.0;
+      }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+          pdg[t][v] += __shfl_xor(pdg[t][v], o, 64);
+          pof[t][v] += __shfl_xor(pof[t][v], o, 64);
+        }
+    if ((lane & 15) == 0) {
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 32 * w + 16 * t + 4 * v + (lane >> 4);
+          s.rdg[row] = (cb == 0 ? 0.0 : s.rdg[row]) + pdg[t][v];
+          s.rof[row] = (cb == 0 ? 0.0 : s.rof[row]) + pof[t][v];
+        }
+    }
+  }
+  __syncthreads();
+}
+
+// Rows m < R of z: column j <- column j - f_j column pc, pc = 64 HF + pl
+// (the pivot column's quarter is wave-uniform, so it selects code).
+template <int HF, int R>
+__device__ __forceinline__ void xl_col_update(double2 (&z)[R][XS], int pl, const double2 (&f)[XS]) {
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const double2 zp = make_double2(readlane_f64(z[m][HF].x, pl), readlane_f64(z[m][HF].y, pl));
+#pragma unroll
+    for (int q = 0; q < XS; ++q) {
+      z[m][q].x = fma(-f[q].x, zp.x, z[m][q].x);
+      z[m][q].x = fma(f[q].y, zp.y, z[m][q].x);
+      z[m][q].y = fma(-f[q].x, zp.y, z[m][q].y);
+      z[m][q].y = fma(-f[q].y, zp.x, z[m][q].y);
+    }
+    if ((m & 1) == 1) __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void xl_update(double2 (&z)[R][XS], int pc, const double2 (&f)[XS]) {
+  const int hf = pc >> 6, pl = pc & 63;
+  switch (hf) {
+    case 0: xl_col_update<0, R>(z, pl, f); break;
+    case 1: xl_col_update<1, R>(z, pl, f); break;
+    case 2: xl_col_update<2, R>(z, pl, f); break;
+    default: xl_col_update<3, R>(z, pl, f); break;
+  }
+}
+
+// The recorded column operations of steps [0, k1) on the rows in z.
+template <int R>
+__device__ __forceinline__ void xl_replay(double2 (&z)[R][XS], int k1, int lane, const double2* __restrict__ frec) {
+#pragma unroll 1
+  for (int k = 0; k < k1; ++k) {
+    double2 f[XS];
+#pragma unroll
+    for (int q = 0; q < XS; ++q) f[q] = gld(&frec[k * NX + 64 * q + lane]);
+    xl_update<R>(z, __builtin_amdgcn_readfirstlane(xl_lds.pcrec[k]), f);
+  }
+}
+
+// Recording elimination of the n x n leading block of Q = c (which = 0) or
+// of Gamma Q - iP (which = 1), 64 rows at a time (rows k0 + w + 8 m of
+// block k0 in wave w): the steps of earlier blocks are replayed on the
+// block's rows, then the block's steps are taken in turn: step k picks,
+// among unused columns < n, the one with the largest |A_kj| (key: the upper
+// 32 bits of |A_kj|^2 with the low 8 bits replaced by 255 - j), records
+// f_j = A_kj / A_k,pc (f_pc = 1 - 1 / A_k,pc) and its pivot column, and
+// subtracts f_j column pc from every column j of the block's rows.  Row
+// k + 1 reaches the other waves through LDS.  s.pos gets the step at which
+// each column was the pivot (its own index for columns >= n).
+__device__ __noinline__ void xl_elim_record(const double2* __restrict__ cg, const double2* __restrict__ dg,
+                                            double2* __restrict__ frec, int N, int which) {
+  XLds& s = xl_lds;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int n = __builtin_amdgcn_readfirstlane(N);
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  const bool refl = __builtin_amdgcn_readfirstlane(which) != 0;
+  unsigned long long um[XS] = {0, 0, 0, 0};  // used columns (the same in every wave)
+  double2* rowbuf = s.xb;
+#pragma unroll 1
+  for (int k0 = 0; k0 < n; k0 += XEB) {
+    double2 z[XEM][XS];
+#pragma unroll
+    for (int m = 0; m < XEM; ++m) {
+      const int row = k0 + wu + XW * m;
+      double gr = 0.0, gi = 0.0;
+      if (refl && row < n) {
+        const double g2v = s.g2s[row];
+        gr = g2v >= 0.0 ? sqrt(g2v) : 0.0;
+        gi = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
+      }
+#pragma unroll
+      for (int q = 0; q < XS; ++q) {
+        const int c = 64 * q + lane;
+        double2 v = make_double2(0.0, 0.0);
+        if (row < n) {
+          const double2 cv = gld(&cg[row * NX + c]);
+          if (refl) {
+            const double2 pv = gld(&dg[row * NX + c]);
+            v = make_double2(gr * cv.x - gi * cv.y + pv.y, gr * cv.y + gi * cv.x - pv.x);
+          } else {
+            v = cv;
+          }
+        }
+        z[m][q] = v;
+      }
+    }
+    xl_replay<XEM>(z, k0, lane, frec);
+    const int k1 = n < k0 + XEB ? n : k0 + XEB;
+    __syncthreads();  // rowbuf aliases the stage buffer and the previous block's last row
+    if (wu == 0) {
+#pragma unroll
+      for (int q = 0; q < XS; ++q) rowbuf[64 * q + lane] = z[0][q];
+    }
+#pragma unroll 1
+    for (int k = k0; k < k1; ++k) {
+      const int slot = k & 1;
+      __syncthreads();
+      double2 v[XS];
+      unsigned key = 0;
+#pragma unroll
+      for (int q = 0; q < XS; ++q) {
+        v[q] = rowbuf[slot * NX + 64 * q + lane];
+        const int c = 64 * q + lane;
+        if (!((um[q] >> lane) & 1ull) && c < n) {
+          const double m2 = v[q].x * v[q].x + v[q].y * v[q].y;
+          const unsigned kq =
+              ((unsigned)(((unsigned long long)__double_as_longlong(m2)) >> 32) & ~255u) | (unsigned)(255 - c);
+          key = kq > key ? kq : key;
+        }
+      }
+      key = wave_max_u32(key);
+      if ((key >> 8) == 0 && tid == 0) s.flag_singular = 1;
+      const int pc = 255 - (int)(key & 255);
+      const int hf = pc >> 6, pl = pc & 63;
+#pragma unroll
+      for (int q = 0; q < XS; ++q)
+        if (q == hf) um[q] |= 1ull << pl;
+      double2 vs = v[0];
+#pragma unroll
+      for (int q = 1; q < XS; ++q)
+        if (q == hf) vs = v[q];
+      const double2 piv = make_double2(readlane_f64(vs.x, pl), readlane_f64(vs.y, pl));
+      const double inv = 1.0 / (piv.x * piv.x + piv.y * piv.y);
+      const double2 ip = make_double2(piv.x * inv, -piv.y * inv);
+      double2 f[XS];
+#pragma unroll
+      for (int q = 0; q < XS; ++q) {
+        f[q] = make_double2(v[q].x * ip.x - v[q].y * ip.y, v[q].x * ip.y + v[q].y * ip.x);
+        if (q == hf && lane == pl) f[q] = make_double2(1.0 - ip.x, -ip.y);
+      }
+      if (wu == 0) {
+#pragma unroll
+        for (int q = 0; q < XS; ++q) gst(&frec[k * NX + 64 * q + lane], f[q]);
+        if (lane == 0) s.pcrec[k] = pc;
+      }
+      xl_update<XEM>(z, pc, f);
+      // row k + 1 of this block: wave (k + 1 - k0) % 8, register (k + 1 - k0) / 8
+      const int nx = k + 1 - k0;
+      if (k + 1 < k1 && wu == (nx & (XW - 1))) {
+        const int mr = nx / XW;
+#pragma unroll
+        for (int m = 0; m < XEM; ++m)
+          if (m == mr) {
+#pragma unroll
+            for (int q = 0; q < XS; ++q) rowbuf[(slot ^ 1) * NX + 64 * q + lane] = z[m][q];
+          }
+      }
+    }
+  }
+  // the multipliers and pivot list are read back by this workgroup only
+  __syncthreads();
+  if (tid < NX) s.pos[tid] = tid;
+  __syncthreads();
+  if (tid < n) s.pos[s.pcrec[tid]] = tid;
+  __syncthreads();
+}
+
+// P <- P Q^{-1} after xl_elim_record(which = 0): the recorded operations on
+// the rows of P, 64 at a time, each column put at its pivot step; c <- I.
+__device__ __noinline__ void xl_replay_p(double2* __restrict__ cg, double2* __restrict__ dg,
+                                         const double2* __restrict__ frec, int N) {
+  XLds& s = xl_lds;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n = __builtin_amdgcn_readfirstlane(N);
+  int pq[XS];
+#pragma unroll
+  for (int q = 0; q < XS; ++q) pq[q] = s.pos[64 * q + lane];
+  // rows >= n are zero rows of P and unit rows of c, which the
+  // transformation leaves as they are
+#pragma unroll 1
+  for (int r0 = 0; r0 < n; r0 += XEB) {
+    double2 z[XEM][XS];
+#pragma unroll
+    for (int m = 0; m < XEM; ++m)
+#pragma unroll
+      for (int q = 0; q < XS; ++q) z[m][q] = gld(&dg[(r0 + w + XW * m) * NX + 64 * q + lane]);
+    xl_replay<XEM>(z, n, lane, frec);
+#pragma unroll
+    for (int m = 0; m < XEM; ++m) {
+      const int row = r0 + w + XW * m;
+#pragma unroll
+      for (int q = 0; q < XS; ++q) {
+        gst(&dg[row * NX + pq[q]], z[m][q]);
+        gst(&cg[row * NX + 64 * q + lane], make_double2(row == 64 * q + lane ? 1.0 : 0.0, 0.0));
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <int STEPPER>
+__device__ void xl_run_pair(const LargeArgs& A, int p, char* slot) {
+  using T = LTab<STEPPER>;
+  const FwdArgs& a = A.f;
+  XLds& s = xl_lds;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  double2* __restrict__ cg = reinterpret_cast<double2*>(slot + XSLOT_C);
+  double2* __restrict__ dg = reinterpret_cast<double2*>(slot + XSLOT_D);
+  double2* __restrict__ frec = reinterpret_cast<double2*>(slot + XSLOT_F);
+  double2* __restrict__ gm = reinterpret_cast<double2*>(slot + XSLOT_G);
+  const StructDev S = a.structs[a.pair_struct[p]];
+  const int N = S.n_beams;
+  const int L = S.n_slices;
+  const double h = S.h;
+  const double2* __restrict__ Us = a.U + S.table_off;
+  const int Wd = 2 * S.kd + 1;
+
+  if (tid < NX) {
+    const int hk0 = tid < N ? a.beams[2 * (S.beam_off + tid)] : 0;
+    const int hk1 = tid < N ? a.beams[2 * (S.beam_off + tid) + 1] : 0;
+    s.bhk[tid][0] = hk0;
+    s.bhk[tid][1] = hk1;
+    s.off[tid] = hk0 * Wd + hk1;
+  }
+  if (tid == 0) {
+    s.flag_singular = 0;
+    s.bad = 0;
+  }
+  if (tid < 2) s.tb[tid][S.box] = make_double2(0.0, 0.0);
+  __syncthreads();
+  const double th0 = a.angles[2 * p], th1 = a.angles[2 * p + 1];
+  if (tid < NX) {
+    // Gamma_j^2 = gamma^2 - |b0 + k_j|^2 (Sec. 2.1), b0 = gamma cos(theta0) (cos theta1, sin theta1)
+    const double b0x = S.gamma * cos(th0) * cos(th1);
+    const double b0y = S.gamma * cos(th0) * sin(th1);
+    double arg = 0.0;
+    if (tid < N) {
+      const double qx = b0x + s.bhk[tid][0] * S.recip[0] + s.bhk[tid][1] * S.recip[2];
+      const double qy = b0y + s.bhk[tid][0] * S.recip[1] + s.bhk[tid][1] * S.recip[3];
+      arg = S.gamma * S.gamma - (qx * qx + qy * qy);
+    }
+    s.g2s[tid] = arg;
+  }
+  __syncthreads();
+  // table index of U_{ik} = u_{g_i - g_k} is base_i - off_k for the A-operand
+  // rows of the thread's two tiles
+  int base[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int i = 32 * w + 16 * t + (lane & 15);
+    base[t] = (s.bhk[i][0] + S.hd) * Wd + (s.bhk[i][1] + S.kd);
+  }
+  // Z0 = [I; i Gamma] (spans the columns of S^{-1}[I; O] of Algorithm 1)
+  for (int e = tid; e < NX * NX; e += XT) {
+    const int row = e / NX, col = e - row * NX;
+    const double g2v = s.g2s[row];
+    const bool dgn = row == col;
+    gst(&cg[e], make_double2(dgn ? 1.0 : 0.0, 0.0));
+    gst(&dg[e], make_double2((dgn && g2v < 0.0) ? sqrt(-g2v) : 0.0, (dgn && g2v >= 0.0) ? sqrt(g2v) : 0.0));
+  }
+  __syncthreads();
+  int nrhst = 0;
+#pragma unroll 1
+  for (int i = 0; i < L; ++i) {
+    xl_slice<STEPPER>(cg, dg, gm, Us, i * T::nodes, S.box, h, N, base);
+    // condition estimate of Q = c (Sec. 3.2): the Gershgorin / Varah bound
+    double hi = 0.0, lo = 1.0e308;
+#pragma unroll
+    for (int q = 0; q < XS; ++q) {
+      const int row = 64 * q + lane;
+      if (row < N) {
+        const double dv = s.rdg[row], ov = s.rof[row];
+        hi = fmax(hi, dv + ov);
+        lo = fmin(lo, dv - ov);
+      }
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      hi = fmax(hi, __shfl_xor(hi, o, 64));
+      lo = fmin(lo, __shfl_xor(lo, o, 64));
+    }
+    const double xi = lo > 0.0 ? hi / lo : INFINITY;
+    if (xi > a.threshold) {
+      ++nrhst;
+      xl_elim_record(cg, dg, frec, N, 0);
+      xl_replay_p(cg, dg, frec, N);
+    }
+  }
+  // reflection (Eq. vrhocomp): upper = Gamma Q - iP, lower = Gamma Q + iP,
+  // rho = lower x with upper x = e_1
+  xl_elim_record(cg, dg, frec, N, 1);
+  if (w == 0) {
+    // x = E e_{pc_0}: the recorded operations in reverse order, each v <- v - e_pc (f . v)
+    const int pc0 = s.pcrec[0];
+    double2 v[XS];
+#pragma unroll
+    for (int q = 0; q < XS; ++q) v[q] = make_double2(64 * q + lane == pc0 ? 1.0 : 0.0, 0.0);
+#pragma unroll 1
+    for (int k = N - 1; k >= 0; --k) {
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int q = 0; q < XS; ++q) {
+        const double2 f = gld(&frec[k * NX + 64 * q + lane]);
+        sr += f.x * v[q].x - f.y * v[q].y;
+        si += f.x * v[q].y + f.y * v[q].x;
+      }
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        sr += __shfl_xor(sr, o, 64);
+        si += __shfl_xor(si, o, 64);
+      }
+      const int pc = __builtin_amdgcn_readfirstlane(s.pcrec[k]);
+      if (lane == (pc & 63)) {
+#pragma unroll
+        for (int q = 0; q < XS; ++q)
+          if (q == (pc >> 6)) v[q] = make_double2(v[q].x - sr, v[q].y - si);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < XS; ++q) s.xv[64 * q + lane] = v[q];
+  }
+  if (tid == 0) {
+    s.bnorm_bits = 0;
+    s.xnorm_bits = 0;
+  }
+  __syncthreads();
+  if (tid < a.ld) {
+    const int j = tid;
+    double eta = 0.0;
+    double2 rj = make_double2(0.0, 0.0);
+    if (j < N) {
+      const double g2v = s.g2s[j];
+      const double g_r = g2v >= 0.0 ? sqrt(g2v) : 0.0, g_i = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
+      double rs = 0.0;  // row j of Gamma Q - iP, for the breakdown test
+      for (int k = 0; k < N; ++k) {
+        const double2 cv = gld(&cg[j * NX + k]), pv = gld(&dg[j * NX + k]), x = s.xv[k];
+        const double lr = g_r * cv.x - g_i * cv.y - pv.y, li = g_r * cv.y + g_i * cv.x + pv.x;
+        rj.x += lr * x.x - li * x.y;
+        rj.y += lr * x.y + li * x.x;
+        const double br = g_r * cv.x - g_i * cv.y + pv.y, bi = g_r * cv.y + g_i * cv.x - pv.x;
+        rs += sqrt(br * br + bi * bi);
+      }
+      if (g2v > 0.0) {
+        eta = (rj.x * rj.x + rj.y * rj.y) * sqrt(s.g2s[0]) / sqrt(g2v);
+        if (a.convention == 1) eta *= sin(th0);
+      }
+      if (!(isfinite(rj.x) && isfinite(rj.y))) atomicOr(&s.bad, 1);
+      const double2 xj = s.xv[j];
+      const double xm = sqrt(xj.x * xj.x + xj.y * xj.y);
+      if (rs == rs) atomicMax(&s.bnorm_bits, (unsigned long long)__double_as_longlong(rs));
+      if (xm == xm) atomicMax(&s.xnorm_bits, (unsigned long long)__double_as_longlong(xm));
+    }
+    a.intensity[(long long)p * a.ld + j] = eta;
+    if (a.rho) a.rho[(long long)p * a.ld + j] = rj;
+  }
+  __syncthreads();
+  const bool brk = !(__longlong_as_double((long long)s.bnorm_bits) * __longlong_as_double((long long)s.xnorm_bits) <=
+                     BREAKDOWN_COND);
+  const int stv = s.flag_singular ? 1 : s.bad ? 2 : brk ? 4 : 0;
+  if (stv != 0 && tid < N) {  // a failed pair's outputs are NaN
+    a.intensity[(long long)p * a.ld + tid] = NAN;
+    if (a.rho) a.rho[(long long)p * a.ld + tid] = make_double2(NAN, NAN);
+  }
+  if (tid == 0) {
+    a.status[p] = stv;
+    if (a.nrhst) a.nrhst[p] = nrhst;
+  }
+}
+
+template <int STEPPER>
+__global__ __launch_bounds__(XT, 1) void forward_xl_kernel(LargeArgs A) {
+  char* slot = A.scratch + (long long)blockIdx.x * XSLOT_BYTES;
+#pragma unroll 1
+  for (int pi = blockIdx.x; pi < A.f.n_pairs; pi += gridDim.x) {
+    const int p = A.f.pair_list ? A.f.pair_list[pi] : pi;
+    xl_run_pair<STEPPER>(A, p, slot);
+    __syncthreads();  // LDS is reused by the next pair
+  }
+}
+
+}  // namespace
+
+hipError_t launch_forward_xl(int stepper, const LargeArgs& a, hipStream_t stream) {
+  if (a.f.n_pairs < 1) return hipSuccess;
+  const int grid = a.f.n_pairs < a.n_slots ? a.f.n_pairs : a.n_slots;
+  if (grid < 1 || (stepper != 0 && stepper != 1) || a.f.ws) return hipErrorInvalidValue;
+  if (stepper == 0)
+    hipLaunchKernelGGL(forward_xl_kernel<0>, dim3(grid), dim3(XT), 0, stream, a);
+  else
+    hipLaunchKernelGGL(forward_xl_kernel<1>, dim3(grid), dim3(XT), 0, stream, a);
+  return hipGetLastError();
+}
+
+int forward_xl_slots(int device) {
+  int cus = 0, p0 = 0, p1 = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p0, forward_xl_kernel<0>, XT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&p1, forward_xl_kernel<1>, XT, 0) != hipSuccess)
+    return 0;
+  const int per = p0 < p1 ? p0 : p1;
+  return cus * (per > 0 ? per : 0);
+}
+
+}  // namespace rheed

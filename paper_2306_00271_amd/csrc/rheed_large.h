@@ -16,6 +16,18 @@ constexpr long long LSLOT_D = (long long)NL * NL * 16;
 constexpr long long LSLOT_F = 2LL * NL * NL * 16;
 constexpr long long LSLOT_BYTES = 3LL * NL * NL * 16;
 
+constexpr int NX = 256;         // padded beam count of the kernel for 128 < N <= 256
+constexpr int MAXBOXX = 1536;   // rod-difference entries per node table row of that kernel
+
+// Device memory of one resident workgroup of the kernel for 128 < N <= 256:
+// c and c' ([NX][NX] complex), the multipliers of its last elimination
+// ([NX][NX]) and the stage products of one column block ([6][NX][16]).
+constexpr long long XSLOT_C = 0;
+constexpr long long XSLOT_D = (long long)NX * NX * 16;
+constexpr long long XSLOT_F = 2LL * NX * NX * 16;
+constexpr long long XSLOT_G = 3LL * NX * NX * 16;
+constexpr long long XSLOT_BYTES = XSLOT_G + 6LL * NX * 16 * 16;
+
 struct LargeArgs {
   FwdArgs f;       // f.pair_list / f.n_pairs: the pairs this kernel runs
   char* scratch;   // n_slots * LSLOT_BYTES, plan-owned
@@ -28,6 +40,9 @@ struct LargeArgs {
 
 hipError_t launch_forward_large(int stepper, const LargeArgs& a, hipStream_t stream);
 int forward_large_slots(int device);  // resident workgroups of the large kernel on the device
+// 128 < N <= 256 (RK steppers, forward only): scratch holds n_slots * XSLOT_BYTES
+hipError_t launch_forward_xl(int stepper, const LargeArgs& a, hipStream_t stream);
+int forward_xl_slots(int device);
 
 // One persistent launch over a batch of pairs with N <= 64 and N > 64
 // (forward_queue_kernel): workgroups take pairs in the order of `order`

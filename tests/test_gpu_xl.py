@@ -1,0 +1,96 @@
+"""Parity of the forward pass for 128 < N <= 256 (the kernel that keeps the
+state in plan-owned memory, stores its stage products there and streams the
+rows of its eliminations) with the oracle's RK multi-slice, through the C
+ABI: several tiles and a ragged tail (N = 129, 160, 199 and the full width
+256), both RK steppers, a batch mixing all three kernels, the N = 199
+workload's slab at full size on sampled angles, and the refusals."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from synth import small_2d
+from tests.gpu_util import eacc, gpu_forward, oracle_forward, physical
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+def _report(name, e):
+    print(f"[parity-xl] {name}: eacc={e:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("stepper,n_beams", [("rk6", 129), ("rk6", 160), ("rk4", 199), ("rk6", 199), ("rk6", 256)])
+def test_forward_xl_matches_oracle(stepper, n_beams):
+    L = 20 if stepper == "rk6" else 32
+    wl = small_2d(n_beams=n_beams, n_slices=L, thickness=0.1 * L, n_layers=1, n_angles=3)
+    res = gpu_forward(wl, stepper=stepper, want_rho=True)
+    assert res["plan"].info.xl_pairs == 3
+    ref, rho_ref, nr = oracle_forward(wl, stepper=stepper)
+    got = res["intensity"][:, :n_beams]
+    assert (res["status"] == 0).all()
+    e = eacc(got, ref)
+    _report(f"{stepper} N={n_beams} rhst={nr.tolist()} gpu_rhst={res['n_rhst'].tolist()}", e)
+    assert e <= TOL
+    assert res["n_rhst"].tolist() == nr.tolist()
+    rho = res["rho"][:, :n_beams]
+    assert np.abs(rho - rho_ref).max() <= 1e-9 * np.abs(rho_ref).max()
+
+
+def test_batch_mixing_three_kernels():
+    """N = 45, 91 and 199 in one plan (one launch per kernel): each
+    structure against the oracle, and zeros beyond each structure's N."""
+    parts = [small_2d(n_beams=n, n_slices=L, thickness=0.1 * L, n_layers=1, n_angles=2, seed=80 + i)
+             for i, (n, L) in enumerate(((45, 30), (91, 24), (199, 16)))]
+    wl = dataclasses.replace(parts[0], structures=[p.structures[0] for p in parts])
+    res = gpu_forward(wl, stepper="rk6")
+    info = res["plan"].info
+    assert info.large_pairs == 2 and info.xl_pairs == 2 and not info.queue
+    assert (res["status"] == 0).all()
+    A = len(wl.theta0)
+    for s, p in enumerate(parts):
+        N = p.structures[0].n_beams
+        ref, _, _ = oracle_forward(wl, s_idx=s, stepper="rk6")
+        e = eacc(res["intensity"][s * A:(s + 1) * A, :N], ref)
+        _report(f"mixed batch structure {s} N={N}", e)
+        assert e <= TOL
+        assert np.all(res["intensity"][s * A:(s + 1) * A, N:] == 0.0)
+
+
+def test_n199_workload_full_size_sampled():
+    """The N = 199 slab of the large workload at full size (60 A in 1000
+    slices, RK6) at four angles: every pair through the validity gate, and
+    one angle against the oracle."""
+    from synth import config5
+    wl = config5(1)
+    idx = [10, 100, 180, 250]
+    sub = dataclasses.replace(wl, theta0=wl.theta0[idx])
+    res = gpu_forward(sub, stepper="rk6")
+    assert (res["status"] == 0).all()
+    got = res["intensity"][:, :199]
+    assert physical(got, sub.absorption).all()
+    ref, _, nr = oracle_forward(sub, angle_idx=[1], stepper="rk6")
+    e = eacc(got[[1]], ref)
+    _report(f"N=199 full size, angle {idx[1]}, rhst gpu {res['n_rhst'][1]} oracle {nr.tolist()}", e)
+    assert e <= TOL
+
+
+def test_xl_refusals():
+    import torch
+    from paper_2306_00271_amd import api
+    from paper_2306_00271_amd._lib import RheedError
+    wl = small_2d(n_beams=150, n_slices=4, thickness=0.4, n_layers=1, n_angles=2)
+    for kw in ({"stepper": "sp4"}, {"stepper": "rk6", "stage_precision": "fp32"}):
+        with pytest.raises(RheedError, match="N > 128|N <= 64"):
+            api.plan_for(wl, **kw)
+    plan = api.plan_for(wl, stepper="rk6")
+    assert plan.info.fwd_workspace == 0 and plan.info.bwd_workspace == 0
+    dev = torch.device("cuda:0")
+    U = plan.potential(api.atoms_for(wl, dev))
+    ws = torch.empty(1024, dtype=torch.uint8, device=dev)
+    with pytest.raises(RheedError, match="N <= 128"):
+        plan.forward(U, api.angles_for(wl, dev), workspace=ws)
+    dI = torch.zeros((plan.n_pairs, plan.max_beams), dtype=torch.float64, device=dev)
+    with pytest.raises(RheedError, match="N <= 128"):
+        plan.backward(U, api.angles_for(wl, dev), dI, ws)
