@@ -91,6 +91,17 @@ def _cpu_worker(args):
         t0 = time.perf_counter()
         driver.rocking_curve(wl3, s_idx=idx, angle_idx=[(idx * 37) % len(wl3.theta0)], stepper=stepper)
         return time.perf_counter() - t0
+    if kind == "n199":
+        # one pair of the N = 199 workload over its first args[3] slices (same step)
+        import dataclasses
+        from synth import config5
+        w5 = config5(1)
+        st5 = w5.structures[0]
+        part = dataclasses.replace(st5, n_slices=args[3], thickness=st5.thickness * args[3] / st5.n_slices)
+        w5 = dataclasses.replace(w5, structures=[part])
+        t0 = time.perf_counter()
+        driver.rocking_curve(w5, angle_idx=[idx], stepper=stepper)
+        return time.perf_counter() - t0
     wl = config4(1)
     t0 = time.perf_counter()
     if kind == "fwd":
@@ -405,6 +416,60 @@ def wide_gradient(steps=2):
             "invalid_pairs": bad, "gradient_finite": finite}
 
 
+def n199_forward(steps=1, cpu=True):
+    """Forward throughput on one structure of the N = 199 workload (7x7
+    supercell, 49 atoms x 12 layers, 60 A in 1000 slices, RK6, all 256
+    angles: one pair per CU), the kernel for 128 < N <= 256, with its
+    algorithmic FP64 rate; the whole workload (64 structures) is 64 such
+    batches."""
+    import torch
+    from paper_2306_00271_amd import api
+    from synth import config5
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    wl = config5(1)
+    plan = api.plan_for(wl, stepper="rk6")
+    U = plan.potential(api.atoms_for(wl, dev))
+    ang = api.angles_for(wl, dev)
+    out = plan.forward(U, ang, want_nrhst=True)
+    torch.cuda.synchronize()
+    print(f"[n199] warm-up forward done ({plan.n_pairs} pairs)", file=sys.stderr, flush=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        out = plan.forward(U, ang, want_nrhst=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = wl.structures[0]
+    nr = out["n_rhst"].cpu().numpy()
+    fl = _flops_forward(st.n_beams, st.n_slices, 7, int(nr.sum()), plan.n_pairs)
+    res = {"pairs": plan.n_pairs, "n_beams": st.n_beams, "slices": st.n_slices, "ms_per_forward": round(ms, 2),
+           "value": round(plan.n_pairs / (ms / 1e3), 3), "unit": "points/s (forward)",
+           "achieved_tflops": round(fl / (ms / 1e3) / 1e12, 3),
+           "frac_of_published": round(fl / (ms / 1e3) / 1e12 / MFMA_FP64_PEAK_TFLOPS, 4),
+           "rhst_per_pair": round(float(nr.mean()), 1), "xl_slots": int(plan.info.xl_slots),
+           "invalid_pairs": invalid_pairs(out["intensity"], out["status"], wl.absorption),
+           "projected_s_whole_workload": round(64 * ms / 1e3, 1)}
+    if cpu:
+        import multiprocessing as mp
+        cores = min(16, os.cpu_count() or 1)
+        part = 100
+        jobs = [("n199", (c * 256) // cores, "rk6", part) for c in range(cores)]
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(cores) as pool:
+            times = pool.map(_cpu_worker, jobs)
+        cwall = time.perf_counter() - t0
+        per_pair = float(sum(times) / len(times)) * st.n_slices / part
+        res["cpu_baseline"] = {"value": round(cores / per_pair, 5), "unit": "points/s", "cores": cores, "kind": "oracle",
+                               "sample": f"{cores} pairs (one angle each) over the first {part} of the {st.n_slices} "
+                                         f"slices, oracle forward, scaled to the whole slab: {per_pair:.1f} s per "
+                                         f"pair; {cores} processes x 1 BLAS thread, {cwall:.1f} s wall"}
+    return res
+
+
 # ------------------------------------------------------------- bulk layer
 BULK_SLICES = 62   # per 3.1 A unit layer (h = 0.05 A): at 0.1 A the 61-beam stack drifts to the wrong modes
 
@@ -589,7 +654,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["fwd", "fwd+adj", "uneven", "steppers", "bulk", "fp32", "wide-grad"],
+    ap.add_argument("--mode", choices=["fwd", "fwd+adj", "uneven", "steppers", "bulk", "fp32", "wide-grad", "n199"],
                     default="fwd+adj",
                     help="uneven: only the uneven-N batched forward variant; steppers: only the accuracy-vs-time "
                          "comparison of the steppers; bulk: only the bulk-layer variant; each as its own JSON line")
@@ -626,6 +691,9 @@ def main():
         return
     if args.mode == "wide-grad":
         print(json.dumps({"gradient_n121": wide_gradient(steps=args.steps)}))
+        return
+    if args.mode == "n199":
+        print(json.dumps({"n199_forward": n199_forward(steps=args.steps, cpu=not args.no_cpu)}))
         return
     if args.mode == "uneven":
         print(json.dumps({"uneven_n_forward": uneven_forward(max(1, args.uneven_structures), steps=args.steps,
@@ -778,6 +846,7 @@ def main():
         variants = variants or {}
         variants["fp32_stages_forward"] = fp32_stages()
         variants["gradient_n121"] = wide_gradient()
+        variants["n199_forward"] = n199_forward(cpu=not args.no_cpu)
 
     rec = {
         "metric": "rocking-curve points (structure x angle)/s at N=61 FP64; " +
