@@ -453,6 +453,27 @@ def n199_forward(steps=1, cpu=True):
            "rhst_per_pair": round(float(nr.mean()), 1), "xl_slots": int(plan.info.xl_slots),
            "invalid_pairs": invalid_pairs(out["intensity"], out["status"], wl.absorption),
            "projected_s_whole_workload": round(64 * ms / 1e3, 1)}
+    del plan, U
+    # one pair alone (the paper's single-angle case): on one workgroup, and
+    # on a group of workgroups that step its column blocks side by side
+    import dataclasses
+    single = dataclasses.replace(wl, theta0=wl.theta0[100:101])
+    res["single_pair"] = {}
+    for layout in ("whole", "auto"):
+        p1 = api.plan_for(single, stepper="rk6", layout=layout)
+        U1 = p1.potential(api.atoms_for(single, dev))
+        a1 = api.angles_for(single, dev)
+        p1.forward(U1, a1)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        o1 = p1.forward(U1, a1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        key = "one_workgroup" if p1.info.xl_group == 1 else f"group_of_{p1.info.xl_group}"
+        res["single_pair"][key] = {"ms": round(e0.elapsed_time(e1), 2),
+                                   "invalid_pairs": invalid_pairs(o1["intensity"], o1["status"], wl.absorption)}
+        print(f"[n199] single pair, {key}: {res['single_pair'][key]['ms']} ms", file=sys.stderr, flush=True)
+        del p1, U1
     if cpu:
         import multiprocessing as mp
         cores = min(16, os.cpu_count() or 1)

@@ -128,7 +128,9 @@ typedef struct {
  * of every pair resident at once, so it holds at most one pair per two CUs
  * (rheed_plan_info.split_max_pairs).  WHOLE runs a pair on one workgroup.
  * AUTO picks SPLIT when the batch fits, WHOLE otherwise.  The results of the
- * two layouts agree to rounding. */
+ * two layouts agree to rounding.  For structures with N > 128, WHOLE keeps
+ * one workgroup per pair; AUTO and SPLIT give a batch that cannot fill the
+ * device a group of workgroups per pair (rheed_plan_info.xl_group). */
 typedef enum { RHEED_LAYOUT_AUTO = 0, RHEED_LAYOUT_WHOLE = 1, RHEED_LAYOUT_SPLIT = 2 } rheed_layout;
 
 /* Precision of the RK stage products U X (the paper's Sec. 6 names single
@@ -171,6 +173,9 @@ typedef struct {
                                 launch over a queue of pairs of both kinds (N <= 64 and N > 64) */
   int32_t xl_pairs;          /* pairs of structures with N > 128 */
   int32_t xl_slots;          /* resident workgroups (state slots) of the kernel for N > 128 */
+  int32_t xl_group;          /* workgroups per pair with N > 128: 1, or (a batch too small to fill the
+                                device, layout not WHOLE) a cooperative group stepping the pair's
+                                column blocks side by side */
 } rheed_plan_info;
 
 /* Vacuum wavenumber gamma (1/A) and the coefficient kappa (1/(A^2 V)) of the

@@ -73,6 +73,7 @@ class PlanInfo(C.Structure):
         ("queue", C.c_int32),
         ("xl_pairs", C.c_int32),
         ("xl_slots", C.c_int32),
+        ("xl_group", C.c_int32),
     ]
 
 

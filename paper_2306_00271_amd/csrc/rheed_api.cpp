@@ -73,6 +73,11 @@ struct rheed_plan_s {
   int* d_xl_pairs = nullptr;
   char* d_xscratch = nullptr;    // per resident workgroup of that kernel: its state slot
   int xl_slots = 0;
+  // small batches: a group of xl_group workgroups per pair (1: one workgroup per pair)
+  int xl_group = 1;
+  char* d_xg_pair = nullptr;
+  char* d_xg_wg = nullptr;
+  unsigned* d_xg_cnt = nullptr;
   int* d_small_pairs = nullptr;  // only when both kinds are present
   int* d_large_pairs = nullptr;  // in cost order (dearest first)
   int* d_large_plain = nullptr;  // in pair order
@@ -452,6 +457,14 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
         return fail(RHEED_E_HIP, "the kernel for N > 128 cannot be resident on this device");
       }
       P->xl_slots = std::min((int)P->xl_pairs.size(), slots);
+      // a batch that cannot fill the device runs each pair on a group of
+      // workgroups (one per 16-column block at most), as many as fit at once
+      int maxn = 0;
+      for (int q : P->xl_pairs) maxn = std::max(maxn, P->hs[P->pair_struct[q]].n_beams);
+      const int n_xl = (int)P->xl_pairs.size();
+      const int cap = opts->layout != RHEED_LAYOUT_WHOLE ? forward_xl_group_max_workgroups(dev) : 0;
+      const int g = std::min((maxn + 15) / 16, cap / n_xl);
+      P->xl_group = g >= 2 ? g : 1;
     }
     if (opts->layout == RHEED_LAYOUT_SPLIT && !P->split && n_small > 0) {
       const int mx = P->split_max;
@@ -473,8 +486,14 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       ((n_large > 0 || !P->xl_pairs.empty()) && n_small > 0 &&
        (e = hipMalloc(&P->d_small_pairs, sizeof(int) * n_small)) != hipSuccess) ||
       (!P->xl_pairs.empty() && (e = hipMalloc(&P->d_xl_pairs, sizeof(int) * P->xl_pairs.size())) != hipSuccess) ||
-      (!P->xl_pairs.empty() &&
+      (!P->xl_pairs.empty() && P->xl_group == 1 &&
        (e = hipMalloc(&P->d_xscratch, (size_t)XSLOT_BYTES * P->xl_slots)) != hipSuccess) ||
+      (P->xl_group > 1 &&
+       (e = hipMalloc(&P->d_xg_pair, (size_t)XG_PAIR_BYTES * P->xl_pairs.size())) != hipSuccess) ||
+      (P->xl_group > 1 &&
+       (e = hipMalloc(&P->d_xg_wg, (size_t)XG_WG_BYTES * P->xl_group * P->xl_pairs.size())) != hipSuccess) ||
+      (P->xl_group > 1 &&
+       (e = hipMalloc(&P->d_xg_cnt, sizeof(unsigned) * 16 * P->xl_pairs.size())) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_large_pairs, sizeof(int) * n_large)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_large_plain, sizeof(int) * n_large)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_lscratch, (size_t)LSLOT_BYTES * P->scratch_slots)) != hipSuccess) ||
@@ -538,6 +557,9 @@ rheed_status rheed_plan_destroy(rheed_plan_t P) {
   if (P->d_lscratch) (void)hipFree(P->d_lscratch);
   if (P->d_xl_pairs) (void)hipFree(P->d_xl_pairs);
   if (P->d_xscratch) (void)hipFree(P->d_xscratch);
+  if (P->d_xg_pair) (void)hipFree(P->d_xg_pair);
+  if (P->d_xg_wg) (void)hipFree(P->d_xg_wg);
+  if (P->d_xg_cnt) (void)hipFree(P->d_xg_cnt);
   if (P->d_queue_order) (void)hipFree(P->d_queue_order);
   if (P->d_queue_counter) (void)hipFree(P->d_queue_counter);
   delete P;
@@ -561,6 +583,7 @@ rheed_status rheed_plan_get_info(rheed_plan_t P, rheed_plan_info* info) {
   info->bulk_workspace = (P->large_pairs.empty() && P->xl_pairs.empty()) ? bulk_extra(P) : 0;
   info->xl_pairs = (int32_t)P->xl_pairs.size();
   info->xl_slots = P->xl_slots;
+  info->xl_group = P->xl_group;
   info->queue = (P->use_queue && P->queue_ok) ? 1 : 0;
   return RHEED_OK;
 }
@@ -733,7 +756,16 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
     xa.f.xch = nullptr;
     xa.scratch = P->d_xscratch;
     xa.n_slots = P->xl_slots;
-    e = launch_forward_xl((int)P->opts.stepper, xa, st);
+    if (P->xl_group > 1) {
+      XlGroup xg{};
+      xg.pair_mem = P->d_xg_pair;
+      xg.wg_mem = P->d_xg_wg;
+      xg.counters = P->d_xg_cnt;
+      xg.group = P->xl_group;
+      e = launch_forward_xl_group((int)P->opts.stepper, xa, xg, st);
+    } else {
+      e = launch_forward_xl((int)P->opts.stepper, xa, st);
+    }
     if (e != hipSuccess) return hip_fail(e, "forward launch (N > 128)");
   }
   return RHEED_OK;

@@ -33,6 +33,16 @@
 //
 // The launch is a persistent grid of one workgroup per CU over the pairs;
 // no workgroup waits for another.  Forward only, RK steppers.
+//
+// For a batch too small to fill the device (down to one pair) the same
+// phases run in a group launch: G cooperatively launched workgroups per pair
+// share the pair's state in memory and step the column blocks cb = g,
+// g + G, ... of every slice (the RK stages act on columns independently).
+// Per slice they meet at one barrier to sum their row-sum partials (in the
+// same order in every workgroup, so all take the same decision); at a
+// transformation workgroup 0 records the elimination, the others wait, and
+// all then replay it on their 64-row blocks of P.  Workgroup 0 alone solves
+// the reflection.
 
 namespace rheed {
 namespace {
@@ -60,6 +70,7 @@ struct XLds {
   unsigned long long xnorm_bits;
   int flag_singular;
   int bad;
+  int sync_fail;                  // group launch: a wait of this workgroup gave up
 };
 
 __shared__ XLds xl_lds;
@@ -69,11 +80,12 @@ __device__ __forceinline__ void xl_load_table(int sl, const double2* __restrict_
   for (int e = threadIdx.x; e < box; e += XT) xl_lds.tb[sl][e] = Us[nn * box + e];
 }
 
-// One slice of the RK step for every column block holding columns < N.
+// One slice of the RK step for the column blocks cb0, cb0 + cbs, ... that
+// hold columns < N; s.rdg / s.rof get those blocks' share of the row sums.
 template <int STEPPER>
 __device__ __noinline__ void xl_slice(double2* __restrict__ cg, double2* __restrict__ dg, double2* __restrict__ gm,
                                       const double2* __restrict__ Us, int nb, int box, double h, int N,
-                                      const int (&base)[2]) {
+                                      const int (&base)[2], int cb0, int cbs) {
   using T = LTab<STEPPER>;
   XLds& s = xl_lds;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -86,8 +98,14 @@ __device__ __noinline__ void xl_slice(double2* __restrict__ cg, double2* __restr
 #pragma unroll
     for (int v = 0; v < 4; ++v) g2[t][v] = s.g2s[32 * w + 16 * t + 4 * v + (lane >> 4)];
   int tag0 = -1, tag1 = -1;  // node held by each table slot (the same in every thread)
+  __syncthreads();  // every wave has read the previous slice's row sums (the badness) before they are cleared
+  if (tid < NX) {
+    s.rdg[tid] = 0.0;
+    s.rof[tid] = 0.0;
+  }
+  __syncthreads();
 #pragma unroll 1
-  for (int cb = 0; cb < ncb; ++cb) {
+  for (int cb = cb0; cb < ncb; cb += cbs) {
     const int col = XCB * cb + (lane & 15);
     double cnr[2][4], cni[2][4], dnr[2][4], dni[2][4];
 #pragma unroll
@@ -204,8 +222,8 @@ __device__ __noinline__ void xl_slice(double2* __restrict__ cg, double2* __restr
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = 32 * w + 16 * t + 4 * v + (lane >> 4);
-          s.rdg[row] = (cb == 0 ? 0.0 : s.rdg[row]) + pdg[t][v];
-          s.rof[row] = (cb == 0 ? 0.0 : s.rof[row]) + pof[t][v];
+          s.rdg[row] += pdg[t][v];
+          s.rof[row] += pof[t][v];
         }
     }
   }
@@ -372,9 +390,10 @@ __device__ __noinline__ void xl_elim_record(const double2* __restrict__ cg, cons
 }
 
 // P <- P Q^{-1} after xl_elim_record(which = 0): the recorded operations on
-// the rows of P, 64 at a time, each column put at its pivot step; c <- I.
+// the rows of P, 64 at a time (row blocks b0, b0 + bs, ...), each column put
+// at its pivot step; c <- I on the same rows.
 __device__ __noinline__ void xl_replay_p(double2* __restrict__ cg, double2* __restrict__ dg,
-                                         const double2* __restrict__ frec, int N) {
+                                         const double2* __restrict__ frec, int N, int b0, int bs) {
   XLds& s = xl_lds;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int n = __builtin_amdgcn_readfirstlane(N);
@@ -384,7 +403,7 @@ __device__ __noinline__ void xl_replay_p(double2* __restrict__ cg, double2* __re
   // rows >= n are zero rows of P and unit rows of c, which the
   // transformation leaves as they are
 #pragma unroll 1
-  for (int r0 = 0; r0 < n; r0 += XEB) {
+  for (int r0 = XEB * b0; r0 < n; r0 += XEB * bs) {
     double2 z[XEM][XS];
 #pragma unroll
     for (int m = 0; m < XEM; ++m)
@@ -404,16 +423,55 @@ __device__ __noinline__ void xl_replay_p(double2* __restrict__ cg, double2* __re
   __syncthreads();
 }
 
-template <int STEPPER>
-__device__ void xl_run_pair(const LargeArgs& A, int p, char* slot) {
+// Barrier of the G workgroups of one pair in a group launch: each raises the
+// pair's counter (an agent-scope release, so its stores are written back
+// first) and waits until all have reached `target` (G times the barriers so
+// far), then acquires.  A wait gives up after XCH_SPIN polls or XCH_TICKS of
+// the constant-rate clock, sets s.sync_fail and the pair's failure word, and
+// the workgroup stops waiting from then on (every wait is bounded).
+__device__ __forceinline__ void xl_group_sync(unsigned* cnt, unsigned target, unsigned* fail_word) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are issued and complete
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (!xl_lds.sync_fail) {
+      const long long t0 = wall_clock64();
+      int it = 0;
+      while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++it > XCH_SPIN || wall_clock64() - t0 > XCH_TICKS) {
+          xl_lds.sync_fail = 1;
+          __hip_atomic_store(fail_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// One pair.  GRP: workgroup g of the pair's G in a group launch (state,
+// multipliers and pivot list in the pair's block of X.pair_mem, stage
+// products and row-sum partials in the workgroup's block of X.wg_mem);
+// otherwise the whole pair in this workgroup's slot.
+template <int STEPPER, bool GRP>
+__device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup& X, int pi, int g) {
   using T = LTab<STEPPER>;
   const FwdArgs& a = A.f;
   XLds& s = xl_lds;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  double2* __restrict__ cg = reinterpret_cast<double2*>(slot + XSLOT_C);
-  double2* __restrict__ dg = reinterpret_cast<double2*>(slot + XSLOT_D);
-  double2* __restrict__ frec = reinterpret_cast<double2*>(slot + XSLOT_F);
-  double2* __restrict__ gm = reinterpret_cast<double2*>(slot + XSLOT_G);
+  const int G = GRP ? X.group : 1;
+  char* pm = GRP ? X.pair_mem + (long long)pi * XG_PAIR_BYTES : slot;
+  char* wm = GRP ? X.wg_mem + ((long long)pi * G + g) * XG_WG_BYTES : slot + XSLOT_G;
+  double2* __restrict__ cg = reinterpret_cast<double2*>(pm + XSLOT_C);
+  double2* __restrict__ dg = reinterpret_cast<double2*>(pm + XSLOT_D);
+  double2* __restrict__ frec = reinterpret_cast<double2*>(pm + XSLOT_F);
+  double2* __restrict__ gm = reinterpret_cast<double2*>(wm);
+  int* pivg = reinterpret_cast<int*>(pm + XSLOT_G);  // GRP: the pivot list of the last elimination
+  unsigned* cnt = GRP ? X.counters + 16LL * pi : nullptr;
+  unsigned* failw = GRP ? cnt + 1 : nullptr;
+  unsigned nsync = 0;
   const StructDev S = a.structs[a.pair_struct[p]];
   const int N = S.n_beams;
   const int L = S.n_slices;
@@ -431,6 +489,7 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot) {
   if (tid == 0) {
     s.flag_singular = 0;
     s.bad = 0;
+    s.sync_fail = 0;
   }
   if (tid < 2) s.tb[tid][S.box] = make_double2(0.0, 0.0);
   __syncthreads();
@@ -456,19 +515,43 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot) {
     const int i = 32 * w + 16 * t + (lane & 15);
     base[t] = (s.bhk[i][0] + S.hd) * Wd + (s.bhk[i][1] + S.kd);
   }
-  // Z0 = [I; i Gamma] (spans the columns of S^{-1}[I; O] of Algorithm 1)
-  for (int e = tid; e < NX * NX; e += XT) {
+  // Z0 = [I; i Gamma] (spans the columns of S^{-1}[I; O] of Algorithm 1); in
+  // a group launch each workgroup writes its share of the rows
+  for (int e = tid + XT * g; e < NX * NX; e += XT * G) {
     const int row = e / NX, col = e - row * NX;
     const double g2v = s.g2s[row];
     const bool dgn = row == col;
     gst(&cg[e], make_double2(dgn ? 1.0 : 0.0, 0.0));
     gst(&dg[e], make_double2((dgn && g2v < 0.0) ? sqrt(-g2v) : 0.0, (dgn && g2v >= 0.0) ? sqrt(g2v) : 0.0));
   }
-  __syncthreads();
+  if constexpr (GRP) xl_group_sync(cnt, G * ++nsync, failw);
+  else __syncthreads();
   int nrhst = 0;
 #pragma unroll 1
   for (int i = 0; i < L; ++i) {
-    xl_slice<STEPPER>(cg, dg, gm, Us, i * T::nodes, S.box, h, N, base);
+    xl_slice<STEPPER>(cg, dg, gm, Us, i * T::nodes, S.box, h, N, base, g, G);
+    if constexpr (GRP) {
+      // the row-sum partials of every workgroup of the pair, summed in the
+      // same order everywhere (two buffers: a workgroup cannot be a slice ahead)
+      double* part = reinterpret_cast<double*>(wm + XG_STAGE_BYTES) + 2 * NX * (i & 1);
+      if (tid < NX) {
+        part[tid] = s.rdg[tid];
+        part[NX + tid] = s.rof[tid];
+      }
+      xl_group_sync(cnt, G * ++nsync, failw);
+      if (tid < NX) {
+        double dv = 0.0, ov = 0.0;
+        for (int q = 0; q < G; ++q) {
+          const double* pq = reinterpret_cast<const double*>(X.wg_mem + ((long long)pi * G + q) * XG_WG_BYTES +
+                                                             XG_STAGE_BYTES) + 2 * NX * (i & 1);
+          dv += pq[tid];
+          ov += pq[NX + tid];
+        }
+        s.rdg[tid] = dv;
+        s.rof[tid] = ov;
+      }
+      __syncthreads();
+    }
     // condition estimate of Q = c (Sec. 3.2): the Gershgorin / Varah bound
     double hi = 0.0, lo = 1.0e308;
 #pragma unroll
@@ -488,9 +571,32 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot) {
     const double xi = lo > 0.0 ? hi / lo : INFINITY;
     if (xi > a.threshold) {
       ++nrhst;
-      xl_elim_record(cg, dg, frec, N, 0);
-      xl_replay_p(cg, dg, frec, N);
+      if constexpr (GRP) {
+        // workgroup 0 records the elimination; all replay it on their row blocks of P
+        if (g == 0) {
+          xl_elim_record(cg, dg, frec, N, 0);
+          if (tid < NX) pivg[tid] = s.pcrec[tid];
+        }
+        xl_group_sync(cnt, G * ++nsync, failw);
+        if (g != 0) {
+          if (tid < NX) {
+            s.pcrec[tid] = pivg[tid];
+            s.pos[tid] = tid;
+          }
+          __syncthreads();
+          if (tid < N) s.pos[s.pcrec[tid]] = tid;
+          __syncthreads();
+        }
+        xl_replay_p(cg, dg, frec, N, g, G);
+        xl_group_sync(cnt, G * ++nsync, failw);
+      } else {
+        xl_elim_record(cg, dg, frec, N, 0);
+        xl_replay_p(cg, dg, frec, N, 0, 1);
+      }
     }
+  }
+  if constexpr (GRP) {
+    if (g != 0) return;  // workgroup 0 solves the reflection
   }
   // reflection (Eq. vrhocomp): upper = Gamma Q - iP, lower = Gamma Q + iP,
   // rho = lower x with upper x = e_1
@@ -562,7 +668,10 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot) {
   __syncthreads();
   const bool brk = !(__longlong_as_double((long long)s.bnorm_bits) * __longlong_as_double((long long)s.xnorm_bits) <=
                      BREAKDOWN_COND);
-  const int stv = s.flag_singular ? 1 : s.bad ? 2 : brk ? 4 : 0;
+  bool lost = false;
+  if constexpr (GRP)
+    lost = s.sync_fail || __hip_atomic_load(failw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+  const int stv = lost ? 3 : s.flag_singular ? 1 : s.bad ? 2 : brk ? 4 : 0;
   if (stv != 0 && tid < N) {  // a failed pair's outputs are NaN
     a.intensity[(long long)p * a.ld + tid] = NAN;
     if (a.rho) a.rho[(long long)p * a.ld + tid] = make_double2(NAN, NAN);
@@ -579,9 +688,22 @@ __global__ __launch_bounds__(XT, 1) void forward_xl_kernel(LargeArgs A) {
 #pragma unroll 1
   for (int pi = blockIdx.x; pi < A.f.n_pairs; pi += gridDim.x) {
     const int p = A.f.pair_list ? A.f.pair_list[pi] : pi;
-    xl_run_pair<STEPPER>(A, p, slot);
+    xl_run_pair<STEPPER, false>(A, p, slot, XlGroup{}, 0, 0);
     __syncthreads();  // LDS is reused by the next pair
   }
+}
+
+// Group launch: G workgroups per pair, grid = pairs x G, all resident
+// (cooperative launch).
+template <int STEPPER>
+__global__ __launch_bounds__(XT, 1) void forward_xl_group_kernel(LargeArgs A, XlGroup X) {
+  const int pi = blockIdx.x / X.group, g = blockIdx.x - pi * X.group;
+  const int p = A.f.pair_list ? A.f.pair_list[pi] : pi;
+  xl_run_pair<STEPPER, true>(A, p, nullptr, X, pi, g);
+}
+
+__global__ void xl_group_reset_kernel(unsigned* counters, int n) {
+  for (int e = threadIdx.x; e < 16 * n; e += blockDim.x) counters[e] = 0u;
 }
 
 }  // namespace
@@ -595,6 +717,29 @@ hipError_t launch_forward_xl(int stepper, const LargeArgs& a, hipStream_t stream
   else
     hipLaunchKernelGGL(forward_xl_kernel<1>, dim3(grid), dim3(XT), 0, stream, a);
   return hipGetLastError();
+}
+
+hipError_t launch_forward_xl_group(int stepper, const LargeArgs& a, const XlGroup& x, hipStream_t stream) {
+  if (a.f.n_pairs < 1) return hipSuccess;
+  if (x.group < 1 || (stepper != 0 && stepper != 1) || a.f.ws) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(xl_group_reset_kernel, dim3(1), dim3(256), 0, stream, x.counters, a.f.n_pairs);
+  LargeArgs aa = a;
+  XlGroup xx = x;
+  void* params[] = {&aa, &xx};
+  const void* f = stepper == 0 ? reinterpret_cast<const void*>(&forward_xl_group_kernel<0>)
+                               : reinterpret_cast<const void*>(&forward_xl_group_kernel<1>);
+  return hipLaunchCooperativeKernel(f, dim3(a.f.n_pairs * x.group), dim3(XT), params, 0, stream);
+}
+
+int forward_xl_group_max_workgroups(int device) {
+  int coop = 0, cus = 0, p0 = 0, p1 = 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p0, forward_xl_group_kernel<0>, XT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&p1, forward_xl_group_kernel<1>, XT, 0) != hipSuccess)
+    return 0;
+  const int per = p0 < p1 ? p0 : p1;
+  return cus * (per > 0 ? per : 0);
 }
 
 int forward_xl_slots(int device) {

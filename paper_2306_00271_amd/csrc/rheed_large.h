@@ -44,6 +44,24 @@ int forward_large_slots(int device);  // resident workgroups of the large kernel
 hipError_t launch_forward_xl(int stepper, const LargeArgs& a, hipStream_t stream);
 int forward_xl_slots(int device);
 
+// Group launch of the same kernel for small batches: `group` workgroups per
+// pair share the pair's state.  Per pair: c, c', the multipliers and the
+// pivot list (XG_PAIR_BYTES); per workgroup: the stage products of one
+// column block and two buffers of row-sum partials (XG_WG_BYTES); per pair
+// 16 counter words (barrier count, failure word), cleared by the launch.
+constexpr long long XG_STAGE_BYTES = 6LL * NX * 16 * 16;
+constexpr long long XG_PAIR_BYTES = XSLOT_G + 4LL * NX;
+constexpr long long XG_WG_BYTES = XG_STAGE_BYTES + 2LL * 2 * NX * 8;
+struct XlGroup {
+  char* pair_mem;
+  char* wg_mem;
+  unsigned* counters;
+  int group;
+  int pad;
+};
+hipError_t launch_forward_xl_group(int stepper, const LargeArgs& a, const XlGroup& x, hipStream_t stream);
+int forward_xl_group_max_workgroups(int device);  // co-resident workgroups of a group launch (0: none)
+
 // One persistent launch over a batch of pairs with N <= 64 and N > 64
 // (forward_queue_kernel): workgroups take pairs in the order of `order`
 // from a counter in device memory; the N <= 64 pairs run the one-workgroup

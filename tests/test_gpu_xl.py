@@ -21,17 +21,21 @@ def _report(name, e):
     print(f"[parity-xl] {name}: eacc={e:.3e}", flush=True)
 
 
+@pytest.mark.parametrize("layout", ["auto", "whole"])
 @pytest.mark.parametrize("stepper,n_beams", [("rk6", 129), ("rk6", 160), ("rk4", 199), ("rk6", 199), ("rk6", 256)])
-def test_forward_xl_matches_oracle(stepper, n_beams):
+def test_forward_xl_matches_oracle(stepper, n_beams, layout):
+    """Three pairs: with layout AUTO each on a group of workgroups (one per
+    16-column block), with WHOLE each on one workgroup."""
     L = 20 if stepper == "rk6" else 32
     wl = small_2d(n_beams=n_beams, n_slices=L, thickness=0.1 * L, n_layers=1, n_angles=3)
-    res = gpu_forward(wl, stepper=stepper, want_rho=True)
+    res = gpu_forward(wl, stepper=stepper, want_rho=True, layout=layout)
     assert res["plan"].info.xl_pairs == 3
+    assert res["plan"].info.xl_group == (1 if layout == "whole" else (n_beams + 15) // 16)
     ref, rho_ref, nr = oracle_forward(wl, stepper=stepper)
     got = res["intensity"][:, :n_beams]
     assert (res["status"] == 0).all()
     e = eacc(got, ref)
-    _report(f"{stepper} N={n_beams} rhst={nr.tolist()} gpu_rhst={res['n_rhst'].tolist()}", e)
+    _report(f"{stepper} N={n_beams} {layout} rhst={nr.tolist()} gpu_rhst={res['n_rhst'].tolist()}", e)
     assert e <= TOL
     assert res["n_rhst"].tolist() == nr.tolist()
     rho = res["rho"][:, :n_beams]
@@ -56,6 +60,35 @@ def test_batch_mixing_three_kernels():
         _report(f"mixed batch structure {s} N={N}", e)
         assert e <= TOL
         assert np.all(res["intensity"][s * A:(s + 1) * A, N:] == 0.0)
+
+
+@pytest.mark.parametrize("n_beams", [150, 199])
+def test_group_and_one_workgroup_agree(n_beams):
+    """The group launch (columns of a pair on several CUs, row sums summed
+    across them) and the one-workgroup launch give the same curves and the
+    same transformation counts."""
+    wl = small_2d(n_beams=n_beams, n_slices=40, thickness=4.0, n_layers=2, n_angles=2, seed=5)
+    grp = gpu_forward(wl, stepper="rk6", layout="auto")
+    one = gpu_forward(wl, stepper="rk6", layout="whole")
+    assert grp["plan"].info.xl_group > 1 and one["plan"].info.xl_group == 1
+    assert (grp["status"] == 0).all() and (one["status"] == 0).all()
+    assert grp["n_rhst"].tolist() == one["n_rhst"].tolist()
+    d = np.abs(grp["intensity"] - one["intensity"]).max()
+    print(f"[parity-xl] N={n_beams} group vs one workgroup: max |diff| = {d:.3e}", flush=True)
+    np.testing.assert_allclose(grp["intensity"], one["intensity"], rtol=0.0, atol=1e-13)
+
+
+def test_single_pair_group_matches_oracle():
+    """One pair of N = 256 alone (16 workgroups on it) against the oracle."""
+    wl = small_2d(n_beams=256, n_slices=24, thickness=2.4, n_layers=1, n_angles=1, theta_range=(2.0, 2.0))
+    res = gpu_forward(wl, stepper="rk6")
+    assert res["plan"].info.xl_group == 16
+    ref, _, nr = oracle_forward(wl, stepper="rk6")
+    assert (res["status"] == 0).all()
+    e = eacc(res["intensity"][:, :256], ref)
+    _report(f"single pair N=256 on 16 workgroups rhst={nr.tolist()} gpu={res['n_rhst'].tolist()}", e)
+    assert e <= TOL
+    assert res["n_rhst"].tolist() == nr.tolist()
 
 
 def test_n199_workload_full_size_sampled():
