@@ -71,8 +71,9 @@ enum {
  * drifts before it have reached; the node tables of a splitting stepper sit
  * at those positions (3 per slice for the fourth-order methods, 9 for the
  * sixth-order ones; positions may lie outside the slice).  Splitting
- * steppers run forward only (no state saving, no rheed_backward, no bulk
- * start), on the one-workgroup layout; for N > 64 only RHEED_SP4. */
+ * steppers run on the one-workgroup layout, with state saving and
+ * rheed_backward for N <= 64 (no bulk start); for N > 64 only RHEED_SP4,
+ * forward only. */
 typedef enum {
   RHEED_RK4 = 0,
   RHEED_RK6 = 1,

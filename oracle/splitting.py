@@ -81,6 +81,21 @@ class Composition:
         q = q - h * self.b[-1] * (Ms[-1] @ c)
         return np.vstack([c, q])
 
+    def step_tangent(self, Z, dZ, Ms, dMs, h):
+        """The slice and its derivative along dZ and the tangents dMs of the
+        M(tau_r) (each kick and drift is linear in (c, c'), so the tangent
+        takes the same kicks and drifts plus -h b_r dM_r c in each kick)."""
+        n = Z.shape[0] // 2
+        c, q, dc, dq = Z[:n].copy(), Z[n:].copy(), dZ[:n].copy(), dZ[n:].copy()
+        for r in range(self.a.size):
+            dq = dq - h * self.b[r] * (dMs[r] @ c + Ms[r] @ dc)
+            q = q - h * self.b[r] * (Ms[r] @ c)
+            c = c + h * self.a[r] * q
+            dc = dc + h * self.a[r] * dq
+        dq = dq - h * self.b[-1] * (dMs[-1] @ c + Ms[-1] @ dc)
+        q = q - h * self.b[-1] * (Ms[-1] @ c)
+        return np.vstack([c, q]), np.vstack([dc, dq])
+
 
 class CompositionABA:
     """An ABA splitting method: drift weights a (s + 1), kick weights b (s).
@@ -121,6 +136,19 @@ class CompositionABA:
             q = q - h * self.b[r] * (Ms[r] @ c)
             c = c + h * self.a[r + 1] * q
         return np.vstack([c, q])
+
+    def step_tangent(self, Z, dZ, Ms, dMs, h):
+        """The slice and its derivative (as Composition.step_tangent)."""
+        n = Z.shape[0] // 2
+        c, q, dc, dq = Z[:n].copy(), Z[n:].copy(), dZ[:n].copy(), dZ[n:].copy()
+        c = c + h * self.a[0] * q
+        dc = dc + h * self.a[0] * dq
+        for r in range(self.b.size):
+            dq = dq - h * self.b[r] * (dMs[r] @ c + Ms[r] @ dc)
+            q = q - h * self.b[r] * (Ms[r] @ c)
+            c = c + h * self.a[r + 1] * q
+            dc = dc + h * self.a[r + 1] * dq
+        return np.vstack([c, q]), np.vstack([dc, dq])
 
 
 def _half_sums(w):

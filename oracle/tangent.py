@@ -1,4 +1,4 @@
-"""Tangent-linear (forward-mode) derivative of the RK method (oracle; test infrastructure).
+"""Tangent-linear (forward-mode) derivative of the RK and splitting methods (oracle; test infrastructure).
 
 Differentiates ``rk.solve_ode_str`` along a direction dU of the potential
 table.  Every step of Algorithm 1 (Sec. 3.2) is linear in Z, so the
@@ -35,6 +35,16 @@ def solve_ode_str_tangent(Mfun, dUfun, gam, h, n_slices, tab, threshold=THRESHOL
     Z = initial_state(gam, y_bottom=y_bottom)
     dZ = np.zeros_like(Z)
     for i in range(n_slices):
+        if hasattr(tab, "step_tangent"):
+            # a splitting method (Sec. 3.4): kicks and drifts, each linear in Z
+            Ms = [Mfun(i, r) for r in range(tab.stages)]
+            dMs = [dUfun(i, r) for r in range(tab.stages)]
+            Z, dZ = tab.step_tangent(Z, dZ, Ms, dMs, h)
+            if estcond_gershgorin(Z[:n]) > threshold:
+                T = np.linalg.inv(Z[:n])
+                Z = Z @ T
+                dZ = (dZ - Z @ dZ[:n]) @ T
+            continue
         K, dK = [], []
         for r in range(tab.stages):
             Yr, dYr = Z.copy(), dZ.copy()

@@ -373,8 +373,11 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     c.state_bytes = (long long)2 * w * w * sizeof(double2);
     const long long mat = (long long)w * w * sizeof(double2), slot_bytes = (long long)max_l * mat;
     c.q_off = c.max_ckpt * c.state_bytes;
-    c.r_off = c.every > 1 ? c.q_off + slot_bytes : 0;
-    const long long end = (c.every > 1 ? c.r_off : c.q_off) + slot_bytes;
+    // a splitting method keeps R at every K: the BAB method's final kick changes
+    // the final state, which therefore cannot stand for the last slice's R
+    const bool rslots = c.every > 1 || P->splitting;
+    c.r_off = rslots ? c.q_off + slot_bytes : 0;
+    const long long end = (rslots ? c.r_off : c.q_off) + slot_bytes;
     c.binv_off = binv ? end : 0;
     c.flags_off = end + (binv ? mat : 0);
     c.pair_stride = ((c.flags_off + max_l + 255) / 256) * 256;
@@ -388,8 +391,15 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
   }
   const int wmax = wide ? NL : NP;
   P->fwd_ws = (size_t)P->ck.pair_stride * P->n_pairs;
-  // adjoint stage buffer: (v_r, g_r) of every stage of every slice
-  P->g_pair_stride = (long long)max_l * (P->opts.stepper == RHEED_RK4 ? 4 : 7) * 2 * wmax;
+  // adjoint stage buffer: (v_r, g_r) of every stage of every slice; for a
+  // splitting method of every kick it keeps per slice (the BAB method's final
+  // kick in one more slice)
+  if (P->splitting) {
+    const int nks = P->sp.form == 0 ? P->sp.kicks - 1 : P->sp.kicks;
+    P->g_pair_stride = (long long)(max_l + 1) * nks * 2 * wmax;
+  } else {
+    P->g_pair_stride = (long long)max_l * (P->opts.stepper == RHEED_RK4 ? 4 : 7) * 2 * wmax;
+  }
   P->bwd_ws = (size_t)P->g_pair_stride * sizeof(double2) * P->n_pairs;
   if (P->ck.every > 1) {  // x at the transformed states of a segment
     P->xs_off = P->bwd_ws;
@@ -419,8 +429,10 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     for (int p = 0; p < P->n_pairs; ++p) P->queue_order[p] = p;
     std::stable_sort(P->queue_order.begin(), P->queue_order.end(), [&](int x, int y) { return qcost(x) > qcost(y); });
   }
-  // the adjoint and its state saving handle the FP64 RK steppers and N <= 128 only
-  if (P->splitting || opts->stage_precision != RHEED_STAGES_FP64 || !P->xl_pairs.empty()) {
+  // the adjoint and its state saving: FP64, the RK steppers for N <= 128 and
+  // the splitting methods for N <= 64
+  if ((P->splitting && !P->large_pairs.empty()) || opts->stage_precision != RHEED_STAGES_FP64 ||
+      !P->xl_pairs.empty()) {
     P->fwd_ws = 0;
     P->bwd_ws = 0;
   }
@@ -673,8 +685,9 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
                           const void* y_bottom, const int* skip, bool final_only = false) {
   if (!P || !U_tables || !angles || !intensity || !pair_status) return fail(RHEED_E_INVALID, "forward: null argument");
   const bool f32 = P->opts.stage_precision == RHEED_STAGES_FP32;
-  if (workspace && (P->splitting || f32))
-    return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs an RK stepper with FP64 stages");
+  if (workspace && ((P->splitting && !P->large_pairs.empty()) || f32))
+    return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs FP64 stages, and with a "
+                                     "splitting stepper every structure to have N <= 64");
   if (workspace && !P->xl_pairs.empty())
     return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs every structure to have N <= 128");
   if (y_bottom && (!P->large_pairs.empty() || !P->xl_pairs.empty()))
@@ -930,8 +943,9 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
                             void* dL_dU, void* workspace, size_t ws_bytes, void* stream) {
   if (!P || !U_tables || !angles || !dL_dI || !dL_dU || !workspace)
     return fail(RHEED_E_INVALID, "backward: null argument");
-  if (P->splitting || P->opts.stage_precision != RHEED_STAGES_FP64)
-    return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs an RK stepper with FP64 stages");
+  if ((P->splitting && !P->large_pairs.empty()) || P->opts.stage_precision != RHEED_STAGES_FP64)
+    return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs FP64 stages, and with a splitting stepper "
+                                     "every structure to have N <= 64");
   if (!P->xl_pairs.empty())
     return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs every structure to have N <= 128");
   if (ws_bytes < P->fwd_ws + P->bwd_ws)
@@ -954,12 +968,14 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
   }
   a.ld = P->max_beams;
   a.convention = (int)P->opts.convention;
+  a.sp = P->sp;
+  const int bcode = P->splitting ? 2 : (int)P->opts.stepper;
   hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
   if (!P->small_pairs.empty()) {  // N <= 64: the 64-wide state layout
     a.pair_list = P->d_small_pairs;  // null when every pair is small
     a.n_pairs = (int)P->small_pairs.size();
-    e = launch_backward((int)P->opts.stepper, false, a, st);
+    e = launch_backward(bcode, false, a, st);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
   }
   if (!P->large_pairs.empty()) {  // 64 < N <= 128: the 128-wide layout
@@ -984,8 +1000,17 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
   g.stages = rk4 ? 4 : 7;
   g.nps = P->nodes_per_slice;
   const int* node = rk4 ? node4 : node6;
+  if (P->splitting) {
+    // the kicks kept per slice (the BAB method's first one carries the
+    // previous slice's last), each at its node of the slice; the BAB final
+    // kick is kick 0 of one more slice (node L nps)
+    g.stages = P->sp.form == 0 ? P->sp.kicks - 1 : P->sp.kicks;
+    g.last_extra = P->sp.form == 0 ? 1 : 0;
+    node = P->sp.node;
+  }
   for (int r = 0; r < g.stages; ++r) {
     const int res = node[r] % g.nps, di = node[r] / g.nps;  // node i nps + node[r] = (i + di) nps + res
+    if (g.n_contrib[res] >= 2) return fail(RHEED_E_UNSUPPORTED, "backward: more than two kicks at one node");
     const int t = g.n_contrib[res]++;
     g.contrib_di[res][t] = -di;
     g.contrib_r[res][t] = r;

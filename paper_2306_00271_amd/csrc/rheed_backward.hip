@@ -58,9 +58,10 @@ struct BGeo {
   static constexpr int cols = W / 8;
   static constexpr int box = W == NP ? MAXBOX : MAXBOXL;  // table row entries in LDS
   // node-table slots: with W = 64 the current slice's (nps + 1) and the next
-  // one's (nps); with W = 128 only the current slice's (LDS), so the next
+  // one's (nps) for the RK steppers, or a splitting method's nps + 1 <= 13
+  // kick positions; with W = 128 only the current slice's (LDS), so the next
   // slice's tables go in after the current one's last product
-  static constexpr int ring = W == NP ? 9 : 5;
+  static constexpr int ring = W == NP ? 13 : 5;
   static constexpr int pf = (4 * box + threads - 1) / threads;  // prefetch registers for nps <= 4 nodes
 };
 
@@ -74,6 +75,13 @@ struct BTab<0> {  // classical RK4, c = 0, 1/2, 1/2, 1
   static constexpr int node[4] = {0, 1, 1, 2};
   static constexpr double a[4][4] = {{0, 0, 0, 0}, {0.5, 0, 0, 0}, {0, 0.5, 0, 0}, {0, 0, 1, 0}};
   static constexpr double b[4] = {1.0 / 6, 1.0 / 3, 1.0 / 3, 1.0 / 6};
+};
+template <>
+struct BTab<2> {  // a splitting method: its kicks and drifts come with the launch (BwdArgs::sp)
+  static constexpr int stages = 1, nps = 1;
+  static constexpr int node[1] = {0};
+  static constexpr double a[1][1] = {{0}};
+  static constexpr double b[1] = {0};
 };
 template <>
 struct BTab<1> {  // Butcher's 6th order, 7 stages, c = 0, 1/3, 2/3, 1/3, 1/2, 1/2, 1
@@ -351,7 +359,27 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
       s.tb[nn % RING][e % box] = Us[(long long)nn * box + e % box];
     }
   };
+  // splitting methods: the nodes of slice i (positions 0 .. nps) in ring slots 0 .. nps
+  auto load_slice_nodes = [&](int i, int count) {
+    const int nps = a.sp.nps;
+    for (int e = tid; e < count * box; e += BT) {
+      const int q = e / box;
+      s.tb[q][e - q * box] = Us[(long long)(i * nps + q) * box + e - q * box];
+    }
+  };
+  const int NKS = STEPPER == 2 ? (a.sp.form == 0 ? a.sp.kicks - 1 : a.sp.kicks) : NS;  // kicks kept per slice
   if (role == 0) {
+    if constexpr (STEPPER == 2) {
+      if (a.sp.form == 0) {
+        // v of the BAB method's final kick (after the last slice): the c part of
+        // psi = Z_L x at the final state, which that kick does not change
+        double2 ac = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < CP; ++q) ac = cadd(ac, cmul(zL[j * W + CP * part + q], s.x[CP * part + q]));
+        ac = row_sum(ac);
+        if (part == 0) gb[(long long)L * NKS * 2 * W + j] = ac;
+      }
+    }
     // Segments of K = ck.every slices, from the top down.  (A) x moves down
     // through the segment's transformations, x <- T_m x for every slice m
     // whose decision byte is set; (B) psi_lo = Z_lo x_lo from the stored
@@ -391,6 +419,50 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
         }
         psic = row_sum(ac);
         psid = row_sum(ad);
+      }
+      if constexpr (STEPPER == 2) {
+        // psi through the segment's kicks and drifts; v_k = psi_c at kick k
+        const SplitSteps& sp = a.sp;
+        for (int i = lo; i < hi; ++i) {
+          if (i > lo && flags[i - 1]) {
+            const double2* R = reinterpret_cast<const double2*>(pws + a.ck.r_off + (long long)(i - 1) * MATB);
+            const double2* xi = xs + (i - lo) * W;
+            double2 ad = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int q = 0; q < CP; ++q) ad = cadd(ad, cmul(R[j * W + CP * part + q], xi[CP * part + q]));
+            psic = xi[j];
+            psid = row_sum(ad);
+          }
+          __syncthreads();  // the previous slice's products are done with the ring
+          load_slice_nodes(i, sp.nps + 1);
+          __syncthreads();
+          double2* gs = gb + (long long)i * NKS * 2 * W;
+          // kick k: v_k = psi_c, psi_d -= h w M(node) psi_c
+          auto kick_up = [&](int k, int node, double wgt) {
+            if (part == 0) {
+              s.vin[k & 1][j] = psic;
+              gs[k * 2 * W + j] = psic;
+            }
+            __syncthreads();
+            const double2 mv = matvec_row<false, W>(s.tb[node], s.vin[k & 1], ix, part, j, g2j);
+            psid = caxpy(-h * wgt, mv, psid);
+          };
+          if (sp.form == 0) {
+            kick_up(0, sp.node[0], i == 0 ? sp.b[0] : sp.b[0] + sp.b[sp.kicks - 1]);
+            for (int r = 0; r + 1 < sp.kicks; ++r) {
+              psic = caxpy(h * sp.a[r], psid, psic);
+              if (r + 2 < sp.kicks) kick_up(r + 1, sp.node[r + 1], sp.b[r + 1]);
+            }
+          } else {
+            psic = caxpy(h * sp.a[0], psid, psic);
+            for (int r = 0; r < sp.kicks; ++r) {
+              kick_up(r, sp.node[r], sp.b[r]);
+              psic = caxpy(h * sp.a[r + 1], psid, psic);
+            }
+          }
+        }
+        hi = lo;
+        continue;
       }
       __syncthreads();  // the previous segment's last products are done with the ring
       load_tables(lo);
@@ -456,6 +528,57 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
         }
       }
       hi = lo;
+    }
+  } else if constexpr (STEPPER == 2) {
+    // Down through every slice of a splitting method: the adjoint of a kick
+    // c' -= h w M c is y_c -= h w M^H y_d (its g = -h w y_d to the stage
+    // buffer), of a drift c += h a c' it is y_d += h a y_c; the projection
+    // y_c = -R^H y_d wherever a transformation followed the slice (R from its
+    // slot: a splitting method always keeps it).
+    const SplitSteps& sp = a.sp;
+    auto kick_down = [&](int k, double2* gs, int node, double wgt) {
+      const int buf = k & 1;
+      if (part == 0) {
+        s.vin[buf][j] = yd;
+        gs[k * 2 * W + W + j] = make_double2(-h * wgt * yd.x, -h * wgt * yd.y);
+      }
+      __syncthreads();
+      const double2 mv = matvec_row<true, W>(s.tb[node], s.vin[buf], ix, part, j, g2j);
+      yc = caxpy(-h * wgt, mv, yc);
+    };
+    if (sp.form == 0) {  // the final kick, at node L nps
+      load_slice_nodes(L, 1);
+      __syncthreads();
+      kick_down(0, gb + (long long)L * NKS * 2 * W, 0, sp.b[sp.kicks - 1]);
+    }
+    for (int i = L - 1; i >= 0; --i) {
+      if (flags[i]) {
+        const double2* R = reinterpret_cast<const double2*>(pws + a.ck.r_off + (long long)i * MATB);
+        __syncthreads();
+        if (part == 0) s.vin[0][j] = yd;
+        __syncthreads();
+        double2 t = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < CP; ++q) t = cadd(t, cmulc(R[(CP * part + q) * W + j], s.vin[0][CP * part + q]));
+        t = row_sum(t);
+        yc = make_double2(-t.x, -t.y);
+      }
+      __syncthreads();  // the previous slice's products are done with the ring and vin
+      load_slice_nodes(i, sp.nps + 1);
+      __syncthreads();
+      double2* gs = gb + (long long)i * NKS * 2 * W;
+      if (sp.form == 0) {
+        for (int r = sp.kicks - 2; r >= 0; --r) {
+          yd = caxpy(h * sp.a[r], yc, yd);
+          kick_down(r, gs, sp.node[r], r == 0 ? (i == 0 ? sp.b[0] : sp.b[0] + sp.b[sp.kicks - 1]) : sp.b[r]);
+        }
+      } else {
+        yd = caxpy(h * sp.a[sp.kicks], yc, yd);
+        for (int r = sp.kicks - 1; r >= 0; --r) {
+          kick_down(r, gs, sp.node[r], sp.b[r]);
+          yd = caxpy(h * sp.a[r], yc, yd);
+        }
+      }
     }
   } else {
     // Down through every slice: the projection y_c = -R^H y_d wherever a
@@ -550,7 +673,7 @@ __global__ __launch_bounds__(256) void grad_assemble_kernel(GradArgs a) {
   int ci[2], cr[2], nc = 0;
   for (int t = 0; t < a.n_contrib[res]; ++t) {
     const int ii = i0 + a.contrib_di[res][t];
-    if (ii >= 0 && ii < S.n_slices) {
+    if (ii >= 0 && ii < S.n_slices + a.last_extra) {
       ci[nc] = ii;
       cr[nc] = a.contrib_r[res][t];
       ++nc;
@@ -733,8 +856,10 @@ hipError_t launch_backward(int stepper, bool wide, const BwdArgs& a, hipStream_t
     const dim3 block(BGeo<NP>::threads);
     if (stepper == 0)
       hipLaunchKernelGGL((backward_kernel<0, NP>), grid, block, 0, stream, a);
-    else
+    else if (stepper == 1)
       hipLaunchKernelGGL((backward_kernel<1, NP>), grid, block, 0, stream, a);
+    else
+      hipLaunchKernelGGL((backward_kernel<2, NP>), grid, block, 0, stream, a);
   }
   return hipGetLastError();
 }

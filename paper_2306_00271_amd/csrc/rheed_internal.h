@@ -148,9 +148,12 @@ struct BwdArgs {
   int convention;
   int n_pairs;
   int pad;
+  SplitSteps sp;             // the splitting stepper's kicks and drifts (N <= 64)
 };
 
-// Stages that use node n = i * nps + res: (slice i + contrib_di, stage contrib_r).
+// Stages (RK) or kicks (splitting) that use node n = i * nps + res:
+// (slice i + contrib_di, stage or kick contrib_r); with last_extra the stage
+// buffer holds one more slice (the BAB method's final kick, node L nps).
 struct GradArgs {
   const StructDev* structs;
   const double2* gbuf;
@@ -160,9 +163,11 @@ struct GradArgs {
   double2* dU;               // all tables
   int stages;
   int nps;
-  int n_contrib[4];
-  int contrib_di[4][2];
-  int contrib_r[4][2];
+  int last_extra;
+  int pad;
+  int n_contrib[12];
+  int contrib_di[12][2];
+  int contrib_r[12][2];
 };
 
 // The bulk layer: from the final states a forward pass over one unit layer

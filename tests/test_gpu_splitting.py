@@ -2,7 +2,8 @@
 fourth-order triple jump of the Stormer-Verlet step and the sixth-order
 triple jump of that) on the GPU with the oracle's own splitting steps,
 through the C ABI: N <= 64 on the one-workgroup kernel, N > 64 (fourth-order
-BAB only) on the kernel that keeps the state in plan-owned memory."""
+BAB only) on the kernel that keeps the state in plan-owned memory; and their
+adjoint (N <= 64) against the oracle's tangent-linear derivatives."""
 import dataclasses
 
 import numpy as np
@@ -132,7 +133,7 @@ def test_sp4_uneven_batch_in_one_launch():
         assert np.all(res["intensity"][s * A:(s + 1) * A, N:] == 0.0)
 
 
-def test_sp4_refuses_split_layout_and_the_adjoint():
+def test_splitting_refuses_split_layout_and_large_n_adjoint():
     import torch
     from paper_2306_00271_amd import api
     from paper_2306_00271_amd._lib import RheedError
@@ -140,9 +141,82 @@ def test_sp4_refuses_split_layout_and_the_adjoint():
     for stepper in ("sp4", "sp6", "sp4a", "sp6a"):
         with pytest.raises(RheedError, match="one-workgroup"):
             api.plan_for(wl, stepper=stepper, layout="split")
-    plan = api.plan_for(wl, stepper="sp4")
+    big = small_2d(n_beams=69, n_slices=4, thickness=0.4, n_layers=2, n_angles=2)
+    plan = api.plan_for(big, stepper="sp4")
+    assert plan.info.fwd_workspace == 0
     dev = torch.device("cuda:0")
-    U = plan.potential(api.atoms_for(wl, dev))
+    U = plan.potential(api.atoms_for(big, dev))
     ws = torch.empty(1024, dtype=torch.uint8, device=dev)
-    with pytest.raises(RheedError, match="RK stepper"):
-        plan.forward(U, api.angles_for(wl, dev), workspace=ws)
+    with pytest.raises(RheedError, match="N <= 64"):
+        plan.forward(U, api.angles_for(big, dev), workspace=ws)
+
+
+def _grad(wl, stepper, target, every):
+    import torch
+    from paper_2306_00271_amd import api
+    dev = torch.device("cuda:0")
+    print(f"[adjoint-sp] {stepper} N={wl.structures[0].n_beams} K={every}", flush=True)
+    plan = api.plan_for(wl, stepper=stepper, checkpoint_every=every)
+    atoms = api.atoms_for(wl, dev)
+    U = plan.potential(atoms)
+    ang = api.angles_for(wl, dev)
+    ws = plan.workspace(dev)
+    out = plan.forward(U, ang, workspace=ws, want_nrhst=True)
+    tgt = torch.from_numpy(np.asarray(target, dtype=np.float64)).to(dev)
+    loss, dI = api.rfactor(out["intensity"], tgt)
+    dU = plan.backward(U, ang, dI, ws)
+    dA = plan.potential_backward(atoms, dU)
+    torch.cuda.synchronize()
+    res = {"loss": float(loss.item()), "dU": dU.cpu().numpy(), "datoms": dA.cpu().numpy(),
+           "status": out["status"].cpu().numpy(), "n_rhst": out["n_rhst"].cpu().numpy()}
+    del ws, plan
+    return res
+
+
+@pytest.mark.parametrize("every", [1, 7])
+@pytest.mark.parametrize("stepper", ["sp4", "sp6", "sp4a", "sp6a"])
+def test_splitting_table_gradient_matches_oracle_tangent(stepper, every):
+    """The splitting adjoint (kicks as Hermitian table products on the
+    adjoint vector, drifts as vector updates, the BAB method's merged end
+    kicks) against the oracle's tangent-linear derivative along random
+    table directions, over a slab with several transformations."""
+    wl = small_2d(n_beams=21, n_slices=30, thickness=3.0, n_layers=1, n_angles=3)
+    tgt = np.random.default_rng(3).uniform(0.0, 0.3, size=3)
+    res = _grad(wl, stepper, tgt, every)
+    assert (res["status"] == 0).all() and res["n_rhst"].min() >= 2
+    st = driver.StructureSetup(wl, wl.structures[0], TABLEAUX[stepper])
+    rng = np.random.default_rng(11)
+    for _ in range(2):
+        dt = rng.normal(size=st.table.shape) + 1j * rng.normal(size=st.table.shape)
+        loss, dl = driver.rfactor_directional_table(wl, 0, dt, tgt, stepper=stepper)
+        got = float(np.real(np.sum(np.conj(res["dU"]) * dt.ravel())))
+        print(f"[adjoint-sp] {stepper} K={every} table direction: gpu {got:.12e} oracle {dl:.12e}", flush=True)
+        assert res["loss"] == pytest.approx(loss, rel=1e-10)
+        assert got == pytest.approx(dl, rel=1e-9)
+
+
+@pytest.mark.parametrize("stepper,every", [("sp4", 1), ("sp6a", 20)])
+def test_splitting_atom_gradient_every_coordinate(stepper, every):
+    """Every coordinate of the 9 atoms of a small slab against the oracle's
+    tangent-linear derivative along that coordinate, entry by entry."""
+    from tests.gpu_util import assert_entrywise, oracle_atom_gradient
+    wl = small_2d(n_beams=29, n_slices=40, thickness=4.0, n_layers=1, n_angles=3)
+    tgt = np.random.default_rng(13).uniform(0.0, 0.3, size=3)
+    res = _grad(wl, stepper, tgt, every)
+    assert (res["status"] == 0).all()
+    n_atoms = wl.structures[0].atoms.shape[0]
+    coords = [(ia, c) for ia in range(n_atoms) for c in range(3)]
+    ref = oracle_atom_gradient(wl, tgt, coords, stepper=stepper)
+    got = np.array([res["datoms"][ia, c] for ia, c in coords])
+    assert_entrywise(got, ref, what=f"{stepper} K={every}, all {len(coords)} coordinates")
+
+
+@pytest.mark.parametrize("stepper", ["sp4", "sp6a"])
+def test_splitting_checkpoint_segments_match_every_slice_states(stepper):
+    wl = small_2d(n_beams=21, n_slices=50, thickness=5.0, n_layers=1, n_angles=3)
+    tgt = np.random.default_rng(6).uniform(0.0, 0.3, size=3)
+    ref = _grad(wl, stepper, tgt, 1)
+    got = _grad(wl, stepper, tgt, 20)
+    err = np.abs(got["dU"] - ref["dU"]).max() / np.abs(ref["dU"]).max()
+    print(f"[adjoint-sp] {stepper} K=20 vs K=1: {err:.3e}", flush=True)
+    np.testing.assert_allclose(got["dU"], ref["dU"], rtol=0.0, atol=1e-13 * np.abs(ref["dU"]).max())

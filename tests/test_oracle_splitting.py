@@ -96,3 +96,57 @@ def test_splitting_conserves_flux_exactly_without_absorption(comp):
         assert _flux(st, float(th)) == pytest.approx(1.0, abs=1e-12)
         worst_rk = max(worst_rk, abs(_flux(st4, float(th)) - 1.0))
     assert worst_rk > 1e-6
+
+
+@pytest.mark.parametrize("name", ["sp4", "sp4a", "sp6"])
+def test_splitting_tangent_matches_central_differences(name):
+    """The splitting methods' tangent (kicks and drifts differentiated,
+    through the right-hand-side transformations of a slab thick enough for
+    several) against central differences of the oracle's own forward along
+    a random complex direction of the potential table."""
+    from oracle import driver, rk, tangent
+    from oracle.tableaux import TABLEAUX
+    from synth import small_2d
+    wl = small_2d(n_beams=13, n_slices=40, thickness=4.0, n_layers=1, n_angles=2)
+    tab = TABLEAUX[name]
+    st = driver.StructureSetup(wl, wl.structures[0], tab)
+    rng = np.random.default_rng(19)
+    dt = rng.normal(size=st.table.shape) + 1j * rng.normal(size=st.table.shape)
+    th = float(wl.theta0[1])
+    gam, _ = st.angle(th)
+
+    def dU(i, r):
+        return dt[tab.node_index(i, r)][st.cidx]
+    rho, drho = tangent.solve_ode_str_tangent(st.mfun(gam), dU, gam, st.h, st.s.n_slices, tab)
+    r0, info = rk.solve_ode_str(st.mfun(gam), gam, st.h, st.s.n_slices, tab)
+    assert info["n_rhst"] >= 3
+    assert np.allclose(rho, r0, rtol=0, atol=1e-14 * np.abs(r0).max())
+    eps = 1e-6
+    rp = rk.solve_ode_str(st.mfun(gam, table=st.table + eps * dt), gam, st.h, st.s.n_slices, tab)[0]
+    rm = rk.solve_ode_str(st.mfun(gam, table=st.table - eps * dt), gam, st.h, st.s.n_slices, tab)[0]
+    fd = (rp - rm) / (2 * eps)
+    assert np.abs(drho - fd).max() <= 1e-6 * np.abs(fd).max()
+
+
+def test_splitting_atom_tangent_matches_central_differences():
+    """The R-factor's derivative along atom displacements with the
+    fourth-order BAB method against central differences."""
+    import copy
+    from oracle import driver
+    from synth import small_2d
+    wl = small_2d(n_beams=9, n_slices=30, thickness=4.0, n_layers=1, n_angles=2)
+    s = wl.structures[0]
+    d = np.zeros_like(s.atoms)
+    d[:4] = np.random.default_rng(5).normal(size=(4, 3))
+    target = np.array([0.01, 0.02])
+    loss, dl = driver.rfactor_directional(wl, 0, d, target, stepper="sp4")
+    eps = 1e-5
+
+    def loss_at(shift):
+        w2 = copy.deepcopy(wl)
+        w2.structures[0].atoms = s.atoms + shift * d
+        eta = driver.rocking_curve(w2, stepper="sp4")[0][:, 0]
+        return driver.rfactor(eta, target)[0]
+    fd = (loss_at(eps) - loss_at(-eps)) / (2 * eps)
+    assert loss == pytest.approx(loss_at(0.0), rel=1e-12)
+    assert dl == pytest.approx(fd, rel=2e-6)
