@@ -580,7 +580,8 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
         xl_group_sync(cnt, G * ++nsync, failw);
         if (g != 0) {
           if (tid < NX) {
-            s.pcrec[tid] = pivg[tid];
+            // masked into range: after a failed barrier the list may be stale
+            s.pcrec[tid] = pivg[tid] & (NX - 1);
             s.pos[tid] = tid;
           }
           __syncthreads();
