@@ -108,12 +108,15 @@ __device__ __noinline__ void xl_slice(double2* __restrict__ cg, double2* __restr
   for (int cb = cb0; cb < ncb; cb += cbs) {
     const int col = XCB * cb + (lane & 15);
     double cnr[2][4], cni[2][4], dnr[2][4], dni[2][4];
+    double2 c0[2][4], d0[2][4];  // the block's c and c' at the slice start, for every stage input
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = 32 * w + 16 * t + 4 * v + (lane >> 4);
         const double2 c = gld(&cg[row * NX + col]), d = gld(&dg[row * NX + col]);
+        c0[t][v] = c;
+        d0[t][v] = d;
         cnr[t][v] = c.x + h * d.x;
         cni[t][v] = c.y + h * d.y;
         dnr[t][v] = d.x;
@@ -140,7 +143,7 @@ __device__ __noinline__ void xl_slice(double2* __restrict__ cg, double2* __restr
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = 32 * w + 16 * t + 4 * v + (lane >> 4);
-          const double2 c = gld(&cg[row * NX + col]), d = gld(&dg[row * NX + col]);
+          const double2 c = c0[t][v], d = d0[t][v];
           double xr = c.x + hc * d.x, xi = c.y + hc * d.y;
 #pragma unroll
           for (int m = 0; m < 6; ++m) {
