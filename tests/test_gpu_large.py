@@ -122,7 +122,7 @@ def test_uniform_grid_is_flagged_at_large_n():
 def test_adjoint_workspace_of_large_plans():
     """Plans with N > 64 keep states for the adjoint with the RK steppers
     (their workspace is sized for states padded to 128 beams and refused
-    when short); the splitting stepper keeps none."""
+    when short); the splitting stepper keeps none above 64 beams."""
     import torch
     from paper_2306_00271_amd import api
     from paper_2306_00271_amd._lib import RheedError
@@ -141,7 +141,7 @@ def test_adjoint_workspace_of_large_plans():
         plan.backward(U, api.angles_for(wl, dev), dI, ws)
     sp = api.plan_for(wl, stepper="sp4")
     assert sp.info.fwd_workspace == 0
-    with pytest.raises(RheedError, match="RK stepper"):
+    with pytest.raises(RheedError, match="N <= 64"):
         sp.forward(sp.potential(api.atoms_for(wl, dev)), api.angles_for(wl, dev), workspace=ws)
 
 
@@ -342,3 +342,4 @@ def test_one_launch_queue_matches_two_launches():
         e = eacc(res_q["intensity"][s * 150 + idx, :N], ref)
         _report(f"queue, 300 pairs, structure {s} N={N} (sampled)", e)
         assert e <= TOL
+
