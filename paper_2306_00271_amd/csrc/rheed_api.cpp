@@ -50,6 +50,7 @@ struct rheed_plan_s {
   std::vector<int> bin_ptr, bin_jk;
   CkptLayout ck{};   // states kept for the adjoint, pairs with N <= 64 (matrices padded to 64)
   CkptLayout ckl{};  // the same for pairs with 64 < N <= 128 (padded to 128); same pair stride
+  CkptLayout ckx{};  // and for pairs with 128 < N <= 256 (padded to 256)
   size_t fwd_ws = 0, bwd_ws = 0;
   StructDev* d_structs = nullptr;
   int* d_beams = nullptr;
@@ -287,12 +288,10 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     // count of the structure's kernels (64 or 128)
     {
       const int W = 2 * d.kd + 1;
-      const int Wp = st.n_beams <= NP ? NP : NL;
+      const int Wp = st.n_beams <= NP ? NP : st.n_beams <= NL ? NL : NX;
       std::vector<std::vector<int>> lists(d.box);
-      // (no adjoint above 128 beams, so no bins there)
-      const int nb = st.n_beams <= NL ? st.n_beams : 0;
-      for (int j = 0; j < nb; ++j)
-        for (int k = 0; k < nb; ++k) {
+      for (int j = 0; j < st.n_beams; ++j)
+        for (int k = 0; k < st.n_beams; ++k) {
           const int dh = st.beam_hk[2 * j] - st.beam_hk[2 * k], dk = st.beam_hk[2 * j + 1] - st.beam_hk[2 * k + 1];
           lists[(dh + d.hd) * W + (dk + d.kd)].push_back(j * Wp + k);
         }
@@ -383,13 +382,19 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     c.pair_stride = ((c.flags_off + max_l + 255) / 256) * 256;
     return c;
   };
-  const bool wide = !P->large_pairs.empty();
+  const bool wide = !P->large_pairs.empty(), xwide = !P->xl_pairs.empty();
   P->ck = layout(NP, false);
+  long long stride = P->ck.pair_stride;
   if (wide) {
     P->ckl = layout(NL, true);
-    P->ck.pair_stride = P->ckl.pair_stride = std::max(P->ck.pair_stride, P->ckl.pair_stride);
+    stride = std::max(stride, P->ckl.pair_stride);
   }
-  const int wmax = wide ? NL : NP;
+  if (xwide) {
+    P->ckx = layout(NX, true);
+    stride = std::max(stride, P->ckx.pair_stride);
+  }
+  P->ck.pair_stride = P->ckl.pair_stride = P->ckx.pair_stride = stride;
+  const int wmax = xwide ? NX : wide ? NL : NP;
   P->fwd_ws = (size_t)P->ck.pair_stride * P->n_pairs;
   // adjoint stage buffer: (v_r, g_r) of every stage of every slice; for a
   // splitting method of every kick it keeps per slice (the BAB method's final
@@ -429,10 +434,9 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     for (int p = 0; p < P->n_pairs; ++p) P->queue_order[p] = p;
     std::stable_sort(P->queue_order.begin(), P->queue_order.end(), [&](int x, int y) { return qcost(x) > qcost(y); });
   }
-  // the adjoint and its state saving: FP64, the RK steppers for N <= 128 and
+  // the adjoint and its state saving: FP64, the RK steppers for every N and
   // the splitting methods for N <= 64
-  if ((P->splitting && !P->large_pairs.empty()) || opts->stage_precision != RHEED_STAGES_FP64 ||
-      !P->xl_pairs.empty()) {
+  if ((P->splitting && !P->large_pairs.empty()) || opts->stage_precision != RHEED_STAGES_FP64) {
     P->fwd_ws = 0;
     P->bwd_ws = 0;
   }
@@ -498,7 +502,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       ((n_large > 0 || !P->xl_pairs.empty()) && n_small > 0 &&
        (e = hipMalloc(&P->d_small_pairs, sizeof(int) * n_small)) != hipSuccess) ||
       (!P->xl_pairs.empty() && (e = hipMalloc(&P->d_xl_pairs, sizeof(int) * P->xl_pairs.size())) != hipSuccess) ||
-      (!P->xl_pairs.empty() && P->xl_group == 1 &&
+      (!P->xl_pairs.empty() &&
        (e = hipMalloc(&P->d_xscratch, (size_t)XSLOT_BYTES * P->xl_slots)) != hipSuccess) ||
       (P->xl_group > 1 &&
        (e = hipMalloc(&P->d_xg_pair, (size_t)XG_PAIR_BYTES * P->xl_pairs.size())) != hipSuccess) ||
@@ -688,8 +692,6 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
   if (workspace && ((P->splitting && !P->large_pairs.empty()) || f32))
     return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs FP64 stages, and with a "
                                      "splitting stepper every structure to have N <= 64");
-  if (workspace && !P->xl_pairs.empty())
-    return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs every structure to have N <= 128");
   if (y_bottom && (!P->large_pairs.empty() || !P->xl_pairs.empty()))
     return fail(RHEED_E_UNSUPPORTED, "forward: the bulk start needs every structure to have N <= 64");
   if (y_bottom && (P->splitting || f32))
@@ -765,11 +767,11 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
     xa.f = a;
     xa.f.pair_list = P->d_xl_pairs;
     xa.f.n_pairs = (int)P->xl_pairs.size();
-    xa.f.ws = nullptr;
+    xa.f.ck = P->ckx;
     xa.f.xch = nullptr;
     xa.scratch = P->d_xscratch;
     xa.n_slots = P->xl_slots;
-    if (P->xl_group > 1) {
+    if (P->xl_group > 1 && !workspace) {
       XlGroup xg{};
       xg.pair_mem = P->d_xg_pair;
       xg.wg_mem = P->d_xg_wg;
@@ -946,8 +948,6 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
   if ((P->splitting && !P->large_pairs.empty()) || P->opts.stage_precision != RHEED_STAGES_FP64)
     return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs FP64 stages, and with a splitting stepper "
                                      "every structure to have N <= 64");
-  if (!P->xl_pairs.empty())
-    return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs every structure to have N <= 128");
   if (ws_bytes < P->fwd_ws + P->bwd_ws)
     return fail(RHEED_E_INVALID, "backward: workspace of " + std::to_string(ws_bytes) + " bytes < " +
                                      std::to_string(P->fwd_ws + P->bwd_ws));
@@ -964,7 +964,7 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
   a.g_pair_stride = P->g_pair_stride;
   if (P->ck.every > 1) {
     a.xs = reinterpret_cast<double2*>(static_cast<char*>(workspace) + P->fwd_ws + P->xs_off);
-    a.xs_stride = (long long)P->ck.every * (P->large_pairs.empty() ? NP : NL);
+    a.xs_stride = (long long)P->ck.every * (!P->xl_pairs.empty() ? NX : !P->large_pairs.empty() ? NL : NP);
   }
   a.ld = P->max_beams;
   a.convention = (int)P->opts.convention;
@@ -975,7 +975,7 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
   if (!P->small_pairs.empty()) {  // N <= 64: the 64-wide state layout
     a.pair_list = P->d_small_pairs;  // null when every pair is small
     a.n_pairs = (int)P->small_pairs.size();
-    e = launch_backward(bcode, false, a, st);
+    e = launch_backward(bcode, NP, a, st);
     if (e != hipSuccess) return hip_fail(e, "backward launch");
   }
   if (!P->large_pairs.empty()) {  // 64 < N <= 128: the 128-wide layout
@@ -983,8 +983,16 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
     b.ck = P->ckl;
     b.pair_list = P->d_large_plain;
     b.n_pairs = (int)P->large_pairs.size();
-    e = launch_backward((int)P->opts.stepper, true, b, st);
+    e = launch_backward((int)P->opts.stepper, NL, b, st);
     if (e != hipSuccess) return hip_fail(e, "backward launch (N > 64)");
+  }
+  if (!P->xl_pairs.empty()) {  // 128 < N <= 256: the 256-wide layout
+    BwdArgs b = a;
+    b.ck = P->ckx;
+    b.pair_list = P->d_xl_pairs;
+    b.n_pairs = (int)P->xl_pairs.size();
+    e = launch_backward((int)P->opts.stepper, NX, b, st);
+    if (e != hipSuccess) return hip_fail(e, "backward launch (N > 128)");
   }
   // stages that use each node of a slice: node offsets of the stages in
   // {0, 1/2} (RK4) or {0, 1/3, 1/2, 2/3} (RK6); offset nps is the next slice's 0
@@ -1015,7 +1023,8 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
     g.contrib_di[res][t] = -di;
     g.contrib_r[res][t] = r;
   }
-  e = launch_grad_assemble(g, P->n_struct, P->max_nodes, !P->small_pairs.empty(), !P->large_pairs.empty(), st);
+  e = launch_grad_assemble(g, P->n_struct, P->max_nodes, !P->small_pairs.empty(), !P->large_pairs.empty(),
+                           !P->xl_pairs.empty(), st);
   return e == hipSuccess ? RHEED_OK : hip_fail(e, "gradient assembly launch");
 }
 

@@ -48,15 +48,19 @@
 namespace rheed {
 
 // Launch geometry of the adjoint for the state width W of its pairs (64 for
-// N <= 64, 128 for 64 < N <= 128): W / 8 waves, and thread t works on row
-// j = t >> 3 and on W / 8 of its columns (the eight threads of a row reduce
-// by butterflies and all hold the row's result).
+// N <= 64, 128 for 64 < N <= 128, 256 above): tpr threads per row (8, or 4
+// at W = 256), thread t works on row j = t / tpr and on W / tpr of its
+// columns (the threads of a row reduce by butterflies and all hold the
+// row's result).  At W = 256 the gather indices of the table come from
+// per-beam offsets in LDS instead of registers.
 template <int W>
 struct BGeo {
-  static constexpr int waves = W / 8;
-  static constexpr int threads = waves * 64;
-  static constexpr int cols = W / 8;
-  static constexpr int box = W == NP ? MAXBOX : MAXBOXL;  // table row entries in LDS
+  static constexpr int tpr = W == NX ? 4 : 8;
+  static constexpr int threads = W * tpr;
+  static constexpr int waves = threads / 64;
+  static constexpr int cols = W / tpr;
+  static constexpr bool idx_regs = W != NX;
+  static constexpr int box = W == NP ? MAXBOX : W == NL ? MAXBOXL : MAXBOXX;  // table row entries in LDS
   // node-table slots: with W = 64 the current slice's (nps + 1) and the next
   // one's (nps) for the RK steppers, or a splitting method's nps + 1 <= 13
   // kick positions; with W = 128 only the current slice's (LDS), so the next
@@ -108,6 +112,8 @@ struct BLds {
   int gj_piv[NP];
   double g2s[W];
   int bhk[W][2];
+  int sbase[W == NX ? W : 1];    // W = 256: (h_j + hd)(2 kd + 1) + k_j + kd and h_j (2 kd + 1) + k_j of beam j
+  int soff[W == NX ? W : 1];
   int flag_singular;
 };
 
@@ -133,16 +139,19 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// Sum over the eight threads of a row (lanes 8r .. 8r+7): pairs, then quads
-// (quad_perm), then the two quads (row_half_mirror); every lane of the eight
-// ends with the same sum.
+// Sum over the TPR threads of a row (8: lanes 8r .. 8r+7, 4: lanes 4r ..
+// 4r+3): pairs, then quads (quad_perm), then for eight the two quads
+// (row_half_mirror); every lane of the row ends with the same sum.
+template <int TPR = 8>
 __device__ __forceinline__ double2 row_sum(double2 v) {
   v.x += dpp_f64<0xB1>(v.x);
   v.y += dpp_f64<0xB1>(v.y);
   v.x += dpp_f64<0x4E>(v.x);
   v.y += dpp_f64<0x4E>(v.y);
-  v.x += dpp_f64<0x141>(v.x);
-  v.y += dpp_f64<0x141>(v.y);
+  if constexpr (TPR == 8) {
+    v.x += dpp_f64<0x141>(v.x);
+    v.y += dpp_f64<0x141>(v.y);
+  }
   return v;
 }
 
@@ -150,18 +159,28 @@ __device__ __forceinline__ double2 row_sum(double2 v) {
 // ix[q] is the table entry of U_{j,k} (or U_{k,j}) for
 // k = C part + ((q + part) mod C), C = W / 8 columns per thread, or `box`
 // (a zero entry) outside the n x n block.
-template <bool HERM, int W>
+// With W = 256 (IX = false) the entry is formed per column from the offsets
+// in LDS: U_{j,k} at sbase_j - soff_k, U_{k,j} at sbase_k - soff_j.
+template <bool HERM, int W, bool IX = BGeo<W>::idx_regs>
 __device__ __forceinline__ double2 matvec_row(const double2* __restrict__ tslot, const double2* __restrict__ v,
-                                              const int (&ix)[W / 8], int part, int j, double g2j) {
-  constexpr int C = W / 8;
+                                              const int (&ix)[IX ? BGeo<W>::cols : 1], int part, int j, double g2j,
+                                              const int* sbase = nullptr, const int* soff = nullptr, int n = 0,
+                                              int box = 0) {
+  constexpr int C = BGeo<W>::cols;
   double2 a0 = make_double2(0.0, 0.0), a1 = make_double2(0.0, 0.0);
-#pragma unroll
+#pragma unroll 4
   for (int h = 0; h < C; h += 4) {  // four products' operands in flight at a time
     double2 u[4], vk[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      u[q] = tslot[ix[h + q]];
-      vk[q] = v[C * part + ((h + q + part) & (C - 1))];
+      const int k = C * part + ((h + q + part) & (C - 1));
+      if constexpr (IX) {
+        u[q] = tslot[ix[h + q]];
+      } else {
+        const bool in = j < n && k < n;
+        u[q] = tslot[in ? (HERM ? sbase[k] - soff[j] : sbase[j] - soff[k]) : box];
+      }
+      vk[q] = v[k];
     }
 #pragma unroll
     for (int q = 0; q < 4; q += 2) {
@@ -170,7 +189,7 @@ __device__ __forceinline__ double2 matvec_row(const double2* __restrict__ tslot,
     }
   }
   const double2 vj = v[j];
-  const double2 acc = row_sum(cadd(a0, a1));
+  const double2 acc = row_sum<BGeo<W>::tpr>(cadd(a0, a1));
   return make_double2(acc.x + g2j * vj.x, acc.y + g2j * vj.y);
 }
 
@@ -182,13 +201,14 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
   using G = BGeo<W>;
   constexpr int NS = T::stages;
   constexpr int NPS = T::nps;
-  constexpr int BW = G::waves, BT = G::threads, CP = G::cols, RING = G::ring, PF = G::pf;
+  constexpr int BW = G::waves, BT = G::threads, CP = G::cols, RING = G::ring, PF = G::pf, TPR = G::tpr;
+  constexpr bool IXR = G::idx_regs;
   // the next slice's tables overwrite slots the current slice still reads
   constexpr bool tight = RING < 2 * NPS + 1;
   __shared__ BLds<W> s;
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6;
-  const int j = tid >> 3, part = tid & 7;
+  const int j = tid / TPR, part = tid % TPR;
   // two workgroups per pair: role 0 carries x down and psi up and writes the
   // stage inputs v_r, role 1 walks the adjoint stages down and writes g_r;
   // the two need nothing from each other
@@ -228,10 +248,10 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
   // k = CP part + ((q + part) mod CP): the eight threads of a row visit their
   // columns in rotated order, so that their reads of the input vector fall in
   // different LDS bank groups
-  int ix[CP];
-  {
+  int ix[IXR ? CP : 1];
+  if constexpr (IXR) {
     const int Wd = 2 * S.kd + 1;
-#pragma unroll
+#pragma unroll 8
     for (int q = 0; q < CP; ++q) {
       const int k = CP * part + ((q + part) & (CP - 1));
       const bool in = j < N && k < N;
@@ -239,9 +259,25 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
       const int bk = (s.bhk[k][0] + S.hd) * Wd + s.bhk[k][1] + S.kd, ok = s.bhk[k][0] * Wd + s.bhk[k][1];
       ix[q] = in ? (role == 0 ? bj - ok : bk - oj) : box;
     }
+  } else {
+    ix[0] = 0;
+    if (tid < W) {
+      const int Wd = 2 * S.kd + 1;
+      s.sbase[tid] = (s.bhk[tid][0] + S.hd) * Wd + s.bhk[tid][1] + S.kd;
+      s.soff[tid] = s.bhk[tid][0] * Wd + s.bhk[tid][1];
+    }
   }
   __syncthreads();
   const double g2j = s.g2s[j];
+  // the product of a stage: (M v)_j (role 0) or (M^H v)_j (role 1) with the table in tslot
+  auto mv_f = [&](const double2* tslot, const double2* v) {
+    if constexpr (IXR) return matvec_row<false, W>(tslot, v, ix, part, j, g2j);
+    else return matvec_row<false, W>(tslot, v, ix, part, j, g2j, s.sbase, s.soff, N, box);
+  };
+  auto mv_h = [&](const double2* tslot, const double2* v) {
+    if constexpr (IXR) return matvec_row<true, W>(tslot, v, ix, part, j, g2j);
+    else return matvec_row<true, W>(tslot, v, ix, part, j, g2j, s.sbase, s.soff, N, box);
+  };
 
   // ---- final step: x = B^{-1} e_1, rho = A x
   const double2* zL = reinterpret_cast<const double2*>(pws + (long long)(a.ck.max_ckpt - 1) * a.ck.state_bytes);
@@ -280,14 +316,14 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
     {
       const double gr = g2j >= 0.0 ? sqrt(g2j) : 0.0, gi = g2j >= 0.0 ? 0.0 : -sqrt(-g2j);
       double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
+#pragma unroll 8
       for (int q = 0; q < CP; ++q) {
         const int k = CP * part + q;
         const double2 qv = zL[j * W + k], pv = zL[W * W + j * W + k];
         const double2 av = make_double2(gr * qv.x - gi * qv.y - pv.y, gr * qv.y + gi * qv.x + pv.x);
         acc = cadd(acc, cmul(av, s.x[k]));
       }
-      rho = row_sum(acc);
+      rho = row_sum<TPR>(acc);
     }
     // rho_bar
     double2 rb = make_double2(0.0, 0.0);
@@ -304,7 +340,7 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
     {
       const int k = j;
       double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
+#pragma unroll 8
       for (int q = 0; q < CP; ++q) {
         const int jj = CP * part + q;
         const double g2v = s.g2s[jj];
@@ -313,7 +349,7 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
         const double2 av = make_double2(gr * qv.x - gi * qv.y - pv.y, gr * qv.y + gi * qv.x + pv.x);
         acc = cadd(acc, cmulc(av, s.vin[0][jj]));
       }
-      xbar = row_sum(acc);
+      xbar = row_sum<TPR>(acc);
     }
     if (part == 0) s.vin[1][j] = xbar;
     __syncthreads();
@@ -333,12 +369,12 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
       for (int q = 0; q < BW; ++q) wv = cadd(wv, s.red[q][j]);
     } else {
       double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
+#pragma unroll 8
       for (int q = 0; q < CP; ++q) {
         const int jj = CP * part + q;
         acc = cadd(acc, cmulc(Binv[(long long)jj * W + j], s.vin[1][jj]));
       }
-      wv = row_sum(acc);
+      wv = row_sum<TPR>(acc);
     }
     yc = make_double2(0.0, 0.0);
     yd = make_double2(0.0, 0.0);
@@ -374,9 +410,9 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
         // v of the BAB method's final kick (after the last slice): the c part of
         // psi = Z_L x at the final state, which that kick does not change
         double2 ac = make_double2(0.0, 0.0);
-#pragma unroll
+#pragma unroll 8
         for (int q = 0; q < CP; ++q) ac = cadd(ac, cmul(zL[j * W + CP * part + q], s.x[CP * part + q]));
-        ac = row_sum(ac);
+        ac = row_sum<TPR>(ac);
         if (part == 0) gb[(long long)L * NKS * 2 * W + j] = ac;
       }
     }
@@ -396,9 +432,9 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
           if (K > 1 && m + 1 < hi && tid < W) xs[(m + 1 - lo) * W + tid] = s.x[tid];
           const double2* Tm = reinterpret_cast<const double2*>(pws + a.ck.q_off + (long long)m * MATB);
           double2 xn = make_double2(0.0, 0.0);
-#pragma unroll
+#pragma unroll 8
           for (int q = 0; q < CP; ++q) xn = cadd(xn, cmul(Tm[j * W + CP * part + q], s.x[CP * part + q]));
-          xn = row_sum(xn);
+          xn = row_sum<TPR>(xn);
           __syncthreads();
           if (part == 0) s.x[j] = xn;
           __syncthreads();
@@ -411,14 +447,14 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
       {
         const double2* z = reinterpret_cast<const double2*>(pws + (long long)(lo / K) * a.ck.state_bytes);
         double2 ac = make_double2(0.0, 0.0), ad = make_double2(0.0, 0.0);
-#pragma unroll
+#pragma unroll 8
         for (int q = 0; q < CP; ++q) {
           const double2 xk = s.x[CP * part + q];
           ac = cadd(ac, cmul(z[j * W + CP * part + q], xk));
           ad = cadd(ad, cmul(z[W * W + j * W + CP * part + q], xk));
         }
-        psic = row_sum(ac);
-        psid = row_sum(ad);
+        psic = row_sum<TPR>(ac);
+        psid = row_sum<TPR>(ad);
       }
       if constexpr (STEPPER == 2) {
         // psi through the segment's kicks and drifts; v_k = psi_c at kick k
@@ -428,10 +464,10 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
             const double2* R = reinterpret_cast<const double2*>(pws + a.ck.r_off + (long long)(i - 1) * MATB);
             const double2* xi = xs + (i - lo) * W;
             double2 ad = make_double2(0.0, 0.0);
-#pragma unroll
+#pragma unroll 8
             for (int q = 0; q < CP; ++q) ad = cadd(ad, cmul(R[j * W + CP * part + q], xi[CP * part + q]));
             psic = xi[j];
-            psid = row_sum(ad);
+            psid = row_sum<TPR>(ad);
           }
           __syncthreads();  // the previous slice's products are done with the ring
           load_slice_nodes(i, sp.nps + 1);
@@ -444,7 +480,7 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
               gs[k * 2 * W + j] = psic;
             }
             __syncthreads();
-            const double2 mv = matvec_row<false, W>(s.tb[node], s.vin[k & 1], ix, part, j, g2j);
+            const double2 mv = mv_f(s.tb[node], s.vin[k & 1]);
             psid = caxpy(-h * wgt, mv, psid);
           };
           if (sp.form == 0) {
@@ -473,10 +509,10 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
           const double2* R = reinterpret_cast<const double2*>(pws + a.ck.r_off + (long long)(i - 1) * MATB);
           const double2* xi = xs + (i - lo) * W;
           double2 ad = make_double2(0.0, 0.0);
-#pragma unroll
+#pragma unroll 8
           for (int q = 0; q < CP; ++q) ad = cadd(ad, cmul(R[j * W + CP * part + q], xi[CP * part + q]));
           psic = xi[j];
-          psid = row_sum(ad);
+          psid = row_sum<TPR>(ad);
         }
         double2 pf[PF];  // the next slice's new nodes, loaded during this one
         if (i + 1 < hi) {
@@ -505,7 +541,7 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
             gs[r * 2 * W + j] = yr;  // v_r
           }
           __syncthreads();
-          const double2 mv = matvec_row<false, W>(s.tb[(nb + T::node[r]) % RING], s.vin[r & 1], ix, part, j, g2j);
+          const double2 mv = mv_f(s.tb[(nb + T::node[r]) % RING], s.vin[r & 1]);
           Kd[r] = make_double2(-mv.x, -mv.y);
         }
         if (i + 1 < hi) {
@@ -543,7 +579,7 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
         gs[k * 2 * W + W + j] = make_double2(-h * wgt * yd.x, -h * wgt * yd.y);
       }
       __syncthreads();
-      const double2 mv = matvec_row<true, W>(s.tb[node], s.vin[buf], ix, part, j, g2j);
+      const double2 mv = mv_h(s.tb[node], s.vin[buf]);
       yc = caxpy(-h * wgt, mv, yc);
     };
     if (sp.form == 0) {  // the final kick, at node L nps
@@ -558,9 +594,9 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
         if (part == 0) s.vin[0][j] = yd;
         __syncthreads();
         double2 t = make_double2(0.0, 0.0);
-#pragma unroll
+#pragma unroll 8
         for (int q = 0; q < CP; ++q) t = cadd(t, cmulc(R[(CP * part + q) * W + j], s.vin[0][CP * part + q]));
-        t = row_sum(t);
+        t = row_sum<TPR>(t);
         yc = make_double2(-t.x, -t.y);
       }
       __syncthreads();  // the previous slice's products are done with the ring and vin
@@ -605,9 +641,9 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
         if (part == 0) s.vin[0][j] = yd;
         __syncthreads();
         double2 t = make_double2(0.0, 0.0);
-#pragma unroll
+#pragma unroll 8
         for (int q = 0; q < CP; ++q) t = cadd(t, cmulc(R[(CP * part + q) * W + j], s.vin[0][CP * part + q]));
-        t = row_sum(t);
+        t = row_sum<TPR>(t);
         yc = make_double2(-t.x, -t.y);
         __syncthreads();
       }
@@ -631,7 +667,7 @@ __global__ __launch_bounds__(BGeo<W>::threads, 1) void backward_kernel(BwdArgs a
           gs[r * 2 * W + W + j] = make_double2(-kd.x, -kd.y);  // g_r = -K_bar^(c')
         }
         __syncthreads();
-        const double2 mv = matvec_row<true, W>(s.tb[(nb + T::node[r]) % RING], s.vin[buf], ix, part, j, g2j);
+        const double2 mv = mv_h(s.tb[(nb + T::node[r]) % RING], s.vin[buf]);
         Ybc[r] = make_double2(-mv.x, -mv.y);  // Y_bar^(c) = -M^H K_bar^(c')
       }
 #pragma unroll
@@ -756,7 +792,7 @@ __global__ __launch_bounds__(512) void grad_assemble_wide_kernel(GradArgs a) {
   __shared__ GLds sm;
   const StructDev S = a.structs[blockIdx.y];
   const int n = blockIdx.x;
-  if (S.n_beams <= NP || n >= S.n_nodes) return;
+  if (S.n_beams <= NP || S.n_beams > NL || n >= S.n_nodes) return;
   const int tid = threadIdx.x;
   const int res = n % a.nps;
   const int i0 = n / a.nps;
@@ -843,10 +879,119 @@ __global__ __launch_bounds__(512) void grad_assemble_wide_kernel(GradArgs a) {
   }
 }
 
-hipError_t launch_backward(int stepper, bool wide, const BwdArgs& a, hipStream_t stream) {
+// The same for structures with 128 < N <= 256 (stage buffer and bins of
+// width NX): the 256 x 256 sum is formed in eight blocks of 128 rows x 64
+// columns (one pass over the node's stage entries each; wave w owns rows
+// 16 w .. +15 of the block) and each block is binned through LDS before the
+// next, every table entry summing the blocks in order and, in each, its
+// (j, k) in bin order.
+__global__ __launch_bounds__(512) void grad_assemble_xl_kernel(GradArgs a) {
+  union GLds {
+    struct {
+      double2 vs[16][64], gsh[16][128];
+    } in;
+    double2 C[128][65];
+  };
+  __shared__ GLds sm;
+  const StructDev S = a.structs[blockIdx.y];
+  const int n = blockIdx.x;
+  if (S.n_beams <= NL || n >= S.n_nodes) return;
+  const int tid = threadIdx.x;
+  const int res = n % a.nps;
+  const int i0 = n / a.nps;
+  int ci[2], cr[2], nc = 0;
+  for (int t = 0; t < a.n_contrib[res]; ++t) {
+    const int ii = i0 + a.contrib_di[res][t];
+    if (ii >= 0 && ii < S.n_slices + a.last_extra) {
+      ci[nc] = ii;
+      cr[nc] = a.contrib_r[res][t];
+      ++nc;
+    }
+  }
+  const int lane = tid & 63, w = tid >> 6;
+  typedef double g4 __attribute__((ext_vector_type(4)));
+  const int* bp = a.bin_ptr + S.bin_ptr_off;
+  const int* bj = a.bin_jk + S.bin_jk_off;
+  constexpr int DPT = (MAXBOXX + 511) / 512;  // table entries per thread
+  double2 acc[DPT];
+#pragma unroll
+  for (int u = 0; u < DPT; ++u) acc[u] = make_double2(0.0, 0.0);
+  const int total = S.n_angles * nc;
+#pragma unroll 1
+  for (int pass = 0; pass < 8; ++pass) {
+    const int rh = pass >> 2, cq = pass & 3;  // rows 128 rh .., columns 64 cq ..
+    g4 p1[4], p2[4], p3[4];
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) p1[jt] = p2[jt] = p3[jt] = g4{0, 0, 0, 0};
+    for (int t0 = 0; t0 < total; t0 += 16) {
+      const int cnt = min(16, total - t0);
+      for (int e = tid; e < 16 * 128; e += 512) {
+        const int tt = e >> 7, jj = e & 127;
+        double2 vv = make_double2(0.0, 0.0), gg = vv;
+        if (tt < cnt) {
+          const int t = t0 + tt;
+          const int pr = S.pair_off + t / nc, c = t % nc;
+          const double2* src =
+              a.gbuf + (long long)pr * a.g_pair_stride + ((long long)ci[c] * a.stages + cr[c]) * 2 * NX;
+          gg = src[NX + 128 * rh + jj];
+          if (jj < 64) vv = src[64 * cq + jj];
+        }
+        sm.in.gsh[tt][jj] = gg;
+        if (jj < 64) sm.in.vs[tt][jj] = vv;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int tk = 4 * q + (lane >> 4);
+        const double2 g = sm.in.gsh[tk][16 * w + (lane & 15)];   // A[j][t] = g_t[j]
+        const double gs = g.x + g.y;
+#pragma unroll
+        for (int jt = 0; jt < 4; ++jt) {
+          const double2 v = sm.in.vs[tk][16 * jt + (lane & 15)];  // B[t][k] = conj(v_t[k])
+          p1[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.x, v.x, p1[jt], 0, 0, 0);
+          p2[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(g.y, -v.y, p2[jt], 0, 0, 0);
+          p3[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(gs, v.x - v.y, p3[jt], 0, 0, 0);
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        sm.C[16 * w + 4 * v + (lane >> 4)][16 * jt + (lane & 15)] =
+            make_double2(p1[jt][v] - p2[jt][v], p3[jt][v] - p1[jt][v] - p2[jt][v]);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < DPT; ++u) {
+      const int d = tid + 512 * u;
+      if (d < S.box) {
+        for (int t = bp[d]; t < bp[d + 1]; ++t) {
+          const int jk = bj[t], jr = jk / NX, kc = jk % NX;
+          if ((jr >> 7) == rh && (kc >> 6) == cq) acc[u] = cadd(acc[u], sm.C[jr - 128 * rh][kc - 64 * cq]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double2* out = a.dU + S.table_off + (long long)n * S.box;
+#pragma unroll
+  for (int u = 0; u < DPT; ++u) {
+    const int d = tid + 512 * u;
+    if (d < S.box) out[d] = acc[u];
+  }
+}
+
+hipError_t launch_backward(int stepper, int width, const BwdArgs& a, hipStream_t stream) {
   if (a.n_pairs < 1) return hipSuccess;
   const dim3 grid(2 * a.n_pairs);
-  if (wide) {
+  if (width == NX) {
+    const dim3 block(BGeo<NX>::threads);
+    if (stepper == 0)
+      hipLaunchKernelGGL((backward_kernel<0, NX>), grid, block, 0, stream, a);
+    else
+      hipLaunchKernelGGL((backward_kernel<1, NX>), grid, block, 0, stream, a);
+  } else if (width == NL) {
     const dim3 block(BGeo<NL>::threads);
     if (stepper == 0)
       hipLaunchKernelGGL((backward_kernel<0, NL>), grid, block, 0, stream, a);
@@ -864,10 +1009,11 @@ hipError_t launch_backward(int stepper, bool wide, const BwdArgs& a, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_grad_assemble(const GradArgs& a, int n_struct, int max_nodes, bool narrow, bool wide,
+hipError_t launch_grad_assemble(const GradArgs& a, int n_struct, int max_nodes, bool narrow, bool wide, bool xl,
                                 hipStream_t stream) {
   if (narrow) hipLaunchKernelGGL(grad_assemble_kernel, dim3(max_nodes, n_struct), dim3(256), 0, stream, a);
   if (wide) hipLaunchKernelGGL(grad_assemble_wide_kernel, dim3(max_nodes, n_struct), dim3(512), 0, stream, a);
+  if (xl) hipLaunchKernelGGL(grad_assemble_xl_kernel, dim3(max_nodes, n_struct), dim3(512), 0, stream, a);
   return hipGetLastError();
 }
 

@@ -32,7 +32,8 @@
 // and applies the recorded operations in reverse to a unit vector.
 //
 // The launch is a persistent grid of one workgroup per CU over the pairs;
-// no workgroup waits for another.  Forward only, RK steppers.
+// no workgroup waits for another.  RK steppers; a separate instance keeps
+// the states the adjoint reads, padded to NX.
 //
 // For a batch too small to fill the device (down to one pair) the same
 // phases run in a group launch: G cooperatively launched workgroups per pair
@@ -454,12 +455,50 @@ __device__ __forceinline__ void xl_group_sync(unsigned* cnt, unsigned target, un
   __syncthreads();
 }
 
+// Q^{-1} (or B^{-1} of the reflection) after xl_elim_record: the recorded
+// column operations replayed on the rows of I, 64 at a time, each column put
+// at its pivot step as in xl_replay_p; all NX rows to out (row major, stride
+// NX; rows >= n stay unit rows).
+__device__ __noinline__ void xl_replay_identity(double2* __restrict__ out, const double2* __restrict__ frec, int N) {
+  XLds& s = xl_lds;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int n = __builtin_amdgcn_readfirstlane(N);
+  int pq[XS];
+#pragma unroll
+  for (int q = 0; q < XS; ++q) pq[q] = s.pos[64 * q + lane];
+#pragma unroll 1
+  for (int r0 = 0; r0 < NX; r0 += XEB) {
+    double2 z[XEM][XS];
+#pragma unroll
+    for (int m = 0; m < XEM; ++m)
+#pragma unroll
+      for (int q = 0; q < XS; ++q) z[m][q] = make_double2(r0 + w + XW * m == 64 * q + lane ? 1.0 : 0.0, 0.0);
+    if (r0 < n) xl_replay<XEM>(z, n, lane, frec);
+#pragma unroll
+    for (int m = 0; m < XEM; ++m) {
+      const int row = r0 + w + XW * m;
+#pragma unroll
+      for (int q = 0; q < XS; ++q) gst(&out[row * NX + pq[q]], z[m][q]);
+    }
+  }
+}
+
+// Copy of an NX x NX block of the slot (for the states the adjoint reads).
+__device__ __forceinline__ void xl_copy(double2* __restrict__ dst, const double2* __restrict__ src) {
+  for (int e = threadIdx.x; e < NX * NX; e += XT) gst(&dst[e], gld(&src[e]));
+}
+
 // One pair.  GRP: workgroup g of the pair's G in a group launch (state,
 // multipliers and pivot list in the pair's block of X.pair_mem, stage
 // products and row-sum partials in the workgroup's block of X.wg_mem);
-// otherwise the whole pair in this workgroup's slot.
-template <int STEPPER, bool GRP>
+// otherwise the whole pair in this workgroup's slot.  SAVE (one workgroup
+// per pair): keep the states the adjoint reads, padded to NX: the state at
+// the start of every ck.every-th slice and after the last, T = Q^{-1} and
+// (ck.every > 1) R of every transformation, one decision byte per slice and
+// B^{-1} of the reflection solve.
+template <int STEPPER, bool GRP, bool SAVE = false>
 __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup& X, int pi, int g) {
+  static_assert(!(GRP && SAVE), "the group launch keeps no states");
   using T = LTab<STEPPER>;
   const FwdArgs& a = A.f;
   XLds& s = xl_lds;
@@ -475,6 +514,8 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
   unsigned* cnt = GRP ? X.counters + 16LL * pi : nullptr;
   unsigned* failw = GRP ? cnt + 1 : nullptr;
   unsigned nsync = 0;
+  char* pws = SAVE ? a.ws + (long long)p * a.ck.pair_stride : nullptr;
+  constexpr long long MATB = (long long)NX * NX * sizeof(double2);
   const StructDev S = a.structs[a.pair_struct[p]];
   const int N = S.n_beams;
   const int L = S.n_slices;
@@ -532,6 +573,13 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
   int nrhst = 0;
 #pragma unroll 1
   for (int i = 0; i < L; ++i) {
+    if constexpr (SAVE) {
+      if ((i % a.ck.every) == 0) {
+        double2* st = reinterpret_cast<double2*>(pws + (long long)(i / a.ck.every) * a.ck.state_bytes);
+        xl_copy(st, cg);
+        xl_copy(st + NX * NX, dg);
+      }
+    }
     xl_slice<STEPPER>(cg, dg, gm, Us, i * T::nodes, S.box, h, N, base, g, G);
     if constexpr (GRP) {
       // the row-sum partials of every workgroup of the pair, summed in the
@@ -572,6 +620,9 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
       lo = fmin(lo, __shfl_xor(lo, o, 64));
     }
     const double xi = lo > 0.0 ? hi / lo : INFINITY;
+    if constexpr (SAVE) {
+      if (tid == 0) pws[a.ck.flags_off + i] = xi > a.threshold ? 1 : 0;
+    }
     if (xi > a.threshold) {
       ++nrhst;
       if constexpr (GRP) {
@@ -595,16 +646,29 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
         xl_group_sync(cnt, G * ++nsync, failw);
       } else {
         xl_elim_record(cg, dg, frec, N, 0);
+        if constexpr (SAVE) xl_replay_identity(reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * MATB), frec, N);
         xl_replay_p(cg, dg, frec, N, 0, 1);
+        if constexpr (SAVE) {
+          if (a.ck.r_off) {  // R = P Q^{-1} for an adjoint that keeps states only every few slices
+            xl_copy(reinterpret_cast<double2*>(pws + a.ck.r_off + (long long)i * MATB), dg);
+            __syncthreads();
+          }
+        }
       }
     }
   }
   if constexpr (GRP) {
     if (g != 0) return;  // workgroup 0 solves the reflection
   }
+  if constexpr (SAVE) {  // the final state
+    double2* st = reinterpret_cast<double2*>(pws + (long long)(a.ck.max_ckpt - 1) * a.ck.state_bytes);
+    xl_copy(st, cg);
+    xl_copy(st + NX * NX, dg);
+  }
   // reflection (Eq. vrhocomp): upper = Gamma Q - iP, lower = Gamma Q + iP,
   // rho = lower x with upper x = e_1
   xl_elim_record(cg, dg, frec, N, 1);
+  if constexpr (SAVE) xl_replay_identity(reinterpret_cast<double2*>(pws + a.ck.binv_off), frec, N);
   if (w == 0) {
     // x = E e_{pc_0}: the recorded operations in reverse order, each v <- v - e_pc (f . v)
     const int pc0 = s.pcrec[0];
@@ -686,13 +750,13 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
   }
 }
 
-template <int STEPPER>
+template <int STEPPER, bool SAVE>
 __global__ __launch_bounds__(XT, 1) void forward_xl_kernel(LargeArgs A) {
   char* slot = A.scratch + (long long)blockIdx.x * XSLOT_BYTES;
 #pragma unroll 1
   for (int pi = blockIdx.x; pi < A.f.n_pairs; pi += gridDim.x) {
     const int p = A.f.pair_list ? A.f.pair_list[pi] : pi;
-    xl_run_pair<STEPPER, false>(A, p, slot, XlGroup{}, 0, 0);
+    xl_run_pair<STEPPER, false, SAVE>(A, p, slot, XlGroup{}, 0, 0);
     __syncthreads();  // LDS is reused by the next pair
   }
 }
@@ -715,11 +779,16 @@ __global__ void xl_group_reset_kernel(unsigned* counters, int n) {
 hipError_t launch_forward_xl(int stepper, const LargeArgs& a, hipStream_t stream) {
   if (a.f.n_pairs < 1) return hipSuccess;
   const int grid = a.f.n_pairs < a.n_slots ? a.f.n_pairs : a.n_slots;
-  if (grid < 1 || (stepper != 0 && stepper != 1) || a.f.ws) return hipErrorInvalidValue;
-  if (stepper == 0)
-    hipLaunchKernelGGL(forward_xl_kernel<0>, dim3(grid), dim3(XT), 0, stream, a);
+  if (grid < 1 || (stepper != 0 && stepper != 1)) return hipErrorInvalidValue;
+  const bool save = a.f.ws != nullptr;
+  if (stepper == 0 && save)
+    hipLaunchKernelGGL((forward_xl_kernel<0, true>), dim3(grid), dim3(XT), 0, stream, a);
+  else if (stepper == 0)
+    hipLaunchKernelGGL((forward_xl_kernel<0, false>), dim3(grid), dim3(XT), 0, stream, a);
+  else if (save)
+    hipLaunchKernelGGL((forward_xl_kernel<1, true>), dim3(grid), dim3(XT), 0, stream, a);
   else
-    hipLaunchKernelGGL(forward_xl_kernel<1>, dim3(grid), dim3(XT), 0, stream, a);
+    hipLaunchKernelGGL((forward_xl_kernel<1, false>), dim3(grid), dim3(XT), 0, stream, a);
   return hipGetLastError();
 }
 
@@ -749,9 +818,14 @@ int forward_xl_group_max_workgroups(int device) {
 int forward_xl_slots(int device) {
   int cus = 0, p0 = 0, p1 = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p0, forward_xl_kernel<0>, XT, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&p1, forward_xl_kernel<1>, XT, 0) != hipSuccess)
+  int p2 = 0, p3 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p0, forward_xl_kernel<0, false>, XT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&p1, forward_xl_kernel<1, false>, XT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&p2, forward_xl_kernel<0, true>, XT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&p3, forward_xl_kernel<1, true>, XT, 0) != hipSuccess)
     return 0;
+  p0 = p0 < p2 ? p0 : p2;
+  p1 = p1 < p3 ? p1 : p3;
   const int per = p0 < p1 ? p0 : p1;
   return cus * (per > 0 ? per : 0);
 }

@@ -198,10 +198,11 @@ hipError_t launch_bulk_update(const BulkArgs& a, hipStream_t stream);
 hipError_t launch_bulk_init(const BulkArgs& a, hipStream_t stream);  // vacuum start, flags cleared
 hipError_t launch_forward_split(int stepper, const FwdArgs& a, hipStream_t stream);
 int forward_split_max_pairs(int device);  // pairs a split launch can hold at once (0: not available)
-// wide: the pairs of the launch have 64 < N <= 128 (state layout W = 128)
-hipError_t launch_backward(int stepper, bool wide, const BwdArgs& a, hipStream_t stream);
-// narrow / wide: launch the assembly for the structures with N <= 64 / with N > 64
-hipError_t launch_grad_assemble(const GradArgs& a, int n_struct, int max_nodes, bool narrow, bool wide,
+// width: the state layout of the launch's pairs, 64 (N <= 64), 128 (N <= 128) or 256
+hipError_t launch_backward(int stepper, int width, const BwdArgs& a, hipStream_t stream);
+// narrow / wide / xl: launch the assembly for the structures with N <= 64 /
+// 64 < N <= 128 / 128 < N <= 256
+hipError_t launch_grad_assemble(const GradArgs& a, int n_struct, int max_nodes, bool narrow, bool wide, bool xl,
                                 hipStream_t stream);
 hipError_t launch_potential(const PotArgs& a, long long max_elems, hipStream_t stream);
 hipError_t launch_potential_bwd(const PotBwdArgs& a, long long n_atoms_total, int n_struct,

@@ -1,6 +1,6 @@
-"""Parity of the HIP adjoint for 64 < N <= 128 (states padded to 128 beams,
-kept by the kernel for N > 64; the vector adjoint on 16 waves; the gradient
-assembly binning C = G^T conj(V) half by half) with the oracle's
+"""Parity of the HIP adjoint for 64 < N <= 256 (states padded to 128 or 256
+beams, kept by the kernels for N > 64; the vector adjoint on 16 waves; the
+gradient assembly binning C = G^T conj(V) in blocks) with the oracle's
 tangent-linear derivatives, with central finite differences of the GPU
 forward, and with the N <= 64 path inside one plan."""
 import dataclasses
@@ -56,16 +56,17 @@ def _loss_only(wl, stepper, target, atoms_np):
 
 
 @pytest.mark.parametrize("every", [1, 7])
-@pytest.mark.parametrize("stepper,n_beams", [("rk4", 65), ("rk6", 91), ("rk6", 128)])
+@pytest.mark.parametrize("stepper,n_beams", [("rk4", 65), ("rk6", 91), ("rk6", 128), ("rk4", 150), ("rk6", 199),
+                                             ("rk6", 256)])
 def test_wide_table_gradient_matches_oracle_tangent(stepper, n_beams, every):
     """The table gradient along random directions against the oracle's
     tangent-linear derivative, with states kept at every slice and every 7
-    (a partial top segment), at N = 65, 91 and the full width 128."""
+    (a partial top segment), at N = 65, 91, 128 (states padded to 128) and
+    150, 199, 256 (padded to 256)."""
     L = 24 if stepper == "rk6" else 40
     wl = small_2d(n_beams=n_beams, n_slices=L, thickness=0.1 * L, n_layers=1, n_angles=3)
     tgt = _target(3)
     res = _run(wl, stepper, tgt, checkpoint_every=every)
-    assert res["large_pairs"] == 3
     assert (res["status"] == 0).all()
     st = driver.StructureSetup(wl, wl.structures[0], driver.TABLEAUX[stepper])
     rng = np.random.default_rng(11)
@@ -79,12 +80,13 @@ def test_wide_table_gradient_matches_oracle_tangent(stepper, n_beams, every):
         assert got == pytest.approx(dl, rel=1e-9)
 
 
-@pytest.mark.parametrize("every", [1, 20])
-def test_wide_atom_gradient_every_coordinate(every):
-    """Every coordinate of the 9 atoms of an N = 91 slab (RK6, 40 slices)
-    against the oracle's tangent-linear derivative along that coordinate,
-    entry by entry (1e-8 relative to the entry, or to 1e-6 of the largest)."""
-    wl = small_2d(n_beams=91, n_slices=40, thickness=4.0, n_layers=1, n_angles=3)
+@pytest.mark.parametrize("n_beams,every", [(91, 1), (91, 20), (170, 1), (170, 20)])
+def test_wide_atom_gradient_every_coordinate(n_beams, every):
+    """Every coordinate of the 9 atoms of an N = 91 or 170 slab (RK6, 40
+    slices) against the oracle's tangent-linear derivative along that
+    coordinate, entry by entry (1e-8 relative to the entry, or to 1e-6 of
+    the largest)."""
+    wl = small_2d(n_beams=n_beams, n_slices=40, thickness=4.0, n_layers=1, n_angles=3)
     tgt = _target(3, seed=13)
     res = _run(wl, "rk6", tgt, checkpoint_every=every)
     assert (res["status"] == 0).all()
@@ -92,7 +94,7 @@ def test_wide_atom_gradient_every_coordinate(every):
     coords = [(ia, c) for ia in range(n_atoms) for c in range(3)]
     ref = oracle_atom_gradient(wl, tgt, coords, stepper="rk6")
     got = np.array([res["datoms"][ia, c] for ia, c in coords])
-    assert_entrywise(got, ref, what=f"N=91 slab K={every}, all {len(coords)} coordinates")
+    assert_entrywise(got, ref, what=f"N={n_beams} slab K={every}, all {len(coords)} coordinates")
 
 
 def test_wide_atom_gradient_against_central_differences():
@@ -112,32 +114,33 @@ def test_wide_atom_gradient_against_central_differences():
         assert g[ia, c] == pytest.approx(fd, rel=1e-5, abs=1e-9 * np.abs(g).max())
 
 
-@pytest.mark.parametrize("stepper", ["rk4", "rk6"])
-def test_wide_checkpoint_segments_match_every_slice_states(stepper):
+@pytest.mark.parametrize("stepper,n_beams", [("rk4", 91), ("rk6", 91), ("rk6", 199)])
+def test_wide_checkpoint_segments_match_every_slice_states(stepper, n_beams):
     """States every 20 slices give the every-slice adjoint's table gradient
-    to rounding (N = 91 over 50 slices: a partial top segment)."""
-    wl = small_2d(n_beams=91, n_slices=50, thickness=5.0, n_layers=1, n_angles=3)
+    to rounding (50 slices: a partial top segment)."""
+    wl = small_2d(n_beams=n_beams, n_slices=50, thickness=5.0, n_layers=1, n_angles=3)
     tgt = _target(3, seed=6)
     ref = _run(wl, stepper, tgt, checkpoint_every=1)
     got = _run(wl, stepper, tgt, checkpoint_every=20)
     assert (ref["status"] == 0).all()
     err = np.abs(got["dU"] - ref["dU"]).max() / np.abs(ref["dU"]).max()
-    print(f"[adjoint-wide] N=91 {stepper} K=20 vs K=1: {err:.3e}", flush=True)
+    print(f"[adjoint-wide] N={n_beams} {stepper} K=20 vs K=1: {err:.3e}", flush=True)
     np.testing.assert_allclose(got["dU"], ref["dU"], rtol=0.0, atol=1e-13 * np.abs(ref["dU"]).max())
 
 
 @pytest.mark.parametrize("layout", ["whole", "split"])
 def test_mixed_plan_gradient_equals_separate_plans(layout):
-    """A plan with an N = 29 and an N = 91 structure (two backward launches,
-    the two state layouts in one workspace) gives each structure the table
+    """A plan with N = 29, 91 and 150 structures (three backward launches,
+    the three state layouts in one workspace) gives each structure the table
     and atom gradient of a plan holding that structure alone."""
     a = small_2d(n_beams=29, n_slices=30, thickness=3.0, n_layers=1, n_angles=3, seed=41)
     b = small_2d(n_beams=91, n_slices=24, thickness=2.4, n_layers=1, n_angles=3, seed=42)
-    wl = dataclasses.replace(a, structures=[a.structures[0], b.structures[0]])
-    tgt = _target(6, seed=8)
+    c = small_2d(n_beams=150, n_slices=16, thickness=1.6, n_layers=1, n_angles=3, seed=43)
+    wl = dataclasses.replace(a, structures=[a.structures[0], b.structures[0], c.structures[0]])
+    tgt = _target(9, seed=8)
     both = _run(wl, "rk6", tgt, checkpoint_every=7, layout=layout)
     assert (both["status"] == 0).all()
-    for s, part in enumerate((a, b)):
+    for s, part in enumerate((a, b, c)):
         alone = _run(part, "rk6", tgt[3 * s:3 * s + 3], checkpoint_every=7, layout=layout)
         t0, t1 = both["table_offsets"][s], both["table_offsets"][s + 1]
         a0, a1 = both["atom_offsets"][s], both["atom_offsets"][s + 1]
@@ -171,5 +174,27 @@ def test_wide_gradient_full_size_n121():
     loss, dl = driver.rfactor_directional(sub, 0, d, tgt, stepper="rk6")
     got = float(np.sum(res["datoms"] * d))
     print(f"[adjoint-wide] N=121 full size (3 angles) direction: gpu {got:.12e} oracle {dl:.12e}", flush=True)
+    assert res["loss"] == pytest.approx(loss, rel=1e-10)
+    assert got == pytest.approx(dl, rel=1e-8)
+
+
+def test_n199_gradient_full_size_one_angle():
+    """The N = 199 slab of the large workload at full size (60 A in 1000
+    slices, RK6, states every 20 slices) at one angle: the pair through the
+    validity gate and the atom gradient along a random direction of all its
+    atoms against the oracle's tangent-linear derivative."""
+    from synth import config5
+    from tests.gpu_util import physical
+    wl = config5(1)
+    sub = dataclasses.replace(wl, theta0=wl.theta0[[120]])
+    tgt = _target(1, seed=29)
+    res = _run(sub, "rk6", tgt, checkpoint_every=20)
+    assert (res["status"] == 0).all()
+    assert physical(res["eta"][:, :199], sub.absorption).all()
+    atoms = sub.structures[0].atoms
+    d = np.random.default_rng(31).normal(size=atoms.shape)
+    loss, dl = driver.rfactor_directional(sub, 0, d, tgt, stepper="rk6")
+    got = float(np.sum(res["datoms"] * d))
+    print(f"[adjoint-wide] N=199 full size (one angle) direction: gpu {got:.12e} oracle {dl:.12e}", flush=True)
     assert res["loss"] == pytest.approx(loss, rel=1e-10)
     assert got == pytest.approx(dl, rel=1e-8)

@@ -118,12 +118,10 @@ def test_xl_refusals():
         with pytest.raises(RheedError, match="N > 128|N <= 64"):
             api.plan_for(wl, **kw)
     plan = api.plan_for(wl, stepper="rk6")
-    assert plan.info.fwd_workspace == 0 and plan.info.bwd_workspace == 0
+    # states padded to 256 beams: at least the final state and B^{-1} per pair
+    assert plan.info.fwd_workspace >= plan.n_pairs * 3 * 256 * 256 * 16
     dev = torch.device("cuda:0")
     U = plan.potential(api.atoms_for(wl, dev))
     ws = torch.empty(1024, dtype=torch.uint8, device=dev)
-    with pytest.raises(RheedError, match="N <= 128"):
+    with pytest.raises(RheedError, match="workspace of"):
         plan.forward(U, api.angles_for(wl, dev), workspace=ws)
-    dI = torch.zeros((plan.n_pairs, plan.max_beams), dtype=torch.float64, device=dev)
-    with pytest.raises(RheedError, match="N <= 128"):
-        plan.backward(U, api.angles_for(wl, dev), dI, ws)
