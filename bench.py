@@ -422,6 +422,8 @@ def n199_forward(steps=1, cpu=True):
     angles: one pair per CU), the kernel for 128 < N <= 256, with its
     algorithmic FP64 rate; the whole workload (64 structures) is 64 such
     batches."""
+    import dataclasses
+    import numpy as np
     import torch
     from paper_2306_00271_amd import api
     from synth import config5
@@ -456,7 +458,6 @@ def n199_forward(steps=1, cpu=True):
     del plan, U
     # one pair alone (the paper's single-angle case): on one workgroup, and
     # on a group of workgroups that step its column blocks side by side
-    import dataclasses
     single = dataclasses.replace(wl, theta0=wl.theta0[100:101])
     res["single_pair"] = {}
     for layout in ("whole", "auto"):
@@ -474,6 +475,36 @@ def n199_forward(steps=1, cpu=True):
                                    "invalid_pairs": invalid_pairs(o1["intensity"], o1["status"], wl.absorption)}
         print(f"[n199] single pair, {key}: {res['single_pair'][key]['ms']} ms", file=sys.stderr, flush=True)
         del p1, U1
+    # the gradient step (potential -> forward keeping states every 20 slices ->
+    # R-factor -> adjoint -> atom gradient) on a few angles per call: the T and R
+    # slots of every slice take about 2 GB per pair at this size
+    ga = 16
+    gw = dataclasses.replace(wl, theta0=wl.theta0[::256 // ga][:ga])
+    pg = api.plan_for(gw, stepper="rk6", checkpoint_every=20)
+    atoms = api.atoms_for(gw, dev)
+    ag = api.angles_for(gw, dev)
+    ws = pg.workspace(dev)
+    tgt = torch.from_numpy(np.random.default_rng(37).uniform(0.0, 0.3, size=pg.n_pairs)).to(dev)
+
+    def gstep():
+        Ug = pg.potential(atoms)
+        og = pg.forward(Ug, ag, workspace=ws)
+        _, dI = api.rfactor(og["intensity"], tgt)
+        return og, pg.potential_backward(atoms, pg.backward(Ug, ag, dI, ws))
+    gstep()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    og, grad = gstep()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gms = e0.elapsed_time(e1)
+    res["gradient"] = {"pairs": pg.n_pairs, "checkpoint_every": 20, "ms_per_step": round(gms, 1),
+                       "value": round(pg.n_pairs / (gms / 1e3), 3), "unit": "points/s (gradient step)",
+                       "workspace_gb": round((pg.info.fwd_workspace + pg.info.bwd_workspace) / 1e9, 1),
+                       "invalid_pairs": invalid_pairs(og["intensity"], og["status"], wl.absorption),
+                       "gradient_finite": bool(torch.isfinite(grad).all().item())}
+    print(f"[n199] gradient step, {pg.n_pairs} pairs: {gms:.1f} ms", file=sys.stderr, flush=True)
+    del pg, ws
     if cpu:
         import multiprocessing as mp
         cores = min(16, os.cpu_count() or 1)

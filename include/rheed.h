@@ -93,7 +93,7 @@ typedef enum { RHEED_INTENSITY_FLUX = 0, RHEED_INTENSITY_PAPER = 1 } rheed_conve
  * memory owned by the plan.  Both have the adjoint (RK steppers, FP64).
  * Structures with 128 < N <= 256 run on a third kernel, also with the state
  * in plan-owned memory, which streams the rows of its eliminations through
- * that memory: RK steppers, FP64, forward only. */
+ * that memory: RK steppers, FP64, with the adjoint. */
 #define RHEED_MAX_BEAMS 256
 /* Largest potential-table row (rod differences) for N <= 64, for
  * 64 < N <= 128 and for 128 < N <= 256. */
