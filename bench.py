@@ -700,6 +700,36 @@ def traffic_probe_uneven(n_structures):
                       "pairs": [len(w.structures) * len(w.theta0), whole.n_pairs]}))
 
 
+def xl_source_hash():
+    """sha256 of the sources the kernel for 128 < N <= 256 is built from."""
+    h = hashlib.sha256()
+    for f in ("rheed_forward_xl.hip", "rheed_forward_large.hip", "rheed_forward.hip", "rheed_forward_all.hip",
+              "rheed_large.h", "rheed_gj.h", "rheed_internal.h"):
+        with open(os.path.join(ROOT, "paper_2306_00271_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_probe_n199():
+    """One forward launch of one structure of the N = 199 workload (256
+    pairs, one workgroup each) and one device copy of 1 GiB, for FETCH_SIZE /
+    WRITE_SIZE counter runs."""
+    import torch
+    from paper_2306_00271_amd import api
+    from synth import config5
+    dev = torch.device("cuda:0")
+    wl = config5(1)
+    plan = api.plan_for(wl, stepper="rk6")
+    U = plan.potential(api.atoms_for(wl, dev))
+    plan.forward(U, api.angles_for(wl, dev))
+    src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": src.numel() * 8, "source_sha256": xl_source_hash(),
+                      "kernel": "forward_xl_kernel<1, false>", "pairs": plan.n_pairs}))
+
+
 # -------------------------------------------------------------------- bench
 def main():
     ap = argparse.ArgumentParser()
@@ -726,6 +756,9 @@ def main():
         print("bench.py measures one GPU: every box in this setup has a single MI355X; "
               "pairs are independent and would shard across GPUs, each GPU running its share of the (structure, angle) pairs.", file=sys.stderr)
         sys.exit(2)
+    if args.traffic_probe and args.mode == "n199":
+        traffic_probe_n199()
+        return
     if args.traffic_probe:
         if args.mode == "uneven":
             traffic_probe_uneven(max(1, args.uneven_structures))
