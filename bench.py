@@ -498,7 +498,8 @@ def n199_forward(steps=1, cpu=True):
     e1.record(stream)
     torch.cuda.synchronize()
     gms = e0.elapsed_time(e1)
-    res["gradient"] = {"pairs": pg.n_pairs, "checkpoint_every": 20, "ms_per_step": round(gms, 1),
+    res["gradient"] = {"pairs": pg.n_pairs, "checkpoint_every": 20, "xl_group": pg.info.xl_group,
+                       "ms_per_step": round(gms, 1),
                        "value": round(pg.n_pairs / (gms / 1e3), 3), "unit": "points/s (gradient step)",
                        "workspace_gb": round((pg.info.fwd_workspace + pg.info.bwd_workspace) / 1e9, 1),
                        "invalid_pairs": invalid_pairs(og["intensity"], og["status"], wl.absorption),

@@ -771,7 +771,7 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
     xa.f.xch = nullptr;
     xa.scratch = P->d_xscratch;
     xa.n_slots = P->xl_slots;
-    if (P->xl_group > 1 && !workspace) {
+    if (P->xl_group > 1) {
       XlGroup xg{};
       xg.pair_mem = P->d_xg_pair;
       xg.wg_mem = P->d_xg_wg;

@@ -43,7 +43,8 @@
 // same order in every workgroup, so all take the same decision); at a
 // transformation workgroup 0 records the elimination, the others wait, and
 // all then replay it on their 64-row blocks of P.  Workgroup 0 alone solves
-// the reflection.
+// the reflection.  Both launches have an instance that keeps the adjoint's
+// states.
 
 namespace rheed {
 namespace {
@@ -456,10 +457,11 @@ __device__ __forceinline__ void xl_group_sync(unsigned* cnt, unsigned target, un
 }
 
 // Q^{-1} (or B^{-1} of the reflection) after xl_elim_record: the recorded
-// column operations replayed on the rows of I, 64 at a time, each column put
-// at its pivot step as in xl_replay_p; all NX rows to out (row major, stride
-// NX; rows >= n stay unit rows).
-__device__ __noinline__ void xl_replay_identity(double2* __restrict__ out, const double2* __restrict__ frec, int N) {
+// column operations replayed on the rows of I, 64 at a time (row blocks b0,
+// b0 + bs, ... of the NX / 64), each column put at its pivot step as in
+// xl_replay_p; rows to out (row major, stride NX; rows >= n stay unit rows).
+__device__ __noinline__ void xl_replay_identity(double2* __restrict__ out, const double2* __restrict__ frec, int N,
+                                                int b0, int bs) {
   XLds& s = xl_lds;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int n = __builtin_amdgcn_readfirstlane(N);
@@ -467,7 +469,7 @@ __device__ __noinline__ void xl_replay_identity(double2* __restrict__ out, const
 #pragma unroll
   for (int q = 0; q < XS; ++q) pq[q] = s.pos[64 * q + lane];
 #pragma unroll 1
-  for (int r0 = 0; r0 < NX; r0 += XEB) {
+  for (int r0 = XEB * b0; r0 < NX; r0 += XEB * bs) {
     double2 z[XEM][XS];
 #pragma unroll
     for (int m = 0; m < XEM; ++m)
@@ -488,17 +490,39 @@ __device__ __forceinline__ void xl_copy(double2* __restrict__ dst, const double2
   for (int e = threadIdx.x; e < NX * NX; e += XT) gst(&dst[e], gld(&src[e]));
 }
 
+// The same for the 16-column blocks cb0, cb0 + cbs, ... of the NX / 16 (a
+// workgroup's share of a state in a group launch: the blocks it steps).
+__device__ __forceinline__ void xl_copy_cols(double2* __restrict__ dst, const double2* __restrict__ src, int cb0,
+                                             int cbs) {
+#pragma unroll 1
+  for (int cb = cb0; cb < NX / XCB; cb += cbs)
+    for (int e = threadIdx.x; e < NX * XCB; e += XT) {
+      const int i = (e / XCB) * NX + XCB * cb + (e & (XCB - 1));
+      gst(&dst[i], gld(&src[i]));
+    }
+}
+
+// The same for the 64-row blocks b0, b0 + bs, ... of the NX / 64.
+__device__ __forceinline__ void xl_copy_rows(double2* __restrict__ dst, const double2* __restrict__ src, int b0,
+                                             int bs) {
+#pragma unroll 1
+  for (int b = b0; b < NX / XEB; b += bs)
+    for (int e = threadIdx.x; e < XEB * NX; e += XT) gst(&dst[XEB * NX * b + e], gld(&src[XEB * NX * b + e]));
+}
+
 // One pair.  GRP: workgroup g of the pair's G in a group launch (state,
 // multipliers and pivot list in the pair's block of X.pair_mem, stage
 // products and row-sum partials in the workgroup's block of X.wg_mem);
-// otherwise the whole pair in this workgroup's slot.  SAVE (one workgroup
-// per pair): keep the states the adjoint reads, padded to NX: the state at
-// the start of every ck.every-th slice and after the last, T = Q^{-1} and
-// (ck.every > 1) R of every transformation, one decision byte per slice and
-// B^{-1} of the reflection solve.
+// otherwise the whole pair in this workgroup's slot.  SAVE: keep the states
+// the adjoint reads, padded to NX: the state at the start of every
+// ck.every-th slice and after the last, T = Q^{-1} and (ck.every > 1) R of
+// every transformation, one decision byte per slice and B^{-1} of the
+// reflection solve.  In a group launch each workgroup copies the column
+// blocks of the states that it steps itself (no other workgroup writes them
+// until the next barrier) and a share of the row blocks of T and R; the
+// decision bytes and B^{-1} are workgroup 0's.
 template <int STEPPER, bool GRP, bool SAVE = false>
 __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup& X, int pi, int g) {
-  static_assert(!(GRP && SAVE), "the group launch keeps no states");
   using T = LTab<STEPPER>;
   const FwdArgs& a = A.f;
   XLds& s = xl_lds;
@@ -576,8 +600,13 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
     if constexpr (SAVE) {
       if ((i % a.ck.every) == 0) {
         double2* st = reinterpret_cast<double2*>(pws + (long long)(i / a.ck.every) * a.ck.state_bytes);
-        xl_copy(st, cg);
-        xl_copy(st + NX * NX, dg);
+        if constexpr (GRP) {
+          xl_copy_cols(st, cg, g, G);
+          xl_copy_cols(st + NX * NX, dg, g, G);
+        } else {
+          xl_copy(st, cg);
+          xl_copy(st + NX * NX, dg);
+        }
       }
     }
     xl_slice<STEPPER>(cg, dg, gm, Us, i * T::nodes, S.box, h, N, base, g, G);
@@ -621,7 +650,7 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
     }
     const double xi = lo > 0.0 ? hi / lo : INFINITY;
     if constexpr (SAVE) {
-      if (tid == 0) pws[a.ck.flags_off + i] = xi > a.threshold ? 1 : 0;
+      if (tid == 0 && g == 0) pws[a.ck.flags_off + i] = xi > a.threshold ? 1 : 0;
     }
     if (xi > a.threshold) {
       ++nrhst;
@@ -643,10 +672,20 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
           __syncthreads();
         }
         xl_replay_p(cg, dg, frec, N, g, G);
+        if constexpr (SAVE) {
+          // T: row block b of I by workgroup (nbp + b) mod G, after the nbp
+          // row blocks of P; R: row block b of P Q^{-1} by workgroup b mod G,
+          // the one that replayed it
+          const int nbp = (N + XEB - 1) / XEB;
+          xl_replay_identity(reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * MATB), frec, N,
+                             ((g - nbp) % G + G) % G, G);
+          if (a.ck.r_off) xl_copy_rows(reinterpret_cast<double2*>(pws + a.ck.r_off + (long long)i * MATB), dg, g, G);
+        }
         xl_group_sync(cnt, G * ++nsync, failw);
       } else {
         xl_elim_record(cg, dg, frec, N, 0);
-        if constexpr (SAVE) xl_replay_identity(reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * MATB), frec, N);
+        if constexpr (SAVE)
+          xl_replay_identity(reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * MATB), frec, N, 0, 1);
         xl_replay_p(cg, dg, frec, N, 0, 1);
         if constexpr (SAVE) {
           if (a.ck.r_off) {  // R = P Q^{-1} for an adjoint that keeps states only every few slices
@@ -657,18 +696,23 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
       }
     }
   }
+  if constexpr (SAVE) {  // the final state (the reflection below only reads c and c')
+    double2* st = reinterpret_cast<double2*>(pws + (long long)(a.ck.max_ckpt - 1) * a.ck.state_bytes);
+    if constexpr (GRP) {
+      xl_copy_cols(st, cg, g, G);
+      xl_copy_cols(st + NX * NX, dg, g, G);
+    } else {
+      xl_copy(st, cg);
+      xl_copy(st + NX * NX, dg);
+    }
+  }
   if constexpr (GRP) {
     if (g != 0) return;  // workgroup 0 solves the reflection
-  }
-  if constexpr (SAVE) {  // the final state
-    double2* st = reinterpret_cast<double2*>(pws + (long long)(a.ck.max_ckpt - 1) * a.ck.state_bytes);
-    xl_copy(st, cg);
-    xl_copy(st + NX * NX, dg);
   }
   // reflection (Eq. vrhocomp): upper = Gamma Q - iP, lower = Gamma Q + iP,
   // rho = lower x with upper x = e_1
   xl_elim_record(cg, dg, frec, N, 1);
-  if constexpr (SAVE) xl_replay_identity(reinterpret_cast<double2*>(pws + a.ck.binv_off), frec, N);
+  if constexpr (SAVE) xl_replay_identity(reinterpret_cast<double2*>(pws + a.ck.binv_off), frec, N, 0, 1);
   if (w == 0) {
     // x = E e_{pc_0}: the recorded operations in reverse order, each v <- v - e_pc (f . v)
     const int pc0 = s.pcrec[0];
@@ -763,11 +807,11 @@ __global__ __launch_bounds__(XT, 1) void forward_xl_kernel(LargeArgs A) {
 
 // Group launch: G workgroups per pair, grid = pairs x G, all resident
 // (cooperative launch).
-template <int STEPPER>
+template <int STEPPER, bool SAVE>
 __global__ __launch_bounds__(XT, 1) void forward_xl_group_kernel(LargeArgs A, XlGroup X) {
   const int pi = blockIdx.x / X.group, g = blockIdx.x - pi * X.group;
   const int p = A.f.pair_list ? A.f.pair_list[pi] : pi;
-  xl_run_pair<STEPPER, true>(A, p, nullptr, X, pi, g);
+  xl_run_pair<STEPPER, true, SAVE>(A, p, nullptr, X, pi, g);
 }
 
 __global__ void xl_group_reset_kernel(unsigned* counters, int n) {
@@ -794,24 +838,30 @@ hipError_t launch_forward_xl(int stepper, const LargeArgs& a, hipStream_t stream
 
 hipError_t launch_forward_xl_group(int stepper, const LargeArgs& a, const XlGroup& x, hipStream_t stream) {
   if (a.f.n_pairs < 1) return hipSuccess;
-  if (x.group < 1 || (stepper != 0 && stepper != 1) || a.f.ws) return hipErrorInvalidValue;
+  if (x.group < 1 || (stepper != 0 && stepper != 1)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(xl_group_reset_kernel, dim3(1), dim3(256), 0, stream, x.counters, a.f.n_pairs);
   LargeArgs aa = a;
   XlGroup xx = x;
   void* params[] = {&aa, &xx};
-  const void* f = stepper == 0 ? reinterpret_cast<const void*>(&forward_xl_group_kernel<0>)
-                               : reinterpret_cast<const void*>(&forward_xl_group_kernel<1>);
+  const bool save = a.f.ws != nullptr;
+  const void* f = stepper == 0 ? (save ? reinterpret_cast<const void*>(&forward_xl_group_kernel<0, true>)
+                                       : reinterpret_cast<const void*>(&forward_xl_group_kernel<0, false>))
+                               : (save ? reinterpret_cast<const void*>(&forward_xl_group_kernel<1, true>)
+                                       : reinterpret_cast<const void*>(&forward_xl_group_kernel<1, false>));
   return hipLaunchCooperativeKernel(f, dim3(a.f.n_pairs * x.group), dim3(XT), params, 0, stream);
 }
 
 int forward_xl_group_max_workgroups(int device) {
-  int coop = 0, cus = 0, p0 = 0, p1 = 0;
+  int coop = 0, cus = 0, p[4] = {0, 0, 0, 0};
   if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, device) != hipSuccess || !coop) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p0, forward_xl_group_kernel<0>, XT, 0) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&p1, forward_xl_group_kernel<1>, XT, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p[0], forward_xl_group_kernel<0, false>, XT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&p[1], forward_xl_group_kernel<1, false>, XT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&p[2], forward_xl_group_kernel<0, true>, XT, 0) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&p[3], forward_xl_group_kernel<1, true>, XT, 0) != hipSuccess)
     return 0;
-  const int per = p0 < p1 ? p0 : p1;
+  int per = p[0];
+  for (int q = 1; q < 4; ++q) per = p[q] < per ? p[q] : per;
   return cus * (per > 0 ? per : 0);
 }
 

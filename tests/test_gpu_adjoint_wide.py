@@ -1,6 +1,7 @@
 """Parity of the HIP adjoint for 64 < N <= 256 (states padded to 128 or 256
-beams, kept by the kernels for N > 64; the vector adjoint on 16 waves; the
-gradient assembly binning C = G^T conj(V) in blocks) with the oracle's
+beams, kept by the kernels for N > 64, for N > 128 by one workgroup per
+pair or by a group of them; the vector adjoint on 16 waves; the gradient
+assembly binning C = G^T conj(V) in blocks) with the oracle's
 tangent-linear derivatives, with central finite differences of the GPU
 forward, and with the N <= 64 path inside one plan."""
 import dataclasses
@@ -29,7 +30,7 @@ def _run(wl, stepper, target, checkpoint_every=1, layout="auto"):
     U = plan.potential(atoms)
     ang = api.angles_for(wl, dev)
     ws = plan.workspace(dev)
-    out = plan.forward(U, ang, workspace=ws)
+    out = plan.forward(U, ang, workspace=ws, want_nrhst=True)
     tgt = torch.from_numpy(np.asarray(target, dtype=np.float64)).to(dev)
     loss, dI = api.rfactor(out["intensity"], tgt)
     dU = plan.backward(U, ang, dI, ws)
@@ -38,7 +39,8 @@ def _run(wl, stepper, target, checkpoint_every=1, layout="auto"):
     res = {"loss": float(loss.item()), "dU": dU.cpu().numpy(), "datoms": dA.cpu().numpy(),
            "eta": out["intensity"].cpu().numpy(), "status": out["status"].cpu().numpy(),
            "table_offsets": plan.table_offsets.copy(), "atom_offsets": plan.atom_offsets.copy(),
-           "large_pairs": plan.info.large_pairs}
+           "large_pairs": plan.info.large_pairs, "xl_group": plan.info.xl_group,
+           "n_rhst": out["n_rhst"].cpu().numpy()}
     del ws, plan
     return res
 
@@ -150,6 +152,28 @@ def test_mixed_plan_gradient_equals_separate_plans(layout):
         np.testing.assert_allclose(du, alone["dU"], rtol=0.0, atol=1e-14 * np.abs(alone["dU"]).max())
         np.testing.assert_allclose(both["datoms"][a0:a1], alone["datoms"], rtol=1e-12,
                                    atol=1e-14 * np.abs(alone["datoms"]).max())
+
+
+@pytest.mark.parametrize("stepper,n_beams,every", [("rk6", 150, 1), ("rk4", 199, 7), ("rk6", 256, 7)])
+def test_group_and_one_workgroup_gradients_agree(stepper, n_beams, every):
+    """For N > 128 the forward on a group of workgroups per pair (each
+    copying the column blocks it steps into the kept states, and a share of
+    the row blocks of T and R) keeps what the one-workgroup launch keeps:
+    the same transformation counts and the same table and atom gradients."""
+    L = 24 if stepper == "rk6" else 40
+    wl = small_2d(n_beams=n_beams, n_slices=L, thickness=0.1 * L, n_layers=2, n_angles=3, seed=17)
+    tgt = _target(3, seed=21)
+    grp = _run(wl, stepper, tgt, checkpoint_every=every, layout="auto")
+    one = _run(wl, stepper, tgt, checkpoint_every=every, layout="whole")
+    assert grp["xl_group"] == (n_beams + 15) // 16 and one["xl_group"] == 1
+    assert (grp["status"] == 0).all() and (one["status"] == 0).all()
+    assert grp["n_rhst"].tolist() == one["n_rhst"].tolist()
+    assert grp["loss"] == pytest.approx(one["loss"], rel=1e-13)
+    du = np.abs(grp["dU"] - one["dU"]).max() / np.abs(one["dU"]).max()
+    da = np.abs(grp["datoms"] - one["datoms"]).max() / np.abs(one["datoms"]).max()
+    print(f"[adjoint-wide] N={n_beams} {stepper} K={every} group of {grp['xl_group']} vs one workgroup: "
+          f"dU {du:.3e}, datoms {da:.3e}", flush=True)
+    assert du <= 1e-12 and da <= 1e-12
 
 
 def test_wide_gradient_full_size_n121():
