@@ -65,10 +65,13 @@ def invalid_pairs(intensity, status, absorption):
 
 # ---------------------------------------------------------------- CPU baseline
 def _cpu_worker(args):
-    os.environ["OMP_NUM_THREADS"] = "1"
-    os.environ["OPENBLAS_NUM_THREADS"] = "1"
-    os.environ["MKL_NUM_THREADS"] = "1"
     kind, idx, stepper = args[:3]
+    # one BLAS thread per process, except for the single-pair case, which the
+    # paper also times with threaded BLAS (idx = threads there)
+    nthr = str(idx) if kind == "n521" else "1"
+    os.environ["OMP_NUM_THREADS"] = nthr
+    os.environ["OPENBLAS_NUM_THREADS"] = nthr
+    os.environ["MKL_NUM_THREADS"] = nthr
     import numpy as np
     from synth import config3, config4
     from oracle import driver
@@ -90,6 +93,17 @@ def _cpu_worker(args):
         wl3 = config3(args[3])
         t0 = time.perf_counter()
         driver.rocking_curve(wl3, s_idx=idx, angle_idx=[(idx * 37) % len(wl3.theta0)], stepper=stepper)
+        return time.perf_counter() - t0
+    if kind == "n521":
+        # the single-angle n = 521 case over its first args[3] slices (same step)
+        import dataclasses
+        from synth import single_angle_n521
+        w6 = single_angle_n521()
+        st6 = w6.structures[0]
+        part = dataclasses.replace(st6, n_slices=args[3], thickness=st6.thickness * args[3] / st6.n_slices)
+        w6 = dataclasses.replace(w6, structures=[part])
+        t0 = time.perf_counter()
+        driver.rocking_curve(w6, stepper=stepper)
         return time.perf_counter() - t0
     if kind == "n199":
         # one pair of the N = 199 workload over its first args[3] slices (same step)
@@ -523,6 +537,60 @@ def n199_forward(steps=1, cpu=True):
     return res
 
 
+# ------------------------------------------- single angle, n = 521 (Sec. 4)
+def n521_single(steps=2, cpu=True):
+    """The paper's single-angle case at its size (n = 521 rods, one angle,
+    9.91 A in 661 RK4 slices of 0.015 A; synthetic 7x7 cell): one pair on a
+    group of ceil(N / 16) workgroups, the kernel for 256 < N <= 576.  The
+    paper's own figure for this case (its RK4 at this step, 8 CPU cores with
+    threaded BLAS) is 23.97 s, quoted as context: other hardware, other
+    input."""
+    import torch
+    from paper_2306_00271_amd import api
+    from synth import single_angle_n521
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    wl = single_angle_n521()
+    plan = api.plan_for(wl, stepper="rk4")
+    U = plan.potential(api.atoms_for(wl, dev))
+    ang = api.angles_for(wl, dev)
+    out = plan.forward(U, ang, want_nrhst=True)
+    torch.cuda.synchronize()
+    print(f"[n521] warm-up forward done (group of {plan.info.xxl_group})", file=sys.stderr, flush=True)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        out = plan.forward(U, ang, want_nrhst=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = wl.structures[0]
+    nr = out["n_rhst"].cpu().numpy()
+    eta = out["intensity"].cpu().numpy()[0, :st.n_beams]
+    fl = _flops_forward(st.n_beams, st.n_slices, 4, int(nr.sum()), 1)
+    res = {"n_beams": st.n_beams, "slices": st.n_slices, "stepper": "rk4", "group": int(plan.info.xxl_group),
+           "ms_per_forward": round(ms, 2), "achieved_tflops": round(fl / (ms / 1e3) / 1e12, 3),
+           "n_rhst": int(nr[0]), "specular": float(f"{eta[0]:.6e}"), "sum_eta": float(f"{eta.sum():.6e}"),
+           "invalid_pairs": invalid_pairs(out["intensity"], out["status"], wl.absorption),
+           "paper_rk4_s_8_cpu_cores": 23.97}
+    print(f"[n521] forward {ms:.1f} ms", file=sys.stderr, flush=True)
+    del plan, U
+    if cpu:
+        import multiprocessing as mp
+        threads = min(16, os.cpu_count() or 1)
+        part = 40
+        with mp.get_context("spawn").Pool(1) as pool:
+            t = pool.map(_cpu_worker, [("n521", threads, "rk4", part)])[0]
+        per_pair = t * st.n_slices / part
+        res["cpu_baseline"] = {"value": round(1.0 / per_pair, 5), "unit": "points/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"the pair over the first {part} of the {st.n_slices} slices, oracle forward "
+                                         f"with {threads} BLAS threads, scaled to the whole slab: {per_pair:.1f} s"}
+    return res
+
+
 # ------------------------------------------------------------- bulk layer
 BULK_SLICES = 62   # per 3.1 A unit layer (h = 0.05 A): at 0.1 A the 61-beam stack drifts to the wrong modes
 
@@ -737,10 +805,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["fwd", "fwd+adj", "uneven", "steppers", "bulk", "fp32", "wide-grad", "n199"],
+    ap.add_argument("--mode", choices=["fwd", "fwd+adj", "uneven", "steppers", "bulk", "fp32", "wide-grad", "n199",
+                                       "n521"],
                     default="fwd+adj",
                     help="uneven: only the uneven-N batched forward variant; steppers: only the accuracy-vs-time "
-                         "comparison of the steppers; bulk: only the bulk-layer variant; each as its own JSON line")
+                         "comparison of the steppers; bulk: only the bulk-layer variant; fp32, wide-grad, n199, "
+                         "n521: only that variant; each as its own JSON line")
     ap.add_argument("--structures", type=int, default=1, help="structures in the batch (128 angles each)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-per-angle", action="store_true",
@@ -780,6 +850,9 @@ def main():
         return
     if args.mode == "n199":
         print(json.dumps({"n199_forward": n199_forward(steps=args.steps, cpu=not args.no_cpu)}))
+        return
+    if args.mode == "n521":
+        print(json.dumps({"n521_single_angle": n521_single(steps=args.steps, cpu=not args.no_cpu)}))
         return
     if args.mode == "uneven":
         print(json.dumps({"uneven_n_forward": uneven_forward(max(1, args.uneven_structures), steps=args.steps,
@@ -933,6 +1006,7 @@ def main():
         variants["fp32_stages_forward"] = fp32_stages()
         variants["gradient_n121"] = wide_gradient()
         variants["n199_forward"] = n199_forward(cpu=not args.no_cpu)
+        variants["n521_single_angle"] = n521_single(cpu=not args.no_cpu)
 
     rec = {
         "metric": "rocking-curve points (structure x angle)/s at N=61 FP64; " +

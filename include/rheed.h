@@ -93,13 +93,18 @@ typedef enum { RHEED_INTENSITY_FLUX = 0, RHEED_INTENSITY_PAPER = 1 } rheed_conve
  * memory owned by the plan.  Both have the adjoint (RK steppers, FP64).
  * Structures with 128 < N <= 256 run on a third kernel, also with the state
  * in plan-owned memory, which streams the rows of its eliminations through
- * that memory: RK steppers, FP64, with the adjoint. */
-#define RHEED_MAX_BEAMS 256
+ * that memory: RK steppers, FP64, with the adjoint.  Structures with
+ * 256 < N <= 576 (the paper's single-angle size, Sec. 4) run on a fourth,
+ * each pair on a cooperative group of workgroups that step its column blocks
+ * side by side: RK steppers, FP64, forward only, at most as many pairs per
+ * plan as the device holds such workgroups at once. */
+#define RHEED_MAX_BEAMS 576
 /* Largest potential-table row (rod differences) for N <= 64, for
- * 64 < N <= 128 and for 128 < N <= 256. */
+ * 64 < N <= 128, for 128 < N <= 256 and for 256 < N <= 576. */
 #define RHEED_MAX_BOX 300
 #define RHEED_MAX_BOX_LARGE 1024
 #define RHEED_MAX_BOX_XL 1536
+#define RHEED_MAX_BOX_XXL 4096
 
 /* One slab.  Rod indices are on the reciprocal basis b1, b2:
  * k_j = h_j b1 + k_j b2 (Sec. 2.1, the reciprocal rods k_j with k_1 = 0). */
@@ -174,9 +179,11 @@ typedef struct {
                                 launch over a queue of pairs of both kinds (N <= 64 and N > 64) */
   int32_t xl_pairs;          /* pairs of structures with N > 128 */
   int32_t xl_slots;          /* resident workgroups (state slots) of the kernel for N > 128 */
-  int32_t xl_group;          /* workgroups per pair with N > 128: 1, or (a batch too small to fill the
-                                device, layout not WHOLE) a cooperative group stepping the pair's
-                                column blocks side by side */
+  int32_t xl_group;          /* workgroups per pair with 128 < N <= 256: 1, or (a batch too small to
+                                fill the device, layout not WHOLE) a cooperative group stepping the
+                                pair's column blocks side by side */
+  int32_t xxl_pairs;         /* pairs of structures with N > 256 (forward only) */
+  int32_t xxl_group;         /* workgroups of the cooperative group of each of them */
 } rheed_plan_info;
 
 /* Vacuum wavenumber gamma (1/A) and the coefficient kappa (1/(A^2 V)) of the

@@ -18,10 +18,11 @@ RHEED_INTENSITY_FLUX, RHEED_INTENSITY_PAPER = 0, 1
 RHEED_PAIR_OK, RHEED_PAIR_SINGULAR, RHEED_PAIR_NONFINITE, RHEED_PAIR_SYNC, RHEED_PAIR_BREAKDOWN = 0, 1, 2, 3, 4
 RHEED_LAYOUT_AUTO, RHEED_LAYOUT_WHOLE, RHEED_LAYOUT_SPLIT = 0, 1, 2
 RHEED_STAGES_FP64, RHEED_STAGES_FP32 = 0, 1
-RHEED_MAX_BEAMS = 256
+RHEED_MAX_BEAMS = 576
 RHEED_MAX_BOX = 300
 RHEED_MAX_BOX_LARGE = 1024
 RHEED_MAX_BOX_XL = 1536
+RHEED_MAX_BOX_XXL = 4096
 RHEED_NOALLOC_MAX_ATOMS = 4096
 
 
@@ -74,6 +75,8 @@ class PlanInfo(C.Structure):
         ("xl_pairs", C.c_int32),
         ("xl_slots", C.c_int32),
         ("xl_group", C.c_int32),
+        ("xxl_pairs", C.c_int32),
+        ("xxl_group", C.c_int32),
     ]
 
 

@@ -79,6 +79,14 @@ struct rheed_plan_s {
   char* d_xg_pair = nullptr;
   char* d_xg_wg = nullptr;
   unsigned* d_xg_cnt = nullptr;
+  // pairs of structures with 256 < N <= 576 (forward only): a group launch of
+  // xxl_group workgroups per pair
+  std::vector<int> xxl_pairs;
+  int* d_xxl_pairs = nullptr;
+  int xxl_group = 1;
+  char* d_xxg_pair = nullptr;
+  char* d_xxg_wg = nullptr;
+  unsigned* d_xxg_cnt = nullptr;
   int* d_small_pairs = nullptr;  // only when both kinds are present
   int* d_large_pairs = nullptr;  // in cost order (dearest first)
   int* d_large_plain = nullptr;  // in pair order
@@ -275,7 +283,8 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     d.hd = hmax - hmin;
     d.kd = kmax - kmin;
     d.box = (2 * d.hd + 1) * (2 * d.kd + 1);
-    const int box_max = (st.n_beams <= NP) ? MAXBOX : (st.n_beams <= NL) ? MAXBOXL : MAXBOXX;
+    const int box_max = (st.n_beams <= NP) ? MAXBOX : (st.n_beams <= NL) ? MAXBOXL : (st.n_beams <= NX) ? MAXBOXX
+                                                                                                     : MAXBOXXX;
     if (d.box > box_max) {
       delete P;
       return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) + ": rod-difference table row of " +
@@ -288,7 +297,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     // count of the structure's kernels (64 or 128)
     {
       const int W = 2 * d.kd + 1;
-      const int Wp = st.n_beams <= NP ? NP : st.n_beams <= NL ? NL : NX;
+      const int Wp = st.n_beams <= NP ? NP : st.n_beams <= NL ? NL : st.n_beams <= NX ? NX : NXX;
       std::vector<std::vector<int>> lists(d.box);
       for (int j = 0; j < st.n_beams; ++j)
         for (int k = 0; k < st.n_beams; ++k) {
@@ -348,7 +357,8 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
     P->max_nodes = std::max(P->max_nodes, d.n_nodes);
     P->n_atoms_total += d.n_atoms;
     for (int a = 0; a < angles_per_struct[s]; ++a) {
-      ((st.n_beams <= NP) ? P->small_pairs : (st.n_beams <= NL) ? P->large_pairs : P->xl_pairs)
+      ((st.n_beams <= NP) ? P->small_pairs : (st.n_beams <= NL) ? P->large_pairs
+                                           : (st.n_beams <= NX) ? P->xl_pairs : P->xxl_pairs)
           .push_back(P->n_pairs + a);
       P->pair_struct.push_back(s);
     }
@@ -436,7 +446,8 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
   }
   // the adjoint and its state saving: FP64, the RK steppers for every N and
   // the splitting methods for N <= 64
-  if ((P->splitting && !P->large_pairs.empty()) || opts->stage_precision != RHEED_STAGES_FP64) {
+  if ((P->splitting && !P->large_pairs.empty()) || opts->stage_precision != RHEED_STAGES_FP64 ||
+      !P->xxl_pairs.empty()) {
     P->fwd_ws = 0;
     P->bwd_ws = 0;
   }
@@ -457,7 +468,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       P->large_slots = std::min(n_large, slots);
       P->scratch_slots = P->large_slots;
       P->queue_ok = n_small > 0 && !P->splitting && opts->stage_precision == RHEED_STAGES_FP64 &&
-                    opts->layout != RHEED_LAYOUT_SPLIT && P->xl_pairs.empty();
+                    opts->layout != RHEED_LAYOUT_SPLIT && P->xl_pairs.empty() && P->xxl_pairs.empty();
       if (P->queue_ok) {
         const int qs = forward_queue_slots(dev);
         P->queue_ok = qs > 0;
@@ -481,6 +492,19 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       const int cap = opts->layout != RHEED_LAYOUT_WHOLE ? forward_xl_group_max_workgroups(dev) : 0;
       const int g = std::min((maxn + 15) / 16, cap / n_xl);
       P->xl_group = g >= 2 ? g : 1;
+    }
+    if (!P->xxl_pairs.empty()) {
+      // every pair on a cooperative group: all of them resident at once
+      const int cap = have_dev ? forward_xxl_group_max_workgroups(dev) : 0;
+      const int n_xxl = (int)P->xxl_pairs.size();
+      if (cap < n_xxl) {
+        delete P;
+        return fail(RHEED_E_UNSUPPORTED, "structures with N > 256 run at most " + std::to_string(cap) +
+                                             " pairs per plan on this device (" + std::to_string(n_xxl) + " given)");
+      }
+      int maxn = 0;
+      for (int q : P->xxl_pairs) maxn = std::max(maxn, P->hs[P->pair_struct[q]].n_beams);
+      P->xxl_group = std::max(1, std::min((maxn + 15) / 16, cap / n_xxl));
     }
     if (opts->layout == RHEED_LAYOUT_SPLIT && !P->split && n_small > 0) {
       const int mx = P->split_max;
@@ -510,6 +534,14 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
        (e = hipMalloc(&P->d_xg_wg, (size_t)XG_WG_BYTES * P->xl_group * P->xl_pairs.size())) != hipSuccess) ||
       (P->xl_group > 1 &&
        (e = hipMalloc(&P->d_xg_cnt, sizeof(unsigned) * 16 * P->xl_pairs.size())) != hipSuccess) ||
+      (!P->xxl_pairs.empty() &&
+       (e = hipMalloc(&P->d_xxl_pairs, sizeof(int) * P->xxl_pairs.size())) != hipSuccess) ||
+      (!P->xxl_pairs.empty() &&
+       (e = hipMalloc(&P->d_xxg_pair, (size_t)XXG_PAIR_BYTES * P->xxl_pairs.size())) != hipSuccess) ||
+      (!P->xxl_pairs.empty() &&
+       (e = hipMalloc(&P->d_xxg_wg, (size_t)XXG_WG_BYTES * P->xxl_group * P->xxl_pairs.size())) != hipSuccess) ||
+      (!P->xxl_pairs.empty() &&
+       (e = hipMalloc(&P->d_xxg_cnt, sizeof(unsigned) * 16 * P->xxl_pairs.size())) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_large_pairs, sizeof(int) * n_large)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_large_plain, sizeof(int) * n_large)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_lscratch, (size_t)LSLOT_BYTES * P->scratch_slots)) != hipSuccess) ||
@@ -534,6 +566,8 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
                                           hipMemcpyHostToDevice)) != hipSuccess) ||
       (P->d_xl_pairs && (e = hipMemcpy(P->d_xl_pairs, P->xl_pairs.data(), sizeof(int) * P->xl_pairs.size(),
                                         hipMemcpyHostToDevice)) != hipSuccess) ||
+      (P->d_xxl_pairs && (e = hipMemcpy(P->d_xxl_pairs, P->xxl_pairs.data(), sizeof(int) * P->xxl_pairs.size(),
+                                         hipMemcpyHostToDevice)) != hipSuccess) ||
       (P->d_large_pairs && (e = hipMemcpy(P->d_large_pairs, P->large_pairs.data(), sizeof(int) * n_large,
                                           hipMemcpyHostToDevice)) != hipSuccess) ||
       (P->d_large_plain && (e = hipMemcpy(P->d_large_plain, P->large_plain.data(), sizeof(int) * n_large,
@@ -576,6 +610,10 @@ rheed_status rheed_plan_destroy(rheed_plan_t P) {
   if (P->d_xg_pair) (void)hipFree(P->d_xg_pair);
   if (P->d_xg_wg) (void)hipFree(P->d_xg_wg);
   if (P->d_xg_cnt) (void)hipFree(P->d_xg_cnt);
+  if (P->d_xxl_pairs) (void)hipFree(P->d_xxl_pairs);
+  if (P->d_xxg_pair) (void)hipFree(P->d_xxg_pair);
+  if (P->d_xxg_wg) (void)hipFree(P->d_xxg_wg);
+  if (P->d_xxg_cnt) (void)hipFree(P->d_xxg_cnt);
   if (P->d_queue_order) (void)hipFree(P->d_queue_order);
   if (P->d_queue_counter) (void)hipFree(P->d_queue_counter);
   delete P;
@@ -596,10 +634,12 @@ rheed_status rheed_plan_get_info(rheed_plan_t P, rheed_plan_info* info) {
   info->split_max_pairs = P->split_max;
   info->large_pairs = (int32_t)P->large_pairs.size();
   info->large_slots = P->large_slots;
-  info->bulk_workspace = (P->large_pairs.empty() && P->xl_pairs.empty()) ? bulk_extra(P) : 0;
+  info->bulk_workspace = (P->large_pairs.empty() && P->xl_pairs.empty() && P->xxl_pairs.empty()) ? bulk_extra(P) : 0;
   info->xl_pairs = (int32_t)P->xl_pairs.size();
   info->xl_slots = P->xl_slots;
   info->xl_group = P->xl_group;
+  info->xxl_pairs = (int32_t)P->xxl_pairs.size();
+  info->xxl_group = P->xxl_group;
   info->queue = (P->use_queue && P->queue_ok) ? 1 : 0;
   return RHEED_OK;
 }
@@ -689,10 +729,10 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
                           const void* y_bottom, const int* skip, bool final_only = false) {
   if (!P || !U_tables || !angles || !intensity || !pair_status) return fail(RHEED_E_INVALID, "forward: null argument");
   const bool f32 = P->opts.stage_precision == RHEED_STAGES_FP32;
-  if (workspace && ((P->splitting && !P->large_pairs.empty()) || f32))
-    return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs FP64 stages, and with a "
-                                     "splitting stepper every structure to have N <= 64");
-  if (y_bottom && (!P->large_pairs.empty() || !P->xl_pairs.empty()))
+  if (workspace && ((P->splitting && !P->large_pairs.empty()) || f32 || !P->xxl_pairs.empty()))
+    return fail(RHEED_E_UNSUPPORTED, "forward: keeping states for the adjoint needs FP64 stages, every structure "
+                                     "to have N <= 256, and with a splitting stepper N <= 64");
+  if (y_bottom && (!P->large_pairs.empty() || !P->xl_pairs.empty() || !P->xxl_pairs.empty()))
     return fail(RHEED_E_UNSUPPORTED, "forward: the bulk start needs every structure to have N <= 64");
   if (y_bottom && (P->splitting || f32))
     return fail(RHEED_E_UNSUPPORTED, "forward: the bulk start needs an RK stepper with FP64 stages");
@@ -783,6 +823,21 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
     }
     if (e != hipSuccess) return hip_fail(e, "forward launch (N > 128)");
   }
+  if (!P->xxl_pairs.empty()) {
+    LargeArgs xa{};
+    xa.f = a;
+    xa.f.pair_list = P->d_xxl_pairs;
+    xa.f.n_pairs = (int)P->xxl_pairs.size();
+    xa.f.ws = nullptr;
+    xa.f.xch = nullptr;
+    XlGroup xg{};
+    xg.pair_mem = P->d_xxg_pair;
+    xg.wg_mem = P->d_xxg_wg;
+    xg.counters = P->d_xxg_cnt;
+    xg.group = P->xxl_group;
+    e = launch_forward_xxl_group((int)P->opts.stepper, xa, xg, st);
+    if (e != hipSuccess) return hip_fail(e, "forward launch (N > 256)");
+  }
   return RHEED_OK;
 }
 
@@ -800,7 +855,8 @@ rheed_status rheed_forward_bulk(rheed_plan_t P, const void* U_tables, const doub
                                 double* intensity, void* rho, int32_t* pair_status, int32_t* n_rhst, void* workspace,
                                 size_t ws_bytes, void* stream) {
   if (!P || !y_bottom) return fail(RHEED_E_INVALID, "forward_bulk: null argument");
-  if (!P->large_pairs.empty() || !P->xl_pairs.empty() || P->splitting || P->opts.stage_precision != RHEED_STAGES_FP64)
+  if (!P->large_pairs.empty() || !P->xl_pairs.empty() || !P->xxl_pairs.empty() || P->splitting ||
+      P->opts.stage_precision != RHEED_STAGES_FP64)
     return fail(RHEED_E_UNSUPPORTED, "forward_bulk: needs an RK stepper with FP64 stages and every structure to have N <= 64");
   return forward_impl(P, U_tables, angles, intensity, rho, pair_status, n_rhst, workspace, ws_bytes, stream,
                       y_bottom, nullptr);
@@ -813,7 +869,8 @@ rheed_status rheed_bulk_reflection(rheed_plan_t P, const void* U_tables, const d
     return fail(RHEED_E_INVALID, "bulk_reflection: null argument");
   if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(RHEED_E_INVALID, "bulk_reflection: tol must be finite and >= 0");
   if (max_layers < 1) return fail(RHEED_E_INVALID, "bulk_reflection: max_layers must be >= 1");
-  if (!P->large_pairs.empty() || !P->xl_pairs.empty() || P->splitting || P->opts.stage_precision != RHEED_STAGES_FP64)
+  if (!P->large_pairs.empty() || !P->xl_pairs.empty() || !P->xxl_pairs.empty() || P->splitting ||
+      P->opts.stage_precision != RHEED_STAGES_FP64)
     return fail(RHEED_E_UNSUPPORTED, "bulk_reflection: needs an RK stepper with FP64 stages and every structure to have N <= 64");
   const size_t need = P->fwd_ws + bulk_extra(P);
   if (ws_bytes < need)
@@ -945,9 +1002,10 @@ rheed_status rheed_backward(rheed_plan_t P, const void* U_tables, const double* 
                             void* dL_dU, void* workspace, size_t ws_bytes, void* stream) {
   if (!P || !U_tables || !angles || !dL_dI || !dL_dU || !workspace)
     return fail(RHEED_E_INVALID, "backward: null argument");
-  if ((P->splitting && !P->large_pairs.empty()) || P->opts.stage_precision != RHEED_STAGES_FP64)
-    return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs FP64 stages, and with a splitting stepper "
-                                     "every structure to have N <= 64");
+  if ((P->splitting && !P->large_pairs.empty()) || P->opts.stage_precision != RHEED_STAGES_FP64 ||
+      !P->xxl_pairs.empty())
+    return fail(RHEED_E_UNSUPPORTED, "backward: the adjoint needs FP64 stages, every structure to have N <= 256, "
+                                     "and with a splitting stepper N <= 64");
   if (ws_bytes < P->fwd_ws + P->bwd_ws)
     return fail(RHEED_E_INVALID, "backward: workspace of " + std::to_string(ws_bytes) + " bytes < " +
                                      std::to_string(P->fwd_ws + P->bwd_ws));

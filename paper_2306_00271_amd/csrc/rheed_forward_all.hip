@@ -1,13 +1,16 @@
 // The translation unit of every forward kernel: the kernels for N <= 64
-// (rheed_forward.hip), the kernel for 64 < N <= 128 (rheed_forward_large.hip),
-// and forward_queue_kernel, one persistent launch over a batch that mixes
-// both (the batching of Sec. 3.5 over (structure, angle) pairs, here of
-// uneven beam counts).  They are one unit so that the LDS of the two pair
+// (rheed_forward.hip), the kernel for 64 < N <= 128
+// (rheed_forward_large.hip), those for 128 < N <= 256 and 256 < N <= 576
+// (rheed_forward_xl.hip, rheed_forward_xxl.hip), and forward_queue_kernel,
+// one persistent launch over a batch that mixes N <= 64 and 64 < N <= 128
+// (the batching of Sec. 3.5 over (structure, angle) pairs, here of uneven
+// beam counts).  They are one unit so that the LDS of the two pair
 // paths is one allocation: a workgroup of forward_queue_kernel runs pairs of
 // either kind one after another in the same LDS.
 #include "rheed_forward.hip"
 #include "rheed_forward_large.hip"
 #include "rheed_forward_xl.hip"
+#include "rheed_forward_xxl.hip"
 
 namespace rheed {
 

@@ -56,8 +56,6 @@ constexpr int XEB = 64;           // rows per elimination block
 constexpr int XEM = XEB / XW;     // rows per wave of an elimination block
 constexpr int XS = NX / 64;       // columns per lane in the eliminations
 
-static_assert(XT >= NX, "the reflection's per-row epilogue has a thread per beam");
-
 struct XLds {
   double2 xb[NX * XCB];           // stage input of a column block; the pivot rows of the eliminations
   double2 tb[2][MAXBOXX + 1];     // node tables of two stages; entry `box` of each stays 0
@@ -235,15 +233,51 @@ __device__ __noinline__ void xl_slice(double2* __restrict__ cg, double2* __restr
   __syncthreads();
 }
 
+// The phases after the stage products (badness, elimination, replay,
+// reflection, group barrier) are shared with the kernel for wider
+// structures; a width configuration gives them the padded beam count, the
+// rows per wave of an elimination block, the LDS and the layout of a pair's
+// memory.
+struct XCfg {
+  static constexpr int NXT = NX;
+  static constexpr int XEMT = XEM;
+  static constexpr int IDXB = 8;        // bits of the column index in a pivot key
+  static constexpr int TSLOTS = 2;      // node-table slots in LDS
+  static constexpr long long SYNC_TICKS = XCH_TICKS;  // a group barrier's wait gives up after this
+  static constexpr int SYNC_SPIN = XCH_SPIN;          // or after this many polls
+  static constexpr long long PAIR_C = XSLOT_C, PAIR_D = XSLOT_D, PAIR_F = XSLOT_F, PAIR_PIV = XSLOT_G;
+  static constexpr long long PAIR_BYTES = XG_PAIR_BYTES;
+  static constexpr long long WG_PART = XG_STAGE_BYTES;  // row-sum partials after the stage products
+  static constexpr long long WG_BYTES = XG_WG_BYTES;
+  static __device__ __forceinline__ XLds& lds() { return xl_lds; }
+  using Base = int[2];
+  // table index of U_{ik} = u_{g_i - g_k} is base_i - off_k for the A-operand
+  // rows of the thread's two tiles
+  static __device__ __forceinline__ void bases(Base& base, int hd, int kd, int w, int lane) {
+    const int Wd = 2 * kd + 1;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int i = 32 * w + 16 * t + (lane & 15);
+      base[t] = (xl_lds.bhk[i][0] + hd) * Wd + (xl_lds.bhk[i][1] + kd);
+    }
+  }
+  template <int STEPPER>
+  static __device__ __forceinline__ void slice(double2* cg, double2* dg, double2* gm, const double2* Us, int nb,
+                                               int box, double h, int N, const Base& base, int cb0, int cbs) {
+    xl_slice<STEPPER>(cg, dg, gm, Us, nb, box, h, N, base, cb0, cbs);
+  }
+};
+
+
 // Rows m < R of z: column j <- column j - f_j column pc, pc = 64 HF + pl
 // (the pivot column's quarter is wave-uniform, so it selects code).
-template <int HF, int R>
-__device__ __forceinline__ void xl_col_update(double2 (&z)[R][XS], int pl, const double2 (&f)[XS]) {
+template <int HF, int R, int XSN>
+__device__ __forceinline__ void xl_col_update(double2 (&z)[R][XSN], int pl, const double2 (&f)[XSN]) {
 #pragma unroll
   for (int m = 0; m < R; ++m) {
     const double2 zp = make_double2(readlane_f64(z[m][HF].x, pl), readlane_f64(z[m][HF].y, pl));
 #pragma unroll
-    for (int q = 0; q < XS; ++q) {
+    for (int q = 0; q < XSN; ++q) {
       z[m][q].x = fma(-f[q].x, zp.x, z[m][q].x);
       z[m][q].x = fma(f[q].y, zp.y, z[m][q].x);
       z[m][q].y = fma(-f[q].x, zp.y, z[m][q].y);
@@ -253,26 +287,42 @@ __device__ __forceinline__ void xl_col_update(double2 (&z)[R][XS], int pl, const
   }
 }
 
-template <int R>
-__device__ __forceinline__ void xl_update(double2 (&z)[R][XS], int pc, const double2 (&f)[XS]) {
+template <int R, int XSN, int H>
+__device__ __forceinline__ void xl_update_from(double2 (&z)[R][XSN], int hf, int pl, const double2 (&f)[XSN]) {
+  if constexpr (H + 1 == XSN) {
+    xl_col_update<H, R, XSN>(z, pl, f);
+  } else {
+    if (hf == H) xl_col_update<H, R, XSN>(z, pl, f);
+    else xl_update_from<R, XSN, H + 1>(z, hf, pl, f);
+  }
+}
+
+template <int R, int XSN>
+__device__ __forceinline__ void xl_update(double2 (&z)[R][XSN], int pc, const double2 (&f)[XSN]) {
   const int hf = pc >> 6, pl = pc & 63;
-  switch (hf) {
-    case 0: xl_col_update<0, R>(z, pl, f); break;
-    case 1: xl_col_update<1, R>(z, pl, f); break;
-    case 2: xl_col_update<2, R>(z, pl, f); break;
-    default: xl_col_update<3, R>(z, pl, f); break;
+  if constexpr (XSN == 4) {
+    switch (hf) {
+      case 0: xl_col_update<0, R, 4>(z, pl, f); break;
+      case 1: xl_col_update<1, R, 4>(z, pl, f); break;
+      case 2: xl_col_update<2, R, 4>(z, pl, f); break;
+      default: xl_col_update<3, R, 4>(z, pl, f); break;
+    }
+  } else {
+    xl_update_from<R, XSN, 0>(z, hf, pl, f);
   }
 }
 
 // The recorded column operations of steps [0, k1) on the rows in z.
-template <int R>
-__device__ __forceinline__ void xl_replay(double2 (&z)[R][XS], int k1, int lane, const double2* __restrict__ frec) {
+template <class C, int R>
+__device__ __forceinline__ void xl_replay(double2 (&z)[R][C::NXT / 64], int k1, int lane,
+                                          const double2* __restrict__ frec) {
+  constexpr int NXT = C::NXT, XST = NXT / 64;
 #pragma unroll 1
   for (int k = 0; k < k1; ++k) {
-    double2 f[XS];
+    double2 f[XST];
 #pragma unroll
-    for (int q = 0; q < XS; ++q) f[q] = gld(&frec[k * NX + 64 * q + lane]);
-    xl_update<R>(z, __builtin_amdgcn_readfirstlane(xl_lds.pcrec[k]), f);
+    for (int q = 0; q < XST; ++q) f[q] = gld(&frec[k * NXT + 64 * q + lane]);
+    xl_update<R, XST>(z, __builtin_amdgcn_readfirstlane(C::lds().pcrec[k]), f);
   }
 }
 
@@ -286,20 +336,26 @@ __device__ __forceinline__ void xl_replay(double2 (&z)[R][XS], int k1, int lane,
 // subtracts f_j column pc from every column j of the block's rows.  Row
 // k + 1 reaches the other waves through LDS.  s.pos gets the step at which
 // each column was the pivot (its own index for columns >= n).
+template <class C>
 __device__ __noinline__ void xl_elim_record(const double2* __restrict__ cg, const double2* __restrict__ dg,
                                             double2* __restrict__ frec, int N, int which) {
-  XLds& s = xl_lds;
+  constexpr int NXT = C::NXT, XST = NXT / 64, XEMT = C::XEMT, XEBT = XW * XEMT;
+  constexpr unsigned IDXM = (1u << C::IDXB) - 1u;
+  static_assert(NXT <= (1 << C::IDXB), "pivot keys hold every column index");
+  auto& s = C::lds();
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int n = __builtin_amdgcn_readfirstlane(N);
   const int wu = __builtin_amdgcn_readfirstlane(w);
   const bool refl = __builtin_amdgcn_readfirstlane(which) != 0;
-  unsigned long long um[XS] = {0, 0, 0, 0};  // used columns (the same in every wave)
+  unsigned long long um[XST];  // used columns (the same in every wave)
+#pragma unroll
+  for (int q = 0; q < XST; ++q) um[q] = 0;
   double2* rowbuf = s.xb;
 #pragma unroll 1
-  for (int k0 = 0; k0 < n; k0 += XEB) {
-    double2 z[XEM][XS];
+  for (int k0 = 0; k0 < n; k0 += XEBT) {
+    double2 z[XEMT][XST];
 #pragma unroll
-    for (int m = 0; m < XEM; ++m) {
+    for (int m = 0; m < XEMT; ++m) {
       const int row = k0 + wu + XW * m;
       double gr = 0.0, gi = 0.0;
       if (refl && row < n) {
@@ -308,13 +364,13 @@ __device__ __noinline__ void xl_elim_record(const double2* __restrict__ cg, cons
         gi = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
       }
 #pragma unroll
-      for (int q = 0; q < XS; ++q) {
+      for (int q = 0; q < XST; ++q) {
         const int c = 64 * q + lane;
         double2 v = make_double2(0.0, 0.0);
         if (row < n) {
-          const double2 cv = gld(&cg[row * NX + c]);
+          const double2 cv = gld(&cg[row * NXT + c]);
           if (refl) {
-            const double2 pv = gld(&dg[row * NX + c]);
+            const double2 pv = gld(&dg[row * NXT + c]);
             v = make_double2(gr * cv.x - gi * cv.y + pv.y, gr * cv.y + gi * cv.x - pv.x);
           } else {
             v = cv;
@@ -323,105 +379,107 @@ __device__ __noinline__ void xl_elim_record(const double2* __restrict__ cg, cons
         z[m][q] = v;
       }
     }
-    xl_replay<XEM>(z, k0, lane, frec);
-    const int k1 = n < k0 + XEB ? n : k0 + XEB;
+    xl_replay<C, XEMT>(z, k0, lane, frec);
+    const int k1 = n < k0 + XEBT ? n : k0 + XEBT;
     __syncthreads();  // rowbuf aliases the stage buffer and the previous block's last row
     if (wu == 0) {
 #pragma unroll
-      for (int q = 0; q < XS; ++q) rowbuf[64 * q + lane] = z[0][q];
+      for (int q = 0; q < XST; ++q) rowbuf[64 * q + lane] = z[0][q];
     }
 #pragma unroll 1
     for (int k = k0; k < k1; ++k) {
       const int slot = k & 1;
       __syncthreads();
-      double2 v[XS];
+      double2 v[XST];
       unsigned key = 0;
 #pragma unroll
-      for (int q = 0; q < XS; ++q) {
-        v[q] = rowbuf[slot * NX + 64 * q + lane];
+      for (int q = 0; q < XST; ++q) {
+        v[q] = rowbuf[slot * NXT + 64 * q + lane];
         const int c = 64 * q + lane;
         if (!((um[q] >> lane) & 1ull) && c < n) {
           const double m2 = v[q].x * v[q].x + v[q].y * v[q].y;
           const unsigned kq =
-              ((unsigned)(((unsigned long long)__double_as_longlong(m2)) >> 32) & ~255u) | (unsigned)(255 - c);
+              ((unsigned)(((unsigned long long)__double_as_longlong(m2)) >> 32) & ~IDXM) | (IDXM - (unsigned)c);
           key = kq > key ? kq : key;
         }
       }
       key = wave_max_u32(key);
-      if ((key >> 8) == 0 && tid == 0) s.flag_singular = 1;
-      const int pc = 255 - (int)(key & 255);
+      if ((key >> C::IDXB) == 0 && tid == 0) s.flag_singular = 1;
+      const int pc = (int)(IDXM - (key & IDXM));
       const int hf = pc >> 6, pl = pc & 63;
 #pragma unroll
-      for (int q = 0; q < XS; ++q)
+      for (int q = 0; q < XST; ++q)
         if (q == hf) um[q] |= 1ull << pl;
       double2 vs = v[0];
 #pragma unroll
-      for (int q = 1; q < XS; ++q)
+      for (int q = 1; q < XST; ++q)
         if (q == hf) vs = v[q];
       const double2 piv = make_double2(readlane_f64(vs.x, pl), readlane_f64(vs.y, pl));
       const double inv = 1.0 / (piv.x * piv.x + piv.y * piv.y);
       const double2 ip = make_double2(piv.x * inv, -piv.y * inv);
-      double2 f[XS];
+      double2 f[XST];
 #pragma unroll
-      for (int q = 0; q < XS; ++q) {
+      for (int q = 0; q < XST; ++q) {
         f[q] = make_double2(v[q].x * ip.x - v[q].y * ip.y, v[q].x * ip.y + v[q].y * ip.x);
         if (q == hf && lane == pl) f[q] = make_double2(1.0 - ip.x, -ip.y);
       }
       if (wu == 0) {
 #pragma unroll
-        for (int q = 0; q < XS; ++q) gst(&frec[k * NX + 64 * q + lane], f[q]);
+        for (int q = 0; q < XST; ++q) gst(&frec[k * NXT + 64 * q + lane], f[q]);
         if (lane == 0) s.pcrec[k] = pc;
       }
-      xl_update<XEM>(z, pc, f);
+      xl_update<XEMT, XST>(z, pc, f);
       // row k + 1 of this block: wave (k + 1 - k0) % 8, register (k + 1 - k0) / 8
       const int nx = k + 1 - k0;
       if (k + 1 < k1 && wu == (nx & (XW - 1))) {
         const int mr = nx / XW;
 #pragma unroll
-        for (int m = 0; m < XEM; ++m)
+        for (int m = 0; m < XEMT; ++m)
           if (m == mr) {
 #pragma unroll
-            for (int q = 0; q < XS; ++q) rowbuf[(slot ^ 1) * NX + 64 * q + lane] = z[m][q];
+            for (int q = 0; q < XST; ++q) rowbuf[(slot ^ 1) * NXT + 64 * q + lane] = z[m][q];
           }
       }
     }
   }
   // the multipliers and pivot list are read back by this workgroup only
   __syncthreads();
-  if (tid < NX) s.pos[tid] = tid;
+  for (int j = tid; j < NXT; j += XT) s.pos[j] = j;
   __syncthreads();
-  if (tid < n) s.pos[s.pcrec[tid]] = tid;
+  for (int j = tid; j < n; j += XT) s.pos[s.pcrec[j]] = j;
   __syncthreads();
 }
 
 // P <- P Q^{-1} after xl_elim_record(which = 0): the recorded operations on
 // the rows of P, 64 at a time (row blocks b0, b0 + bs, ...), each column put
 // at its pivot step; c <- I on the same rows.
+template <class C>
 __device__ __noinline__ void xl_replay_p(double2* __restrict__ cg, double2* __restrict__ dg,
                                          const double2* __restrict__ frec, int N, int b0, int bs) {
-  XLds& s = xl_lds;
+  constexpr int NXT = C::NXT, XST = NXT / 64, XEMT = C::XEMT, XEBT = XW * XEMT;
+  auto& s = C::lds();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int n = __builtin_amdgcn_readfirstlane(N);
-  int pq[XS];
+  int pq[XST];
 #pragma unroll
-  for (int q = 0; q < XS; ++q) pq[q] = s.pos[64 * q + lane];
+  for (int q = 0; q < XST; ++q) pq[q] = s.pos[64 * q + lane];
   // rows >= n are zero rows of P and unit rows of c, which the
   // transformation leaves as they are
 #pragma unroll 1
-  for (int r0 = XEB * b0; r0 < n; r0 += XEB * bs) {
-    double2 z[XEM][XS];
+  for (int r0 = XEBT * b0; r0 < n; r0 += XEBT * bs) {
+    double2 z[XEMT][XST];
 #pragma unroll
-    for (int m = 0; m < XEM; ++m)
+    for (int m = 0; m < XEMT; ++m)
 #pragma unroll
-      for (int q = 0; q < XS; ++q) z[m][q] = gld(&dg[(r0 + w + XW * m) * NX + 64 * q + lane]);
-    xl_replay<XEM>(z, n, lane, frec);
+      for (int q = 0; q < XST; ++q) z[m][q] = gld(&dg[(r0 + w + XW * m) * NXT + 64 * q + lane]);
+    xl_replay<C, XEMT>(z, n, lane, frec);
 #pragma unroll
-    for (int m = 0; m < XEM; ++m) {
+    for (int m = 0; m < XEMT; ++m) {
       const int row = r0 + w + XW * m;
 #pragma unroll
-      for (int q = 0; q < XS; ++q) {
-        gst(&dg[row * NX + pq[q]], z[m][q]);
-        gst(&cg[row * NX + 64 * q + lane], make_double2(row == 64 * q + lane ? 1.0 : 0.0, 0.0));
+      for (int q = 0; q < XST; ++q) {
+        gst(&dg[row * NXT + pq[q]], z[m][q]);
+        gst(&cg[row * NXT + 64 * q + lane], make_double2(row == 64 * q + lane ? 1.0 : 0.0, 0.0));
       }
     }
   }
@@ -431,20 +489,23 @@ __device__ __noinline__ void xl_replay_p(double2* __restrict__ cg, double2* __re
 // Barrier of the G workgroups of one pair in a group launch: each raises the
 // pair's counter (an agent-scope release, so its stores are written back
 // first) and waits until all have reached `target` (G times the barriers so
-// far), then acquires.  A wait gives up after XCH_SPIN polls or XCH_TICKS of
-// the constant-rate clock, sets s.sync_fail and the pair's failure word, and
-// the workgroup stops waiting from then on (every wait is bounded).
+// far), then acquires.  A wait gives up after C::SYNC_SPIN polls or
+// C::SYNC_TICKS of the constant-rate clock (about 20 ms here, 200 ms for the
+// wider kernel, whose eliminations are longer), sets s.sync_fail and the
+// pair's failure word, and the workgroup stops waiting from then on (every
+// wait is bounded).
+template <class C>
 __device__ __forceinline__ void xl_group_sync(unsigned* cnt, unsigned target, unsigned* fail_word) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are issued and complete
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (!xl_lds.sync_fail) {
+    if (!C::lds().sync_fail) {
       const long long t0 = wall_clock64();
       int it = 0;
       while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (++it > XCH_SPIN || wall_clock64() - t0 > XCH_TICKS) {
-          xl_lds.sync_fail = 1;
+        if (++it > C::SYNC_SPIN || wall_clock64() - t0 > C::SYNC_TICKS) {
+          C::lds().sync_fail = 1;
           __hip_atomic_store(fail_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           break;
         }
@@ -475,7 +536,7 @@ __device__ __noinline__ void xl_replay_identity(double2* __restrict__ out, const
     for (int m = 0; m < XEM; ++m)
 #pragma unroll
       for (int q = 0; q < XS; ++q) z[m][q] = make_double2(r0 + w + XW * m == 64 * q + lane ? 1.0 : 0.0, 0.0);
-    if (r0 < n) xl_replay<XEM>(z, n, lane, frec);
+    if (r0 < n) xl_replay<XCfg, XEM>(z, n, lane, frec);
 #pragma unroll
     for (int m = 0; m < XEM; ++m) {
       const int row = r0 + w + XW * m;
@@ -521,20 +582,23 @@ __device__ __forceinline__ void xl_copy_rows(double2* __restrict__ dst, const do
 // blocks of the states that it steps itself (no other workgroup writes them
 // until the next barrier) and a share of the row blocks of T and R; the
 // decision bytes and B^{-1} are workgroup 0's.
-template <int STEPPER, bool GRP, bool SAVE = false>
+template <class C, int STEPPER, bool GRP, bool SAVE = false>
 __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup& X, int pi, int g) {
+  static_assert(!SAVE || C::NXT == NX, "states are kept for N <= 256");
+  static_assert(GRP || C::NXT == NX, "the one-workgroup launch is for N <= 256");
   using T = LTab<STEPPER>;
+  constexpr int NXT = C::NXT, XST = NXT / 64;
   const FwdArgs& a = A.f;
-  XLds& s = xl_lds;
+  auto& s = C::lds();
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int G = GRP ? X.group : 1;
-  char* pm = GRP ? X.pair_mem + (long long)pi * XG_PAIR_BYTES : slot;
-  char* wm = GRP ? X.wg_mem + ((long long)pi * G + g) * XG_WG_BYTES : slot + XSLOT_G;
-  double2* __restrict__ cg = reinterpret_cast<double2*>(pm + XSLOT_C);
-  double2* __restrict__ dg = reinterpret_cast<double2*>(pm + XSLOT_D);
-  double2* __restrict__ frec = reinterpret_cast<double2*>(pm + XSLOT_F);
+  char* pm = GRP ? X.pair_mem + (long long)pi * C::PAIR_BYTES : slot;
+  char* wm = GRP ? X.wg_mem + ((long long)pi * G + g) * C::WG_BYTES : slot + XSLOT_G;
+  double2* __restrict__ cg = reinterpret_cast<double2*>(pm + C::PAIR_C);
+  double2* __restrict__ dg = reinterpret_cast<double2*>(pm + C::PAIR_D);
+  double2* __restrict__ frec = reinterpret_cast<double2*>(pm + C::PAIR_F);
   double2* __restrict__ gm = reinterpret_cast<double2*>(wm);
-  int* pivg = reinterpret_cast<int*>(pm + XSLOT_G);  // GRP: the pivot list of the last elimination
+  int* pivg = reinterpret_cast<int*>(pm + C::PAIR_PIV);  // GRP: the pivot list of the last elimination
   unsigned* cnt = GRP ? X.counters + 16LL * pi : nullptr;
   unsigned* failw = GRP ? cnt + 1 : nullptr;
   unsigned nsync = 0;
@@ -547,52 +611,46 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
   const double2* __restrict__ Us = a.U + S.table_off;
   const int Wd = 2 * S.kd + 1;
 
-  if (tid < NX) {
-    const int hk0 = tid < N ? a.beams[2 * (S.beam_off + tid)] : 0;
-    const int hk1 = tid < N ? a.beams[2 * (S.beam_off + tid) + 1] : 0;
-    s.bhk[tid][0] = hk0;
-    s.bhk[tid][1] = hk1;
-    s.off[tid] = hk0 * Wd + hk1;
+  for (int j = tid; j < NXT; j += XT) {
+    const int hk0 = j < N ? a.beams[2 * (S.beam_off + j)] : 0;
+    const int hk1 = j < N ? a.beams[2 * (S.beam_off + j) + 1] : 0;
+    s.bhk[j][0] = hk0;
+    s.bhk[j][1] = hk1;
+    s.off[j] = hk0 * Wd + hk1;
   }
   if (tid == 0) {
     s.flag_singular = 0;
     s.bad = 0;
     s.sync_fail = 0;
   }
-  if (tid < 2) s.tb[tid][S.box] = make_double2(0.0, 0.0);
+  if (tid < C::TSLOTS) s.tb[tid][S.box] = make_double2(0.0, 0.0);
   __syncthreads();
   const double th0 = a.angles[2 * p], th1 = a.angles[2 * p + 1];
-  if (tid < NX) {
+  for (int j = tid; j < NXT; j += XT) {
     // Gamma_j^2 = gamma^2 - |b0 + k_j|^2 (Sec. 2.1), b0 = gamma cos(theta0) (cos theta1, sin theta1)
     const double b0x = S.gamma * cos(th0) * cos(th1);
     const double b0y = S.gamma * cos(th0) * sin(th1);
     double arg = 0.0;
-    if (tid < N) {
-      const double qx = b0x + s.bhk[tid][0] * S.recip[0] + s.bhk[tid][1] * S.recip[2];
-      const double qy = b0y + s.bhk[tid][0] * S.recip[1] + s.bhk[tid][1] * S.recip[3];
+    if (j < N) {
+      const double qx = b0x + s.bhk[j][0] * S.recip[0] + s.bhk[j][1] * S.recip[2];
+      const double qy = b0y + s.bhk[j][0] * S.recip[1] + s.bhk[j][1] * S.recip[3];
       arg = S.gamma * S.gamma - (qx * qx + qy * qy);
     }
-    s.g2s[tid] = arg;
+    s.g2s[j] = arg;
   }
   __syncthreads();
-  // table index of U_{ik} = u_{g_i - g_k} is base_i - off_k for the A-operand
-  // rows of the thread's two tiles
-  int base[2];
-#pragma unroll
-  for (int t = 0; t < 2; ++t) {
-    const int i = 32 * w + 16 * t + (lane & 15);
-    base[t] = (s.bhk[i][0] + S.hd) * Wd + (s.bhk[i][1] + S.kd);
-  }
+  typename C::Base base;
+  C::bases(base, S.hd, S.kd, w, lane);
   // Z0 = [I; i Gamma] (spans the columns of S^{-1}[I; O] of Algorithm 1); in
   // a group launch each workgroup writes its share of the rows
-  for (int e = tid + XT * g; e < NX * NX; e += XT * G) {
-    const int row = e / NX, col = e - row * NX;
+  for (int e = tid + XT * g; e < NXT * NXT; e += XT * G) {
+    const int row = e / NXT, col = e - row * NXT;
     const double g2v = s.g2s[row];
     const bool dgn = row == col;
     gst(&cg[e], make_double2(dgn ? 1.0 : 0.0, 0.0));
     gst(&dg[e], make_double2((dgn && g2v < 0.0) ? sqrt(-g2v) : 0.0, (dgn && g2v >= 0.0) ? sqrt(g2v) : 0.0));
   }
-  if constexpr (GRP) xl_group_sync(cnt, G * ++nsync, failw);
+  if constexpr (GRP) xl_group_sync<C>(cnt, G * ++nsync, failw);
   else __syncthreads();
   int nrhst = 0;
 #pragma unroll 1
@@ -609,33 +667,33 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
         }
       }
     }
-    xl_slice<STEPPER>(cg, dg, gm, Us, i * T::nodes, S.box, h, N, base, g, G);
+    C::template slice<STEPPER>(cg, dg, gm, Us, i * T::nodes, S.box, h, N, base, g, G);
     if constexpr (GRP) {
       // the row-sum partials of every workgroup of the pair, summed in the
       // same order everywhere (two buffers: a workgroup cannot be a slice ahead)
-      double* part = reinterpret_cast<double*>(wm + XG_STAGE_BYTES) + 2 * NX * (i & 1);
-      if (tid < NX) {
-        part[tid] = s.rdg[tid];
-        part[NX + tid] = s.rof[tid];
+      double* part = reinterpret_cast<double*>(wm + C::WG_PART) + 2 * NXT * (i & 1);
+      for (int j = tid; j < NXT; j += XT) {
+        part[j] = s.rdg[j];
+        part[NXT + j] = s.rof[j];
       }
-      xl_group_sync(cnt, G * ++nsync, failw);
-      if (tid < NX) {
+      xl_group_sync<C>(cnt, G * ++nsync, failw);
+      for (int j = tid; j < NXT; j += XT) {
         double dv = 0.0, ov = 0.0;
         for (int q = 0; q < G; ++q) {
-          const double* pq = reinterpret_cast<const double*>(X.wg_mem + ((long long)pi * G + q) * XG_WG_BYTES +
-                                                             XG_STAGE_BYTES) + 2 * NX * (i & 1);
-          dv += pq[tid];
-          ov += pq[NX + tid];
+          const double* pq = reinterpret_cast<const double*>(X.wg_mem + ((long long)pi * G + q) * C::WG_BYTES +
+                                                             C::WG_PART) + 2 * NXT * (i & 1);
+          dv += pq[j];
+          ov += pq[NXT + j];
         }
-        s.rdg[tid] = dv;
-        s.rof[tid] = ov;
+        s.rdg[j] = dv;
+        s.rof[j] = ov;
       }
       __syncthreads();
     }
     // condition estimate of Q = c (Sec. 3.2): the Gershgorin / Varah bound
     double hi = 0.0, lo = 1.0e308;
 #pragma unroll
-    for (int q = 0; q < XS; ++q) {
+    for (int q = 0; q < XST; ++q) {
       const int row = 64 * q + lane;
       if (row < N) {
         const double dv = s.rdg[row], ov = s.rof[row];
@@ -657,21 +715,21 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
       if constexpr (GRP) {
         // workgroup 0 records the elimination; all replay it on their row blocks of P
         if (g == 0) {
-          xl_elim_record(cg, dg, frec, N, 0);
-          if (tid < NX) pivg[tid] = s.pcrec[tid];
+          xl_elim_record<C>(cg, dg, frec, N, 0);
+          for (int j = tid; j < NXT; j += XT) pivg[j] = s.pcrec[j];
         }
-        xl_group_sync(cnt, G * ++nsync, failw);
+        xl_group_sync<C>(cnt, G * ++nsync, failw);
         if (g != 0) {
-          if (tid < NX) {
-            // masked into range: after a failed barrier the list may be stale
-            s.pcrec[tid] = pivg[tid] & (NX - 1);
-            s.pos[tid] = tid;
+          for (int j = tid; j < NXT; j += XT) {
+            // brought into range: after a failed barrier the list may be stale
+            s.pcrec[j] = (int)((unsigned)pivg[j] % (unsigned)NXT);
+            s.pos[j] = j;
           }
           __syncthreads();
-          if (tid < N) s.pos[s.pcrec[tid]] = tid;
+          for (int j = tid; j < N; j += XT) s.pos[s.pcrec[j]] = j;
           __syncthreads();
         }
-        xl_replay_p(cg, dg, frec, N, g, G);
+        xl_replay_p<C>(cg, dg, frec, N, g, G);
         if constexpr (SAVE) {
           // T: row block b of I by workgroup (nbp + b) mod G, after the nbp
           // row blocks of P; R: row block b of P Q^{-1} by workgroup b mod G,
@@ -681,12 +739,12 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
                              ((g - nbp) % G + G) % G, G);
           if (a.ck.r_off) xl_copy_rows(reinterpret_cast<double2*>(pws + a.ck.r_off + (long long)i * MATB), dg, g, G);
         }
-        xl_group_sync(cnt, G * ++nsync, failw);
+        xl_group_sync<C>(cnt, G * ++nsync, failw);
       } else {
-        xl_elim_record(cg, dg, frec, N, 0);
+        xl_elim_record<C>(cg, dg, frec, N, 0);
         if constexpr (SAVE)
           xl_replay_identity(reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * MATB), frec, N, 0, 1);
-        xl_replay_p(cg, dg, frec, N, 0, 1);
+        xl_replay_p<C>(cg, dg, frec, N, 0, 1);
         if constexpr (SAVE) {
           if (a.ck.r_off) {  // R = P Q^{-1} for an adjoint that keeps states only every few slices
             xl_copy(reinterpret_cast<double2*>(pws + a.ck.r_off + (long long)i * MATB), dg);
@@ -711,20 +769,20 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
   }
   // reflection (Eq. vrhocomp): upper = Gamma Q - iP, lower = Gamma Q + iP,
   // rho = lower x with upper x = e_1
-  xl_elim_record(cg, dg, frec, N, 1);
+  xl_elim_record<C>(cg, dg, frec, N, 1);
   if constexpr (SAVE) xl_replay_identity(reinterpret_cast<double2*>(pws + a.ck.binv_off), frec, N, 0, 1);
   if (w == 0) {
     // x = E e_{pc_0}: the recorded operations in reverse order, each v <- v - e_pc (f . v)
     const int pc0 = s.pcrec[0];
-    double2 v[XS];
+    double2 v[XST];
 #pragma unroll
-    for (int q = 0; q < XS; ++q) v[q] = make_double2(64 * q + lane == pc0 ? 1.0 : 0.0, 0.0);
+    for (int q = 0; q < XST; ++q) v[q] = make_double2(64 * q + lane == pc0 ? 1.0 : 0.0, 0.0);
 #pragma unroll 1
     for (int k = N - 1; k >= 0; --k) {
       double sr = 0.0, si = 0.0;
 #pragma unroll
-      for (int q = 0; q < XS; ++q) {
-        const double2 f = gld(&frec[k * NX + 64 * q + lane]);
+      for (int q = 0; q < XST; ++q) {
+        const double2 f = gld(&frec[k * NXT + 64 * q + lane]);
         sr += f.x * v[q].x - f.y * v[q].y;
         si += f.x * v[q].y + f.y * v[q].x;
       }
@@ -736,20 +794,19 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
       const int pc = __builtin_amdgcn_readfirstlane(s.pcrec[k]);
       if (lane == (pc & 63)) {
 #pragma unroll
-        for (int q = 0; q < XS; ++q)
+        for (int q = 0; q < XST; ++q)
           if (q == (pc >> 6)) v[q] = make_double2(v[q].x - sr, v[q].y - si);
       }
     }
 #pragma unroll
-    for (int q = 0; q < XS; ++q) s.xv[64 * q + lane] = v[q];
+    for (int q = 0; q < XST; ++q) s.xv[64 * q + lane] = v[q];
   }
   if (tid == 0) {
     s.bnorm_bits = 0;
     s.xnorm_bits = 0;
   }
   __syncthreads();
-  if (tid < a.ld) {
-    const int j = tid;
+  for (int j = tid; j < a.ld; j += XT) {
     double eta = 0.0;
     double2 rj = make_double2(0.0, 0.0);
     if (j < N) {
@@ -757,7 +814,7 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
       const double g_r = g2v >= 0.0 ? sqrt(g2v) : 0.0, g_i = g2v >= 0.0 ? 0.0 : -sqrt(-g2v);
       double rs = 0.0;  // row j of Gamma Q - iP, for the breakdown test
       for (int k = 0; k < N; ++k) {
-        const double2 cv = gld(&cg[j * NX + k]), pv = gld(&dg[j * NX + k]), x = s.xv[k];
+        const double2 cv = gld(&cg[j * NXT + k]), pv = gld(&dg[j * NXT + k]), x = s.xv[k];
         const double lr = g_r * cv.x - g_i * cv.y - pv.y, li = g_r * cv.y + g_i * cv.x + pv.x;
         rj.x += lr * x.x - li * x.y;
         rj.y += lr * x.y + li * x.x;
@@ -784,9 +841,11 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
   if constexpr (GRP)
     lost = s.sync_fail || __hip_atomic_load(failw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
   const int stv = lost ? 3 : s.flag_singular ? 1 : s.bad ? 2 : brk ? 4 : 0;
-  if (stv != 0 && tid < N) {  // a failed pair's outputs are NaN
-    a.intensity[(long long)p * a.ld + tid] = NAN;
-    if (a.rho) a.rho[(long long)p * a.ld + tid] = make_double2(NAN, NAN);
+  if (stv != 0) {  // a failed pair's outputs are NaN
+    for (int j = tid; j < N; j += XT) {
+      a.intensity[(long long)p * a.ld + j] = NAN;
+      if (a.rho) a.rho[(long long)p * a.ld + j] = make_double2(NAN, NAN);
+    }
   }
   if (tid == 0) {
     a.status[p] = stv;
@@ -800,7 +859,7 @@ __global__ __launch_bounds__(XT, 1) void forward_xl_kernel(LargeArgs A) {
 #pragma unroll 1
   for (int pi = blockIdx.x; pi < A.f.n_pairs; pi += gridDim.x) {
     const int p = A.f.pair_list ? A.f.pair_list[pi] : pi;
-    xl_run_pair<STEPPER, false, SAVE>(A, p, slot, XlGroup{}, 0, 0);
+    xl_run_pair<XCfg, STEPPER, false, SAVE>(A, p, slot, XlGroup{}, 0, 0);
     __syncthreads();  // LDS is reused by the next pair
   }
 }
@@ -811,7 +870,7 @@ template <int STEPPER, bool SAVE>
 __global__ __launch_bounds__(XT, 1) void forward_xl_group_kernel(LargeArgs A, XlGroup X) {
   const int pi = blockIdx.x / X.group, g = blockIdx.x - pi * X.group;
   const int p = A.f.pair_list ? A.f.pair_list[pi] : pi;
-  xl_run_pair<STEPPER, true, SAVE>(A, p, nullptr, X, pi, g);
+  xl_run_pair<XCfg, STEPPER, true, SAVE>(A, p, nullptr, X, pi, g);
 }
 
 __global__ void xl_group_reset_kernel(unsigned* counters, int n) {

@@ -62,6 +62,22 @@ struct XlGroup {
 hipError_t launch_forward_xl_group(int stepper, const LargeArgs& a, const XlGroup& x, hipStream_t stream);
 int forward_xl_group_max_workgroups(int device);  // co-resident workgroups of a group launch (0: none)
 
+// 256 < N <= 576 (RK steppers, forward only), group launch only: a pair's
+// c, c', multipliers and pivot list (XXG_PAIR_BYTES); per workgroup the 7
+// stage products and the stage input of one column block and two buffers
+// of row-sum partials (XXG_WG_BYTES); 16 counter words per pair.
+constexpr int NXX = 576;        // padded beam count of the kernel for 256 < N <= 576
+constexpr int MAXBOXXX = 4096;  // rod-difference entries per node table row of that kernel
+constexpr long long XXG_C = 0;
+constexpr long long XXG_D = (long long)NXX * NXX * 16;
+constexpr long long XXG_F = 2LL * NXX * NXX * 16;
+constexpr long long XXG_PIV = 3LL * NXX * NXX * 16;
+constexpr long long XXG_PAIR_BYTES = XXG_PIV + 4LL * NXX;
+constexpr long long XXG_STAGE_BYTES = 8LL * NXX * 16 * 16;  // G_0 .. G_6 and X of a block
+constexpr long long XXG_WG_BYTES = XXG_STAGE_BYTES + 2LL * 2 * NXX * 8;
+hipError_t launch_forward_xxl_group(int stepper, const LargeArgs& a, const XlGroup& x, hipStream_t stream);
+int forward_xxl_group_max_workgroups(int device);  // co-resident workgroups of its launch (0: none)
+
 // One persistent launch over a batch of pairs with N <= 64 and N > 64
 // (forward_queue_kernel): workgroups take pairs in the order of `order`
 // from a counter in device memory; the N <= 64 pairs run the one-workgroup

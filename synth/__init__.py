@@ -18,6 +18,7 @@ from .workloads import (  # noqa: F401
     config3,
     config4,
     config5,
+    single_angle_n521,
     small_2d,
     small_row,
     WORKLOADS,

@@ -220,6 +220,24 @@ def config5(n_structures: int = 64) -> Workload:
                     _deg(np.linspace(0.3, 6.0, 256)), 0.0)
 
 
+def single_angle_n521(n_slices: int = 661) -> Workload:
+    """The single-angle case of the paper's timing table at its size (Sec. 4,
+    Tables 2 and 3: n = 521 rods, one glancing angle of 1.3 deg at azimuth
+    -30 deg, a 9.91 A domain without a bulk layer, RK4 at dz = 0.015 A):
+    N = 521 rods of a 7x7 supercell, 49 atoms x 3 layers, 10 keV positrons,
+    9.91 A in 661 slices.  The Si(111)-7x7 input itself is not available,
+    so the cell, atoms and potential are synthetic like every other
+    workload here (seeds of workload 6)."""
+    rec = _recip(7)
+    beams = beams_nearest(521, rec)
+    a, b = _scattering(np.random.default_rng(1006))
+    atoms = _layers(7, 3, 0.1, np.random.default_rng(100000 * 1006))
+    s = Structure(beams=beams, recip=rec, cell_area=(7 * CELL) ** 2, atoms=atoms, scat_a=a, scat_b=b,
+                  thickness=9.91, n_slices=n_slices)
+    return Workload("paper-n521-single-angle", [s], 10_000.0, -1, 0.1, _deg(np.array([1.3])),
+                    float(_deg(-30.0)))
+
+
 def bulk_layer(surface: Workload, n_slices: int, images: int = 2) -> Workload:
     """The ideal bulk under a surface workload, one unit layer per structure.
 

@@ -79,7 +79,7 @@ def test_plan_create_rejects_bad_descriptors(case, code):
     elif case == "slices":
         kw["n_slices"] = 0
     elif case == "toomany":
-        beams = [[0, 0]] + [[h, 0] for h in range(1, 257)]   # N = 257 > RHEED_MAX_BEAMS
+        beams = [[0, 0]] + [[h, 0] for h in range(1, 577)]   # N = 577 > RHEED_MAX_BEAMS
     elif case == "box":
         beams = [[0, 0], [9, 0], [0, 9], [-9, 0], [0, -9]]
     st, keep = _structure(lib, beams, **kw)
