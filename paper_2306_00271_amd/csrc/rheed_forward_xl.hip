@@ -245,6 +245,7 @@ struct XCfg {
   static constexpr int TSLOTS = 2;      // node-table slots in LDS
   static constexpr long long SYNC_TICKS = XCH_TICKS;  // a group barrier's wait gives up after this
   static constexpr int SYNC_SPIN = XCH_SPIN;          // or after this many polls
+  static constexpr bool GROUP_ELIM = false;           // a group launch's eliminations run on workgroup 0
   static constexpr long long PAIR_C = XSLOT_C, PAIR_D = XSLOT_D, PAIR_F = XSLOT_F, PAIR_PIV = XSLOT_G;
   static constexpr long long PAIR_BYTES = XG_PAIR_BYTES;
   static constexpr long long WG_PART = XG_STAGE_BYTES;  // row-sum partials after the stage products
@@ -312,13 +313,13 @@ __device__ __forceinline__ void xl_update(double2 (&z)[R][XSN], int pc, const do
   }
 }
 
-// The recorded column operations of steps [0, k1) on the rows in z.
+// The recorded column operations of steps [k0, k1) on the rows in z.
 template <class C, int R>
-__device__ __forceinline__ void xl_replay(double2 (&z)[R][C::NXT / 64], int k1, int lane,
+__device__ __forceinline__ void xl_replay(double2 (&z)[R][C::NXT / 64], int k0, int k1, int lane,
                                           const double2* __restrict__ frec) {
   constexpr int NXT = C::NXT, XST = NXT / 64;
 #pragma unroll 1
-  for (int k = 0; k < k1; ++k) {
+  for (int k = k0; k < k1; ++k) {
     double2 f[XST];
 #pragma unroll
     for (int q = 0; q < XST; ++q) f[q] = gld(&frec[k * NXT + 64 * q + lane]);
@@ -326,22 +327,97 @@ __device__ __forceinline__ void xl_replay(double2 (&z)[R][C::NXT / 64], int k1, 
   }
 }
 
+// Steps k0 .. k1 - 1 of a recording elimination, on the rows of the block
+// that starts at row k0 (rows k0 + w + XW m of it in wave w, in z, each
+// carrying every earlier step): step k picks, among the unused columns < n
+// (um, the same in every wave), the one with the largest |A_kj| (key: the
+// upper 32 bits of |A_kj|^2 with the low C::IDXB bits replaced by the
+// complement of j, so near-ties go to the smaller index), records
+// f_j = A_kj / A_k,pc (f_pc = 1 - 1 / A_k,pc) in frec and its pivot column in
+// s.pcrec, and subtracts f_j column pc from every column j of the block's
+// rows.  Row k + 1 reaches the other waves through LDS.
+template <class C>
+__device__ __forceinline__ void xl_record_steps(double2 (&z)[C::XEMT][C::NXT / 64],
+                                                unsigned long long (&um)[C::NXT / 64], int k0, int k1, int n,
+                                                double2* __restrict__ frec) {
+  constexpr int NXT = C::NXT, XST = NXT / 64, XEMT = C::XEMT;
+  constexpr unsigned IDXM = (1u << C::IDXB) - 1u;
+  static_assert(NXT <= (1 << C::IDXB), "pivot keys hold every column index");
+  auto& s = C::lds();
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double2* rowbuf = s.xb;
+  __syncthreads();  // rowbuf aliases the stage buffer and the previous block's last row
+  if (wu == 0) {
+#pragma unroll
+    for (int q = 0; q < XST; ++q) rowbuf[64 * q + lane] = z[0][q];
+  }
+#pragma unroll 1
+  for (int k = k0; k < k1; ++k) {
+    const int slot = k & 1;
+    __syncthreads();
+    double2 v[XST];
+    unsigned key = 0;
+#pragma unroll
+    for (int q = 0; q < XST; ++q) {
+      v[q] = rowbuf[slot * NXT + 64 * q + lane];
+      const int c = 64 * q + lane;
+      if (!((um[q] >> lane) & 1ull) && c < n) {
+        const double m2 = v[q].x * v[q].x + v[q].y * v[q].y;
+        const unsigned kq =
+            ((unsigned)(((unsigned long long)__double_as_longlong(m2)) >> 32) & ~IDXM) | (IDXM - (unsigned)c);
+        key = kq > key ? kq : key;
+      }
+    }
+    key = wave_max_u32(key);
+    if ((key >> C::IDXB) == 0 && tid == 0) s.flag_singular = 1;
+    const int pc = (int)(IDXM - (key & IDXM));
+    const int hf = pc >> 6, pl = pc & 63;
+#pragma unroll
+    for (int q = 0; q < XST; ++q)
+      if (q == hf) um[q] |= 1ull << pl;
+    double2 vs = v[0];
+#pragma unroll
+    for (int q = 1; q < XST; ++q)
+      if (q == hf) vs = v[q];
+    const double2 piv = make_double2(readlane_f64(vs.x, pl), readlane_f64(vs.y, pl));
+    const double inv = 1.0 / (piv.x * piv.x + piv.y * piv.y);
+    const double2 ip = make_double2(piv.x * inv, -piv.y * inv);
+    double2 f[XST];
+#pragma unroll
+    for (int q = 0; q < XST; ++q) {
+      f[q] = make_double2(v[q].x * ip.x - v[q].y * ip.y, v[q].x * ip.y + v[q].y * ip.x);
+      if (q == hf && lane == pl) f[q] = make_double2(1.0 - ip.x, -ip.y);
+    }
+    if (wu == 0) {
+#pragma unroll
+      for (int q = 0; q < XST; ++q) gst(&frec[k * NXT + 64 * q + lane], f[q]);
+      if (lane == 0) s.pcrec[k] = pc;
+    }
+    xl_update<XEMT, XST>(z, pc, f);
+    // row k + 1 of this block: wave (k + 1 - k0) % XW, register (k + 1 - k0) / XW
+    const int nx = k + 1 - k0;
+    if (k + 1 < k1 && wu == (nx & (XW - 1))) {
+      const int mr = nx / XW;
+#pragma unroll
+      for (int m = 0; m < XEMT; ++m)
+        if (m == mr) {
+#pragma unroll
+          for (int q = 0; q < XST; ++q) rowbuf[(slot ^ 1) * NXT + 64 * q + lane] = z[m][q];
+        }
+    }
+  }
+}
+
 // Recording elimination of the n x n leading block of Q = c (which = 0) or
-// of Gamma Q - iP (which = 1), 64 rows at a time (rows k0 + w + 8 m of
-// block k0 in wave w): the steps of earlier blocks are replayed on the
-// block's rows, then the block's steps are taken in turn: step k picks,
-// among unused columns < n, the one with the largest |A_kj| (key: the upper
-// 32 bits of |A_kj|^2 with the low 8 bits replaced by 255 - j), records
-// f_j = A_kj / A_k,pc (f_pc = 1 - 1 / A_k,pc) and its pivot column, and
-// subtracts f_j column pc from every column j of the block's rows.  Row
-// k + 1 reaches the other waves through LDS.  s.pos gets the step at which
+// of Gamma Q - iP (which = 1), XW * C::XEMT rows at a time (a left-looking
+// order): the steps of earlier blocks are replayed on a block's rows, then
+// its own steps are taken (xl_record_steps).  s.pos gets the step at which
 // each column was the pivot (its own index for columns >= n).
 template <class C>
 __device__ __noinline__ void xl_elim_record(const double2* __restrict__ cg, const double2* __restrict__ dg,
                                             double2* __restrict__ frec, int N, int which) {
   constexpr int NXT = C::NXT, XST = NXT / 64, XEMT = C::XEMT, XEBT = XW * XEMT;
-  constexpr unsigned IDXM = (1u << C::IDXB) - 1u;
-  static_assert(NXT <= (1 << C::IDXB), "pivot keys hold every column index");
   auto& s = C::lds();
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int n = __builtin_amdgcn_readfirstlane(N);
@@ -350,7 +426,6 @@ __device__ __noinline__ void xl_elim_record(const double2* __restrict__ cg, cons
   unsigned long long um[XST];  // used columns (the same in every wave)
 #pragma unroll
   for (int q = 0; q < XST; ++q) um[q] = 0;
-  double2* rowbuf = s.xb;
 #pragma unroll 1
   for (int k0 = 0; k0 < n; k0 += XEBT) {
     double2 z[XEMT][XST];
@@ -379,68 +454,8 @@ __device__ __noinline__ void xl_elim_record(const double2* __restrict__ cg, cons
         z[m][q] = v;
       }
     }
-    xl_replay<C, XEMT>(z, k0, lane, frec);
-    const int k1 = n < k0 + XEBT ? n : k0 + XEBT;
-    __syncthreads();  // rowbuf aliases the stage buffer and the previous block's last row
-    if (wu == 0) {
-#pragma unroll
-      for (int q = 0; q < XST; ++q) rowbuf[64 * q + lane] = z[0][q];
-    }
-#pragma unroll 1
-    for (int k = k0; k < k1; ++k) {
-      const int slot = k & 1;
-      __syncthreads();
-      double2 v[XST];
-      unsigned key = 0;
-#pragma unroll
-      for (int q = 0; q < XST; ++q) {
-        v[q] = rowbuf[slot * NXT + 64 * q + lane];
-        const int c = 64 * q + lane;
-        if (!((um[q] >> lane) & 1ull) && c < n) {
-          const double m2 = v[q].x * v[q].x + v[q].y * v[q].y;
-          const unsigned kq =
-              ((unsigned)(((unsigned long long)__double_as_longlong(m2)) >> 32) & ~IDXM) | (IDXM - (unsigned)c);
-          key = kq > key ? kq : key;
-        }
-      }
-      key = wave_max_u32(key);
-      if ((key >> C::IDXB) == 0 && tid == 0) s.flag_singular = 1;
-      const int pc = (int)(IDXM - (key & IDXM));
-      const int hf = pc >> 6, pl = pc & 63;
-#pragma unroll
-      for (int q = 0; q < XST; ++q)
-        if (q == hf) um[q] |= 1ull << pl;
-      double2 vs = v[0];
-#pragma unroll
-      for (int q = 1; q < XST; ++q)
-        if (q == hf) vs = v[q];
-      const double2 piv = make_double2(readlane_f64(vs.x, pl), readlane_f64(vs.y, pl));
-      const double inv = 1.0 / (piv.x * piv.x + piv.y * piv.y);
-      const double2 ip = make_double2(piv.x * inv, -piv.y * inv);
-      double2 f[XST];
-#pragma unroll
-      for (int q = 0; q < XST; ++q) {
-        f[q] = make_double2(v[q].x * ip.x - v[q].y * ip.y, v[q].x * ip.y + v[q].y * ip.x);
-        if (q == hf && lane == pl) f[q] = make_double2(1.0 - ip.x, -ip.y);
-      }
-      if (wu == 0) {
-#pragma unroll
-        for (int q = 0; q < XST; ++q) gst(&frec[k * NXT + 64 * q + lane], f[q]);
-        if (lane == 0) s.pcrec[k] = pc;
-      }
-      xl_update<XEMT, XST>(z, pc, f);
-      // row k + 1 of this block: wave (k + 1 - k0) % 8, register (k + 1 - k0) / 8
-      const int nx = k + 1 - k0;
-      if (k + 1 < k1 && wu == (nx & (XW - 1))) {
-        const int mr = nx / XW;
-#pragma unroll
-        for (int m = 0; m < XEMT; ++m)
-          if (m == mr) {
-#pragma unroll
-            for (int q = 0; q < XST; ++q) rowbuf[(slot ^ 1) * NXT + 64 * q + lane] = z[m][q];
-          }
-      }
-    }
+    xl_replay<C, XEMT>(z, 0, k0, lane, frec);
+    xl_record_steps<C>(z, um, k0, n < k0 + XEBT ? n : k0 + XEBT, n, frec);
   }
   // the multipliers and pivot list are read back by this workgroup only
   __syncthreads();
@@ -472,7 +487,7 @@ __device__ __noinline__ void xl_replay_p(double2* __restrict__ cg, double2* __re
     for (int m = 0; m < XEMT; ++m)
 #pragma unroll
       for (int q = 0; q < XST; ++q) z[m][q] = gld(&dg[(r0 + w + XW * m) * NXT + 64 * q + lane]);
-    xl_replay<C, XEMT>(z, n, lane, frec);
+    xl_replay<C, XEMT>(z, 0, n, lane, frec);
 #pragma unroll
     for (int m = 0; m < XEMT; ++m) {
       const int row = r0 + w + XW * m;
@@ -536,7 +551,7 @@ __device__ __noinline__ void xl_replay_identity(double2* __restrict__ out, const
     for (int m = 0; m < XEM; ++m)
 #pragma unroll
       for (int q = 0; q < XS; ++q) z[m][q] = make_double2(r0 + w + XW * m == 64 * q + lane ? 1.0 : 0.0, 0.0);
-    if (r0 < n) xl_replay<XCfg, XEM>(z, n, lane, frec);
+    if (r0 < n) xl_replay<XCfg, XEM>(z, 0, n, lane, frec);
 #pragma unroll
     for (int m = 0; m < XEM; ++m) {
       const int row = r0 + w + XW * m;
@@ -713,13 +728,18 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
     if (xi > a.threshold) {
       ++nrhst;
       if constexpr (GRP) {
-        // workgroup 0 records the elimination; all replay it on their row blocks of P
-        if (g == 0) {
-          xl_elim_record<C>(cg, dg, frec, N, 0);
-          for (int j = tid; j < NXT; j += XT) pivg[j] = s.pcrec[j];
+        if constexpr (C::GROUP_ELIM) {
+          // the elimination spread over the group (ends after a barrier)
+          C::group_elim(cg, frec, pivg, N, g, G, cnt, nsync, failw);
+        } else {
+          // workgroup 0 records the elimination; all replay it on their row blocks of P
+          if (g == 0) {
+            xl_elim_record<C>(cg, dg, frec, N, 0);
+            for (int j = tid; j < NXT; j += XT) pivg[j] = s.pcrec[j];
+          }
+          xl_group_sync<C>(cnt, G * ++nsync, failw);
         }
-        xl_group_sync<C>(cnt, G * ++nsync, failw);
-        if (g != 0) {
+        if (C::GROUP_ELIM || g != 0) {
           for (int j = tid; j < NXT; j += XT) {
             // brought into range: after a failed barrier the list may be stale
             s.pcrec[j] = (int)((unsigned)pivg[j] % (unsigned)NXT);
