@@ -41,10 +41,11 @@
 // g + G, ... of every slice (the RK stages act on columns independently).
 // Per slice they meet at one barrier to sum their row-sum partials (in the
 // same order in every workgroup, so all take the same decision); at a
-// transformation workgroup 0 records the elimination, the others wait, and
-// all then replay it on their 64-row blocks of P.  Workgroup 0 alone solves
-// the reflection.  Both launches have an instance that keeps the adjoint's
-// states.
+// transformation the elimination runs in blocks of 16 steps, workgroup 0
+// recording a block and every workgroup applying it to the later row blocks
+// it owns, and all then replay it on their 16-row blocks of P.  Workgroup 0
+// alone solves the reflection.  Both launches have an instance that keeps the
+// adjoint's states.
 
 namespace rheed {
 namespace {
@@ -66,6 +67,7 @@ struct XLds {
   int pcrec[NX];                  // pivot column of every elimination step
   int pos[NX];                    // pivot step of every column in the last elimination
   double2 xv[NX];                 // first column of the inverse in the reflection
+  unsigned long long umask[NX / 64];  // group elimination: columns already pivots (workgroup 0)
   unsigned long long bnorm_bits;  // ||Gamma Q - iP||_inf and ||x||_inf of the reflection
   unsigned long long xnorm_bits;
   int flag_singular;
@@ -245,7 +247,7 @@ struct XCfg {
   static constexpr int TSLOTS = 2;      // node-table slots in LDS
   static constexpr long long SYNC_TICKS = XCH_TICKS;  // a group barrier's wait gives up after this
   static constexpr int SYNC_SPIN = XCH_SPIN;          // or after this many polls
-  static constexpr bool GROUP_ELIM = false;           // a group launch's eliminations run on workgroup 0
+  using ElimCfg = XCfg;                               // the one-workgroup eliminations (and the reflection's)
   static constexpr long long PAIR_C = XSLOT_C, PAIR_D = XSLOT_D, PAIR_F = XSLOT_F, PAIR_PIV = XSLOT_G;
   static constexpr long long PAIR_BYTES = XG_PAIR_BYTES;
   static constexpr long long WG_PART = XG_STAGE_BYTES;  // row-sum partials after the stage products
@@ -269,6 +271,13 @@ struct XCfg {
   }
 };
 
+
+// The group launch: the same, with the transformation's elimination
+// spread over the group in blocks of 16 steps (2 rows per wave; the replay
+// on P and the copies of R take the same 16-row blocks).
+struct XCfgG : XCfg {
+  static constexpr int XEMT = 2;
+};
 
 // Rows m < R of z: column j <- column j - f_j column pc, pc = 64 HF + pl
 // (the pivot column's quarter is wave-uniform, so it selects code).
@@ -501,6 +510,90 @@ __device__ __noinline__ void xl_replay_p(double2* __restrict__ cg, double2* __re
   __syncthreads();
 }
 
+// The transformation's elimination of Q (Sec. 3.2) spread over a pair's
+// group in blocks of XW * C::XEMT steps (a right-looking order of the same
+// column operations): workgroup 0 takes row block b, whose rows already
+// carry every earlier step, and records its steps (multipliers to frec,
+// pivot columns to the pair's list); after a barrier every workgroup applies
+// those steps to the rows of the later blocks it owns (block b' by workgroup
+// b' mod G) and writes them back, before the next barrier.  Every row meets
+// the same operations in the same order as in the one-workgroup elimination,
+// so the multipliers are the same.  c holds the partly eliminated rows
+// meanwhile; the replay on P that follows sets it to I.
+
+// Workgroup 0: the steps of row block b.
+template <class C>
+__device__ __noinline__ void xl_record_block(const double2* __restrict__ cg, double2* __restrict__ frec,
+                                             int* __restrict__ pivg, int N, int b) {
+  constexpr int NXT = C::NXT, XST = NXT / 64, XEMT = C::XEMT, XEBT = XW * XEMT;
+  auto& s = C::lds();
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int n = __builtin_amdgcn_readfirstlane(N);
+  const int k0 = XEBT * __builtin_amdgcn_readfirstlane(b);
+  const int k1 = n < k0 + XEBT ? n : k0 + XEBT;
+  __syncthreads();  // the used-column words of the previous block are written
+  unsigned long long um[XST];
+#pragma unroll
+  for (int q = 0; q < XST; ++q) um[q] = s.umask[q];
+  double2 z[XEMT][XST];
+#pragma unroll
+  for (int m = 0; m < XEMT; ++m) {
+    const int row = k0 + wu + XW * m;
+#pragma unroll
+    for (int q = 0; q < XST; ++q)
+      z[m][q] = row < n ? gld(&cg[(long long)row * NXT + 64 * q + lane]) : make_double2(0.0, 0.0);
+  }
+  xl_record_steps<C>(z, um, k0, k1, n, frec);
+  __syncthreads();
+  if (tid == 0) {
+#pragma unroll
+    for (int q = 0; q < XST; ++q) s.umask[q] = um[q];
+  }
+  for (int j = tid; j < k1 - k0; j += XT) pivg[k0 + j] = s.pcrec[k0 + j];
+}
+
+// Every workgroup: the steps of block b on the rows of the later blocks it
+// owns.
+template <class C>
+__device__ __noinline__ void xl_apply_block(double2* __restrict__ cg, const double2* __restrict__ frec,
+                                            const int* __restrict__ pivg, int N, int b, int g, int G) {
+  constexpr int NXT = C::NXT, XST = NXT / 64, XEMT = C::XEMT, XEBT = XW * XEMT;
+  auto& s = C::lds();
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int n = __builtin_amdgcn_readfirstlane(N);
+  const int bu = __builtin_amdgcn_readfirstlane(b);
+  const int gu = __builtin_amdgcn_readfirstlane(g), gs = __builtin_amdgcn_readfirstlane(G);
+  const int k0 = XEBT * bu;
+  const int k1 = n < k0 + XEBT ? n : k0 + XEBT;
+  const int nb = (n + XEBT - 1) / XEBT;
+  // the block's pivot columns (brought into range: after a failed barrier
+  // the list may be stale)
+  for (int j = tid; j < k1 - k0; j += XT) s.pcrec[k0 + j] = (int)((unsigned)pivg[k0 + j] % (unsigned)NXT);
+  __syncthreads();
+#pragma unroll 1
+  for (int bb = bu + 1 + ((gu - (bu + 1) % gs) + gs) % gs; bb < nb; bb += gs) {
+    double2 z[XEMT][XST];
+#pragma unroll
+    for (int m = 0; m < XEMT; ++m) {
+      const int row = XEBT * bb + wu + XW * m;
+#pragma unroll
+      for (int q = 0; q < XST; ++q)
+        z[m][q] = row < n ? gld(&cg[(long long)row * NXT + 64 * q + lane]) : make_double2(0.0, 0.0);
+    }
+    xl_replay<C, XEMT>(z, k0, k1, lane, frec);
+#pragma unroll
+    for (int m = 0; m < XEMT; ++m) {
+      const int row = XEBT * bb + wu + XW * m;
+      if (row < n) {
+#pragma unroll
+        for (int q = 0; q < XST; ++q) gst(&cg[(long long)row * NXT + 64 * q + lane], z[m][q]);
+      }
+    }
+  }
+}
+
 // Barrier of the G workgroups of one pair in a group launch: each raises the
 // pair's counter (an agent-scope release, so its stores are written back
 // first) and waits until all have reached `target` (G times the barriers so
@@ -530,6 +623,25 @@ __device__ __forceinline__ void xl_group_sync(unsigned* cnt, unsigned target, un
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
+}
+
+// The block loop of the group elimination (ends after a barrier, with frec
+// and the pair's pivot list complete).
+template <class C>
+__device__ __forceinline__ void xl_group_elim(double2* cg, double2* frec, int* pivg, int N, int g, int G,
+                                              unsigned* cnt, unsigned& nsync, unsigned* failw) {
+  constexpr int XEBT = XW * C::XEMT;
+  const int nb = (N + XEBT - 1) / XEBT;
+  if (g == 0 && threadIdx.x < C::NXT / 64) C::lds().umask[threadIdx.x] = 0;
+#pragma unroll 1
+  for (int b = 0; b < nb; ++b) {
+    if (g == 0) xl_record_block<C>(cg, frec, pivg, N, b);
+    xl_group_sync<C>(cnt, G * ++nsync, failw);
+    if (b + 1 < nb) {
+      xl_apply_block<C>(cg, frec, pivg, N, b, g, G);
+      xl_group_sync<C>(cnt, G * ++nsync, failw);
+    }
+  }
 }
 
 // Q^{-1} (or B^{-1} of the reflection) after xl_elim_record: the recorded
@@ -578,12 +690,13 @@ __device__ __forceinline__ void xl_copy_cols(double2* __restrict__ dst, const do
     }
 }
 
-// The same for the 64-row blocks b0, b0 + bs, ... of the NX / 64.
+// The same for the RB-row blocks b0, b0 + bs, ... of the NX / RB.
+template <int RB>
 __device__ __forceinline__ void xl_copy_rows(double2* __restrict__ dst, const double2* __restrict__ src, int b0,
                                              int bs) {
 #pragma unroll 1
-  for (int b = b0; b < NX / XEB; b += bs)
-    for (int e = threadIdx.x; e < XEB * NX; e += XT) gst(&dst[XEB * NX * b + e], gld(&src[XEB * NX * b + e]));
+  for (int b = b0; b < NX / RB; b += bs)
+    for (int e = threadIdx.x; e < RB * NX; e += XT) gst(&dst[RB * NX * b + e], gld(&src[RB * NX * b + e]));
 }
 
 // One pair.  GRP: workgroup g of the pair's G in a group launch (state,
@@ -728,18 +841,10 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
     if (xi > a.threshold) {
       ++nrhst;
       if constexpr (GRP) {
-        if constexpr (C::GROUP_ELIM) {
-          // the elimination spread over the group (ends after a barrier)
-          C::group_elim(cg, frec, pivg, N, g, G, cnt, nsync, failw);
-        } else {
-          // workgroup 0 records the elimination; all replay it on their row blocks of P
-          if (g == 0) {
-            xl_elim_record<C>(cg, dg, frec, N, 0);
-            for (int j = tid; j < NXT; j += XT) pivg[j] = s.pcrec[j];
-          }
-          xl_group_sync<C>(cnt, G * ++nsync, failw);
-        }
-        if (C::GROUP_ELIM || g != 0) {
+        // the elimination spread over the group (ends after a barrier); all
+        // then replay it on their row blocks of P
+        xl_group_elim<C>(cg, frec, pivg, N, g, G, cnt, nsync, failw);
+        {
           for (int j = tid; j < NXT; j += XT) {
             // brought into range: after a failed barrier the list may be stale
             s.pcrec[j] = (int)((unsigned)pivg[j] % (unsigned)NXT);
@@ -751,17 +856,18 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
         }
         xl_replay_p<C>(cg, dg, frec, N, g, G);
         if constexpr (SAVE) {
-          // T: row block b of I by workgroup (nbp + b) mod G, after the nbp
-          // row blocks of P; R: row block b of P Q^{-1} by workgroup b mod G,
-          // the one that replayed it
+          // T: 64-row block b of I by workgroup (nbp + b) mod G; R: row block
+          // b of P Q^{-1} (the replay's blocks) by workgroup b mod G, the one
+          // that replayed it
           const int nbp = (N + XEB - 1) / XEB;
           xl_replay_identity(reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * MATB), frec, N,
                              ((g - nbp) % G + G) % G, G);
-          if (a.ck.r_off) xl_copy_rows(reinterpret_cast<double2*>(pws + a.ck.r_off + (long long)i * MATB), dg, g, G);
+          if (a.ck.r_off)
+            xl_copy_rows<XW * C::XEMT>(reinterpret_cast<double2*>(pws + a.ck.r_off + (long long)i * MATB), dg, g, G);
         }
         xl_group_sync<C>(cnt, G * ++nsync, failw);
       } else {
-        xl_elim_record<C>(cg, dg, frec, N, 0);
+        xl_elim_record<typename C::ElimCfg>(cg, dg, frec, N, 0);
         if constexpr (SAVE)
           xl_replay_identity(reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * MATB), frec, N, 0, 1);
         xl_replay_p<C>(cg, dg, frec, N, 0, 1);
@@ -789,7 +895,7 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
   }
   // reflection (Eq. vrhocomp): upper = Gamma Q - iP, lower = Gamma Q + iP,
   // rho = lower x with upper x = e_1
-  xl_elim_record<C>(cg, dg, frec, N, 1);
+  xl_elim_record<typename C::ElimCfg>(cg, dg, frec, N, 1);
   if constexpr (SAVE) xl_replay_identity(reinterpret_cast<double2*>(pws + a.ck.binv_off), frec, N, 0, 1);
   if (w == 0) {
     // x = E e_{pc_0}: the recorded operations in reverse order, each v <- v - e_pc (f . v)
@@ -890,7 +996,7 @@ template <int STEPPER, bool SAVE>
 __global__ __launch_bounds__(XT, 1) void forward_xl_group_kernel(LargeArgs A, XlGroup X) {
   const int pi = blockIdx.x / X.group, g = blockIdx.x - pi * X.group;
   const int p = A.f.pair_list ? A.f.pair_list[pi] : pi;
-  xl_run_pair<XCfg, STEPPER, true, SAVE>(A, p, nullptr, X, pi, g);
+  xl_run_pair<XCfgG, STEPPER, true, SAVE>(A, p, nullptr, X, pi, g);
 }
 
 __global__ void xl_group_reset_kernel(unsigned* counters, int n) {

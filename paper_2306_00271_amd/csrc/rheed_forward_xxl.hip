@@ -23,8 +23,9 @@
 //     stored stage products (summed in stage order) and adds their moduli to
 //     the row sums of the badness.
 // Everything after the slice (the Gershgorin / Varah decision, the
-// transformation of Sec. 3.2 by a recorded column elimination and its
-// replay on P, the reflection solve) is the N <= 256 code at this width.
+// transformation of Sec. 3.2 by a column elimination spread over the group
+// in blocks of 16 steps and its replay on P, the reflection solve) is the
+// N <= 256 group code at this width.
 
 namespace rheed {
 namespace {
@@ -210,25 +211,6 @@ __device__ __noinline__ void xxl_slice(double2* __restrict__ cg, double2* __rest
   __syncthreads();
 }
 
-struct XXCfg;
-
-// The transformation's elimination of Q (Sec. 3.2) spread over the pair's
-// group in blocks of XEB2 = XW * XXEM steps (a right-looking order of the
-// same column operations): workgroup 0 takes row block b, whose rows already
-// carry every earlier step, and records its steps (multipliers to frec, pivot
-// columns to the pair's list); after a barrier every workgroup applies those
-// steps to the rows of the later blocks it owns (block b' by workgroup
-// b' mod G) and writes them back, before the next barrier.  Every row meets
-// the same operations in the same order as in the one-workgroup elimination.
-// c holds the partly eliminated rows meanwhile; the replay on P that follows
-// sets it to I.
-constexpr int XEB2 = XW * XXEM;
-
-__device__ __noinline__ void xxl_record_block(const double2* __restrict__ cg, double2* __restrict__ frec,
-                                              int* __restrict__ pivg, int N, int b);
-__device__ __noinline__ void xxl_apply_block(double2* __restrict__ cg, const double2* __restrict__ frec,
-                                             const int* __restrict__ pivg, int N, int b, int g, int G);
-
 struct XXCfg {
   static constexpr int NXT = NXX;
   static constexpr int XEMT = XXEM;
@@ -259,93 +241,8 @@ struct XXCfg {
                                                int box, double h, int N, const Base& base, int cb0, int cbs) {
     xxl_slice<STEPPER>(cg, dg, gm, Us, nb, box, h, N, base, cb0, cbs);
   }
-  static constexpr bool GROUP_ELIM = true;
-  static __device__ __forceinline__ void group_elim(double2* cg, double2* frec, int* pivg, int N, int g, int G,
-                                                    unsigned* cnt, unsigned& nsync, unsigned* failw) {
-    const int nb = (N + XEB2 - 1) / XEB2;
-    if (g == 0 && threadIdx.x < NXX / 64) xxl_lds.umask[threadIdx.x] = 0;
-#pragma unroll 1
-    for (int b = 0; b < nb; ++b) {
-      if (g == 0) xxl_record_block(cg, frec, pivg, N, b);
-      xl_group_sync<XXCfg>(cnt, G * ++nsync, failw);
-      if (b + 1 < nb) {
-        xxl_apply_block(cg, frec, pivg, N, b, g, G);
-        xl_group_sync<XXCfg>(cnt, G * ++nsync, failw);
-      }
-    }
-  }
+  using ElimCfg = XXCfg;
 };
-
-// Workgroup 0: the steps of row block b (see above).
-__device__ __noinline__ void xxl_record_block(const double2* __restrict__ cg, double2* __restrict__ frec,
-                                              int* __restrict__ pivg, int N, int b) {
-  constexpr int XST = NXX / 64;
-  XXLds& s = xxl_lds;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int n = __builtin_amdgcn_readfirstlane(N);
-  const int k0 = XEB2 * __builtin_amdgcn_readfirstlane(b);
-  const int k1 = n < k0 + XEB2 ? n : k0 + XEB2;
-  __syncthreads();  // the used-column words of the previous block are written
-  unsigned long long um[XST];
-#pragma unroll
-  for (int q = 0; q < XST; ++q) um[q] = s.umask[q];
-  double2 z[XXEM][XST];
-#pragma unroll
-  for (int m = 0; m < XXEM; ++m) {
-    const int row = k0 + wu + XW * m;
-#pragma unroll
-    for (int q = 0; q < XST; ++q)
-      z[m][q] = row < n ? gld(&cg[(long long)row * NXX + 64 * q + lane]) : make_double2(0.0, 0.0);
-  }
-  xl_record_steps<XXCfg>(z, um, k0, k1, n, frec);
-  __syncthreads();
-  if (tid == 0) {
-#pragma unroll
-    for (int q = 0; q < XST; ++q) s.umask[q] = um[q];
-  }
-  for (int j = tid; j < k1 - k0; j += XT) pivg[k0 + j] = s.pcrec[k0 + j];
-}
-
-// Every workgroup: the steps of block b on the rows of the later blocks it
-// owns.
-__device__ __noinline__ void xxl_apply_block(double2* __restrict__ cg, const double2* __restrict__ frec,
-                                             const int* __restrict__ pivg, int N, int b, int g, int G) {
-  constexpr int XST = NXX / 64;
-  XXLds& s = xxl_lds;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int n = __builtin_amdgcn_readfirstlane(N);
-  const int bu = __builtin_amdgcn_readfirstlane(b);
-  const int gu = __builtin_amdgcn_readfirstlane(g), gs = __builtin_amdgcn_readfirstlane(G);
-  const int k0 = XEB2 * bu;
-  const int k1 = n < k0 + XEB2 ? n : k0 + XEB2;
-  const int nb = (n + XEB2 - 1) / XEB2;
-  // the block's pivot columns (brought into range: after a failed barrier
-  // the list may be stale)
-  for (int j = tid; j < k1 - k0; j += XT) s.pcrec[k0 + j] = (int)((unsigned)pivg[k0 + j] % (unsigned)NXX);
-  __syncthreads();
-#pragma unroll 1
-  for (int bb = bu + 1 + ((gu - (bu + 1) % gs) + gs) % gs; bb < nb; bb += gs) {
-    double2 z[XXEM][XST];
-#pragma unroll
-    for (int m = 0; m < XXEM; ++m) {
-      const int row = XEB2 * bb + wu + XW * m;
-#pragma unroll
-      for (int q = 0; q < XST; ++q)
-        z[m][q] = row < n ? gld(&cg[(long long)row * NXX + 64 * q + lane]) : make_double2(0.0, 0.0);
-    }
-    xl_replay<XXCfg, XXEM>(z, k0, k1, lane, frec);
-#pragma unroll
-    for (int m = 0; m < XXEM; ++m) {
-      const int row = XEB2 * bb + wu + XW * m;
-      if (row < n) {
-#pragma unroll
-        for (int q = 0; q < XST; ++q) gst(&cg[(long long)row * NXX + 64 * q + lane], z[m][q]);
-      }
-    }
-  }
-}
 
 template <int STEPPER>
 __global__ __launch_bounds__(XT, 1) void forward_xxl_group_kernel(LargeArgs A, XlGroup X) {
