@@ -533,7 +533,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (P->xl_group > 1 &&
        (e = hipMalloc(&P->d_xg_wg, (size_t)XG_WG_BYTES * P->xl_group * P->xl_pairs.size())) != hipSuccess) ||
       (P->xl_group > 1 &&
-       (e = hipMalloc(&P->d_xg_cnt, sizeof(unsigned) * 16 * P->xl_pairs.size())) != hipSuccess) ||
+       (e = hipMalloc(&P->d_xg_cnt, sizeof(unsigned) * XG_CTR_WORDS * P->xl_pairs.size())) != hipSuccess) ||
       (!P->xxl_pairs.empty() &&
        (e = hipMalloc(&P->d_xxl_pairs, sizeof(int) * P->xxl_pairs.size())) != hipSuccess) ||
       (!P->xxl_pairs.empty() &&
@@ -541,7 +541,7 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (!P->xxl_pairs.empty() &&
        (e = hipMalloc(&P->d_xxg_wg, (size_t)XXG_WG_BYTES * P->xxl_group * P->xxl_pairs.size())) != hipSuccess) ||
       (!P->xxl_pairs.empty() &&
-       (e = hipMalloc(&P->d_xxg_cnt, sizeof(unsigned) * 16 * P->xxl_pairs.size())) != hipSuccess) ||
+       (e = hipMalloc(&P->d_xxg_cnt, sizeof(unsigned) * XG_CTR_WORDS * P->xxl_pairs.size())) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_large_pairs, sizeof(int) * n_large)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_large_plain, sizeof(int) * n_large)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_lscratch, (size_t)LSLOT_BYTES * P->scratch_slots)) != hipSuccess) ||

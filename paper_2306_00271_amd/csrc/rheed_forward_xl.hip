@@ -67,7 +67,6 @@ struct XLds {
   int pcrec[NX];                  // pivot column of every elimination step
   int pos[NX];                    // pivot step of every column in the last elimination
   double2 xv[NX];                 // first column of the inverse in the reflection
-  unsigned long long umask[NX / 64];  // group elimination: columns already pivots (workgroup 0)
   unsigned long long bnorm_bits;  // ||Gamma Q - iP||_inf and ||x||_inf of the reflection
   unsigned long long xnorm_bits;
   int flag_singular;
@@ -463,6 +462,7 @@ __device__ __noinline__ void xl_elim_record(const double2* __restrict__ cg, cons
         z[m][q] = v;
       }
     }
+    __syncthreads();  // the previous block's last multipliers are stored
     xl_replay<C, XEMT>(z, 0, k0, lane, frec);
     xl_record_steps<C>(z, um, k0, n < k0 + XEBT ? n : k0 + XEBT, n, frec);
   }
@@ -510,90 +510,6 @@ __device__ __noinline__ void xl_replay_p(double2* __restrict__ cg, double2* __re
   __syncthreads();
 }
 
-// The transformation's elimination of Q (Sec. 3.2) spread over a pair's
-// group in blocks of XW * C::XEMT steps (a right-looking order of the same
-// column operations): workgroup 0 takes row block b, whose rows already
-// carry every earlier step, and records its steps (multipliers to frec,
-// pivot columns to the pair's list); after a barrier every workgroup applies
-// those steps to the rows of the later blocks it owns (block b' by workgroup
-// b' mod G) and writes them back, before the next barrier.  Every row meets
-// the same operations in the same order as in the one-workgroup elimination,
-// so the multipliers are the same.  c holds the partly eliminated rows
-// meanwhile; the replay on P that follows sets it to I.
-
-// Workgroup 0: the steps of row block b.
-template <class C>
-__device__ __noinline__ void xl_record_block(const double2* __restrict__ cg, double2* __restrict__ frec,
-                                             int* __restrict__ pivg, int N, int b) {
-  constexpr int NXT = C::NXT, XST = NXT / 64, XEMT = C::XEMT, XEBT = XW * XEMT;
-  auto& s = C::lds();
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int n = __builtin_amdgcn_readfirstlane(N);
-  const int k0 = XEBT * __builtin_amdgcn_readfirstlane(b);
-  const int k1 = n < k0 + XEBT ? n : k0 + XEBT;
-  __syncthreads();  // the used-column words of the previous block are written
-  unsigned long long um[XST];
-#pragma unroll
-  for (int q = 0; q < XST; ++q) um[q] = s.umask[q];
-  double2 z[XEMT][XST];
-#pragma unroll
-  for (int m = 0; m < XEMT; ++m) {
-    const int row = k0 + wu + XW * m;
-#pragma unroll
-    for (int q = 0; q < XST; ++q)
-      z[m][q] = row < n ? gld(&cg[(long long)row * NXT + 64 * q + lane]) : make_double2(0.0, 0.0);
-  }
-  xl_record_steps<C>(z, um, k0, k1, n, frec);
-  __syncthreads();
-  if (tid == 0) {
-#pragma unroll
-    for (int q = 0; q < XST; ++q) s.umask[q] = um[q];
-  }
-  for (int j = tid; j < k1 - k0; j += XT) pivg[k0 + j] = s.pcrec[k0 + j];
-}
-
-// Every workgroup: the steps of block b on the rows of the later blocks it
-// owns.
-template <class C>
-__device__ __noinline__ void xl_apply_block(double2* __restrict__ cg, const double2* __restrict__ frec,
-                                            const int* __restrict__ pivg, int N, int b, int g, int G) {
-  constexpr int NXT = C::NXT, XST = NXT / 64, XEMT = C::XEMT, XEBT = XW * XEMT;
-  auto& s = C::lds();
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int n = __builtin_amdgcn_readfirstlane(N);
-  const int bu = __builtin_amdgcn_readfirstlane(b);
-  const int gu = __builtin_amdgcn_readfirstlane(g), gs = __builtin_amdgcn_readfirstlane(G);
-  const int k0 = XEBT * bu;
-  const int k1 = n < k0 + XEBT ? n : k0 + XEBT;
-  const int nb = (n + XEBT - 1) / XEBT;
-  // the block's pivot columns (brought into range: after a failed barrier
-  // the list may be stale)
-  for (int j = tid; j < k1 - k0; j += XT) s.pcrec[k0 + j] = (int)((unsigned)pivg[k0 + j] % (unsigned)NXT);
-  __syncthreads();
-#pragma unroll 1
-  for (int bb = bu + 1 + ((gu - (bu + 1) % gs) + gs) % gs; bb < nb; bb += gs) {
-    double2 z[XEMT][XST];
-#pragma unroll
-    for (int m = 0; m < XEMT; ++m) {
-      const int row = XEBT * bb + wu + XW * m;
-#pragma unroll
-      for (int q = 0; q < XST; ++q)
-        z[m][q] = row < n ? gld(&cg[(long long)row * NXT + 64 * q + lane]) : make_double2(0.0, 0.0);
-    }
-    xl_replay<C, XEMT>(z, k0, k1, lane, frec);
-#pragma unroll
-    for (int m = 0; m < XEMT; ++m) {
-      const int row = XEBT * bb + wu + XW * m;
-      if (row < n) {
-#pragma unroll
-        for (int q = 0; q < XST; ++q) gst(&cg[(long long)row * NXT + 64 * q + lane], z[m][q]);
-      }
-    }
-  }
-}
-
 // Barrier of the G workgroups of one pair in a group launch: each raises the
 // pair's counter (an agent-scope release, so its stores are written back
 // first) and waits until all have reached `target` (G times the barriers so
@@ -625,23 +541,148 @@ __device__ __forceinline__ void xl_group_sync(unsigned* cnt, unsigned target, un
   __syncthreads();
 }
 
-// The block loop of the group elimination (ends after a barrier, with frec
-// and the pair's pivot list complete).
+// Bounded wait of a workgroup until *word >= target (thread 0 polls, then
+// acquires); gives up like xl_group_sync, and returns at once after an
+// earlier give-up.
 template <class C>
-__device__ __forceinline__ void xl_group_elim(double2* cg, double2* frec, int* pivg, int N, int g, int G,
-                                              unsigned* cnt, unsigned& nsync, unsigned* failw) {
-  constexpr int XEBT = XW * C::XEMT;
-  const int nb = (N + XEBT - 1) / XEBT;
-  if (g == 0 && threadIdx.x < C::NXT / 64) C::lds().umask[threadIdx.x] = 0;
+__device__ __forceinline__ void xl_wait_geq(const unsigned* word, unsigned target, unsigned* fail_word) {
+  if (threadIdx.x == 0) {
+    if (!C::lds().sync_fail) {
+      const long long t0 = wall_clock64();
+      int it = 0;
+      while (__hip_atomic_load(word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++it > C::SYNC_SPIN || wall_clock64() - t0 > C::SYNC_TICKS) {
+          C::lds().sync_fail = 1;
+          __hip_atomic_store(fail_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  }
+  __syncthreads();
+}
+
+// Publishes value in *word (one writer per word) once every wave's stores
+// are complete: an agent-scope release, so the stores are written back first.
+__device__ __forceinline__ void xl_publish(unsigned* word, unsigned value) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(word, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The transformation's elimination of Q (Sec. 3.2) spread over a pair's
+// group of G >= 2 workgroups in blocks of XW * C::XEMT steps, as a pipeline.
+// Row block bb belongs to workgroup 1 + bb mod (G - 1).  Workgroup 0 takes
+// the blocks in turn: it waits until the owner of block b has applied the
+// steps of block b - 2 to it, applies block b - 1's steps itself, records
+// block b's steps (multipliers to frec, pivot columns to the pair's list)
+// and publishes ctr[2] = e0 + b + 1.  Owner g, for each block b, waits for
+// that word, applies block b's steps to its blocks >= b + 2, writes them back
+// and publishes ctr[3 + g] = e0 + b + 1.  Every row meets the same column
+// operations in the same order as in the one-workgroup elimination, so the
+// multipliers are the same; c holds the partly eliminated rows meanwhile (the
+// replay on P that follows sets it to I).  e0 counts the pair's earlier
+// blocks, so the words only grow within a launch.
+
+// Workgroup 0's part.
+template <class C>
+__device__ __noinline__ void xl_pipe_record(const double2* __restrict__ cg, double2* __restrict__ frec,
+                                            int* __restrict__ pivg, int N, int G, unsigned* ctr, unsigned e0) {
+  constexpr int NXT = C::NXT, XST = NXT / 64, XEMT = C::XEMT, XEBT = XW * XEMT;
+  auto& s = C::lds();
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int n = __builtin_amdgcn_readfirstlane(N);
+  const int gs = __builtin_amdgcn_readfirstlane(G);
+  const int nb = (n + XEBT - 1) / XEBT;
+  unsigned long long um[XST];  // used columns (the same in every wave)
+#pragma unroll
+  for (int q = 0; q < XST; ++q) um[q] = 0;
 #pragma unroll 1
   for (int b = 0; b < nb; ++b) {
-    if (g == 0) xl_record_block<C>(cg, frec, pivg, N, b);
-    xl_group_sync<C>(cnt, G * ++nsync, failw);
-    if (b + 1 < nb) {
-      xl_apply_block<C>(cg, frec, pivg, N, b, g, G);
-      xl_group_sync<C>(cnt, G * ++nsync, failw);
+    const int k0 = XEBT * b, k1 = n < k0 + XEBT ? n : k0 + XEBT;
+    if (b >= 2) xl_wait_geq<C>(&ctr[3 + 1 + b % (gs - 1)], e0 + b - 1, ctr + 1);
+    double2 z[XEMT][XST];
+#pragma unroll
+    for (int m = 0; m < XEMT; ++m) {
+      const int row = k0 + wu + XW * m;
+#pragma unroll
+      for (int q = 0; q < XST; ++q)
+        z[m][q] = row < n ? gld(&cg[(long long)row * NXT + 64 * q + lane]) : make_double2(0.0, 0.0);
     }
+    if (b >= 1) {
+      __syncthreads();  // the previous block's last multipliers are stored
+      xl_replay<C, XEMT>(z, k0 - XEBT, k0, lane, frec);
+    }
+    xl_record_steps<C>(z, um, k0, k1, n, frec);
+    __syncthreads();
+    for (int j = tid; j < k1 - k0; j += XT) pivg[k0 + j] = s.pcrec[k0 + j];
+    xl_publish(&ctr[2], e0 + b + 1);
   }
+}
+
+// Owner g's part (1 <= g < G).
+template <class C>
+__device__ __noinline__ void xl_pipe_apply(double2* __restrict__ cg, const double2* __restrict__ frec,
+                                           const int* __restrict__ pivg, int N, int g, int G, unsigned* ctr,
+                                           unsigned e0) {
+  constexpr int NXT = C::NXT, XST = NXT / 64, XEMT = C::XEMT, XEBT = XW * XEMT;
+  auto& s = C::lds();
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int n = __builtin_amdgcn_readfirstlane(N);
+  const int gu = __builtin_amdgcn_readfirstlane(g), go = __builtin_amdgcn_readfirstlane(G) - 1;
+  const int nb = (n + XEBT - 1) / XEBT;
+#pragma unroll 1
+  for (int b = 0; b + 2 < nb; ++b) {
+    const int k0 = XEBT * b, k1 = n < k0 + XEBT ? n : k0 + XEBT;
+    xl_wait_geq<C>(&ctr[2], e0 + b + 1, ctr + 1);
+    // the block's pivot columns (brought into range: after a failed wait the
+    // list may be stale)
+    for (int j = tid; j < k1 - k0; j += XT) s.pcrec[k0 + j] = (int)((unsigned)pivg[k0 + j] % (unsigned)NXT);
+    __syncthreads();
+#pragma unroll 1
+    for (int bb = b + 2 + (((gu - 1) - (b + 2) % go) + go) % go; bb < nb; bb += go) {
+      double2 z[XEMT][XST];
+#pragma unroll
+      for (int m = 0; m < XEMT; ++m) {
+        const int row = XEBT * bb + wu + XW * m;
+#pragma unroll
+        for (int q = 0; q < XST; ++q)
+          z[m][q] = row < n ? gld(&cg[(long long)row * NXT + 64 * q + lane]) : make_double2(0.0, 0.0);
+      }
+      xl_replay<C, XEMT>(z, k0, k1, lane, frec);
+#pragma unroll
+      for (int m = 0; m < XEMT; ++m) {
+        const int row = XEBT * bb + wu + XW * m;
+        if (row < n) {
+#pragma unroll
+          for (int q = 0; q < XST; ++q) gst(&cg[(long long)row * NXT + 64 * q + lane], z[m][q]);
+        }
+      }
+    }
+    xl_publish(&ctr[3 + gu], e0 + b + 1);
+  }
+}
+
+// The group elimination (ends after a barrier, with frec and the pair's
+// pivot list complete); a group of one runs the one-workgroup elimination.
+template <class C>
+__device__ __forceinline__ void xl_group_elim(double2* cg, const double2* dg, double2* frec, int* pivg, int N,
+                                              int g, int G, unsigned* ctr, unsigned& nsync, unsigned& eblk) {
+  constexpr int XEBT = XW * C::XEMT;
+  if (G == 1) {
+    xl_elim_record<typename C::ElimCfg>(cg, dg, frec, N, 0);
+    for (int j = threadIdx.x; j < N; j += XT) pivg[j] = C::lds().pcrec[j];
+  } else if (g == 0) {
+    xl_pipe_record<C>(cg, frec, pivg, N, G, ctr, eblk);
+  } else {
+    xl_pipe_apply<C>(cg, frec, pivg, N, g, G, ctr, eblk);
+  }
+  eblk += (N + XEBT - 1) / XEBT;
+  xl_group_sync<C>(ctr, G * ++nsync, ctr + 1);
 }
 
 // Q^{-1} (or B^{-1} of the reflection) after xl_elim_record: the recorded
@@ -727,9 +768,10 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
   double2* __restrict__ frec = reinterpret_cast<double2*>(pm + C::PAIR_F);
   double2* __restrict__ gm = reinterpret_cast<double2*>(wm);
   int* pivg = reinterpret_cast<int*>(pm + C::PAIR_PIV);  // GRP: the pivot list of the last elimination
-  unsigned* cnt = GRP ? X.counters + 16LL * pi : nullptr;
+  unsigned* cnt = GRP ? X.counters + (long long)XG_CTR_WORDS * pi : nullptr;
   unsigned* failw = GRP ? cnt + 1 : nullptr;
-  unsigned nsync = 0;
+  unsigned nsync = 0;  // group barriers so far
+  unsigned eblk = 0;   // elimination blocks so far (the pipeline's progress words count them)
   char* pws = SAVE ? a.ws + (long long)p * a.ck.pair_stride : nullptr;
   constexpr long long MATB = (long long)NX * NX * sizeof(double2);
   const StructDev S = a.structs[a.pair_struct[p]];
@@ -843,7 +885,7 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
       if constexpr (GRP) {
         // the elimination spread over the group (ends after a barrier); all
         // then replay it on their row blocks of P
-        xl_group_elim<C>(cg, frec, pivg, N, g, G, cnt, nsync, failw);
+        xl_group_elim<C>(cg, dg, frec, pivg, N, g, G, cnt, nsync, eblk);
         {
           for (int j = tid; j < NXT; j += XT) {
             // brought into range: after a failed barrier the list may be stale
@@ -1000,7 +1042,7 @@ __global__ __launch_bounds__(XT, 1) void forward_xl_group_kernel(LargeArgs A, Xl
 }
 
 __global__ void xl_group_reset_kernel(unsigned* counters, int n) {
-  for (int e = threadIdx.x; e < 16 * n; e += blockDim.x) counters[e] = 0u;
+  for (int e = threadIdx.x; e < XG_CTR_WORDS * n; e += blockDim.x) counters[e] = 0u;
 }
 
 }  // namespace

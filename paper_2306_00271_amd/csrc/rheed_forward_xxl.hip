@@ -47,7 +47,6 @@ struct XXLds {
   int pcrec[NXX];                   // pivot column of every elimination step
   int pos[NXX];                     // pivot step of every column in the last elimination
   double2 xv[NXX];                  // first column of the inverse in the reflection
-  unsigned long long umask[NXX / 64];  // group elimination: columns already pivots (workgroup 0)
   unsigned long long bnorm_bits;
   unsigned long long xnorm_bits;
   int flag_singular;

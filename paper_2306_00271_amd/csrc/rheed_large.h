@@ -48,8 +48,11 @@ int forward_xl_slots(int device);
 // pair share the pair's state.  Per pair: c, c', the multipliers and the
 // pivot list (XG_PAIR_BYTES); per workgroup: the stage products of one
 // column block and two buffers of row-sum partials (XG_WG_BYTES); per pair
-// 16 counter words (barrier count, failure word), cleared by the launch.
+// XG_CTR_WORDS counter words (barrier count, failure word, and the progress
+// words of the elimination pipeline), cleared by the launch.
 constexpr long long XG_STAGE_BYTES = 6LL * NX * 16 * 16;
+constexpr int XG_CTR_WORDS = 64;  // per pair: [0] barrier count, [1] failure word, [2] blocks recorded,
+                                  // [3 + g] blocks applied by workgroup g (g < 61)
 constexpr long long XG_PAIR_BYTES = XSLOT_G + 4LL * NX;
 constexpr long long XG_WG_BYTES = XG_STAGE_BYTES + 2LL * 2 * NX * 8;
 struct XlGroup {
@@ -65,7 +68,7 @@ int forward_xl_group_max_workgroups(int device);  // co-resident workgroups of a
 // 256 < N <= 576 (RK steppers, forward only), group launch only: a pair's
 // c, c', multipliers and pivot list (XXG_PAIR_BYTES); per workgroup the 7
 // stage products and the stage input of one column block and two buffers
-// of row-sum partials (XXG_WG_BYTES); 16 counter words per pair.
+// of row-sum partials (XXG_WG_BYTES); XG_CTR_WORDS counter words per pair.
 constexpr int NXX = 576;        // padded beam count of the kernel for 256 < N <= 576
 constexpr int MAXBOXXX = 4096;  // rod-difference entries per node table row of that kernel
 constexpr long long XXG_C = 0;

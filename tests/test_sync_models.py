@@ -144,3 +144,84 @@ def test_group_barrier_reports_give_ups_before_the_last(p_give_up):
             assert report == "lost"
         if p_give_up == 0.0:
             assert report == "ok" and not gave_up_at
+
+
+def _run_pipeline(nb, G, rng, p_give_up):
+    """The group elimination's pipeline (G >= 2 workgroups, nb row blocks of
+    16 steps).  Row block bb belongs to workgroup 1 + bb mod (G - 1).
+    Workgroup 0, for each block b: waits until the owner of b has published
+    that it applied block b - 2 (b >= 2), applies block b - 1 itself (b >= 1),
+    records b and publishes `recorded` = b + 1.  Owner g, for each b up to
+    nb - 3: waits for `recorded` >= b + 1, applies block b to its blocks
+    >= b + 2, publishes `applied[g]` = b + 1.  A wait may give up (then the
+    workgroup stops waiting and sets its failure flag).  Returns the order
+    in which each row block received the blocks' steps, the blocks whose
+    record saw an incompletely updated row block, reads of unrecorded
+    blocks, and the failure flags."""
+    owner = lambda bb: 1 + bb % (G - 1)
+    recorded = [0]
+    applied = [0] * G
+    got = [[] for _ in range(nb)]        # blocks applied to each row block, in order
+    bad_record = []                      # (b, what the rows carried) when recorded too early
+    bad_read = []                        # (g, b) applies of a block not yet recorded
+    failed = [False] * G
+
+    def wait(g, pred):
+        while not failed[g] and not pred():
+            if rng.random() < p_give_up:
+                failed[g] = True
+                break
+            yield
+
+    def wg0():
+        for b in range(nb):
+            if b >= 2:
+                yield from wait(0, lambda: applied[owner(b)] >= b - 1)
+            if b >= 1:
+                got[b].append(b - 1)
+            if got[b] != list(range(b)) and not any(failed):
+                bad_record.append((b, list(got[b])))
+            yield
+            recorded[0] = b + 1
+            yield
+
+    def own(g):
+        for b in range(nb - 2):
+            yield from wait(g, lambda: recorded[0] >= b + 1)
+            if recorded[0] < b + 1 and not failed[g]:
+                bad_read.append((g, b))
+            for bb in range(b + 2, nb):
+                if owner(bb) == g:
+                    got[bb].append(b)
+                    yield
+            applied[g] = b + 1
+            yield
+
+    procs = [wg0()] + [own(g) for g in range(1, G)]
+    steps = 0
+    while procs:
+        p = rng.choice(procs)
+        try:
+            next(p)
+        except StopIteration:
+            procs.remove(p)
+        steps += 1
+        assert steps < 500000, "the model did not end"
+    return got, bad_record, bad_read, failed
+
+
+@pytest.mark.parametrize("p_give_up", [0.0, 0.01, 0.2])
+def test_group_elimination_pipeline_orders_every_row_block(p_give_up):
+    """Without a give-up every row block has received the steps of every
+    earlier block, in order, when workgroup 0 records it, and no owner
+    applies a block before it is recorded; every run ends, also when waits
+    give up."""
+    rng = random.Random(23)
+    for _ in range(800):
+        nb, G = rng.randint(1, 14), rng.randint(2, 9)
+        got, bad_record, bad_read, failed = _run_pipeline(nb, G, rng, p_give_up)
+        if not any(failed):
+            assert not bad_record and not bad_read
+            assert all(got[bb] == list(range(bb)) for bb in range(nb))
+        if p_give_up == 0.0:
+            assert not any(failed)
