@@ -974,7 +974,9 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
     s.xnorm_bits = 0;
   }
   __syncthreads();
-  for (int j = tid; j < a.ld; j += XT) {
+  // row j of the reflection's outputs (a thread per row, or a loop over rows
+  // when the width exceeds the workgroup)
+  auto out_row = [&](int j) {
     double eta = 0.0;
     double2 rj = make_double2(0.0, 0.0);
     if (j < N) {
@@ -1001,6 +1003,11 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
     }
     a.intensity[(long long)p * a.ld + j] = eta;
     if (a.rho) a.rho[(long long)p * a.ld + j] = rj;
+  };
+  if constexpr (NXT <= XT) {
+    if (tid < a.ld) out_row(tid);
+  } else {
+    for (int j = tid; j < a.ld; j += XT) out_row(j);
   }
   __syncthreads();
   const bool brk = !(__longlong_as_double((long long)s.bnorm_bits) * __longlong_as_double((long long)s.xnorm_bits) <=

@@ -125,3 +125,18 @@ def test_xl_refusals():
     ws = torch.empty(1024, dtype=torch.uint8, device=dev)
     with pytest.raises(RheedError, match="workspace of"):
         plan.forward(U, api.angles_for(wl, dev), workspace=ws)
+
+
+def test_group_of_two_matches_one_workgroup():
+    """128 pairs of N = 150 get groups of 2 (the elimination pipeline with a
+    single owner): the same curves and transformation counts as one
+    workgroup per pair."""
+    wl = small_2d(n_beams=150, n_slices=12, thickness=1.2, n_layers=1, n_angles=128, seed=9)
+    grp = gpu_forward(wl, stepper="rk6", layout="auto")
+    one = gpu_forward(wl, stepper="rk6", layout="whole")
+    assert grp["plan"].info.xl_group == 2 and one["plan"].info.xl_group == 1
+    assert (grp["status"] == 0).all() and (one["status"] == 0).all()
+    assert grp["n_rhst"].tolist() == one["n_rhst"].tolist()
+    d = np.abs(grp["intensity"] - one["intensity"]).max()
+    print(f"[parity-xl] N=150, 128 pairs, groups of 2 vs one workgroup: max |diff| = {d:.3e}", flush=True)
+    np.testing.assert_allclose(grp["intensity"], one["intensity"], rtol=0.0, atol=1e-13)

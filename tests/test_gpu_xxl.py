@@ -100,3 +100,22 @@ def test_xxl_refusals():
     many = dataclasses.replace(wl, theta0=np.linspace(0.01, 0.1, 300))
     with pytest.raises(RheedError, match="pairs per plan"):
         api.plan_for(many, stepper="rk6")
+
+
+@pytest.mark.parametrize("n_angles,group", [(100, 2), (200, 1)])
+def test_many_pairs_small_groups(n_angles, group):
+    """Enough pairs that each gets a group of 2 (one owner in the
+    elimination pipeline) or of 1 (the one-workgroup elimination): N = 257
+    on a thin slab, sampled pairs against the oracle, every pair valid."""
+    wl = small_2d(n_beams=257, n_slices=6, thickness=0.6, n_layers=1, n_angles=n_angles, m=7)
+    res = gpu_forward(wl, stepper="rk6")
+    assert res["plan"].info.xxl_group == group
+    assert (res["status"] == 0).all()
+    assert physical(res["intensity"][:, :257], wl.absorption).all()
+    idx = [0, n_angles // 2, n_angles - 1]
+    ref, _, nr = oracle_forward(wl, angle_idx=idx, stepper="rk6")
+    e = eacc(res["intensity"][idx, :257], ref)
+    _report(f"N=257, {n_angles} pairs on groups of {group}, rhst gpu {res['n_rhst'][idx].tolist()} "
+            f"oracle {nr.tolist()}", e)
+    assert e <= TOL
+    assert res["n_rhst"][idx].tolist() == nr.tolist()
