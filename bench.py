@@ -469,7 +469,25 @@ def n199_forward(steps=1, cpu=True):
            "rhst_per_pair": round(float(nr.mean()), 1), "xl_slots": int(plan.info.xl_slots),
            "invalid_pairs": invalid_pairs(out["intensity"], out["status"], wl.absorption),
            "projected_s_whole_workload": round(64 * ms / 1e3, 1)}
-    del plan, U
+    # the same batch with the stage products in FP32 (the lower-precision
+    # evaluation; everything else FP64)
+    p32 = api.plan_for(wl, stepper="rk6", stage_precision="fp32")
+    U32 = p32.potential(api.atoms_for(wl, dev))
+    p32.forward(U32, ang)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    o32 = p32.forward(U32, ang)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms32 = e0.elapsed_time(e1)
+    a64 = out["intensity"][:, :st.n_beams].cpu().numpy()
+    a32 = o32["intensity"][:, :st.n_beams].cpu().numpy()
+    e32 = float(np.max(np.linalg.norm(a32 - a64, axis=1)) / np.max(np.linalg.norm(a64, axis=1)))
+    res["fp32_stages"] = {"ms_per_forward": round(ms32, 2), "speedup": round(ms / ms32, 3),
+                          "eacc_vs_fp64_stages": float(f"{e32:.3e}"),
+                          "invalid_pairs": invalid_pairs(o32["intensity"], o32["status"], wl.absorption)}
+    print(f"[n199] FP32 stages: {ms32:.1f} ms, eacc vs FP64 {e32:.2e}", file=sys.stderr, flush=True)
+    del plan, U, p32, U32
     # one pair alone (the paper's single-angle case): on one workgroup, and
     # on a group of workgroups that step its column blocks side by side
     single = dataclasses.replace(wl, theta0=wl.theta0[100:101])

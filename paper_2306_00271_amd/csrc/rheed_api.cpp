@@ -242,13 +242,14 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       delete P;
       return fail(RHEED_E_UNSUPPORTED, buf);
     }
-    if (opts->stage_precision == RHEED_STAGES_FP32 && st.n_beams > NP) {
+    if (opts->stage_precision == RHEED_STAGES_FP32 && ((st.n_beams > NP && st.n_beams <= NL) || st.n_beams > NX)) {
       delete P;
-      return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) + ": FP32 stage products need N <= 64");
+      return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) +
+                                           ": FP32 stage products need N <= 64 or 128 < N <= 256");
     }
-    if (st.n_beams > NL && (splitting || opts->stage_precision != RHEED_STAGES_FP64)) {
+    if (st.n_beams > NL && splitting) {
       delete P;
-      return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) + ": N > 128 needs an RK stepper with FP64 stages");
+      return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) + ": N > 128 needs an RK stepper");
     }
     if (splitting && st.n_beams > NP && opts->stepper != RHEED_SP4) {
       delete P;
@@ -817,9 +818,9 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
       xg.wg_mem = P->d_xg_wg;
       xg.counters = P->d_xg_cnt;
       xg.group = P->xl_group;
-      e = launch_forward_xl_group((int)P->opts.stepper, xa, xg, st);
+      e = launch_forward_xl_group((int)P->opts.stepper | (f32 ? 8 : 0), xa, xg, st);
     } else {
-      e = launch_forward_xl((int)P->opts.stepper, xa, st);
+      e = launch_forward_xl((int)P->opts.stepper | (f32 ? 8 : 0), xa, st);
     }
     if (e != hipSuccess) return hip_fail(e, "forward launch (N > 128)");
   }

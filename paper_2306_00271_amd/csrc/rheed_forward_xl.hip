@@ -81,9 +81,21 @@ __device__ __forceinline__ void xl_load_table(int sl, const double2* __restrict_
   for (int e = threadIdx.x; e < box; e += XT) xl_lds.tb[sl][e] = Us[nn * box + e];
 }
 
+// Matrix-core step of a stage product: FP64, or with F32 the operands
+// rounded to FP32 on v_mfma_f32_16x16x4f32 (the lower-precision evaluation;
+// the A rows are then supplied in a_row<true> order, so that register v
+// holds the same row as in FP64).
+__device__ __forceinline__ d4 mma(double a, double b, d4 c) { return mfma(a, b, c); }
+__device__ __forceinline__ f4 mma(double a, double b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, c, 0, 0, 0);
+}
+template <bool F32> struct XAcc { using T = d4; };
+template <> struct XAcc<true> { using T = f4; };
+
 // One slice of the RK step for the column blocks cb0, cb0 + cbs, ... that
 // hold columns < N; s.rdg / s.rof get those blocks' share of the row sums.
-template <int STEPPER>
+// F32: the stage products U X in FP32 (everything else FP64).
+template <int STEPPER, bool F32>
 __device__ __noinline__ void xl_slice(double2* __restrict__ cg, double2* __restrict__ dg, double2* __restrict__ gm,
                                       const double2* __restrict__ Us, int nb, int box, double h, int N,
                                       const int (&base)[2], int cb0, int cbs) {
@@ -159,10 +171,10 @@ __device__ __noinline__ void xl_slice(double2* __restrict__ cg, double2* __restr
       __syncthreads();
       // G_r = U X_r + Gamma^2 X_r on the two tiles (3-real-product form)
       const double2* __restrict__ tsl = s.tb[sl];
-      d4 p1[2], p2[2], p3[2];
+      typename XAcc<F32>::T p1[2], p2[2], p3[2];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) p1[t] = p2[t] = p3[t] = d4{0, 0, 0, 0};
-      const int ra0 = 32 * w + (lane & 15), ra1 = ra0 + 16;  // A-operand rows of the two tiles
+      for (int t = 0; t < 2; ++t) p1[t] = p2[t] = p3[t] = {0, 0, 0, 0};
+      const int ra0 = 32 * w + a_row<F32>(lane & 15), ra1 = ra0 + 16;  // A-operand rows of the two tiles
 #pragma unroll 2
       for (int q = 0; q < nq; ++q) {
         const int k = 4 * q + (lane >> 4);
@@ -172,12 +184,12 @@ __device__ __noinline__ void xl_slice(double2* __restrict__ cg, double2* __restr
         const double2 u0 = tsl[(kin && ra0 < N) ? base[0] - ok : box];
         const double2 u1 = tsl[(kin && ra1 < N) ? base[1] - ok : box];
         const double xs = x.x + x.y;
-        p1[0] = mfma(u0.x, x.x, p1[0]);
-        p2[0] = mfma(u0.y, x.y, p2[0]);
-        p3[0] = mfma(u0.x + u0.y, xs, p3[0]);
-        p1[1] = mfma(u1.x, x.x, p1[1]);
-        p2[1] = mfma(u1.y, x.y, p2[1]);
-        p3[1] = mfma(u1.x + u1.y, xs, p3[1]);
+        p1[0] = mma(u0.x, x.x, p1[0]);
+        p2[0] = mma(u0.y, x.y, p2[0]);
+        p3[0] = mma(u0.x + u0.y, xs, p3[0]);
+        p1[1] = mma(u1.x, x.x, p1[1]);
+        p2[1] = mma(u1.y, x.y, p2[1]);
+        p3[1] = mma(u1.x + u1.y, xs, p3[1]);
       }
 #pragma unroll
       for (int t = 0; t < 2; ++t)
@@ -185,8 +197,9 @@ __device__ __noinline__ void xl_slice(double2* __restrict__ cg, double2* __restr
         for (int v = 0; v < 4; ++v) {
           const int row = 32 * w + 16 * t + 4 * v + (lane >> 4);
           const double2 x = s.xb[row * XCB + (lane & 15)];
-          const double gr = p1[t][v] - p2[t][v] + g2[t][v] * x.x;
-          const double gi = p3[t][v] - p1[t][v] - p2[t][v] + g2[t][v] * x.y;
+          const double a1 = p1[t][v], a2 = p2[t][v], a3 = p3[t][v];
+          const double gr = a1 - a2 + g2[t][v] * x.x;
+          const double gi = a3 - a1 - a2 + g2[t][v] * x.y;
           if (r + 1 < T::stages) gst(&gm[(r * NX + row) * XCB + (lane & 15)], make_double2(gr, gi));
           if (T::ba(r) != 0.0) {
             cnr[t][v] -= hh * T::ba(r) * gr;
@@ -255,18 +268,20 @@ struct XCfg {
   using Base = int[2];
   // table index of U_{ik} = u_{g_i - g_k} is base_i - off_k for the A-operand
   // rows of the thread's two tiles
+  template <bool F32>
   static __device__ __forceinline__ void bases(Base& base, int hd, int kd, int w, int lane) {
     const int Wd = 2 * kd + 1;
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      const int i = 32 * w + 16 * t + (lane & 15);
+      const int i = 32 * w + 16 * t + a_row<F32>(lane & 15);
       base[t] = (xl_lds.bhk[i][0] + hd) * Wd + (xl_lds.bhk[i][1] + kd);
     }
   }
+  // STEPPER: bits 0-2 the method, bit 3 the FP32 stage products
   template <int STEPPER>
   static __device__ __forceinline__ void slice(double2* cg, double2* dg, double2* gm, const double2* Us, int nb,
                                                int box, double h, int N, const Base& base, int cb0, int cbs) {
-    xl_slice<STEPPER>(cg, dg, gm, Us, nb, box, h, N, base, cb0, cbs);
+    xl_slice<(STEPPER & 7), (STEPPER & F32_STAGES) != 0>(cg, dg, gm, Us, nb, box, h, N, base, cb0, cbs);
   }
 };
 
@@ -755,7 +770,9 @@ template <class C, int STEPPER, bool GRP, bool SAVE = false>
 __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup& X, int pi, int g) {
   static_assert(!SAVE || C::NXT == NX, "states are kept for N <= 256");
   static_assert(GRP || C::NXT == NX, "the one-workgroup launch is for N <= 256");
-  using T = LTab<STEPPER>;
+  constexpr bool F32 = (STEPPER & F32_STAGES) != 0;  // FP32 stage products
+  static_assert(!(F32 && SAVE), "the adjoint's states come from FP64 stages");
+  using T = LTab<(STEPPER & 7)>;
   constexpr int NXT = C::NXT, XST = NXT / 64;
   const FwdArgs& a = A.f;
   auto& s = C::lds();
@@ -810,7 +827,7 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
   }
   __syncthreads();
   typename C::Base base;
-  C::bases(base, S.hd, S.kd, w, lane);
+  C::template bases<F32>(base, S.hd, S.kd, w, lane);
   // Z0 = [I; i Gamma] (spans the columns of S^{-1}[I; O] of Algorithm 1); in
   // a group launch each workgroup writes its share of the rows
   for (int e = tid + XT * g; e < NXT * NXT; e += XT * G) {
@@ -1057,31 +1074,42 @@ __global__ void xl_group_reset_kernel(unsigned* counters, int n) {
 hipError_t launch_forward_xl(int stepper, const LargeArgs& a, hipStream_t stream) {
   if (a.f.n_pairs < 1) return hipSuccess;
   const int grid = a.f.n_pairs < a.n_slots ? a.f.n_pairs : a.n_slots;
-  if (grid < 1 || (stepper != 0 && stepper != 1)) return hipErrorInvalidValue;
+  if (grid < 1 || (stepper != 0 && stepper != 1 && stepper != (0 | F32_STAGES) && stepper != (1 | F32_STAGES)))
+    return hipErrorInvalidValue;
   const bool save = a.f.ws != nullptr;
+  if (save && (stepper & F32_STAGES)) return hipErrorInvalidValue;
   if (stepper == 0 && save)
     hipLaunchKernelGGL((forward_xl_kernel<0, true>), dim3(grid), dim3(XT), 0, stream, a);
   else if (stepper == 0)
     hipLaunchKernelGGL((forward_xl_kernel<0, false>), dim3(grid), dim3(XT), 0, stream, a);
-  else if (save)
+  else if (stepper == 1 && save)
     hipLaunchKernelGGL((forward_xl_kernel<1, true>), dim3(grid), dim3(XT), 0, stream, a);
-  else
+  else if (stepper == 1)
     hipLaunchKernelGGL((forward_xl_kernel<1, false>), dim3(grid), dim3(XT), 0, stream, a);
+  else if (stepper == (0 | F32_STAGES))
+    hipLaunchKernelGGL((forward_xl_kernel<0 | F32_STAGES, false>), dim3(grid), dim3(XT), 0, stream, a);
+  else
+    hipLaunchKernelGGL((forward_xl_kernel<1 | F32_STAGES, false>), dim3(grid), dim3(XT), 0, stream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_forward_xl_group(int stepper, const LargeArgs& a, const XlGroup& x, hipStream_t stream) {
   if (a.f.n_pairs < 1) return hipSuccess;
-  if (x.group < 1 || (stepper != 0 && stepper != 1)) return hipErrorInvalidValue;
+  const bool save = a.f.ws != nullptr;
+  const void* f = nullptr;
+  if (stepper == 0) f = save ? reinterpret_cast<const void*>(&forward_xl_group_kernel<0, true>)
+                             : reinterpret_cast<const void*>(&forward_xl_group_kernel<0, false>);
+  else if (stepper == 1) f = save ? reinterpret_cast<const void*>(&forward_xl_group_kernel<1, true>)
+                                  : reinterpret_cast<const void*>(&forward_xl_group_kernel<1, false>);
+  else if (stepper == (0 | F32_STAGES) && !save)
+    f = reinterpret_cast<const void*>(&forward_xl_group_kernel<0 | F32_STAGES, false>);
+  else if (stepper == (1 | F32_STAGES) && !save)
+    f = reinterpret_cast<const void*>(&forward_xl_group_kernel<1 | F32_STAGES, false>);
+  if (x.group < 1 || !f) return hipErrorInvalidValue;
   hipLaunchKernelGGL(xl_group_reset_kernel, dim3(1), dim3(256), 0, stream, x.counters, a.f.n_pairs);
   LargeArgs aa = a;
   XlGroup xx = x;
   void* params[] = {&aa, &xx};
-  const bool save = a.f.ws != nullptr;
-  const void* f = stepper == 0 ? (save ? reinterpret_cast<const void*>(&forward_xl_group_kernel<0, true>)
-                                       : reinterpret_cast<const void*>(&forward_xl_group_kernel<0, false>))
-                               : (save ? reinterpret_cast<const void*>(&forward_xl_group_kernel<1, true>)
-                                       : reinterpret_cast<const void*>(&forward_xl_group_kernel<1, false>));
   return hipLaunchCooperativeKernel(f, dim3(a.f.n_pairs * x.group), dim3(XT), params, 0, stream);
 }
 

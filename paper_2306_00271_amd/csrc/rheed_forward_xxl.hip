@@ -227,7 +227,9 @@ struct XXCfg {
   using Base = int[XXTP];
   // table index of U_{ik} = u_{g_i - g_k} is base_i - off_k for the A-operand
   // rows of the wave's tiles (rows beyond NXX: tiles that do not exist)
+  template <bool F32>
   static __device__ __forceinline__ void bases(Base& base, int hd, int kd, int w, int lane) {
+    static_assert(!F32, "FP64 stage products only at this width");
     const int Wd = 2 * kd + 1;
 #pragma unroll
     for (int j = 0; j < XXTP; ++j) {
