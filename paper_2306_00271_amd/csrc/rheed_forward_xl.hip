@@ -259,6 +259,7 @@ struct XCfg {
   static constexpr int TSLOTS = 2;      // node-table slots in LDS
   static constexpr long long SYNC_TICKS = XCH_TICKS;  // a group barrier's wait gives up after this
   static constexpr int SYNC_SPIN = XCH_SPIN;          // or after this many polls
+  static constexpr int FROWS = XCB;                   // multiplier rows a replay stages in the stage-input buffer
   using ElimCfg = XCfg;                               // the one-workgroup eliminations (and the reflection's)
   static constexpr long long PAIR_C = XSLOT_C, PAIR_D = XSLOT_D, PAIR_F = XSLOT_F, PAIR_PIV = XSLOT_G;
   static constexpr long long PAIR_BYTES = XG_PAIR_BYTES;
@@ -336,17 +337,35 @@ __device__ __forceinline__ void xl_update(double2 (&z)[R][XSN], int pc, const do
   }
 }
 
-// The recorded column operations of steps [k0, k1) on the rows in z.
+// The recorded column operations of steps [k0, k1) on the rows in z.  The
+// multiplier rows are staged through the stage-input buffer (free during
+// every replay) C::FROWS at a time by the whole workgroup, with direct
+// global-to-LDS loads all in flight at once, so each chunk costs one memory
+// latency instead of one per step; every wave calls it with the same k0 and
+// k1.
 template <class C, int R>
 __device__ __forceinline__ void xl_replay(double2 (&z)[R][C::NXT / 64], int k0, int k1, int lane,
                                           const double2* __restrict__ frec) {
-  constexpr int NXT = C::NXT, XST = NXT / 64;
+  constexpr int NXT = C::NXT, XST = NXT / 64, FR = C::FROWS;
+  double2* fb = C::lds().xb;
+  const int wu = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll 1
-  for (int k = k0; k < k1; ++k) {
-    double2 f[XST];
+  for (int kc = k0; kc < k1; kc += FR) {
+    const int kn = k1 - kc < FR ? k1 - kc : FR;
+    __syncthreads();  // the previous chunk is consumed; the buffer's other users are done
+    // 64-entry pieces of the kn rows (NXT is a multiple of 64), one 16-byte load per lane
+    for (int t = wu; t < kn * XST; t += XW)
+      __builtin_amdgcn_global_load_lds((const void*)(frec + (long long)kc * NXT + 64 * t + lane),
+                                       (__attribute__((address_space(3))) void*)(fb + 64 * t), 16, 0, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+#pragma unroll 1
+    for (int j = 0; j < kn; ++j) {
+      double2 f[XST];
 #pragma unroll
-    for (int q = 0; q < XST; ++q) f[q] = gld(&frec[k * NXT + 64 * q + lane]);
-    xl_update<R, XST>(z, __builtin_amdgcn_readfirstlane(C::lds().pcrec[k]), f);
+      for (int q = 0; q < XST; ++q) f[q] = fb[j * NXT + 64 * q + lane];
+      xl_update<R, XST>(z, __builtin_amdgcn_readfirstlane(C::lds().pcrec[kc + j]), f);
+    }
   }
 }
 

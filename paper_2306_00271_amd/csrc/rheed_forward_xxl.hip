@@ -219,6 +219,7 @@ struct XXCfg {
   // up to 576 steps: a longer (still bounded) wait than for N <= 256
   static constexpr long long SYNC_TICKS = 10 * XCH_TICKS;
   static constexpr int SYNC_SPIN = 10 * XCH_SPIN;
+  static constexpr int FROWS = XKC * XCB / NXX;  // multiplier rows a replay stages in the stage-input buffer
   static constexpr long long PAIR_C = XXG_C, PAIR_D = XXG_D, PAIR_F = XXG_F, PAIR_PIV = XXG_PIV;
   static constexpr long long PAIR_BYTES = XXG_PAIR_BYTES;
   static constexpr long long WG_PART = XXG_STAGE_BYTES;
