@@ -96,8 +96,8 @@ typedef enum { RHEED_INTENSITY_FLUX = 0, RHEED_INTENSITY_PAPER = 1 } rheed_conve
  * that memory: RK steppers, FP64, with the adjoint.  Structures with
  * 256 < N <= 576 (the paper's single-angle size, Sec. 4) run on a fourth,
  * each pair on a cooperative group of workgroups that step its column blocks
- * side by side: RK steppers, FP64, forward only, at most as many pairs per
- * plan as the device holds such workgroups at once. */
+ * side by side: RK steppers, FP64, forward only; a batch larger than the
+ * device holds at once runs in several launches. */
 #define RHEED_MAX_BEAMS 576
 /* Largest potential-table row (rod differences) for N <= 64, for
  * 64 < N <= 128, for 128 < N <= 256 and for 256 < N <= 576. */

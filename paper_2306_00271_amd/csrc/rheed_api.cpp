@@ -84,6 +84,7 @@ struct rheed_plan_s {
   std::vector<int> xxl_pairs;
   int* d_xxl_pairs = nullptr;
   int xxl_group = 1;
+  int xxl_per_launch = 0;        // pairs per launch (all resident at once); larger batches take several
   char* d_xxg_pair = nullptr;
   char* d_xxg_wg = nullptr;
   unsigned* d_xxg_cnt = nullptr;
@@ -495,17 +496,19 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       P->xl_group = g >= 2 ? g : 1;
     }
     if (!P->xxl_pairs.empty()) {
-      // every pair on a cooperative group: all of them resident at once
+      // every pair on a cooperative group, as many pairs per launch as the
+      // device holds at once (a larger batch takes several launches, which
+      // reuse the group memory)
       const int cap = have_dev ? forward_xxl_group_max_workgroups(dev) : 0;
-      const int n_xxl = (int)P->xxl_pairs.size();
-      if (cap < n_xxl) {
+      if (cap < 1) {
         delete P;
-        return fail(RHEED_E_UNSUPPORTED, "structures with N > 256 run at most " + std::to_string(cap) +
-                                             " pairs per plan on this device (" + std::to_string(n_xxl) + " given)");
+        return fail(RHEED_E_HIP, "the kernel for N > 256 cannot be resident on this device");
       }
+      const int n_xxl = (int)P->xxl_pairs.size();
       int maxn = 0;
       for (int q : P->xxl_pairs) maxn = std::max(maxn, P->hs[P->pair_struct[q]].n_beams);
-      P->xxl_group = std::max(1, std::min((maxn + 15) / 16, cap / n_xxl));
+      P->xxl_group = std::max(1, std::min((maxn + 15) / 16, cap / std::min(n_xxl, cap)));
+      P->xxl_per_launch = std::min(n_xxl, cap / P->xxl_group);
     }
     if (opts->layout == RHEED_LAYOUT_SPLIT && !P->split && n_small > 0) {
       const int mx = P->split_max;
@@ -538,11 +541,11 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       (!P->xxl_pairs.empty() &&
        (e = hipMalloc(&P->d_xxl_pairs, sizeof(int) * P->xxl_pairs.size())) != hipSuccess) ||
       (!P->xxl_pairs.empty() &&
-       (e = hipMalloc(&P->d_xxg_pair, (size_t)XXG_PAIR_BYTES * P->xxl_pairs.size())) != hipSuccess) ||
+       (e = hipMalloc(&P->d_xxg_pair, (size_t)XXG_PAIR_BYTES * P->xxl_per_launch)) != hipSuccess) ||
       (!P->xxl_pairs.empty() &&
-       (e = hipMalloc(&P->d_xxg_wg, (size_t)XXG_WG_BYTES * P->xxl_group * P->xxl_pairs.size())) != hipSuccess) ||
+       (e = hipMalloc(&P->d_xxg_wg, (size_t)XXG_WG_BYTES * P->xxl_group * P->xxl_per_launch)) != hipSuccess) ||
       (!P->xxl_pairs.empty() &&
-       (e = hipMalloc(&P->d_xxg_cnt, sizeof(unsigned) * XG_CTR_WORDS * P->xxl_pairs.size())) != hipSuccess) ||
+       (e = hipMalloc(&P->d_xxg_cnt, sizeof(unsigned) * XG_CTR_WORDS * P->xxl_per_launch)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_large_pairs, sizeof(int) * n_large)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_large_plain, sizeof(int) * n_large)) != hipSuccess) ||
       (n_large > 0 && (e = hipMalloc(&P->d_lscratch, (size_t)LSLOT_BYTES * P->scratch_slots)) != hipSuccess) ||
@@ -827,8 +830,6 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
   if (!P->xxl_pairs.empty()) {
     LargeArgs xa{};
     xa.f = a;
-    xa.f.pair_list = P->d_xxl_pairs;
-    xa.f.n_pairs = (int)P->xxl_pairs.size();
     xa.f.ws = nullptr;
     xa.f.xch = nullptr;
     XlGroup xg{};
@@ -836,8 +837,13 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
     xg.wg_mem = P->d_xxg_wg;
     xg.counters = P->d_xxg_cnt;
     xg.group = P->xxl_group;
-    e = launch_forward_xxl_group((int)P->opts.stepper, xa, xg, st);
-    if (e != hipSuccess) return hip_fail(e, "forward launch (N > 256)");
+    const int n_xxl = (int)P->xxl_pairs.size();
+    for (int off = 0; off < n_xxl; off += P->xxl_per_launch) {  // launches on one stream run in order
+      xa.f.pair_list = P->d_xxl_pairs + off;
+      xa.f.n_pairs = std::min(P->xxl_per_launch, n_xxl - off);
+      e = launch_forward_xxl_group((int)P->opts.stepper, xa, xg, st);
+      if (e != hipSuccess) return hip_fail(e, "forward launch (N > 256)");
+    }
   }
   return RHEED_OK;
 }
