@@ -544,40 +544,11 @@ __device__ __noinline__ void xl_replay_p(double2* __restrict__ cg, double2* __re
   __syncthreads();
 }
 
-// Barrier of the G workgroups of one pair in a group launch: each raises the
-// pair's counter (an agent-scope release, so its stores are written back
-// first) and waits until all have reached `target` (G times the barriers so
-// far), then acquires.  A wait gives up after C::SYNC_SPIN polls or
-// C::SYNC_TICKS of the constant-rate clock (about 20 ms here, 200 ms for the
-// wider kernel, whose eliminations are longer), sets s.sync_fail and the
-// pair's failure word, and the workgroup stops waiting from then on (every
-// wait is bounded).
-template <class C>
-__device__ __forceinline__ void xl_group_sync(unsigned* cnt, unsigned target, unsigned* fail_word) {
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are issued and complete
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    if (!C::lds().sync_fail) {
-      const long long t0 = wall_clock64();
-      int it = 0;
-      while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        if (++it > C::SYNC_SPIN || wall_clock64() - t0 > C::SYNC_TICKS) {
-          C::lds().sync_fail = 1;
-          __hip_atomic_store(fail_word, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(2);
-      }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  __syncthreads();
-}
-
 // Bounded wait of a workgroup until *word >= target (thread 0 polls, then
-// acquires); gives up like xl_group_sync, and returns at once after an
-// earlier give-up.
+// acquires).  It gives up after C::SYNC_SPIN polls or C::SYNC_TICKS of the
+// constant-rate clock (about 20 ms for N <= 256, 200 ms for the wider kernel,
+// whose eliminations are longer), sets s.sync_fail and the pair's failure
+// word, and returns at once after an earlier give-up.
 template <class C>
 __device__ __forceinline__ void xl_wait_geq(const unsigned* word, unsigned target, unsigned* fail_word) {
   if (threadIdx.x == 0) {
@@ -596,6 +567,19 @@ __device__ __forceinline__ void xl_wait_geq(const unsigned* word, unsigned targe
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
+}
+
+// Barrier of the G workgroups of one pair in a group launch: each raises the
+// pair's counter (an agent-scope release, so its stores are written back
+// first) and waits until all have reached `target` (G times the barriers so
+// far), then acquires (xl_wait_geq: the wait is bounded, and a workgroup
+// whose wait gave up stops waiting from then on).
+template <class C>
+__device__ __forceinline__ void xl_group_sync(unsigned* cnt, unsigned target, unsigned* fail_word) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this wave's stores are issued and complete
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  xl_wait_geq<C>(cnt, target, fail_word);
 }
 
 // Publishes value in *word (one writer per word) once every wave's stores
