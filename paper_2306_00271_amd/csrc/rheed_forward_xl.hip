@@ -23,11 +23,12 @@
 // The Gershgorin / Varah estimate of cond(Q) decides the transformation
 // Z <- Z Q^{-1} (Sec. 3.2) as for N <= 128.  The elimination of Q (column
 // Gauss-Jordan with partial pivoting, recording its multipliers) does not
-// hold Q on chip: rows are taken 64 at a time (8 per wave, 4 columns per
-// lane), the column operations of all earlier steps are replayed on them
-// from the recorded multipliers, and the block's own steps are then
+// hold Q on chip: rows are taken 16 at a time (2 per wave, 4 columns per
+// lane: more rows per wave spill on every step), the column operations of
+// all earlier steps are replayed on them from the recorded multipliers
+// (staged through LDS 16 rows at a time), and the block's own steps are then
 // eliminated and recorded (a left-looking order of the same operations).
-// The rows of P are replayed the same way, 64 at a time, and written back
+// The rows of P are replayed the same way, 16 at a time, and written back
 // in pivot order: P Q^{-1}.  The reflection eliminates Gamma Q - iP likewise
 // and applies the recorded operations in reverse to a unit vector.
 //
@@ -53,8 +54,6 @@ namespace {
 constexpr int XW = 8;             // waves per workgroup
 constexpr int XT = XW * 64;       // threads per workgroup
 constexpr int XCB = 16;           // columns per block
-constexpr int XEB = 64;           // rows per elimination block
-constexpr int XEM = XEB / XW;     // rows per wave of an elimination block
 constexpr int XS = NX / 64;       // columns per lane in the eliminations
 
 struct XLds {
@@ -254,7 +253,7 @@ __device__ __noinline__ void xl_slice(double2* __restrict__ cg, double2* __restr
 // memory.
 struct XCfg {
   static constexpr int NXT = NX;
-  static constexpr int XEMT = XEM;
+  static constexpr int XEMT = 2;  // rows per wave of an elimination or replay block (16-row blocks)
   static constexpr int IDXB = 8;        // bits of the column index in a pivot key
   static constexpr int TSLOTS = 2;      // node-table slots in LDS
   static constexpr long long SYNC_TICKS = XCH_TICKS;  // a group barrier's wait gives up after this
@@ -287,12 +286,6 @@ struct XCfg {
 };
 
 
-// The group launch: the same, with the transformation's elimination
-// spread over the group in blocks of 16 steps (2 rows per wave; the replay
-// on P and the copies of R take the same 16-row blocks).
-struct XCfgG : XCfg {
-  static constexpr int XEMT = 2;
-};
 
 // Rows m < R of z: column j <- column j - f_j column pc, pc = 64 HF + pl
 // (the pivot column's quarter is wave-uniform, so it selects code).
@@ -704,11 +697,12 @@ __device__ __forceinline__ void xl_group_elim(double2* cg, const double2* dg, do
 }
 
 // Q^{-1} (or B^{-1} of the reflection) after xl_elim_record: the recorded
-// column operations replayed on the rows of I, 64 at a time (row blocks b0,
-// b0 + bs, ... of the NX / 64), each column put at its pivot step as in
+// column operations replayed on the rows of I, XW * XCfg::XEMT at a time (row
+// blocks b0, b0 + bs, ...), each column put at its pivot step as in
 // xl_replay_p; rows to out (row major, stride NX; rows >= n stay unit rows).
 __device__ __noinline__ void xl_replay_identity(double2* __restrict__ out, const double2* __restrict__ frec, int N,
                                                 int b0, int bs) {
+  constexpr int RM = XCfg::XEMT, RB = XW * RM;
   XLds& s = xl_lds;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int n = __builtin_amdgcn_readfirstlane(N);
@@ -716,15 +710,15 @@ __device__ __noinline__ void xl_replay_identity(double2* __restrict__ out, const
 #pragma unroll
   for (int q = 0; q < XS; ++q) pq[q] = s.pos[64 * q + lane];
 #pragma unroll 1
-  for (int r0 = XEB * b0; r0 < NX; r0 += XEB * bs) {
-    double2 z[XEM][XS];
+  for (int r0 = RB * b0; r0 < NX; r0 += RB * bs) {
+    double2 z[RM][XS];
 #pragma unroll
-    for (int m = 0; m < XEM; ++m)
+    for (int m = 0; m < RM; ++m)
 #pragma unroll
       for (int q = 0; q < XS; ++q) z[m][q] = make_double2(r0 + w + XW * m == 64 * q + lane ? 1.0 : 0.0, 0.0);
-    if (r0 < n) xl_replay<XCfg, XEM>(z, 0, n, lane, frec);
+    if (r0 < n) xl_replay<XCfg, RM>(z, 0, n, lane, frec);
 #pragma unroll
-    for (int m = 0; m < XEM; ++m) {
+    for (int m = 0; m < RM; ++m) {
       const int row = r0 + w + XW * m;
 #pragma unroll
       for (int q = 0; q < XS; ++q) gst(&out[row * NX + pq[q]], z[m][q]);
@@ -918,10 +912,10 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
         }
         xl_replay_p<C>(cg, dg, frec, N, g, G);
         if constexpr (SAVE) {
-          // T: 64-row block b of I by workgroup (nbp + b) mod G; R: row block
-          // b of P Q^{-1} (the replay's blocks) by workgroup b mod G, the one
+          // T: row block b of I by workgroup (nbp + b) mod G; R: row block b
+          // of P Q^{-1} (the replay's blocks) by workgroup b mod G, the one
           // that replayed it
-          const int nbp = (N + XEB - 1) / XEB;
+          const int nbp = (N + XW * XCfg::XEMT - 1) / (XW * XCfg::XEMT);
           xl_replay_identity(reinterpret_cast<double2*>(pws + a.ck.q_off + (long long)i * MATB), frec, N,
                              ((g - nbp) % G + G) % G, G);
           if (a.ck.r_off)
@@ -1065,7 +1059,7 @@ template <int STEPPER, bool SAVE>
 __global__ __launch_bounds__(XT, 1) void forward_xl_group_kernel(LargeArgs A, XlGroup X) {
   const int pi = blockIdx.x / X.group, g = blockIdx.x - pi * X.group;
   const int p = A.f.pair_list ? A.f.pair_list[pi] : pi;
-  xl_run_pair<XCfgG, STEPPER, true, SAVE>(A, p, nullptr, X, pi, g);
+  xl_run_pair<XCfg, STEPPER, true, SAVE>(A, p, nullptr, X, pi, g);
 }
 
 __global__ void xl_group_reset_kernel(unsigned* counters, int n) {
