@@ -34,11 +34,14 @@ constexpr int XXTP = (NXX / 16 + XW - 1) / XW;  // row tiles per wave (5)
 constexpr int XKC = 128;                        // rows of the stage input per LDS chunk
 constexpr int XXST = 7;                         // stage products kept per block (RK6)
 constexpr int XXEM = 2;                         // rows per wave of an elimination block (2 x 9 per lane in registers)
+constexpr int XXFR = 6;                         // multiplier rows a replay stages in LDS
+constexpr int XXB = XKC * XCB > XXFR * NXX ? XKC * XCB : XXFR * NXX;  // entries of the shared buffer
 
 static_assert(XXST * NXX * XCB * 16LL + NXX * XCB * 16LL <= XXG_STAGE_BYTES, "stage buffer of a workgroup");
 
 struct XXLds {
-  double2 xb[XKC * XCB];            // a chunk of the stage input; the pivot rows of the eliminations
+  double2 xb[XXB];                  // a chunk of the stage input; the pivot rows of the eliminations;
+                                    // the multiplier rows of a replay
   double2 tb[1][MAXBOXXX + 1];      // node table of the current stage; entry `box` stays 0
   int off[NXX];                     // h_k (2 kd + 1) + k_k of beam k
   int bhk[NXX][2];
@@ -219,7 +222,7 @@ struct XXCfg {
   // up to 576 steps: a longer (still bounded) wait than for N <= 256
   static constexpr long long SYNC_TICKS = 10 * XCH_TICKS;
   static constexpr int SYNC_SPIN = 10 * XCH_SPIN;
-  static constexpr int FROWS = XKC * XCB / NXX;  // multiplier rows a replay stages in the stage-input buffer
+  static constexpr int FROWS = XXFR;  // multiplier rows a replay stages in the stage-input buffer
   static constexpr long long PAIR_C = XXG_C, PAIR_D = XXG_D, PAIR_F = XXG_F, PAIR_PIV = XXG_PIV;
   static constexpr long long PAIR_BYTES = XXG_PAIR_BYTES;
   static constexpr long long WG_PART = XXG_STAGE_BYTES;
