@@ -199,13 +199,15 @@ rheed_status rheed_plan_create(rheed_plan_t* plan, const rheed_opts* opts, int32
                                const rheed_structure* structs, const int32_t* angles_per_struct);
 rheed_status rheed_plan_destroy(rheed_plan_t plan);
 rheed_status rheed_plan_get_info(rheed_plan_t plan, rheed_plan_info* info);
-/* Failure path of the split layout, for tests: with half = 0 or 1, the
- * first wait of that workgroup of every pair in later split launches gives
- * up at once, as a wait does when the partner workgroup stops answering for
- * about 20 ms.  Such a pair must come back with RHEED_PAIR_SYNC (whichever
- * half gave up) while the call itself succeeds and every workgroup ends
- * normally.  half = -1 (the default) turns it off.  Host only; no effect on
- * the other layouts. */
+/* Failure path of the multi-workgroup launches, for tests: with half = 0
+ * or 1, the first wait of that workgroup of every pair in later split
+ * launches gives up at once, as a wait does when the partner workgroup stops
+ * answering for about 20 ms; in the group launches (N > 128) workgroup half
+ * of every pair's group starts as if a wait had given up (it waits for no
+ * other workgroup).  Such a pair must come back with RHEED_PAIR_SYNC while
+ * the call itself succeeds and every workgroup ends normally.  half = -1
+ * (the default) turns it off.  Host only; no effect on the one-workgroup
+ * layouts. */
 rheed_status rheed_plan_force_sync_failure(rheed_plan_t plan, int32_t half);
 
 /* host out[n_struct + 1]: complex-element offset of each structure's table;

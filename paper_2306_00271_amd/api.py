@@ -140,7 +140,8 @@ class Plan:
             self.close()
 
     def force_sync_failure(self, half: int) -> None:
-        """rheed_plan_force_sync_failure: the split layout's failure path, for tests."""
+        """rheed_plan_force_sync_failure: the failure path of the split layout and
+        of the group launches, for tests."""
         _lib.check(_lib.lib().rheed_plan_force_sync_failure(self._handle(), int(half)), "plan_force_sync_failure")
 
     def _handle(self):

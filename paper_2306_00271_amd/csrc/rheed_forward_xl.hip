@@ -806,6 +806,14 @@ __device__ void xl_run_pair(const LargeArgs& A, int p, char* slot, const XlGroup
     s.flag_singular = 0;
     s.bad = 0;
     s.sync_fail = 0;
+    if constexpr (GRP) {
+      // failure path for tests (rheed_plan_force_sync_failure): this
+      // workgroup starts as if its first wait had given up
+      if (a.xch_give_up == g) {
+        s.sync_fail = 1;
+        __hip_atomic_store(failw, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
   }
   if (tid < C::TSLOTS) s.tb[tid][S.box] = make_double2(0.0, 0.0);
   __syncthreads();

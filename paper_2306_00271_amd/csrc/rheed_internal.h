@@ -72,7 +72,8 @@ struct FwdArgs {
   int ld;
   int convention;
   int n_pairs;               // pairs of this launch
-  int xch_give_up;           // split launches: the half (0, 1) whose first wait fails at once; -1 normally
+  int xch_give_up;           // split launches: the half (0, 1) whose first wait fails at once; group launches:
+                             // the workgroup of each group that starts as if it had given up; -1 normally
   double threshold;
   // split launches (two workgroups per pair): per-pair exchange blocks
   char* xch;

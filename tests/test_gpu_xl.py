@@ -139,3 +139,36 @@ def test_group_of_two_matches_one_workgroup():
     d = np.abs(grp["intensity"] - one["intensity"]).max()
     print(f"[parity-xl] N=150, 128 pairs, groups of 2 vs one workgroup: max |diff| = {d:.3e}", flush=True)
     np.testing.assert_allclose(grp["intensity"], one["intensity"], rtol=0.0, atol=1e-13)
+
+
+@pytest.mark.parametrize("half", [0, 1])
+def test_group_wait_failure_is_reported(half):
+    """The group launch's failure path, forced from the host: workgroup 0
+    (which records the eliminations) or 1 (an owner in the elimination
+    pipeline) of every pair's group waits for no other workgroup, as after
+    a give-up.  Every pair must come back RHEED_PAIR_SYNC with NaN outputs
+    from a call that succeeds; with the hook off the same plan is back to
+    oracle parity."""
+    import torch
+    from paper_2306_00271_amd import api
+    wl = small_2d(n_beams=150, n_slices=16, thickness=1.6, n_layers=1, n_angles=2)
+    dev = torch.device("cuda:0")
+    plan = api.plan_for(wl, stepper="rk6")
+    assert plan.info.xl_group == 10
+    U = plan.potential(api.atoms_for(wl, dev))
+    ang = api.angles_for(wl, dev)
+    plan.force_sync_failure(half)
+    out = plan.forward(U, ang)
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    print(f"[parity-xl] forced give-up in workgroup {half}: status {st.tolist()}", flush=True)
+    assert (st == 3).all()
+    assert np.isnan(out["intensity"].cpu().numpy()[:, :150]).all()
+    plan.force_sync_failure(-1)
+    out = plan.forward(U, ang)
+    torch.cuda.synchronize()
+    assert (out["status"].cpu().numpy() == 0).all()
+    ref, _, _ = oracle_forward(wl, stepper="rk6")
+    e = eacc(out["intensity"].cpu().numpy()[:, :150], ref)
+    _report("group launch after the forced failure", e)
+    assert e <= TOL

@@ -116,3 +116,33 @@ def test_many_pairs_small_groups(n_angles, group):
             f"oracle {nr.tolist()}", e)
     assert e <= TOL
     assert res["n_rhst"][idx].tolist() == nr.tolist()
+
+
+@pytest.mark.parametrize("half", [0, 1])
+def test_group_wait_failure_is_reported(half):
+    """As for N <= 256: a workgroup of every pair's group forced to wait
+    for no other; every pair RHEED_PAIR_SYNC from a call that succeeds, then
+    oracle parity again with the hook off."""
+    import torch
+    from paper_2306_00271_amd import api
+    wl = small_2d(n_beams=300, n_slices=8, thickness=0.8, n_layers=1, n_angles=2, m=7)
+    dev = torch.device("cuda:0")
+    plan = api.plan_for(wl, stepper="rk6")
+    assert plan.info.xxl_group == 19
+    U = plan.potential(api.atoms_for(wl, dev))
+    ang = api.angles_for(wl, dev)
+    plan.force_sync_failure(half)
+    out = plan.forward(U, ang)
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    print(f"[parity-xxl] forced give-up in workgroup {half}: status {st.tolist()}", flush=True)
+    assert (st == 3).all()
+    assert np.isnan(out["intensity"].cpu().numpy()[:, :300]).all()
+    plan.force_sync_failure(-1)
+    out = plan.forward(U, ang)
+    torch.cuda.synchronize()
+    assert (out["status"].cpu().numpy() == 0).all()
+    ref, _, _ = oracle_forward(wl, stepper="rk6")
+    e = eacc(out["intensity"].cpu().numpy()[:, :300], ref)
+    _report("group launch after the forced failure", e)
+    assert e <= TOL
