@@ -508,13 +508,15 @@ def n199_forward(steps=1, cpu=True):
         print(f"[n199] single pair, {key}: {res['single_pair'][key]['ms']} ms", file=sys.stderr, flush=True)
         del p1, U1
     # the gradient step (potential -> forward keeping states every 20 slices ->
-    # R-factor -> adjoint -> atom gradient) on a few angles per call: the T and R
-    # slots of every slice take about 2 GB per pair at this size
-    ga = 16
+    # R-factor -> adjoint -> atom gradient) on 64 angles per call: the T and R
+    # slots of every slice take about 2.3 GB per pair at this size, 145 GB of
+    # the 288 GB of HBM for the call (16 pairs per call: 22 points/s; 100: 37)
+    ga = 64
     gw = dataclasses.replace(wl, theta0=wl.theta0[::256 // ga][:ga])
     pg = api.plan_for(gw, stepper="rk6", checkpoint_every=20)
     atoms = api.atoms_for(gw, dev)
     ag = api.angles_for(gw, dev)
+    torch.cuda.empty_cache()  # the earlier variants' cached blocks, before the large workspace
     ws = pg.workspace(dev)
     tgt = torch.from_numpy(np.random.default_rng(37).uniform(0.0, 0.3, size=pg.n_pairs)).to(dev)
 
@@ -538,6 +540,7 @@ def n199_forward(steps=1, cpu=True):
                        "gradient_finite": bool(torch.isfinite(grad).all().item())}
     print(f"[n199] gradient step, {pg.n_pairs} pairs: {gms:.1f} ms", file=sys.stderr, flush=True)
     del pg, ws
+    torch.cuda.empty_cache()
     if cpu:
         import multiprocessing as mp
         cores = min(16, os.cpu_count() or 1)
