@@ -926,8 +926,9 @@ struct SplitLds {
   double2 cx[2 * NP * HC];   // c of this half [NP][HC], then the stage input [NP][HC]; [NP][NP] at the end
   double2 ext[NP * NP];      // Q of both halves for the elimination, then Q^{-1}
   double2 tb[5][MAXBOX + 1];
-  double2 gj_row[2 * NP];
-  int gj_piv[NP];
+  int gj_piv[NP];            // pivot column of every elimination step
+  int gj_pos[NP];            // step at which each column was the pivot
+  int gj_cnt;                // elimination steps published so far
   double g2s[NP];
   double bnorm;              // ||Gamma Q - iP||_inf of the reflection solve
   int bhk[NP][2];
@@ -996,20 +997,23 @@ __device__ __forceinline__ void xch_wait(unsigned long long* cnt, unsigned long 
 
 // Q^{-1} of the leading n x n block of split_lds.ext (row major, identity
 // outside the block), written back over it; with t != null the columns
-// [col0, col0 + HC) also go to t (global, row major [NP][NP]).
+// [col0, col0 + HC) also go to t (global, row major [NP][NP]).  The
+// elimination is pipelined over the four waves (gj_inverse_pipe); its step
+// records go to the rows of ext, which the waves have read by then.
 __device__ __noinline__ void invert_split(int n, double2* t, int col0) {
   SplitLds& s = split_lds;
+  constexpr int RB = NP / SW;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  double2 z[2 * NP / SW];
+  double2 za[RB], zs[RB];
 #pragma unroll
-  for (int m = 0; m < NP / SW; ++m) z[m] = s.ext[(w + SW * m) * NP + lane];
-  const int pos = gj_inverse<SW>(z, n, lane, w, s.gj_row, s.gj_piv, &s.flag_singular);
+  for (int m = 0; m < RB; ++m) za[m] = s.ext[(RB * w + m) * NP + lane];
+  const int pos = gj_inverse_pipe<SW>(za, zs, n, lane, w, s.ext, s.gj_piv, s.gj_pos, &s.gj_cnt, &s.flag_singular);
   const bool mine = t != nullptr && pos >= col0 && pos < col0 + HC;
 #pragma unroll
-  for (int m = NP / SW; m < 2 * NP / SW; ++m) {
-    const int sl = w + SW * (m - NP / SW);
+  for (int m = 0; m < RB; ++m) {
+    const int sl = RB * w + m;
     const int row = sl < n ? s.gj_piv[sl] : sl;
-    const double2 val = sl < n ? z[m] : make_double2(pos == sl ? 1.0 : 0.0, 0.0);
+    const double2 val = sl < n ? zs[m] : make_double2(pos == sl ? 1.0 : 0.0, 0.0);
     s.ext[row * NP + pos] = val;
     if (mine) t[row * NP + pos] = val;
   }

@@ -131,4 +131,137 @@ __device__ __forceinline__ int gj_inverse(double2 (&z)[2 * NP / NWV], int n, int
   return pos;
 }
 
+// The same elimination as a pipeline over the waves, for a workgroup of NWV
+// waves on NWV SIMDs (the arithmetic of every step is that of GjInv, so the
+// result is the same bit for bit).  Wave w holds rows RB w .. RB w + RB - 1
+// of A (RB = NP / NWV) in za.  Step k is taken by the wave that owns row k,
+// alone and without a workgroup barrier: row k is in its registers with every
+// earlier step applied, so it picks the pivot, writes the step's multipliers
+// f to rec[k][.] and pc_k to pivrec[k], raises the step counter (a
+// workgroup-scope release store in LDS) and applies the step to its later
+// rows.  The other waves apply the published steps in order: to their rows
+// of A before their own block, and to the inverse rows of their block (zs)
+// after it.  Inverse row pc_s is e_{pc_s} until step s, and steps before s
+// leave it unchanged (its entry in their pivot columns is zero), so zs is
+// set up once the block's pivots are known and takes steps RB w .. n - 1.
+// A wave waits only for the step it applies next, and every step depends on
+// earlier steps alone, so every wait ends.  A wait that finds the matrix
+// already flagged singular returns at once (the results are discarded then),
+// and one that still exceeds GJ_PIPE_SPIN polls flags it and gives up, so no
+// wave can spin for long whatever the data.  rec may be the
+// matrix's own storage (row k of it is read only by the wave that owns row
+// k, before step k); posrec[j] ends as the step at which column j was the
+// pivot (j if none).  Returns this lane's position, as gj_inverse.
+constexpr int GJ_PIPE_SPIN = 1 << 18;
+
+__device__ __forceinline__ void gj_wait_step(const int* cnt, int k, int* flag_singular) {
+  int it = 0;
+  while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) <= k) {
+    if (__builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(flag_singular, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) != 0 ||
+        ++it > GJ_PIPE_SPIN) {
+      *flag_singular = 1;
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// Step (pc, f) on rows M0 .. RB - 1 of z: z_m <- z_m - f z_m[pc].
+template <int RB, int M0>
+__device__ __forceinline__ void gj_apply(double2 (&z)[RB], int pc, double2 f) {
+  double2 zp[RB];
+#pragma unroll
+  for (int m = M0; m < RB; ++m) zp[m] = make_double2(readlane_f64(z[m].x, pc), readlane_f64(z[m].y, pc));
+#pragma unroll
+  for (int m = M0; m < RB; ++m) {
+    z[m].x = fma(-f.x, zp[m].x, z[m].x);
+    z[m].x = fma(f.y, zp[m].y, z[m].x);
+    z[m].y = fma(-f.x, zp[m].y, z[m].y);
+    z[m].y = fma(-f.y, zp[m].x, z[m].y);
+  }
+}
+
+template <int NWV, int J>
+struct GjPanel {
+  static constexpr int RB = NP / NWV;
+  static __device__ __forceinline__ void run(double2 (&za)[RB], int n, int lane, int k0, unsigned long long& um,
+                                             double2* rec, int* pivrec, int* posrec, int* cnt, int* flag_singular) {
+    const int k = k0 + J;
+    if (k >= n) return;
+    const double2 v = za[J];
+    const double m2 = v.x * v.x + v.y * v.y;
+    unsigned key = 0;
+    if (!((um >> lane) & 1ull) && lane < n)
+      key = ((unsigned)(((unsigned long long)__double_as_longlong(m2)) >> 32) & ~63u) | (unsigned)(63 - lane);
+    key = wave_max_u32(key);
+    if ((key >> 6) == 0 && lane == 0) *flag_singular = 1;
+    const int pc = 63 - (int)(key & 63);
+    um |= 1ull << pc;
+    const double2 piv = make_double2(readlane_f64(v.x, pc), readlane_f64(v.y, pc));
+    const double inv = 1.0 / (piv.x * piv.x + piv.y * piv.y);
+    const double2 ip = make_double2(piv.x * inv, -piv.y * inv);
+    double2 f = make_double2(v.x * ip.x - v.y * ip.y, v.x * ip.y + v.y * ip.x);
+    if (lane == pc) f = make_double2(1.0 - ip.x, -ip.y);
+    rec[k * NP + lane] = f;
+    if (lane == 0) {
+      pivrec[k] = pc;
+      posrec[pc] = k;
+    }
+    __hip_atomic_store(cnt, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    gj_apply<RB, J + 1>(za, pc, f);  // row k itself is not used again
+    GjPanel<NWV, J + 1>::run(za, n, lane, k0, um, rec, pivrec, posrec, cnt, flag_singular);
+  }
+};
+template <int NWV>
+struct GjPanel<NWV, NP / NWV> {
+  static __device__ __forceinline__ void run(double2 (&)[NP / NWV], int, int, int, unsigned long long&, double2*, int*,
+                                             int*, int*, int*) {}
+};
+
+//   za: rows of A as above (rows >= n must be those of the identity);
+//   zs: out, inverse row pivrec[RB w + m] in zs[m] for RB w + m < n.
+//   rec: n x NP entries; pivrec, posrec: NP ints; cnt: one int.
+template <int NWV>
+__device__ __forceinline__ int gj_inverse_pipe(double2 (&za)[NP / NWV], double2 (&zs)[NP / NWV], int n, int lane,
+                                               int w, double2* rec, int* pivrec, int* posrec, int* cnt,
+                                               int* flag_singular) {
+  constexpr int RB = NP / NWV;
+  const int wu = __builtin_amdgcn_readfirstlane(w);
+  const int k0 = RB * wu;
+  if (wu == 0) {
+    posrec[lane] = lane;
+    if (lane == 0) *cnt = 0;
+  }
+#pragma unroll
+  for (int m = 0; m < RB; ++m) zs[m] = make_double2(0.0, 0.0);
+  __syncthreads();
+  if (k0 < n) {
+    unsigned long long um = 0;
+    // the earlier blocks' steps on this wave's rows of A
+#pragma unroll 1
+    for (int k = 0; k < k0; ++k) {
+      gj_wait_step(cnt, k, flag_singular);
+      const double2 f = rec[k * NP + lane];
+      const int pc = __builtin_amdgcn_readfirstlane(pivrec[k]) & 63;
+      um |= 1ull << pc;
+      gj_apply<RB, 0>(za, pc, f);
+    }
+    GjPanel<NWV, 0>::run(za, n, lane, k0, um, rec, pivrec, posrec, cnt, flag_singular);
+    // this block's inverse rows, from step k0 on
+#pragma unroll
+    for (int m = 0; m < RB; ++m)
+      if (k0 + m < n) zs[m] = make_double2(lane == pivrec[k0 + m] ? 1.0 : 0.0, 0.0);
+#pragma unroll 1
+    for (int k = k0; k < n; ++k) {
+      if (k >= k0 + RB) gj_wait_step(cnt, k, flag_singular);
+      const double2 f = rec[k * NP + lane];
+      const int pc = __builtin_amdgcn_readfirstlane(pivrec[k]) & 63;
+      gj_apply<RB, 0>(zs, pc, f);
+    }
+  }
+  __syncthreads();
+  return posrec[lane];
+}
+
 }  // namespace rheed
