@@ -141,9 +141,10 @@ __device__ __forceinline__ int gj_inverse(double2 (&z)[2 * NP / NWV], int n, int
 // workgroup-scope release store in LDS) and applies the step to its later
 // rows.  The other waves apply the published steps in order: to their rows
 // of A before their own block, and to the inverse rows of their block (zs)
-// after it.  Inverse row pc_s is e_{pc_s} until step s, and steps before s
-// leave it unchanged (its entry in their pivot columns is zero), so zs is
-// set up once the block's pivots are known and takes steps RB w .. n - 1.
+// after it.  Inverse row pc_s is e_{pc_s} until step s (earlier steps leave
+// it unchanged: its entry in their pivot columns is zero), so once the
+// block's steps are recorded its inverse rows are formed from them and take
+// the later blocks' steps as these come.
 // A wave waits only for the step it applies next, and every step depends on
 // earlier steps alone, so every wait ends.  A wait that finds the matrix
 // already flagged singular returns at once (the results are discarded then),
@@ -154,27 +155,32 @@ __device__ __forceinline__ int gj_inverse(double2 (&z)[2 * NP / NWV], int n, int
 // pivot (j if none).  Returns this lane's position, as gj_inverse.
 constexpr int GJ_PIPE_SPIN = 1 << 18;
 
-__device__ __forceinline__ void gj_wait_step(const int* cnt, int k, int* flag_singular) {
+// Waits until more than k steps are published; returns the count it saw
+// (k + 1 if the wait gave up).
+__device__ __forceinline__ int gj_wait_step(const int* cnt, int k, int* flag_singular) {
   int it = 0;
-  while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) <= k) {
+  for (;;) {
+    const int c =
+        __builtin_amdgcn_readfirstlane(__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+    if (c > k) return c;
     if (__builtin_amdgcn_readfirstlane(
             __hip_atomic_load(flag_singular, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) != 0 ||
         ++it > GJ_PIPE_SPIN) {
       *flag_singular = 1;
-      break;
+      return k + 1;
     }
     __builtin_amdgcn_s_sleep(1);
   }
 }
 
-// Step (pc, f) on rows M0 .. RB - 1 of z: z_m <- z_m - f z_m[pc].
-template <int RB, int M0>
+// Step (pc, f) on rows M0 .. M1 - 1 of z: z_m <- z_m - f z_m[pc].
+template <int RB, int M0, int M1 = RB>
 __device__ __forceinline__ void gj_apply(double2 (&z)[RB], int pc, double2 f) {
   double2 zp[RB];
 #pragma unroll
-  for (int m = M0; m < RB; ++m) zp[m] = make_double2(readlane_f64(z[m].x, pc), readlane_f64(z[m].y, pc));
+  for (int m = M0; m < M1; ++m) zp[m] = make_double2(readlane_f64(z[m].x, pc), readlane_f64(z[m].y, pc));
 #pragma unroll
-  for (int m = M0; m < RB; ++m) {
+  for (int m = M0; m < M1; ++m) {
     z[m].x = fma(-f.x, zp[m].x, z[m].x);
     z[m].x = fma(f.y, zp[m].y, z[m].x);
     z[m].y = fma(-f.x, zp[m].y, z[m].y);
@@ -182,20 +188,64 @@ __device__ __forceinline__ void gj_apply(double2 (&z)[RB], int pc, double2 f) {
   }
 }
 
-template <int NWV, int J>
+// Published steps kb .. ke - 1 on all rows of z, in order.  avail counts the
+// steps known to be published (from the last look at the counter); the next
+// step's record is read while the current one is applied whenever it is
+// known to be there, and the counter is looked at again only when avail runs
+// out.  With USED, the pivot columns are collected in *um.
+template <int RB, bool USED>
+__device__ __forceinline__ void gj_consume(double2 (&z)[RB], int kb, int ke, int lane, int& avail,
+                                           unsigned long long* um, const double2* rec, const int* pivrec,
+                                           const int* cnt, int* flag_singular) {
+  if (kb >= ke) return;
+  if (kb >= avail) avail = gj_wait_step(cnt, kb, flag_singular);
+  double2 f = rec[kb * NP + lane];
+  int pv = pivrec[kb];
+#pragma unroll 1
+  for (int k = kb; k < ke; ++k) {
+    const int pc = __builtin_amdgcn_readfirstlane(pv) & 63;
+    const int k1 = k + 1;
+    if (k1 < ke && k1 >= avail)  // a look without waiting
+      avail = __builtin_amdgcn_readfirstlane(__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+    const bool ahead = k1 < ke && k1 < avail;
+    double2 fn = f;
+    int pn = pv;
+    if (ahead) {
+      fn = rec[k1 * NP + lane];
+      pn = pivrec[k1];
+    }
+    if (USED) *um |= 1ull << pc;
+    gj_apply<RB, 0>(z, pc, f);
+    if (k1 < ke && !ahead) {
+      avail = gj_wait_step(cnt, k1, flag_singular);
+      fn = rec[k1 * NP + lane];
+      pn = pivrec[k1];
+    }
+    f = fn;
+    pv = pn;
+  }
+}
+
+// A wave's own block of steps.  With FULL (the block lies inside the
+// matrix) it is straight-line code: the next pivot row takes the step first,
+// the step is published, then the remaining rows take it, so the scheduler
+// can overlap the next step's pivot search with this step's row updates.
+// The singular test accumulates in sing.
+template <int NWV, int J, bool FULL>
 struct GjPanel {
   static constexpr int RB = NP / NWV;
+  static constexpr int J2 = J + 2 < RB ? J + 2 : RB;
   static __device__ __forceinline__ void run(double2 (&za)[RB], int n, int lane, int k0, unsigned long long& um,
-                                             double2* rec, int* pivrec, int* posrec, int* cnt, int* flag_singular) {
+                                             bool& sing, double2* rec, int* pivrec, int* posrec, int* cnt) {
     const int k = k0 + J;
-    if (k >= n) return;
+    if (!FULL && k >= n) return;
     const double2 v = za[J];
     const double m2 = v.x * v.x + v.y * v.y;
     unsigned key = 0;
     if (!((um >> lane) & 1ull) && lane < n)
       key = ((unsigned)(((unsigned long long)__double_as_longlong(m2)) >> 32) & ~63u) | (unsigned)(63 - lane);
     key = wave_max_u32(key);
-    if ((key >> 6) == 0 && lane == 0) *flag_singular = 1;
+    sing |= (key >> 6) == 0;
     const int pc = 63 - (int)(key & 63);
     um |= 1ull << pc;
     const double2 piv = make_double2(readlane_f64(v.x, pc), readlane_f64(v.y, pc));
@@ -204,19 +254,108 @@ struct GjPanel {
     double2 f = make_double2(v.x * ip.x - v.y * ip.y, v.x * ip.y + v.y * ip.x);
     if (lane == pc) f = make_double2(1.0 - ip.x, -ip.y);
     rec[k * NP + lane] = f;
-    if (lane == 0) {
-      pivrec[k] = pc;
-      posrec[pc] = k;
-    }
+    pivrec[k] = pc;  // every lane stores the same value
+    posrec[pc] = k;
+    gj_apply<RB, J + 1, J2>(za, pc, f);  // row k itself is not used again
     __hip_atomic_store(cnt, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-    gj_apply<RB, J + 1>(za, pc, f);  // row k itself is not used again
-    GjPanel<NWV, J + 1>::run(za, n, lane, k0, um, rec, pivrec, posrec, cnt, flag_singular);
+    gj_apply<RB, J2, RB>(za, pc, f);
+    GjPanel<NWV, J + 1, FULL>::run(za, n, lane, k0, um, sing, rec, pivrec, posrec, cnt);
+  }
+};
+template <int NWV, bool FULL>
+struct GjPanel<NWV, NP / NWV, FULL> {
+  static __device__ __forceinline__ void run(double2 (&)[NP / NWV], int, int, int, unsigned long long&, bool&,
+                                             double2*, int*, int*, int*) {}
+};
+
+// The full block as a software pipeline: step J's pivot search, division
+// and multipliers run in eight pieces (key, the six DPP stages, the pivot
+// and its reciprocal), and step J - 1's update of rows J + 1 .. RB - 1,
+// deferred to here, is cut into eight chunks placed after the pieces, with
+// scheduling barriers between them, so that the row updates fill the latency
+// of the search.  Row J + 1 takes step J - 1 in the first chunk that holds
+// it and step J right after the multipliers are known, so every row still
+// takes its steps in order, with the same arithmetic.
+template <int RB, int D0, int ND, int I>
+__device__ __forceinline__ void gj_chunk(double2 (&za)[RB], int pc, double2 f) {
+  if constexpr (ND > 0) gj_apply<RB, D0 + ND * I / 8, D0 + ND * (I + 1) / 8>(za, pc, f);
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int NWV, int J>
+struct GjPanelPipe {
+  static constexpr int RB = NP / NWV;
+  static constexpr int D0 = J + 1, ND = J == 0 ? 0 : RB - (J + 1);  // rows waiting for step J - 1
+  static __device__ __forceinline__ void run(double2 (&za)[RB], int n, int lane, int k0, unsigned long long& um,
+                                             bool& sing, double2* rec, int* pivrec, int* posrec, int* cnt, int pcp,
+                                             double2 fp) {
+    const int k = k0 + J;
+    const double2 v = za[J];
+    const double m2 = v.x * v.x + v.y * v.y;
+    unsigned key = 0;
+    if (!((um >> lane) & 1ull) && lane < n)
+      key = ((unsigned)(((unsigned long long)__double_as_longlong(m2)) >> 32) & ~63u) | (unsigned)(63 - lane);
+    gj_chunk<RB, D0, ND, 0>(za, pcp, fp);
+    unsigned o = (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0xB1, 0xf, 0xf, false);
+    key = o > key ? o : key;
+    gj_chunk<RB, D0, ND, 1>(za, pcp, fp);
+    o = (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x4E, 0xf, 0xf, false);
+    key = o > key ? o : key;
+    gj_chunk<RB, D0, ND, 2>(za, pcp, fp);
+    o = (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x141, 0xf, 0xf, false);
+    key = o > key ? o : key;
+    gj_chunk<RB, D0, ND, 3>(za, pcp, fp);
+    o = (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x140, 0xf, 0xf, false);
+    key = o > key ? o : key;
+    gj_chunk<RB, D0, ND, 4>(za, pcp, fp);
+    o = (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x142, 0xa, 0xf, false);
+    key = o > key ? o : key;
+    gj_chunk<RB, D0, ND, 5>(za, pcp, fp);
+    o = (unsigned)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x143, 0xc, 0xf, false);
+    key = o > key ? o : key;
+    key = (unsigned)__builtin_amdgcn_readlane((int)key, 63);
+    sing |= (key >> 6) == 0;
+    const int pc = 63 - (int)(key & 63);
+    um |= 1ull << pc;
+    const double2 piv = make_double2(readlane_f64(v.x, pc), readlane_f64(v.y, pc));
+    gj_chunk<RB, D0, ND, 6>(za, pcp, fp);
+    const double inv = 1.0 / (piv.x * piv.x + piv.y * piv.y);
+    const double2 ip = make_double2(piv.x * inv, -piv.y * inv);
+    double2 f = make_double2(v.x * ip.x - v.y * ip.y, v.x * ip.y + v.y * ip.x);
+    if (lane == pc) f = make_double2(1.0 - ip.x, -ip.y);
+    gj_chunk<RB, D0, ND, 7>(za, pcp, fp);
+    rec[k * NP + lane] = f;
+    pivrec[k] = pc;  // every lane stores the same value
+    posrec[pc] = k;
+    if constexpr (J + 1 < RB) gj_apply<RB, J + 1, J + 2>(za, pc, f);
+    __hip_atomic_store(cnt, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    GjPanelPipe<NWV, J + 1>::run(za, n, lane, k0, um, sing, rec, pivrec, posrec, cnt, pc, f);
   }
 };
 template <int NWV>
-struct GjPanel<NWV, NP / NWV> {
-  static __device__ __forceinline__ void run(double2 (&)[NP / NWV], int, int, int, unsigned long long&, double2*, int*,
-                                             int*, int*, int*) {}
+struct GjPanelPipe<NWV, NP / NWV> {
+  static __device__ __forceinline__ void run(double2 (&)[NP / NWV], int, int, int, unsigned long long&, bool&,
+                                             double2*, int*, int*, int*, int, double2) {}
+};
+
+// The inverse rows of a wave's own block through its own steps: row J is
+// e_{pc} before step k0 + J, which it then takes with rows 0 .. J - 1.
+template <int RB, int J>
+struct GjOwnRows {
+  static __device__ __forceinline__ void run(double2 (&zs)[RB], int n, int lane, int k0, const double2* rec,
+                                             const int* pivrec) {
+    const int k = k0 + J;
+    if (k >= n) return;
+    const double2 f = rec[k * NP + lane];
+    const int pc = __builtin_amdgcn_readfirstlane(pivrec[k]) & 63;
+    zs[J] = make_double2(lane == pc ? 1.0 : 0.0, 0.0);
+    gj_apply<RB, 0, J + 1>(zs, pc, f);
+    GjOwnRows<RB, J + 1>::run(zs, n, lane, k0, rec, pivrec);
+  }
+};
+template <int RB>
+struct GjOwnRows<RB, RB> {
+  static __device__ __forceinline__ void run(double2 (&)[RB], int, int, int, const double2*, const int*) {}
 };
 
 //   za: rows of A as above (rows >= n must be those of the identity);
@@ -238,27 +377,16 @@ __device__ __forceinline__ int gj_inverse_pipe(double2 (&za)[NP / NWV], double2 
   __syncthreads();
   if (k0 < n) {
     unsigned long long um = 0;
-    // the earlier blocks' steps on this wave's rows of A
-#pragma unroll 1
-    for (int k = 0; k < k0; ++k) {
-      gj_wait_step(cnt, k, flag_singular);
-      const double2 f = rec[k * NP + lane];
-      const int pc = __builtin_amdgcn_readfirstlane(pivrec[k]) & 63;
-      um |= 1ull << pc;
-      gj_apply<RB, 0>(za, pc, f);
-    }
-    GjPanel<NWV, 0>::run(za, n, lane, k0, um, rec, pivrec, posrec, cnt, flag_singular);
-    // this block's inverse rows, from step k0 on
-#pragma unroll
-    for (int m = 0; m < RB; ++m)
-      if (k0 + m < n) zs[m] = make_double2(lane == pivrec[k0 + m] ? 1.0 : 0.0, 0.0);
-#pragma unroll 1
-    for (int k = k0; k < n; ++k) {
-      if (k >= k0 + RB) gj_wait_step(cnt, k, flag_singular);
-      const double2 f = rec[k * NP + lane];
-      const int pc = __builtin_amdgcn_readfirstlane(pivrec[k]) & 63;
-      gj_apply<RB, 0>(zs, pc, f);
-    }
+    int avail = 0;
+    gj_consume<RB, true>(za, 0, k0, lane, avail, &um, rec, pivrec, cnt, flag_singular);  // earlier blocks' steps
+    bool sing = false;
+    if (k0 + RB <= n)
+      GjPanelPipe<NWV, 0>::run(za, n, lane, k0, um, sing, rec, pivrec, posrec, cnt, 0, make_double2(0.0, 0.0));
+    else
+      GjPanel<NWV, 0, false>::run(za, n, lane, k0, um, sing, rec, pivrec, posrec, cnt);
+    if (sing && lane == 0) *flag_singular = 1;
+    GjOwnRows<RB, 0>::run(zs, n, lane, k0, rec, pivrec);
+    gj_consume<RB, false>(zs, k0 + RB, n, lane, avail, nullptr, rec, pivrec, cnt, flag_singular);
   }
   __syncthreads();
   return posrec[lane];
