@@ -77,8 +77,9 @@ struct Tab<2> {  // a splitting method: its nodes per slice come with the launch
 struct Lds {
   double2 xb[2 * NP * NP];   // [c; X]: c block and stage-input buffer; [Q; P] during eliminations
   double2 tb[5][MAXBOX + 1]; // node tables (Ur, Ui); entry `box` of every row stays 0
-  double2 gj_row[2 * NP];    // elimination scratch: pivot rows (two steps in flight)
-  int gj_piv[NP];            //   pivot column of every step
+  int gj_piv[NP];            // elimination: pivot column of every step,
+  int gj_pos[NP];            //   step at which each column was the pivot,
+  int gj_cnt;                //   steps published so far
   double g2s[NP];            // Gamma_j^2 (real), 0 on padding
   double bnorm;              // ||Gamma Q - iP||_inf of the reflection solve
   int bhk[NP][2];
@@ -96,20 +97,23 @@ __device__ Lds& fwd_lds_ref();
 // (row major), written back over it (identity outside the n x n block) and,
 // with WITH_T, also to t in global memory.  Kept out of line so that its
 // registers (the matrix is held in registers during the elimination) do not
-// add to those of the RK stages.
+// add to those of the RK stages.  The elimination is pipelined over the
+// eight waves (gj_inverse_pipe); its step records go to the rows of the
+// matrix, which the waves have read by then.
 template <bool WITH_T>
 __device__ __noinline__ void invert_top(int n, double2* t) {
   Lds& s = fwd_lds_ref();
+  constexpr int RB = NP / FW;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  double2 z[2 * NP / FW];
+  double2 za[RB], zs[RB];
 #pragma unroll
-  for (int m = 0; m < NP / FW; ++m) z[m] = s.xb[(w + FW * m) * NP + lane];
-  const int pos = gj_inverse<FW>(z, n, lane, w, s.gj_row, s.gj_piv, &s.flag_singular);
+  for (int m = 0; m < RB; ++m) za[m] = s.xb[(RB * w + m) * NP + lane];
+  const int pos = gj_inverse_pipe<FW>(za, zs, n, lane, w, s.xb, s.gj_piv, s.gj_pos, &s.gj_cnt, &s.flag_singular);
 #pragma unroll
-  for (int m = NP / FW; m < 2 * NP / FW; ++m) {
-    const int sl = w + FW * (m - NP / FW);
+  for (int m = 0; m < RB; ++m) {
+    const int sl = RB * w + m;
     const int row = sl < n ? s.gj_piv[sl] : sl;
-    const double2 val = sl < n ? z[m] : make_double2(pos == sl ? 1.0 : 0.0, 0.0);
+    const double2 val = sl < n ? zs[m] : make_double2(pos == sl ? 1.0 : 0.0, 0.0);
     s.xb[row * NP + pos] = val;
     if (WITH_T) t[row * NP + pos] = val;
   }
