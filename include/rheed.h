@@ -144,8 +144,7 @@ typedef enum { RHEED_LAYOUT_AUTO = 0, RHEED_LAYOUT_WHOLE = 1, RHEED_LAYOUT_SPLIT
  * cores (v_mfma_f32_16x16x4f32) with the operands rounded to FP32 and
  * everything else in FP64 (the Gamma^2 X term, the stage combinations, the
  * state, the transformation, the reflection).  FP32 stages: RK steppers,
- * N <= 64 and 128 < N <= 256, forward only (no state saving, no bulk
- * start); the intensities then differ from the FP64 ones by about 1e-7 to
+ * N <= 256, forward only (no state saving, no bulk start); the intensities then differ from the FP64 ones by about 1e-7 to
  * 1e-6 in eacc on the test slabs, well below the step's own discretisation
  * error at the usual grids. */
 typedef enum { RHEED_STAGES_FP64 = 0, RHEED_STAGES_FP32 = 1 } rheed_stage_precision;

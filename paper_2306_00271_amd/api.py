@@ -133,10 +133,11 @@ class Plan:
     def __exit__(self, *exc):
         self.close()
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # no HIP call once the interpreter is shutting down: the exit hook
-        # has closed every plan by then
-        if not sys.is_finalizing():
+        # has closed every plan by then (the check is bound at definition,
+        # since module globals may already be gone at that point)
+        if not _finalizing():
             self.close()
 
     def force_sync_failure(self, half: int) -> None:

@@ -243,10 +243,9 @@ rheed_status rheed_plan_create(rheed_plan_t* out, const rheed_opts* opts, int32_
       delete P;
       return fail(RHEED_E_UNSUPPORTED, buf);
     }
-    if (opts->stage_precision == RHEED_STAGES_FP32 && ((st.n_beams > NP && st.n_beams <= NL) || st.n_beams > NX)) {
+    if (opts->stage_precision == RHEED_STAGES_FP32 && st.n_beams > NX) {
       delete P;
-      return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) +
-                                           ": FP32 stage products need N <= 64 or 128 < N <= 256");
+      return fail(RHEED_E_UNSUPPORTED, "structure " + std::to_string(s) + ": FP32 stage products need N <= 256");
     }
     if (st.n_beams > NL && splitting) {
       delete P;
@@ -803,7 +802,7 @@ rheed_status forward_impl(rheed_plan_t P, const void* U_tables, const double* an
     la.n_slots = P->large_slots;
     for (int q = 0; q < 3; ++q) la.sp_a[q] = P->sp_a[q];
     for (int q = 0; q < 4; ++q) la.sp_b[q] = P->sp_b[q];
-    e = launch_forward_large((int)P->opts.stepper, la, st);
+    e = launch_forward_large((int)P->opts.stepper | (f32 ? 8 : 0), la, st);
     if (e != hipSuccess) return hip_fail(e, "forward launch (N > 64)");
   }
   if (!P->xl_pairs.empty()) {

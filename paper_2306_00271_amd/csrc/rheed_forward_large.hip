@@ -171,12 +171,16 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 
 // (U X) for the wave's 16 x 16 tile: A = U gathered from the node table,
 // B = X of the block in LDS (row stride LCB).  Element v of the result
-// belongs to row 16 w + 4 v + (lane >> 4), block column lane & 15.
-template <int KQ>
+// belongs to row 16 w + 4 v + (lane >> 4), block column lane & 15.  F32:
+// the same chains on v_mfma_f32_16x16x4f32 (the gather indices then hold
+// the A rows in a_row<true> order), operands rounded to FP32, the chains
+// combined in FP64.
+template <int KQ, bool F32 = false>
 __device__ __forceinline__ void gemm_tile(const double2* __restrict__ xb, const double2* __restrict__ tsl,
                                           const unsigned* __restrict__ gix, int lane, LMat& out) {
   __builtin_amdgcn_sched_barrier(0);
-  d4 t1 = d4{0, 0, 0, 0}, t2 = t1, t3 = t1;
+  using Acc = typename std::conditional<F32, f4, d4>::type;
+  Acc t1 = Acc{0, 0, 0, 0}, t2 = t1, t3 = t1;
   int bb = (lane >> 4) * LCB + (lane & 15);
   asm volatile("" : "+v"(bb));  // keep the addresses from being hoisted out of the caller's loops
 #pragma unroll
@@ -186,15 +190,22 @@ __device__ __forceinline__ void gemm_tile(const double2* __restrict__ xb, const 
     const unsigned gi = (q & 1) ? (gw >> 16) : (gw & 0xffffu);
     const double2 u = tsl[gi];
     const double2 x = xb[bb + 4 * LCB * q];
-    t1 = mfma(u.x, x.x, t1);
-    t2 = mfma(u.y, x.y, t2);
-    t3 = mfma(u.x + u.y, x.x + x.y, t3);
+    if constexpr (F32) {
+      t1 = __builtin_amdgcn_mfma_f32_16x16x4f32((float)u.x, (float)x.x, t1, 0, 0, 0);
+      t2 = __builtin_amdgcn_mfma_f32_16x16x4f32((float)u.y, (float)x.y, t2, 0, 0, 0);
+      t3 = __builtin_amdgcn_mfma_f32_16x16x4f32((float)(u.x + u.y), (float)(x.x + x.y), t3, 0, 0, 0);
+    } else {
+      t1 = mfma(u.x, x.x, t1);
+      t2 = mfma(u.y, x.y, t2);
+      t3 = mfma(u.x + u.y, x.x + x.y, t3);
+    }
     if ((q & 3) == 3) __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    out.r[v] = t1[v] - t2[v];
-    out.i[v] = t3[v] - t1[v] - t2[v];
+    const double a1 = t1[v], a2 = t2[v], a3 = t3[v];
+    out.r[v] = a1 - a2;
+    out.i[v] = a3 - a1 - a2;
   }
   __builtin_amdgcn_sched_barrier(0);
 }
@@ -204,7 +215,7 @@ __device__ __forceinline__ void gemm_tile(const double2* __restrict__ xb, const 
 template <int STEPPER, int KQ>
 __device__ __forceinline__ void step_block(LLds& s, LMat& c, LMat& d, const double (&g2)[4], int ob, int lane,
                                            int nb, double h) {
-  using T = LTab<STEPPER>;
+  using T = LTab<(STEPPER & 7)>;
   constexpr int SL = T::nodes + 1;
   const double hh = h * h;
   LMat G[T::stages];
@@ -232,7 +243,7 @@ __device__ __forceinline__ void step_block(LLds& s, LMat& c, LMat& d, const doub
       s.xb[ob + 4 * LCB * e] = make_double2(xr, xi);
     }
     __syncthreads();
-    gemm_tile<KQ>(s.xb, s.tb[(nb + T::node(r)) % SL], &s.gix[0][threadIdx.x], lane, G[r]);
+    gemm_tile<KQ, (STEPPER & F32_STAGES) != 0>(s.xb, s.tb[(nb + T::node(r)) % SL], &s.gix[0][threadIdx.x], lane, G[r]);
 #pragma unroll
     for (int e = 0; e < LNE; ++e) {
       const double2 x = s.xb[ob + 4 * LCB * e];  // X_r back from LDS rather than kept in registers
@@ -658,7 +669,8 @@ __device__ __forceinline__ void copy_block(double2* __restrict__ dst, const doub
 // forward-only code keeps its own register allocation).
 template <int STEPPER, bool SAVE>
 __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
-  using T = LTab<STEPPER>;
+  static_assert(!(SAVE && (STEPPER & F32_STAGES)), "FP32 stages run forward only");
+  using T = LTab<(STEPPER & 7)>;
   constexpr int SL = T::nodes + 1;
   const FwdArgs& a = A.f;
   LLds& s = large_lds_ref();
@@ -708,7 +720,7 @@ __device__ void run_pair(const LargeArgs& A, int p, char* slot) {
   // (row 16 w + (lane & 15), k = 4 q + (lane >> 4)); padding reads entry `box` = 0
   {
     const int W = 2 * S.kd + 1;
-    const int iA = 16 * w + (lane & 15);
+    const int iA = 16 * w + a_row<(STEPPER & F32_STAGES) != 0>(lane & 15);
     const int baseA = (s.bhk[iA][0] + S.hd) * W + (s.bhk[iA][1] + S.kd);
 #pragma unroll 4
     for (int q = 0; q < LQ; q += 2) {
@@ -932,8 +944,14 @@ hipError_t launch_forward_large(int stepper, const LargeArgs& a, hipStream_t str
     hipLaunchKernelGGL((forward_large_kernel<1, true>), dim3(grid), dim3(LT), 0, stream, a);
   else if (stepper == 1)
     hipLaunchKernelGGL((forward_large_kernel<1, false>), dim3(grid), dim3(LT), 0, stream, a);
-  else
+  else if (stepper == 2)
     hipLaunchKernelGGL((forward_large_kernel<2, false>), dim3(grid), dim3(LT), 0, stream, a);
+  else if (stepper == (0 | F32_STAGES) && !save)
+    hipLaunchKernelGGL((forward_large_kernel<0 | F32_STAGES, false>), dim3(grid), dim3(LT), 0, stream, a);
+  else if (stepper == (1 | F32_STAGES) && !save)
+    hipLaunchKernelGGL((forward_large_kernel<1 | F32_STAGES, false>), dim3(grid), dim3(LT), 0, stream, a);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -941,8 +959,12 @@ int forward_large_slots(int device) {
   int cus = 0, per0 = 0, per1 = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) return 0;
   int per2 = 0;
-  int per3 = 0, per4 = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per0, forward_large_kernel<0, false>, LT, 0) != hipSuccess ||
+  int per3 = 0, per4 = 0, per5 = 0, per6 = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per5, forward_large_kernel<0 | F32_STAGES, false>, LT, 0) !=
+          hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per6, forward_large_kernel<1 | F32_STAGES, false>, LT, 0) !=
+          hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per0, forward_large_kernel<0, false>, LT, 0) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per1, forward_large_kernel<1, false>, LT, 0) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per2, forward_large_kernel<2, false>, LT, 0) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per3, forward_large_kernel<0, true>, LT, 0) != hipSuccess ||
@@ -952,6 +974,8 @@ int forward_large_slots(int device) {
   per = per < per2 ? per : per2;
   per = per < per3 ? per : per3;
   per = per < per4 ? per : per4;
+  per = per < per5 ? per : per5;
+  per = per < per6 ? per : per6;
   return cus * (per > 0 ? per : 0);
 }
 
