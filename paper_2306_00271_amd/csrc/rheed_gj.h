@@ -226,19 +226,17 @@ __device__ __forceinline__ void gj_consume(double2 (&z)[RB], int kb, int ke, int
   }
 }
 
-// A wave's own block of steps.  With FULL (the block lies inside the
-// matrix) it is straight-line code: the next pivot row takes the step first,
-// the step is published, then the remaining rows take it, so the scheduler
-// can overlap the next step's pivot search with this step's row updates.
-// The singular test accumulates in sing.
-template <int NWV, int J, bool FULL>
+// A wave's own block of steps, step by step (used for the block that
+// reaches the matrix's last row; full blocks run as GjPanelPipe below).  The
+// singular test accumulates in sing.
+template <int NWV, int J>
 struct GjPanel {
   static constexpr int RB = NP / NWV;
   static constexpr int J2 = J + 2 < RB ? J + 2 : RB;
   static __device__ __forceinline__ void run(double2 (&za)[RB], int n, int lane, int k0, unsigned long long& um,
                                              bool& sing, double2* rec, int* pivrec, int* posrec, int* cnt) {
     const int k = k0 + J;
-    if (!FULL && k >= n) return;
+    if (k >= n) return;
     const double2 v = za[J];
     const double m2 = v.x * v.x + v.y * v.y;
     unsigned key = 0;
@@ -259,11 +257,11 @@ struct GjPanel {
     gj_apply<RB, J + 1, J2>(za, pc, f);  // row k itself is not used again
     __hip_atomic_store(cnt, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     gj_apply<RB, J2, RB>(za, pc, f);
-    GjPanel<NWV, J + 1, FULL>::run(za, n, lane, k0, um, sing, rec, pivrec, posrec, cnt);
+    GjPanel<NWV, J + 1>::run(za, n, lane, k0, um, sing, rec, pivrec, posrec, cnt);
   }
 };
-template <int NWV, bool FULL>
-struct GjPanel<NWV, NP / NWV, FULL> {
+template <int NWV>
+struct GjPanel<NWV, NP / NWV> {
   static __device__ __forceinline__ void run(double2 (&)[NP / NWV], int, int, int, unsigned long long&, bool&,
                                              double2*, int*, int*, int*) {}
 };
@@ -383,7 +381,7 @@ __device__ __forceinline__ int gj_inverse_pipe(double2 (&za)[NP / NWV], double2 
     if (k0 + RB <= n)
       GjPanelPipe<NWV, 0>::run(za, n, lane, k0, um, sing, rec, pivrec, posrec, cnt, 0, make_double2(0.0, 0.0));
     else
-      GjPanel<NWV, 0, false>::run(za, n, lane, k0, um, sing, rec, pivrec, posrec, cnt);
+      GjPanel<NWV, 0>::run(za, n, lane, k0, um, sing, rec, pivrec, posrec, cnt);
     if (sing && lane == 0) *flag_singular = 1;
     GjOwnRows<RB, 0>::run(zs, n, lane, k0, rec, pivrec);
     gj_consume<RB, false>(zs, k0 + RB, n, lane, avail, nullptr, rec, pivrec, cnt, flag_singular);
